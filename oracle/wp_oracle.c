@@ -1,0 +1,620 @@
+/*
+ * CPU ORACLE -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, scalar, deliberately slow implementation of what the decoder
+ * computes, written from Lemire & Boytsov, "Decoding billions of integers
+ * per second through vectorization" (arXiv:1209.2137). Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg may load it. It shares
+ * no source, header, table or helper with the GPU library; both follow the
+ * stream layout written out in the design document (re-stated below).
+ *
+ * Every function cites the passage of the paper it follows. Arithmetic on
+ * array values is uint32 modulo 2^32 throughout.
+ *
+ * Stream layout (little-endian 32-bit words):
+ *   header  (8 words) magic, n_lo, n_hi, stride, n_units, tail_bytes,
+ *                     tail_off, total_words
+ *   directory         one entry per unit (+1 for the tail when present):
+ *                     [unit word offset, base_0 .. base_{S-1}], S = stride,
+ *                     base_s = x[start - S + s] (0 before the array start);
+ *                     zero-padded to a multiple of 4 words
+ *   units             binary packing: 4-word width descriptor (byte j = b_j)
+ *                     then 16 blocks of 128 values, block j in 4*b_j words.
+ *                     patched (FastPFOR) page of up to 512 blocks: see
+ *                     oracle_fp_encode
+ *   tail              Variable Byte of the last n mod 128 deltas,
+ *                     zero-padded to a word
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OB 128u                /* block length: 128 integers (Section 6.2) */
+#define OBP_BLOCKS 16u         /* SIMD-BP128 meta-block: 16 blocks (Section 6.2) */
+#define OFP_BLOCKS 512u        /* patched page: 2^16 integers (Section 5) */
+#define OMAGIC_BP 0x31425057u  /* "WPB1" */
+#define OMAGIC_FP 0x31465057u  /* "WPF1" */
+
+enum { O_OK = 0, O_ERR_ARG = -1, O_ERR_CAP = -2, O_ERR_CORRUPT = -3 };
+
+/* ---- Section 2 (binary notation): a positive integer x needs
+ * ceil(log2(x+1)) binary digits; zero needs none. Counted digit by digit. */
+uint32_t oracle_bits(uint32_t x)
+{
+    uint32_t b = 0;
+    while (x != 0) {
+        b++;
+        x >>= 1;
+    }
+    return b;
+}
+
+/* ---- Section 4, Figs. 4-5: fields of b bits laid end to end, field i
+ * occupying bits [i*b, i*b+b) of the word sequence, word w holding bits
+ * [32w, 32w+32), least significant bit first; a field may straddle two
+ * words. Written bit by bit. Only the low b bits of each value are kept
+ * (the 2^b-1 mask of Section 4). `words` must hold ceil(count*b/32) words;
+ * they are cleared first. */
+void oracle_pack(const uint32_t *vals, uint64_t count, uint32_t b, uint32_t *words)
+{
+    uint64_t nwords = (count * b + 31) / 32;
+    memset(words, 0, nwords * sizeof(uint32_t));
+    for (uint64_t i = 0; i < count; i++) {
+        for (uint32_t j = 0; j < b; j++) {
+            if ((vals[i] >> j) & 1u) {
+                uint64_t bit = i * b + j;
+                words[bit / 32] |= 1u << (bit % 32);
+            }
+        }
+    }
+}
+
+void oracle_unpack(const uint32_t *words, uint64_t count, uint32_t b, uint32_t *vals)
+{
+    for (uint64_t i = 0; i < count; i++) {
+        uint32_t v = 0;
+        for (uint32_t j = 0; j < b; j++) {
+            uint64_t bit = i * b + j;
+            if ((words[bit / 32] >> (bit % 32)) & 1u)
+                v |= 1u << j;
+        }
+        vals[i] = v;
+    }
+}
+
+/* ---- Section 3: differential coding. stride 1: d_i = x_i - x_{i-1};
+ * stride 4 (the vectorised form): d_i = x_i - x_{i-4}, the first four
+ * values kept; stride 0: no differencing. Values before the array start
+ * count as `init` (0 for the codecs). Computed in place from the largest
+ * index down, as the section's worked example (1,4,13 -> 1,3,9) does. */
+int oracle_delta_encode_inplace(uint32_t *data, uint64_t n, uint32_t init, int stride)
+{
+    if (stride != 0 && stride != 1 && stride != 4)
+        return O_ERR_ARG;
+    if (stride == 0)
+        return O_OK;
+    for (uint64_t i = n; i-- > 0;) {
+        uint32_t prev = (i >= (uint64_t)stride) ? data[i - stride] : init;
+        data[i] = data[i] - prev;
+    }
+    return O_OK;
+}
+
+/* Section 3: decoding is the prefix sum x_i = d_i + x_{i-S}, computed in
+ * place in increasing index order (worked example 1,3,9 -> 1,4,13). */
+int oracle_delta_decode_inplace(uint32_t *data, uint64_t n, uint32_t init, int stride)
+{
+    if (stride != 0 && stride != 1 && stride != 4)
+        return O_ERR_ARG;
+    if (stride == 0)
+        return O_OK;
+    for (uint64_t i = 0; i < n; i++) {
+        uint32_t prev = (i >= (uint64_t)stride) ? data[i - stride] : init;
+        data[i] = data[i] + prev;
+    }
+    return O_OK;
+}
+
+/* ---- Section 2 (Variable Byte): seven data bits per byte, low-order group
+ * first; the eighth bit is 1 only on the last byte of an integer (the
+ * section's example: 200 becomes the bytes 0x48, 0x81). Returns bytes written. */
+uint32_t oracle_vbyte_encode(const uint32_t *vals, uint32_t count, uint8_t *out)
+{
+    uint32_t p = 0;
+    for (uint32_t i = 0; i < count; i++) {
+        uint32_t v = vals[i];
+        while (v >= 128u) {
+            out[p++] = (uint8_t)(v & 127u);
+            v >>= 7;
+        }
+        out[p++] = (uint8_t)(v | 128u);
+    }
+    return p;
+}
+
+/* Decodes `count` integers from at most `nbytes` bytes. Returns the number
+ * of bytes consumed, or -1 if the bytes run out or an integer is longer
+ * than five bytes or overflows 32 bits. */
+int64_t oracle_vbyte_decode(const uint8_t *in, uint64_t nbytes, uint32_t count, uint32_t *vals)
+{
+    uint64_t p = 0;
+    for (uint32_t i = 0; i < count; i++) {
+        uint64_t v = 0;
+        uint32_t shift = 0;
+        for (;;) {
+            if (p >= nbytes || shift > 28)
+                return -1;
+            uint8_t byte = in[p++];
+            v |= (uint64_t)(byte & 127u) << shift;
+            shift += 7;
+            if (byte & 128u)
+                break;
+        }
+        if (v > 0xFFFFFFFFull)
+            return -1;
+        vals[i] = (uint32_t)v;
+    }
+    return (int64_t)p;
+}
+
+/* ---- Section 5: width choice of the patched schemes for one block of
+ * `count` values. A histogram of bit widths 0..32; maxb the largest width;
+ * for each candidate b in [0, maxb] the exceptions are the c(b) values
+ * wider than b, each costed at 8 bits of position plus maxb-b high bits;
+ * the block costs count*b + c(b)*(8 + maxb - b) bits. The smallest cost
+ * wins; equal costs keep the wider b (fewer exceptions). Writes b, maxb and
+ * the exception count c. */
+void oracle_fp_choose(const uint32_t *vals, uint32_t count, uint32_t *b_out,
+                      uint32_t *maxb_out, uint32_t *c_out)
+{
+    uint64_t hist[33];
+    memset(hist, 0, sizeof hist);
+    for (uint32_t i = 0; i < count; i++)
+        hist[oracle_bits(vals[i])]++;
+    uint32_t maxb = 0;
+    for (uint32_t w = 0; w <= 32; w++)
+        if (hist[w] != 0)
+            maxb = w;
+    uint32_t best_b = maxb;
+    uint64_t best_cost = (uint64_t)count * maxb;
+    uint64_t best_c = 0;
+    for (int b = (int)maxb - 1; b >= 0; b--) {
+        uint64_t c = 0;
+        for (uint32_t w = (uint32_t)b + 1; w <= 32; w++)
+            c += hist[w];
+        uint64_t cost = (uint64_t)count * (uint64_t)b + c * (8u + maxb - (uint32_t)b);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best_b = (uint32_t)b;
+            best_c = c;
+        }
+    }
+    *b_out = best_b;
+    *maxb_out = maxb;
+    *c_out = (uint32_t)best_c;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Stream assembly shared by both codecs (header, directory, tail).        */
+
+static uint64_t o_pad4(uint64_t w) { return (w + 3u) & ~(uint64_t)3u; }
+
+static uint64_t o_units(int codec, uint64_t n)
+{
+    uint64_t nfull = n / OB;
+    uint64_t per = codec == 0 ? OBP_BLOCKS : OFP_BLOCKS;
+    return (nfull + per - 1) / per;
+}
+
+/* Worst-case stream size in words, computed from the layout. */
+uint64_t oracle_max_words(int codec, uint64_t n)
+{
+    uint64_t nfull = n / OB;
+    uint64_t tail = n % OB;
+    uint64_t units = o_units(codec, n);
+    uint64_t words = 8 + o_pad4((1 + 4) * (units + 1));
+    if (codec == 0) {
+        words += units * 4 + nfull * OB;
+    } else {
+        /* per page: header <= 36 words; packed <= 128 words per block;
+         * metadata <= (3 + 127) bytes per block (+16 B padding); every array
+         * k holds at most one group of padding, and the exception bits of a
+         * block never exceed 32*127 */
+        words += units * (36 + 4 + 32 * 4 * 32) + nfull * (OB + (3 + 127) / 4 + 1 + 127);
+    }
+    words += (tail * 5 + 3) / 4;
+    return words;
+}
+
+/* ---- Section 6.2, SIMD-BP128: blocks of 128 deltas, each stored in
+ * b = bits(max) bits (computed, as the section suggests, from one OR over
+ * the block: the width of the OR equals the largest width), 16 blocks per
+ * meta-block behind a 128-bit descriptor of 8-bit widths. The remainder
+ * after the last full block is Variable Byte (Section 6.2).
+ * codec 0 = binary packing, 1 = patched pages (oracle_fp_encode).
+ * Returns the stream length in words or a negative error. */
+static int64_t o_encode(int codec, const uint32_t *x, uint64_t n, int stride,
+                        uint32_t *out, uint64_t cap);
+
+int64_t oracle_bp_encode(const uint32_t *x, uint64_t n, int stride, uint32_t *out, uint64_t cap)
+{
+    return o_encode(0, x, n, stride, out, cap);
+}
+
+int64_t oracle_fp_encode(const uint32_t *x, uint64_t n, int stride, uint32_t *out, uint64_t cap)
+{
+    return o_encode(1, x, n, stride, out, cap);
+}
+
+/* Binary-packing meta-block: the descriptor then each block's packed words. */
+static uint64_t o_bp_unit(const uint32_t *d, uint64_t nblocks, uint32_t *out)
+{
+    uint32_t desc[4] = {0, 0, 0, 0};
+    uint64_t pos = 4;
+    for (uint64_t j = 0; j < nblocks; j++) {
+        uint32_t all = 0;
+        for (uint32_t i = 0; i < OB; i++)
+            all |= d[j * OB + i];
+        uint32_t b = oracle_bits(all);
+        desc[j / 4] |= b << (8 * (j % 4));
+        oracle_pack(d + j * OB, OB, b, out + pos);
+        pos += (uint64_t)OB * b / 32;
+    }
+    memcpy(out, desc, sizeof desc);
+    return pos;
+}
+
+/* ---- Section 5, FastPFOR page, re-arranged for parallel parsing:
+ *   [nblocks, packed_words, meta_bytes, bitset] + count_k for every set k
+ *       (ascending), zero-padded to 4 words.  bitset bit k-1 <=> array k
+ *       non-empty, k = 1..32 (the 32-bit bitset of Section 5)
+ *   packed: block t's low b_t bits of its 128 values, 4*b_t words each,
+ *       blocks back to back
+ *   metadata bytes: b[nblocks], maxb[nblocks], c[nblocks], then every
+ *       block's exception positions (0..127) in block order -- the same
+ *       bytes as the section's per-block byte array, grouped by kind;
+ *       zero-padded to 16 bytes
+ *   exception arrays, for each set k ascending: the high parts (value >> b)
+ *       of exceptions of blocks with maxb - b = k, in block order, packed
+ *       at k bits in groups of 128 (SIMD-FastPFOR pads to a multiple of 128
+ *       values; the padding values are 0), 4*k words per group. */
+static uint64_t o_fp_page(const uint32_t *d, uint64_t nblocks, uint32_t *out)
+{
+    uint32_t *bw = malloc(nblocks * sizeof(uint32_t));
+    uint32_t *mb = malloc(nblocks * sizeof(uint32_t));
+    uint32_t *cc = malloc(nblocks * sizeof(uint32_t));
+    uint32_t *arr[33];
+    uint64_t cnt[33];
+    uint64_t need[33];
+    memset(need, 0, sizeof need);
+    for (uint64_t t = 0; t < nblocks; t++) {
+        oracle_fp_choose(d + t * OB, OB, &bw[t], &mb[t], &cc[t]);
+        need[mb[t] - bw[t]] += cc[t];
+    }
+    for (int k = 0; k <= 32; k++) {
+        arr[k] = malloc((need[k] + OB) * sizeof(uint32_t));
+        cnt[k] = 0;
+    }
+    uint8_t *pos_bytes = malloc(nblocks * OB + 1);
+    uint64_t npos = 0;
+    uint64_t packed_words = 0;
+    for (uint64_t t = 0; t < nblocks; t++) {
+        const uint32_t *blk = d + t * OB;
+        packed_words += (uint64_t)OB * bw[t] / 32;
+        uint32_t k = mb[t] - bw[t];
+        for (uint32_t i = 0; i < OB; i++) {
+            if (oracle_bits(blk[i]) > bw[t]) {
+                pos_bytes[npos++] = (uint8_t)i;
+                arr[k][cnt[k]++] = blk[i] >> bw[t];
+            }
+        }
+    }
+    uint32_t bitset = 0;
+    uint32_t nset = 0;
+    for (uint32_t k = 1; k <= 32; k++)
+        if (cnt[k] != 0) {
+            bitset |= 1u << (k - 1);
+            nset++;
+        }
+    uint64_t meta_bytes = 3 * nblocks + npos;
+    uint64_t hdr_words = o_pad4(4 + nset);
+    memset(out, 0, hdr_words * sizeof(uint32_t));
+    out[0] = (uint32_t)nblocks;
+    out[1] = (uint32_t)packed_words;
+    out[2] = (uint32_t)meta_bytes;
+    out[3] = bitset;
+    uint32_t hi = 4;
+    for (uint32_t k = 1; k <= 32; k++)
+        if (cnt[k] != 0)
+            out[hi++] = (uint32_t)cnt[k];
+    uint64_t p = hdr_words;
+    /* packed truncated values (oracle_pack keeps the low b bits) */
+    for (uint64_t t = 0; t < nblocks; t++) {
+        oracle_pack(d + t * OB, OB, bw[t], out + p);
+        p += (uint64_t)OB * bw[t] / 32;
+    }
+    /* metadata bytes */
+    uint64_t meta_words = ((meta_bytes + 15) / 16) * 4;
+    uint8_t *mbytes = (uint8_t *)(out + p);
+    memset(mbytes, 0, meta_words * 4);
+    for (uint64_t t = 0; t < nblocks; t++) {
+        mbytes[t] = (uint8_t)bw[t];
+        mbytes[nblocks + t] = (uint8_t)mb[t];
+        mbytes[2 * nblocks + t] = (uint8_t)cc[t];
+    }
+    for (uint64_t e = 0; e < npos; e++)
+        mbytes[3 * nblocks + e] = pos_bytes[e];
+    p += meta_words;
+    /* exception arrays */
+    for (uint32_t k = 1; k <= 32; k++) {
+        if (cnt[k] == 0)
+            continue;
+        uint64_t padded = ((cnt[k] + OB - 1) / OB) * OB;
+        for (uint64_t e = cnt[k]; e < padded; e++)
+            arr[k][e] = 0;
+        oracle_pack(arr[k], padded, k, out + p);
+        p += padded * k / 32;
+    }
+    for (int k = 0; k <= 32; k++)
+        free(arr[k]);
+    free(bw);
+    free(mb);
+    free(cc);
+    free(pos_bytes);
+    return p;
+}
+
+static int64_t o_encode(int codec, const uint32_t *x, uint64_t n, int stride,
+                        uint32_t *out, uint64_t cap)
+{
+    if (stride != 0 && stride != 1 && stride != 4)
+        return O_ERR_ARG;
+    if (cap < oracle_max_words(codec, n))
+        return O_ERR_CAP;
+    if (oracle_max_words(codec, n) >= 0xFFFFFFFFull)
+        return O_ERR_ARG;
+    uint32_t *d = malloc((n + 1) * sizeof(uint32_t));
+    memcpy(d, x, n * sizeof(uint32_t));
+    oracle_delta_encode_inplace(d, n, 0, stride);
+
+    uint64_t nfull = n / OB;
+    uint64_t tail = n % OB;
+    uint64_t units = o_units(codec, n);
+    uint64_t per = codec == 0 ? OBP_BLOCKS : OFP_BLOCKS;
+    uint64_t E = 1 + (uint64_t)stride;
+    uint64_t ndir = units + (tail ? 1 : 0);
+    uint64_t dir_words = o_pad4(E * ndir);
+    memset(out, 0, (8 + dir_words) * sizeof(uint32_t));
+    uint64_t p = 8 + dir_words;
+    for (uint64_t u = 0; u < ndir; u++) {
+        uint64_t start = u * per * OB; /* first value of the unit (or tail) */
+        if (u == units)
+            start = nfull * OB;
+        uint32_t *ent = out + 8 + u * E;
+        ent[0] = (uint32_t)p;
+        for (uint64_t s = 0; s < (uint64_t)stride; s++) {
+            /* base_s = x[start - S + s], 0 before the array start */
+            ent[1 + s] = (start + s >= (uint64_t)stride) ? x[start + s - stride] : 0u;
+        }
+        if (u < units) {
+            uint64_t nb = nfull - u * per;
+            if (nb > per)
+                nb = per;
+            p += codec == 0 ? o_bp_unit(d + start, nb, out + p)
+                            : o_fp_page(d + start, nb, out + p);
+        }
+    }
+    uint64_t tail_off = p;
+    uint32_t tail_bytes = 0;
+    if (tail) {
+        uint8_t buf[OB * 5];
+        tail_bytes = oracle_vbyte_encode(d + nfull * OB, (uint32_t)tail, buf);
+        uint64_t tw = (tail_bytes + 3) / 4;
+        memset(out + p, 0, tw * 4);
+        memcpy(out + p, buf, tail_bytes);
+        p += tw;
+    }
+    out[0] = codec == 0 ? OMAGIC_BP : OMAGIC_FP;
+    out[1] = (uint32_t)(n & 0xFFFFFFFFu);
+    out[2] = (uint32_t)(n >> 32);
+    out[3] = (uint32_t)stride;
+    out[4] = (uint32_t)units;
+    out[5] = tail_bytes;
+    out[6] = (uint32_t)tail_off;
+    out[7] = (uint32_t)p;
+    free(d);
+    return (int64_t)p;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Decoding: the exact inverse, with every field checked against the       */
+/* stream's bounds; a bad stream returns O_ERR_CORRUPT.                     */
+
+static int o_bp_unit_decode(const uint32_t *w, uint64_t avail, uint64_t nblocks, uint32_t *d)
+{
+    if (avail < 4)
+        return O_ERR_CORRUPT;
+    uint64_t pos = 4;
+    for (uint64_t j = 0; j < OBP_BLOCKS; j++) {
+        uint32_t b = (w[j / 4] >> (8 * (j % 4))) & 255u;
+        if (j >= nblocks) {
+            if (b != 0)
+                return O_ERR_CORRUPT;
+            continue;
+        }
+        if (b > 32 || pos + (uint64_t)OB * b / 32 > avail)
+            return O_ERR_CORRUPT;
+        oracle_unpack(w + pos, OB, b, d + j * OB);
+        pos += (uint64_t)OB * b / 32;
+    }
+    if (pos != avail)
+        return O_ERR_CORRUPT;
+    return O_OK;
+}
+
+/* Section 5: exceptions are first decoded in bulk for the whole page, then
+ * each block is unpacked and its exceptions patched in: the value at each
+ * listed position gains the next high part of array k = maxb - b, shifted
+ * left by b. */
+static int o_fp_page_decode(const uint32_t *w, uint64_t avail, uint64_t nblocks_expected,
+                            uint32_t *d)
+{
+    if (avail < 4)
+        return O_ERR_CORRUPT;
+    uint64_t nblocks = w[0], packed_words = w[1], meta_bytes = w[2];
+    uint32_t bitset = w[3];
+    if (nblocks != nblocks_expected)
+        return O_ERR_CORRUPT;
+    uint32_t nset = 0;
+    for (uint32_t k = 1; k <= 32; k++)
+        if (bitset & (1u << (k - 1)))
+            nset++;
+    uint64_t hdr_words = o_pad4(4 + nset);
+    if (hdr_words > avail)
+        return O_ERR_CORRUPT;
+    uint64_t cnt[33] = {0};
+    uint32_t hi = 4;
+    for (uint32_t k = 1; k <= 32; k++)
+        if (bitset & (1u << (k - 1))) {
+            cnt[k] = w[hi++];
+            if (cnt[k] == 0 || cnt[k] > nblocks * OB)
+                return O_ERR_CORRUPT;
+        }
+    uint64_t p = hdr_words;
+    uint64_t packed_at = p;
+    if (packed_words > avail - p)
+        return O_ERR_CORRUPT;
+    p += packed_words;
+    uint64_t meta_words = ((meta_bytes + 15) / 16) * 4;
+    if (meta_bytes < 3 * nblocks || meta_words > avail - p)
+        return O_ERR_CORRUPT;
+    const uint8_t *mbytes = (const uint8_t *)(w + p);
+    p += meta_words;
+    /* bulk-decode every exception array */
+    uint32_t *arr[33] = {0};
+    uint64_t used[33] = {0};
+    int rc = O_OK;
+    for (uint32_t k = 1; k <= 32; k++) {
+        if (cnt[k] == 0)
+            continue;
+        uint64_t padded = ((cnt[k] + OB - 1) / OB) * OB;
+        if (padded * k / 32 > avail - p) {
+            rc = O_ERR_CORRUPT;
+            goto done;
+        }
+        arr[k] = malloc(padded * sizeof(uint32_t));
+        oracle_unpack(w + p, padded, k, arr[k]);
+        p += padded * k / 32;
+    }
+    if (p != avail) {
+        rc = O_ERR_CORRUPT;
+        goto done;
+    }
+    uint64_t bitpos_words = 0;
+    uint64_t epos = 3 * nblocks;
+    for (uint64_t t = 0; t < nblocks; t++) {
+        uint32_t b = mbytes[t], maxb = mbytes[nblocks + t], c = mbytes[2 * nblocks + t];
+        if (b > 32 || maxb > 32 || maxb < b || c > OB || (c == 0) != (maxb == b)) {
+            rc = O_ERR_CORRUPT;
+            goto done;
+        }
+        if (bitpos_words + (uint64_t)OB * b / 32 > packed_words) {
+            rc = O_ERR_CORRUPT;
+            goto done;
+        }
+        oracle_unpack(w + packed_at + bitpos_words, OB, b, d + t * OB);
+        bitpos_words += (uint64_t)OB * b / 32;
+        uint32_t k = maxb - b;
+        for (uint32_t e = 0; e < c; e++) {
+            if (epos >= meta_bytes || arr[k] == NULL || used[k] >= cnt[k]) {
+                rc = O_ERR_CORRUPT;
+                goto done;
+            }
+            uint32_t at = mbytes[epos++];
+            if (at >= OB) {
+                rc = O_ERR_CORRUPT;
+                goto done;
+            }
+            d[t * OB + at] |= arr[k][used[k]++] << b;
+        }
+    }
+    if (bitpos_words != packed_words || epos != meta_bytes) {
+        rc = O_ERR_CORRUPT;
+        goto done;
+    }
+    for (uint32_t k = 1; k <= 32; k++)
+        if (used[k] != cnt[k])
+            rc = O_ERR_CORRUPT;
+done:
+    for (uint32_t k = 1; k <= 32; k++)
+        free(arr[k]);
+    return rc;
+}
+
+static int o_decode(int codec, const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n)
+{
+    if (in_words < 8)
+        return O_ERR_CORRUPT;
+    if (in[0] != (codec == 0 ? OMAGIC_BP : OMAGIC_FP))
+        return O_ERR_CORRUPT;
+    uint64_t hn = (uint64_t)in[1] | ((uint64_t)in[2] << 32);
+    int stride = (int)in[3];
+    if (hn != n || (stride != 0 && stride != 1 && stride != 4))
+        return O_ERR_CORRUPT;
+    uint64_t nfull = n / OB, tail = n % OB;
+    uint64_t units = o_units(codec, n);
+    uint64_t per = codec == 0 ? OBP_BLOCKS : OFP_BLOCKS;
+    uint64_t total = in[7], tail_off = in[6], tail_bytes = in[5];
+    if (in[4] != units || total > in_words || (tail == 0) != (tail_bytes == 0))
+        return O_ERR_CORRUPT;
+    uint64_t E = 1 + (uint64_t)stride;
+    uint64_t ndir = units + (tail ? 1 : 0);
+    uint64_t dir_end = 8 + o_pad4(E * ndir);
+    if (dir_end > total || tail_off > total)
+        return O_ERR_CORRUPT;
+    for (uint64_t u = 0; u < ndir; u++) {
+        const uint32_t *ent = in + 8 + u * E;
+        uint64_t off = ent[0];
+        uint64_t end = (u + 1 < units) ? in[8 + (u + 1) * E] : tail_off;
+        uint64_t start = (u == units) ? nfull * OB : u * per * OB;
+        uint64_t count;
+        int rc;
+        if (u < units) {
+            uint64_t nb = nfull - u * per;
+            if (nb > per)
+                nb = per;
+            count = nb * OB;
+            if (off < dir_end || end < off || end > total)
+                return O_ERR_CORRUPT;
+            rc = codec == 0 ? o_bp_unit_decode(in + off, end - off, nb, out + start)
+                            : o_fp_page_decode(in + off, end - off, nb, out + start);
+        } else {
+            count = tail;
+            if (off != tail_off || off + (tail_bytes + 3) / 4 != total)
+                return O_ERR_CORRUPT;
+            int64_t used = oracle_vbyte_decode((const uint8_t *)(in + off), tail_bytes,
+                                               (uint32_t)tail, out + start);
+            rc = (used == (int64_t)tail_bytes) ? O_OK : O_ERR_CORRUPT;
+        }
+        if (rc != O_OK)
+            return rc;
+        /* prefix sum of the unit from its stored bases (Section 3) */
+        for (uint64_t i = 0; i < count && stride != 0; i++) {
+            uint32_t prev = (i >= (uint64_t)stride) ? out[start + i - stride] : ent[1 + i];
+            out[start + i] = out[start + i] + prev;
+        }
+    }
+    if (ndir == 0 && total != dir_end)
+        return O_ERR_CORRUPT;
+    return O_OK;
+}
+
+int oracle_bp_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n)
+{
+    return o_decode(0, in, in_words, out, n);
+}
+
+int oracle_fp_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n)
+{
+    return o_decode(1, in, in_words, out, n);
+}
