@@ -1,0 +1,170 @@
+/*
+ * wavepack -- MI355X (gfx950) decoder for binary-packed and patched
+ * (SIMD-BP128 / SIMD-FastPFOR style) compressed uint32 arrays, after
+ * Lemire & Boytsov, "Decoding billions of integers per second through
+ * vectorization" (arXiv:1209.2137).
+ *
+ * C ABI. Plain pointers and sizes only.
+ *
+ * Conventions for every call below
+ *   - Pointers are DEVICE pointers (memory of the current HIP device) unless
+ *     the name starts with h_ (host memory).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are asynchronous on `stream`: they enqueue work and return.
+ *   - Compressed streams (`in`, `out` of the encoders) and decoded outputs
+ *     must be 16-byte aligned (hipMalloc and torch allocations are).
+ *   - The caller owns every buffer and keeps it alive until the stream work
+ *     has completed. The library never frees caller memory.
+ *   - Return value: WP_OK (0) or a negative WP_ERR_* code. Problems the host
+ *     can see (null pointers, bad stride, capacity, misalignment) return at
+ *     once and enqueue nothing. Problems inside a compressed stream are
+ *     found by the kernels: they record WP_ERR_CORRUPT in a per-device
+ *     error word (read and cleared by wp_check), skip the bad unit, and
+ *     never write outside [out, out + n).
+ *   - All arithmetic on values is uint32 modulo 2^32 (sums wrap).
+ *
+ * Stream layout (32-bit little-endian words; both codecs)
+ *   header, 8 words: magic ('WPB1' binary packing, 'WPF1' patched), n low,
+ *       n high, stride S (0, 1 or 4), n_units, tail_bytes, tail_off,
+ *       total_words
+ *   directory: one entry per unit, plus one for the tail when n % 128 != 0:
+ *       [word offset of the unit from the stream start, base_0..base_{S-1}]
+ *       with base_s = x[start - S + s] (0 before the array start), so every
+ *       unit decodes on its own; zero-padded to a multiple of 4 words
+ *   units: binary packing -- a meta-block of up to 16 blocks of 128 values
+ *       (2048 values): a 16-byte descriptor whose byte j is block j's width
+ *       b_j, then each block's 128 deltas packed at b_j bits in 4*b_j words
+ *       (field i at bits [i*b, i*b+b) of the block's words, least
+ *       significant bit first). Section 4 (bit layout) and Section 6.2
+ *       (SIMD-BP128: 16 blocks of 128 integers behind a 128-bit descriptor).
+ *       patched -- a page of up to 512 blocks (2^16 values), Section 5:
+ *       [nblocks, packed_words, meta_bytes, bitset] + one count per
+ *       non-empty exception array k (bit k-1 of bitset), padded to 4 words;
+ *       the blocks' low b bits (4*b words each); the metadata bytes
+ *       b[nblocks], maxb[nblocks], c[nblocks] and all exception positions,
+ *       padded to 16 bytes; then for each k ascending the high parts
+ *       (delta >> b) of the exceptions of blocks with maxb - b = k, packed
+ *       at k bits in groups of 128 (zero padded).
+ *   tail: Variable Byte (Section 2.4; 7 data bits per byte, low group
+ *       first, top bit set on the last byte) of the last n % 128 deltas,
+ *       zero-padded to a word.
+ *   Deltas: Section 3. S = 1: d_i = x_i - x_{i-1}; S = 4: d_i = x_i - x_{i-4};
+ *   S = 0: the values themselves. Decoding is the prefix sum.
+ */
+#ifndef WAVEPACK_H
+#define WAVEPACK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WP_OK 0
+#define WP_ERR_INVALID_ARG (-1) /* null pointer, bad stride, misaligned, n too large */
+#define WP_ERR_CAPACITY (-2)    /* out_cap_words below wp_max_compressed_words(codec, n) */
+#define WP_ERR_CORRUPT (-3)     /* reported by wp_check: a stream failed validation */
+#define WP_ERR_HIP (-4)         /* a HIP runtime call failed */
+
+#define WP_CODEC_BP 0 /* binary packing, 16 x 128-integer blocks per unit */
+#define WP_CODEC_FP 1 /* patched pages of 2^16 integers */
+
+/* Largest stream any input of n integers can produce, in 32-bit words.
+ * Host only, pure. Returns 0 when n is beyond the format (streams are
+ * addressed with 32-bit word offsets). */
+uint64_t wp_max_compressed_words(int32_t codec, uint64_t n);
+
+/* Binary-packing encoder (Section 6.2, SIMD-BP128; widths as in Section 6.2:
+ * b = bits of the OR of a block's deltas; remainder in Variable Byte).
+ *   in[n]            values to compress (any uint32; sorted input compresses best)
+ *   delta_stride     0 (no differencing), 1 (standard) or 4 (vectorised), Section 3
+ *   out[out_cap_words]  receives the stream; out_cap_words must be at least
+ *                    wp_max_compressed_words(WP_CODEC_BP, n)
+ *   out_words        device uint64: receives the stream length in words
+ *                    (written on the stream, no implicit synchronisation)
+ * Uses a library-owned scratch area per (device, stream), grown on demand. */
+int32_t bp_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,
+                  uint64_t out_cap_words, uint64_t *out_words, void *stream);
+
+/* Binary-packing decoder: writes out[0..n) from the stream in[0..in_words).
+ * Unpacks each 128-integer block at its width (Section 4), then runs the
+ * prefix sum of Section 3 from the unit's stored base. n must equal the n
+ * recorded in the stream header (checked on the device). Allocates nothing. */
+int32_t bp_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
+                  void *stream);
+
+/* Patched encoder (Section 5, FastPFOR with SIMD-FastPFOR padding): per
+ * 128-integer block the width b minimising 128*b + c*(8 + maxb - b) (c =
+ * values wider than b; equal costs keep the larger b); exceptions' high bits
+ * go to page-wide arrays by k = maxb - b. Arguments as bp_encode, with
+ * WP_CODEC_FP for the capacity. */
+int32_t fastpfor_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,
+                        uint64_t out_cap_words, uint64_t *out_words, void *stream);
+
+/* Patched decoder (Section 5): unpack each block's low bits, patch each
+ * exception with its high part from array k shifted left by b, then the
+ * prefix sum. Arguments as bp_decode. Allocates nothing. */
+int32_t fastpfor_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
+                        void *stream);
+
+/* In-place differential decoding (Section 3): data[i] += data[i - stride]
+ * in increasing index order, values before index 0 taken as `init`:
+ *   stride 1: data[i] = init + d_0 + ... + d_i
+ *   stride 4: data[i] = init + sum of d_j, j <= i, j = i (mod 4)
+ * One pass over the data (8 bytes of traffic per integer) with a
+ * decoupled look-back across tiles. Uses a library-owned scratch area per
+ * (device, stream) of 32 bytes per 8192 integers, grown on demand. */
+int32_t delta_decode_inplace(uint32_t *data, uint64_t n, uint32_t init, int32_t stride,
+                             void *stream);
+
+/* Synchronises `stream`, then returns and clears this device's error word:
+ * WP_OK, WP_ERR_CORRUPT, or WP_ERR_HIP if the synchronisation failed. */
+int32_t wp_check(void *stream);
+
+/* Static description of a code. */
+const char *wp_strerror(int32_t code);
+
+/* ---------------------------------------------------------------------- */
+/* Batched decoding of many lists in one launch (not in the paper: the GPU
+ * counterpart of decoding many posting lists). A plan turns a list
+ * registry into work items -- one per unit (meta-block or page) and per
+ * tail -- that a persistent kernel pulls from an atomic counter. */
+
+typedef struct wp_list {
+    uint64_t comp_off_words; /* stream start, in words from `pool` (multiple of 4) */
+    uint64_t comp_words;     /* stream length in words */
+    uint64_t out_off;        /* first output element, from `out_base` (multiple of 4) */
+    uint64_t n;              /* integers in the list */
+    int32_t codec;           /* WP_CODEC_BP or WP_CODEC_FP */
+    int32_t reserved;        /* must be 0 */
+} wp_list;
+
+typedef struct wp_tune {
+    int32_t waves;     /* waves per workgroup: 4 or 8 (0 = default) */
+    int32_t vpl;       /* integers per lane and pass: 4 or 8 (0 = default) */
+    int32_t wg_per_cu; /* persistent workgroups per compute unit (0 = default) */
+    int32_t use_graph; /* 1 = replay a captured hipGraph, 0 = plain launches */
+} wp_tune;
+
+/* Builds a plan: validates the registry on the host, builds and uploads the
+ * item array (stream-ordered copy on `stream`), and keeps `pool`/`out_base`.
+ * h_lists is host memory and may be freed on return. `tune` may be NULL.
+ * *h_plan receives an opaque handle owned by the caller (wp_batch_free). */
+int32_t wp_batch_plan(const uint32_t *pool, uint32_t *out_base, const wp_list *h_lists,
+                      uint64_t nlists, const wp_tune *tune, void **h_plan, void *stream);
+
+/* Decodes every list of the plan: resets the work counter and launches the
+ * persistent kernel, as one hipGraph replay when the plan's tune asks. */
+int32_t wp_batch_decode(void *h_plan, void *stream);
+
+/* Number of work items in a plan (host). */
+uint64_t wp_batch_items(const void *h_plan);
+
+/* Releases a plan (synchronises with its last launch first). */
+int32_t wp_batch_free(void *h_plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WAVEPACK_H */

@@ -531,7 +531,8 @@ static int o_fp_page_decode(const uint32_t *w, uint64_t avail, uint64_t nblocks_
                 goto done;
             }
             uint32_t at = mbytes[epos++];
-            if (at >= OB) {
+            /* positions lie in [0, 127], ascending inside a block */
+            if (at >= OB || (e > 0 && at <= mbytes[epos - 2])) {
                 rc = O_ERR_CORRUPT;
                 goto done;
             }

@@ -1,0 +1,204 @@
+"""wavepack: MI355X (gfx950) decoding of binary-packed and patched uint32
+streams (Lemire & Boytsov, arXiv:1209.2137), behind a C ABI.
+
+This module is argument marshalling only: every decode/encode step runs in
+the HIP kernels of ``libwavepack.so``. PyTorch provides device memory and
+streams. Tensors holding uint32 data may be ``torch.int32`` or
+``torch.uint32`` (same bits); outputs are allocated as ``torch.int32``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libwavepack.so")
+
+OK = 0
+ERR_INVALID_ARG = -1
+ERR_CAPACITY = -2
+ERR_CORRUPT = -3
+ERR_HIP = -4
+CODEC_BP = 0
+CODEC_FP = 1
+
+EXPORTS = (
+    "bp_encode", "bp_decode", "fastpfor_encode", "fastpfor_decode", "delta_decode_inplace",
+    "wp_max_compressed_words", "wp_check", "wp_strerror", "wp_set_decode_tune",
+    "wp_batch_plan", "wp_batch_decode", "wp_batch_items", "wp_batch_free",
+)
+
+_lib = None
+
+
+class WavepackError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {strerror(code)} ({code})" if what else f"{strerror(code)} ({code})")
+
+
+class wp_list(ctypes.Structure):
+    _fields_ = [("comp_off_words", ctypes.c_uint64), ("comp_words", ctypes.c_uint64),
+                ("out_off", ctypes.c_uint64), ("n", ctypes.c_uint64),
+                ("codec", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class wp_tune(ctypes.Structure):
+    _fields_ = [("waves", ctypes.c_int32), ("vpl", ctypes.c_int32),
+                ("wg_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+def lib():
+    """The loaded C library. Raises if it has not been built: there is no
+    fallback path."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(wavepack has no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, i32, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint32
+    for name in ("bp_encode", "fastpfor_encode"):
+        f = getattr(L, name)
+        f.argtypes = [vp, u64, i32, vp, u64, vp, vp]
+        f.restype = i32
+    for name in ("bp_decode", "fastpfor_decode"):
+        f = getattr(L, name)
+        f.argtypes = [vp, u64, vp, u64, vp]
+        f.restype = i32
+    L.delta_decode_inplace.argtypes = [vp, u64, u32, i32, vp]
+    L.delta_decode_inplace.restype = i32
+    L.wp_max_compressed_words.argtypes = [i32, u64]
+    L.wp_max_compressed_words.restype = u64
+    L.wp_check.argtypes = [vp]
+    L.wp_check.restype = i32
+    L.wp_strerror.argtypes = [i32]
+    L.wp_strerror.restype = ctypes.c_char_p
+    L.wp_set_decode_tune.argtypes = [i32, i32, i32]
+    L.wp_set_decode_tune.restype = i32
+    L.wp_batch_plan.argtypes = [vp, vp, ctypes.POINTER(wp_list), u64, ctypes.POINTER(wp_tune),
+                                ctypes.POINTER(vp), vp]
+    L.wp_batch_plan.restype = i32
+    L.wp_batch_decode.argtypes = [vp, vp]
+    L.wp_batch_decode.restype = i32
+    L.wp_batch_items.argtypes = [vp]
+    L.wp_batch_items.restype = u64
+    L.wp_batch_free.argtypes = [vp]
+    L.wp_batch_free.restype = i32
+    _lib = L
+    return L
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().wp_strerror(code).decode()
+    except RuntimeError:
+        return f"code {code}"
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise WavepackError(rc, what)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need_u32(t, what):
+    import torch
+    if t.dtype not in (torch.int32, torch.uint32) or not t.is_contiguous() or not t.is_cuda:
+        raise TypeError(f"{what} must be a contiguous int32/uint32 CUDA tensor")
+
+
+def max_compressed_words(codec: int, n: int) -> int:
+    return int(lib().wp_max_compressed_words(codec, n))
+
+
+def set_decode_tune(codec: int, waves: int, vpl: int):
+    _check(lib().wp_set_decode_tune(codec, waves, vpl), "set_decode_tune")
+
+
+def _decode(fn, comp, n, out, stream, name):
+    import torch
+    _need_u32(comp, "comp")
+    if out is None:
+        out = torch.empty(max(int(n), 0), dtype=torch.int32, device=comp.device)
+    _need_u32(out, "out")
+    if out.numel() < n:
+        raise ValueError("out is smaller than n")
+    _check(fn(_ptr(comp), comp.numel(), _ptr(out), int(n), _stream(stream)), name)
+    return out
+
+
+def bp_decode(comp, n: int, out=None, stream=None):
+    """Decodes a binary-packing stream (device tensor) into out[0:n]."""
+    return _decode(lib().bp_decode, comp, n, out, stream, "bp_decode")
+
+
+def fastpfor_decode(comp, n: int, out=None, stream=None):
+    """Decodes a patched (FastPFOR page) stream (device tensor) into out[0:n]."""
+    return _decode(lib().fastpfor_decode, comp, n, out, stream, "fastpfor_decode")
+
+
+def _encode(fn, codec, x, stride, out, out_words, stream, name):
+    import torch
+    _need_u32(x, "x")
+    n = x.numel()
+    cap = max_compressed_words(codec, n)
+    if cap == 0:
+        raise ValueError("n beyond the stream format")
+    if out is None:
+        out = torch.empty(cap, dtype=torch.int32, device=x.device)
+    _need_u32(out, "out")
+    if out_words is None:
+        out_words = torch.zeros(1, dtype=torch.int64, device=x.device)
+    _check(fn(_ptr(x), n, int(stride), _ptr(out), out.numel(), _ptr(out_words), _stream(stream)), name)
+    return out, out_words
+
+
+def bp_encode(x, stride: int = 1, out=None, out_words=None, stream=None):
+    """Encodes x (device uint32) as a binary-packing stream. Returns
+    (buffer, words) where words is a one-element device int64 tensor."""
+    return _encode(lib().bp_encode, CODEC_BP, x, stride, out, out_words, stream, "bp_encode")
+
+
+def fastpfor_encode(x, stride: int = 1, out=None, out_words=None, stream=None):
+    """Encodes x (device uint32) as a patched-page stream."""
+    return _encode(lib().fastpfor_encode, CODEC_FP, x, stride, out, out_words, stream, "fastpfor_encode")
+
+
+def encode_trimmed(x, codec: int = CODEC_BP, stride: int = 1, stream=None):
+    """Encodes and returns a tensor of exactly the stream's length
+    (synchronises the stream to read the length)."""
+    enc = bp_encode if codec == CODEC_BP else fastpfor_encode
+    buf, words = enc(x, stride, stream=stream)
+    check(stream)
+    return buf[: int(words.item())].clone()
+
+
+def delta_decode_inplace(data, init: int = 0, stride: int = 1, stream=None):
+    """In-place prefix sum (differential decoding, Section 3) of a device tensor."""
+    _need_u32(data, "data")
+    _check(lib().delta_decode_inplace(_ptr(data), data.numel(), int(init) & 0xFFFFFFFF, int(stride),
+                                      _stream(stream)), "delta_decode_inplace")
+    return data
+
+
+def check(stream=None):
+    """Synchronises the stream and raises WavepackError if a kernel flagged
+    a corrupt stream since the last check."""
+    rc = lib().wp_check(_stream(stream))
+    _check(rc, "device check")
+
+
+def check_code(stream=None) -> int:
+    return int(lib().wp_check(_stream(stream)))

@@ -1,0 +1,620 @@
+// Device building blocks of the wavepack decoders (gfx950, wave64).
+//
+// Every decoder here is a workgroup-wide routine: all threads of the
+// workgroup call it together (it contains barriers). A workgroup has WAVES
+// wavefronts; in each pass a lane owns VPL consecutive integers of one
+// 128-integer block (VPL = 4 or 8, so a block spans 32 or 16 lanes and a
+// wave covers 2 or 4 blocks).
+//
+// Per pass the steps are the ones of the paper's decoder, fused:
+//   1. the packed words of the pass are staged from HBM into LDS with
+//      16-byte loads (coalesced);
+//   2. each lane extracts its VPL fields with a funnel shift of two LDS
+//      words and a mask (Section 4: field i at bits [i*b, i*b+b));
+//   3. patched pages OR each exception's high bits, shifted left by b, into
+//      its position (Section 5);
+//   4. the differential decoding of Section 3 is an inclusive prefix sum:
+//      serial inside the lane, a DPP scan across the wavefront, an LDS
+//      exchange across wavefronts, seeded by the unit's stored base;
+//   5. lanes store their integers with 16-byte stores.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wp {
+
+constexpr uint32_t kBlock = 128;      // integers per block (Section 6.2)
+constexpr uint32_t kBpBlocks = 16;    // blocks per binary-packing meta-block (Section 6.2)
+constexpr uint32_t kFpBlocks = 512;   // blocks per patched page, 2^16 integers (Section 5)
+constexpr uint32_t kBpUnitInts = kBlock * kBpBlocks;
+constexpr uint32_t kFpUnitInts = kBlock * kFpBlocks;
+constexpr uint32_t kMagicBP = 0x31425057u;  // "WPB1"
+constexpr uint32_t kMagicFP = 0x31465057u;  // "WPF1"
+constexpr uint32_t kHdrWords = 8;
+constexpr uint32_t kMaxTailBytes = 127 * 5;
+constexpr int kErrCorrupt = -3;
+
+__host__ __device__ constexpr uint32_t pad4(uint32_t w) { return (w + 3u) & ~3u; }
+
+__device__ __forceinline__ uint32_t lane_id()
+{
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Number of set bits of `m` in lanes below this one.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Inclusive prefix sum inside each row of 16 lanes (row_shr 1, 2, 4, 8).
+__device__ __forceinline__ uint32_t row_scan_incl(uint32_t v)
+{
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, false);
+    return v;
+}
+
+// Inclusive prefix sum over the 64 lanes: row scans, then row_bcast:15
+// (rows 1 and 3 add the last lane of the row before) and row_bcast:31
+// (rows 2 and 3 add lane 31).
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v)
+{
+    v = row_scan_incl(v);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_read(uint32_t v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+__device__ __forceinline__ uint32_t width_mask(uint32_t b) { return b >= 32u ? 0xffffffffu : ((1u << b) - 1u); }
+
+// Field of `mask`'s width starting at bit `bit` of the word string `w`:
+// funnel shift of two neighbouring words (v_alignbit_b32 uses bit & 31).
+__device__ __forceinline__ uint32_t fetch_field(const uint32_t *w, uint32_t bit, uint32_t mask)
+{
+    const uint32_t i = bit >> 5;
+    return __builtin_amdgcn_alignbit(w[i + 1], w[i], bit) & mask;
+}
+
+// Stream header, read with uniform (scalar) loads.
+struct Hdr {
+    uint32_t magic, n_lo, n_hi, stride, n_units, tail_bytes, tail_off, total;
+};
+
+__device__ __forceinline__ Hdr load_hdr(const uint32_t *in)
+{
+    Hdr h;
+    h.magic = in[0];
+    h.n_lo = in[1];
+    h.n_hi = in[2];
+    h.stride = in[3];
+    h.n_units = in[4];
+    h.tail_bytes = in[5];
+    h.tail_off = in[6];
+    h.total = in[7];
+    return h;
+}
+
+// Geometry of a pass for a (WAVES, VPL) configuration.
+template <int WAVES, int VPL>
+struct Geo {
+    static_assert(WAVES == 2 || WAVES == 4 || WAVES == 8 || WAVES == 16, "waves");
+    static_assert(VPL == 4 || VPL == 8, "integers per lane");
+    static constexpr int T = 64 * WAVES;        // threads
+    static constexpr int LPB = kBlock / VPL;    // lanes per block
+    static constexpr int BPW = 64 / LPB;        // blocks per wave
+    static constexpr int BPP = WAVES * BPW;     // blocks per pass
+    static constexpr int WPP = BPP * kBlock;    // packed words per pass, at most
+    static constexpr int U4PT = WPP / 4 / T;    // 16-byte staging loads per thread
+    static_assert(U4PT * 4 * T == WPP, "staging split");
+};
+
+// Prefix sum of one pass (Section 3), in place on the lane's VPL deltas.
+// stride 1: x_i = x_{i-1} + d_i; stride 4: x_i = x_{i-4} + d_i (a lane's
+// VPL consecutive integers hold VPL/4 of each residue class mod 4, passes
+// start at multiples of 128); stride 0: no change. `carry` holds the value(s)
+// before the pass (per residue class for stride 4) and is advanced to the
+// end of the pass. wtot is a WAVES x 4 LDS scratch; contains one barrier.
+template <int WAVES, int VPL>
+__device__ __forceinline__ void scan_pass(uint32_t (&v)[VPL], uint32_t S, uint32_t (&carry)[4],
+                                          uint32_t (*wtot)[4])
+{
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform(threadIdx.x >> 6);
+    if (S == 1) {
+#pragma unroll
+        for (int r = 1; r < VPL; ++r)
+            v[r] += v[r - 1];
+        const uint32_t incl = wave_scan_incl(v[VPL - 1]);
+        const uint32_t excl = incl - v[VPL - 1];
+        if (lane == 63)
+            wtot[wave][0] = incl;
+        __syncthreads();
+        uint32_t before = carry[0], all = 0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            const uint32_t t = wtot[w][0];
+            before += (w < (int)wave) ? t : 0u;
+            all += t;
+        }
+        const uint32_t add = before + excl;
+#pragma unroll
+        for (int r = 0; r < VPL; ++r)
+            v[r] += add;
+        carry[0] += all;
+    } else if (S == 4) {
+#pragma unroll
+        for (int r = 4; r < VPL; ++r)
+            v[r] += v[r - 4];
+        uint32_t excl[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t t = v[VPL - 4 + c];
+            const uint32_t incl = wave_scan_incl(t);
+            excl[c] = incl - t;
+            if (lane == 63)
+                wtot[wave][c] = incl;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            uint32_t before = carry[c], all = 0;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) {
+                const uint32_t t = wtot[w][c];
+                before += (w < (int)wave) ? t : 0u;
+                all += t;
+            }
+            excl[c] += before;
+            carry[c] += all;
+        }
+#pragma unroll
+        for (int r = 0; r < VPL; ++r)
+            v[r] += excl[r & 3];
+    }
+}
+
+template <int VPL>
+__device__ __forceinline__ void store_lane(uint32_t *dst, const uint32_t (&v)[VPL])
+{
+#pragma unroll
+    for (int r = 0; r < VPL; r += 4)
+        *reinterpret_cast<uint4 *>(dst + r) = make_uint4(v[r], v[r + 1], v[r + 2], v[r + 3]);
+}
+
+template <int VPL>
+__device__ __forceinline__ void unpack_lane(const uint32_t *words, uint32_t bit0, uint32_t b,
+                                            uint32_t (&v)[VPL])
+{
+    const uint32_t mask = width_mask(b);
+    uint32_t bit = bit0;
+#pragma unroll
+    for (int r = 0; r < VPL; ++r) {
+        v[r] = fetch_field(words, bit, mask);
+        bit += b;
+    }
+}
+
+// ------------------------------------------------------------------------
+// LDS arena shared by all roles (a workgroup plays one role at a time).
+
+template <int WAVES, int VPL>
+struct BpLds {
+    uint4 pk[kBpUnitInts / 4 + 1];  // staged blocks of a meta-block (+1 word of over-read)
+    uint32_t b[kBpBlocks];
+    uint32_t off[kBpBlocks];
+    uint32_t wtot[2][WAVES][4];
+};
+
+template <int WAVES, int VPL>
+struct FpLds {
+    uint4 pk[Geo<WAVES, VPL>::WPP / 4 + 1];             // staged packed words of one pass
+    alignas(16) uint32_t ptc[Geo<WAVES, VPL>::BPP * kBlock];  // patch area of one pass
+    uint8_t b[kFpBlocks];
+    uint8_t mb[kFpBlocks];
+    uint8_t c[kFpBlocks];
+    uint32_t blkoff[kFpBlocks + 1];  // word offset of each block in the packed region
+    uint32_t posoff[kFpBlocks + 1];  // offset of each block's positions
+    uint32_t rank[kFpBlocks];        // index of the block's first exception in its array
+    uint32_t ktot[WAVES][33];
+    uint32_t kcar[33];
+    uint32_t excbase[33];            // word offset of array k from the page start
+    uint32_t kcnt[33];
+    uint32_t stot[WAVES][2];
+    uint32_t wtot[2][WAVES][4];
+    uint32_t bad;
+};
+
+template <int WAVES>
+struct TailLds {
+    uint32_t words[(kMaxTailBytes + 3) / 4 + 4];
+    uint32_t vals[kBlock];
+    uint32_t cnt[16 * 2];
+    uint32_t bad;
+};
+
+template <int WAVES, int VPL>
+union DecodeLds {
+    BpLds<WAVES, VPL> bp;
+    FpLds<WAVES, VPL> fp;
+    TailLds<WAVES> tail;
+};
+
+// ------------------------------------------------------------------------
+// Binary-packing meta-block (Section 6.2): descriptor + up to 16 blocks.
+// `unit` points at the descriptor (16-byte aligned), `nwords` is the unit's
+// length in words, `nb` the number of full blocks it must hold, `out` the
+// unit's first output integer. Returns false (uniformly) on a bad unit,
+// before writing anything.
+template <int WAVES, int VPL>
+__device__ bool bp_unit(const uint32_t *__restrict__ unit, uint32_t nwords, uint32_t nb, uint32_t S,
+                        const uint32_t (&base)[4], uint32_t *__restrict__ out, BpLds<WAVES, VPL> &L)
+{
+    using G = Geo<WAVES, VPL>;
+    const uint32_t tid = threadIdx.x;
+    if (nwords < 4)
+        return false;
+    // widths from the 128-bit descriptor (uniform loads)
+    const uint32_t d[4] = {unit[0], unit[1], unit[2], unit[3]};
+    uint32_t sum = 0;
+    bool ok = true;
+#pragma unroll
+    for (uint32_t j = 0; j < kBpBlocks; ++j) {
+        const uint32_t b = (d[j >> 2] >> (8 * (j & 3))) & 255u;
+        ok = ok && b <= 32 && (j < nb || b == 0);
+        sum += b;
+    }
+    ok = ok && nwords == 4 + 4 * sum;
+    if (!ok)
+        return false;
+    const uint4 *src = reinterpret_cast<const uint4 *>(unit + 4);
+    const uint32_t n4 = sum;  // (4 * sum words) / 4
+    for (uint32_t i = tid; i < n4; i += G::T)
+        L.pk[i] = src[i];
+    if (tid < kBpBlocks) {
+        uint32_t pre = 0;
+        for (uint32_t j = 0; j < tid; ++j)
+            pre += (d[j >> 2] >> (8 * (j & 3))) & 255u;
+        L.b[tid] = (d[tid >> 2] >> (8 * (tid & 3))) & 255u;
+        L.off[tid] = 4 * pre;
+    }
+    __syncthreads();
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform(tid >> 6);
+    const uint32_t q = lane % G::LPB;
+    const uint32_t *words = reinterpret_cast<const uint32_t *>(L.pk);
+    uint32_t carry[4] = {base[0], base[1], base[2], base[3]};
+#pragma unroll
+    for (int p = 0; p < (int)kBpBlocks / G::BPP; ++p) {
+        const uint32_t j = p * G::BPP + wave * G::BPW + lane / G::LPB;
+        const uint32_t b = L.b[j];
+        uint32_t v[VPL];
+        unpack_lane<VPL>(words, L.off[j] * 32 + VPL * q * b, b, v);
+        scan_pass<WAVES, VPL>(v, S, carry, L.wtot[p & 1]);
+        if (j < nb)
+            store_lane<VPL>(out + j * kBlock + VPL * q, v);
+    }
+    return true;
+}
+
+// ------------------------------------------------------------------------
+// Variable Byte tail (Section 2.4, remainder after the last block as in
+// Section 6.2): up to 127 integers of 1..5 bytes, low 7-bit group first,
+// top bit set on the last byte. Parallel parse: each byte is looked at by
+// one lane; terminator bytes are counted with ballots to give each integer
+// its index; the terminator's lane gathers the integer's bytes.
+template <int WAVES>
+__device__ bool tail_decode(const uint32_t *__restrict__ tw, uint32_t tail_bytes, uint32_t count,
+                            uint32_t S, const uint32_t (&base)[4], uint32_t *__restrict__ out,
+                            TailLds<WAVES> &L)
+{
+    constexpr int T = 64 * WAVES;
+    constexpr int R = (kMaxTailBytes + T - 1) / T;
+    static_assert(R * WAVES <= 32, "tail counters");
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform(tid >> 6);
+    if (count == 0 || count >= kBlock || tail_bytes < count || tail_bytes > 5 * count)
+        return false;
+    const uint32_t nw = (tail_bytes + 3) / 4;
+    for (uint32_t i = tid; i < nw; i += T)
+        L.words[i] = tw[i];
+    if (tid == 0)
+        L.bad = 0;
+    __syncthreads();
+    const uint8_t *by = reinterpret_cast<const uint8_t *>(L.words);
+    uint64_t m[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t i = r * T + tid;
+        const bool f = i < tail_bytes && (by[i] & 0x80u);
+        m[r] = ballot(f);
+        if (lane == 0)
+            L.cnt[r * WAVES + wave] = (uint32_t)__builtin_popcountll(m[r]);
+    }
+    __syncthreads();
+    uint32_t total = 0;
+    for (int c = 0; c < R * WAVES; ++c)
+        total += L.cnt[c];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t i = r * T + tid;
+        const bool f = i < tail_bytes && (by[i] & 0x80u);
+        if (f) {
+            uint32_t idx = lanes_below(m[r]);
+            for (int c = 0; c < r * WAVES + (int)wave; ++c)
+                idx += L.cnt[c];
+            uint32_t s = i, len = 1;
+            while (s > 0 && !(by[s - 1] & 0x80u) && len <= 5) {
+                --s;
+                ++len;
+            }
+            uint64_t v = 0;
+            for (uint32_t k = 0; k < len && k < 5; ++k)
+                v |= (uint64_t)(by[s + k] & 0x7fu) << (7 * k);
+            if (len > 5 || v > 0xffffffffull || idx >= count)
+                L.bad = 1;
+            else
+                L.vals[idx] = (uint32_t)v;
+        }
+    }
+    __syncthreads();
+    if (L.bad || total != count || !(by[tail_bytes - 1] & 0x80u))
+        return false;
+    if (wave == 0) {
+        if (S == 4) {
+            // class c = row, element m of the class is integer 4m + c
+            const uint32_t c = lane >> 4, mm = 2 * (lane & 15);
+            const uint32_t i0 = 4 * mm + c, i1 = 4 * (mm + 1) + c;
+            uint32_t v0 = i0 < count ? L.vals[i0] : 0u;
+            uint32_t v1 = i1 < count ? L.vals[i1] : 0u;
+            v1 += v0;
+            const uint32_t incl = row_scan_incl(v1);
+            const uint32_t add = incl - v1 + base[c];
+            if (i0 < count)
+                out[i0] = v0 + add;
+            if (i1 < count)
+                out[i1] = v1 + add;
+        } else {
+            const uint32_t i0 = 2 * lane, i1 = 2 * lane + 1;
+            uint32_t v0 = i0 < count ? L.vals[i0] : 0u;
+            uint32_t v1 = i1 < count ? L.vals[i1] : 0u;
+            if (S == 1) {
+                v1 += v0;
+                const uint32_t incl = wave_scan_incl(v1);
+                const uint32_t add = incl - v1 + base[0];
+                v0 += add;
+                v1 += add;
+            }
+            if (i0 < count)
+                out[i0] = v0;
+            if (i1 < count)
+                out[i1] = v1;
+        }
+    }
+    return true;
+}
+
+// ------------------------------------------------------------------------
+// Patched page (Section 5). `page` points at the page header (16-byte
+// aligned), `nwords` its length, `nb` the number of blocks it must hold.
+// Setup: block offsets in the packed region, offsets into the position
+// bytes and, per block, the index of its first exception inside its array
+// k = maxb - b (the paper appends exceptions to array k in block order, so
+// this is the number of exceptions of earlier blocks with the same k).
+// Then passes of BPP blocks: stage, unpack, patch, scan, store.
+template <int WAVES, int VPL>
+__device__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint32_t nb, uint32_t S,
+                        const uint32_t (&base)[4], uint32_t *__restrict__ out, FpLds<WAVES, VPL> &L)
+{
+    using G = Geo<WAVES, VPL>;
+    constexpr int T = G::T;
+    static_assert(T <= (int)kFpBlocks, "setup maps at most one thread per block and round");
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform(tid >> 6);
+    if (nwords < 4)
+        return false;
+    const uint32_t h_nb = page[0], packed_words = page[1], meta_bytes = page[2], bitset = page[3];
+    const uint32_t nset = __builtin_popcount(bitset);
+    const uint32_t hdr_w = pad4(4 + nset);
+    const uint32_t meta_w = ((meta_bytes + 15u) / 16u) * 4u;
+    if (h_nb != nb || nb == 0 || hdr_w > nwords || packed_words > nwords - hdr_w ||
+        meta_bytes < 3 * nb || meta_bytes > 3 * nb + 127 * nb || meta_w > nwords - hdr_w - packed_words ||
+        (packed_words & 3u))
+        return false;
+    const uint32_t exc_at = hdr_w + packed_words + meta_w;
+    const uint8_t *meta = reinterpret_cast<const uint8_t *>(page + hdr_w + packed_words);
+
+    // exception array directory: lanes 0..31 of wave 0 own k = lane + 1
+    if (wave == 0) {
+        const bool kl = lane < 32;
+        const uint32_t k = lane + 1;
+        const bool set = kl && ((bitset >> (lane & 31u)) & 1u);
+        const uint32_t ci = kl ? (uint32_t)__builtin_popcount(bitset & ((1u << (lane & 31u)) - 1u)) : 0u;
+        const uint32_t cnt = set ? page[4 + ci] : 0u;
+        const bool badk = set && (cnt == 0 || cnt > nb * kBlock);
+        const uint32_t wk = (set && !badk) ? ((cnt + kBlock - 1) / kBlock) * 4u * k : 0u;
+        const uint32_t incl = wave_scan_incl(wk);
+        const uint32_t tot = wave_read(incl, 63);
+        const uint64_t anybad = ballot(badk);
+        if (kl) {
+            L.excbase[k] = exc_at + incl - wk;
+            L.kcnt[k] = cnt;
+        }
+        if (lane < 33)
+            L.kcar[lane] = 0;
+        if (lane == 32) {
+            L.excbase[0] = exc_at;
+            L.kcnt[0] = 0;
+        }
+        if (lane == 0)
+            L.bad = (anybad != 0 || exc_at + tot != nwords) ? 1u : 0u;
+    }
+    for (uint32_t t = tid; t < kFpBlocks; t += T) {
+        uint32_t b = 0, mb = 0, c = 0;
+        if (t < nb) {
+            b = meta[t];
+            mb = meta[nb + t];
+            c = meta[2 * nb + t];
+        }
+        L.b[t] = (uint8_t)b;
+        L.mb[t] = (uint8_t)mb;
+        L.c[t] = (uint8_t)c;
+    }
+    for (uint32_t i = tid; i < WAVES * 33; i += T)
+        (&L.ktot[0][0])[i] = 0;
+    __syncthreads();
+    // validate block metadata
+    for (uint32_t t = tid; t < nb; t += T) {
+        const uint32_t b = L.b[t], mb = L.mb[t], c = L.c[t];
+        if (b > 32 || mb > 32 || mb < b || c >= kBlock || ((c == 0) != (mb == b)))
+            L.bad = 1;
+    }
+    // block-wide scans of packed words, position counts and per-k ranks
+    uint32_t carry_w = 0, carry_p = 0;
+    for (uint32_t r0 = 0; r0 < kFpBlocks; r0 += T) {
+        const uint32_t t = r0 + tid;
+        const uint32_t bw = 4u * L.b[t];
+        const uint32_t cc = L.c[t];
+        const uint32_t kk = (uint32_t)L.mb[t] - (uint32_t)L.b[t];
+        const uint32_t iw = wave_scan_incl(bw);
+        const uint32_t ip = wave_scan_incl(cc);
+        if (lane == 63) {
+            L.stot[wave][0] = iw;
+            L.stot[wave][1] = ip;
+        }
+        // rank among the wave's earlier blocks of the same k
+        uint32_t rk = 0;
+        uint64_t todo = ballot(cc > 0);
+        while (todo) {
+            const uint32_t lead = (uint32_t)__builtin_ctzll(todo);
+            const uint32_t k0 = wave_read(kk, lead);
+            const bool mine = cc > 0 && kk == k0;
+            const uint64_t mm = ballot(mine);
+            const uint32_t x = mine ? cc : 0u;
+            const uint32_t incl = wave_scan_incl(x);
+            if (mine)
+                rk = incl - x;
+            if (lane == 0)
+                L.ktot[wave][k0 > 32 ? 0 : k0] = wave_read(incl, 63);
+            todo &= ~mm;
+        }
+        __syncthreads();
+        uint32_t bw_before = carry_w, p_before = carry_p, all_w = 0, all_p = 0, k_before = 0;
+        for (int w = 0; w < WAVES; ++w) {
+            const uint32_t a = L.stot[w][0], c2 = L.stot[w][1];
+            if (w < (int)wave) {
+                bw_before += a;
+                p_before += c2;
+            }
+            all_w += a;
+            all_p += c2;
+        }
+        if (cc > 0 && kk <= 32) {
+            k_before = L.kcar[kk];
+            for (int w = 0; w < (int)wave; ++w)
+                k_before += L.ktot[w][kk];
+        }
+        L.blkoff[t] = bw_before + iw - bw;
+        L.posoff[t] = p_before + ip - cc;
+        L.rank[t] = k_before + rk;
+        carry_w += all_w;
+        carry_p += all_p;
+        __syncthreads();
+        if (tid < 33) {
+            uint32_t s = 0;
+            for (int w = 0; w < WAVES; ++w) {
+                s += L.ktot[w][tid];
+                L.ktot[w][tid] = 0;
+            }
+            L.kcar[tid] += s;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        L.blkoff[kFpBlocks] = carry_w;
+        if (carry_w != packed_words || 3 * nb + carry_p != meta_bytes)
+            L.bad = 1;
+    }
+    if (tid >= 1 && tid <= 32 && L.kcar[tid] != L.kcnt[tid])
+        L.bad = 1;
+    __syncthreads();
+    if (L.bad)
+        return false;
+
+    // passes of BPP blocks
+    const uint32_t *packed = page + hdr_w;
+    const uint32_t q = lane % G::LPB;
+    const uint32_t hb = wave * G::BPW + lane / G::LPB;  // block within the pass
+    const uint32_t *words = reinterpret_cast<const uint32_t *>(L.pk);
+    uint32_t carry[4] = {base[0], base[1], base[2], base[3]};
+    const uint32_t npass = (nb + G::BPP - 1) / G::BPP;
+    for (uint32_t p = 0; p < npass; ++p) {
+        const uint32_t f = p * G::BPP;
+        const uint32_t last = f + G::BPP < nb ? f + G::BPP : nb;
+        const uint32_t w0 = L.blkoff[f];
+        const uint32_t w1 = last < nb ? L.blkoff[last] : packed_words;
+        const uint4 *src = reinterpret_cast<const uint4 *>(packed + w0);
+        const uint32_t n4 = (w1 - w0) / 4;
+#pragma unroll
+        for (int r = 0; r < G::U4PT; ++r) {
+            const uint32_t i = tid + r * T;
+            if (i < n4)
+                L.pk[i] = src[i];
+        }
+        __syncthreads();
+        const uint32_t j = f + hb;
+        const bool live = j < nb;
+        const uint32_t b = live ? L.b[j] : 0u;
+        uint32_t v[VPL];
+        unpack_lane<VPL>(words, (live ? L.blkoff[j] - w0 : 0u) * 32 + VPL * q * b, b, v);
+        // exceptions: values go through LDS so that any lane can patch any position
+        uint32_t *pt = L.ptc + hb * kBlock;
+        store_lane<VPL>(pt + VPL * q, v);
+        __syncthreads();
+        const uint32_t c = live ? L.c[j] : 0u;
+        if (c) {
+            const uint32_t k = (uint32_t)L.mb[j] - b;
+            const uint32_t kmask = width_mask(k);
+            const uint32_t rk = L.rank[j];
+            const uint8_t *pos = meta + 3 * nb + L.posoff[j];
+            const uint32_t *arr = page + L.excbase[k];
+            for (uint32_t e = q; e < c; e += G::LPB) {
+                const uint32_t at = pos[e] & (kBlock - 1);
+                if (pos[e] >= kBlock || (e > 0 && pos[e - 1] >= pos[e]))
+                    L.bad = 1;
+                const uint32_t bit = (rk + e) * k;
+                const uint32_t wi = bit >> 5;
+                const uint32_t lo = arr[wi];
+                const uint32_t hi = ((bit & 31u) + k > 32u) ? arr[wi + 1] : 0u;
+                const uint32_t hv = __builtin_amdgcn_alignbit(hi, lo, bit) & kmask;
+                pt[at] |= hv << b;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < VPL; r += 4) {
+            const uint4 x = *reinterpret_cast<const uint4 *>(pt + VPL * q + r);
+            v[r] = x.x;
+            v[r + 1] = x.y;
+            v[r + 2] = x.z;
+            v[r + 3] = x.w;
+        }
+        scan_pass<WAVES, VPL>(v, S, carry, L.wtot[p & 1]);
+        if (live)
+            store_lane<VPL>(out + j * kBlock + VPL * q, v);
+    }
+    return true;
+}
+
+}  // namespace wp

@@ -1,0 +1,39 @@
+// Host-side state shared by the wavepack translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wavepack.h"
+
+namespace wp {
+
+// Per-device state: the error word kernels report corrupt streams into,
+// and the device's compute-unit count.
+struct DevState {
+    int *err = nullptr;
+    int cus = 0;
+    int device = -1;
+};
+
+// Returns the current device's state, creating it on first use
+// (one 16-byte allocation per device). nullptr if HIP fails.
+DevState *dev_state();
+
+// Scratch memory owned by the library for one (device, stream) pair: calls
+// on one stream run in order, so they can share it. Grows on demand (the
+// old buffer is released after synchronising the stream). nullptr on failure.
+void *stream_scratch(hipStream_t stream, size_t bytes);
+
+// Decoder configuration for the single-list entry points.
+struct Tune {
+    int waves;
+    int vpl;
+};
+Tune decode_tune(int codec);
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace wp

@@ -1,0 +1,287 @@
+// delta_decode_inplace: the in-place prefix sum of Section 3 over a whole
+// device array, in one pass (read 4 B + write 4 B per integer).
+//
+// Tiles of 4096 integers (256 threads x 4 rows x 4 integers) take their
+// index from an atomic counter, so a tile's predecessors always started
+// first. Each tile scans locally, publishes its aggregate, then looks back
+// over its predecessors (a whole wavefront reads 64 of them at once) until
+// it meets one that has published its inclusive prefix (decoupled look-back,
+// Merrill & Garland). Each status is one 64-bit word {flag, value} written
+// and read with device-scope relaxed atomics, so flag and value always
+// travel together and no cache-wide release is needed. Stride 4 keeps four
+// independent sums (residue classes mod 4): four status words per kind.
+#include <mutex>
+#include <unordered_map>
+
+#include "wp_device.hpp"
+#include "wp_host.hpp"
+
+namespace wp {
+
+constexpr int kScanWaves = 4;
+constexpr int kScanT = 64 * kScanWaves;
+constexpr int kScanRows = 4;
+constexpr uint32_t kTileInts = kScanT * kScanRows * 4;  // 4096
+constexpr uint64_t kFlagAgg = 1ull << 32;
+constexpr uint64_t kFlagInc = 2ull << 32;
+constexpr int kStatusWords = 8;  // per tile: aggregate[4], inclusive[4]
+
+__device__ __forceinline__ void st_status(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t ld_status(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_fill_zero(uint64_t *__restrict__ p, uint64_t count)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count)
+        p[i] = 0;
+}
+
+// counter lives in status[0]; tile t's words at status[8 + 8t ...]
+__global__ __launch_bounds__(kScanT) void k_delta_scan(uint32_t *__restrict__ data, uint64_t n, uint32_t init,
+                                                       uint32_t S, uint64_t *__restrict__ status)
+{
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_tot[kScanRows][kScanWaves][4];
+    __shared__ uint32_t s_excl[4];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform(tid >> 6);
+    if (tid == 0)
+        s_tile = (uint32_t)atomicAdd(reinterpret_cast<unsigned long long *>(status), 1ull);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint64_t t0 = (uint64_t)tile * kTileInts;
+    uint32_t v[kScanRows][4];
+#pragma unroll
+    for (int m = 0; m < kScanRows; ++m) {
+        const uint64_t g = t0 + (uint64_t)m * (kScanT * 4) + 4ull * tid;
+        if (g + 4 <= n) {
+            const uint4 x = *reinterpret_cast<const uint4 *>(data + g);
+            v[m][0] = x.x, v[m][1] = x.y, v[m][2] = x.z, v[m][3] = x.w;
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                v[m][r] = (g + r < n) ? data[g + r] : 0u;
+        }
+    }
+    // local inclusive scans: per row, lane-serial then across the wavefront
+    uint32_t excl[kScanRows][4];
+#pragma unroll
+    for (int m = 0; m < kScanRows; ++m) {
+        if (S == 1) {
+            v[m][1] += v[m][0];
+            v[m][2] += v[m][1];
+            v[m][3] += v[m][2];
+            const uint32_t incl = wave_scan_incl(v[m][3]);
+            excl[m][0] = incl - v[m][3];
+            if (lane == 63)
+                s_tot[m][wave][0] = incl;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const uint32_t incl = wave_scan_incl(v[m][c]);
+                excl[m][c] = incl - v[m][c];
+                if (lane == 63)
+                    s_tot[m][wave][c] = incl;
+            }
+        }
+    }
+    __syncthreads();
+    // prefix of earlier (row, wave) segments inside the tile, and the tile total
+    const int NC = S == 1 ? 1 : 4;
+    uint32_t agg[4] = {0, 0, 0, 0};
+    uint32_t seg_before[kScanRows][4] = {};
+    for (int c = 0; c < NC; ++c) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int m = 0; m < kScanRows; ++m) {
+            uint32_t row_all = 0, row_before = 0;
+#pragma unroll
+            for (int w = 0; w < kScanWaves; ++w) {
+                const uint32_t t = s_tot[m][w][c];
+                row_before += (w < (int)wave) ? t : 0u;
+                row_all += t;
+            }
+            seg_before[m][c] = run + row_before;
+            run += row_all;
+        }
+        agg[c] = run;
+    }
+    // publish and look back (wave 0)
+    uint64_t *my = status + kStatusWords + (uint64_t)tile * kStatusWords;
+    if (wave == 0) {
+        uint32_t pre[4] = {init, init, init, init};
+        if (tile == 0) {
+            if (lane < (uint32_t)NC)
+                st_status(my + 4 + lane, kFlagInc | (uint32_t)(init + agg[lane & 3]));
+        } else {
+            if (lane < (uint32_t)NC)
+                st_status(my + lane, kFlagAgg | agg[lane & 3]);
+            uint32_t acc[4] = {0, 0, 0, 0};
+            int64_t pos = (int64_t)tile;
+            for (;;) {
+                const int64_t t = pos - 1 - (int64_t)lane;
+                // per lane: state of predecessor t (2 = inclusive, 1 = aggregate, 0 = not ready)
+                uint32_t state = 0;
+                uint32_t val[4] = {0, 0, 0, 0};
+                if (t < 0) {
+                    state = 2;
+                    val[0] = val[1] = val[2] = val[3] = init;
+                } else {
+                    const uint64_t *st = status + kStatusWords + (uint64_t)t * kStatusWords;
+                    bool inc = true, ag = true;
+                    uint64_t w[4];
+                    for (int c = 0; c < NC; ++c) {
+                        w[c] = ld_status(st + 4 + c);
+                        inc = inc && (w[c] >> 32) == 2;
+                    }
+                    if (inc) {
+                        state = 2;
+                        for (int c = 0; c < NC; ++c)
+                            val[c] = (uint32_t)w[c];
+                    } else {
+                        for (int c = 0; c < NC; ++c) {
+                            w[c] = ld_status(st + c);
+                            ag = ag && (w[c] >> 32) == 1;
+                        }
+                        if (ag) {
+                            state = 1;
+                            for (int c = 0; c < NC; ++c)
+                                val[c] = (uint32_t)w[c];
+                        }
+                    }
+                }
+                const uint64_t incm = ballot(state == 2);
+                const uint64_t notready = ballot(state == 0);
+                const uint32_t first = incm ? (uint32_t)__builtin_ctzll(incm) : 64u;
+                const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1ull);
+                if (notready & need) {
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                for (int c = 0; c < NC; ++c) {
+                    const uint32_t x = lane <= first ? val[c] : 0u;
+                    acc[c] += wave_read(wave_scan_incl(x), 63);
+                }
+                if (first < 64)
+                    break;
+                pos -= 64;
+            }
+            for (int c = 0; c < NC; ++c)
+                pre[c] = acc[c];
+            if (lane < (uint32_t)NC) {
+                uint32_t mine = 0;
+                for (int c = 0; c < NC; ++c)
+                    if ((uint32_t)c == lane)
+                        mine = pre[c] + agg[c];
+                st_status(my + 4 + lane, kFlagInc | mine);
+            }
+        }
+        if (lane == 0)
+            for (int c = 0; c < 4; ++c)
+                s_excl[c] = pre[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kScanRows; ++m) {
+        const uint64_t g = t0 + (uint64_t)m * (kScanT * 4) + 4ull * tid;
+        uint32_t o[4];
+        if (S == 1) {
+            const uint32_t add = s_excl[0] + seg_before[m][0] + excl[m][0];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                o[r] = v[m][r] + add;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                o[c] = v[m][c] + s_excl[c] + seg_before[m][c] + excl[m][c];
+        }
+        if (g + 4 <= n) {
+            *reinterpret_cast<uint4 *>(data + g) = make_uint4(o[0], o[1], o[2], o[3]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (g + r < n)
+                    data[g + r] = o[r];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+
+struct ScratchKey {
+    int dev;
+    hipStream_t st;
+    bool operator==(const ScratchKey &o) const { return dev == o.dev && st == o.st; }
+};
+struct ScratchHash {
+    size_t operator()(const ScratchKey &k) const
+    {
+        return std::hash<void *>()(reinterpret_cast<void *>(k.st)) ^ (size_t)k.dev;
+    }
+};
+struct ScratchBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+static std::mutex g_smu;
+static std::unordered_map<ScratchKey, ScratchBuf, ScratchHash> g_scratch;
+
+void *stream_scratch(hipStream_t stream, size_t bytes)
+{
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess)
+        return nullptr;
+    std::lock_guard<std::mutex> lk(g_smu);
+    ScratchBuf &b = g_scratch[ScratchKey{d, stream}];
+    if (b.bytes >= bytes && b.p)
+        return b.p;
+    if (b.p) {
+        if (hipStreamSynchronize(stream) != hipSuccess)
+            return nullptr;
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = bytes < (1u << 20) ? (1u << 20) : bytes + bytes / 4;
+    void *p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess)
+        return nullptr;
+    b.p = p;
+    b.bytes = want;
+    return p;
+}
+
+}  // namespace wp
+
+using namespace wp;
+
+extern "C" int32_t delta_decode_inplace(uint32_t *data, uint64_t n, uint32_t init, int32_t stride, void *stream)
+{
+    if (stride != 1 && stride != 4)
+        return WP_ERR_INVALID_ARG;
+    if (n == 0)
+        return WP_OK;
+    if (data == nullptr || !aligned16(data))
+        return WP_ERR_INVALID_ARG;
+    const uint64_t tiles = (n + kTileInts - 1) / kTileInts;
+    if (tiles > 0x7FFFFFFFull)
+        return WP_ERR_INVALID_ARG;
+    hipStream_t st = as_stream(stream);
+    const uint64_t words = (uint64_t)kStatusWords * (tiles + 1);
+    uint64_t *status = static_cast<uint64_t *>(stream_scratch(st, words * sizeof(uint64_t)));
+    if (status == nullptr)
+        return WP_ERR_HIP;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_fill_zero, dim3((uint32_t)((words + 255) / 256)), dim3(256), 0, st, status, words);
+    hipLaunchKernelGGL(k_delta_scan, dim3((uint32_t)tiles), dim3(kScanT), 0, st, data, n, init, (uint32_t)stride,
+                       status);
+    return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
+}

@@ -1,0 +1,219 @@
+"""GPU parity: the HIP decoders against the CPU oracle and the generators.
+
+Streams are produced by the oracle's encoder; the expected output is the
+generator's array itself (decoding is lossless, so decode(encode(x)) == x is
+the plain definition of the result). Comparisons are exact (integer work).
+Outputs sit between canary fences to catch writes outside [out, out + n).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1209_2137_amd as wp
+from paper_1209_2137_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+CANARY = 0x5A5A5A5A
+PAD = 64
+BP_TUNES = [(8, 4), (4, 4), (4, 8), (2, 8)]
+FP_TUNES = [(8, 4), (4, 4), (4, 8), (8, 8)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "the GPU tests need a GPU"
+    wp.lib()
+    yield
+    wp.set_decode_tune(wp.CODEC_BP, 8, 4)
+    wp.set_decode_tune(wp.CODEC_FP, 8, 4)
+
+
+def to_dev(a):
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    if a.size == 0:
+        return torch.zeros(0, dtype=torch.int32, device="cuda")
+    return torch.from_numpy(a.view(np.int32)).to("cuda")
+
+
+def to_host(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def gpu_decode(codec, stream_np, n):
+    comp = to_dev(stream_np)
+    buf = torch.full((n + 2 * PAD,), CANARY, dtype=torch.int32, device="cuda")
+    out = buf[PAD:PAD + n]
+    (wp.bp_decode if codec == wp.CODEC_BP else wp.fastpfor_decode)(comp, n, out)
+    rc = wp.check_code()
+    h = to_host(buf)
+    assert (h[:PAD] == CANARY).all() and (h[PAD + n:] == CANARY).all(), "write outside [out, out + n)"
+    return rc, h[PAD:PAD + n]
+
+
+def encode(codec, x, stride):
+    return (oracle.bp_encode if codec == wp.CODEC_BP else oracle.fp_encode)(x, stride)
+
+
+def assert_same(got, want, what=""):
+    if not np.array_equal(got, want):
+        bad = np.nonzero(got != want)[0]
+        raise AssertionError(f"{what}: {bad.size} mismatches, first at {bad[0]}: "
+                             f"got {got[bad[0]]} want {want[bad[0]]}")
+
+
+LENGTHS = [0, 1, 3, 4, 5, 100, 127, 128, 129, 255, 256, 1000, 2047, 2048, 2049, 4096 + 127,
+           3 * 2048 + 5, 65535, 65536, 65537, 2 * 65536 + 3 * 128 + 77]
+
+
+@pytest.mark.parametrize("codec,tunes", [(wp.CODEC_BP, BP_TUNES), (wp.CODEC_FP, FP_TUNES)])
+@pytest.mark.parametrize("stride", [0, 1, 4])
+def test_lengths_strides_tunes(codec, tunes, stride):
+    rng = np.random.default_rng(1000 * codec + stride)
+    cases = []
+    for n in LENGTHS:
+        kind = n % 3
+        if kind == 0:
+            x = rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)
+        elif kind == 1:
+            x = datagen.single_geometric(n, mean=float(rng.integers(2, 5000)), seed=n)
+        else:
+            x = datagen.patched_gaps(n, seed=n) if n else np.zeros(0, np.uint32)
+        cases.append((n, x, encode(codec, x, stride)))
+    for waves, vpl in tunes:
+        wp.set_decode_tune(codec, waves, vpl)
+        for n, x, s in cases:
+            print(f"codec={codec} stride={stride} tune=({waves},{vpl}) n={n}", flush=True)
+            rc, got = gpu_decode(codec, s, n)
+            assert rc == wp.OK
+            assert_same(got, x, f"n={n} tune=({waves},{vpl})")
+
+
+@pytest.mark.parametrize("codec", [wp.CODEC_BP, wp.CODEC_FP])
+def test_every_block_width(codec):
+    # 33 blocks, block j holds values of exactly j bits (one at 2^j - 1), stride 0
+    rng = np.random.default_rng(5)
+    blocks = []
+    for b in range(33):
+        hi = (1 << b) - 1
+        v = (rng.integers(0, 2**32, size=128, dtype=np.uint64) & hi).astype(np.uint32)
+        v[int(rng.integers(0, 128))] = hi
+        blocks.append(v)
+    x = np.concatenate(blocks + [np.array([7, 1 << 31, 5], dtype=np.uint32)])
+    tunes = BP_TUNES if codec == wp.CODEC_BP else FP_TUNES
+    for waves, vpl in tunes:
+        wp.set_decode_tune(codec, waves, vpl)
+        rc, got = gpu_decode(codec, encode(codec, x, 0), x.size)
+        assert rc == wp.OK
+        assert_same(got, x)
+
+
+def test_config_small_single_list():
+    # 2^20 sorted integers, x_1 ~ U[0,1000), geometric gaps of mean 8
+    x = datagen.single_geometric(1 << 20, mean=8.0, seed=1)
+    for codec in (wp.CODEC_BP, wp.CODEC_FP):
+        for stride in (1, 4):
+            rc, got = gpu_decode(codec, encode(codec, x, stride), x.size)
+            assert rc == wp.OK
+            assert_same(got, x)
+
+
+def test_full_size_binary_packing_lists():
+    # the 2^26 single-list workloads: recursive-cluster and uniform distinct values
+    for x in (datagen.cluster_sorted(), datagen.uniform_sorted()):
+        s = oracle.bp_encode(x, 1)
+        comp = to_dev(s)
+        out = torch.empty(x.size, dtype=torch.int32, device="cuda")
+        wp.set_decode_tune(wp.CODEC_BP, 8, 4)
+        wp.bp_decode(comp, x.size, out)
+        assert wp.check_code() == wp.OK
+        assert torch.equal(out, to_dev(x))
+
+
+def test_full_size_patched_list():
+    # the 2^28 patched workload (wraps modulo 2^32)
+    x = datagen.patched_gaps()
+    s = oracle.fp_encode(x, 1)
+    comp = to_dev(s)
+    xd = to_dev(x)
+    del x
+    out = torch.empty(xd.numel(), dtype=torch.int32, device="cuda")
+    wp.set_decode_tune(wp.CODEC_FP, 8, 4)
+    wp.fastpfor_decode(comp, xd.numel(), out)
+    assert wp.check_code() == wp.OK
+    assert torch.equal(out, xd)
+
+
+@pytest.mark.parametrize("codec", [wp.CODEC_BP, wp.CODEC_FP])
+def test_corrupt_streams_flagged_without_stray_writes(codec):
+    n = 2 * 65536 + 300
+    x = datagen.patched_gaps(n, seed=77)
+    s = encode(codec, x, 1)
+    rc, got = gpu_decode(codec, s, n)
+    assert rc == wp.OK and np.array_equal(got, x)
+    unit = int(s[8])
+    mutations = {
+        "magic": (0, int(s[0]) ^ 1),
+        "stride": (3, 2),
+        "units": (4, int(s[4]) + 1),
+        "total": (7, int(s[7]) + 100),
+        "unit_offset": (8, 0xFFFFFF),
+        "tail_bytes": (5, int(s[5]) + 1),
+    }
+    if codec == wp.CODEC_BP:
+        mutations["width33"] = (unit, (int(s[unit]) & ~0xFF) | 33)
+    else:
+        mutations["nblocks"] = (unit, 7)
+        mutations["packed_words"] = (unit + 1, int(s[unit + 1]) + 4)
+        mutations["bitset"] = (unit + 3, int(s[unit + 3]) ^ 0x80000000)
+    for what, (at, val) in mutations.items():
+        bad = s.copy()
+        bad[at] = val & 0xFFFFFFFF
+        print("corruption", what, flush=True)
+        rc, _ = gpu_decode(codec, bad, n)
+        assert rc == wp.ERR_CORRUPT, what
+        # the oracle agrees that the stream is bad
+        assert (oracle.bp_decode_rc if codec == wp.CODEC_BP else oracle.fp_decode_rc)(bad, n) == oracle.ERR_CORRUPT
+    # wrong n: flagged as well
+    rc, _ = gpu_decode(codec, s, n - 1)
+    assert rc == wp.ERR_CORRUPT
+    # a good decode afterwards is clean again
+    rc, got = gpu_decode(codec, s, n)
+    assert rc == wp.OK and np.array_equal(got, x)
+
+
+DELTA_SIZES = [1, 3, 4, 5, 4095, 4096, 4097, 12345, 1 << 20, (1 << 22) + 3]
+
+
+@pytest.mark.parametrize("stride", [1, 4])
+def test_delta_decode_inplace_matches_oracle(stride):
+    rng = np.random.default_rng(stride)
+    for n in DELTA_SIZES:
+        for init in (0, 0xFFFFFFF0):
+            d = rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)
+            want = d.copy()
+            oracle.delta_decode_inplace(want, init, stride)
+            t = to_dev(d)
+            wp.delta_decode_inplace(t, init, stride)
+            torch.cuda.synchronize()
+            print(f"delta n={n} stride={stride} init={init:#x}", flush=True)
+            assert_same(to_host(t), want, f"n={n}")
+
+
+def test_delta_decode_inplace_paper_example():
+    t = to_dev(np.array([1, 3, 9], dtype=np.uint32))
+    wp.delta_decode_inplace(t, 0, 1)
+    assert list(to_host(t)) == [1, 4, 13]
+
+
+def test_delta_decode_inplace_large_repeatable():
+    n = (1 << 26) + 1
+    rng = np.random.default_rng(9)
+    d = rng.integers(0, 1 << 8, size=n, dtype=np.uint64).astype(np.uint32)
+    want = (np.cumsum(d.astype(np.uint64)) & 0xFFFFFFFF).astype(np.uint32)
+    for _ in range(2):
+        t = to_dev(d)
+        wp.delta_decode_inplace(t, 0, 1)
+        torch.cuda.synchronize()
+        assert_same(to_host(t), want)
