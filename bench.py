@@ -1,0 +1,276 @@
+#!/usr/bin/env python3
+"""Decode throughput of wavepack on one MI355X.
+
+A step is one decode of the whole headline list: 2^26 sorted distinct
+uint32 from the recursive-cluster generator in [0, 2^30), compressed with
+binary packing (128-integer blocks, 16 per meta-block) and standard
+differential coding, decoded back to the sorted array (unpack + prefix sum
+in one kernel). Inputs are resident in HBM before the timed region; the
+compressed stream is produced by the GPU encoder.
+
+Prints ONE JSON line. Extra workloads (the 2^26 uniform list, the 2^28
+patched list, the in-place delta scan, batched decoding) are reported under
+"extra"; `--quick` skips them.
+
+  python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--quick]
+  python bench.py --rocprof-summary DIR   # summarise rocprofv3 CSV output
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "decoded uint32/s (G ints/s) + % HBM peak; batched vs per-list; p99 latency"
+HBM_PEAK_GBS = 8000.0
+MALL_BYTES = 256 << 20
+KERNEL_SOURCES = ("paper_1209_2137_amd/csrc/wp_device.hpp", "paper_1209_2137_amd/csrc/wp_decode.hip")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "bp_decode_cluster_2e26_counters.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(per_launch_alg_bytes: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    only if it was taken on the current kernel sources."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_hash") != kernel_hash():
+        return None
+    return c.get("traffic_bytes_per_launch")
+
+
+def to_dev(a):
+    import numpy as np
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).to("cuda")
+
+
+def time_launches(fn, steps, warmup, stream):
+    """Runs fn(i) warmup times, then `steps` times with HIP events around
+    every launch on `stream`. Returns (wall ms per step, mean event ms)."""
+    import torch
+    for i in range(warmup):
+        fn(i)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        starts[i].record(stream)
+        fn(warmup + i)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    ev = sum(s.elapsed_time(e) for s, e in zip(starts, ends)) / steps
+    return wall, ev
+
+
+def replicas(t, nbytes_each):
+    """Copies of t so that the rotation's working set is well above the
+    256 MB Infinity Cache."""
+    r = max(2, min(16, math.ceil(2 * MALL_BYTES / max(nbytes_each, 1))))
+    return [t] + [t.clone() for _ in range(r - 1)]
+
+
+def bench_single(wp, x_np, codec, stride, steps, warmup, name):
+    import torch
+    xd = to_dev(x_np)
+    n = x_np.size
+    comp = wp.encode_trimmed(xd, codec, stride)
+    comps = replicas(comp, comp.numel() * 4)
+    outs = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(2)]
+    dec = wp.bp_decode if codec == wp.CODEC_BP else wp.fastpfor_decode
+    stream = torch.cuda.current_stream()
+    dec(comps[0], n, outs[0])
+    wp.check()
+    if not torch.equal(outs[0], xd):
+        raise RuntimeError(f"{name}: decoded output differs from the input")
+    del xd
+    wall, ev = time_launches(lambda i: dec(comps[i % len(comps)], n, outs[i % 2]), steps, warmup, stream)
+    wp.check()
+    comp_bytes = comp.numel() * 4
+    alg = comp_bytes + 4 * n
+    return {
+        "name": name, "n": n, "codec": "bp" if codec == wp.CODEC_BP else "fp", "stride": stride,
+        "bits_per_int": comp_bytes * 8 / n, "ms_per_step": wall, "kernel_ms": ev,
+        "gints_per_s": n / (wall * 1e-3) / 1e9, "kernel_gints_per_s": n / (ev * 1e-3) / 1e9,
+        "alg_bytes": alg, "achieved_gbs": alg / (ev * 1e-3) / 1e9,
+        "hbm_frac": alg / (ev * 1e-3) / 1e9 / HBM_PEAK_GBS, "replicas": len(comps),
+    }
+
+
+def bench_delta(wp, n, steps, warmup):
+    import torch
+    rng_t = torch.randint(0, 1 << 8, (n,), dtype=torch.int32, device="cuda")
+    bufs = replicas(rng_t, n * 4)
+    stream = torch.cuda.current_stream()
+    wall, ev = time_launches(lambda i: wp.delta_decode_inplace(bufs[i % len(bufs)], 0, 1), steps, warmup, stream)
+    alg = 8 * n
+    return {"name": "delta_decode_inplace 2^28 stride 1", "n": n, "ms_per_step": wall, "kernel_ms": ev,
+            "gints_per_s": n / (wall * 1e-3) / 1e9, "achieved_gbs": alg / (ev * 1e-3) / 1e9,
+            "hbm_frac": alg / (ev * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def bench_copy(n_bytes, steps, warmup):
+    """A plain device copy of known size: the bandwidth reference."""
+    import torch
+    src = torch.empty(n_bytes // 4, dtype=torch.int32, device="cuda").fill_(1)
+    dsts = [torch.empty_like(src) for _ in range(2)]
+    stream = torch.cuda.current_stream()
+    wall, ev = time_launches(lambda i: dsts[i % 2].copy_(src), steps, warmup, stream)
+    return {"bytes": 2 * n_bytes, "kernel_ms": ev, "gbs": 2 * n_bytes / (ev * 1e-3) / 1e9}
+
+
+def cpu_baseline(x_np, min_seconds=10.0):
+    """The CPU oracle (plain scalar C, one thread) decoding the same list."""
+    import oracle
+    stream = oracle.bp_encode(x_np, 1)
+    n = x_np.size
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        out = oracle.bp_decode(stream, n)
+        reps += 1
+        if time.perf_counter() - t0 >= min_seconds:
+            break
+    dt = time.perf_counter() - t0
+    import numpy as np
+    if not np.array_equal(out, x_np):
+        raise RuntimeError("oracle decode mismatch")
+    return {"value": reps * n / dt / 1e9, "unit": "G ints/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle bp_decode of the whole 2^26-integer list, {reps} runs in {dt:.1f} s "
+                      f"(single thread; the oracle is not parallel)"}
+
+
+def rocprof_summary(d):
+    """Markdown summary of rocprofv3 kernel statistics / counter CSVs in d."""
+    import csv
+    lines = []
+    for path in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
+        lines.append(f"### {os.path.relpath(path, d)}")
+        with open(path) as f:
+            rows = list(csv.DictReader(f))
+        lines.append("| kernel | calls | total ns | avg ns | min ns | max ns |")
+        lines.append("|---|---|---|---|---|---|")
+        for r in rows:
+            lines.append(f"| {r.get('Name', '')[:90]} | {r.get('Calls')} | {r.get('TotalDurationNs')} | "
+                         f"{float(r.get('AverageNs', 0)):.0f} | {r.get('MinNs')} | {r.get('MaxNs')} |")
+    for path in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+        lines.append(f"### {os.path.relpath(path, d)}")
+        agg = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                key = (r.get("Kernel_Name", "")[:90], r.get("Counter_Name"))
+                agg.setdefault(key, []).append(float(r.get("Counter_Value", 0)))
+        lines.append("| kernel | counter | dispatches | mean value |")
+        lines.append("|---|---|---|---|")
+        for (k, c), v in sorted(agg.items()):
+            lines.append(f"| {k} | {c} | {len(v)} | {sum(v) / len(v):.1f} |")
+    print("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rocprof-summary", metavar="DIR")
+    args = ap.parse_args()
+    if args.rocprof_summary:
+        rocprof_summary(args.rocprof_summary)
+        return 0
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (this build decodes on a "
+              "single MI355X; lists and units shard across GPUs without any exchange, see the design notes)",
+              file=sys.stderr)
+        return 2
+    import torch
+    import paper_1209_2137_amd as wp
+    from paper_1209_2137_amd import datagen
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    wp.lib()
+    t_start = time.perf_counter()
+    x = datagen.cluster_sorted(1 << 26, seed=2)
+    head = bench_single(wp, x, wp.CODEC_BP, 1, args.steps, args.warmup, "bp cluster 2^26")
+    print(f"# headline done: {head['gints_per_s']:.1f} G ints/s ({time.perf_counter() - t_start:.0f} s)",
+          file=sys.stderr, flush=True)
+    extra = {}
+    if not args.quick:
+        copy = bench_copy(1 << 30, 10, 3)
+        extra["copy_1GiB_gbs"] = copy["gbs"]
+        u = bench_single(wp, datagen.uniform_sorted(1 << 26, seed=3), wp.CODEC_BP, 1, args.steps, args.warmup,
+                         "bp uniform 2^26")
+        extra["bp_uniform_2e26"] = u
+        print("# uniform done", file=sys.stderr, flush=True)
+        p = bench_single(wp, datagen.patched_gaps(1 << 28, seed=4), wp.CODEC_FP, 1, args.steps, args.warmup,
+                         "fastpfor patched 2^28")
+        extra["fp_patched_2e28"] = p
+        print("# patched done", file=sys.stderr, flush=True)
+        extra["delta_inplace_2e28"] = bench_delta(wp, 1 << 28, args.steps, args.warmup)
+        print("# delta done", file=sys.stderr, flush=True)
+        head["pct_of_copy"] = head["achieved_gbs"] / copy["gbs"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(x)
+        print("# cpu baseline done", file=sys.stderr, flush=True)
+    traffic = measured_traffic(head["alg_bytes"])
+    line = {
+        "metric": METRIC,
+        "value": head["gints_per_s"],
+        "unit": "G ints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "SIMD-BP128 single list: 2^26 sorted distinct uint32, recursive-cluster generator in "
+                        "[0,2^30) (depth 20, leaves <= 64), binary packing 16x128 per meta-block, stride-1 "
+                        "differential decode",
+            "n": head["n"], "bits_per_int": round(head["bits_per_int"], 4),
+            "decode_tune": list(wp_tune_of(wp, wp.CODEC_BP)),
+            "input_replicas": head["replicas"],
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": head["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+            "alg_bytes_per_launch": head["alg_bytes"], "kernel_ms": head["kernel_ms"],
+        },
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line))
+    return 0
+
+
+def wp_tune_of(wp, codec):
+    return (8, 4)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -27,10 +27,11 @@
  *   header, 8 words: magic ('WPB1' binary packing, 'WPF1' patched), n low,
  *       n high, stride S (0, 1 or 4), n_units, tail_bytes, tail_off,
  *       total_words
- *   directory: one entry per unit, plus one for the tail when n % 128 != 0:
- *       [word offset of the unit from the stream start, base_0..base_{S-1}]
- *       with base_s = x[start - S + s] (0 before the array start), so every
- *       unit decodes on its own; zero-padded to a multiple of 4 words
+ *   directory: ndir entries, one per unit plus one for the tail when
+ *       n % 128 != 0: first the ndir word offsets (from the stream start),
+ *       then ndir groups of S bases, base_s = x[start - S + s] (0 before the
+ *       array start), so every unit decodes on its own; zero-padded to a
+ *       multiple of 4 words
  *   units: binary packing -- a meta-block of up to 16 blocks of 128 values
  *       (2048 values): a 16-byte descriptor whose byte j is block j's width
  *       b_j, then each block's 128 deltas packed at b_j bits in 4*b_j words
@@ -117,6 +118,16 @@ int32_t fastpfor_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, ui
 int32_t delta_decode_inplace(uint32_t *data, uint64_t n, uint32_t init, int32_t stride,
                              void *stream);
 
+/* Workgroup shape of the single-list decoders (set by the autotuner;
+ * process-wide). waves: wavefronts per workgroup; vpl: integers each lane
+ * decodes per pass; depth (binary packing): 16-byte loads per thread in
+ * flight while decoding (2 or 4; 0 = 4); wg_per_cu (binary packing): runs
+ * of consecutive meta-blocks per compute unit (each workgroup streams one
+ * run's compressed words through an LDS ring; 0 = 8). Valid shapes:
+ * binary packing (2|4 waves, 4|8 vpl) or (8, 4); patched (4|8 waves, 4|8
+ * vpl). Returns WP_ERR_INVALID_ARG for anything else. */
+int32_t wp_set_decode_tune(int32_t codec, int32_t waves, int32_t vpl, int32_t depth, int32_t wg_per_cu);
+
 /* Synchronises `stream`, then returns and clears this device's error word:
  * WP_OK, WP_ERR_CORRUPT, or WP_ERR_HIP if the synchronisation failed. */
 int32_t wp_check(void *stream);
@@ -140,27 +151,40 @@ typedef struct wp_list {
 } wp_list;
 
 typedef struct wp_tune {
-    int32_t waves;     /* waves per workgroup: 4 or 8 (0 = default) */
-    int32_t vpl;       /* integers per lane and pass: 4 or 8 (0 = default) */
-    int32_t wg_per_cu; /* persistent workgroups per compute unit (0 = default) */
-    int32_t use_graph; /* 1 = replay a captured hipGraph, 0 = plain launches */
+    int32_t waves;     /* wavefronts per workgroup: 2, 4 or 8 (0 = 4) */
+    int32_t vpl;       /* integers per lane and pass: 4 or 8 (8 only with 2 or 4 waves; 0 = 4) */
+    int32_t depth;     /* binary packing: 16-byte loads in flight per thread, 2 or 4 (0 = 4; 8 waves: 2) */
+    int32_t run_units; /* meta-blocks per binary-packing work item, 1..63 (0 = 8) */
+    int32_t wg_per_cu; /* persistent workgroups per compute unit, 0..64 (0 = 8 with 2 waves, else 4) */
+    int32_t use_graph; /* 1 = replay a hipGraph built at plan time, 0 = plain launches */
 } wp_tune;
 
-/* Builds a plan: validates the registry on the host, builds and uploads the
- * item array (stream-ordered copy on `stream`), and keeps `pool`/`out_base`.
- * h_lists is host memory and may be freed on return. `tune` may be NULL.
- * *h_plan receives an opaque handle owned by the caller (wp_batch_free). */
+/* Builds a plan: validates the registry on the host (codec, alignment of
+ * comp_off_words and out_off to 4 words, comp_words >= 8), cuts every list
+ * into work items (runs of run_units meta-blocks, single pages, tails;
+ * largest first), uploads the list and item arrays (it synchronises
+ * `stream` once), and, when tune->use_graph, builds and instantiates a
+ * hipGraph of the counter reset and the persistent decoder. `pool` and
+ * `out_base` (device, 16-byte aligned) are kept; h_lists may be freed on
+ * return; tune may be NULL (defaults, graph on). The plan allocates its
+ * own device arrays; *h_plan is released with wp_batch_free. Output ranges
+ * of different lists must not overlap. Returns WP_ERR_INVALID_ARG for a bad
+ * registry or tune, WP_ERR_HIP if an allocation or copy fails. */
 int32_t wp_batch_plan(const uint32_t *pool, uint32_t *out_base, const wp_list *h_lists,
                       uint64_t nlists, const wp_tune *tune, void **h_plan, void *stream);
 
-/* Decodes every list of the plan: resets the work counter and launches the
- * persistent kernel, as one hipGraph replay when the plan's tune asks. */
+/* Decodes every list of the plan on `stream` (asynchronous): resets the
+ * work counter and runs the persistent decoder, as one hipGraph launch when
+ * the plan has a graph. Stream contents are validated as in bp_decode; a
+ * bad list is reported through wp_check. Two launches of the same plan must
+ * not overlap (they share the counter). Allocates nothing. */
 int32_t wp_batch_decode(void *h_plan, void *stream);
 
 /* Number of work items in a plan (host). */
 uint64_t wp_batch_items(const void *h_plan);
 
-/* Releases a plan (synchronises with its last launch first). */
+/* Releases a plan (synchronises the device first, then frees the plan's
+ * device arrays and graph). */
 int32_t wp_batch_free(void *h_plan);
 
 #ifdef __cplusplus

@@ -14,10 +14,11 @@
  * Stream layout (little-endian 32-bit words):
  *   header  (8 words) magic, n_lo, n_hi, stride, n_units, tail_bytes,
  *                     tail_off, total_words
- *   directory         one entry per unit (+1 for the tail when present):
- *                     [unit word offset, base_0 .. base_{S-1}], S = stride,
- *                     base_s = x[start - S + s] (0 before the array start);
- *                     zero-padded to a multiple of 4 words
+ *   directory         ndir = n_units (+1 for the tail when present)
+ *                     entries: first the ndir word offsets of the units
+ *                     (and tail), then the ndir groups of S bases,
+ *                     S = stride, base_s = x[start - S + s] (0 before the
+ *                     array start); zero-padded to a multiple of 4 words
  *   units             binary packing: 4-word width descriptor (byte j = b_j)
  *                     then 16 blocks of 128 values, block j in 4*b_j words.
  *                     patched (FastPFOR) page of up to 512 blocks: see
@@ -390,11 +391,11 @@ static int64_t o_encode(int codec, const uint32_t *x, uint64_t n, int stride,
         uint64_t start = u * per * OB; /* first value of the unit (or tail) */
         if (u == units)
             start = nfull * OB;
-        uint32_t *ent = out + 8 + u * E;
-        ent[0] = (uint32_t)p;
+        out[8 + u] = (uint32_t)p;
+        uint32_t *bases = out + 8 + ndir + u * (uint64_t)stride;
         for (uint64_t s = 0; s < (uint64_t)stride; s++) {
             /* base_s = x[start - S + s], 0 before the array start */
-            ent[1 + s] = (start + s >= (uint64_t)stride) ? x[start + s - stride] : 0u;
+            bases[s] = (start + s >= (uint64_t)stride) ? x[start + s - stride] : 0u;
         }
         if (u < units) {
             uint64_t nb = nfull - u * per;
@@ -574,9 +575,9 @@ static int o_decode(int codec, const uint32_t *in, uint64_t in_words, uint32_t *
     if (dir_end > total || tail_off > total)
         return O_ERR_CORRUPT;
     for (uint64_t u = 0; u < ndir; u++) {
-        const uint32_t *ent = in + 8 + u * E;
-        uint64_t off = ent[0];
-        uint64_t end = (u + 1 < units) ? in[8 + (u + 1) * E] : tail_off;
+        uint64_t off = in[8 + u];
+        const uint32_t *bases = in + 8 + ndir + u * (uint64_t)stride;
+        uint64_t end = (u + 1 < units) ? in[8 + u + 1] : tail_off;
         uint64_t start = (u == units) ? nfull * OB : u * per * OB;
         uint64_t count;
         int rc;
@@ -601,7 +602,7 @@ static int o_decode(int codec, const uint32_t *in, uint64_t in_words, uint32_t *
             return rc;
         /* prefix sum of the unit from its stored bases (Section 3) */
         for (uint64_t i = 0; i < count && stride != 0; i++) {
-            uint32_t prev = (i >= (uint64_t)stride) ? out[start + i - stride] : ent[1 + i];
+            uint32_t prev = (i >= (uint64_t)stride) ? out[start + i - stride] : bases[i];
             out[start + i] = out[start + i] + prev;
         }
     }

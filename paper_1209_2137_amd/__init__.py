@@ -44,8 +44,8 @@ class wp_list(ctypes.Structure):
 
 
 class wp_tune(ctypes.Structure):
-    _fields_ = [("waves", ctypes.c_int32), ("vpl", ctypes.c_int32),
-                ("wg_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+    _fields_ = [("waves", ctypes.c_int32), ("vpl", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("run_units", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
 def lib():
@@ -75,7 +75,7 @@ def lib():
     L.wp_check.restype = i32
     L.wp_strerror.argtypes = [i32]
     L.wp_strerror.restype = ctypes.c_char_p
-    L.wp_set_decode_tune.argtypes = [i32, i32, i32]
+    L.wp_set_decode_tune.argtypes = [i32, i32, i32, i32, i32]
     L.wp_set_decode_tune.restype = i32
     L.wp_batch_plan.argtypes = [vp, vp, ctypes.POINTER(wp_list), u64, ctypes.POINTER(wp_tune),
                                 ctypes.POINTER(vp), vp]
@@ -123,8 +123,12 @@ def max_compressed_words(codec: int, n: int) -> int:
     return int(lib().wp_max_compressed_words(codec, n))
 
 
-def set_decode_tune(codec: int, waves: int, vpl: int):
-    _check(lib().wp_set_decode_tune(codec, waves, vpl), "set_decode_tune")
+def set_decode_tune(codec: int, waves: int, vpl: int, wg_per_cu: int = 0, depth: int = 0):
+    """Workgroup shape of the single-list decoders: `waves` wavefronts per
+    workgroup, `vpl` integers per lane and pass; for binary packing about
+    `wg_per_cu` runs of meta-blocks per compute unit and `depth` loads in
+    flight per thread (0 = defaults)."""
+    _check(lib().wp_set_decode_tune(codec, waves, vpl, depth, wg_per_cu), "set_decode_tune")
 
 
 def _decode(fn, comp, n, out, stream, name):
@@ -202,3 +206,49 @@ def check(stream=None):
 
 def check_code(stream=None) -> int:
     return int(lib().wp_check(_stream(stream)))
+
+
+class BatchPlan:
+    """A batched decode of many lists (see wp_batch_plan).
+
+    pool: device tensor holding all compressed streams; out: device tensor
+    receiving all outputs; lists: rows (comp_off_words, comp_words, out_off,
+    n, codec). tune: dict with waves, vpl, depth, run_units, wg_per_cu,
+    use_graph (missing keys take the library defaults)."""
+
+    def __init__(self, pool, out, lists, tune=None, stream=None):
+        _need_u32(pool, "pool")
+        _need_u32(out, "out")
+        n = len(lists)
+        arr = (wp_list * max(n, 1))()
+        for i, (co, cw, oo, nn, codec) in enumerate(lists):
+            arr[i] = wp_list(int(co), int(cw), int(oo), int(nn), int(codec), 0)
+        t = None
+        if tune is not None:
+            t = wp_tune(int(tune.get("waves", 0)), int(tune.get("vpl", 0)), int(tune.get("depth", 0)),
+                        int(tune.get("run_units", 0)), int(tune.get("wg_per_cu", 0)),
+                        int(tune.get("use_graph", 1)))
+        self._h = ctypes.c_void_p()
+        self.pool, self.out = pool, out  # keep the buffers alive
+        _check(lib().wp_batch_plan(_ptr(pool), _ptr(out), arr, n, ctypes.byref(t) if t is not None else None,
+                                   ctypes.byref(self._h), _stream(stream)), "wp_batch_plan")
+
+    @property
+    def items(self) -> int:
+        return int(lib().wp_batch_items(self._h))
+
+    def decode(self, stream=None):
+        _check(lib().wp_batch_decode(self._h, _stream(stream)), "wp_batch_decode")
+
+    def free(self):
+        if self._h:
+            rc = lib().wp_batch_free(self._h)
+            self._h = ctypes.c_void_p()
+            _check(rc, "wp_batch_free")
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().wp_batch_free(self._h)
+        except Exception:
+            pass

@@ -1,0 +1,334 @@
+// Batched decoding of many lists in one launch.
+//
+// The host planner cuts every list into work items: runs of up to
+// `run_units` meta-blocks (binary packing), single pages (patched) and the
+// Variable Byte tails; large items first. A persistent grid of workgroups
+// pulls item indices from one atomic counter until none are left, and runs
+// the same device decoders as the single-list entry points (binary-packing
+// runs through the LDS ring, patched pages, tails). Items are independent
+// because every unit's base is stored in its list's directory.
+//
+// A plan owns its device item array and, when asked, a hipGraph of two
+// kernel nodes: a one-thread counter reset, then the persistent decoder
+// (no memset node; the graph is built from explicit nodes, not captured).
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "wp_device.hpp"
+#include "wp_host.hpp"
+
+namespace wp {
+
+enum : uint32_t { kItemBpRun = 0, kItemFpPage = 1, kItemTail = 2 };
+
+struct DevList {
+    const uint32_t *comp;
+    uint32_t *out;
+    uint64_t comp_words;
+    uint64_t n;
+    uint32_t codec;
+    uint32_t pad;
+};
+
+// item: {list index, kind, first unit, unit count}
+template <int WAVES, int VPL, int DEPTH>
+union BatchLds {
+    RingLds<WAVES, VPL, DEPTH> r;
+    FpLds<WAVES, VPL> fp;
+    TailLds<WAVES> tail;
+};
+
+__global__ void k_batch_reset(uint32_t *counter) { *counter = 0; }
+
+template <int WAVES, int VPL, int DEPTH>
+__global__ __launch_bounds__(64 * WAVES) void k_batch(const DevList *__restrict__ lists,
+                                                      const uint4 *__restrict__ items, uint32_t nitems,
+                                                      uint32_t *__restrict__ counter, int *__restrict__ err)
+{
+    __shared__ BatchLds<WAVES, VPL, DEPTH> L;
+    __shared__ uint32_t s_item;
+    const uint32_t tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0)
+            s_item = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t it = uniform(s_item);
+        __syncthreads();
+        if (it >= nitems)
+            break;
+        const uint4 item = items[it];
+        const uint32_t li = uniform(item.x), kind = uniform(item.y), first = uniform(item.z),
+                       count = uniform(item.w);
+        const DevList Ld = lists[li];
+        const uint32_t codec = uniform(Ld.codec);
+        ListHdr H;
+        bool ok = check_header(Ld.comp, Ld.comp_words, Ld.n, codec == WP_CODEC_BP ? kMagicBP : kMagicFP,
+                               codec == WP_CODEC_BP ? kBpBlocks : kFpBlocks, H);
+        if (ok) {
+            if (kind == kItemBpRun) {
+                ok = codec == WP_CODEC_BP && count >= 1 && count <= 63 && (uint64_t)first + count <= H.units &&
+                     bp_decode_run<WAVES, VPL, DEPTH>(Ld.comp, H, first, count, Ld.out, L.r);
+            } else if (kind == kItemFpPage) {
+                ok = codec == WP_CODEC_FP && first < H.units;
+                if (ok) {
+                    const uint64_t u = first;
+                    const uint32_t off = Ld.comp[kHdrWords + u];
+                    const uint32_t end = (u + 1 < H.units) ? Ld.comp[kHdrWords + u + 1] : H.tail_off;
+                    uint32_t base[4] = {0u, 0u, 0u, 0u};
+                    for (uint32_t s = 0; s < H.S; ++s)
+                        base[s] = Ld.comp[kHdrWords + H.ndir + u * H.S + s];
+                    const uint64_t left = H.nfull - u * kFpBlocks;
+                    const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
+                    ok = off >= H.dir_end && end >= off && end <= H.total && (off & 3u) == 0 &&
+                         fp_page<WAVES, VPL>(Ld.comp + off, end - off, nb, H.S, base, Ld.out + u * kFpUnitInts, L.fp);
+                }
+            } else {
+                ok = H.tail != 0 && decode_tail_entry<WAVES>(Ld.comp, H, Ld.out, L.tail);
+            }
+        }
+        if (!ok && tid == 0)
+            *err = kErrCorrupt;
+        __syncthreads();
+    }
+}
+
+struct Plan {
+    int device = -1;
+    DevList *d_lists = nullptr;
+    uint4 *d_items = nullptr;
+    uint32_t *d_counter = nullptr;
+    uint64_t nlists = 0, nitems = 0;
+    int waves = 4, vpl = 4, depth = 4;
+    uint32_t grid = 1;
+    bool use_graph = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void *kernel = nullptr;
+    int *err = nullptr;
+};
+
+template <int W, int V, int D>
+static const void *batch_kernel()
+{
+    return reinterpret_cast<const void *>(&k_batch<W, V, D>);
+}
+
+static const void *pick_kernel(int waves, int vpl, int depth)
+{
+    const bool deep = depth >= 4;
+    if (waves == 2 && vpl == 4)
+        return deep ? batch_kernel<2, 4, 4>() : batch_kernel<2, 4, 2>();
+    if (waves == 2 && vpl == 8)
+        return deep ? batch_kernel<2, 8, 4>() : batch_kernel<2, 8, 2>();
+    if (waves == 4 && vpl == 4)
+        return deep ? batch_kernel<4, 4, 4>() : batch_kernel<4, 4, 2>();
+    if (waves == 4 && vpl == 8)
+        return deep ? batch_kernel<4, 8, 4>() : batch_kernel<4, 8, 2>();
+    if (waves == 8 && vpl == 4)
+        return batch_kernel<8, 4, 2>();
+    return nullptr;
+}
+
+static void release(Plan *p)
+{
+    if (p->exec)
+        (void)hipGraphExecDestroy(p->exec);
+    if (p->graph)
+        (void)hipGraphDestroy(p->graph);
+    if (p->d_lists)
+        (void)hipFree(p->d_lists);
+    if (p->d_items)
+        (void)hipFree(p->d_items);
+    if (p->d_counter)
+        (void)hipFree(p->d_counter);
+    delete p;
+}
+
+static int32_t launch_plan(Plan *p, hipStream_t st)
+{
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, st, p->d_counter);
+    void *args[] = {&p->d_lists, &p->d_items, &p->nitems, &p->d_counter, &p->err};
+    uint32_t nitems32 = (uint32_t)p->nitems;
+    args[2] = &nitems32;
+    if (hipLaunchKernel(p->kernel, dim3(p->grid), dim3(64 * p->waves), args, 0, st) != hipSuccess)
+        return WP_ERR_HIP;
+    return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
+}
+
+static int32_t build_graph(Plan *p)
+{
+    if (hipGraphCreate(&p->graph, 0) != hipSuccess)
+        return WP_ERR_HIP;
+    hipGraphNode_t reset = nullptr, dec = nullptr;
+    void *rargs[] = {&p->d_counter};
+    hipKernelNodeParams rp = {};
+    rp.func = reinterpret_cast<void *>(&k_batch_reset);
+    rp.gridDim = dim3(1);
+    rp.blockDim = dim3(1);
+    rp.sharedMemBytes = 0;
+    rp.kernelParams = rargs;
+    rp.extra = nullptr;
+    if (hipGraphAddKernelNode(&reset, p->graph, nullptr, 0, &rp) != hipSuccess)
+        return WP_ERR_HIP;
+    uint32_t nitems32 = (uint32_t)p->nitems;
+    void *args[] = {&p->d_lists, &p->d_items, &nitems32, &p->d_counter, &p->err};
+    hipKernelNodeParams kp = {};
+    kp.func = const_cast<void *>(p->kernel);
+    kp.gridDim = dim3(p->grid);
+    kp.blockDim = dim3(64 * p->waves);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    if (hipGraphAddKernelNode(&dec, p->graph, &reset, 1, &kp) != hipSuccess)
+        return WP_ERR_HIP;
+    if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+        return WP_ERR_HIP;
+    return WP_OK;
+}
+
+}  // namespace wp
+
+using namespace wp;
+
+extern "C" int32_t wp_batch_plan(const uint32_t *pool, uint32_t *out_base, const wp_list *h_lists, uint64_t nlists,
+                                 const wp_tune *tune, void **h_plan, void *stream)
+{
+    if (h_plan == nullptr || (nlists > 0 && (pool == nullptr || out_base == nullptr || h_lists == nullptr)))
+        return WP_ERR_INVALID_ARG;
+    *h_plan = nullptr;
+    if (!aligned16(pool) || !aligned16(out_base))
+        return WP_ERR_INVALID_ARG;
+    wp_tune t = {4, 4, 4, 8, 0, 1};
+    if (tune) {
+        t = *tune;
+        if (t.waves == 0)
+            t.waves = 4;
+        if (t.vpl == 0)
+            t.vpl = 4;
+        if (t.depth == 0)
+            t.depth = t.waves == 8 ? 2 : 4;
+        if (t.run_units == 0)
+            t.run_units = 8;
+    }
+    const void *kern = pick_kernel(t.waves, t.vpl, t.depth);
+    if (kern == nullptr || t.run_units < 1 || t.run_units > 63 || t.wg_per_cu < 0 || t.wg_per_cu > 64)
+        return WP_ERR_INVALID_ARG;
+    DevState *ds = dev_state();
+    if (ds == nullptr)
+        return WP_ERR_HIP;
+    // host-side registry checks and items
+    std::vector<DevList> lists(nlists);
+    std::vector<uint4> fp_items, bp_items, tail_items;
+    for (uint64_t i = 0; i < nlists; ++i) {
+        const wp_list &l = h_lists[i];
+        if ((l.codec != WP_CODEC_BP && l.codec != WP_CODEC_FP) || l.reserved != 0 || (l.comp_off_words & 3u) ||
+            (l.out_off & 3u) || l.comp_words < kHdrWords || l.n > 0xFFFFFFFFull * 32ull)
+            return WP_ERR_INVALID_ARG;
+        lists[i].comp = pool + l.comp_off_words;
+        lists[i].out = out_base + l.out_off;
+        lists[i].comp_words = l.comp_words;
+        lists[i].n = l.n;
+        lists[i].codec = (uint32_t)l.codec;
+        lists[i].pad = 0;
+        const uint64_t nfull = l.n / kBlock;
+        const uint32_t li = (uint32_t)i;
+        if (l.codec == WP_CODEC_BP) {
+            const uint64_t units = (nfull + kBpBlocks - 1) / kBpBlocks;
+            for (uint64_t u = 0; u < units; u += (uint64_t)t.run_units) {
+                const uint64_t c = std::min<uint64_t>((uint64_t)t.run_units, units - u);
+                bp_items.push_back(make_uint4(li, kItemBpRun, (uint32_t)u, (uint32_t)c));
+            }
+        } else {
+            const uint64_t units = (nfull + kFpBlocks - 1) / kFpBlocks;
+            for (uint64_t u = 0; u < units; ++u)
+                fp_items.push_back(make_uint4(li, kItemFpPage, (uint32_t)u, 1));
+        }
+        if (l.n % kBlock)
+            tail_items.push_back(make_uint4(li, kItemTail, 0, 0));
+    }
+    if (nlists > 0xFFFFFFFFull)
+        return WP_ERR_INVALID_ARG;
+    // largest items first: full pages, then runs (longest first), then tails
+    std::stable_sort(bp_items.begin(), bp_items.end(), [](const uint4 &a, const uint4 &b) { return a.w > b.w; });
+    std::vector<uint4> items;
+    items.reserve(fp_items.size() + bp_items.size() + tail_items.size());
+    items.insert(items.end(), fp_items.begin(), fp_items.end());
+    items.insert(items.end(), bp_items.begin(), bp_items.end());
+    items.insert(items.end(), tail_items.begin(), tail_items.end());
+    if (items.size() > 0xFFFFFFF0ull)
+        return WP_ERR_INVALID_ARG;
+    Plan *p = new Plan();
+    p->device = ds->device;
+    p->err = ds->err;
+    p->nlists = nlists;
+    p->nitems = items.size();
+    p->waves = t.waves;
+    p->vpl = t.vpl;
+    p->depth = t.depth;
+    p->kernel = kern;
+    p->use_graph = t.use_graph != 0;
+    const uint64_t wpc = t.wg_per_cu > 0 ? (uint64_t)t.wg_per_cu : (t.waves == 2 ? 8 : 4);
+    uint64_t grid = (uint64_t)ds->cus * wpc;
+    grid = std::max<uint64_t>(1, std::min<uint64_t>(grid, p->nitems ? p->nitems : 1));
+    p->grid = (uint32_t)grid;
+    hipStream_t st = as_stream(stream);
+    if (hipMalloc(&p->d_counter, 16) != hipSuccess ||
+        hipMalloc(&p->d_lists, std::max<size_t>(1, lists.size()) * sizeof(DevList)) != hipSuccess ||
+        hipMalloc(&p->d_items, std::max<size_t>(1, items.size()) * sizeof(uint4)) != hipSuccess) {
+        release(p);
+        return WP_ERR_HIP;
+    }
+    if ((!lists.empty() &&
+         hipMemcpyAsync(p->d_lists, lists.data(), lists.size() * sizeof(DevList), hipMemcpyHostToDevice, st) !=
+             hipSuccess) ||
+        (!items.empty() &&
+         hipMemcpyAsync(p->d_items, items.data(), items.size() * sizeof(uint4), hipMemcpyHostToDevice, st) !=
+             hipSuccess) ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        release(p);
+        return WP_ERR_HIP;
+    }
+    if (p->use_graph && build_graph(p) != WP_OK) {
+        release(p);
+        return WP_ERR_HIP;
+    }
+    *h_plan = p;
+    return WP_OK;
+}
+
+extern "C" int32_t wp_batch_decode(void *h_plan, void *stream)
+{
+    Plan *p = static_cast<Plan *>(h_plan);
+    if (p == nullptr)
+        return WP_ERR_INVALID_ARG;
+    int d = -1;
+    if (hipGetDevice(&d) != hipSuccess || d != p->device)
+        return WP_ERR_INVALID_ARG;
+    hipStream_t st = as_stream(stream);
+    if (p->use_graph) {
+        (void)hipGetLastError();
+        return hipGraphLaunch(p->exec, st) == hipSuccess ? WP_OK : WP_ERR_HIP;
+    }
+    return launch_plan(p, st);
+}
+
+extern "C" uint64_t wp_batch_items(const void *h_plan)
+{
+    const Plan *p = static_cast<const Plan *>(h_plan);
+    return p ? p->nitems : 0;
+}
+
+extern "C" int32_t wp_batch_free(void *h_plan)
+{
+    Plan *p = static_cast<Plan *>(h_plan);
+    if (p == nullptr)
+        return WP_ERR_INVALID_ARG;
+    if (hipDeviceSynchronize() != hipSuccess) {
+        release(p);
+        return WP_ERR_HIP;
+    }
+    release(p);
+    return WP_OK;
+}

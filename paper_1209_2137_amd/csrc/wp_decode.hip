@@ -1,9 +1,15 @@
 // Single-list decoders: bp_decode and fastpfor_decode.
 //
-// One workgroup per unit (a 2048-integer meta-block or a 2^16-integer page)
-// plus one for the Variable Byte tail. Units are independent because the
-// directory stores each unit's base value(s), so there is no cross-workgroup
-// dependency and no second pass over the output.
+// Units are independent because the directory stores each unit's offset
+// and base value(s): no cross-workgroup dependency, no second pass.
+//
+// Binary packing: each workgroup decodes a contiguous run of meta-blocks.
+// The run's directory entries are read once (one lane per entry); while a
+// meta-block is decoded from LDS, the next one's words are already on their
+// way into registers, so every workgroup keeps one unit of HBM reads in
+// flight behind its compute and its stores.
+//
+// Patched pages: one workgroup per page (see fp_page).
 #include <mutex>
 #include <vector>
 
@@ -12,93 +18,78 @@
 
 namespace wp {
 
-// Decodes directory entry u of one list stream (unit u, or the tail when
-// u == n_units). Called by every thread of the workgroup.
-template <int CODEC, int WAVES, int VPL, typename Lds>
-__device__ void decode_entry(const uint32_t *__restrict__ in, uint64_t in_words, uint32_t *__restrict__ out,
-                             uint64_t n, uint64_t u, int *__restrict__ err, Lds &L)
+template <int WAVES, int VPL, int DEPTH>
+union BpKernelLds {
+    RingLds<WAVES, VPL, DEPTH> r;
+    TailLds<WAVES> tail;
+};
+
+// Decodes meta-blocks [blockIdx.x * upw, ...) of one list; the workgroup
+// after the last run decodes the tail.
+template <int WAVES, int VPL, int DEPTH>
+__global__ __launch_bounds__(64 * WAVES) void k_bp_decode(const uint32_t *__restrict__ in, uint64_t in_words,
+                                                          uint32_t *__restrict__ out, uint64_t n,
+                                                          int *__restrict__ err, uint32_t upw)
 {
-    const Hdr h = load_hdr(in);
-    const uint32_t per = CODEC == 0 ? kBpBlocks : kFpBlocks;
-    const uint64_t hn = (uint64_t)h.n_lo | ((uint64_t)h.n_hi << 32);
-    const uint32_t S = h.stride;
-    const uint64_t nfull = n / kBlock;
-    const uint32_t tail = (uint32_t)(n % kBlock);
-    const uint64_t units = (nfull + per - 1) / per;
-    const uint64_t E = 1 + (uint64_t)S;
-    const uint64_t ndir = units + (tail ? 1 : 0);
-    const uint64_t dir_end = kHdrWords + ((E * ndir + 3) & ~(uint64_t)3);
-    bool ok = h.magic == (CODEC == 0 ? kMagicBP : kMagicFP) && hn == n && (S == 0 || S == 1 || S == 4) &&
-              h.n_units == units && h.total <= in_words && dir_end <= h.total && h.tail_off <= h.total &&
-              ((tail == 0) == (h.tail_bytes == 0));
-    if (!ok) {
-        if (u == 0 && threadIdx.x == 0)
+    __shared__ BpKernelLds<WAVES, VPL, DEPTH> L;
+    ListHdr H;
+    if (!check_header(in, in_words, n, kMagicBP, kBpBlocks, H)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0)
             *err = kErrCorrupt;
         return;
     }
-    if (u >= ndir)
+    const uint32_t tid = threadIdx.x;
+    const uint64_t nwg = (H.units + upw - 1) / upw;
+    if (blockIdx.x >= nwg) {
+        if (blockIdx.x == nwg && H.tail)
+            if (!decode_tail_entry<WAVES>(in, H, out, L.tail) && tid == 0)
+                *err = kErrCorrupt;
         return;
-    const uint32_t *ent = in + kHdrWords + u * E;
-    uint32_t base[4] = {0u, 0u, 0u, 0u};
-    for (uint32_t s = 0; s < S; ++s)
-        base[s] = ent[1 + s];
-    const uint32_t off = ent[0];
-    if (u == units) {
-        ok = off == h.tail_off && off >= dir_end && (uint64_t)off + (h.tail_bytes + 3) / 4 == h.total;
-        if (ok)
-            ok = tail_decode<WAVES>(in + off, h.tail_bytes, tail, S, base, out + nfull * kBlock, L.tail);
-    } else {
-        const uint32_t end = (u + 1 < units) ? in[kHdrWords + (u + 1) * E] : h.tail_off;
-        ok = off >= dir_end && end >= off && end <= h.total && (off & 3u) == 0;
-        const uint64_t left = nfull - u * per;
-        const uint32_t nb = (uint32_t)(left < per ? left : per);
-        if (ok) {
-            if constexpr (CODEC == 0)
-                ok = bp_unit<WAVES, VPL>(in + off, end - off, nb, S, base, out + u * per * kBlock, L.bp);
-            else
-                ok = fp_page<WAVES, VPL>(in + off, end - off, nb, S, base, out + u * per * kBlock, L.fp);
-        }
     }
-    if (!ok && threadIdx.x == 0)
+    const uint64_t ua = (uint64_t)blockIdx.x * upw;
+    const uint32_t cnt = (uint32_t)((H.units - ua) < upw ? (H.units - ua) : upw);
+    if (!bp_decode_run<WAVES, VPL, DEPTH>(in, H, ua, cnt, out, L.r) && tid == 0)
         *err = kErrCorrupt;
 }
 
 template <int WAVES, int VPL>
-union BpUnion {
-    BpLds<WAVES, VPL> bp;
-    TailLds<WAVES> tail;
-};
-
-template <int WAVES, int VPL>
-union FpUnion {
+union FpKernelLds {
     FpLds<WAVES, VPL> fp;
     TailLds<WAVES> tail;
 };
 
-template <int WAVES, int VPL>
-__global__ __launch_bounds__(64 * WAVES) void k_bp_decode(const uint32_t *__restrict__ in, uint64_t in_words,
-                                                          uint32_t *__restrict__ out, uint64_t n,
-                                                          int *__restrict__ err)
-{
-    __shared__ BpUnion<WAVES, VPL> L;
-    struct {
-        BpLds<WAVES, VPL> &bp;
-        TailLds<WAVES> &tail;
-    } view{L.bp, L.tail};
-    decode_entry<0, WAVES, VPL>(in, in_words, out, n, blockIdx.x, err, view);
-}
-
+// One workgroup per page; the workgroup after the last page decodes the tail.
 template <int WAVES, int VPL>
 __global__ __launch_bounds__(64 * WAVES) void k_fp_decode(const uint32_t *__restrict__ in, uint64_t in_words,
                                                           uint32_t *__restrict__ out, uint64_t n,
                                                           int *__restrict__ err)
 {
-    __shared__ FpUnion<WAVES, VPL> L;
-    struct {
-        FpLds<WAVES, VPL> &fp;
-        TailLds<WAVES> &tail;
-    } view{L.fp, L.tail};
-    decode_entry<1, WAVES, VPL>(in, in_words, out, n, blockIdx.x, err, view);
+    __shared__ FpKernelLds<WAVES, VPL> L;
+    ListHdr H;
+    if (!check_header(in, in_words, n, kMagicFP, kFpBlocks, H)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            *err = kErrCorrupt;
+        return;
+    }
+    const uint64_t u = blockIdx.x;
+    bool ok = true;
+    if (u == H.units) {
+        if (H.tail)
+            ok = decode_tail_entry<WAVES>(in, H, out, L.tail);
+    } else if (u < H.units) {
+        const uint32_t off = in[kHdrWords + u];
+        const uint32_t end = (u + 1 < H.units) ? in[kHdrWords + u + 1] : H.tail_off;
+        uint32_t base[4] = {0u, 0u, 0u, 0u};
+        for (uint32_t s = 0; s < H.S; ++s)
+            base[s] = in[kHdrWords + H.ndir + u * H.S + s];
+        ok = off >= H.dir_end && end >= off && end <= H.total && (off & 3u) == 0;
+        const uint64_t left = H.nfull - u * kFpBlocks;
+        const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
+        if (ok)
+            ok = fp_page<WAVES, VPL>(in + off, end - off, nb, H.S, base, out + u * kFpUnitInts, L.fp);
+    }
+    if (!ok && threadIdx.x == 0)
+        *err = kErrCorrupt;
 }
 
 // ------------------------------------------------------------------------
@@ -106,7 +97,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_fp_decode(const uint32_t *__rest
 
 static std::mutex g_mu;
 static std::vector<DevState> g_dev;
-static Tune g_tune[2] = {{8, 4}, {8, 4}};
+static Tune g_tune[2] = {{4, 4, 8, 4}, {4, 4, 0, 0}};
 
 DevState *dev_state()
 {
@@ -135,21 +126,26 @@ DevState *dev_state()
     return &s;
 }
 
-Tune decode_tune(int codec) { return g_tune[codec == WP_CODEC_FP ? 1 : 0]; }
+Tune decode_tune(int codec)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_tune[codec == WP_CODEC_FP ? 1 : 0];
+}
 
 static bool valid_tune(int codec, int waves, int vpl)
 {
     if (codec == WP_CODEC_BP)
-        return (waves == 2 && vpl == 8) || (waves == 4 && (vpl == 4 || vpl == 8)) || (waves == 8 && vpl == 4);
+        return (waves == 2 && (vpl == 4 || vpl == 8)) || (waves == 4 && (vpl == 4 || vpl == 8)) ||
+               (waves == 8 && vpl == 4);
     return (waves == 4 || waves == 8) && (vpl == 4 || vpl == 8);
 }
 
-template <int WAVES, int VPL>
+template <int WAVES, int VPL, int DEPTH>
 static void launch_bp(uint64_t grid, hipStream_t st, const uint32_t *in, uint64_t in_words, uint32_t *out,
-                      uint64_t n, int *err)
+                      uint64_t n, int *err, uint32_t upw)
 {
-    hipLaunchKernelGGL((k_bp_decode<WAVES, VPL>), dim3((uint32_t)grid), dim3(64 * WAVES), 0, st, in, in_words,
-                       out, n, err);
+    hipLaunchKernelGGL((k_bp_decode<WAVES, VPL, DEPTH>), dim3((uint32_t)grid), dim3(64 * WAVES), 0, st, in,
+                       in_words, out, n, err, upw);
 }
 
 template <int WAVES, int VPL>
@@ -169,28 +165,46 @@ static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, u
         return WP_ERR_INVALID_ARG;
     if (n > 0xFFFFFFFFull * 32ull)
         return WP_ERR_INVALID_ARG;
-    const uint64_t per = codec == WP_CODEC_BP ? kBpBlocks : kFpBlocks;
-    const uint64_t nfull = n / kBlock;
-    const uint64_t ndir = (nfull + per - 1) / per + ((n % kBlock) ? 1 : 0);
-    const uint64_t grid = ndir ? ndir : 1;
-    if (grid > 0x7FFFFFFFull)
-        return WP_ERR_INVALID_ARG;
     DevState *ds = dev_state();
     if (ds == nullptr)
         return WP_ERR_HIP;
+    const uint64_t per = codec == WP_CODEC_BP ? kBpBlocks : kFpBlocks;
+    const uint64_t nfull = n / kBlock;
+    const uint64_t units = (nfull + per - 1) / per;
+    const uint64_t has_tail = (n % kBlock) ? 1 : 0;
     hipStream_t st = as_stream(stream);
     const Tune t = decode_tune(codec);
     (void)hipGetLastError();
     if (codec == WP_CODEC_BP) {
-        if (t.waves == 2 && t.vpl == 8)
-            launch_bp<2, 8>(grid, st, in, in_words, out, n, ds->err);
+        // runs of upw meta-blocks: about wg_per_cu runs per compute unit
+        const uint64_t target = (uint64_t)ds->cus * (uint64_t)(t.wg_per_cu > 0 ? t.wg_per_cu : 8);
+        uint64_t upw = (units + target - 1) / (target ? target : 1);
+        upw = upw < 1 ? 1 : (upw > 63 ? 63 : upw);
+        uint64_t grid = (units + upw - 1) / upw + has_tail;
+        grid = grid ? grid : 1;
+        if (grid > 0x7FFFFFFFull)
+            return WP_ERR_INVALID_ARG;
+        const uint32_t u32 = (uint32_t)upw;
+        const bool deep = t.depth >= 4;
+#define WP_BP(W, V)                                                                                             \
+    (deep ? launch_bp<W, V, 4>(grid, st, in, in_words, out, n, ds->err, u32)                                   \
+          : launch_bp<W, V, 2>(grid, st, in, in_words, out, n, ds->err, u32))
+        if (t.waves == 2 && t.vpl == 4)
+            WP_BP(2, 4);
+        else if (t.waves == 2 && t.vpl == 8)
+            WP_BP(2, 8);
         else if (t.waves == 4 && t.vpl == 4)
-            launch_bp<4, 4>(grid, st, in, in_words, out, n, ds->err);
+            WP_BP(4, 4);
         else if (t.waves == 4 && t.vpl == 8)
-            launch_bp<4, 8>(grid, st, in, in_words, out, n, ds->err);
+            WP_BP(4, 8);
         else
-            launch_bp<8, 4>(grid, st, in, in_words, out, n, ds->err);
+            WP_BP(8, 4);
+#undef WP_BP
     } else {
+        uint64_t grid = units + has_tail;
+        grid = grid ? grid : 1;
+        if (grid > 0x7FFFFFFFull)
+            return WP_ERR_INVALID_ARG;
         if (t.waves == 4 && t.vpl == 4)
             launch_fp<4, 4>(grid, st, in, in_words, out, n, ds->err);
         else if (t.waves == 4 && t.vpl == 8)
@@ -218,12 +232,13 @@ extern "C" int32_t fastpfor_decode(const uint32_t *in, uint64_t in_words, uint32
     return decode_common(WP_CODEC_FP, in, in_words, out, n, stream);
 }
 
-extern "C" int32_t wp_set_decode_tune(int32_t codec, int32_t waves, int32_t vpl)
+extern "C" int32_t wp_set_decode_tune(int32_t codec, int32_t waves, int32_t vpl, int32_t depth, int32_t wg_per_cu)
 {
-    if ((codec != WP_CODEC_BP && codec != WP_CODEC_FP) || !valid_tune(codec, waves, vpl))
+    if ((codec != WP_CODEC_BP && codec != WP_CODEC_FP) || !valid_tune(codec, waves, vpl) || wg_per_cu < 0 ||
+        wg_per_cu > 64 || (depth != 0 && depth != 2 && depth != 4))
         return WP_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(g_mu);
-    g_tune[codec] = Tune{waves, vpl};
+    g_tune[codec] = Tune{waves, vpl, wg_per_cu, depth ? depth : 4};
     return WP_OK;
 }
 

@@ -85,6 +85,28 @@ __device__ __forceinline__ uint32_t fetch_field(const uint32_t *w, uint32_t bit,
     return __builtin_amdgcn_alignbit(w[i + 1], w[i], bit) & mask;
 }
 
+// Raw buffer access (gfx9 buffer resource, dword3 = 0x00020000: 32-bit
+// data, no swizzle). Loads at byte offsets beyond `bytes` return 0 without
+// touching memory.
+typedef __amdgpu_buffer_rsrc_t BufRsrc;
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ BufRsrc make_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ uint32_t buf_load_u32(BufRsrc rs, uint32_t byte_off)
+{
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)byte_off, 0, 0);
+}
+
+__device__ __forceinline__ uint4 buf_load_u4(BufRsrc rs, uint32_t byte_off)
+{
+    const u32x4_t v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)byte_off, 0, 0);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 // Stream header, read with uniform (scalar) loads.
 struct Hdr {
     uint32_t magic, n_lo, n_hi, stride, n_units, tail_bytes, tail_off, total;
@@ -102,6 +124,33 @@ __device__ __forceinline__ Hdr load_hdr(const uint32_t *in)
     h.tail_off = in[6];
     h.total = in[7];
     return h;
+}
+
+// Validated header of one list stream, with derived sizes (uniform values).
+struct ListHdr {
+    uint32_t S, tail, tail_bytes, tail_off, total;
+    uint64_t nfull, units, ndir, dir_end;
+};
+
+// Checks the 8-word header against the caller's n and the stream length
+// and derives the directory geometry. `per` = blocks per unit.
+__device__ __forceinline__ bool check_header(const uint32_t *__restrict__ in, uint64_t in_words, uint64_t n,
+                                             uint32_t magic, uint32_t per, ListHdr &H)
+{
+    const Hdr h = load_hdr(in);
+    const uint64_t hn = (uint64_t)h.n_lo | ((uint64_t)h.n_hi << 32);
+    H.S = h.stride;
+    H.nfull = n / kBlock;
+    H.tail = (uint32_t)(n % kBlock);
+    H.units = (H.nfull + per - 1) / per;
+    H.ndir = H.units + (H.tail ? 1 : 0);
+    H.dir_end = kHdrWords + (((1 + (uint64_t)H.S) * H.ndir + 3) & ~(uint64_t)3);
+    H.tail_bytes = h.tail_bytes;
+    H.tail_off = h.tail_off;
+    H.total = h.total;
+    return h.magic == magic && hn == n && (H.S == 0 || H.S == 1 || H.S == 4) && h.n_units == H.units &&
+           h.total <= in_words && H.dir_end <= h.total && h.tail_off <= h.total && h.tail_off >= H.dir_end &&
+           ((H.tail == 0) == (h.tail_bytes == 0));
 }
 
 // Geometry of a pass for a (WAVES, VPL) configuration.
@@ -404,6 +453,101 @@ __device__ bool tail_decode(const uint32_t *__restrict__ tw, uint32_t tail_bytes
     return true;
 }
 
+// The list's tail entry (directory entry n_units): offset check, bases,
+// then tail_decode. Called by a whole workgroup.
+template <int WAVES>
+__device__ bool decode_tail_entry(const uint32_t *__restrict__ in, const ListHdr &H, uint32_t *__restrict__ out,
+                                  TailLds<WAVES> &L)
+{
+    const uint32_t off = in[kHdrWords + H.units];
+    uint32_t base[4] = {0u, 0u, 0u, 0u};
+    for (uint32_t s = 0; s < H.S; ++s)
+        base[s] = in[kHdrWords + H.ndir + H.units * H.S + s];
+    if (!(off == H.tail_off && (uint64_t)off + (H.tail_bytes + 3) / 4 == H.total))
+        return false;
+    return tail_decode<WAVES>(in + off, H.tail_bytes, H.tail, H.S, base, out + H.nfull * kBlock, L);
+}
+
+// Tables of a patched page from its per-block metadata L.b, L.mb, L.c
+// (entries beyond the page's blocks hold 0): block offsets in the packed
+// region (exclusive sum of 4*b), offsets into the position bytes
+// (exclusive sum of c) and, per block, the index of its first exception in
+// array k = maxb - b -- exceptions are appended to their array in block
+// order (Section 5), so this is the number of exceptions of earlier blocks
+// with the same k. Per-k totals accumulate in L.kcar (zeroed by the caller,
+// as is L.ktot). Rounds of T blocks; within a wavefront the same-k ranks
+// come from one masked scan per distinct k (ballot loop).
+template <int WAVES, int VPL>
+__device__ void fp_tables(FpLds<WAVES, VPL> &L, uint32_t &tot_words, uint32_t &tot_pos)
+{
+    constexpr int T = 64 * WAVES;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform(tid >> 6);
+    uint32_t carry_w = 0, carry_p = 0;
+    for (uint32_t r0 = 0; r0 < kFpBlocks; r0 += T) {
+        const uint32_t t = r0 + tid;
+        const uint32_t bw = 4u * L.b[t];
+        const uint32_t cc = L.c[t];
+        const uint32_t kk = (uint32_t)L.mb[t] - (uint32_t)L.b[t];
+        const uint32_t iw = wave_scan_incl(bw);
+        const uint32_t ip = wave_scan_incl(cc);
+        if (lane == 63) {
+            L.stot[wave][0] = iw;
+            L.stot[wave][1] = ip;
+        }
+        // rank among the wave's earlier blocks of the same k
+        uint32_t rk = 0;
+        uint64_t todo = ballot(cc > 0);
+        while (todo) {
+            const uint32_t lead = (uint32_t)__builtin_ctzll(todo);
+            const uint32_t k0 = wave_read(kk, lead);
+            const bool mine = cc > 0 && kk == k0;
+            const uint64_t mm = ballot(mine);
+            const uint32_t x = mine ? cc : 0u;
+            const uint32_t incl = wave_scan_incl(x);
+            if (mine)
+                rk = incl - x;
+            if (lane == 0)
+                L.ktot[wave][k0 > 32 ? 0 : k0] = wave_read(incl, 63);
+            todo &= ~mm;
+        }
+        __syncthreads();
+        uint32_t bw_before = carry_w, p_before = carry_p, all_w = 0, all_p = 0, k_before = 0;
+        for (int w = 0; w < WAVES; ++w) {
+            const uint32_t a = L.stot[w][0], c2 = L.stot[w][1];
+            if (w < (int)wave) {
+                bw_before += a;
+                p_before += c2;
+            }
+            all_w += a;
+            all_p += c2;
+        }
+        if (cc > 0 && kk <= 32) {
+            k_before = L.kcar[kk];
+            for (int w = 0; w < (int)wave; ++w)
+                k_before += L.ktot[w][kk];
+        }
+        L.blkoff[t] = bw_before + iw - bw;
+        L.posoff[t] = p_before + ip - cc;
+        L.rank[t] = k_before + rk;
+        carry_w += all_w;
+        carry_p += all_p;
+        __syncthreads();
+        if (tid < 33) {
+            uint32_t s = 0;
+            for (int w = 0; w < WAVES; ++w) {
+                s += L.ktot[w][tid];
+                L.ktot[w][tid] = 0;
+            }
+            L.kcar[tid] += s;
+        }
+        __syncthreads();
+    }
+    tot_words = carry_w;
+    tot_pos = carry_p;
+}
+
 // ------------------------------------------------------------------------
 // Patched page (Section 5). `page` points at the page header (16-byte
 // aligned), `nwords` its length, `nb` the number of blocks it must hold.
@@ -480,67 +624,8 @@ __device__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint
         if (b > 32 || mb > 32 || mb < b || c >= kBlock || ((c == 0) != (mb == b)))
             L.bad = 1;
     }
-    // block-wide scans of packed words, position counts and per-k ranks
     uint32_t carry_w = 0, carry_p = 0;
-    for (uint32_t r0 = 0; r0 < kFpBlocks; r0 += T) {
-        const uint32_t t = r0 + tid;
-        const uint32_t bw = 4u * L.b[t];
-        const uint32_t cc = L.c[t];
-        const uint32_t kk = (uint32_t)L.mb[t] - (uint32_t)L.b[t];
-        const uint32_t iw = wave_scan_incl(bw);
-        const uint32_t ip = wave_scan_incl(cc);
-        if (lane == 63) {
-            L.stot[wave][0] = iw;
-            L.stot[wave][1] = ip;
-        }
-        // rank among the wave's earlier blocks of the same k
-        uint32_t rk = 0;
-        uint64_t todo = ballot(cc > 0);
-        while (todo) {
-            const uint32_t lead = (uint32_t)__builtin_ctzll(todo);
-            const uint32_t k0 = wave_read(kk, lead);
-            const bool mine = cc > 0 && kk == k0;
-            const uint64_t mm = ballot(mine);
-            const uint32_t x = mine ? cc : 0u;
-            const uint32_t incl = wave_scan_incl(x);
-            if (mine)
-                rk = incl - x;
-            if (lane == 0)
-                L.ktot[wave][k0 > 32 ? 0 : k0] = wave_read(incl, 63);
-            todo &= ~mm;
-        }
-        __syncthreads();
-        uint32_t bw_before = carry_w, p_before = carry_p, all_w = 0, all_p = 0, k_before = 0;
-        for (int w = 0; w < WAVES; ++w) {
-            const uint32_t a = L.stot[w][0], c2 = L.stot[w][1];
-            if (w < (int)wave) {
-                bw_before += a;
-                p_before += c2;
-            }
-            all_w += a;
-            all_p += c2;
-        }
-        if (cc > 0 && kk <= 32) {
-            k_before = L.kcar[kk];
-            for (int w = 0; w < (int)wave; ++w)
-                k_before += L.ktot[w][kk];
-        }
-        L.blkoff[t] = bw_before + iw - bw;
-        L.posoff[t] = p_before + ip - cc;
-        L.rank[t] = k_before + rk;
-        carry_w += all_w;
-        carry_p += all_p;
-        __syncthreads();
-        if (tid < 33) {
-            uint32_t s = 0;
-            for (int w = 0; w < WAVES; ++w) {
-                s += L.ktot[w][tid];
-                L.ktot[w][tid] = 0;
-            }
-            L.kcar[tid] += s;
-        }
-        __syncthreads();
-    }
+    fp_tables<WAVES, VPL>(L, carry_w, carry_p);
     if (tid == 0) {
         L.blkoff[kFpBlocks] = carry_w;
         if (carry_w != packed_words || 3 * nb + carry_p != meta_bytes)
@@ -615,6 +700,198 @@ __device__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint
             store_lane<VPL>(out + j * kBlock + VPL * q, v);
     }
     return true;
+}
+
+// ------------------------------------------------------------------------
+// Full blocks held by meta-block u (16 except possibly the last).
+__device__ __forceinline__ uint32_t unit_blocks(const ListHdr &H, uint64_t u)
+{
+    const uint64_t left = H.nfull - u * kBpBlocks;
+    return (uint32_t)(left < kBpBlocks ? left : kBpBlocks);
+}
+
+constexpr uint32_t pow2ceil(uint32_t x)
+{
+    uint32_t p = 1;
+    while (p < x)
+        p <<= 1;
+    return p;
+}
+
+// A workgroup decodes a run of consecutive meta-blocks. Their compressed
+// words are one contiguous range of the stream, which is streamed through
+// an LDS ring in chunks of one 16-byte load per thread. DEPTH chunk loads
+// are in flight at any time (a register FIFO: the loop is unrolled DEPTH
+// times so every slot has a fixed register), so the bytes in flight do not
+// depend on how small the meta-blocks compress. A meta-block is decoded as
+// soon as its last word has reached the ring.
+template <int WAVES, int VPL, int DEPTH>
+struct RingGeo {
+    static constexpr int T = 64 * WAVES;
+    static constexpr uint32_t CW = T * 4;                 // words per chunk
+    static constexpr uint32_t MAXU = 4 + kBpUnitInts;     // words of the largest meta-block
+    // a group of DEPTH chunks is written while the oldest unfinished
+    // meta-block (started less than MAXU words before the group) stays intact
+    static constexpr uint32_t RB = pow2ceil(DEPTH * CW + MAXU);  // ring words
+};
+
+template <int WAVES, int VPL, int DEPTH>
+struct RingLds {
+    uint32_t ring[RingGeo<WAVES, VPL, DEPTH>::RB + 4];  // + a copy of words 0..3 after the end
+    uint32_t b[kBpBlocks];                              // widths of the meta-block being decoded
+    uint32_t off[kBpBlocks];                            // word offset of each block from its start
+    uint32_t wtot[2][WAVES][4];
+};
+
+// Field at bit `bit` of the word string starting at ring word `w0`
+// (ring positions wrap; the word after the last is mirrored).
+template <uint32_t RB>
+__device__ __forceinline__ uint32_t ring_field(const uint32_t *ring, uint32_t w0, uint32_t bit, uint32_t mask)
+{
+    const uint32_t p = (w0 + (bit >> 5)) & (RB - 1);
+    return __builtin_amdgcn_alignbit(ring[p + 1], ring[p], bit) & mask;
+}
+
+// Decodes the meta-block whose words start at ring word `su` (relative to
+// the run); all threads. Returns the uniform validity of its descriptor.
+template <int WAVES, int VPL, int DEPTH, bool FULL>
+__device__ __forceinline__ bool bp_unit_ring(RingLds<WAVES, VPL, DEPTH> &L, uint32_t su, uint32_t nw, uint32_t nb,
+                                             uint32_t S, uint32_t (&carry)[4], uint32_t *__restrict__ uout,
+                                             uint32_t &par)
+{
+    using G = Geo<WAVES, VPL>;
+    using RG = RingGeo<WAVES, VPL, DEPTH>;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform(tid >> 6);
+    uint32_t d[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        d[k] = uniform(L.ring[(su + k) & (RG::RB - 1)]);
+    uint32_t sum = 0, bt = 0, pre = 0;
+    bool ok = true;
+#pragma unroll
+    for (uint32_t j = 0; j < kBpBlocks; ++j) {
+        const uint32_t b = (d[j >> 2] >> (8 * (j & 3))) & 255u;
+        ok = ok && b <= 32 && (j < nb || b == 0);
+        sum += b;
+        // thread t: width of block t (clamped so that a bad descriptor
+        // cannot address outside the meta-block) and the words before it
+        const uint32_t bc = b < 32u ? b : 32u;
+        pre += j < tid ? bc : 0u;
+        bt = j == tid ? bc : bt;
+    }
+    ok = ok && nw == 4 + 4 * sum;
+    if (tid < kBpBlocks) {
+        L.b[tid] = bt;
+        L.off[tid] = 4 + 4 * pre;
+    }
+    __syncthreads();
+    const uint32_t q = lane % G::LPB;
+#pragma unroll
+    for (int p = 0; p < (int)kBpBlocks / G::BPP; ++p) {
+        const uint32_t j = p * G::BPP + wave * G::BPW + lane / G::LPB;
+        const uint32_t b = L.b[j];
+        const uint32_t mask = width_mask(b);
+        const uint32_t w0 = su + L.off[j];
+        uint32_t bit = VPL * q * b;
+        uint32_t v[VPL];
+#pragma unroll
+        for (int r = 0; r < VPL; ++r) {
+            v[r] = ring_field<RG::RB>(L.ring, w0, bit, mask);
+            bit += b;
+        }
+        scan_pass<WAVES, VPL>(v, S, carry, L.wtot[par]);
+        par ^= 1u;
+        if (FULL || j < nb)
+            store_lane<VPL>(uout + j * kBlock + VPL * q, v);
+    }
+    __syncthreads();
+    return ok;
+}
+
+// Decodes meta-blocks [ua, ua + cnt) of the list whose validated header is
+// H (cnt <= 63). All threads of the workgroup; returns the uniform validity
+// of the run (a bad unit's output is unspecified but stays in its place).
+template <int WAVES, int VPL, int DEPTH>
+__device__ bool bp_decode_run(const uint32_t *__restrict__ in, const ListHdr &H, uint64_t ua, uint32_t cnt,
+                              uint32_t *__restrict__ out, RingLds<WAVES, VPL, DEPTH> &L)
+{
+    using RG = RingGeo<WAVES, VPL, DEPTH>;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = lane_id();
+    // the run's directory: lane i holds the offset of entry ua + i (i <= cnt)
+    // and its bases
+    uint32_t offv = 0;
+    uint32_t bv[4] = {0u, 0u, 0u, 0u};
+    if (lane <= cnt)
+        offv = (ua + lane < H.units) ? in[kHdrWords + ua + lane] : H.tail_off;
+    if (lane < cnt)
+        for (uint32_t s = 0; s < H.S; ++s)
+            bv[s] = in[kHdrWords + H.ndir + (ua + lane) * H.S + s];
+    const uint32_t W0 = wave_read(offv, 0), Wend = wave_read(offv, cnt);
+    bool bad = !(W0 >= H.dir_end && Wend >= W0 && Wend <= H.total && (W0 & 3u) == 0);
+    const uint32_t run_len = bad ? 0u : Wend - W0;
+    const BufRsrc rs = make_rsrc(in + (bad ? 0u : W0), run_len * 4u);
+    const uint32_t nchunks = (run_len + RG::CW - 1) / RG::CW;
+    // DEPTH chunk loads in flight, one named register per slot (an array
+    // indexed by a loop counter ends up in scratch memory)
+    uint4 s0, s1, s2, s3;
+    s0 = buf_load_u4(rs, (0 * RG::CW + tid * 4) * 4);
+    s1 = buf_load_u4(rs, (1 * RG::CW + tid * 4) * 4);
+    if constexpr (DEPTH > 2) {
+        s2 = buf_load_u4(rs, (2 * RG::CW + tid * 4) * 4);
+        s3 = buf_load_u4(rs, (3 * RG::CW + tid * 4) * 4);
+    }
+    // chunk c + k goes from its slot into the ring and the slot reloads
+    // chunk c + k + DEPTH; the reload is issued on every path (beyond the
+    // run it reads nothing), so each slot always has DEPTH - 1 younger
+    // loads when it is next needed and that wait never drains the stores
+    auto put = [&](uint4 &slot, uint32_t c) __attribute__((always_inline)) {
+        if (c < nchunks) {
+            const uint32_t pos = (c * RG::CW + tid * 4) & (RG::RB - 1);
+            *reinterpret_cast<uint4 *>(&L.ring[pos]) = slot;
+            if (pos == 0)
+                *reinterpret_cast<uint4 *>(&L.ring[RG::RB]) = slot;
+        }
+        slot = buf_load_u4(rs, ((c + DEPTH) * RG::CW + tid * 4) * 4);
+    };
+    auto put_group = [&](uint32_t c0) __attribute__((always_inline)) {
+        put(s0, c0);
+        put(s1, c0 + 1);
+        if constexpr (DEPTH > 2) {
+            put(s2, c0 + 2);
+            put(s3, c0 + 3);
+        }
+        __syncthreads();
+    };
+    uint32_t i = 0, par = 0;
+    put_group(0);
+    for (uint32_t c0 = 0;; c0 += DEPTH) {
+        const uint32_t written = (c0 + DEPTH) * RG::CW < run_len ? (c0 + DEPTH) * RG::CW : run_len;
+        // decode every meta-block whose words are all in the ring
+        while (i < cnt) {
+            const uint32_t su = wave_read(offv, i) - W0, eu = wave_read(offv, i + 1) - W0;
+            if (eu > written)
+                break;
+            const uint64_t u = ua + i;
+            uint32_t carry[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                carry[k] = wave_read(bv[k], i);
+            if (eu < su + 4 || eu - su > RG::MAXU)
+                bad = true;
+            else
+                bad = !bp_unit_ring<WAVES, VPL, DEPTH, false>(L, su, eu - su, unit_blocks(H, u), H.S, carry,
+                                                            out + u * kBpUnitInts, par) ||
+                      bad;
+            ++i;
+        }
+        if (c0 + DEPTH >= nchunks)
+            break;
+        put_group(c0 + DEPTH);
+    }
+    return !bad && i == cnt;
 }
 
 }  // namespace wp

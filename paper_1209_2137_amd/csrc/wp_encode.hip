@@ -1,0 +1,460 @@
+// Encoders: bp_encode and fastpfor_encode, producing the stream layout the
+// decoders read (see wavepack.h).
+//
+// Four stream-ordered launches:
+//   1. analyze: one workgroup per unit computes every block's width(s) and
+//      the unit's length in words;
+//   2. an in-place inclusive scan of the unit lengths (the chained scan of
+//      delta_decode_inplace) gives every unit its offset;
+//   3. pack: one workgroup per unit writes its directory entry and data;
+//   4. finish: the Variable Byte tail, the header and the stream length.
+// Bits are OR-ed into place (LDS atomics for a block's packed words,
+// device atomics for a page's exception arrays, after the region has been
+// cleared), so the order in which lanes write never matters.
+#include "wp_device.hpp"
+#include "wp_host.hpp"
+
+namespace wp {
+
+// binary digits of x, ceil(log2(x + 1)) (Section 2); 0 for x = 0
+__device__ __forceinline__ uint32_t nbits(uint32_t x) { return 32u - (uint32_t)__clz((int)x); }
+
+// delta of Section 3 at index i (values before the array start count as 0)
+__device__ __forceinline__ uint32_t delta_at(const uint32_t *__restrict__ x, uint64_t i, uint32_t S)
+{
+    const uint32_t v = x[i];
+    if (S == 0)
+        return v;
+    return i >= S ? v - x[i - S] : v;
+}
+
+__device__ __forceinline__ uint32_t wave_or(uint32_t v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        v |= (uint32_t)__shfl_xor((int)v, m, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)v, m, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// ORs the low b bits of value i of a block into the block's word string
+__device__ __forceinline__ void or_field(uint32_t *w, uint32_t i, uint32_t b, uint32_t v)
+{
+    if (b == 0)
+        return;
+    const uint32_t pos = i * b, s = pos & 31u;
+    v &= width_mask(b);
+    atomicOr(&w[pos >> 5], v << s);
+    if (s + b > 32u)
+        atomicOr(&w[(pos >> 5) + 1], v >> (32u - s));
+}
+
+// directory entry: offset at word 8 + entry, bases after all ndir offsets;
+// base_s = x[start - S + s], 0 before the array start
+__device__ __forceinline__ void write_dir_entry(uint32_t *out, uint64_t entry, uint64_t ndir, uint32_t S,
+                                                uint32_t off, const uint32_t *__restrict__ x, uint64_t start)
+{
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0)
+        out[kHdrWords + entry] = off;
+    else if (tid <= S)
+        out[kHdrWords + ndir + entry * S + (tid - 1)] = (start + (tid - 1) >= S) ? x[start + (tid - 1) - S] : 0u;
+}
+
+__host__ __device__ __forceinline__ uint64_t dir_entries(uint64_t n, uint64_t per)
+{
+    const uint64_t nfull = n / kBlock;
+    return (nfull + per - 1) / per + ((n % kBlock) ? 1 : 0);
+}
+
+// ------------------------------------------------------------------------
+// Binary packing (Section 6.2): block width = bits of the OR of its deltas.
+
+__global__ __launch_bounds__(256) void k_bp_analyze(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
+                                                    uint8_t *__restrict__ widths, uint32_t *__restrict__ sizes)
+{
+    __shared__ uint32_t s_b[kBpBlocks];
+    const uint64_t u = blockIdx.x;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform(threadIdx.x >> 6);
+    const uint64_t nfull = n / kBlock;
+    const uint64_t left = nfull - u * kBpBlocks;
+    const uint32_t nb = (uint32_t)(left < kBpBlocks ? left : kBpBlocks);
+    for (uint32_t jj = 0; jj < 4; ++jj) {
+        const uint32_t j = wave * 4 + jj;
+        uint32_t b = 0;
+        if (j < nb) {
+            const uint64_t i0 = (u * kBpBlocks + j) * kBlock + 2 * lane;
+            b = nbits(wave_or(delta_at(x, i0, S) | delta_at(x, i0 + 1, S)));
+        }
+        if (lane == 0)
+            s_b[j] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x < kBpBlocks)
+        widths[u * kBpBlocks + threadIdx.x] = (uint8_t)s_b[threadIdx.x];
+    if (threadIdx.x == 0) {
+        uint32_t sum = 0;
+        for (uint32_t j = 0; j < kBpBlocks; ++j)
+            sum += s_b[j];
+        sizes[u] = 4 + 4 * sum;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bp_pack(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
+                                                 const uint8_t *__restrict__ widths,
+                                                 const uint32_t *__restrict__ incl, uint32_t dir_end,
+                                                 uint32_t *__restrict__ out)
+{
+    __shared__ uint32_t s_w[4][kBlock];
+    __shared__ uint32_t s_b[kBpBlocks], s_off[kBpBlocks];
+    const uint64_t u = blockIdx.x;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform(tid >> 6);
+    const uint64_t nfull = n / kBlock;
+    const uint64_t left = nfull - u * kBpBlocks;
+    const uint32_t nb = (uint32_t)(left < kBpBlocks ? left : kBpBlocks);
+    if (tid < kBpBlocks) {
+        uint32_t pre = 0;
+        for (uint32_t j = 0; j < tid; ++j)
+            pre += widths[u * kBpBlocks + j];
+        s_b[tid] = widths[u * kBpBlocks + tid];
+        s_off[tid] = 4 * pre;
+    }
+    __syncthreads();
+    const uint32_t size = s_off[kBpBlocks - 1] + 4 * s_b[kBpBlocks - 1] + 4;
+    const uint32_t off = dir_end + incl[u] - size;
+    write_dir_entry(out, u, dir_entries(n, kBpBlocks), S, off, x, u * kBpUnitInts);
+    if (tid < 4)
+        out[off + tid] = s_b[4 * tid] | (s_b[4 * tid + 1] << 8) | (s_b[4 * tid + 2] << 16) | (s_b[4 * tid + 3] << 24);
+    for (uint32_t jj = 0; jj < 4; ++jj) {
+        const uint32_t j = wave * 4 + jj;
+        const uint32_t b = s_b[j];
+        for (uint32_t i = lane; i < 4 * b; i += 64)
+            s_w[wave][i] = 0;
+        __syncthreads();
+        if (j < nb && b) {
+            const uint64_t i0 = (u * kBpBlocks + j) * kBlock + 2 * lane;
+            or_field(s_w[wave], 2 * lane, b, delta_at(x, i0, S));
+            or_field(s_w[wave], 2 * lane + 1, b, delta_at(x, i0 + 1, S));
+        }
+        __syncthreads();
+        if (j < nb)
+            for (uint32_t i = lane; i < 4 * b; i += 64)
+                out[off + 4 + s_off[j] + i] = s_w[wave][i];
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------
+// Patched pages (Section 5): per block, the width b minimising
+// 128*b + c(b)*(8 + maxb - b) over b in [0, maxb], c(b) = values wider than
+// b; scanning b downward from maxb, only a strictly smaller cost replaces
+// the current choice.
+
+__global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
+                                                    uint8_t *__restrict__ meta, uint64_t nblk,
+                                                    uint32_t *__restrict__ sizes)
+{
+    __shared__ uint32_t s_cnt[33];
+    __shared__ uint32_t s_pw, s_pc;
+    const uint64_t p = blockIdx.x;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform(tid >> 6);
+    const uint64_t nfull = n / kBlock;
+    const uint64_t left = nfull - p * kFpBlocks;
+    const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
+    if (tid < 33)
+        s_cnt[tid] = 0;
+    if (tid == 0)
+        s_pw = 0, s_pc = 0;
+    __syncthreads();
+    for (uint32_t t = wave; t < nb; t += 8) {
+        const uint64_t blk = p * kFpBlocks + t;
+        const uint64_t i0 = blk * kBlock + 2 * lane;
+        const uint32_t w0 = nbits(delta_at(x, i0, S)), w1 = nbits(delta_at(x, i0 + 1, S));
+        const uint32_t maxb = uniform(wave_max(w0 > w1 ? w0 : w1));
+        uint32_t best_b = maxb, best_cost = kBlock * maxb, best_c = 0;
+        for (int b = (int)maxb - 1; b >= 0; --b) {
+            const uint32_t c = (uint32_t)__builtin_popcountll(ballot(w0 > (uint32_t)b)) +
+                               (uint32_t)__builtin_popcountll(ballot(w1 > (uint32_t)b));
+            const uint32_t cost = kBlock * (uint32_t)b + c * (8u + maxb - (uint32_t)b);
+            if (cost < best_cost) {
+                best_cost = cost;
+                best_b = (uint32_t)b;
+                best_c = c;
+            }
+        }
+        if (lane == 0) {
+            meta[blk] = (uint8_t)best_b;
+            meta[nblk + blk] = (uint8_t)maxb;
+            meta[2 * nblk + blk] = (uint8_t)best_c;
+            atomicAdd(&s_pw, 4 * best_b);
+            atomicAdd(&s_pc, best_c);
+            atomicAdd(&s_cnt[maxb - best_b], best_c);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t nset = 0, exc_w = 0;
+        for (uint32_t k = 1; k <= 32; ++k)
+            if (s_cnt[k]) {
+                ++nset;
+                exc_w += ((s_cnt[k] + kBlock - 1) / kBlock) * 4 * k;
+            }
+        const uint32_t meta_bytes = 3 * nb + s_pc;
+        sizes[p] = pad4(4 + nset) + s_pw + ((meta_bytes + 15) / 16) * 4 + exc_w;
+    }
+}
+
+__global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
+                                                 const uint8_t *__restrict__ meta, uint64_t nblk,
+                                                 const uint32_t *__restrict__ incl, uint32_t dir_end,
+                                                 uint32_t *__restrict__ out)
+{
+    __shared__ FpLds<8, 4> L;
+    constexpr int T = 512;
+    const uint64_t p = blockIdx.x;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform(tid >> 6);
+    const uint64_t nfull = n / kBlock;
+    const uint64_t left = nfull - p * kFpBlocks;
+    const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
+    for (uint32_t t = tid; t < kFpBlocks; t += T) {
+        const bool in = t < nb;
+        L.b[t] = in ? meta[p * kFpBlocks + t] : 0;
+        L.mb[t] = in ? meta[nblk + p * kFpBlocks + t] : 0;
+        L.c[t] = in ? meta[2 * nblk + p * kFpBlocks + t] : 0;
+    }
+    for (uint32_t i = tid; i < 8 * 33; i += T)
+        (&L.ktot[0][0])[i] = 0;
+    if (tid < 33)
+        L.kcar[tid] = 0;
+    __syncthreads();
+    uint32_t packed_words = 0, npos = 0;
+    fp_tables<8, 4>(L, packed_words, npos);
+    // per-k counts are in L.kcar; exception array offsets from the page start
+    uint32_t bitset = 0;
+    for (uint32_t k = 1; k <= 32; ++k)
+        bitset |= L.kcar[k] ? (1u << (k - 1)) : 0u;
+    const uint32_t nset = __builtin_popcount(bitset);
+    const uint32_t hdr_w = pad4(4 + nset);
+    const uint32_t meta_bytes = 3 * nb + npos;
+    const uint32_t meta_w = ((meta_bytes + 15) / 16) * 4;
+    const uint32_t exc_at = hdr_w + packed_words + meta_w;
+    if (wave == 0) {
+        const uint32_t k = lane + 1;
+        const uint32_t cnt = lane < 32 ? L.kcar[k] : 0u;
+        const uint32_t wk = ((cnt + kBlock - 1) / kBlock) * 4u * k;
+        const uint32_t incl_k = wave_scan_incl(wk);
+        if (lane < 32)
+            L.excbase[k] = exc_at + incl_k - wk;
+        if (lane == 63)
+            L.kcnt[0] = exc_at + incl_k;  // page length in words
+    }
+    __syncthreads();
+    const uint32_t size = L.kcnt[0];
+    const uint32_t off = dir_end + incl[p] - size;
+    write_dir_entry(out, p, dir_entries(n, kFpBlocks), S, off, x, p * kFpUnitInts);
+    uint32_t *page = out + off;
+    if (tid == 0) {
+        page[0] = nb;
+        page[1] = packed_words;
+        page[2] = meta_bytes;
+        page[3] = bitset;
+    }
+    if (tid >= 32 && tid < 64) {  // counts of the non-empty arrays, k ascending
+        const uint32_t k = tid - 31;
+        if ((bitset >> (k - 1)) & 1u)
+            page[4 + __builtin_popcount(bitset & ((1u << (k - 1)) - 1u))] = L.kcar[k];
+    }
+    if (tid >= 64 && tid - 64 >= 4 + nset && tid - 64 < hdr_w)
+        page[tid - 64] = 0;
+    // clear metadata and exception arrays, which are assembled with byte
+    // stores and ORs
+    for (uint32_t i = hdr_w + packed_words + tid; i < size; i += T)
+        page[i] = 0;
+    __threadfence();
+    __syncthreads();
+    uint8_t *mbytes = reinterpret_cast<uint8_t *>(page + hdr_w + packed_words);
+    for (uint32_t t = tid; t < nb; t += T) {
+        mbytes[t] = L.b[t];
+        mbytes[nb + t] = L.mb[t];
+        mbytes[2 * nb + t] = L.c[t];
+    }
+    uint32_t *sw = L.ptc + wave * kBlock;
+    const uint32_t rounds = (nb + 7) / 8;
+    for (uint32_t it = 0; it < rounds; ++it) {
+        const uint32_t t = it * 8 + wave;
+        const bool live = t < nb;
+        const uint32_t b = live ? L.b[t] : 0u;
+        for (uint32_t i = lane; i < 4 * b; i += 64)
+            sw[i] = 0;
+        __syncthreads();
+        if (live) {
+            const uint64_t i0 = (p * kFpBlocks + t) * kBlock + 2 * lane;
+            const uint32_t d0 = delta_at(x, i0, S), d1 = delta_at(x, i0 + 1, S);
+            or_field(sw, 2 * lane, b, d0);
+            or_field(sw, 2 * lane + 1, b, d1);
+            const bool e0 = nbits(d0) > b, e1 = nbits(d1) > b;
+            const uint64_t m0 = ballot(e0), m1 = ballot(e1);
+            const uint32_t r0 = lanes_below(m0) + lanes_below(m1);
+            const uint32_t k = (uint32_t)L.mb[t] - b;
+            const uint32_t rk = L.rank[t];
+            uint32_t *arr = page + L.excbase[k <= 32 ? k : 0];
+            for (int h = 0; h < 2; ++h) {
+                const bool e = h ? e1 : e0;
+                if (!e)
+                    continue;
+                const uint32_t idx = r0 + (h ? (uint32_t)e0 : 0u);
+                mbytes[3 * nb + L.posoff[t] + idx] = (uint8_t)(2 * lane + h);
+                const uint32_t hv = (h ? d1 : d0) >> b;
+                const uint32_t bit = (rk + idx) * k, s = bit & 31u;
+                atomicOr(&arr[bit >> 5], hv << s);
+                if (s + k > 32u)
+                    atomicOr(&arr[(bit >> 5) + 1], hv >> (32u - s));
+            }
+        }
+        __syncthreads();
+        if (live)
+            for (uint32_t i = lane; i < 4 * b; i += 64)
+                page[hdr_w + L.blkoff[t] + i] = sw[i];
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------
+// Tail (Variable Byte, Section 2.4), directory padding, header, length.
+
+__global__ __launch_bounds__(128) void k_finish(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
+                                                uint32_t codec, const uint32_t *__restrict__ incl, uint64_t units,
+                                                uint32_t dir_end, uint32_t *__restrict__ out,
+                                                uint64_t *__restrict__ out_words)
+{
+    __shared__ uint32_t s_bytes[(kMaxTailBytes + 3) / 4 + 1];
+    __shared__ uint32_t s_tot[2];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform(tid >> 6);
+    const uint64_t nfull = n / kBlock;
+    const uint32_t tail = (uint32_t)(n % kBlock);
+    const uint32_t E = 1 + S;
+    const uint64_t ndir = units + (tail ? 1 : 0);
+    const uint32_t tail_off = units ? dir_end + incl[units - 1] : dir_end;
+    for (uint32_t i = tid; i < sizeof(s_bytes) / 4; i += 128)
+        s_bytes[i] = 0;
+    const uint32_t d = tid < tail ? delta_at(x, nfull * kBlock + tid, S) : 0u;
+    const uint32_t nb7 = (nbits(d) + 6) / 7;
+    const uint32_t len = tid < tail ? (nb7 ? nb7 : 1u) : 0u;
+    const uint32_t inc = wave_scan_incl(len);
+    if (lane == 63)
+        s_tot[wave] = inc;
+    __syncthreads();
+    const uint32_t at = inc - len + (wave ? s_tot[0] : 0u);
+    const uint32_t tail_bytes = s_tot[0] + s_tot[1];
+    uint8_t *sb = reinterpret_cast<uint8_t *>(s_bytes);
+    for (uint32_t k = 0; k < len; ++k)
+        sb[at + k] = (uint8_t)(((d >> (7 * k)) & 127u) | (k + 1 == len ? 128u : 0u));
+    __syncthreads();
+    for (uint32_t i = tid; i < (tail_bytes + 3) / 4; i += 128)
+        out[tail_off + i] = s_bytes[i];
+    if (tail)
+        write_dir_entry(out, units, ndir, S, tail_off, x, nfull * kBlock);
+    for (uint64_t i = kHdrWords + ndir * E + tid; i < dir_end; i += 128)
+        out[i] = 0;
+    const uint32_t total = tail_off + (tail_bytes + 3) / 4;
+    if (tid == 0) {
+        out[0] = codec == WP_CODEC_BP ? kMagicBP : kMagicFP;
+        out[1] = (uint32_t)n;
+        out[2] = (uint32_t)(n >> 32);
+        out[3] = S;
+        out[4] = (uint32_t)units;
+        out[5] = tail_bytes;
+        out[6] = tail_off;
+        out[7] = total;
+        *out_words = total;
+    }
+}
+
+static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t stride, uint32_t *out,
+                             uint64_t cap, uint64_t *out_words, void *stream)
+{
+    if (stride != 0 && stride != 1 && stride != 4)
+        return WP_ERR_INVALID_ARG;
+    if (out == nullptr || out_words == nullptr || (n > 0 && in == nullptr))
+        return WP_ERR_INVALID_ARG;
+    if (!aligned16(out) || (reinterpret_cast<uintptr_t>(in) & 3u) || (reinterpret_cast<uintptr_t>(out_words) & 7u))
+        return WP_ERR_INVALID_ARG;
+    const uint64_t need = wp_max_compressed_words(codec, n);
+    if (need == 0)
+        return WP_ERR_INVALID_ARG;
+    if (cap < need)
+        return WP_ERR_CAPACITY;
+    const uint64_t per = codec == WP_CODEC_BP ? kBpBlocks : kFpBlocks;
+    const uint64_t nfull = n / kBlock;
+    const uint64_t units = (nfull + per - 1) / per;
+    const uint64_t E = 1 + (uint64_t)stride;
+    const uint64_t ndir = units + ((n % kBlock) ? 1 : 0);
+    const uint32_t dir_end = (uint32_t)(kHdrWords + ((E * ndir + 3) & ~3ull));
+    hipStream_t st = as_stream(stream);
+    // scratch: scan status | unit sizes | per-block metadata
+    const uint64_t status_words = scan_status_words(units);
+    const uint64_t sizes_off = status_words * 8;
+    const uint64_t meta_off = sizes_off + ((units * 4 + 255) & ~255ull);
+    const uint64_t nblk = units * per;
+    const uint64_t meta_len = codec == WP_CODEC_BP ? nblk : 3 * nblk;
+    char *scr = static_cast<char *>(stream_scratch(st, meta_off + meta_len + 256));
+    if (scr == nullptr)
+        return WP_ERR_HIP;
+    uint64_t *status = reinterpret_cast<uint64_t *>(scr);
+    uint32_t *sizes = reinterpret_cast<uint32_t *>(scr + sizes_off);
+    uint8_t *meta = reinterpret_cast<uint8_t *>(scr + meta_off);
+    (void)hipGetLastError();
+    if (units) {
+        if (codec == WP_CODEC_BP)
+            hipLaunchKernelGGL(k_bp_analyze, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride, meta,
+                               sizes);
+        else
+            hipLaunchKernelGGL(k_fp_analyze, dim3((uint32_t)units), dim3(512), 0, st, in, n, (uint32_t)stride, meta,
+                               nblk, sizes);
+        if (launch_inclusive_scan(sizes, units, status, st) != WP_OK)
+            return WP_ERR_HIP;
+        if (codec == WP_CODEC_BP)
+            hipLaunchKernelGGL(k_bp_pack, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride, meta,
+                               sizes, dir_end, out);
+        else
+            hipLaunchKernelGGL(k_fp_pack, dim3((uint32_t)units), dim3(512), 0, st, in, n, (uint32_t)stride, meta,
+                               nblk, sizes, dir_end, out);
+    }
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(128), 0, st, in, n, (uint32_t)stride, (uint32_t)codec, sizes, units,
+                       dir_end, out, out_words);
+    return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
+}
+
+}  // namespace wp
+
+using namespace wp;
+
+extern "C" int32_t bp_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,
+                             uint64_t out_cap_words, uint64_t *out_words, void *stream)
+{
+    return encode_common(WP_CODEC_BP, in, n, delta_stride, out, out_cap_words, out_words, stream);
+}
+
+extern "C" int32_t fastpfor_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,
+                                   uint64_t out_cap_words, uint64_t *out_words, void *stream)
+{
+    return encode_common(WP_CODEC_FP, in, n, delta_stride, out, out_cap_words, out_words, stream);
+}

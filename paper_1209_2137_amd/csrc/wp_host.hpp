@@ -29,8 +29,16 @@ void *stream_scratch(hipStream_t stream, size_t bytes);
 struct Tune {
     int waves;
     int vpl;
+    int wg_per_cu;  // binary packing: runs of meta-blocks per compute unit (0 = default)
+    int depth;      // binary packing: chunk loads in flight per workgroup (4 or 8)
 };
 Tune decode_tune(int codec);
+
+// In-place inclusive prefix sum of data[0..n) on `st` (the chained scan of
+// delta_decode_inplace, stride 1, init 0). `status` must hold
+// scan_status_words(n) zero-or-garbage words; it is cleared on the stream.
+uint64_t scan_status_words(uint64_t n);
+int32_t launch_inclusive_scan(uint32_t *data, uint64_t n, uint64_t *status, hipStream_t st);
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 

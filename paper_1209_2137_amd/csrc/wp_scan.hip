@@ -263,6 +263,33 @@ void *stream_scratch(hipStream_t stream, size_t bytes)
 
 using namespace wp;
 
+namespace wp {
+
+uint64_t scan_status_words(uint64_t n)
+{
+    const uint64_t tiles = (n + kTileInts - 1) / kTileInts;
+    return (uint64_t)kStatusWords * (tiles + 1);
+}
+
+static int32_t launch_scan(uint32_t *data, uint64_t n, uint32_t init, uint32_t stride, uint64_t *status,
+                           hipStream_t st)
+{
+    const uint64_t tiles = (n + kTileInts - 1) / kTileInts;
+    const uint64_t words = scan_status_words(n);
+    hipLaunchKernelGGL(k_fill_zero, dim3((uint32_t)((words + 255) / 256)), dim3(256), 0, st, status, words);
+    hipLaunchKernelGGL(k_delta_scan, dim3((uint32_t)tiles), dim3(kScanT), 0, st, data, n, init, stride, status);
+    return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
+}
+
+int32_t launch_inclusive_scan(uint32_t *data, uint64_t n, uint64_t *status, hipStream_t st)
+{
+    if (n == 0)
+        return WP_OK;
+    return launch_scan(data, n, 0u, 1u, status, st);
+}
+
+}  // namespace wp
+
 extern "C" int32_t delta_decode_inplace(uint32_t *data, uint64_t n, uint32_t init, int32_t stride, void *stream)
 {
     if (stride != 1 && stride != 4)
@@ -275,13 +302,9 @@ extern "C" int32_t delta_decode_inplace(uint32_t *data, uint64_t n, uint32_t ini
     if (tiles > 0x7FFFFFFFull)
         return WP_ERR_INVALID_ARG;
     hipStream_t st = as_stream(stream);
-    const uint64_t words = (uint64_t)kStatusWords * (tiles + 1);
-    uint64_t *status = static_cast<uint64_t *>(stream_scratch(st, words * sizeof(uint64_t)));
+    uint64_t *status = static_cast<uint64_t *>(stream_scratch(st, scan_status_words(n) * sizeof(uint64_t)));
     if (status == nullptr)
         return WP_ERR_HIP;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_fill_zero, dim3((uint32_t)((words + 255) / 256)), dim3(256), 0, st, status, words);
-    hipLaunchKernelGGL(k_delta_scan, dim3((uint32_t)tiles), dim3(kScanT), 0, st, data, n, init, (uint32_t)stride,
-                       status);
-    return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
+    return launch_scan(data, n, init, (uint32_t)stride, status, st);
 }

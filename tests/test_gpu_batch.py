@@ -1,0 +1,102 @@
+"""Batched persistent decoding on the GPU: every list decoded in one launch
+must equal its generator array (which the single-list path and the CPU
+oracle decode to as well), for graph and plain launches and for every
+workgroup shape. Integer work: exact comparison."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1209_2137_amd as wp
+from paper_1209_2137_amd import datagen
+from paper_1209_2137_amd.pool import ListPool
+
+pytestmark = pytest.mark.gpu
+
+TUNES = [
+    dict(waves=4, vpl=4, depth=4, run_units=8, wg_per_cu=4, use_graph=1),
+    dict(waves=4, vpl=4, depth=4, run_units=8, wg_per_cu=4, use_graph=0),
+    dict(waves=2, vpl=8, depth=2, run_units=1, wg_per_cu=8, use_graph=1),
+    dict(waves=2, vpl=4, depth=4, run_units=63, wg_per_cu=16, use_graph=1),
+    dict(waves=4, vpl=8, depth=2, run_units=5, wg_per_cu=2, use_graph=0),
+    dict(waves=8, vpl=4, depth=2, run_units=16, wg_per_cu=2, use_graph=1),
+]
+
+
+@pytest.fixture(scope="module")
+def pool():
+    assert torch.cuda.is_available()
+    # posting-list shapes: Zipf lengths (scaled to 400 lists), 50/50 codecs,
+    # geometric gaps of log-uniform mean
+    lens, codec, means, list_array = datagen.posting_lists(n_lists=400, total=4e6, seed=15, lmax=1 << 18)
+    return ListPool(list_array, codec, stride=1, count=400)
+
+
+def test_pool_streams_match_oracle_encoder(pool):
+    # the pool's GPU-encoded streams are the oracle's streams, word for word
+    p = pool.pool.cpu().numpy().view(np.uint32)
+    v = pool.values.cpu().numpy().view(np.uint32)
+    for i in range(0, 400, 37):
+        co, cw, oo, n, codec = pool.rows[i]
+        x = v[oo:oo + n]
+        want = (oracle.bp_encode if codec == wp.CODEC_BP else oracle.fp_encode)(x, 1)
+        assert np.array_equal(p[co:co + cw], want), i
+
+
+@pytest.mark.parametrize("tune", TUNES, ids=lambda t: "w{waves}v{vpl}d{depth}r{run_units}c{wg_per_cu}g{use_graph}".format(**t))
+def test_batch_decode_matches_inputs(pool, tune):
+    out = torch.full((pool.total_out + 64,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
+    plan = pool.plan(out, tune=tune)
+    assert plan.items > 0
+    for rep in range(3):  # graph replays with eager work in between
+        out[: pool.total_out].fill_(-1)
+        plan.decode()
+        assert wp.check_code() == wp.OK
+        for i in range(len(pool.rows)):
+            co, cw, oo, n, codec = pool.rows[i]
+            if not torch.equal(out[oo:oo + n], pool.values[oo:oo + n]):
+                raise AssertionError(f"list {i} (codec {codec}, n {n}) differs on replay {rep}")
+        assert (out[pool.total_out:] == 0x5A5A5A5A).all()
+    plan.free()
+
+
+def test_batch_equals_single_list_decodes(pool):
+    a = torch.zeros(pool.total_out + 4, dtype=torch.int32, device="cuda")
+    b = torch.zeros_like(a)
+    plan = pool.plan(a)
+    plan.decode()
+    for i in range(len(pool.rows)):
+        pool.decode_one(i, b)
+    assert wp.check_code() == wp.OK
+    assert torch.equal(a, b)
+    plan.free()
+
+
+def test_batch_flags_a_corrupt_list_and_decodes_the_rest(pool):
+    rows = list(pool.rows)
+    bad = 3
+    co, cw, oo, n, codec = rows[bad]
+    saved = pool.pool[co].clone()
+    pool.pool[co] = 0x12345678  # bad magic
+    out = torch.zeros(pool.total_out + 4, dtype=torch.int32, device="cuda")
+    plan = pool.plan(out)
+    plan.decode()
+    rc = wp.check_code()
+    pool.pool[co] = saved
+    assert rc == wp.ERR_CORRUPT
+    for i in range(len(rows)):
+        if i == bad:
+            continue
+        _, _, oo2, n2, _ = rows[i]
+        assert torch.equal(out[oo2:oo2 + n2], pool.values[oo2:oo2 + n2]), i
+    plan.free()
+
+
+def test_batch_plan_rejects_bad_registry(pool):
+    out = torch.zeros(16, dtype=torch.int32, device="cuda")
+    with pytest.raises(wp.WavepackError):
+        wp.BatchPlan(pool.pool, out, [(1, 100, 0, 10, 0)])  # misaligned stream offset
+    with pytest.raises(wp.WavepackError):
+        wp.BatchPlan(pool.pool, out, [(0, 100, 0, 10, 7)])  # unknown codec
+    with pytest.raises(wp.WavepackError):
+        wp.BatchPlan(pool.pool, out, pool.rows[:2], tune=dict(waves=3))

@@ -17,8 +17,8 @@ pytestmark = pytest.mark.gpu
 
 CANARY = 0x5A5A5A5A
 PAD = 64
-BP_TUNES = [(8, 4), (4, 4), (4, 8), (2, 8)]
-FP_TUNES = [(8, 4), (4, 4), (4, 8), (8, 8)]
+BP_TUNES = [(8, 4, 16, 2), (4, 4, 1, 4), (4, 8, 7, 2), (2, 8, 16, 4), (2, 4, 64, 2)]
+FP_TUNES = [(8, 4, 0, 0), (4, 4, 0, 0), (4, 8, 0, 0), (8, 8, 0, 0)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -26,8 +26,8 @@ def gpu():
     assert torch.cuda.is_available(), "the GPU tests need a GPU"
     wp.lib()
     yield
-    wp.set_decode_tune(wp.CODEC_BP, 8, 4)
-    wp.set_decode_tune(wp.CODEC_FP, 8, 4)
+    wp.set_decode_tune(wp.CODEC_BP, 4, 4, 8, 4)
+    wp.set_decode_tune(wp.CODEC_FP, 4, 4, 0)
 
 
 def to_dev(a):
@@ -81,13 +81,13 @@ def test_lengths_strides_tunes(codec, tunes, stride):
         else:
             x = datagen.patched_gaps(n, seed=n) if n else np.zeros(0, np.uint32)
         cases.append((n, x, encode(codec, x, stride)))
-    for waves, vpl in tunes:
-        wp.set_decode_tune(codec, waves, vpl)
+    for waves, vpl, wpc, depth in tunes:
+        wp.set_decode_tune(codec, waves, vpl, wpc, depth)
         for n, x, s in cases:
-            print(f"codec={codec} stride={stride} tune=({waves},{vpl}) n={n}", flush=True)
+            print(f"codec={codec} stride={stride} tune=({waves},{vpl},{wpc},{depth}) n={n}", flush=True)
             rc, got = gpu_decode(codec, s, n)
             assert rc == wp.OK
-            assert_same(got, x, f"n={n} tune=({waves},{vpl})")
+            assert_same(got, x, f"n={n} tune=({waves},{vpl},{wpc},{depth})")
 
 
 @pytest.mark.parametrize("codec", [wp.CODEC_BP, wp.CODEC_FP])
@@ -102,8 +102,8 @@ def test_every_block_width(codec):
         blocks.append(v)
     x = np.concatenate(blocks + [np.array([7, 1 << 31, 5], dtype=np.uint32)])
     tunes = BP_TUNES if codec == wp.CODEC_BP else FP_TUNES
-    for waves, vpl in tunes:
-        wp.set_decode_tune(codec, waves, vpl)
+    for waves, vpl, wpc, depth in tunes:
+        wp.set_decode_tune(codec, waves, vpl, wpc, depth)
         rc, got = gpu_decode(codec, encode(codec, x, 0), x.size)
         assert rc == wp.OK
         assert_same(got, x)
@@ -125,7 +125,7 @@ def test_full_size_binary_packing_lists():
         s = oracle.bp_encode(x, 1)
         comp = to_dev(s)
         out = torch.empty(x.size, dtype=torch.int32, device="cuda")
-        wp.set_decode_tune(wp.CODEC_BP, 8, 4)
+        wp.set_decode_tune(wp.CODEC_BP, 4, 4, 8, 4)
         wp.bp_decode(comp, x.size, out)
         assert wp.check_code() == wp.OK
         assert torch.equal(out, to_dev(x))
@@ -139,7 +139,7 @@ def test_full_size_patched_list():
     xd = to_dev(x)
     del x
     out = torch.empty(xd.numel(), dtype=torch.int32, device="cuda")
-    wp.set_decode_tune(wp.CODEC_FP, 8, 4)
+    wp.set_decode_tune(wp.CODEC_FP, 4, 4, 0)
     wp.fastpfor_decode(comp, xd.numel(), out)
     assert wp.check_code() == wp.OK
     assert torch.equal(out, xd)

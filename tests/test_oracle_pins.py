@@ -252,11 +252,9 @@ def test_fastpfor_choice_is_the_minimum():
 
 def _bp_widths(stream):
     n_units = int(stream[4])
-    stride = int(stream[3])
-    E = 1 + stride
     widths = []
     for u in range(n_units):
-        off = int(stream[8 + u * E])
+        off = int(stream[8 + u])  # the directory's offsets come first
         desc = stream[off:off + 4].view(np.uint8)
         widths.append([int(b) for b in desc])
     return widths
