@@ -139,6 +139,81 @@ def bench_copy(n_bytes, steps, warmup):
     return {"bytes": 2 * n_bytes, "kernel_ms": ev, "gbs": 2 * n_bytes / (ev * 1e-3) / 1e9}
 
 
+def bench_batch(wp, steps, warmup, n_lists=100_000, total=1.2e9, per_list_passes=2):
+    """Posting-list pool: one batched persistent decode (hipGraph) vs one
+    single-list launch per list on the same stream."""
+    import torch
+    from paper_1209_2137_amd import datagen
+    from paper_1209_2137_amd.autotune import batch_tune
+    from paper_1209_2137_amd.pool import ListPool
+    t0 = time.perf_counter()
+    lens, codec, means, list_array = datagen.posting_lists(n_lists=n_lists, total=total, seed=5)
+    pool = ListPool(list_array, codec, stride=1, count=n_lists, keep_values=True)
+    t_setup = time.perf_counter() - t0
+    out = torch.zeros(pool.total_out + 4, dtype=torch.int32, device="cuda")
+    tune = batch_tune() or dict(waves=4, vpl=4, depth=4, run_units=8, wg_per_cu=4, use_graph=1)
+    tune = dict(tune, use_graph=1)
+    plan = pool.plan(out, tune=tune)
+    plan.decode()
+    wp.check()
+    if not torch.equal(out[:pool.total_out], pool.values[:pool.total_out]):
+        raise RuntimeError("batched decode differs from the inputs")
+    stream = torch.cuda.current_stream()
+    wall_b, ev_b = time_launches(lambda i: plan.decode(), steps, warmup, stream)
+    out.zero_()
+    n = len(pool.rows)
+
+    def per_list(_i):
+        for j in range(n):
+            pool.decode_one(j, out)
+
+    wall_p, ev_p = time_launches(per_list, per_list_passes, 1, stream)
+    wp.check()
+    if not torch.equal(out[:pool.total_out], pool.values[:pool.total_out]):
+        raise RuntimeError("per-list decode differs from the inputs")
+    alg = pool.comp_bytes + 4 * pool.total_n
+    res = {
+        "name": "batched posting lists", "lists": n, "n": pool.total_n, "items": plan.items,
+        "bits_per_int": pool.comp_bytes * 8 / pool.total_n, "tune": tune,
+        "batched_ms": wall_b, "batched_kernel_ms": ev_b, "batched_gints_per_s": pool.total_n / (wall_b * 1e-3) / 1e9,
+        "batched_achieved_gbs": alg / (ev_b * 1e-3) / 1e9, "batched_hbm_frac": alg / (ev_b * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "per_list_ms": wall_p, "per_list_gpu_ms": ev_p, "per_list_gints_per_s": pool.total_n / (wall_p * 1e-3) / 1e9,
+        "speedup_batched_vs_per_list": wall_p / wall_b, "setup_s": t_setup,
+    }
+    plan.free()
+    del out
+    return res, pool
+
+
+def bench_serve(wp, pool, seconds=10.0, rate=2000.0, budget_bytes=64 << 30):
+    """Poisson arrivals of requests for 1..32 lists of the resident pool,
+    continuous batching under an HBM output budget."""
+    import torch
+    from paper_1209_2137_amd import datagen
+    from paper_1209_2137_amd.serve import Server, summarize
+    times, reqs = datagen.poisson_arrivals(rate=rate, duration=seconds, pool=len(pool.rows), seed=6)
+    arena = min(budget_bytes // 4, 1 << 30)
+    srv = Server(pool, arena_elems=arena, budget_bytes=budget_bytes, streams=4)
+    bad = []
+
+    def check(r, a):
+        if r.rid % 64 == 0:
+            for li, o in zip(r.lists, r.offsets):
+                _, _, oo, n, _ = pool.rows[li]
+                if not torch.equal(a[r.out_off + o:r.out_off + o + n], pool.values[oo:oo + n]):
+                    bad.append(r.rid)
+
+    done = srv.run(times, reqs, check=check)
+    srv.close()
+    wp.check()
+    if bad:
+        raise RuntimeError(f"served outputs differ for requests {bad[:5]}")
+    st = summarize(done, srv.wall)
+    st.update({"rate_req_s": rate, "seconds": seconds, "budget_bytes": budget_bytes,
+               "arena_bytes": 4 * arena, "streams": 4})
+    return st
+
+
 def cpu_baseline(x_np, min_seconds=10.0):
     """The CPU oracle (plain scalar C, one thread) decoding the same list."""
     import oracle
@@ -193,6 +268,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched and serving legs")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the serving run (the full workload is 60 s)")
     ap.add_argument("--rocprof-summary", metavar="DIR")
     args = ap.parse_args()
     if args.rocprof_summary:
@@ -230,6 +308,13 @@ def main():
         extra["delta_inplace_2e28"] = bench_delta(wp, 1 << 28, args.steps, args.warmup)
         print("# delta done", file=sys.stderr, flush=True)
         head["pct_of_copy"] = head["achieved_gbs"] / copy["gbs"]
+        if not args.no_batch:
+            extra["batched_posting_lists"], pool = bench_batch(wp, max(3, args.steps // 2), 2)
+            print("# batched done", file=sys.stderr, flush=True)
+            if args.serve_seconds > 0:
+                extra["serving"] = bench_serve(wp, pool, seconds=args.serve_seconds)
+                print("# serving done", file=sys.stderr, flush=True)
+            del pool
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(x)
@@ -253,7 +338,7 @@ def main():
                         "[0,2^30) (depth 20, leaves <= 64), binary packing 16x128 per meta-block, stride-1 "
                         "differential decode",
             "n": head["n"], "bits_per_int": round(head["bits_per_int"], 4),
-            "decode_tune": list(wp_tune_of(wp, wp.CODEC_BP)),
+            "decode_tune": wp_tune_of(),
             "input_replicas": head["replicas"],
         },
         "roofline": {
@@ -268,8 +353,9 @@ def main():
     return 0
 
 
-def wp_tune_of(wp, codec):
-    return (8, 4)
+def wp_tune_of():
+    from paper_1209_2137_amd.autotune import arch, load
+    return load().get(arch(), {}).get("bp_single")
 
 
 if __name__ == "__main__":

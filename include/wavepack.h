@@ -180,6 +180,17 @@ int32_t wp_batch_plan(const uint32_t *pool, uint32_t *out_base, const wp_list *h
  * not overlap (they share the counter). Allocates nothing. */
 int32_t wp_batch_decode(void *h_plan, void *stream);
 
+/* Re-targets an existing plan at a new registry (same meaning as in
+ * wp_batch_plan) for callers that plan many small batches, such as a
+ * serving loop: the list and item arrays are staged in plan-owned pinned
+ * host memory and copied on `stream` without synchronising it, reusing the
+ * plan's device arrays (they only grow, with a synchronisation, when the
+ * new registry is larger than any before). The plan then uses plain
+ * launches (a graph would hold the old item count). The caller enqueues
+ * the previous decode of this plan on the same stream or has waited for it. */
+int32_t wp_batch_replan(void *h_plan, const uint32_t *pool, uint32_t *out_base, const wp_list *h_lists,
+                        uint64_t nlists, void *stream);
+
 /* Number of work items in a plan (host). */
 uint64_t wp_batch_items(const void *h_plan);
 

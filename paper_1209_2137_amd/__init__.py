@@ -25,7 +25,7 @@ CODEC_FP = 1
 EXPORTS = (
     "bp_encode", "bp_decode", "fastpfor_encode", "fastpfor_decode", "delta_decode_inplace",
     "wp_max_compressed_words", "wp_check", "wp_strerror", "wp_set_decode_tune",
-    "wp_batch_plan", "wp_batch_decode", "wp_batch_items", "wp_batch_free",
+    "wp_batch_plan", "wp_batch_replan", "wp_batch_decode", "wp_batch_items", "wp_batch_free",
 )
 
 _lib = None
@@ -80,6 +80,8 @@ def lib():
     L.wp_batch_plan.argtypes = [vp, vp, ctypes.POINTER(wp_list), u64, ctypes.POINTER(wp_tune),
                                 ctypes.POINTER(vp), vp]
     L.wp_batch_plan.restype = i32
+    L.wp_batch_replan.argtypes = [vp, vp, vp, ctypes.POINTER(wp_list), u64, vp]
+    L.wp_batch_replan.restype = i32
     L.wp_batch_decode.argtypes = [vp, vp]
     L.wp_batch_decode.restype = i32
     L.wp_batch_items.argtypes = [vp]
@@ -87,6 +89,12 @@ def lib():
     L.wp_batch_free.argtypes = [vp]
     L.wp_batch_free.restype = i32
     _lib = L
+    # workgroup shapes chosen by the autotuner for this architecture, if any
+    try:
+        from .autotune import apply
+        apply()
+    except Exception:  # a missing or stale table leaves the built-in shapes
+        pass
     return L
 
 
@@ -232,6 +240,17 @@ class BatchPlan:
         self.pool, self.out = pool, out  # keep the buffers alive
         _check(lib().wp_batch_plan(_ptr(pool), _ptr(out), arr, n, ctypes.byref(t) if t is not None else None,
                                    ctypes.byref(self._h), _stream(stream)), "wp_batch_plan")
+
+    def replan(self, pool, out, lists, stream=None):
+        """Points the plan at a new registry without allocating (async copy)."""
+        _need_u32(pool, "pool")
+        _need_u32(out, "out")
+        n = len(lists)
+        arr = (wp_list * max(n, 1))()
+        for i, (co, cw, oo, nn, codec) in enumerate(lists):
+            arr[i] = wp_list(int(co), int(cw), int(oo), int(nn), int(codec), 0)
+        self.pool, self.out = pool, out
+        _check(lib().wp_batch_replan(self._h, _ptr(pool), _ptr(out), arr, n, _stream(stream)), "wp_batch_replan")
 
     @property
     def items(self) -> int:

@@ -106,6 +106,14 @@ struct Plan {
     hipGraphExec_t exec = nullptr;
     const void *kernel = nullptr;
     int *err = nullptr;
+    // re-planning without allocation: capacities and pinned staging
+    uint64_t cap_lists = 0, cap_items = 0;
+    DevList *h_lists_pin = nullptr;
+    uint4 *h_items_pin = nullptr;
+    uint64_t pin_lists = 0, pin_items = 0;
+    hipEvent_t copied = nullptr;
+    int run_units = 8, wpc = 4;
+    int cus = 256;
 };
 
 template <int W, int V, int D>
@@ -132,6 +140,12 @@ static const void *pick_kernel(int waves, int vpl, int depth)
 
 static void release(Plan *p)
 {
+    if (p->copied)
+        (void)hipEventSynchronize(p->copied), (void)hipEventDestroy(p->copied);
+    if (p->h_lists_pin)
+        (void)hipHostFree(p->h_lists_pin);
+    if (p->h_items_pin)
+        (void)hipHostFree(p->h_items_pin);
     if (p->exec)
         (void)hipGraphExecDestroy(p->exec);
     if (p->graph)
@@ -188,6 +202,53 @@ static int32_t build_graph(Plan *p)
     return WP_OK;
 }
 
+// Validates a registry and cuts it into work items: binary-packing runs of
+// run_units meta-blocks, single pages, tails; largest first.
+static bool build_items(const uint32_t *pool, uint32_t *out_base, const wp_list *h_lists, uint64_t nlists,
+                        int run_units, std::vector<DevList> &lists, std::vector<uint4> &items)
+{
+    lists.assign(nlists, DevList{});
+    std::vector<uint4> fp_items, bp_items, tail_items;
+    for (uint64_t i = 0; i < nlists; ++i) {
+        const wp_list &l = h_lists[i];
+        if ((l.codec != WP_CODEC_BP && l.codec != WP_CODEC_FP) || l.reserved != 0 || (l.comp_off_words & 3u) ||
+            (l.out_off & 3u) || l.comp_words < kHdrWords || l.n > 0xFFFFFFFFull * 32ull)
+            return false;
+        lists[i].comp = pool + l.comp_off_words;
+        lists[i].out = out_base + l.out_off;
+        lists[i].comp_words = l.comp_words;
+        lists[i].n = l.n;
+        lists[i].codec = (uint32_t)l.codec;
+        lists[i].pad = 0;
+        const uint64_t nfull = l.n / kBlock;
+        const uint32_t li = (uint32_t)i;
+        if (l.codec == WP_CODEC_BP) {
+            const uint64_t units = (nfull + kBpBlocks - 1) / kBpBlocks;
+            for (uint64_t u = 0; u < units; u += (uint64_t)run_units) {
+                const uint64_t c = std::min<uint64_t>((uint64_t)run_units, units - u);
+                bp_items.push_back(make_uint4(li, kItemBpRun, (uint32_t)u, (uint32_t)c));
+            }
+        } else {
+            const uint64_t units = (nfull + kFpBlocks - 1) / kFpBlocks;
+            for (uint64_t u = 0; u < units; ++u)
+                fp_items.push_back(make_uint4(li, kItemFpPage, (uint32_t)u, 1));
+        }
+        if (l.n % kBlock)
+            tail_items.push_back(make_uint4(li, kItemTail, 0, 0));
+    }
+    if (nlists > 0xFFFFFFFFull)
+        return WP_ERR_INVALID_ARG;
+    // largest items first: full pages, then runs (longest first), then tails
+    std::stable_sort(bp_items.begin(), bp_items.end(), [](const uint4 &a, const uint4 &b) { return a.w > b.w; });
+    items.reserve(fp_items.size() + bp_items.size() + tail_items.size());
+    items.insert(items.end(), fp_items.begin(), fp_items.end());
+    items.insert(items.end(), bp_items.begin(), bp_items.end());
+    items.insert(items.end(), tail_items.begin(), tail_items.end());
+    if (items.size() > 0xFFFFFFF0ull)
+        return WP_ERR_INVALID_ARG;
+    return true;
+}
+
 }  // namespace wp
 
 using namespace wp;
@@ -218,46 +279,9 @@ extern "C" int32_t wp_batch_plan(const uint32_t *pool, uint32_t *out_base, const
     DevState *ds = dev_state();
     if (ds == nullptr)
         return WP_ERR_HIP;
-    // host-side registry checks and items
-    std::vector<DevList> lists(nlists);
-    std::vector<uint4> fp_items, bp_items, tail_items;
-    for (uint64_t i = 0; i < nlists; ++i) {
-        const wp_list &l = h_lists[i];
-        if ((l.codec != WP_CODEC_BP && l.codec != WP_CODEC_FP) || l.reserved != 0 || (l.comp_off_words & 3u) ||
-            (l.out_off & 3u) || l.comp_words < kHdrWords || l.n > 0xFFFFFFFFull * 32ull)
-            return WP_ERR_INVALID_ARG;
-        lists[i].comp = pool + l.comp_off_words;
-        lists[i].out = out_base + l.out_off;
-        lists[i].comp_words = l.comp_words;
-        lists[i].n = l.n;
-        lists[i].codec = (uint32_t)l.codec;
-        lists[i].pad = 0;
-        const uint64_t nfull = l.n / kBlock;
-        const uint32_t li = (uint32_t)i;
-        if (l.codec == WP_CODEC_BP) {
-            const uint64_t units = (nfull + kBpBlocks - 1) / kBpBlocks;
-            for (uint64_t u = 0; u < units; u += (uint64_t)t.run_units) {
-                const uint64_t c = std::min<uint64_t>((uint64_t)t.run_units, units - u);
-                bp_items.push_back(make_uint4(li, kItemBpRun, (uint32_t)u, (uint32_t)c));
-            }
-        } else {
-            const uint64_t units = (nfull + kFpBlocks - 1) / kFpBlocks;
-            for (uint64_t u = 0; u < units; ++u)
-                fp_items.push_back(make_uint4(li, kItemFpPage, (uint32_t)u, 1));
-        }
-        if (l.n % kBlock)
-            tail_items.push_back(make_uint4(li, kItemTail, 0, 0));
-    }
-    if (nlists > 0xFFFFFFFFull)
-        return WP_ERR_INVALID_ARG;
-    // largest items first: full pages, then runs (longest first), then tails
-    std::stable_sort(bp_items.begin(), bp_items.end(), [](const uint4 &a, const uint4 &b) { return a.w > b.w; });
+    std::vector<DevList> lists;
     std::vector<uint4> items;
-    items.reserve(fp_items.size() + bp_items.size() + tail_items.size());
-    items.insert(items.end(), fp_items.begin(), fp_items.end());
-    items.insert(items.end(), bp_items.begin(), bp_items.end());
-    items.insert(items.end(), tail_items.begin(), tail_items.end());
-    if (items.size() > 0xFFFFFFF0ull)
+    if (!build_items(pool, out_base, h_lists, nlists, t.run_units, lists, items))
         return WP_ERR_INVALID_ARG;
     Plan *p = new Plan();
     p->device = ds->device;
@@ -269,7 +293,12 @@ extern "C" int32_t wp_batch_plan(const uint32_t *pool, uint32_t *out_base, const
     p->depth = t.depth;
     p->kernel = kern;
     p->use_graph = t.use_graph != 0;
+    p->run_units = t.run_units;
+    p->cus = ds->cus;
     const uint64_t wpc = t.wg_per_cu > 0 ? (uint64_t)t.wg_per_cu : (t.waves == 2 ? 8 : 4);
+    p->wpc = (int)wpc;
+    p->cap_lists = std::max<uint64_t>(1, lists.size());
+    p->cap_items = std::max<uint64_t>(1, items.size());
     uint64_t grid = (uint64_t)ds->cus * wpc;
     grid = std::max<uint64_t>(1, std::min<uint64_t>(grid, p->nitems ? p->nitems : 1));
     p->grid = (uint32_t)grid;
@@ -330,5 +359,87 @@ extern "C" int32_t wp_batch_free(void *h_plan)
         return WP_ERR_HIP;
     }
     release(p);
+    return WP_OK;
+}
+
+extern "C" int32_t wp_batch_replan(void *h_plan, const uint32_t *pool, uint32_t *out_base, const wp_list *h_lists,
+                                   uint64_t nlists, void *stream)
+{
+    Plan *p = static_cast<Plan *>(h_plan);
+    if (p == nullptr || (nlists > 0 && (pool == nullptr || out_base == nullptr || h_lists == nullptr)) ||
+        !aligned16(pool) || !aligned16(out_base))
+        return WP_ERR_INVALID_ARG;
+    int d = -1;
+    if (hipGetDevice(&d) != hipSuccess || d != p->device)
+        return WP_ERR_INVALID_ARG;
+    std::vector<DevList> lists;
+    std::vector<uint4> items;
+    if (!build_items(pool, out_base, h_lists, nlists, p->run_units, lists, items) || items.size() > 0xFFFFFFF0ull)
+        return WP_ERR_INVALID_ARG;
+    hipStream_t st = as_stream(stream);
+    // the previous copy out of the pinned staging must have finished
+    if (p->copied && hipEventSynchronize(p->copied) != hipSuccess)
+        return WP_ERR_HIP;
+    if (lists.size() > p->cap_lists || items.size() > p->cap_items) {
+        // grow: earlier launches of this plan may still read the old arrays
+        if (hipStreamSynchronize(st) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+            return WP_ERR_HIP;
+        if (lists.size() > p->cap_lists) {
+            (void)hipFree(p->d_lists);
+            p->d_lists = nullptr;
+            p->cap_lists = lists.size() + lists.size() / 2;
+            if (hipMalloc(&p->d_lists, p->cap_lists * sizeof(DevList)) != hipSuccess)
+                return WP_ERR_HIP;
+        }
+        if (items.size() > p->cap_items) {
+            (void)hipFree(p->d_items);
+            p->d_items = nullptr;
+            p->cap_items = items.size() + items.size() / 2;
+            if (hipMalloc(&p->d_items, p->cap_items * sizeof(uint4)) != hipSuccess)
+                return WP_ERR_HIP;
+        }
+    }
+    if (lists.size() > p->pin_lists) {
+        if (p->h_lists_pin)
+            (void)hipHostFree(p->h_lists_pin);
+        p->h_lists_pin = nullptr;
+        p->pin_lists = std::max<uint64_t>(lists.size() * 2, 64);
+        if (hipHostMalloc(&p->h_lists_pin, p->pin_lists * sizeof(DevList), 0) != hipSuccess) {
+            p->pin_lists = 0;
+            return WP_ERR_HIP;
+        }
+    }
+    if (items.size() > p->pin_items) {
+        if (p->h_items_pin)
+            (void)hipHostFree(p->h_items_pin);
+        p->h_items_pin = nullptr;
+        p->pin_items = std::max<uint64_t>(items.size() * 2, 256);
+        if (hipHostMalloc(&p->h_items_pin, p->pin_items * sizeof(uint4), 0) != hipSuccess) {
+            p->pin_items = 0;
+            return WP_ERR_HIP;
+        }
+    }
+    if (p->copied == nullptr && hipEventCreateWithFlags(&p->copied, hipEventDisableTiming) != hipSuccess)
+        return WP_ERR_HIP;
+    std::copy(lists.begin(), lists.end(), p->h_lists_pin);
+    std::copy(items.begin(), items.end(), p->h_items_pin);
+    (void)hipGetLastError();
+    if ((!lists.empty() && hipMemcpyAsync(p->d_lists, p->h_lists_pin, lists.size() * sizeof(DevList),
+                                          hipMemcpyHostToDevice, st) != hipSuccess) ||
+        (!items.empty() && hipMemcpyAsync(p->d_items, p->h_items_pin, items.size() * sizeof(uint4),
+                                          hipMemcpyHostToDevice, st) != hipSuccess) ||
+        hipEventRecord(p->copied, st) != hipSuccess)
+        return WP_ERR_HIP;
+    p->nlists = lists.size();
+    p->nitems = items.size();
+    uint64_t grid = (uint64_t)p->cus * (uint64_t)p->wpc;
+    grid = std::max<uint64_t>(1, std::min<uint64_t>(grid, p->nitems ? p->nitems : 1));
+    p->grid = (uint32_t)grid;
+    // the graph baked in the old item count and grid
+    if (p->exec)
+        (void)hipGraphExecDestroy(p->exec), p->exec = nullptr;
+    if (p->graph)
+        (void)hipGraphDestroy(p->graph), p->graph = nullptr;
+    p->use_graph = false;
     return WP_OK;
 }
