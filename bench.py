@@ -261,6 +261,21 @@ def rocprof_summary(d):
     print("\n".join(lines))
 
 
+def profile_run(steps):
+    import torch
+    import paper_1209_2137_amd as wp
+    from paper_1209_2137_amd import datagen
+    wp.lib()
+    x = datagen.cluster_sorted(1 << 26, seed=2)
+    r = bench_single(wp, x, wp.CODEC_BP, 1, steps, 2, "bp cluster 2^26")
+    c = bench_copy(1 << 30, steps, 0)
+    torch.cuda.synchronize()
+    print(json.dumps({"decode_kernel_ms": r["kernel_ms"], "decode_alg_bytes": r["alg_bytes"],
+                      "copy_bytes_each_way": 1 << 30, "copy_kernel_ms": c["kernel_ms"],
+                      "kernel_hash": kernel_hash()}))
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -272,10 +287,15 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the serving run (the full workload is 60 s)")
     ap.add_argument("--rocprof-summary", metavar="DIR")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="for rocprofv3: the headline decode `--steps` times, then a 1 GiB device copy "
+                         "(the counter calibration kernel) `--steps` times")
     args = ap.parse_args()
     if args.rocprof_summary:
         rocprof_summary(args.rocprof_summary)
         return 0
+    if args.profile_run:
+        return profile_run(args.steps)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (this build decodes on a "
               "single MI355X; lists and units shard across GPUs without any exchange, see the design notes)",
