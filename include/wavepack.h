@@ -119,13 +119,15 @@ int32_t delta_decode_inplace(uint32_t *data, uint64_t n, uint32_t init, int32_t 
                              void *stream);
 
 /* Workgroup shape of the single-list decoders (set by the autotuner;
- * process-wide). waves: wavefronts per workgroup; vpl: integers each lane
- * decodes per pass; depth (binary packing): 16-byte loads per thread in
- * flight while decoding (2 or 4; 0 = 4); wg_per_cu (binary packing): runs
- * of consecutive meta-blocks per compute unit (each workgroup streams one
- * run's compressed words through an LDS ring; 0 = 8). Valid shapes:
- * binary packing (2|4 waves, 4|8 vpl) or (8, 4); patched (4|8 waves, 4|8
- * vpl). Returns WP_ERR_INVALID_ARG for anything else. */
+ * process-wide). Binary packing: every wavefront decodes its own run of
+ * consecutive meta-blocks, streaming the run's compressed words through a
+ * private LDS ring; waves: wavefronts per workgroup (1, 2, 4 or 8); vpl
+ * must be 4 (each lane unpacks four integers of a block per pass); depth:
+ * 16-byte loads per lane in flight (2, 3 or 4; 0 = 2); wg_per_cu: runs
+ * per compute unit, 0..1024, which sets the run length (0 = 128; many
+ * short runs let the hardware balance the load). Patched pages:
+ * waves 4 or 8, vpl (integers per lane and pass) 4 or 8; depth and
+ * wg_per_cu are ignored. Returns WP_ERR_INVALID_ARG for anything else. */
 int32_t wp_set_decode_tune(int32_t codec, int32_t waves, int32_t vpl, int32_t depth, int32_t wg_per_cu);
 
 /* Synchronises `stream`, then returns and clears this device's error word:
@@ -138,8 +140,9 @@ const char *wp_strerror(int32_t code);
 /* ---------------------------------------------------------------------- */
 /* Batched decoding of many lists in one launch (not in the paper: the GPU
  * counterpart of decoding many posting lists). A plan turns a list
- * registry into work items -- one per unit (meta-block or page) and per
- * tail -- that a persistent kernel pulls from an atomic counter. */
+ * registry into work items -- patched pages, runs of meta-blocks and
+ * tails -- that a persistent kernel pulls from atomic counters: pages by
+ * whole workgroups first, then runs and tails by single wavefronts. */
 
 typedef struct wp_list {
     uint64_t comp_off_words; /* stream start, in words from `pool` (multiple of 4) */
@@ -152,10 +155,10 @@ typedef struct wp_list {
 
 typedef struct wp_tune {
     int32_t waves;     /* wavefronts per workgroup: 2, 4 or 8 (0 = 4) */
-    int32_t vpl;       /* integers per lane and pass: 4 or 8 (8 only with 2 or 4 waves; 0 = 4) */
-    int32_t depth;     /* binary packing: 16-byte loads in flight per thread, 2 or 4 (0 = 4; 8 waves: 2) */
-    int32_t run_units; /* meta-blocks per binary-packing work item, 1..63 (0 = 8) */
-    int32_t wg_per_cu; /* persistent workgroups per compute unit, 0..64 (0 = 8 with 2 waves, else 4) */
+    int32_t vpl;       /* patched pages: integers per lane and pass, 4 or 8 (8 only with 2 or 4 waves; 0 = 4) */
+    int32_t depth;     /* binary packing: 16-byte loads per lane in flight, 2, 3 or 4 (0 = 2) */
+    int32_t run_units; /* meta-blocks per binary-packing work item (one wavefront), 1..63 (0 = 8) */
+    int32_t wg_per_cu; /* persistent workgroups per compute unit, 0..64 (0 = 28 / waves) */
     int32_t use_graph; /* 1 = replay a hipGraph built at plan time, 0 = plain launches */
 } wp_tune;
 

@@ -1,11 +1,12 @@
 """Autotuner for the decoders' workgroup shapes.
 
 Knobs:
-  waves      wavefronts per workgroup (2, 4, 8)
-  vpl        integers per lane and pass; blocks per wavefront = vpl / 2
-  depth      binary packing: 16-byte loads in flight per thread, which also
-             sizes the LDS ring (the LDS tile: depth chunks + one meta-block)
-  wg_per_cu  workgroups (runs of meta-blocks) per compute unit
+  waves      wavefronts per workgroup (binary packing 1, 2, 4, 8; patched 4, 8)
+  vpl        patched pages: integers per lane and pass (binary packing: 4)
+  depth      binary packing: 16-byte loads in flight per lane, which also
+             sizes each wavefront's LDS ring (2 or 3: 4 KB, 4: 8 KB)
+  wg_per_cu  single list, binary packing: runs (one per wavefront) per
+             compute unit; batched: persistent workgroups per compute unit
   run_units  batched decoding: meta-blocks per work item
 
 Each candidate is timed with HIP events (median of `steps` launches after
@@ -22,13 +23,13 @@ import time
 
 TUNING_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 
-BP_SINGLE = [dict(waves=w, vpl=v, depth=d, wg_per_cu=c)
-             for (w, v) in ((2, 4), (2, 8), (4, 4), (4, 8)) for d in (2, 4) for c in (4, 8, 16)] + \
-            [dict(waves=8, vpl=4, depth=2, wg_per_cu=c) for c in (2, 4)]
+BP_SINGLE = [dict(waves=w, vpl=4, depth=d, wg_per_cu=c)
+             for w in (1, 2, 4, 8) for d in (2, 3) for c in (28, 56, 128, 256)] + \
+            [dict(waves=w, vpl=4, depth=4, wg_per_cu=c) for w in (1, 4) for c in (64, 128)]
 FP_SINGLE = [dict(waves=w, vpl=v) for (w, v) in ((4, 4), (4, 8), (8, 4), (8, 8))]
 BATCH = [dict(waves=w, vpl=v, depth=d, run_units=r, wg_per_cu=c, use_graph=1)
-         for (w, v, d) in ((2, 4, 2), (2, 8, 2), (4, 4, 4), (4, 4, 2), (4, 8, 4))
-         for r in (4, 8, 16) for c in (4, 8)]
+         for (w, v) in ((2, 8), (4, 4), (4, 8), (8, 4)) for d in (2, 3)
+         for r in (2, 4, 8) for c in (0, 28 // w + 2)]
 
 
 def load(path: str = TUNING_PATH) -> dict:

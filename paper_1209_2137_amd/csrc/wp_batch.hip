@@ -1,12 +1,14 @@
 // Batched decoding of many lists in one launch.
 //
-// The host planner cuts every list into work items: runs of up to
-// `run_units` meta-blocks (binary packing), single pages (patched) and the
-// Variable Byte tails; large items first. A persistent grid of workgroups
-// pulls item indices from one atomic counter until none are left, and runs
-// the same device decoders as the single-list entry points (binary-packing
-// runs through the LDS ring, patched pages, tails). Items are independent
-// because every unit's base is stored in its list's directory.
+// The host planner cuts every list into work items: single pages
+// (patched), runs of up to `run_units` meta-blocks (binary packing) and
+// the Variable Byte tails; pages first, then runs longest first, then
+// tails. A persistent grid works through them in two phases: whole
+// workgroups take pages from a first atomic counter (a page needs the
+// workgroup's barriers); once pages run out, every wavefront takes runs
+// and tails by itself from a second counter, with no barrier at all.
+// Items are independent because every unit's base is stored in its list's
+// directory.
 //
 // A plan owns its device item array and, when asked, a hipGraph of two
 // kernel nodes: a one-thread counter reset, then the persistent decoder
@@ -31,65 +33,108 @@ struct DevList {
     uint32_t pad;
 };
 
+template <int DEPTH>
+union WaveItemLds {
+    WaveLds<DEPTH> r;
+    TailLds<1> tail;
+};
+
 // item: {list index, kind, first unit, unit count}
 template <int WAVES, int VPL, int DEPTH>
 union BatchLds {
-    RingLds<WAVES, VPL, DEPTH> r;
+    WaveItemLds<DEPTH> w[WAVES];
     FpLds<WAVES, VPL> fp;
-    TailLds<WAVES> tail;
 };
 
-__global__ void k_batch_reset(uint32_t *counter) { *counter = 0; }
+__global__ void k_batch_reset(uint32_t *counter)
+{
+    counter[0] = 0;
+    counter[1] = 0;
+}
+
+// Header check of item `it`'s list; uniform.
+__device__ __forceinline__ bool item_header(const DevList *__restrict__ lists, const uint4 *__restrict__ items,
+                                            uint32_t it, uint4 &item, DevList &Ld, ListHdr &H)
+{
+    const uint4 t = items[it];
+    item = make_uint4(uniform(t.x), uniform(t.y), uniform(t.z), uniform(t.w));
+    Ld = lists[item.x];
+    Ld.codec = uniform(Ld.codec);
+    return check_header(Ld.comp, Ld.comp_words, Ld.n, Ld.codec == WP_CODEC_BP ? kMagicBP : kMagicFP,
+                        Ld.codec == WP_CODEC_BP ? kBpBlocks : kFpBlocks, H);
+}
 
 template <int WAVES, int VPL, int DEPTH>
 __global__ __launch_bounds__(64 * WAVES) void k_batch(const DevList *__restrict__ lists,
-                                                      const uint4 *__restrict__ items, uint32_t nitems,
-                                                      uint32_t *__restrict__ counter, int *__restrict__ err)
+                                                      const uint4 *__restrict__ items, uint32_t npages,
+                                                      uint32_t nitems, uint32_t *__restrict__ counter,
+                                                      int *__restrict__ err)
 {
     __shared__ BatchLds<WAVES, VPL, DEPTH> L;
     __shared__ uint32_t s_item;
     const uint32_t tid = threadIdx.x;
-    for (;;) {
+    const uint32_t lane = lane_id();
+    // phase 1: pages, one workgroup each
+    while (npages > 0) {
         if (tid == 0)
-            s_item = atomicAdd(counter, 1u);
+            s_item = atomicAdd(&counter[0], 1u);
         __syncthreads();
         const uint32_t it = uniform(s_item);
         __syncthreads();
-        if (it >= nitems)
+        if (it >= npages)
             break;
-        const uint4 item = items[it];
-        const uint32_t li = uniform(item.x), kind = uniform(item.y), first = uniform(item.z),
-                       count = uniform(item.w);
-        const DevList Ld = lists[li];
-        const uint32_t codec = uniform(Ld.codec);
+        uint4 item;
+        DevList Ld;
         ListHdr H;
-        bool ok = check_header(Ld.comp, Ld.comp_words, Ld.n, codec == WP_CODEC_BP ? kMagicBP : kMagicFP,
-                               codec == WP_CODEC_BP ? kBpBlocks : kFpBlocks, H);
+        bool ok = item_header(lists, items, it, item, Ld, H) && item.y == kItemFpPage &&
+                  Ld.codec == WP_CODEC_FP && item.z < H.units;
         if (ok) {
-            if (kind == kItemBpRun) {
-                ok = codec == WP_CODEC_BP && count >= 1 && count <= 63 && (uint64_t)first + count <= H.units &&
-                     bp_decode_run<WAVES, VPL, DEPTH>(Ld.comp, H, first, count, Ld.out, L.r);
-            } else if (kind == kItemFpPage) {
-                ok = codec == WP_CODEC_FP && first < H.units;
-                if (ok) {
-                    const uint64_t u = first;
-                    const uint32_t off = Ld.comp[kHdrWords + u];
-                    const uint32_t end = (u + 1 < H.units) ? Ld.comp[kHdrWords + u + 1] : H.tail_off;
-                    uint32_t base[4] = {0u, 0u, 0u, 0u};
-                    for (uint32_t s = 0; s < H.S; ++s)
-                        base[s] = Ld.comp[kHdrWords + H.ndir + u * H.S + s];
-                    const uint64_t left = H.nfull - u * kFpBlocks;
-                    const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
-                    ok = off >= H.dir_end && end >= off && end <= H.total && (off & 3u) == 0 &&
-                         fp_page<WAVES, VPL>(Ld.comp + off, end - off, nb, H.S, base, Ld.out + u * kFpUnitInts, L.fp);
-                }
-            } else {
-                ok = H.tail != 0 && decode_tail_entry<WAVES>(Ld.comp, H, Ld.out, L.tail);
-            }
+            const uint64_t u = item.z;
+            const uint32_t off = Ld.comp[kHdrWords + u];
+            const uint32_t end = (u + 1 < H.units) ? Ld.comp[kHdrWords + u + 1] : H.tail_off;
+            uint32_t base[4] = {0u, 0u, 0u, 0u};
+            for (uint32_t s = 0; s < H.S; ++s)
+                base[s] = Ld.comp[kHdrWords + H.ndir + u * H.S + s];
+            const uint64_t left = H.nfull - u * kFpBlocks;
+            const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
+            ok = off >= H.dir_end && end >= off && end <= H.total && (off & 3u) == 0 &&
+                 fp_page<WAVES, VPL>(Ld.comp + off, end - off, nb, H.S, base, Ld.out + u * kFpUnitInts, L.fp);
         }
         if (!ok && tid == 0)
             *err = kErrCorrupt;
         __syncthreads();
+    }
+    // phase 2: runs and tails, one wavefront each (each wavefront owns its
+    // LDS slice; the page phase's last barrier is behind every wavefront)
+    const uint32_t wave = uniform(tid >> 6);
+    WaveItemLds<DEPTH> &W = L.w[wave];
+    for (;;) {
+        uint32_t got = 0;
+        if (lane == 0)
+            got = atomicAdd(&counter[1], 1u);
+        const uint32_t it = npages + wave_read(got, 0);
+        if (it >= nitems)
+            break;
+        uint4 item;
+        DevList Ld;
+        ListHdr H;
+        bool ok = item_header(lists, items, it, item, Ld, H);
+        if (ok) {
+            if (item.y == kItemBpRun) {
+                const uint32_t first = item.z, count = item.w;
+                ok = Ld.codec == WP_CODEC_BP && count >= 1 && count <= 63 && (uint64_t)first + count <= H.units;
+                if (ok)
+                    ok = H.S == 1   ? bp_wave_run<DEPTH, 1>(Ld.comp, H, first, count, Ld.out, W.r)
+                         : H.S == 4 ? bp_wave_run<DEPTH, 4>(Ld.comp, H, first, count, Ld.out, W.r)
+                                    : bp_wave_run<DEPTH, 0>(Ld.comp, H, first, count, Ld.out, W.r);
+            } else {
+                ok = item.y == kItemTail && H.tail != 0 && decode_tail_entry<1, false>(Ld.comp, H, Ld.out, W.tail);
+            }
+        }
+        if (!ok && lane == 0)
+            *err = kErrCorrupt;
+        // the next item reuses this wavefront's LDS slice
+        wave_lds_order();
     }
 }
 
@@ -97,8 +142,8 @@ struct Plan {
     int device = -1;
     DevList *d_lists = nullptr;
     uint4 *d_items = nullptr;
-    uint32_t *d_counter = nullptr;
-    uint64_t nlists = 0, nitems = 0;
+    uint32_t *d_counter = nullptr;  // [pages taken, runs and tails taken]
+    uint64_t nlists = 0, nitems = 0, npages = 0;
     int waves = 4, vpl = 4, depth = 4;
     uint32_t grid = 1;
     bool use_graph = false;
@@ -122,19 +167,27 @@ static const void *batch_kernel()
     return reinterpret_cast<const void *>(&k_batch<W, V, D>);
 }
 
+template <int W, int V>
+static const void *batch_kernel_depth(int depth)
+{
+    return depth == 2 ? batch_kernel<W, V, 2>() : depth == 3 ? batch_kernel<W, V, 3>() : batch_kernel<W, V, 4>();
+}
+
+// waves x vpl shapes of the page decoder, each with ring depth 2..4
 static const void *pick_kernel(int waves, int vpl, int depth)
 {
-    const bool deep = depth >= 4;
+    if (depth < 2 || depth > 4)
+        return nullptr;
     if (waves == 2 && vpl == 4)
-        return deep ? batch_kernel<2, 4, 4>() : batch_kernel<2, 4, 2>();
+        return batch_kernel_depth<2, 4>(depth);
     if (waves == 2 && vpl == 8)
-        return deep ? batch_kernel<2, 8, 4>() : batch_kernel<2, 8, 2>();
+        return batch_kernel_depth<2, 8>(depth);
     if (waves == 4 && vpl == 4)
-        return deep ? batch_kernel<4, 4, 4>() : batch_kernel<4, 4, 2>();
+        return batch_kernel_depth<4, 4>(depth);
     if (waves == 4 && vpl == 8)
-        return deep ? batch_kernel<4, 8, 4>() : batch_kernel<4, 8, 2>();
+        return batch_kernel_depth<4, 8>(depth);
     if (waves == 8 && vpl == 4)
-        return batch_kernel<8, 4, 2>();
+        return batch_kernel_depth<8, 4>(depth);
     return nullptr;
 }
 
@@ -163,9 +216,8 @@ static int32_t launch_plan(Plan *p, hipStream_t st)
 {
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, st, p->d_counter);
-    void *args[] = {&p->d_lists, &p->d_items, &p->nitems, &p->d_counter, &p->err};
-    uint32_t nitems32 = (uint32_t)p->nitems;
-    args[2] = &nitems32;
+    uint32_t npages32 = (uint32_t)p->npages, nitems32 = (uint32_t)p->nitems;
+    void *args[] = {&p->d_lists, &p->d_items, &npages32, &nitems32, &p->d_counter, &p->err};
     if (hipLaunchKernel(p->kernel, dim3(p->grid), dim3(64 * p->waves), args, 0, st) != hipSuccess)
         return WP_ERR_HIP;
     return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
@@ -186,8 +238,8 @@ static int32_t build_graph(Plan *p)
     rp.extra = nullptr;
     if (hipGraphAddKernelNode(&reset, p->graph, nullptr, 0, &rp) != hipSuccess)
         return WP_ERR_HIP;
-    uint32_t nitems32 = (uint32_t)p->nitems;
-    void *args[] = {&p->d_lists, &p->d_items, &nitems32, &p->d_counter, &p->err};
+    uint32_t npages32 = (uint32_t)p->npages, nitems32 = (uint32_t)p->nitems;
+    void *args[] = {&p->d_lists, &p->d_items, &npages32, &nitems32, &p->d_counter, &p->err};
     hipKernelNodeParams kp = {};
     kp.func = const_cast<void *>(p->kernel);
     kp.gridDim = dim3(p->grid);
@@ -205,7 +257,7 @@ static int32_t build_graph(Plan *p)
 // Validates a registry and cuts it into work items: binary-packing runs of
 // run_units meta-blocks, single pages, tails; largest first.
 static bool build_items(const uint32_t *pool, uint32_t *out_base, const wp_list *h_lists, uint64_t nlists,
-                        int run_units, std::vector<DevList> &lists, std::vector<uint4> &items)
+                        int run_units, std::vector<DevList> &lists, std::vector<uint4> &items, uint64_t &npages)
 {
     lists.assign(nlists, DevList{});
     std::vector<uint4> fp_items, bp_items, tail_items;
@@ -237,15 +289,16 @@ static bool build_items(const uint32_t *pool, uint32_t *out_base, const wp_list 
             tail_items.push_back(make_uint4(li, kItemTail, 0, 0));
     }
     if (nlists > 0xFFFFFFFFull)
-        return WP_ERR_INVALID_ARG;
+        return false;
     // largest items first: full pages, then runs (longest first), then tails
     std::stable_sort(bp_items.begin(), bp_items.end(), [](const uint4 &a, const uint4 &b) { return a.w > b.w; });
     items.reserve(fp_items.size() + bp_items.size() + tail_items.size());
     items.insert(items.end(), fp_items.begin(), fp_items.end());
+    npages = fp_items.size();
     items.insert(items.end(), bp_items.begin(), bp_items.end());
     items.insert(items.end(), tail_items.begin(), tail_items.end());
     if (items.size() > 0xFFFFFFF0ull)
-        return WP_ERR_INVALID_ARG;
+        return false;
     return true;
 }
 
@@ -261,7 +314,7 @@ extern "C" int32_t wp_batch_plan(const uint32_t *pool, uint32_t *out_base, const
     *h_plan = nullptr;
     if (!aligned16(pool) || !aligned16(out_base))
         return WP_ERR_INVALID_ARG;
-    wp_tune t = {4, 4, 4, 8, 0, 1};
+    wp_tune t = {4, 4, 2, 8, 0, 1};
     if (tune) {
         t = *tune;
         if (t.waves == 0)
@@ -269,7 +322,7 @@ extern "C" int32_t wp_batch_plan(const uint32_t *pool, uint32_t *out_base, const
         if (t.vpl == 0)
             t.vpl = 4;
         if (t.depth == 0)
-            t.depth = t.waves == 8 ? 2 : 4;
+            t.depth = 2;
         if (t.run_units == 0)
             t.run_units = 8;
     }
@@ -281,13 +334,15 @@ extern "C" int32_t wp_batch_plan(const uint32_t *pool, uint32_t *out_base, const
         return WP_ERR_HIP;
     std::vector<DevList> lists;
     std::vector<uint4> items;
-    if (!build_items(pool, out_base, h_lists, nlists, t.run_units, lists, items))
+    uint64_t npages = 0;
+    if (!build_items(pool, out_base, h_lists, nlists, t.run_units, lists, items, npages))
         return WP_ERR_INVALID_ARG;
     Plan *p = new Plan();
     p->device = ds->device;
     p->err = ds->err;
     p->nlists = nlists;
     p->nitems = items.size();
+    p->npages = npages;
     p->waves = t.waves;
     p->vpl = t.vpl;
     p->depth = t.depth;
@@ -295,7 +350,8 @@ extern "C" int32_t wp_batch_plan(const uint32_t *pool, uint32_t *out_base, const
     p->use_graph = t.use_graph != 0;
     p->run_units = t.run_units;
     p->cus = ds->cus;
-    const uint64_t wpc = t.wg_per_cu > 0 ? (uint64_t)t.wg_per_cu : (t.waves == 2 ? 8 : 4);
+    // default: about kBpRunsPerCu wavefronts per compute unit
+    const uint64_t wpc = t.wg_per_cu > 0 ? (uint64_t)t.wg_per_cu : std::max<uint64_t>(1, kBpRunsPerCu / t.waves);
     p->wpc = (int)wpc;
     p->cap_lists = std::max<uint64_t>(1, lists.size());
     p->cap_items = std::max<uint64_t>(1, items.size());
@@ -374,7 +430,9 @@ extern "C" int32_t wp_batch_replan(void *h_plan, const uint32_t *pool, uint32_t 
         return WP_ERR_INVALID_ARG;
     std::vector<DevList> lists;
     std::vector<uint4> items;
-    if (!build_items(pool, out_base, h_lists, nlists, p->run_units, lists, items) || items.size() > 0xFFFFFFF0ull)
+    uint64_t npages = 0;
+    if (!build_items(pool, out_base, h_lists, nlists, p->run_units, lists, items, npages) ||
+        items.size() > 0xFFFFFFF0ull)
         return WP_ERR_INVALID_ARG;
     hipStream_t st = as_stream(stream);
     // the previous copy out of the pinned staging must have finished
@@ -432,6 +490,7 @@ extern "C" int32_t wp_batch_replan(void *h_plan, const uint32_t *pool, uint32_t 
         return WP_ERR_HIP;
     p->nlists = lists.size();
     p->nitems = items.size();
+    p->npages = npages;
     uint64_t grid = (uint64_t)p->cus * (uint64_t)p->wpc;
     grid = std::max<uint64_t>(1, std::min<uint64_t>(grid, p->nitems ? p->nitems : 1));
     p->grid = (uint32_t)grid;

@@ -3,11 +3,9 @@
 // Units are independent because the directory stores each unit's offset
 // and base value(s): no cross-workgroup dependency, no second pass.
 //
-// Binary packing: each workgroup decodes a contiguous run of meta-blocks.
-// The run's directory entries are read once (one lane per entry); while a
-// meta-block is decoded from LDS, the next one's words are already on their
-// way into registers, so every workgroup keeps one unit of HBM reads in
-// flight behind its compute and its stores.
+// Binary packing: every wavefront decodes its own contiguous run of
+// meta-blocks (bp_wave_run); a workgroup is just WAVES such runs side by
+// side. The workgroup after the last run decodes the Variable Byte tail.
 //
 // Patched pages: one workgroup per page (see fp_page).
 #include <mutex>
@@ -18,37 +16,44 @@
 
 namespace wp {
 
-template <int WAVES, int VPL, int DEPTH>
+template <int WAVES, int DEPTH>
 union BpKernelLds {
-    RingLds<WAVES, VPL, DEPTH> r;
+    WaveLds<DEPTH> w[WAVES];
     TailLds<WAVES> tail;
 };
 
-// Decodes meta-blocks [blockIdx.x * upw, ...) of one list; the workgroup
-// after the last run decodes the tail.
-template <int WAVES, int VPL, int DEPTH>
+// Wavefront w of workgroup g decodes run g * WAVES + w: meta-blocks
+// [run * upw, run * upw + upw) of one list.
+template <int WAVES, int DEPTH>
 __global__ __launch_bounds__(64 * WAVES) void k_bp_decode(const uint32_t *__restrict__ in, uint64_t in_words,
                                                           uint32_t *__restrict__ out, uint64_t n,
                                                           int *__restrict__ err, uint32_t upw)
 {
-    __shared__ BpKernelLds<WAVES, VPL, DEPTH> L;
+    __shared__ BpKernelLds<WAVES, DEPTH> L;
     ListHdr H;
     if (!check_header(in, in_words, n, kMagicBP, kBpBlocks, H)) {
         if (blockIdx.x == 0 && threadIdx.x == 0)
             *err = kErrCorrupt;
         return;
     }
-    const uint32_t tid = threadIdx.x;
-    const uint64_t nwg = (H.units + upw - 1) / upw;
+    const uint64_t nruns = (H.units + upw - 1) / upw;
+    const uint64_t nwg = (nruns + WAVES - 1) / WAVES;
     if (blockIdx.x >= nwg) {
         if (blockIdx.x == nwg && H.tail)
-            if (!decode_tail_entry<WAVES>(in, H, out, L.tail) && tid == 0)
+            if (!decode_tail_entry<WAVES>(in, H, out, L.tail) && threadIdx.x == 0)
                 *err = kErrCorrupt;
         return;
     }
-    const uint64_t ua = (uint64_t)blockIdx.x * upw;
+    const uint32_t wave = uniform(threadIdx.x >> 6);
+    const uint64_t r = (uint64_t)blockIdx.x * WAVES + wave;
+    if (r >= nruns)
+        return;
+    const uint64_t ua = r * upw;
     const uint32_t cnt = (uint32_t)((H.units - ua) < upw ? (H.units - ua) : upw);
-    if (!bp_decode_run<WAVES, VPL, DEPTH>(in, H, ua, cnt, out, L.r) && tid == 0)
+    const bool ok = H.S == 1   ? bp_wave_run<DEPTH, 1>(in, H, ua, cnt, out, L.w[wave])
+                    : H.S == 4 ? bp_wave_run<DEPTH, 4>(in, H, ua, cnt, out, L.w[wave])
+                               : bp_wave_run<DEPTH, 0>(in, H, ua, cnt, out, L.w[wave]);
+    if (!ok && lane_id() == 0)
         *err = kErrCorrupt;
 }
 
@@ -97,7 +102,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_fp_decode(const uint32_t *__rest
 
 static std::mutex g_mu;
 static std::vector<DevState> g_dev;
-static Tune g_tune[2] = {{4, 4, 8, 4}, {4, 4, 0, 0}};
+static Tune g_tune[2] = {{4, 4, kBpRunsPerCu, 2}, {4, 4, 0, 0}};
 
 DevState *dev_state()
 {
@@ -135,16 +140,15 @@ Tune decode_tune(int codec)
 static bool valid_tune(int codec, int waves, int vpl)
 {
     if (codec == WP_CODEC_BP)
-        return (waves == 2 && (vpl == 4 || vpl == 8)) || (waves == 4 && (vpl == 4 || vpl == 8)) ||
-               (waves == 8 && vpl == 4);
+        return (waves == 1 || waves == 2 || waves == 4 || waves == 8) && vpl == 4;
     return (waves == 4 || waves == 8) && (vpl == 4 || vpl == 8);
 }
 
-template <int WAVES, int VPL, int DEPTH>
+template <int WAVES, int DEPTH>
 static void launch_bp(uint64_t grid, hipStream_t st, const uint32_t *in, uint64_t in_words, uint32_t *out,
                       uint64_t n, int *err, uint32_t upw)
 {
-    hipLaunchKernelGGL((k_bp_decode<WAVES, VPL, DEPTH>), dim3((uint32_t)grid), dim3(64 * WAVES), 0, st, in,
+    hipLaunchKernelGGL((k_bp_decode<WAVES, DEPTH>), dim3((uint32_t)grid), dim3(64 * WAVES), 0, st, in,
                        in_words, out, n, err, upw);
 }
 
@@ -176,29 +180,29 @@ static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, u
     const Tune t = decode_tune(codec);
     (void)hipGetLastError();
     if (codec == WP_CODEC_BP) {
-        // runs of upw meta-blocks: about wg_per_cu runs per compute unit
-        const uint64_t target = (uint64_t)ds->cus * (uint64_t)(t.wg_per_cu > 0 ? t.wg_per_cu : 8);
+        // runs of upw meta-blocks, one per wavefront: about wg_per_cu runs
+        // per compute unit
+        const uint64_t target = (uint64_t)ds->cus * (uint64_t)(t.wg_per_cu > 0 ? t.wg_per_cu : kBpRunsPerCu);
         uint64_t upw = (units + target - 1) / (target ? target : 1);
         upw = upw < 1 ? 1 : (upw > 63 ? 63 : upw);
-        uint64_t grid = (units + upw - 1) / upw + has_tail;
+        const uint64_t nruns = (units + upw - 1) / upw;
+        uint64_t grid = (nruns + t.waves - 1) / t.waves + has_tail;
         grid = grid ? grid : 1;
         if (grid > 0x7FFFFFFFull)
             return WP_ERR_INVALID_ARG;
         const uint32_t u32 = (uint32_t)upw;
-        const bool deep = t.depth >= 4;
-#define WP_BP(W, V)                                                                                             \
-    (deep ? launch_bp<W, V, 4>(grid, st, in, in_words, out, n, ds->err, u32)                                   \
-          : launch_bp<W, V, 2>(grid, st, in, in_words, out, n, ds->err, u32))
-        if (t.waves == 2 && t.vpl == 4)
-            WP_BP(2, 4);
-        else if (t.waves == 2 && t.vpl == 8)
-            WP_BP(2, 8);
-        else if (t.waves == 4 && t.vpl == 4)
-            WP_BP(4, 4);
-        else if (t.waves == 4 && t.vpl == 8)
-            WP_BP(4, 8);
+#define WP_BP(W)                                                                                                \
+    (t.depth >= 4   ? launch_bp<W, 4>(grid, st, in, in_words, out, n, ds->err, u32)                            \
+     : t.depth == 3 ? launch_bp<W, 3>(grid, st, in, in_words, out, n, ds->err, u32)                            \
+                    : launch_bp<W, 2>(grid, st, in, in_words, out, n, ds->err, u32))
+        if (t.waves == 1)
+            WP_BP(1);
+        else if (t.waves == 2)
+            WP_BP(2);
+        else if (t.waves == 4)
+            WP_BP(4);
         else
-            WP_BP(8, 4);
+            WP_BP(8);
 #undef WP_BP
     } else {
         uint64_t grid = units + has_tail;
@@ -235,10 +239,10 @@ extern "C" int32_t fastpfor_decode(const uint32_t *in, uint64_t in_words, uint32
 extern "C" int32_t wp_set_decode_tune(int32_t codec, int32_t waves, int32_t vpl, int32_t depth, int32_t wg_per_cu)
 {
     if ((codec != WP_CODEC_BP && codec != WP_CODEC_FP) || !valid_tune(codec, waves, vpl) || wg_per_cu < 0 ||
-        wg_per_cu > 64 || (depth != 0 && depth != 2 && depth != 4))
+        wg_per_cu > 1024 || depth < 0 || depth == 1 || depth > 4)
         return WP_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(g_mu);
-    g_tune[codec] = Tune{waves, vpl, wg_per_cu, depth ? depth : 4};
+    g_tune[codec] = Tune{waves, vpl, wg_per_cu, depth ? depth : 2};
     return WP_OK;
 }
 

@@ -75,6 +75,15 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v)
 
 __device__ __forceinline__ uint32_t wave_read(uint32_t v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 
+// Orders this wavefront's LDS accesses around a lane exchange (LDS
+// instructions of one wavefront execute in issue order; this only stops the
+// compiler from moving them).
+__device__ __forceinline__ void wave_lds_order()
+{
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 __device__ __forceinline__ uint32_t width_mask(uint32_t b) { return b >= 32u ? 0xffffffffu : ((1u << b) - 1u); }
 
 // Field of `mask`'s width starting at bit `bit` of the word string `w`:
@@ -257,14 +266,6 @@ __device__ __forceinline__ void unpack_lane(const uint32_t *words, uint32_t bit0
 // LDS arena shared by all roles (a workgroup plays one role at a time).
 
 template <int WAVES, int VPL>
-struct BpLds {
-    uint4 pk[kBpUnitInts / 4 + 1];  // staged blocks of a meta-block (+1 word of over-read)
-    uint32_t b[kBpBlocks];
-    uint32_t off[kBpBlocks];
-    uint32_t wtot[2][WAVES][4];
-};
-
-template <int WAVES, int VPL>
 struct FpLds {
     uint4 pk[Geo<WAVES, VPL>::WPP / 4 + 1];             // staged packed words of one pass
     alignas(16) uint32_t ptc[Geo<WAVES, VPL>::BPP * kBlock];  // patch area of one pass
@@ -291,87 +292,32 @@ struct TailLds {
     uint32_t bad;
 };
 
-template <int WAVES, int VPL>
-union DecodeLds {
-    BpLds<WAVES, VPL> bp;
-    FpLds<WAVES, VPL> fp;
-    TailLds<WAVES> tail;
-};
-
-// ------------------------------------------------------------------------
-// Binary-packing meta-block (Section 6.2): descriptor + up to 16 blocks.
-// `unit` points at the descriptor (16-byte aligned), `nwords` is the unit's
-// length in words, `nb` the number of full blocks it must hold, `out` the
-// unit's first output integer. Returns false (uniformly) on a bad unit,
-// before writing anything.
-template <int WAVES, int VPL>
-__device__ bool bp_unit(const uint32_t *__restrict__ unit, uint32_t nwords, uint32_t nb, uint32_t S,
-                        const uint32_t (&base)[4], uint32_t *__restrict__ out, BpLds<WAVES, VPL> &L)
-{
-    using G = Geo<WAVES, VPL>;
-    const uint32_t tid = threadIdx.x;
-    if (nwords < 4)
-        return false;
-    // widths from the 128-bit descriptor (uniform loads)
-    const uint32_t d[4] = {unit[0], unit[1], unit[2], unit[3]};
-    uint32_t sum = 0;
-    bool ok = true;
-#pragma unroll
-    for (uint32_t j = 0; j < kBpBlocks; ++j) {
-        const uint32_t b = (d[j >> 2] >> (8 * (j & 3))) & 255u;
-        ok = ok && b <= 32 && (j < nb || b == 0);
-        sum += b;
-    }
-    ok = ok && nwords == 4 + 4 * sum;
-    if (!ok)
-        return false;
-    const uint4 *src = reinterpret_cast<const uint4 *>(unit + 4);
-    const uint32_t n4 = sum;  // (4 * sum words) / 4
-    for (uint32_t i = tid; i < n4; i += G::T)
-        L.pk[i] = src[i];
-    if (tid < kBpBlocks) {
-        uint32_t pre = 0;
-        for (uint32_t j = 0; j < tid; ++j)
-            pre += (d[j >> 2] >> (8 * (j & 3))) & 255u;
-        L.b[tid] = (d[tid >> 2] >> (8 * (tid & 3))) & 255u;
-        L.off[tid] = 4 * pre;
-    }
-    __syncthreads();
-    const uint32_t lane = lane_id();
-    const uint32_t wave = uniform(tid >> 6);
-    const uint32_t q = lane % G::LPB;
-    const uint32_t *words = reinterpret_cast<const uint32_t *>(L.pk);
-    uint32_t carry[4] = {base[0], base[1], base[2], base[3]};
-#pragma unroll
-    for (int p = 0; p < (int)kBpBlocks / G::BPP; ++p) {
-        const uint32_t j = p * G::BPP + wave * G::BPW + lane / G::LPB;
-        const uint32_t b = L.b[j];
-        uint32_t v[VPL];
-        unpack_lane<VPL>(words, L.off[j] * 32 + VPL * q * b, b, v);
-        scan_pass<WAVES, VPL>(v, S, carry, L.wtot[p & 1]);
-        if (j < nb)
-            store_lane<VPL>(out + j * kBlock + VPL * q, v);
-    }
-    return true;
-}
-
 // ------------------------------------------------------------------------
 // Variable Byte tail (Section 2.4, remainder after the last block as in
 // Section 6.2): up to 127 integers of 1..5 bytes, low 7-bit group first,
 // top bit set on the last byte. Parallel parse: each byte is looked at by
 // one lane; terminator bytes are counted with ballots to give each integer
 // its index; the terminator's lane gathers the integer's bytes.
-template <int WAVES>
+// WG: the whole workgroup of WAVES wavefronts takes part; otherwise one
+// wavefront by itself (WAVES == 1, no workgroup barrier).
+template <int WAVES, bool WG = true>
 __device__ bool tail_decode(const uint32_t *__restrict__ tw, uint32_t tail_bytes, uint32_t count,
                             uint32_t S, const uint32_t (&base)[4], uint32_t *__restrict__ out,
                             TailLds<WAVES> &L)
 {
+    static_assert(WG || WAVES == 1, "a single wavefront");
     constexpr int T = 64 * WAVES;
     constexpr int R = (kMaxTailBytes + T - 1) / T;
     static_assert(R * WAVES <= 32, "tail counters");
-    const uint32_t tid = threadIdx.x;
     const uint32_t lane = lane_id();
-    const uint32_t wave = uniform(tid >> 6);
+    const uint32_t tid = WG ? threadIdx.x : lane;
+    const uint32_t wave = WG ? uniform(tid >> 6) : 0u;
+    auto sync = [&]() __attribute__((always_inline)) {
+        if constexpr (WG)
+            __syncthreads();
+        else
+            wave_lds_order();
+    };
     if (count == 0 || count >= kBlock || tail_bytes < count || tail_bytes > 5 * count)
         return false;
     const uint32_t nw = (tail_bytes + 3) / 4;
@@ -379,7 +325,7 @@ __device__ bool tail_decode(const uint32_t *__restrict__ tw, uint32_t tail_bytes
         L.words[i] = tw[i];
     if (tid == 0)
         L.bad = 0;
-    __syncthreads();
+    sync();
     const uint8_t *by = reinterpret_cast<const uint8_t *>(L.words);
     uint64_t m[R];
 #pragma unroll
@@ -390,7 +336,7 @@ __device__ bool tail_decode(const uint32_t *__restrict__ tw, uint32_t tail_bytes
         if (lane == 0)
             L.cnt[r * WAVES + wave] = (uint32_t)__builtin_popcountll(m[r]);
     }
-    __syncthreads();
+    sync();
     uint32_t total = 0;
     for (int c = 0; c < R * WAVES; ++c)
         total += L.cnt[c];
@@ -416,7 +362,7 @@ __device__ bool tail_decode(const uint32_t *__restrict__ tw, uint32_t tail_bytes
                 L.vals[idx] = (uint32_t)v;
         }
     }
-    __syncthreads();
+    sync();
     if (L.bad || total != count || !(by[tail_bytes - 1] & 0x80u))
         return false;
     if (wave == 0) {
@@ -454,8 +400,8 @@ __device__ bool tail_decode(const uint32_t *__restrict__ tw, uint32_t tail_bytes
 }
 
 // The list's tail entry (directory entry n_units): offset check, bases,
-// then tail_decode. Called by a whole workgroup.
-template <int WAVES>
+// then tail_decode. Called by a whole workgroup (WG) or one wavefront.
+template <int WAVES, bool WG = true>
 __device__ bool decode_tail_entry(const uint32_t *__restrict__ in, const ListHdr &H, uint32_t *__restrict__ out,
                                   TailLds<WAVES> &L)
 {
@@ -465,7 +411,7 @@ __device__ bool decode_tail_entry(const uint32_t *__restrict__ in, const ListHdr
         base[s] = in[kHdrWords + H.ndir + H.units * H.S + s];
     if (!(off == H.tail_off && (uint64_t)off + (H.tail_bytes + 3) / 4 == H.total))
         return false;
-    return tail_decode<WAVES>(in + off, H.tail_bytes, H.tail, H.S, base, out + H.nfull * kBlock, L);
+    return tail_decode<WAVES, WG>(in + off, H.tail_bytes, H.tail, H.S, base, out + H.nfull * kBlock, L);
 }
 
 // Tables of a patched page from its per-block metadata L.b, L.mb, L.c
@@ -718,107 +664,101 @@ constexpr uint32_t pow2ceil(uint32_t x)
     return p;
 }
 
-// A workgroup decodes a run of consecutive meta-blocks. Their compressed
-// words are one contiguous range of the stream, which is streamed through
-// an LDS ring in chunks of one 16-byte load per thread. DEPTH chunk loads
-// are in flight at any time (a register FIFO: the loop is unrolled DEPTH
-// times so every slot has a fixed register), so the bytes in flight do not
-// depend on how small the meta-blocks compress. A meta-block is decoded as
-// soon as its last word has reached the ring.
-template <int WAVES, int VPL, int DEPTH>
-struct RingGeo {
-    static constexpr int T = 64 * WAVES;
-    static constexpr uint32_t CW = T * 4;                 // words per chunk
-    static constexpr uint32_t MAXU = 4 + kBpUnitInts;     // words of the largest meta-block
-    // a group of DEPTH chunks is written while the oldest unfinished
-    // meta-block (started less than MAXU words before the group) stays intact
-    static constexpr uint32_t RB = pow2ceil(DEPTH * CW + MAXU);  // ring words
-};
-
-template <int WAVES, int VPL, int DEPTH>
-struct RingLds {
-    uint32_t ring[RingGeo<WAVES, VPL, DEPTH>::RB + 4];  // + a copy of words 0..3 after the end
-    uint32_t b[kBpBlocks];                              // widths of the meta-block being decoded
-    uint32_t off[kBpBlocks];                            // word offset of each block from its start
-    uint32_t wtot[2][WAVES][4];
-};
-
-// Field at bit `bit` of the word string starting at ring word `w0`
-// (ring positions wrap; the word after the last is mirrored).
-template <uint32_t RB>
-__device__ __forceinline__ uint32_t ring_field(const uint32_t *ring, uint32_t w0, uint32_t bit, uint32_t mask)
+__device__ __forceinline__ void buf_store_u4(BufRsrc rs, uint32_t byte_off, uint32_t soff, uint4 v)
 {
-    const uint32_t p = (w0 + (bit >> 5)) & (RB - 1);
-    return __builtin_amdgcn_alignbit(ring[p + 1], ring[p], bit) & mask;
+    const u32x4_t w = {v.x, v.y, v.z, v.w};
+    __builtin_amdgcn_raw_buffer_store_b128(w, rs, (int)byte_off, (int)soff, 0);
 }
 
-// Decodes the meta-block whose words start at ring word `su` (relative to
-// the run); all threads. Returns the uniform validity of its descriptor.
-template <int WAVES, int VPL, int DEPTH, bool FULL>
-__device__ __forceinline__ bool bp_unit_ring(RingLds<WAVES, VPL, DEPTH> &L, uint32_t su, uint32_t nw, uint32_t nb,
-                                             uint32_t S, uint32_t (&carry)[4], uint32_t *__restrict__ uout,
-                                             uint32_t &par)
+// Binary packing, one wavefront per run of meta-blocks (Section 6.2 format,
+// Section 4 bit layout, Section 3 prefix sum).
+//
+// A wavefront decodes a run of consecutive meta-blocks by itself, so no
+// workgroup barrier is involved. The run's compressed words (one contiguous
+// range) stream through a private LDS ring in chunks of one 16-byte load
+// per lane (256 words); DEPTH chunk loads stay in flight in named registers
+// and are written to the ring a group at a time, whenever the next pass
+// needs words that are not there yet.
+//
+// A pass decodes two blocks: lanes 0..31 the first, lanes 32..63 the
+// second. Lane q of a block takes integers q, q+32, q+64 and q+96: integer
+// q + 32m starts at bit q*b + 32*m*b, i.e. in word (q*b >> 5) + m*b at the
+// same shift q*b & 31 for every m. Each integer costs an address add, a
+// paired LDS read, a funnel shift and a mask, and the lanes of a block read
+// consecutive words. The integers are then transposed through LDS so that
+// lane l holds integers 4l..4l+3 of the pass for the prefix sum and the
+// 16-byte stores.
+template <int DEPTH>
+struct WaveGeo {
+    static_assert(DEPTH >= 2 && DEPTH <= 4, "depth");
+    static constexpr uint32_t CW = 256;               // words per chunk
+    static constexpr uint32_t PASS = 2 * kBlock;      // integers of a pass, and the most words it reads
+    // a group is written while the pass that needs it (at most PASS words,
+    // starting less than PASS words before the group) stays intact
+    static constexpr uint32_t RB = pow2ceil(DEPTH * CW + PASS);
+    static constexpr uint32_t MIR = kBlock + 4;       // ring words mirrored after the end
+    static constexpr uint32_t MAXU = 4 + kBpUnitInts; // words of the largest meta-block
+};
+
+template <int DEPTH>
+struct alignas(16) WaveLds {
+    uint32_t ring[WaveGeo<DEPTH>::RB + WaveGeo<DEPTH>::MIR];
+    uint32_t xp[WaveGeo<DEPTH>::PASS];                // transposition of one pass
+};
+
+// Prefix sum of one pass held as four consecutive integers per lane, in
+// place. stride 1: lane-serial sums, a wave scan of the lane totals, plus
+// the carry; stride 4: one wave scan per residue class (each lane holds
+// one integer of each class); stride 0: nothing. carry advances to the
+// value(s) at the end of the pass.
+template <uint32_t S>
+__device__ __forceinline__ void scan_wave4(uint32_t (&x)[4], uint32_t (&carry)[4])
 {
-    using G = Geo<WAVES, VPL>;
-    using RG = RingGeo<WAVES, VPL, DEPTH>;
-    const uint32_t tid = threadIdx.x;
-    const uint32_t lane = lane_id();
-    const uint32_t wave = uniform(tid >> 6);
-    uint32_t d[4];
+    if constexpr (S == 1) {
+        x[1] += x[0];
+        x[2] += x[1];
+        x[3] += x[2];
+        const uint32_t incl = wave_scan_incl(x[3]);
+        const uint32_t add = incl - x[3] + carry[0];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-        d[k] = uniform(L.ring[(su + k) & (RG::RB - 1)]);
-    uint32_t sum = 0, bt = 0, pre = 0;
-    bool ok = true;
+        for (int r = 0; r < 4; ++r)
+            x[r] += add;
+        carry[0] += wave_read(incl, 63);
+    } else if constexpr (S == 4) {
 #pragma unroll
-    for (uint32_t j = 0; j < kBpBlocks; ++j) {
-        const uint32_t b = (d[j >> 2] >> (8 * (j & 3))) & 255u;
-        ok = ok && b <= 32 && (j < nb || b == 0);
-        sum += b;
-        // thread t: width of block t (clamped so that a bad descriptor
-        // cannot address outside the meta-block) and the words before it
-        const uint32_t bc = b < 32u ? b : 32u;
-        pre += j < tid ? bc : 0u;
-        bt = j == tid ? bc : bt;
-    }
-    ok = ok && nw == 4 + 4 * sum;
-    if (tid < kBpBlocks) {
-        L.b[tid] = bt;
-        L.off[tid] = 4 + 4 * pre;
-    }
-    __syncthreads();
-    const uint32_t q = lane % G::LPB;
-#pragma unroll
-    for (int p = 0; p < (int)kBpBlocks / G::BPP; ++p) {
-        const uint32_t j = p * G::BPP + wave * G::BPW + lane / G::LPB;
-        const uint32_t b = L.b[j];
-        const uint32_t mask = width_mask(b);
-        const uint32_t w0 = su + L.off[j];
-        uint32_t bit = VPL * q * b;
-        uint32_t v[VPL];
-#pragma unroll
-        for (int r = 0; r < VPL; ++r) {
-            v[r] = ring_field<RG::RB>(L.ring, w0, bit, mask);
-            bit += b;
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t incl = wave_scan_incl(x[c]);
+            x[c] = incl + carry[c];
+            carry[c] += wave_read(incl, 63);
         }
-        scan_pass<WAVES, VPL>(v, S, carry, L.wtot[par]);
-        par ^= 1u;
-        if (FULL || j < nb)
-            store_lane<VPL>(uout + j * kBlock + VPL * q, v);
     }
-    __syncthreads();
-    return ok;
 }
 
-// Decodes meta-blocks [ua, ua + cnt) of the list whose validated header is
-// H (cnt <= 63). All threads of the workgroup; returns the uniform validity
-// of the run (a bad unit's output is unspecified but stays in its place).
-template <int WAVES, int VPL, int DEPTH>
-__device__ bool bp_decode_run(const uint32_t *__restrict__ in, const ListHdr &H, uint64_t ua, uint32_t cnt,
-                              uint32_t *__restrict__ out, RingLds<WAVES, VPL, DEPTH> &L)
+// Sum of the four byte lanes of each word, and whether any byte exceeds 32.
+__device__ __forceinline__ uint32_t byte_sum(uint32_t d)
 {
-    using RG = RingGeo<WAVES, VPL, DEPTH>;
-    const uint32_t tid = threadIdx.x;
+    const uint32_t s = (d & 0x00ff00ffu) + ((d >> 8) & 0x00ff00ffu);
+    return (s & 0xffffu) + (s >> 16);
+}
+__device__ __forceinline__ bool byte_over32(uint32_t d)
+{
+    const uint32_t low5 = d & 0x1f1f1f1fu;
+    const uint32_t nz = ((low5 + 0x7f7f7f7fu) & 0x80808080u) >> 7;  // low five bits non-zero
+    const uint32_t b5 = (d >> 5) & 0x01010101u;                     // bit 5 set
+    return (d & 0xc0c0c0c0u) != 0u || (nz & b5) != 0u;
+}
+
+// Decodes meta-blocks [ua, ua + cnt) (cnt <= 63) of the list whose validated
+// header is H, whose stride is S; one wavefront, its own LDS slice L.
+// Returns the uniform validity of the run: on a bad run the wavefront
+// stops, its output is unspecified but every store stays inside the run's
+// output range.
+template <int DEPTH, uint32_t S>
+__device__ bool bp_wave_run(const uint32_t *__restrict__ in, const ListHdr &H, uint64_t ua, uint32_t cnt,
+                            uint32_t *__restrict__ out, WaveLds<DEPTH> &L)
+{
+    using G = WaveGeo<DEPTH>;
+    constexpr uint32_t RB = G::RB, CW = G::CW;
     const uint32_t lane = lane_id();
     // the run's directory: lane i holds the offset of entry ua + i (i <= cnt)
     // and its bases
@@ -827,71 +767,120 @@ __device__ bool bp_decode_run(const uint32_t *__restrict__ in, const ListHdr &H,
     if (lane <= cnt)
         offv = (ua + lane < H.units) ? in[kHdrWords + ua + lane] : H.tail_off;
     if (lane < cnt)
-        for (uint32_t s = 0; s < H.S; ++s)
-            bv[s] = in[kHdrWords + H.ndir + (ua + lane) * H.S + s];
+        for (uint32_t s = 0; s < S; ++s)
+            bv[s] = in[kHdrWords + H.ndir + (ua + lane) * S + s];
+    const uint32_t nxt = __shfl_down(offv, 1);
+    const bool lane_bad = lane < cnt && (nxt < offv || nxt - offv > G::MAXU || (offv & 3u) != 0u);
     const uint32_t W0 = wave_read(offv, 0), Wend = wave_read(offv, cnt);
-    bool bad = !(W0 >= H.dir_end && Wend >= W0 && Wend <= H.total && (W0 & 3u) == 0);
-    const uint32_t run_len = bad ? 0u : Wend - W0;
-    const BufRsrc rs = make_rsrc(in + (bad ? 0u : W0), run_len * 4u);
-    const uint32_t nchunks = (run_len + RG::CW - 1) / RG::CW;
-    // DEPTH chunk loads in flight, one named register per slot (an array
-    // indexed by a loop counter ends up in scratch memory)
+    if (ballot(lane_bad) != 0 || !(W0 >= H.dir_end && Wend <= H.total))
+        return false;
+    const uint32_t run_len = Wend - W0;  // <= 63 * MAXU words
+    const BufRsrc rs = make_rsrc(in + W0, run_len * 4u);
+    // output of the run: full blocks only (the tail belongs to another
+    // workgroup); stores beyond the range are dropped by the hardware
+    const uint64_t o0 = ua * kBpUnitInts;
+    const uint64_t o1e = (ua + cnt) * kBpUnitInts, o2e = H.nfull * kBlock;
+    const BufRsrc ro = make_rsrc(out + o0, (uint32_t)(((o1e < o2e ? o1e : o2e) - o0) * 4u));
+
+    // slots are loaded, written and reloaded in the same order, so the
+    // wait for a slot never covers a younger slot's load
     uint4 s0, s1, s2, s3;
-    s0 = buf_load_u4(rs, (0 * RG::CW + tid * 4) * 4);
-    s1 = buf_load_u4(rs, (1 * RG::CW + tid * 4) * 4);
-    if constexpr (DEPTH > 2) {
-        s2 = buf_load_u4(rs, (2 * RG::CW + tid * 4) * 4);
-        s3 = buf_load_u4(rs, (3 * RG::CW + tid * 4) * 4);
-    }
-    // chunk c + k goes from its slot into the ring and the slot reloads
-    // chunk c + k + DEPTH; the reload is issued on every path (beyond the
-    // run it reads nothing), so each slot always has DEPTH - 1 younger
-    // loads when it is next needed and that wait never drains the stores
+    s0 = buf_load_u4(rs, (0 * CW + lane * 4) * 4);
+    __builtin_amdgcn_sched_barrier(0);
+    s1 = buf_load_u4(rs, (1 * CW + lane * 4) * 4);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (DEPTH > 2)
+        s2 = buf_load_u4(rs, (2 * CW + lane * 4) * 4);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (DEPTH > 3)
+        s3 = buf_load_u4(rs, (3 * CW + lane * 4) * 4);
+    uint32_t written = 0;  // words of the run already in the ring
     auto put = [&](uint4 &slot, uint32_t c) __attribute__((always_inline)) {
-        if (c < nchunks) {
-            const uint32_t pos = (c * RG::CW + tid * 4) & (RG::RB - 1);
-            *reinterpret_cast<uint4 *>(&L.ring[pos]) = slot;
-            if (pos == 0)
-                *reinterpret_cast<uint4 *>(&L.ring[RG::RB]) = slot;
-        }
-        slot = buf_load_u4(rs, ((c + DEPTH) * RG::CW + tid * 4) * 4);
+        const uint32_t pos = (c * CW + lane * 4) & (RB - 1);
+        *reinterpret_cast<uint4 *>(&L.ring[pos]) = slot;
+        if (pos < G::MIR)
+            *reinterpret_cast<uint4 *>(&L.ring[RB + pos]) = slot;
+        slot = buf_load_u4(rs, ((c + DEPTH) * CW + lane * 4) * 4);
     };
-    auto put_group = [&](uint32_t c0) __attribute__((always_inline)) {
-        put(s0, c0);
-        put(s1, c0 + 1);
-        if constexpr (DEPTH > 2) {
-            put(s2, c0 + 2);
-            put(s3, c0 + 3);
+    // Brings the ring up to word `need` with at most one group: a pass
+    // reads at most PASS words starting at or before `written`, and a
+    // descriptor starts where the previous meta-block ended, so one group
+    // (DEPTH * CW >= PASS words) always suffices for a consistent run (no
+    // loop here: a loop would make every wait cover all younger stores).
+    auto fill_to = [&](uint32_t need) __attribute__((always_inline)) {
+        if (written < need) {
+            const uint32_t c = written / CW;
+            put(s0, c);
+            put(s1, c + 1);
+            if constexpr (DEPTH > 2)
+                put(s2, c + 2);
+            if constexpr (DEPTH > 3)
+                put(s3, c + 3);
+            written += DEPTH * CW;
         }
-        __syncthreads();
+        return written >= need;
     };
-    uint32_t i = 0, par = 0;
-    put_group(0);
-    for (uint32_t c0 = 0;; c0 += DEPTH) {
-        const uint32_t written = (c0 + DEPTH) * RG::CW < run_len ? (c0 + DEPTH) * RG::CW : run_len;
-        // decode every meta-block whose words are all in the ring
-        while (i < cnt) {
-            const uint32_t su = wave_read(offv, i) - W0, eu = wave_read(offv, i + 1) - W0;
-            if (eu > written)
-                break;
-            const uint64_t u = ua + i;
-            uint32_t carry[4];
+
+    const uint32_t q = lane & 31u;
+    const bool hi = lane >= 32u;
+    uint32_t *const xw = &L.xp[lane + (hi ? 96u : 0u)];   // integer q of the lane's block
+    const uint4 *const xr = reinterpret_cast<const uint4 *>(&L.xp[4 * lane]);
+    for (uint32_t i = 0; i < cnt; ++i) {
+        const uint32_t su = wave_read(offv, i) - W0, eu = wave_read(offv, i + 1) - W0;
+        const uint32_t nb = unit_blocks(H, ua + i);
+        if (!fill_to(su + 4))
+            return false;
+        const uint4 dsc = *reinterpret_cast<const uint4 *>(&L.ring[su & (RB - 1)]);
+        const uint32_t d0 = uniform(dsc.x), d1 = uniform(dsc.y), d2 = uniform(dsc.z), d3 = uniform(dsc.w);
+        // widths <= 32, none beyond the meta-block's blocks, sizes agree
+        const uint32_t nbb = 8u * nb;  // descriptor bits in use
+        const uint32_t k0 = nbb >= 32u ? 0u : (0xffffffffu << nbb);
+        const uint32_t k1 = nbb >= 64u ? 0u : nbb <= 32u ? 0xffffffffu : (0xffffffffu << (nbb - 32u));
+        const uint32_t k2 = nbb >= 96u ? 0u : nbb <= 64u ? 0xffffffffu : (0xffffffffu << (nbb - 64u));
+        const uint32_t k3 = nbb >= 128u ? 0u : nbb <= 96u ? 0xffffffffu : (0xffffffffu << (nbb - 96u));
+        const uint32_t sum = byte_sum(d0) + byte_sum(d1) + byte_sum(d2) + byte_sum(d3);
+        if (byte_over32(d0) || byte_over32(d1) || byte_over32(d2) || byte_over32(d3) ||
+            ((d0 & k0) | (d1 & k1) | (d2 & k2) | (d3 & k3)) != 0u || eu - su != 4u + 4u * sum)
+            return false;
+        uint32_t carry[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                carry[k] = wave_read(bv[k], i);
-            if (eu < su + 4 || eu - su > RG::MAXU)
-                bad = true;
-            else
-                bad = !bp_unit_ring<WAVES, VPL, DEPTH, false>(L, su, eu - su, unit_blocks(H, u), H.S, carry,
-                                                            out + u * kBpUnitInts, par) ||
-                      bad;
-            ++i;
+        for (int k = 0; k < 4; ++k)
+            carry[k] = wave_read(bv[k], i);
+        uint32_t ps = su + 4;  // first word of the pass
+        uint64_t dd = ((uint64_t)d1 << 32) | d0;
+        const uint32_t sbase = i * (kBpUnitInts * 4u);
+        for (uint32_t p = 0; 2 * p < nb; ++p) {
+            if (p == 4)
+                dd = ((uint64_t)d3 << 32) | d2;
+            const uint32_t bA = (uint32_t)dd & 255u, bB = ((uint32_t)dd >> 8) & 255u;
+            dd >>= 16;
+            const uint32_t pe = ps + 4u * (bA + bB);
+            if (!fill_to(pe))
+                return false;
+            const uint32_t b = hi ? bB : bA;
+            const uint32_t st = hi ? ps + 4u * bA : ps;
+            const uint32_t qb = q * b;
+            const uint32_t w0 = (st + (qb >> 5)) & (RB - 1);
+            const uint32_t mask = width_mask(b);
+            uint32_t v[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const uint32_t w = w0 + m * b;
+                v[m] = __builtin_amdgcn_alignbit(L.ring[w + 1], L.ring[w], qb) & mask;
+            }
+            wave_lds_order();
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                xw[32 * m] = v[m];
+            wave_lds_order();
+            const uint4 t = *xr;
+            uint32_t x[4] = {t.x, t.y, t.z, t.w};
+            scan_wave4<S>(x, carry);
+            buf_store_u4(ro, lane * 16u, sbase + p * (G::PASS * 4u), make_uint4(x[0], x[1], x[2], x[3]));
+            ps = pe;
         }
-        if (c0 + DEPTH >= nchunks)
-            break;
-        put_group(c0 + DEPTH);
     }
-    return !bad && i == cnt;
+    return true;
 }
 
 }  // namespace wp

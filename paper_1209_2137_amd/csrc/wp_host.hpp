@@ -29,9 +29,14 @@ void *stream_scratch(hipStream_t stream, size_t bytes);
 struct Tune {
     int waves;
     int vpl;
-    int wg_per_cu;  // binary packing: runs of meta-blocks per compute unit (0 = default)
-    int depth;      // binary packing: chunk loads in flight per workgroup (4 or 8)
+    int wg_per_cu;  // binary packing: runs (one per wavefront) per compute unit (0 = default)
+    int depth;      // binary packing: 16-byte chunk loads in flight per wavefront (2..4)
 };
+
+// Default binary-packing runs per compute unit. Many short runs (down to
+// one meta-block per wavefront) let the hardware dispatcher balance the
+// load: wavefronts that finish early take the next runs.
+constexpr int kBpRunsPerCu = 128;
 Tune decode_tune(int codec);
 
 // In-place inclusive prefix sum of data[0..n) on `st` (the chained scan of

@@ -11,13 +11,15 @@ import torch
 
 import oracle
 import paper_1209_2137_amd as wp
+from paper_1209_2137_amd import autotune
 from paper_1209_2137_amd import datagen
 
 pytestmark = pytest.mark.gpu
 
 CANARY = 0x5A5A5A5A
 PAD = 64
-BP_TUNES = [(8, 4, 16, 2), (4, 4, 1, 4), (4, 8, 7, 2), (2, 8, 16, 4), (2, 4, 64, 2)]
+# (waves, vpl, runs or workgroups per CU, depth)
+BP_TUNES = [(4, 4, 28, 2), (1, 4, 4, 3), (2, 4, 64, 4), (8, 4, 16, 2), (4, 4, 1, 3)]
 FP_TUNES = [(8, 4, 0, 0), (4, 4, 0, 0), (4, 8, 0, 0), (8, 8, 0, 0)]
 
 
@@ -26,8 +28,7 @@ def gpu():
     assert torch.cuda.is_available(), "the GPU tests need a GPU"
     wp.lib()
     yield
-    wp.set_decode_tune(wp.CODEC_BP, 4, 4, 8, 4)
-    wp.set_decode_tune(wp.CODEC_FP, 4, 4, 0)
+    autotune.apply()
 
 
 def to_dev(a):
@@ -109,6 +110,35 @@ def test_every_block_width(codec):
         assert_same(got, x)
 
 
+@pytest.mark.parametrize("stride", [0, 1])
+def test_mixed_block_widths_long_runs(stride):
+    # 150 meta-blocks whose blocks take widths 0..32 in random order, with
+    # stretches of 32-bit and of empty blocks: passes that read 0..256 words,
+    # ring wrap-around at every offset, runs of every length; plus a tail
+    rng = np.random.default_rng(77 + stride)
+    nblk = 150 * 16
+    widths = rng.integers(0, 33, size=nblk)
+    widths[100:180] = 32
+    widths[300:420] = 0
+    widths[1000:1003] = [32, 0, 32]
+    d = []
+    for j, b in enumerate(widths):
+        hi = (1 << int(b)) - 1
+        v = (rng.integers(0, 2**32, size=128, dtype=np.uint64) & hi).astype(np.uint32)
+        v[j % 128] = hi
+        d.append(v)
+    d.append(rng.integers(0, 2**32, size=77, dtype=np.uint64).astype(np.uint32))
+    d = np.concatenate(d)
+    x = d if stride == 0 else np.cumsum(d.astype(np.uint64)).astype(np.uint32)
+    s = encode(wp.CODEC_BP, x, stride)
+    for waves, vpl, wpc, depth in BP_TUNES:
+        wp.set_decode_tune(wp.CODEC_BP, waves, vpl, wpc, depth)
+        print(f"stride={stride} tune=({waves},{vpl},{wpc},{depth}) n={x.size}", flush=True)
+        rc, got = gpu_decode(wp.CODEC_BP, s, x.size)
+        assert rc == wp.OK
+        assert_same(got, x, f"tune=({waves},{vpl},{wpc},{depth})")
+
+
 def test_config_small_single_list():
     # 2^20 sorted integers, x_1 ~ U[0,1000), geometric gaps of mean 8
     x = datagen.single_geometric(1 << 20, mean=8.0, seed=1)
@@ -125,7 +155,7 @@ def test_full_size_binary_packing_lists():
         s = oracle.bp_encode(x, 1)
         comp = to_dev(s)
         out = torch.empty(x.size, dtype=torch.int32, device="cuda")
-        wp.set_decode_tune(wp.CODEC_BP, 4, 4, 8, 4)
+        autotune.apply()  # the tuned launch shape, as timed by the benchmark
         wp.bp_decode(comp, x.size, out)
         assert wp.check_code() == wp.OK
         assert torch.equal(out, to_dev(x))
@@ -139,7 +169,7 @@ def test_full_size_patched_list():
     xd = to_dev(x)
     del x
     out = torch.empty(xd.numel(), dtype=torch.int32, device="cuda")
-    wp.set_decode_tune(wp.CODEC_FP, 4, 4, 0)
+    autotune.apply()
     wp.fastpfor_decode(comp, xd.numel(), out)
     assert wp.check_code() == wp.OK
     assert torch.equal(out, xd)
