@@ -1,9 +1,10 @@
 // delta_decode_inplace: the in-place prefix sum of Section 3 over a whole
 // device array, in one pass (read 4 B + write 4 B per integer).
 //
-// Tiles of 4096 integers (256 threads x 4 rows x 4 integers) take their
-// index from an atomic counter, so a tile's predecessors always started
-// first. Each tile scans locally, publishes its aggregate, then looks back
+// Tiles of 16384 integers (1024 threads x 4 rows x 4 integers, 64 KB) take
+// their index from an atomic counter, so a tile's predecessors always
+// started first. Large tiles matter: the inclusive prefix advances by at
+// most one look-back window (64 tiles) per device-scope round trip. Each tile scans locally, publishes its aggregate, then looks back
 // over its predecessors (a whole wavefront reads 64 of them at once) until
 // it meets one that has published its inclusive prefix (decoupled look-back,
 // Merrill & Garland). Each status is one 64-bit word {flag, value} written
@@ -18,10 +19,10 @@
 
 namespace wp {
 
-constexpr int kScanWaves = 4;
+constexpr int kScanWaves = 16;
 constexpr int kScanT = 64 * kScanWaves;
-constexpr int kScanRows = 4;
-constexpr uint32_t kTileInts = kScanT * kScanRows * 4;  // 4096
+constexpr int kRows1 = 4, kRows4 = 4;  // rows per tile for stride 1 and stride 4
+constexpr uint32_t tile_ints(uint32_t S) { return kScanT * 4u * (S == 1 ? kRows1 : kRows4); }
 constexpr uint64_t kFlagAgg = 1ull << 32;
 constexpr uint64_t kFlagInc = 2ull << 32;
 constexpr int kStatusWords = 8;  // per tile: aggregate[4], inclusive[4]
@@ -44,9 +45,12 @@ __global__ void k_fill_zero(uint64_t *__restrict__ p, uint64_t count)
 }
 
 // counter lives in status[0]; tile t's words at status[8 + 8t ...]
+template <uint32_t S>
 __global__ __launch_bounds__(kScanT) void k_delta_scan(uint32_t *__restrict__ data, uint64_t n, uint32_t init,
-                                                       uint32_t S, uint64_t *__restrict__ status)
+                                                       uint64_t *__restrict__ status)
 {
+    constexpr int kScanRows = S == 1 ? kRows1 : kRows4;
+    constexpr uint32_t kTileInts = tile_ints(S);
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_tot[kScanRows][kScanWaves][4];
     __shared__ uint32_t s_excl[4];
@@ -58,61 +62,74 @@ __global__ __launch_bounds__(kScanT) void k_delta_scan(uint32_t *__restrict__ da
     __syncthreads();
     const uint32_t tile = s_tile;
     const uint64_t t0 = (uint64_t)tile * kTileInts;
+    uint32_t *const tb = data + t0;  // uniform tile base; rows at 32-bit offsets
+    const bool full = t0 + kTileInts <= n;
     uint32_t v[kScanRows][4];
+    if (full) {
 #pragma unroll
-    for (int m = 0; m < kScanRows; ++m) {
-        const uint64_t g = t0 + (uint64_t)m * (kScanT * 4) + 4ull * tid;
-        if (g + 4 <= n) {
-            const uint4 x = *reinterpret_cast<const uint4 *>(data + g);
+        for (int m = 0; m < kScanRows; ++m) {
+            const uint4 x = *reinterpret_cast<const uint4 *>(tb + m * (kScanT * 4) + 4 * tid);
             v[m][0] = x.x, v[m][1] = x.y, v[m][2] = x.z, v[m][3] = x.w;
-        } else {
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                v[m][r] = (g + r < n) ? data[g + r] : 0u;
         }
+    } else {
+        const uint32_t left = (uint32_t)(n - t0);
+#pragma unroll
+        for (int m = 0; m < kScanRows; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t i = m * (kScanT * 4) + 4 * tid + r;
+                v[m][r] = i < left ? tb[i] : 0u;
+            }
     }
-    // local inclusive scans: per row, lane-serial then across the wavefront
-    uint32_t excl[kScanRows][4];
+    // local inclusive scans: per row, lane-serial then across the wavefront;
+    // the wavefront's exclusive prefix is folded in at once
 #pragma unroll
     for (int m = 0; m < kScanRows; ++m) {
-        if (S == 1) {
+        if constexpr (S == 1) {
             v[m][1] += v[m][0];
             v[m][2] += v[m][1];
             v[m][3] += v[m][2];
             const uint32_t incl = wave_scan_incl(v[m][3]);
-            excl[m][0] = incl - v[m][3];
+            const uint32_t ex = incl - v[m][3];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                v[m][r] += ex;
             if (lane == 63)
                 s_tot[m][wave][0] = incl;
         } else {
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const uint32_t incl = wave_scan_incl(v[m][c]);
-                excl[m][c] = incl - v[m][c];
+                v[m][c] = incl;
                 if (lane == 63)
                     s_tot[m][wave][c] = incl;
             }
         }
     }
     __syncthreads();
-    // prefix of earlier (row, wave) segments inside the tile, and the tile total
-    const int NC = S == 1 ? 1 : 4;
+    // add the earlier (row, wave) segments inside the tile: the rows x waves
+    // segment totals, in tile order, are exactly one wavefront's worth (64),
+    // so one wave scan per residue class gives every segment's offset
+    static_assert(kScanRows * kScanWaves == 64, "one segment per lane");
+    constexpr int NC = S == 1 ? 1 : 4;
     uint32_t agg[4] = {0, 0, 0, 0};
-    uint32_t seg_before[kScanRows][4] = {};
+#pragma unroll
     for (int c = 0; c < NC; ++c) {
-        uint32_t run = 0;
+        const uint32_t seg = (&s_tot[0][0][0])[lane * 4 + c];  // segment (lane / W, lane % W)
+        const uint32_t incl = wave_scan_incl(seg);
+        const uint32_t ex = incl - seg;
+        agg[c] = wave_read(incl, 63);
 #pragma unroll
         for (int m = 0; m < kScanRows; ++m) {
-            uint32_t row_all = 0, row_before = 0;
+            const uint32_t off = __builtin_amdgcn_readlane(ex, m * kScanWaves + (int)wave);
+            if constexpr (S == 1) {
 #pragma unroll
-            for (int w = 0; w < kScanWaves; ++w) {
-                const uint32_t t = s_tot[m][w][c];
-                row_before += (w < (int)wave) ? t : 0u;
-                row_all += t;
+                for (int r = 0; r < 4; ++r)
+                    v[m][r] += off;
+            } else {
+                v[m][c] += off;
             }
-            seg_before[m][c] = run + row_before;
-            run += row_all;
         }
-        agg[c] = run;
     }
     // publish and look back (wave 0)
     uint64_t *my = status + kStatusWords + (uint64_t)tile * kStatusWords;
@@ -189,28 +206,35 @@ __global__ __launch_bounds__(kScanT) void k_delta_scan(uint32_t *__restrict__ da
                 s_excl[c] = pre[c];
     }
     __syncthreads();
+    const uint32_t e0 = s_excl[0], e1 = s_excl[1], e2 = s_excl[2], e3 = s_excl[3];
 #pragma unroll
     for (int m = 0; m < kScanRows; ++m) {
-        const uint64_t g = t0 + (uint64_t)m * (kScanT * 4) + 4ull * tid;
-        uint32_t o[4];
-        if (S == 1) {
-            const uint32_t add = s_excl[0] + seg_before[m][0] + excl[m][0];
+        if constexpr (S == 1) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                o[r] = v[m][r] + add;
+                v[m][r] += e0;
         } else {
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                o[c] = v[m][c] + s_excl[c] + seg_before[m][c] + excl[m][c];
+            v[m][0] += e0;
+            v[m][1] += e1;
+            v[m][2] += e2;
+            v[m][3] += e3;
         }
-        if (g + 4 <= n) {
-            *reinterpret_cast<uint4 *>(data + g) = make_uint4(o[0], o[1], o[2], o[3]);
-        } else {
+    }
+    if (full) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (g + r < n)
-                    data[g + r] = o[r];
-        }
+        for (int m = 0; m < kScanRows; ++m)
+            *reinterpret_cast<uint4 *>(tb + m * (kScanT * 4) + 4 * tid) =
+                make_uint4(v[m][0], v[m][1], v[m][2], v[m][3]);
+    } else {
+        const uint32_t left = (uint32_t)(n - t0);
+#pragma unroll
+        for (int m = 0; m < kScanRows; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t i = m * (kScanT * 4) + 4 * tid + r;
+                if (i < left)
+                    tb[i] = v[m][r];
+            }
     }
 }
 
@@ -265,19 +289,25 @@ using namespace wp;
 
 namespace wp {
 
+// status words for n integers (sized for the smaller stride-4 tiles, so
+// one size fits both strides)
 uint64_t scan_status_words(uint64_t n)
 {
-    const uint64_t tiles = (n + kTileInts - 1) / kTileInts;
+    const uint64_t tiles = (n + tile_ints(4) - 1) / tile_ints(4);
     return (uint64_t)kStatusWords * (tiles + 1);
 }
 
 static int32_t launch_scan(uint32_t *data, uint64_t n, uint32_t init, uint32_t stride, uint64_t *status,
                            hipStream_t st)
 {
-    const uint64_t tiles = (n + kTileInts - 1) / kTileInts;
-    const uint64_t words = scan_status_words(n);
+    const uint32_t ti = tile_ints(stride);
+    const uint64_t tiles = (n + ti - 1) / ti;
+    const uint64_t words = (uint64_t)kStatusWords * (tiles + 1);
     hipLaunchKernelGGL(k_fill_zero, dim3((uint32_t)((words + 255) / 256)), dim3(256), 0, st, status, words);
-    hipLaunchKernelGGL(k_delta_scan, dim3((uint32_t)tiles), dim3(kScanT), 0, st, data, n, init, stride, status);
+    if (stride == 1)
+        hipLaunchKernelGGL(k_delta_scan<1>, dim3((uint32_t)tiles), dim3(kScanT), 0, st, data, n, init, status);
+    else
+        hipLaunchKernelGGL(k_delta_scan<4>, dim3((uint32_t)tiles), dim3(kScanT), 0, st, data, n, init, status);
     return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
 }
 
@@ -298,7 +328,7 @@ extern "C" int32_t delta_decode_inplace(uint32_t *data, uint64_t n, uint32_t ini
         return WP_OK;
     if (data == nullptr || !aligned16(data))
         return WP_ERR_INVALID_ARG;
-    const uint64_t tiles = (n + kTileInts - 1) / kTileInts;
+    const uint64_t tiles = (n + tile_ints(4) - 1) / tile_ints(4);
     if (tiles > 0x7FFFFFFFull)
         return WP_ERR_INVALID_ARG;
     hipStream_t st = as_stream(stream);
