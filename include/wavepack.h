@@ -125,9 +125,10 @@ int32_t delta_decode_inplace(uint32_t *data, uint64_t n, uint32_t init, int32_t 
  * must be 4 (each lane unpacks four integers of a block per pass); depth:
  * 16-byte loads per lane in flight (2, 3 or 4; 0 = 2); wg_per_cu: runs
  * per compute unit, 0..1024, which sets the run length (0 = 128; many
- * short runs let the hardware balance the load). Patched pages:
- * waves 4 or 8, vpl (integers per lane and pass) 4 or 8; depth and
- * wg_per_cu are ignored. Returns WP_ERR_INVALID_ARG for anything else. */
+ * short runs let the hardware balance the load). Patched pages: one
+ * workgroup per page, waves 2, 4 or 8 (each wavefront unpacks two blocks
+ * per pass), vpl 4; depth and wg_per_cu are ignored. Returns
+ * WP_ERR_INVALID_ARG for anything else. */
 int32_t wp_set_decode_tune(int32_t codec, int32_t waves, int32_t vpl, int32_t depth, int32_t wg_per_cu);
 
 /* Synchronises `stream`, then returns and clears this device's error word:
@@ -155,7 +156,7 @@ typedef struct wp_list {
 
 typedef struct wp_tune {
     int32_t waves;     /* wavefronts per workgroup: 2, 4 or 8 (0 = 4) */
-    int32_t vpl;       /* patched pages: integers per lane and pass, 4 or 8 (8 only with 2 or 4 waves; 0 = 4) */
+    int32_t vpl;       /* integers per lane and pass: 4 (0 = 4) */
     int32_t depth;     /* binary packing: 16-byte loads per lane in flight, 2, 3 or 4 (0 = 2) */
     int32_t run_units; /* meta-blocks per binary-packing work item (one wavefront), 1..63 (0 = 8) */
     int32_t wg_per_cu; /* persistent workgroups per compute unit, 0..64 (0 = 28 / waves) */

@@ -1,8 +1,8 @@
 """Autotuner for the decoders' workgroup shapes.
 
 Knobs:
-  waves      wavefronts per workgroup (binary packing 1, 2, 4, 8; patched 4, 8)
-  vpl        patched pages: integers per lane and pass (binary packing: 4)
+  waves      wavefronts per workgroup (binary packing 1, 2, 4, 8; patched 2, 4, 8)
+  vpl        integers per lane and pass (4)
   depth      binary packing: 16-byte loads in flight per lane, which also
              sizes each wavefront's LDS ring (2 or 3: 4 KB, 4: 8 KB)
   wg_per_cu  single list, binary packing: runs (one per wavefront) per
@@ -26,9 +26,9 @@ TUNING_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.j
 BP_SINGLE = [dict(waves=w, vpl=4, depth=d, wg_per_cu=c)
              for w in (1, 2, 4, 8) for d in (2, 3) for c in (28, 56, 128, 256)] + \
             [dict(waves=w, vpl=4, depth=4, wg_per_cu=c) for w in (1, 4) for c in (64, 128)]
-FP_SINGLE = [dict(waves=w, vpl=v) for (w, v) in ((4, 4), (4, 8), (8, 4), (8, 8))]
-BATCH = [dict(waves=w, vpl=v, depth=d, run_units=r, wg_per_cu=c, use_graph=1)
-         for (w, v) in ((2, 8), (4, 4), (4, 8), (8, 4)) for d in (2, 3)
+FP_SINGLE = [dict(waves=w, vpl=4) for w in (2, 4, 8)]
+BATCH = [dict(waves=w, vpl=4, depth=d, run_units=r, wg_per_cu=c, use_graph=1)
+         for w in (2, 4, 8) for d in (2, 3)
          for r in (2, 4, 8) for c in (0, 28 // w + 2)]
 
 
@@ -65,7 +65,7 @@ def apply(table: dict | None = None, arch_name: str = "gfx950"):
         lib().wp_set_decode_tune(CODEC_BP, bp["waves"], bp["vpl"], bp.get("depth", 0), bp.get("wg_per_cu", 0))
     fp = ent.get("fp_single")
     if fp:
-        lib().wp_set_decode_tune(CODEC_FP, fp["waves"], fp["vpl"], 0, 0)
+        lib().wp_set_decode_tune(CODEC_FP, fp["waves"], fp["vpl"], fp.get("depth", 0), 0)
 
 
 def batch_tune(table: dict | None = None, arch_name: str = "gfx950") -> dict | None:

@@ -40,10 +40,10 @@ union WaveItemLds {
 };
 
 // item: {list index, kind, first unit, unit count}
-template <int WAVES, int VPL, int DEPTH>
+template <int WAVES, int DEPTH>
 union BatchLds {
     WaveItemLds<DEPTH> w[WAVES];
-    FpLds<WAVES, VPL> fp;
+    FpLds<WAVES> fp;
 };
 
 __global__ void k_batch_reset(uint32_t *counter)
@@ -64,13 +64,13 @@ __device__ __forceinline__ bool item_header(const DevList *__restrict__ lists, c
                         Ld.codec == WP_CODEC_BP ? kBpBlocks : kFpBlocks, H);
 }
 
-template <int WAVES, int VPL, int DEPTH>
+template <int WAVES, int DEPTH>
 __global__ __launch_bounds__(64 * WAVES) void k_batch(const DevList *__restrict__ lists,
                                                       const uint4 *__restrict__ items, uint32_t npages,
                                                       uint32_t nitems, uint32_t *__restrict__ counter,
                                                       int *__restrict__ err)
 {
-    __shared__ BatchLds<WAVES, VPL, DEPTH> L;
+    __shared__ BatchLds<WAVES, DEPTH> L;
     __shared__ uint32_t s_item;
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = lane_id();
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch(const DevList *__restrict_
             const uint64_t left = H.nfull - u * kFpBlocks;
             const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
             ok = off >= H.dir_end && end >= off && end <= H.total && (off & 3u) == 0 &&
-                 fp_page<WAVES, VPL>(Ld.comp + off, end - off, nb, H.S, base, Ld.out + u * kFpUnitInts, L.fp);
+                 fp_page<WAVES>(Ld.comp + off, end - off, nb, H.S, base, Ld.out + u * kFpUnitInts, L.fp);
         }
         if (!ok && tid == 0)
             *err = kErrCorrupt;
@@ -161,33 +161,29 @@ struct Plan {
     int cus = 256;
 };
 
-template <int W, int V, int D>
+template <int W, int D>
 static const void *batch_kernel()
 {
-    return reinterpret_cast<const void *>(&k_batch<W, V, D>);
+    return reinterpret_cast<const void *>(&k_batch<W, D>);
 }
 
-template <int W, int V>
+template <int W>
 static const void *batch_kernel_depth(int depth)
 {
-    return depth == 2 ? batch_kernel<W, V, 2>() : depth == 3 ? batch_kernel<W, V, 3>() : batch_kernel<W, V, 4>();
+    return depth == 2 ? batch_kernel<W, 2>() : depth == 3 ? batch_kernel<W, 3>() : batch_kernel<W, 4>();
 }
 
-// waves x vpl shapes of the page decoder, each with ring depth 2..4
+// waves 2, 4 or 8 (vpl 4), each with ring depth 2..4
 static const void *pick_kernel(int waves, int vpl, int depth)
 {
-    if (depth < 2 || depth > 4)
+    if (depth < 2 || depth > 4 || vpl != 4)
         return nullptr;
-    if (waves == 2 && vpl == 4)
-        return batch_kernel_depth<2, 4>(depth);
-    if (waves == 2 && vpl == 8)
-        return batch_kernel_depth<2, 8>(depth);
-    if (waves == 4 && vpl == 4)
-        return batch_kernel_depth<4, 4>(depth);
-    if (waves == 4 && vpl == 8)
-        return batch_kernel_depth<4, 8>(depth);
-    if (waves == 8 && vpl == 4)
-        return batch_kernel_depth<8, 4>(depth);
+    if (waves == 2)
+        return batch_kernel_depth<2>(depth);
+    if (waves == 4)
+        return batch_kernel_depth<4>(depth);
+    if (waves == 8)
+        return batch_kernel_depth<8>(depth);
     return nullptr;
 }
 

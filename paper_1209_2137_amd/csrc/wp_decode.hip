@@ -57,19 +57,19 @@ __global__ __launch_bounds__(64 * WAVES) void k_bp_decode(const uint32_t *__rest
         *err = kErrCorrupt;
 }
 
-template <int WAVES, int VPL>
+template <int WAVES>
 union FpKernelLds {
-    FpLds<WAVES, VPL> fp;
+    FpLds<WAVES> fp;
     TailLds<WAVES> tail;
 };
 
 // One workgroup per page; the workgroup after the last page decodes the tail.
-template <int WAVES, int VPL>
+template <int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_fp_decode(const uint32_t *__restrict__ in, uint64_t in_words,
                                                           uint32_t *__restrict__ out, uint64_t n,
                                                           int *__restrict__ err)
 {
-    __shared__ FpKernelLds<WAVES, VPL> L;
+    __shared__ FpKernelLds<WAVES> L;
     ListHdr H;
     if (!check_header(in, in_words, n, kMagicFP, kFpBlocks, H)) {
         if (blockIdx.x == 0 && threadIdx.x == 0)
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_fp_decode(const uint32_t *__rest
         const uint64_t left = H.nfull - u * kFpBlocks;
         const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
         if (ok)
-            ok = fp_page<WAVES, VPL>(in + off, end - off, nb, H.S, base, out + u * kFpUnitInts, L.fp);
+            ok = fp_page<WAVES>(in + off, end - off, nb, H.S, base, out + u * kFpUnitInts, L.fp);
     }
     if (!ok && threadIdx.x == 0)
         *err = kErrCorrupt;
@@ -141,7 +141,7 @@ static bool valid_tune(int codec, int waves, int vpl)
 {
     if (codec == WP_CODEC_BP)
         return (waves == 1 || waves == 2 || waves == 4 || waves == 8) && vpl == 4;
-    return (waves == 4 || waves == 8) && (vpl == 4 || vpl == 8);
+    return (waves == 2 || waves == 4 || waves == 8) && vpl == 4;
 }
 
 template <int WAVES, int DEPTH>
@@ -152,12 +152,12 @@ static void launch_bp(uint64_t grid, hipStream_t st, const uint32_t *in, uint64_
                        in_words, out, n, err, upw);
 }
 
-template <int WAVES, int VPL>
+template <int WAVES>
 static void launch_fp(uint64_t grid, hipStream_t st, const uint32_t *in, uint64_t in_words, uint32_t *out,
                       uint64_t n, int *err)
 {
-    hipLaunchKernelGGL((k_fp_decode<WAVES, VPL>), dim3((uint32_t)grid), dim3(64 * WAVES), 0, st, in, in_words,
-                       out, n, err);
+    hipLaunchKernelGGL((k_fp_decode<WAVES>), dim3((uint32_t)grid), dim3(64 * WAVES), 0, st, in, in_words, out,
+                       n, err);
 }
 
 static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
@@ -209,14 +209,12 @@ static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, u
         grid = grid ? grid : 1;
         if (grid > 0x7FFFFFFFull)
             return WP_ERR_INVALID_ARG;
-        if (t.waves == 4 && t.vpl == 4)
-            launch_fp<4, 4>(grid, st, in, in_words, out, n, ds->err);
-        else if (t.waves == 4 && t.vpl == 8)
-            launch_fp<4, 8>(grid, st, in, in_words, out, n, ds->err);
-        else if (t.waves == 8 && t.vpl == 8)
-            launch_fp<8, 8>(grid, st, in, in_words, out, n, ds->err);
+        if (t.waves == 2)
+            launch_fp<2>(grid, st, in, in_words, out, n, ds->err);
+        else if (t.waves == 4)
+            launch_fp<4>(grid, st, in, in_words, out, n, ds->err);
         else
-            launch_fp<8, 4>(grid, st, in, in_words, out, n, ds->err);
+            launch_fp<8>(grid, st, in, in_words, out, n, ds->err);
     }
     return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
 }

@@ -116,6 +116,12 @@ __device__ __forceinline__ uint4 buf_load_u4(BufRsrc rs, uint32_t byte_off)
     return make_uint4(v.x, v.y, v.z, v.w);
 }
 
+__device__ __forceinline__ void buf_store_u4(BufRsrc rs, uint32_t byte_off, uint32_t soff, uint4 v)
+{
+    const u32x4_t w = {v.x, v.y, v.z, v.w};
+    __builtin_amdgcn_raw_buffer_store_b128(w, rs, (int)byte_off, (int)soff, 0);
+}
+
 // Stream header, read with uniform (scalar) loads.
 struct Hdr {
     uint32_t magic, n_lo, n_hi, stride, n_units, tail_bytes, tail_off, total;
@@ -265,10 +271,14 @@ __device__ __forceinline__ void unpack_lane(const uint32_t *words, uint32_t bit0
 // ------------------------------------------------------------------------
 // LDS arena shared by all roles (a workgroup plays one role at a time).
 
-template <int WAVES, int VPL>
+// Page tables of a patched page (shared by the encoder and the decoder)
+// plus, for the decoder, each wavefront's staging and transposition areas.
+template <int WAVES>
 struct FpLds {
-    uint4 pk[Geo<WAVES, VPL>::WPP / 4 + 1];             // staged packed words of one pass
-    alignas(16) uint32_t ptc[Geo<WAVES, VPL>::BPP * kBlock];  // patch area of one pass
+    uint32_t stage[WAVES][2 * kBlock + 4];  // a wavefront's two blocks of packed words (+1 word)
+    uint32_t xp[WAVES][2 * kBlock];         // a wavefront's two blocks, transposed and patched
+    uint4 rec[kFpBlocks];                   // per block: {b | k << 8 | c << 16, packed word offset,
+                                            //  bit offset of its first exception's high part, position offset}
     uint8_t b[kFpBlocks];
     uint8_t mb[kFpBlocks];
     uint8_t c[kFpBlocks];
@@ -423,8 +433,8 @@ __device__ bool decode_tail_entry(const uint32_t *__restrict__ in, const ListHdr
 // with the same k. Per-k totals accumulate in L.kcar (zeroed by the caller,
 // as is L.ktot). Rounds of T blocks; within a wavefront the same-k ranks
 // come from one masked scan per distinct k (ballot loop).
-template <int WAVES, int VPL>
-__device__ void fp_tables(FpLds<WAVES, VPL> &L, uint32_t &tot_words, uint32_t &tot_pos)
+template <int WAVES>
+__device__ void fp_tables(FpLds<WAVES> &L, uint32_t &tot_words, uint32_t &tot_pos)
 {
     constexpr int T = 64 * WAVES;
     const uint32_t tid = threadIdx.x;
@@ -501,13 +511,21 @@ __device__ void fp_tables(FpLds<WAVES, VPL> &L, uint32_t &tot_words, uint32_t &t
 // bytes and, per block, the index of its first exception inside its array
 // k = maxb - b (the paper appends exceptions to array k in block order, so
 // this is the number of exceptions of earlier blocks with the same k).
-// Then passes of BPP blocks: stage, unpack, patch, scan, store.
-template <int WAVES, int VPL>
+//
+// Then passes of 2 * WAVES blocks: wavefront w takes blocks 2w and 2w + 1
+// of the pass and unpacks them as the binary-packing decoder does (strided
+// fields, LDS transpose); its lanes each patch one exception (position
+// byte and k-bit high part, OR-ed in above bit b; a pair of blocks with
+// more than 64 exceptions patches the rest in a slower loop). Everything a
+// block needs is in one 16-byte record, and the packed words and
+// exceptions of the next pass are fetched into registers while the
+// current one is decoded; one barrier per pass hands the wavefront totals
+// over for the prefix sum.
+template <int WAVES>
 __device__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint32_t nb, uint32_t S,
-                        const uint32_t (&base)[4], uint32_t *__restrict__ out, FpLds<WAVES, VPL> &L)
+                        const uint32_t (&base)[4], uint32_t *__restrict__ out, FpLds<WAVES> &L)
 {
-    using G = Geo<WAVES, VPL>;
-    constexpr int T = G::T;
+    constexpr int T = 64 * WAVES;
     static_assert(T <= (int)kFpBlocks, "setup maps at most one thread per block and round");
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = lane_id();
@@ -571,7 +589,7 @@ __device__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint
             L.bad = 1;
     }
     uint32_t carry_w = 0, carry_p = 0;
-    fp_tables<WAVES, VPL>(L, carry_w, carry_p);
+    fp_tables<WAVES>(L, carry_w, carry_p);
     if (tid == 0) {
         L.blkoff[kFpBlocks] = carry_w;
         if (carry_w != packed_words || 3 * nb + carry_p != meta_bytes)
@@ -583,69 +601,179 @@ __device__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint
     if (L.bad)
         return false;
 
-    // passes of BPP blocks
-    const uint32_t *packed = page + hdr_w;
-    const uint32_t q = lane % G::LPB;
-    const uint32_t hb = wave * G::BPW + lane / G::LPB;  // block within the pass
-    const uint32_t *words = reinterpret_cast<const uint32_t *>(L.pk);
+    // block records
+    for (uint32_t t = tid; t < kFpBlocks; t += T) {
+        const uint32_t b = L.b[t], k = (uint32_t)L.mb[t] - b, c = L.c[t];
+        L.rec[t] = make_uint4(b | (k << 8) | (c << 16), L.blkoff[t], L.excbase[k <= 32 ? k : 0] * 32u + L.rank[t] * k,
+                              L.posoff[t]);
+    }
+    __syncthreads();
+
+    // passes of 2 * WAVES blocks
+    constexpr uint32_t BPP = 2 * WAVES;
+    const uint32_t q = lane & 31u;
+    const bool hi = lane >= 32u;
+    uint32_t *const stg = L.stage[wave];
+    uint32_t *const xpw = L.xp[wave];
+    uint32_t *const xw = &xpw[lane + (hi ? 96u : 0u)];
+    const uint4 *const xr = reinterpret_cast<const uint4 *>(&xpw[4 * lane]);
+    uint4 *const sw = reinterpret_cast<uint4 *>(&stg[4 * lane]);
+    const uint32_t pos_at = (hdr_w + packed_words) * 4u + 3u * nb;  // byte offset of the positions
+    const BufRsrc rpg = make_rsrc(page, nwords * 4u);
+    const BufRsrc rout = make_rsrc(out, nb * kBlock * 4u);
+    constexpr uint32_t kOut = 0xfffffff0u;  // a buffer offset beyond every page: reads nothing
+
+    // a wavefront's pair of blocks in pass p: both records (uniform), the
+    // pair's packed words, and exception e = lane of the pair (position
+    // byte, the two words holding its high part)
+    struct Fetch {
+        uint32_t a0, a2, b0, b2;  // record words 0 and 2 of the two blocks
+        uint4 pk;
+        uint32_t pos, lo, hi;
+    };
+    auto fetch = [&](uint32_t p) __attribute__((always_inline)) {
+        Fetch f;
+        const uint32_t jA = p * BPP + 2u * wave;
+        const uint4 ra = jA < nb ? L.rec[jA] : make_uint4(0u, 0u, 0u, 0u);
+        const uint4 rb = jA + 1u < nb ? L.rec[jA + 1u] : make_uint4(0u, 0u, 0u, 0u);
+        f.a0 = uniform(ra.x);
+        f.a2 = uniform(ra.z);
+        f.b0 = uniform(rb.x);
+        f.b2 = uniform(rb.z);
+        const uint32_t pa = uniform(ra.w), pbb = uniform(rb.w);
+        const uint32_t bA = f.a0 & 255u, bB = f.b0 & 255u, cA = f.a0 >> 16, cB = f.b0 >> 16;
+        const BufRsrc rp = make_rsrc(page + hdr_w + uniform(ra.y), 16u * (bA + bB));
+        f.pk = buf_load_u4(rp, lane * 16u);
+        const bool inA = lane < cA, inB = !inA && lane < cA + cB;
+        const uint32_t idx = inA ? lane : lane - cA;
+        const uint32_t k = ((inA ? f.a0 : f.b0) >> 8) & 255u;
+        const uint32_t bit = (inA ? f.a2 : f.b2) + idx * k;
+        const uint32_t poff = (inA || inB) ? pos_at + (inA ? pa : pbb) + idx : kOut;
+        const uint32_t woff = (inA || inB) ? (bit >> 5) * 4u : kOut;
+        f.pos = __builtin_amdgcn_raw_buffer_load_b8(rpg, (int)poff, 0, 0);
+        f.lo = buf_load_u32(rpg, woff);
+        f.hi = buf_load_u32(rpg, woff + 4u);
+        return f;
+    };
+    // exception e (any index) of the pair whose records are r0/r2 (A) and
+    // s0/s2 (B): target block, shift, high part
+    auto exc_of = [&](const Fetch &f, uint32_t e, uint32_t lo, uint32_t hw, uint32_t &blk, uint32_t &b)
+        __attribute__((always_inline)) {
+        const uint32_t cA = f.a0 >> 16;
+        const bool inA = e < cA;
+        const uint32_t w0 = inA ? f.a0 : f.b0;
+        const uint32_t idx = inA ? e : e - cA;
+        const uint32_t k = (w0 >> 8) & 255u;
+        const uint32_t bit = (inA ? f.a2 : f.b2) + idx * k;
+        blk = inA ? 0u : 1u;
+        b = w0 & 255u;
+        return __builtin_amdgcn_alignbit(hw, lo, bit) & width_mask(k);
+    };
+
     uint32_t carry[4] = {base[0], base[1], base[2], base[3]};
-    const uint32_t npass = (nb + G::BPP - 1) / G::BPP;
+    const uint32_t npass = (nb + BPP - 1) / BPP;
+    Fetch cur = fetch(0);
     for (uint32_t p = 0; p < npass; ++p) {
-        const uint32_t f = p * G::BPP;
-        const uint32_t last = f + G::BPP < nb ? f + G::BPP : nb;
-        const uint32_t w0 = L.blkoff[f];
-        const uint32_t w1 = last < nb ? L.blkoff[last] : packed_words;
-        const uint4 *src = reinterpret_cast<const uint4 *>(packed + w0);
-        const uint32_t n4 = (w1 - w0) / 4;
+        const Fetch f = cur;
+        cur = fetch(p + 1);  // beyond the page it reads nothing
+        const uint32_t jA = p * BPP + 2u * wave;
+        const uint32_t bA = f.a0 & 255u, bB = f.b0 & 255u, cA = f.a0 >> 16, cB = f.b0 >> 16;
+        *sw = f.pk;
+        wave_lds_order();
+        const uint32_t b = hi ? bB : bA;
+        const uint32_t qb = q * b;
+        const uint32_t w0 = (hi ? 4u * bA : 0u) + (qb >> 5);
+        const uint32_t mask = width_mask(b);
+        uint32_t v[4];
 #pragma unroll
-        for (int r = 0; r < G::U4PT; ++r) {
-            const uint32_t i = tid + r * T;
-            if (i < n4)
-                L.pk[i] = src[i];
+        for (int m = 0; m < 4; ++m) {
+            const uint32_t wi = w0 + m * b;
+            v[m] = __builtin_amdgcn_alignbit(stg[wi + 1], stg[wi], qb) & mask;
         }
-        __syncthreads();
-        const uint32_t j = f + hb;
-        const bool live = j < nb;
-        const uint32_t b = live ? L.b[j] : 0u;
-        uint32_t v[VPL];
-        unpack_lane<VPL>(words, (live ? L.blkoff[j] - w0 : 0u) * 32 + VPL * q * b, b, v);
-        // exceptions: values go through LDS so that any lane can patch any position
-        uint32_t *pt = L.ptc + hb * kBlock;
-        store_lane<VPL>(pt + VPL * q, v);
-        __syncthreads();
-        const uint32_t c = live ? L.c[j] : 0u;
-        if (c) {
-            const uint32_t k = (uint32_t)L.mb[j] - b;
-            const uint32_t kmask = width_mask(k);
-            const uint32_t rk = L.rank[j];
-            const uint8_t *pos = meta + 3 * nb + L.posoff[j];
-            const uint32_t *arr = page + L.excbase[k];
-            for (uint32_t e = q; e < c; e += G::LPB) {
-                const uint32_t at = pos[e] & (kBlock - 1);
-                if (pos[e] >= kBlock || (e > 0 && pos[e - 1] >= pos[e]))
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            xw[32 * m] = v[m];
+        wave_lds_order();
+        // exceptions: one per lane, the rest (more than 64 in the pair) in rounds
+        const uint32_t ce = cA + cB;
+        {
+            const uint32_t prev = __shfl_up(f.pos, 1);
+            if (lane < ce) {
+                uint32_t blk, eb;
+                const uint32_t hv = exc_of(f, lane, f.lo, f.hi, blk, eb);
+                if (f.pos >= kBlock || (lane != 0 && lane != cA && prev >= f.pos))
                     L.bad = 1;
-                const uint32_t bit = (rk + e) * k;
-                const uint32_t wi = bit >> 5;
-                const uint32_t lo = arr[wi];
-                const uint32_t hi = ((bit & 31u) + k > 32u) ? arr[wi + 1] : 0u;
-                const uint32_t hv = __builtin_amdgcn_alignbit(hi, lo, bit) & kmask;
-                pt[at] |= hv << b;
+                atomicOr(&xpw[blk * kBlock + (f.pos & (kBlock - 1u))], hv << eb);
             }
         }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < VPL; r += 4) {
-            const uint4 x = *reinterpret_cast<const uint4 *>(pt + VPL * q + r);
-            v[r] = x.x;
-            v[r + 1] = x.y;
-            v[r + 2] = x.z;
-            v[r + 3] = x.w;
+        for (uint32_t e0 = 64; e0 < ce; e0 += 64) {
+            const uint32_t e = e0 + lane;
+            if (e < ce) {
+                const bool inA = e < cA;
+                const uint32_t idx = inA ? e : e - cA;
+                const uint32_t k = ((inA ? f.a0 : f.b0) >> 8) & 255u;
+                const uint32_t bit = (inA ? f.a2 : f.b2) + idx * k;
+                const uint8_t *pb = reinterpret_cast<const uint8_t *>(page) + pos_at +
+                                    (inA ? L.rec[jA].w : L.rec[jA + 1u].w) + idx;
+                const uint32_t pos = pb[0], pprev = idx > 0 ? pb[-1] : 0u;
+                const uint32_t lo = page[bit >> 5];
+                const uint32_t hw = (bit & 31u) + k > 32u ? page[(bit >> 5) + 1u] : 0u;
+                uint32_t blk, eb;
+                const uint32_t hv = exc_of(f, e, lo, hw, blk, eb);
+                if (pos >= kBlock || (idx > 0 && pprev >= pos))
+                    L.bad = 1;
+                atomicOr(&xpw[blk * kBlock + (pos & (kBlock - 1u))], hv << eb);
+            }
         }
-        scan_pass<WAVES, VPL>(v, S, carry, L.wtot[p & 1]);
-        if (live)
-            store_lane<VPL>(out + j * kBlock + VPL * q, v);
+        wave_lds_order();
+        const uint4 tq = *xr;
+        uint32_t x[4] = {tq.x, tq.y, tq.z, tq.w};
+        // prefix sum: inside the wavefront, then across wavefronts
+        uint32_t tot[4] = {0u, 0u, 0u, 0u};
+        if (S == 1) {
+            x[1] += x[0];
+            x[2] += x[1];
+            x[3] += x[2];
+            const uint32_t incl = wave_scan_incl(x[3]);
+            const uint32_t ex = incl - x[3];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                x[r] += ex;
+            tot[0] = wave_read(incl, 63);
+        } else if (S == 4) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const uint32_t incl = wave_scan_incl(x[c]);
+                x[c] = incl;
+                tot[c] = wave_read(incl, 63);
+            }
+        }
+        if (S != 0 && lane == 0)
+            *reinterpret_cast<uint4 *>(&L.wtot[p & 1][wave][0]) = make_uint4(tot[0], tot[1], tot[2], tot[3]);
+        __syncthreads();
+        if (S != 0) {
+            uint32_t before[4] = {0u, 0u, 0u, 0u}, all[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) {
+                const uint4 tw = *reinterpret_cast<const uint4 *>(&L.wtot[p & 1][w][0]);
+                const uint32_t tv[4] = {tw.x, tw.y, tw.z, tw.w};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    before[c] += w < (int)wave ? tv[c] : 0u;
+                    all[c] += tv[c];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                x[r] += carry[S == 1 ? 0 : r] + before[S == 1 ? 0 : r];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                carry[c] += all[c];
+        }
+        buf_store_u4(rout, lane * 16u, uniform(jA * (kBlock * 4u)), make_uint4(x[0], x[1], x[2], x[3]));
     }
-    return true;
+    __syncthreads();
+    return L.bad == 0;
 }
 
 // ------------------------------------------------------------------------
@@ -662,12 +790,6 @@ constexpr uint32_t pow2ceil(uint32_t x)
     while (p < x)
         p <<= 1;
     return p;
-}
-
-__device__ __forceinline__ void buf_store_u4(BufRsrc rs, uint32_t byte_off, uint32_t soff, uint4 v)
-{
-    const u32x4_t w = {v.x, v.y, v.z, v.w};
-    __builtin_amdgcn_raw_buffer_store_b128(w, rs, (int)byte_off, (int)soff, 0);
 }
 
 // Binary packing, one wavefront per run of meta-blocks (Section 6.2 format,

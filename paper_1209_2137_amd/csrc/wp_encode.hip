@@ -223,7 +223,7 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
                                                  const uint32_t *__restrict__ incl, uint32_t dir_end,
                                                  uint32_t *__restrict__ out)
 {
-    __shared__ FpLds<8, 4> L;
+    __shared__ FpLds<8> L;
     constexpr int T = 512;
     const uint64_t p = blockIdx.x;
     const uint32_t tid = threadIdx.x;
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
         L.kcar[tid] = 0;
     __syncthreads();
     uint32_t packed_words = 0, npos = 0;
-    fp_tables<8, 4>(L, packed_words, npos);
+    fp_tables<8>(L, packed_words, npos);
     // per-k counts are in L.kcar; exception array offsets from the page start
     uint32_t bitset = 0;
     for (uint32_t k = 1; k <= 32; ++k)
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
         mbytes[nb + t] = L.mb[t];
         mbytes[2 * nb + t] = L.c[t];
     }
-    uint32_t *sw = L.ptc + wave * kBlock;
+    uint32_t *sw = L.xp[wave];
     const uint32_t rounds = (nb + 7) / 8;
     for (uint32_t it = 0; it < rounds; ++it) {
         const uint32_t t = it * 8 + wave;

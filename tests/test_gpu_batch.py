@@ -16,10 +16,10 @@ pytestmark = pytest.mark.gpu
 TUNES = [
     dict(waves=4, vpl=4, depth=2, run_units=8, wg_per_cu=4, use_graph=1),
     dict(waves=4, vpl=4, depth=2, run_units=8, wg_per_cu=4, use_graph=0),
-    dict(waves=2, vpl=8, depth=3, run_units=1, wg_per_cu=8, use_graph=1),
+    dict(waves=2, vpl=4, depth=3, run_units=1, wg_per_cu=8, use_graph=1),
     dict(waves=2, vpl=4, depth=4, run_units=63, wg_per_cu=16, use_graph=1),
-    dict(waves=4, vpl=8, depth=2, run_units=5, wg_per_cu=2, use_graph=0),
-    dict(waves=8, vpl=4, depth=3, run_units=16, wg_per_cu=2, use_graph=1),
+    dict(waves=8, vpl=4, depth=2, run_units=5, wg_per_cu=2, use_graph=0),
+    dict(waves=8, vpl=4, depth=3, run_units=16, wg_per_cu=0, use_graph=1),
 ]
 
 

@@ -20,7 +20,7 @@ CANARY = 0x5A5A5A5A
 PAD = 64
 # (waves, vpl, runs or workgroups per CU, depth)
 BP_TUNES = [(4, 4, 28, 2), (1, 4, 4, 3), (2, 4, 64, 4), (8, 4, 16, 2), (4, 4, 1, 3)]
-FP_TUNES = [(8, 4, 0, 0), (4, 4, 0, 0), (4, 8, 0, 0), (8, 8, 0, 0)]
+FP_TUNES = [(8, 4, 0, 0), (4, 4, 0, 0), (2, 4, 0, 0)]
 
 
 @pytest.fixture(scope="module", autouse=True)
