@@ -98,7 +98,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch(const DevList *__restrict_
             const uint64_t left = H.nfull - u * kFpBlocks;
             const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
             ok = off >= H.dir_end && end >= off && end <= H.total && (off & 3u) == 0 &&
-                 fp_page<WAVES>(Ld.comp + off, end - off, nb, H.S, base, Ld.out + u * kFpUnitInts, L.fp);
+                 (H.S == 1   ? fp_page<WAVES, 1>(Ld.comp + off, end - off, nb, base, Ld.out + u * kFpUnitInts, L.fp)
+                  : H.S == 4 ? fp_page<WAVES, 4>(Ld.comp + off, end - off, nb, base, Ld.out + u * kFpUnitInts, L.fp)
+                             : fp_page<WAVES, 0>(Ld.comp + off, end - off, nb, base, Ld.out + u * kFpUnitInts, L.fp));
         }
         if (!ok && tid == 0)
             *err = kErrCorrupt;

@@ -91,7 +91,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_fp_decode(const uint32_t *__rest
         const uint64_t left = H.nfull - u * kFpBlocks;
         const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
         if (ok)
-            ok = fp_page<WAVES>(in + off, end - off, nb, H.S, base, out + u * kFpUnitInts, L.fp);
+            ok = H.S == 1 ? fp_page<WAVES, 1>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp)
+               : H.S == 4 ? fp_page<WAVES, 4>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp)
+                          : fp_page<WAVES, 0>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp);
     }
     if (!ok && threadIdx.x == 0)
         *err = kErrCorrupt;

@@ -521,8 +521,8 @@ __device__ void fp_tables(FpLds<WAVES> &L, uint32_t &tot_words, uint32_t &tot_po
 // exceptions of the next pass are fetched into registers while the
 // current one is decoded; one barrier per pass hands the wavefront totals
 // over for the prefix sum.
-template <int WAVES>
-__device__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint32_t nb, uint32_t S,
+template <int WAVES, uint32_t S>
+__device__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint32_t nb,
                         const uint32_t (&base)[4], uint32_t *__restrict__ out, FpLds<WAVES> &L)
 {
     constexpr int T = 64 * WAVES;
@@ -672,10 +672,10 @@ __device__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint
 
     uint32_t carry[4] = {base[0], base[1], base[2], base[3]};
     const uint32_t npass = (nb + BPP - 1) / BPP;
-    Fetch cur = fetch(0);
-    for (uint32_t p = 0; p < npass; ++p) {
-        const Fetch f = cur;
-        cur = fetch(p + 1);  // beyond the page it reads nothing
+    // pass p from slot f; the slot is refilled with pass p + 2 as soon as
+    // its packed words and exceptions have been used (two named slots, so
+    // nothing is copied between passes)
+    auto run_pass = [&](uint32_t p, Fetch &f) __attribute__((always_inline)) {
         const uint32_t jA = p * BPP + 2u * wave;
         const uint32_t bA = f.a0 & 255u, bB = f.b0 & 255u, cA = f.a0 >> 16, cB = f.b0 >> 16;
         *sw = f.pk;
@@ -725,53 +725,64 @@ __device__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint
                 atomicOr(&xpw[blk * kBlock + (pos & (kBlock - 1u))], hv << eb);
             }
         }
+        f = fetch(p + 2);  // beyond the page it reads nothing
         wave_lds_order();
         const uint4 tq = *xr;
         uint32_t x[4] = {tq.x, tq.y, tq.z, tq.w};
         // prefix sum: inside the wavefront, then across wavefronts
-        uint32_t tot[4] = {0u, 0u, 0u, 0u};
-        if (S == 1) {
+        if constexpr (S == 1) {
             x[1] += x[0];
             x[2] += x[1];
             x[3] += x[2];
             const uint32_t incl = wave_scan_incl(x[3]);
-            const uint32_t ex = incl - x[3];
+            if (lane == 63)
+                L.wtot[p & 1][wave][0] = incl;
+            __syncthreads();
+            uint32_t before = carry[0], all = 0;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) {
+                const uint32_t tw = uniform(L.wtot[p & 1][w][0]);
+                before += w < (int)wave ? tw : 0u;
+                all += tw;
+            }
+            const uint32_t add = incl - x[3] + before;
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                x[r] += ex;
-            tot[0] = wave_read(incl, 63);
-        } else if (S == 4) {
+                x[r] += add;
+            carry[0] += all;
+        } else if constexpr (S == 4) {
+            uint32_t incl[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const uint32_t incl = wave_scan_incl(x[c]);
-                x[c] = incl;
-                tot[c] = wave_read(incl, 63);
-            }
-        }
-        if (S != 0 && lane == 0)
-            *reinterpret_cast<uint4 *>(&L.wtot[p & 1][wave][0]) = make_uint4(tot[0], tot[1], tot[2], tot[3]);
-        __syncthreads();
-        if (S != 0) {
-            uint32_t before[4] = {0u, 0u, 0u, 0u}, all[4] = {0u, 0u, 0u, 0u};
+            for (int c = 0; c < 4; ++c)
+                incl[c] = wave_scan_incl(x[c]);
+            if (lane == 63)
+                *reinterpret_cast<uint4 *>(&L.wtot[p & 1][wave][0]) = make_uint4(incl[0], incl[1], incl[2], incl[3]);
+            __syncthreads();
+            uint32_t before[4] = {carry[0], carry[1], carry[2], carry[3]};
 #pragma unroll
             for (int w = 0; w < WAVES; ++w) {
                 const uint4 tw = *reinterpret_cast<const uint4 *>(&L.wtot[p & 1][w][0]);
-                const uint32_t tv[4] = {tw.x, tw.y, tw.z, tw.w};
+                const uint32_t tv[4] = {uniform(tw.x), uniform(tw.y), uniform(tw.z), uniform(tw.w)};
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     before[c] += w < (int)wave ? tv[c] : 0u;
-                    all[c] += tv[c];
+                    carry[c] += tv[c];
                 }
             }
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                x[r] += carry[S == 1 ? 0 : r] + before[S == 1 ? 0 : r];
-#pragma unroll
             for (int c = 0; c < 4; ++c)
-                carry[c] += all[c];
+                x[c] = incl[c] + before[c];
         }
         buf_store_u4(rout, lane * 16u, uniform(jA * (kBlock * 4u)), make_uint4(x[0], x[1], x[2], x[3]));
+    };
+    Fetch f0 = fetch(0), f1 = fetch(1);
+    uint32_t p = 0;
+    for (; p + 2 <= npass; p += 2) {
+        run_pass(p, f0);
+        run_pass(p + 1, f1);
     }
+    if (p < npass)
+        run_pass(p, f0);
     __syncthreads();
     return L.bad == 0;
 }
