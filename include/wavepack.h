@@ -142,8 +142,10 @@ const char *wp_strerror(int32_t code);
 /* Batched decoding of many lists in one launch (not in the paper: the GPU
  * counterpart of decoding many posting lists). A plan turns a list
  * registry into work items -- patched pages, runs of meta-blocks and
- * tails -- that a persistent kernel pulls from atomic counters: pages by
- * whole workgroups first, then runs and tails by single wavefronts. */
+ * tails of lists without full blocks -- that a persistent kernel pulls
+ * from atomic counters: pages by whole workgroups first, then runs and
+ * tails by single wavefronts. The item holding a list's last unit also
+ * decodes the list's tail. */
 
 typedef struct wp_list {
     uint64_t comp_off_words; /* stream start, in words from `pool` (multiple of 4) */
@@ -165,8 +167,8 @@ typedef struct wp_tune {
 
 /* Builds a plan: validates the registry on the host (codec, alignment of
  * comp_off_words and out_off to 4 words, comp_words >= 8), cuts every list
- * into work items (runs of run_units meta-blocks, single pages, tails;
- * largest first), uploads the list and item arrays (it synchronises
+ * into work items (runs of run_units meta-blocks, single pages, tails
+ * of lists without full blocks; largest first), uploads the list and item arrays (it synchronises
  * `stream` once), and, when tune->use_graph, builds and instantiates a
  * hipGraph of the counter reset and the persistent decoder. `pool` and
  * `out_base` (device, 16-byte aligned) are kept; h_lists may be freed on

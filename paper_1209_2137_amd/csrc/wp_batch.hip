@@ -2,8 +2,9 @@
 //
 // The host planner cuts every list into work items: single pages
 // (patched), runs of up to `run_units` meta-blocks (binary packing) and
-// the Variable Byte tails; pages first, then runs longest first, then
-// tails. A persistent grid works through them in two phases: whole
+// the Variable Byte tails of lists without full blocks; pages first, then
+// runs longest first, then tails. Other tails are decoded by the item that
+// holds the list's last unit. A persistent grid works through them in two phases: whole
 // workgroups take pages from a first atomic counter (a page needs the
 // workgroup's barriers); once pages run out, every wavefront takes runs
 // and tails by itself from a second counter, with no barrier at all.
@@ -44,6 +45,7 @@ template <int WAVES, int DEPTH>
 union BatchLds {
     WaveItemLds<DEPTH> w[WAVES];
     FpLds<WAVES> fp;
+    TailLds<WAVES> tail;
 };
 
 __global__ void k_batch_reset(uint32_t *counter)
@@ -101,6 +103,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch(const DevList *__restrict_
                  (H.S == 1   ? fp_page<WAVES, 1>(Ld.comp + off, end - off, nb, base, Ld.out + u * kFpUnitInts, L.fp)
                   : H.S == 4 ? fp_page<WAVES, 4>(Ld.comp + off, end - off, nb, base, Ld.out + u * kFpUnitInts, L.fp)
                              : fp_page<WAVES, 0>(Ld.comp + off, end - off, nb, base, Ld.out + u * kFpUnitInts, L.fp));
+            // the list's last page also decodes its tail
+            if (u + 1 == H.units && H.tail) {
+                __syncthreads();
+                ok = decode_tail_entry<WAVES>(Ld.comp, H, Ld.out, L.tail) && ok;
+            }
         }
         if (!ok && tid == 0)
             *err = kErrCorrupt;
@@ -129,6 +136,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch(const DevList *__restrict_
                     ok = H.S == 1   ? bp_wave_run<DEPTH, 1>(Ld.comp, H, first, count, Ld.out, W.r)
                          : H.S == 4 ? bp_wave_run<DEPTH, 4>(Ld.comp, H, first, count, Ld.out, W.r)
                                     : bp_wave_run<DEPTH, 0>(Ld.comp, H, first, count, Ld.out, W.r);
+                // the list's last run also decodes its tail
+                if (ok && first + count == H.units && H.tail) {
+                    wave_lds_order();
+                    ok = decode_tail_entry<1, false>(Ld.comp, H, Ld.out, W.tail);
+                }
             } else {
                 ok = item.y == kItemTail && H.tail != 0 && decode_tail_entry<1, false>(Ld.comp, H, Ld.out, W.tail);
             }
@@ -283,7 +295,9 @@ static bool build_items(const uint32_t *pool, uint32_t *out_base, const wp_list 
             for (uint64_t u = 0; u < units; ++u)
                 fp_items.push_back(make_uint4(li, kItemFpPage, (uint32_t)u, 1));
         }
-        if (l.n % kBlock)
+        // a tail has an item of its own only in a list without full blocks;
+        // otherwise the list's last run or page decodes it
+        if ((l.n % kBlock) && nfull == 0)
             tail_items.push_back(make_uint4(li, kItemTail, 0, 0));
     }
     if (nlists > 0xFFFFFFFFull)

@@ -425,8 +425,8 @@ __device__ bool decode_tail_entry(const uint32_t *__restrict__ in, const ListHdr
 }
 
 // Tables of a patched page from its per-block metadata L.b, L.mb, L.c
-// (entries beyond the page's blocks hold 0): block offsets in the packed
-// region (exclusive sum of 4*b), offsets into the position bytes
+// (entries from nb to the end of its last round of T blocks hold 0): block
+// offsets in the packed region (exclusive sum of 4*b), offsets into the position bytes
 // (exclusive sum of c) and, per block, the index of its first exception in
 // array k = maxb - b -- exceptions are appended to their array in block
 // order (Section 5), so this is the number of exceptions of earlier blocks
@@ -434,14 +434,14 @@ __device__ bool decode_tail_entry(const uint32_t *__restrict__ in, const ListHdr
 // as is L.ktot). Rounds of T blocks; within a wavefront the same-k ranks
 // come from one masked scan per distinct k (ballot loop).
 template <int WAVES>
-__device__ void fp_tables(FpLds<WAVES> &L, uint32_t &tot_words, uint32_t &tot_pos)
+__device__ void fp_tables(FpLds<WAVES> &L, uint32_t nb, uint32_t &tot_words, uint32_t &tot_pos)
 {
     constexpr int T = 64 * WAVES;
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = lane_id();
     const uint32_t wave = uniform(tid >> 6);
     uint32_t carry_w = 0, carry_p = 0;
-    for (uint32_t r0 = 0; r0 < kFpBlocks; r0 += T) {
+    for (uint32_t r0 = 0; r0 < nb; r0 += T) {
         const uint32_t t = r0 + tid;
         const uint32_t bw = 4u * L.b[t];
         const uint32_t cc = L.c[t];
@@ -568,7 +568,8 @@ __device__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint
         if (lane == 0)
             L.bad = (anybad != 0 || exc_at + tot != nwords) ? 1u : 0u;
     }
-    for (uint32_t t = tid; t < kFpBlocks; t += T) {
+    const uint32_t nbr = ((nb + T - 1) / T) * T;  // the rounds of the table pass (entries beyond nb are 0)
+    for (uint32_t t = tid; t < nbr; t += T) {
         uint32_t b = 0, mb = 0, c = 0;
         if (t < nb) {
             b = meta[t];
@@ -589,7 +590,7 @@ __device__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint
             L.bad = 1;
     }
     uint32_t carry_w = 0, carry_p = 0;
-    fp_tables<WAVES>(L, carry_w, carry_p);
+    fp_tables<WAVES>(L, nb, carry_w, carry_p);
     if (tid == 0) {
         L.blkoff[kFpBlocks] = carry_w;
         if (carry_w != packed_words || 3 * nb + carry_p != meta_bytes)
@@ -602,7 +603,7 @@ __device__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint
         return false;
 
     // block records
-    for (uint32_t t = tid; t < kFpBlocks; t += T) {
+    for (uint32_t t = tid; t < nb; t += T) {
         const uint32_t b = L.b[t], k = (uint32_t)L.mb[t] - b, c = L.c[t];
         L.rec[t] = make_uint4(b | (k << 8) | (c << 16), L.blkoff[t], L.excbase[k <= 32 ? k : 0] * 32u + L.rank[t] * k,
                               L.posoff[t]);

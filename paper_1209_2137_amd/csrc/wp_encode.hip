@@ -244,7 +244,7 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
         L.kcar[tid] = 0;
     __syncthreads();
     uint32_t packed_words = 0, npos = 0;
-    fp_tables<8>(L, packed_words, npos);
+    fp_tables<8>(L, nb, packed_words, npos);
     // per-k counts are in L.kcar; exception array offsets from the page start
     uint32_t bitset = 0;
     for (uint32_t k = 1; k <= 32; ++k)
