@@ -40,7 +40,7 @@ union WaveItemLds {
     TailLds<1> tail;
 };
 
-// item: {list index, kind, first unit, unit count}
+// item: {list index, kind, first unit, unit count (pages: the page's blocks)}
 template <int WAVES, int DEPTH>
 union BatchLds {
     WaveItemLds<DEPTH> w[WAVES];
@@ -48,10 +48,17 @@ union BatchLds {
     TailLds<WAVES> tail;
 };
 
+// Work counters: kCounters per phase, kCounterStride words apart (one
+// 64-byte line each), so the claims of different workgroups spread over
+// several addresses. Workgroup g uses counter g % min(kCounters, grid),
+// which hands out that class's items c, c + C, c + 2C, ...
+constexpr uint32_t kCounters = 8, kCounterStride = 16;
+constexpr uint32_t kCounterWords = 2 * kCounters * kCounterStride;
+
 __global__ void k_batch_reset(uint32_t *counter)
 {
-    counter[0] = 0;
-    counter[1] = 0;
+    if (threadIdx.x < 2 * kCounters)
+        counter[threadIdx.x * kCounterStride] = 0;
 }
 
 // Header check of item `it`'s list; uniform.
@@ -66,25 +73,41 @@ __device__ __forceinline__ bool item_header(const DevList *__restrict__ lists, c
                         Ld.codec == WP_CODEC_BP ? kBpBlocks : kFpBlocks, H);
 }
 
+// grabs: items claimed per atomic, pages in the low 16 bits and runs and
+// tails in the high 16 bits (claiming several items at a time divides the
+// traffic on the counters)
 template <int WAVES, int DEPTH>
 __global__ __launch_bounds__(64 * WAVES) void k_batch(const DevList *__restrict__ lists,
                                                       const uint4 *__restrict__ items, uint32_t npages,
-                                                      uint32_t nitems, uint32_t *__restrict__ counter,
+                                                      uint32_t nitems, uint32_t grabs, uint32_t *__restrict__ counter,
                                                       int *__restrict__ err)
 {
+    const uint32_t grab_p = grabs & 0xffffu, grab_w = grabs >> 16;
+    const uint32_t nc = gridDim.x < kCounters ? gridDim.x : kCounters;
+    const uint32_t cls = blockIdx.x % nc;
+    uint32_t *const cnt_p = counter + cls * kCounterStride;
+    uint32_t *const cnt_w = counter + (kCounters + cls) * kCounterStride;
     __shared__ BatchLds<WAVES, DEPTH> L;
     __shared__ uint32_t s_item;
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = lane_id();
-    // phase 1: pages, one workgroup each
+    // phase 1: pages, one workgroup each: this class's pages cls + nc * k
+    uint32_t k = 0, k_end = 0;
     while (npages > 0) {
-        if (tid == 0)
-            s_item = atomicAdd(&counter[0], 1u);
-        __syncthreads();
-        const uint32_t it = uniform(s_item);
-        __syncthreads();
-        if (it >= npages)
+        if (k + 1 < k_end) {
+            ++k;
+        } else {
+            if (tid == 0)
+                s_item = atomicAdd(cnt_p, grab_p);
+            __syncthreads();
+            k = uniform(s_item);
+            k_end = k + grab_p;
+            __syncthreads();
+        }
+        const uint64_t it64 = (uint64_t)cls + (uint64_t)nc * k;
+        if (it64 >= npages)
             break;
+        const uint32_t it = (uint32_t)it64;
         uint4 item;
         DevList Ld;
         ListHdr H;
@@ -117,13 +140,23 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch(const DevList *__restrict_
     // LDS slice; the page phase's last barrier is behind every wavefront)
     const uint32_t wave = uniform(tid >> 6);
     WaveItemLds<DEPTH> &W = L.w[wave];
+    const uint32_t nw = nitems - npages;
+    k = 0;
+    k_end = 0;
     for (;;) {
-        uint32_t got = 0;
-        if (lane == 0)
-            got = atomicAdd(&counter[1], 1u);
-        const uint32_t it = npages + wave_read(got, 0);
-        if (it >= nitems)
+        if (k + 1 < k_end) {
+            ++k;
+        } else {
+            uint32_t got = 0;
+            if (lane == 0)
+                got = atomicAdd(cnt_w, grab_w);
+            k = wave_read(got, 0);
+            k_end = k + grab_w;
+        }
+        const uint64_t i64 = (uint64_t)cls + (uint64_t)nc * k;
+        if (i64 >= nw)
             break;
+        const uint32_t it = npages + (uint32_t)i64;
         uint4 item;
         DevList Ld;
         ListHdr H;
@@ -156,8 +189,9 @@ struct Plan {
     int device = -1;
     DevList *d_lists = nullptr;
     uint4 *d_items = nullptr;
-    uint32_t *d_counter = nullptr;  // [pages taken, runs and tails taken]
+    uint32_t *d_counter = nullptr;  // kCounters page counters, then kCounters run and tail counters
     uint64_t nlists = 0, nitems = 0, npages = 0;
+    uint32_t grabs = 0x00010001u;  // items per atomic: runs and tails << 16 | pages
     int waves = 4, vpl = 4, depth = 4;
     uint32_t grid = 1;
     bool use_graph = false;
@@ -222,12 +256,15 @@ static void release(Plan *p)
     delete p;
 }
 
+// Items claimed per atomic: 2 pages, 4 runs or tails.
+static void set_grabs(Plan *p) { p->grabs = 4u << 16 | 2u; }
+
 static int32_t launch_plan(Plan *p, hipStream_t st)
 {
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, st, p->d_counter);
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, p->d_counter);
     uint32_t npages32 = (uint32_t)p->npages, nitems32 = (uint32_t)p->nitems;
-    void *args[] = {&p->d_lists, &p->d_items, &npages32, &nitems32, &p->d_counter, &p->err};
+    void *args[] = {&p->d_lists, &p->d_items, &npages32, &nitems32, &p->grabs, &p->d_counter, &p->err};
     if (hipLaunchKernel(p->kernel, dim3(p->grid), dim3(64 * p->waves), args, 0, st) != hipSuccess)
         return WP_ERR_HIP;
     return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
@@ -242,14 +279,14 @@ static int32_t build_graph(Plan *p)
     hipKernelNodeParams rp = {};
     rp.func = reinterpret_cast<void *>(&k_batch_reset);
     rp.gridDim = dim3(1);
-    rp.blockDim = dim3(1);
+    rp.blockDim = dim3(64);
     rp.sharedMemBytes = 0;
     rp.kernelParams = rargs;
     rp.extra = nullptr;
     if (hipGraphAddKernelNode(&reset, p->graph, nullptr, 0, &rp) != hipSuccess)
         return WP_ERR_HIP;
     uint32_t npages32 = (uint32_t)p->npages, nitems32 = (uint32_t)p->nitems;
-    void *args[] = {&p->d_lists, &p->d_items, &npages32, &nitems32, &p->d_counter, &p->err};
+    void *args[] = {&p->d_lists, &p->d_items, &npages32, &nitems32, &p->grabs, &p->d_counter, &p->err};
     hipKernelNodeParams kp = {};
     kp.func = const_cast<void *>(p->kernel);
     kp.gridDim = dim3(p->grid);
@@ -292,8 +329,10 @@ static bool build_items(const uint32_t *pool, uint32_t *out_base, const wp_list 
             }
         } else {
             const uint64_t units = (nfull + kFpBlocks - 1) / kFpBlocks;
-            for (uint64_t u = 0; u < units; ++u)
-                fp_items.push_back(make_uint4(li, kItemFpPage, (uint32_t)u, 1));
+            for (uint64_t u = 0; u < units; ++u) {
+                const uint64_t nb = std::min<uint64_t>(kFpBlocks, nfull - u * kFpBlocks);
+                fp_items.push_back(make_uint4(li, kItemFpPage, (uint32_t)u, (uint32_t)nb));  // w: blocks (for ordering)
+            }
         }
         // a tail has an item of its own only in a list without full blocks;
         // otherwise the list's last run or page decodes it
@@ -302,7 +341,8 @@ static bool build_items(const uint32_t *pool, uint32_t *out_base, const wp_list 
     }
     if (nlists > 0xFFFFFFFFull)
         return false;
-    // largest items first: full pages, then runs (longest first), then tails
+    // largest items first: pages (most blocks first), runs (longest first), then tails
+    std::stable_sort(fp_items.begin(), fp_items.end(), [](const uint4 &a, const uint4 &b) { return a.w > b.w; });
     std::stable_sort(bp_items.begin(), bp_items.end(), [](const uint4 &a, const uint4 &b) { return a.w > b.w; });
     items.reserve(fp_items.size() + bp_items.size() + tail_items.size());
     items.insert(items.end(), fp_items.begin(), fp_items.end());
@@ -370,8 +410,9 @@ extern "C" int32_t wp_batch_plan(const uint32_t *pool, uint32_t *out_base, const
     uint64_t grid = (uint64_t)ds->cus * wpc;
     grid = std::max<uint64_t>(1, std::min<uint64_t>(grid, p->nitems ? p->nitems : 1));
     p->grid = (uint32_t)grid;
+    set_grabs(p);
     hipStream_t st = as_stream(stream);
-    if (hipMalloc(&p->d_counter, 16) != hipSuccess ||
+    if (hipMalloc(&p->d_counter, kCounterWords * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&p->d_lists, std::max<size_t>(1, lists.size()) * sizeof(DevList)) != hipSuccess ||
         hipMalloc(&p->d_items, std::max<size_t>(1, items.size()) * sizeof(uint4)) != hipSuccess) {
         release(p);
@@ -506,6 +547,7 @@ extern "C" int32_t wp_batch_replan(void *h_plan, const uint32_t *pool, uint32_t 
     uint64_t grid = (uint64_t)p->cus * (uint64_t)p->wpc;
     grid = std::max<uint64_t>(1, std::min<uint64_t>(grid, p->nitems ? p->nitems : 1));
     p->grid = (uint32_t)grid;
+    set_grabs(p);
     // the graph baked in the old item count and grid
     if (p->exec)
         (void)hipGraphExecDestroy(p->exec), p->exec = nullptr;
