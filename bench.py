@@ -32,7 +32,8 @@ sys.path.insert(0, ROOT)
 METRIC = "decoded uint32/s (G ints/s) + % HBM peak; batched vs per-list; p99 latency"
 HBM_PEAK_GBS = 8000.0
 MALL_BYTES = 256 << 20
-KERNEL_SOURCES = ("paper_1209_2137_amd/csrc/wp_device.hpp", "paper_1209_2137_amd/csrc/wp_decode.hip")
+KERNEL_SOURCES = ("paper_1209_2137_amd/csrc/wp_device.hpp", "paper_1209_2137_amd/csrc/wp_decode.hip",
+                  "paper_1209_2137_amd/tuning.json")
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "bp_decode_cluster_2e26_counters.json")
 
 
@@ -262,15 +263,25 @@ def rocprof_summary(d):
 
 
 def profile_run(steps):
+    """For rocprofv3: the headline decode, the 2^28 patched decode and the
+    2^28 in-place delta decode `steps` times each (after their warm-ups),
+    then a 1 GiB device copy `steps` times (the counter calibration)."""
     import torch
     import paper_1209_2137_amd as wp
     from paper_1209_2137_amd import datagen
     wp.lib()
     x = datagen.cluster_sorted(1 << 26, seed=2)
     r = bench_single(wp, x, wp.CODEC_BP, 1, steps, 2, "bp cluster 2^26")
+    del x
+    xf = datagen.patched_gaps(1 << 28, seed=4)
+    f = bench_single(wp, xf, wp.CODEC_FP, 1, steps, 2, "fastpfor patched 2^28")
+    del xf
+    d = bench_delta(wp, 1 << 28, steps, 2)
     c = bench_copy(1 << 30, steps, 0)
     torch.cuda.synchronize()
     print(json.dumps({"decode_kernel_ms": r["kernel_ms"], "decode_alg_bytes": r["alg_bytes"],
+                      "fp_kernel_ms": f["kernel_ms"], "fp_alg_bytes": f["alg_bytes"],
+                      "delta_kernel_ms": d["kernel_ms"], "delta_alg_bytes": 8 * (1 << 28),
                       "copy_bytes_each_way": 1 << 30, "copy_kernel_ms": c["kernel_ms"],
                       "kernel_hash": kernel_hash()}))
     return 0
@@ -288,8 +299,9 @@ def main():
                     help="length of the serving run (the full workload is 60 s)")
     ap.add_argument("--rocprof-summary", metavar="DIR")
     ap.add_argument("--profile-run", action="store_true",
-                    help="for rocprofv3: the headline decode `--steps` times, then a 1 GiB device copy "
-                         "(the counter calibration kernel) `--steps` times")
+                    help="for rocprofv3: the headline decode, the 2^28 patched decode and the 2^28 "
+                         "in-place delta decode `--steps` times each, then a 1 GiB device copy (the "
+                         "counter calibration kernel) `--steps` times")
     args = ap.parse_args()
     if args.rocprof_summary:
         rocprof_summary(args.rocprof_summary)
