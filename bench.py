@@ -64,20 +64,31 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).to("cuda")
 
 
-def time_launches(fn, steps, warmup, stream):
-    """Runs fn(i) warmup times, then `steps` times with HIP events around
-    every launch on `stream`. Returns (wall ms per step, mean event ms)."""
+def time_launches(fn, steps, warmup, stream, kernel_events=None):
+    """Runs fn(i) warmup times, then `steps` times. Returns (wall ms per
+    step, mean event ms). With kernel_events (the package), each launch's
+    own main kernel records a pair of HIP events when it starts and ends
+    (wp_time_next_launch), so the event time is the kernel's duration;
+    otherwise the events bracket each launch on `stream`."""
     import torch
     for i in range(warmup):
         fn(i)
     torch.cuda.synchronize()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    if kernel_events is not None:
+        for e in starts + ends:  # create the events on the device before handing them over
+            e.record(stream)
+        torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        starts[i].record(stream)
+        if kernel_events is not None:
+            kernel_events.time_next_launch(starts[i], ends[i])
+        else:
+            starts[i].record(stream)
         fn(warmup + i)
-        ends[i].record(stream)
+        if kernel_events is None:
+            ends[i].record(stream)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / steps
     ev = sum(s.elapsed_time(e) for s, e in zip(starts, ends)) / steps
@@ -105,7 +116,8 @@ def bench_single(wp, x_np, codec, stride, steps, warmup, name):
     if not torch.equal(outs[0], xd):
         raise RuntimeError(f"{name}: decoded output differs from the input")
     del xd
-    wall, ev = time_launches(lambda i: dec(comps[i % len(comps)], n, outs[i % 2]), steps, warmup, stream)
+    wall, ev = time_launches(lambda i: dec(comps[i % len(comps)], n, outs[i % 2]), steps, warmup, stream,
+                            kernel_events=wp)
     wp.check()
     comp_bytes = comp.numel() * 4
     alg = comp_bytes + 4 * n
@@ -123,7 +135,8 @@ def bench_delta(wp, n, steps, warmup):
     rng_t = torch.randint(0, 1 << 8, (n,), dtype=torch.int32, device="cuda")
     bufs = replicas(rng_t, n * 4)
     stream = torch.cuda.current_stream()
-    wall, ev = time_launches(lambda i: wp.delta_decode_inplace(bufs[i % len(bufs)], 0, 1), steps, warmup, stream)
+    wall, ev = time_launches(lambda i: wp.delta_decode_inplace(bufs[i % len(bufs)], 0, 1), steps, warmup, stream,
+                             kernel_events=wp)
     alg = 8 * n
     return {"name": "delta_decode_inplace 2^28 stride 1", "n": n, "ms_per_step": wall, "kernel_ms": ev,
             "gints_per_s": n / (wall * 1e-3) / 1e9, "achieved_gbs": alg / (ev * 1e-3) / 1e9,

@@ -118,6 +118,14 @@ int32_t fastpfor_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, ui
 int32_t delta_decode_inplace(uint32_t *data, uint64_t n, uint32_t init, int32_t stride,
                              void *stream);
 
+/* Timing hook (host): the calling thread's next bp_decode,
+ * fastpfor_decode or delta_decode_inplace records `start_event` when its
+ * main kernel starts and `stop_event` when that kernel ends (hipEvent_t,
+ * created by the caller with timing enabled; either may be NULL). The
+ * events bracket the kernel alone, not the launch path before it; they
+ * are consumed by that one call. Always returns WP_OK. */
+int32_t wp_time_next_launch(void *start_event, void *stop_event);
+
 /* Workgroup shape of the single-list decoders (set by the autotuner;
  * process-wide). Binary packing: every wavefront decodes its own run of
  * consecutive meta-blocks, streaming the run's compressed words through a

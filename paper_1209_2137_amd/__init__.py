@@ -24,7 +24,7 @@ CODEC_FP = 1
 
 EXPORTS = (
     "bp_encode", "bp_decode", "fastpfor_encode", "fastpfor_decode", "delta_decode_inplace",
-    "wp_max_compressed_words", "wp_check", "wp_strerror", "wp_set_decode_tune",
+    "wp_max_compressed_words", "wp_check", "wp_strerror", "wp_set_decode_tune", "wp_time_next_launch",
     "wp_batch_plan", "wp_batch_replan", "wp_batch_decode", "wp_batch_items", "wp_batch_free",
 )
 
@@ -77,6 +77,8 @@ def lib():
     L.wp_strerror.restype = ctypes.c_char_p
     L.wp_set_decode_tune.argtypes = [i32, i32, i32, i32, i32]
     L.wp_set_decode_tune.restype = i32
+    L.wp_time_next_launch.argtypes = [vp, vp]
+    L.wp_time_next_launch.restype = i32
     L.wp_batch_plan.argtypes = [vp, vp, ctypes.POINTER(wp_list), u64, ctypes.POINTER(wp_tune),
                                 ctypes.POINTER(vp), vp]
     L.wp_batch_plan.restype = i32
@@ -137,6 +139,15 @@ def set_decode_tune(codec: int, waves: int, vpl: int, wg_per_cu: int = 0, depth:
     `wg_per_cu` runs of meta-blocks per compute unit and `depth` loads in
     flight per thread (0 = defaults)."""
     _check(lib().wp_set_decode_tune(codec, waves, vpl, depth, wg_per_cu), "set_decode_tune")
+
+
+def time_next_launch(start, stop):
+    """The calling thread's next bp_decode / fastpfor_decode /
+    delta_decode_inplace records the torch.cuda.Event `start` when its main
+    kernel starts and `stop` when it ends (both must already exist on the
+    device: record them once before first use)."""
+    _check(lib().wp_time_next_launch(ctypes.c_void_p(start.cuda_event), ctypes.c_void_p(stop.cuda_event)),
+           "time_next_launch")
 
 
 def _decode(fn, comp, n, out, stream, name):

@@ -104,6 +104,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_fp_decode(const uint32_t *__rest
 
 static std::mutex g_mu;
 static std::vector<DevState> g_dev;
+static thread_local LaunchEvents t_events;
+
+LaunchEvents take_launch_events()
+{
+    const LaunchEvents e = t_events;
+    t_events = LaunchEvents{};
+    return e;
+}
 static Tune g_tune[2] = {{4, 4, kBpRunsPerCu, 2}, {4, 4, 0, 0}};
 
 DevState *dev_state()
@@ -150,16 +158,15 @@ template <int WAVES, int DEPTH>
 static void launch_bp(uint64_t grid, hipStream_t st, const uint32_t *in, uint64_t in_words, uint32_t *out,
                       uint64_t n, int *err, uint32_t upw)
 {
-    hipLaunchKernelGGL((k_bp_decode<WAVES, DEPTH>), dim3((uint32_t)grid), dim3(64 * WAVES), 0, st, in,
-                       in_words, out, n, err, upw);
+    launch_timed(k_bp_decode<WAVES, DEPTH>, dim3((uint32_t)grid), dim3(64 * WAVES), st, in, in_words, out, n, err,
+                 upw);
 }
 
 template <int WAVES>
 static void launch_fp(uint64_t grid, hipStream_t st, const uint32_t *in, uint64_t in_words, uint32_t *out,
                       uint64_t n, int *err)
 {
-    hipLaunchKernelGGL((k_fp_decode<WAVES>), dim3((uint32_t)grid), dim3(64 * WAVES), 0, st, in, in_words, out,
-                       n, err);
+    launch_timed(k_fp_decode<WAVES>, dim3((uint32_t)grid), dim3(64 * WAVES), st, in, in_words, out, n, err);
 }
 
 static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
@@ -243,6 +250,13 @@ extern "C" int32_t wp_set_decode_tune(int32_t codec, int32_t waves, int32_t vpl,
         return WP_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(g_mu);
     g_tune[codec] = Tune{waves, vpl, wg_per_cu, depth ? depth : 2};
+    return WP_OK;
+}
+
+extern "C" int32_t wp_time_next_launch(void *start_event, void *stop_event)
+{
+    t_events.start = reinterpret_cast<hipEvent_t>(start_event);
+    t_events.stop = reinterpret_cast<hipEvent_t>(stop_event);
     return WP_OK;
 }
 

@@ -1,6 +1,7 @@
 // Host-side state shared by the wavepack translation units.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -46,6 +47,23 @@ uint64_t scan_status_words(uint64_t n);
 int32_t launch_inclusive_scan(uint32_t *data, uint64_t n, uint64_t *status, hipStream_t st);
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Events the calling thread's next decoder launch records when its main
+// kernel starts and ends (set by wp_time_next_launch); taking them clears
+// them.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchEvents take_launch_events();
+
+// Launches kernel(args...) on st, recording the thread's launch events
+// around it if any are set.
+template <typename F, typename... Args>
+inline void launch_timed(F kernel, dim3 grid, dim3 block, hipStream_t st, Args... args)
+{
+    const LaunchEvents e = take_launch_events();
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e.start, e.stop, 0, args...);
+}
 
 inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 

@@ -298,16 +298,19 @@ uint64_t scan_status_words(uint64_t n)
 }
 
 static int32_t launch_scan(uint32_t *data, uint64_t n, uint32_t init, uint32_t stride, uint64_t *status,
-                           hipStream_t st)
+                           hipStream_t st, bool timed)
 {
     const uint32_t ti = tile_ints(stride);
     const uint64_t tiles = (n + ti - 1) / ti;
     const uint64_t words = (uint64_t)kStatusWords * (tiles + 1);
     hipLaunchKernelGGL(k_fill_zero, dim3((uint32_t)((words + 255) / 256)), dim3(256), 0, st, status, words);
+    const LaunchEvents e = timed ? take_launch_events() : LaunchEvents{};
     if (stride == 1)
-        hipLaunchKernelGGL(k_delta_scan<1>, dim3((uint32_t)tiles), dim3(kScanT), 0, st, data, n, init, status);
+        hipExtLaunchKernelGGL(k_delta_scan<1>, dim3((uint32_t)tiles), dim3(kScanT), 0, st, e.start, e.stop, 0, data, n,
+                              init, status);
     else
-        hipLaunchKernelGGL(k_delta_scan<4>, dim3((uint32_t)tiles), dim3(kScanT), 0, st, data, n, init, status);
+        hipExtLaunchKernelGGL(k_delta_scan<4>, dim3((uint32_t)tiles), dim3(kScanT), 0, st, e.start, e.stop, 0, data, n,
+                              init, status);
     return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
 }
 
@@ -315,7 +318,7 @@ int32_t launch_inclusive_scan(uint32_t *data, uint64_t n, uint64_t *status, hipS
 {
     if (n == 0)
         return WP_OK;
-    return launch_scan(data, n, 0u, 1u, status, st);
+    return launch_scan(data, n, 0u, 1u, status, st, false);
 }
 
 }  // namespace wp
@@ -336,5 +339,5 @@ extern "C" int32_t delta_decode_inplace(uint32_t *data, uint64_t n, uint32_t ini
     if (status == nullptr)
         return WP_ERR_HIP;
     (void)hipGetLastError();
-    return launch_scan(data, n, init, (uint32_t)stride, status, st);
+    return launch_scan(data, n, init, (uint32_t)stride, status, st, true);
 }

@@ -247,3 +247,25 @@ def test_delta_decode_inplace_large_repeatable():
         wp.delta_decode_inplace(t, 0, 1)
         torch.cuda.synchronize()
         assert_same(to_host(t), want)
+
+
+def test_time_next_launch_brackets_the_kernel():
+    # the timing hook records the caller's events around the decoder's own
+    # kernel; the decode is unchanged and the hook is consumed by one call
+    x = datagen.single_geometric(1 << 20, mean=8.0, seed=11)
+    comp = to_dev(oracle.bp_encode(x, 1))
+    out = torch.empty(x.size, dtype=torch.int32, device="cuda")
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    stop.record()
+    torch.cuda.synchronize()
+    wp.time_next_launch(start, stop)
+    wp.bp_decode(comp, x.size, out)
+    stop.synchronize()
+    ms = start.elapsed_time(stop)
+    assert wp.check_code() == wp.OK
+    assert_same(out.cpu().numpy().view(np.uint32), x)
+    assert 0.0 < ms < 100.0
+    wp.bp_decode(comp, x.size, out)  # no events pending: a plain launch
+    torch.cuda.synchronize()
+    assert wp.check_code() == wp.OK
