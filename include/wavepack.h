@@ -151,9 +151,10 @@ const char *wp_strerror(int32_t code);
  * counterpart of decoding many posting lists). A plan turns a list
  * registry into work items -- patched pages, runs of meta-blocks and
  * tails of lists without full blocks -- that a persistent kernel pulls
- * from atomic counters: pages by whole workgroups first, then runs and
- * tails by single wavefronts. The item holding a list's last unit also
- * decodes the list's tail. */
+ * from atomic counters: patched pages of more than 64 blocks by whole
+ * workgroups first, then runs, small pages and tails by single
+ * wavefronts. The item holding a list's last unit also decodes the list's
+ * tail. */
 
 typedef struct wp_list {
     uint64_t comp_off_words; /* stream start, in words from `pool` (multiple of 4) */

@@ -1,19 +1,19 @@
 // Batched decoding of many lists in one launch.
 //
-// The host planner cuts every list into work items: single pages
-// (patched), runs of up to `run_units` meta-blocks (binary packing) and
-// the Variable Byte tails of lists without full blocks; pages first, then
-// runs longest first, then tails. Other tails are decoded by the item that
-// holds the list's last unit. A persistent grid works through them in two phases: whole
-// workgroups take pages from a first atomic counter (a page needs the
-// workgroup's barriers); once pages run out, every wavefront takes runs
-// and tails by itself from a second counter, with no barrier at all.
-// Items are independent because every unit's base is stored in its list's
-// directory.
+// The host planner cuts every list into work items: single patched pages,
+// runs of up to `run_units` meta-blocks (binary packing) and the Variable
+// Byte tails of lists without full blocks. The tail of any other list is
+// decoded by the item that holds the list's last unit. A persistent grid
+// works through the items in two phases: whole workgroups take the patched
+// pages of more than 64 blocks (a page needs the workgroup's barriers),
+// largest first; then every wavefront takes runs, small patched pages and
+// tails by itself, largest first, with no barrier at all. Claims are spread
+// over several counters. Items are independent because every unit's base
+// is stored in its list's directory.
 //
 // A plan owns its device item array and, when asked, a hipGraph of two
-// kernel nodes: a one-thread counter reset, then the persistent decoder
-// (no memset node; the graph is built from explicit nodes, not captured).
+// kernel nodes: a counter reset, then the persistent decoder (no memset
+// node; the graph is built from explicit nodes, not captured).
 #include <algorithm>
 #include <mutex>
 #include <vector>
@@ -23,7 +23,10 @@
 
 namespace wp {
 
-enum : uint32_t { kItemBpRun = 0, kItemFpPage = 1, kItemTail = 2 };
+enum : uint32_t { kItemBpRun = 0, kItemFpPage = 1, kItemTail = 2, kItemFpSmall = 3 };
+
+// Patched pages of at most this many blocks are decoded by one wavefront.
+constexpr uint32_t kSmallPageBlocks = 64;
 
 struct DevList {
     const uint32_t *comp;
@@ -37,6 +40,7 @@ struct DevList {
 template <int DEPTH>
 union WaveItemLds {
     WaveLds<DEPTH> r;
+    FpWaveLds fp;
     TailLds<1> tail;
 };
 
@@ -173,6 +177,30 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch(const DevList *__restrict_
                 if (ok && first + count == H.units && H.tail) {
                     wave_lds_order();
                     ok = decode_tail_entry<1, false>(Ld.comp, H, Ld.out, W.tail);
+                }
+            } else if (item.y == kItemFpSmall) {
+                const uint64_t u = item.z;
+                ok = Ld.codec == WP_CODEC_FP && u < H.units;
+                if (ok) {
+                    const uint32_t off = Ld.comp[kHdrWords + u];
+                    const uint32_t end = (u + 1 < H.units) ? Ld.comp[kHdrWords + u + 1] : H.tail_off;
+                    uint32_t base[4] = {0u, 0u, 0u, 0u};
+                    for (uint32_t s = 0; s < H.S; ++s)
+                        base[s] = Ld.comp[kHdrWords + H.ndir + u * H.S + s];
+                    const uint64_t left = H.nfull - u * kFpBlocks;
+                    const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
+                    const uint32_t *pg = Ld.comp + off;
+                    uint32_t *po = Ld.out + u * kFpUnitInts;
+                    ok = off >= H.dir_end && end >= off && end <= H.total && (off & 3u) == 0 &&
+                         nb <= kSmallPageBlocks &&
+                         (H.S == 1   ? fp_small_page<1>(pg, end - off, nb, base, po, W.fp)
+                          : H.S == 4 ? fp_small_page<4>(pg, end - off, nb, base, po, W.fp)
+                                     : fp_small_page<0>(pg, end - off, nb, base, po, W.fp));
+                    // the list's last page also decodes its tail
+                    if (ok && u + 1 == H.units && H.tail) {
+                        wave_lds_order();
+                        ok = decode_tail_entry<1, false>(Ld.comp, H, Ld.out, W.tail);
+                    }
                 }
             } else {
                 ok = item.y == kItemTail && H.tail != 0 && decode_tail_entry<1, false>(Ld.comp, H, Ld.out, W.tail);
@@ -331,7 +359,11 @@ static bool build_items(const uint32_t *pool, uint32_t *out_base, const wp_list 
             const uint64_t units = (nfull + kFpBlocks - 1) / kFpBlocks;
             for (uint64_t u = 0; u < units; ++u) {
                 const uint64_t nb = std::min<uint64_t>(kFpBlocks, nfull - u * kFpBlocks);
-                fp_items.push_back(make_uint4(li, kItemFpPage, (uint32_t)u, (uint32_t)nb));  // w: blocks (for ordering)
+                // w: blocks (for ordering); small pages go to single wavefronts
+                if (nb <= kSmallPageBlocks)
+                    bp_items.push_back(make_uint4(li, kItemFpSmall, (uint32_t)u, (uint32_t)nb));
+                else
+                    fp_items.push_back(make_uint4(li, kItemFpPage, (uint32_t)u, (uint32_t)nb));
             }
         }
         // a tail has an item of its own only in a list without full blocks;
@@ -343,7 +375,10 @@ static bool build_items(const uint32_t *pool, uint32_t *out_base, const wp_list 
         return false;
     // largest items first: pages (most blocks first), runs (longest first), then tails
     std::stable_sort(fp_items.begin(), fp_items.end(), [](const uint4 &a, const uint4 &b) { return a.w > b.w; });
-    std::stable_sort(bp_items.begin(), bp_items.end(), [](const uint4 &a, const uint4 &b) { return a.w > b.w; });
+    // wavefront items by blocks: a run of w meta-blocks holds up to 16 w
+    auto blocks = [](const uint4 &a) { return a.y == kItemBpRun ? 16u * a.w : a.w; };
+    std::stable_sort(bp_items.begin(), bp_items.end(),
+                     [&](const uint4 &a, const uint4 &b) { return blocks(a) > blocks(b); });
     items.reserve(fp_items.size() + bp_items.size() + tail_items.size());
     items.insert(items.end(), fp_items.begin(), fp_items.end());
     npages = fp_items.size();

@@ -504,23 +504,185 @@ __device__ void fp_tables(FpLds<WAVES> &L, uint32_t nb, uint32_t &tot_words, uin
     tot_pos = carry_p;
 }
 
+// Prefix sum of one pass held as four consecutive integers per lane, in
+// place. stride 1: lane-serial sums, a wave scan of the lane totals, plus
+// the carry; stride 4: one wave scan per residue class (each lane holds
+// one integer of each class); stride 0: nothing. carry advances to the
+// value(s) at the end of the pass.
+template <uint32_t S>
+__device__ __forceinline__ void scan_wave4(uint32_t (&x)[4], uint32_t (&carry)[4])
+{
+    if constexpr (S == 1) {
+        x[1] += x[0];
+        x[2] += x[1];
+        x[3] += x[2];
+        const uint32_t incl = wave_scan_incl(x[3]);
+        const uint32_t add = incl - x[3] + carry[0];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            x[r] += add;
+        carry[0] += wave_read(incl, 63);
+    } else if constexpr (S == 4) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t incl = wave_scan_incl(x[c]);
+            x[c] = incl + carry[c];
+            carry[c] += wave_read(incl, 63);
+        }
+    }
+}
+
 // ------------------------------------------------------------------------
-// Patched page (Section 5). `page` points at the page header (16-byte
-// aligned), `nwords` its length, `nb` the number of blocks it must hold.
-// Setup: block offsets in the packed region, offsets into the position
-// bytes and, per block, the index of its first exception inside its array
-// k = maxb - b (the paper appends exceptions to array k in block order, so
-// this is the number of exceptions of earlier blocks with the same k).
+// Patched pages (Section 5): decoding a pair of blocks in one wavefront.
 //
-// Then passes of 2 * WAVES blocks: wavefront w takes blocks 2w and 2w + 1
-// of the pass and unpacks them as the binary-packing decoder does (strided
-// fields, LDS transpose); its lanes each patch one exception (position
-// byte and k-bit high part, OR-ed in above bit b; a pair of blocks with
-// more than 64 exceptions patches the rest in a slower loop). Everything a
-// block needs is in one 16-byte record, and the packed words and
-// exceptions of the next pass are fetched into registers while the
-// current one is decoded; one barrier per pass hands the wavefront totals
-// over for the prefix sum.
+// Every block of a page is described by one 16-byte record {b | k << 8 |
+// c << 16, packed word offset, bit offset of its first exception's high
+// part, position offset}, k = maxb - b. A wavefront takes two blocks at a
+// time and unpacks them as the binary-packing decoder does (lanes 0..31 the
+// first, 32..63 the second, strided fields, LDS transpose); lane e patches
+// exception e of the pair (position byte and k-bit high part, OR-ed in above
+// bit b; a pair with more than 64 exceptions patches the rest in a slower
+// loop). The pair's packed words and one exception per lane are fetched by
+// `fetch` into registers ahead of use.
+struct FpPairFetch {
+    uint32_t a0, a2, b0, b2;  // record words 0 and 2 of the two blocks (uniform)
+    uint4 pk;                 // the pair's packed words, 16 bytes per lane
+    uint32_t pos, lo, hi;     // exception `lane`: position byte, words of its high part
+};
+
+struct FpPair {
+    const uint32_t *page;
+    const uint4 *rec;  // the page's block records (LDS)
+    uint32_t nb, hdr_w, pos_at;
+    BufRsrc rpg;
+    uint32_t *stg, *xpw;  // this wavefront's staging and transposition areas (LDS)
+    uint32_t *bad;        // set on a bad position (LDS)
+
+    static constexpr uint32_t kOut = 0xfffffff0u;  // a buffer offset beyond every page: reads nothing
+
+    // blocks jA, jA + 1 (either may be past nb: no words, no exceptions)
+    __device__ __forceinline__ FpPairFetch fetch(uint32_t jA) const
+    {
+        const uint32_t lane = lane_id();
+        FpPairFetch f;
+        const uint4 ra = jA < nb ? rec[jA] : make_uint4(0u, 0u, 0u, 0u);
+        const uint4 rb = jA + 1u < nb ? rec[jA + 1u] : make_uint4(0u, 0u, 0u, 0u);
+        f.a0 = uniform(ra.x);
+        f.a2 = uniform(ra.z);
+        f.b0 = uniform(rb.x);
+        f.b2 = uniform(rb.z);
+        const uint32_t pa = uniform(ra.w), pbb = uniform(rb.w);
+        const uint32_t bA = f.a0 & 255u, bB = f.b0 & 255u, cA = f.a0 >> 16, cB = f.b0 >> 16;
+        const BufRsrc rp = make_rsrc(page + hdr_w + uniform(ra.y), 16u * (bA + bB));
+        f.pk = buf_load_u4(rp, lane * 16u);
+        const bool inA = lane < cA, inB = !inA && lane < cA + cB;
+        const uint32_t idx = inA ? lane : lane - cA;
+        const uint32_t k = ((inA ? f.a0 : f.b0) >> 8) & 255u;
+        const uint32_t bit = (inA ? f.a2 : f.b2) + idx * k;
+        const uint32_t poff = (inA || inB) ? pos_at + (inA ? pa : pbb) + idx : kOut;
+        const uint32_t woff = (inA || inB) ? (bit >> 5) * 4u : kOut;
+        f.pos = __builtin_amdgcn_raw_buffer_load_b8(rpg, (int)poff, 0, 0);
+        f.lo = buf_load_u32(rpg, woff);
+        f.hi = buf_load_u32(rpg, woff + 4u);
+        return f;
+    }
+
+    // exception e of the pair: high part, target block (0 or 1), shift b
+    __device__ __forceinline__ static uint32_t exc_of(const FpPairFetch &f, uint32_t e, uint32_t lo, uint32_t hw,
+                                                      uint32_t &blk, uint32_t &b)
+    {
+        const uint32_t cA = f.a0 >> 16;
+        const bool inA = e < cA;
+        const uint32_t w0 = inA ? f.a0 : f.b0;
+        const uint32_t idx = inA ? e : e - cA;
+        const uint32_t k = (w0 >> 8) & 255u;
+        const uint32_t bit = (inA ? f.a2 : f.b2) + idx * k;
+        blk = inA ? 0u : 1u;
+        b = w0 & 255u;
+        return __builtin_amdgcn_alignbit(hw, lo, bit) & width_mask(k);
+    }
+
+    // Unpacks and patches blocks jA, jA + 1 from f into the transposition
+    // area; after it, lane l's integers 4l..4l+3 of the pair are read with
+    // read_back(). f may be refilled once this returns.
+    __device__ __forceinline__ void unpack_patch(const FpPairFetch &f, uint32_t jA) const
+    {
+        const uint32_t lane = lane_id();
+        const uint32_t q = lane & 31u;
+        const bool hi = lane >= 32u;
+        const uint32_t bA = f.a0 & 255u, bB = f.b0 & 255u, cA = f.a0 >> 16, cB = f.b0 >> 16;
+        *reinterpret_cast<uint4 *>(&stg[4 * lane]) = f.pk;
+        wave_lds_order();
+        const uint32_t b = hi ? bB : bA;
+        const uint32_t qb = q * b;
+        const uint32_t w0 = (hi ? 4u * bA : 0u) + (qb >> 5);
+        const uint32_t mask = width_mask(b);
+        uint32_t v[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const uint32_t wi = w0 + m * b;
+            v[m] = __builtin_amdgcn_alignbit(stg[wi + 1], stg[wi], qb) & mask;
+        }
+        uint32_t *const xw = &xpw[lane + (hi ? 96u : 0u)];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            xw[32 * m] = v[m];
+        wave_lds_order();
+        // exceptions: one per lane, the rest (more than 64 in the pair) in rounds
+        const uint32_t ce = cA + cB;
+        {
+            const uint32_t prev = __shfl_up(f.pos, 1);
+            if (lane < ce) {
+                uint32_t blk, eb;
+                const uint32_t hv = exc_of(f, lane, f.lo, f.hi, blk, eb);
+                if (f.pos >= kBlock || (lane != 0 && lane != cA && prev >= f.pos))
+                    *bad = 1;
+                atomicOr(&xpw[blk * kBlock + (f.pos & (kBlock - 1u))], hv << eb);
+            }
+        }
+        for (uint32_t e0 = 64; e0 < ce; e0 += 64) {
+            const uint32_t e = e0 + lane;
+            if (e < ce) {
+                const bool inA = e < cA;
+                const uint32_t idx = inA ? e : e - cA;
+                const uint32_t k = ((inA ? f.a0 : f.b0) >> 8) & 255u;
+                const uint32_t bit = (inA ? f.a2 : f.b2) + idx * k;
+                const uint8_t *pb =
+                    reinterpret_cast<const uint8_t *>(page) + pos_at + (inA ? rec[jA].w : rec[jA + 1u].w) + idx;
+                const uint32_t pos = pb[0], pprev = idx > 0 ? pb[-1] : 0u;
+                const uint32_t lo = page[bit >> 5];
+                const uint32_t hw = (bit & 31u) + k > 32u ? page[(bit >> 5) + 1u] : 0u;
+                uint32_t blk, eb;
+                const uint32_t hv = exc_of(f, e, lo, hw, blk, eb);
+                if (pos >= kBlock || (idx > 0 && pprev >= pos))
+                    *bad = 1;
+                atomicOr(&xpw[blk * kBlock + (pos & (kBlock - 1u))], hv << eb);
+            }
+        }
+    }
+
+    __device__ __forceinline__ void read_back(uint32_t (&x)[4]) const
+    {
+        wave_lds_order();
+        const uint4 t = *reinterpret_cast<const uint4 *>(&xpw[4 * lane_id()]);
+        x[0] = t.x;
+        x[1] = t.y;
+        x[2] = t.z;
+        x[3] = t.w;
+    }
+};
+
+// Patched page (Section 5) decoded by a whole workgroup. `page` points at
+// the page header (16-byte aligned), `nwords` its length, `nb` the number
+// of blocks it must hold. Setup (bounded by nb): the exception-array
+// directory, the block metadata, block offsets in the packed region,
+// offsets into the position bytes and, per block, the index of its first
+// exception inside its array k = maxb - b (exceptions are appended to
+// array k in block order, so this is the number of exceptions of earlier
+// blocks with the same k); then the block records. Then passes of 2 * WAVES
+// blocks: wavefront w decodes pair w of the pass (FpPair), the next pass's
+// words and exceptions in flight; one barrier per pass hands the wavefront
+// totals over for the prefix sum.
 template <int WAVES, uint32_t S>
 __device__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint32_t nb,
                         const uint32_t (&base)[4], uint32_t *__restrict__ out, FpLds<WAVES> &L)
@@ -612,124 +774,20 @@ __device__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint
 
     // passes of 2 * WAVES blocks
     constexpr uint32_t BPP = 2 * WAVES;
-    const uint32_t q = lane & 31u;
-    const bool hi = lane >= 32u;
-    uint32_t *const stg = L.stage[wave];
-    uint32_t *const xpw = L.xp[wave];
-    uint32_t *const xw = &xpw[lane + (hi ? 96u : 0u)];
-    const uint4 *const xr = reinterpret_cast<const uint4 *>(&xpw[4 * lane]);
-    uint4 *const sw = reinterpret_cast<uint4 *>(&stg[4 * lane]);
     const uint32_t pos_at = (hdr_w + packed_words) * 4u + 3u * nb;  // byte offset of the positions
-    const BufRsrc rpg = make_rsrc(page, nwords * 4u);
+    const FpPair pair{page, L.rec, nb, hdr_w, pos_at, make_rsrc(page, nwords * 4u), L.stage[wave], L.xp[wave], &L.bad};
     const BufRsrc rout = make_rsrc(out, nb * kBlock * 4u);
-    constexpr uint32_t kOut = 0xfffffff0u;  // a buffer offset beyond every page: reads nothing
-
-    // a wavefront's pair of blocks in pass p: both records (uniform), the
-    // pair's packed words, and exception e = lane of the pair (position
-    // byte, the two words holding its high part)
-    struct Fetch {
-        uint32_t a0, a2, b0, b2;  // record words 0 and 2 of the two blocks
-        uint4 pk;
-        uint32_t pos, lo, hi;
-    };
-    auto fetch = [&](uint32_t p) __attribute__((always_inline)) {
-        Fetch f;
-        const uint32_t jA = p * BPP + 2u * wave;
-        const uint4 ra = jA < nb ? L.rec[jA] : make_uint4(0u, 0u, 0u, 0u);
-        const uint4 rb = jA + 1u < nb ? L.rec[jA + 1u] : make_uint4(0u, 0u, 0u, 0u);
-        f.a0 = uniform(ra.x);
-        f.a2 = uniform(ra.z);
-        f.b0 = uniform(rb.x);
-        f.b2 = uniform(rb.z);
-        const uint32_t pa = uniform(ra.w), pbb = uniform(rb.w);
-        const uint32_t bA = f.a0 & 255u, bB = f.b0 & 255u, cA = f.a0 >> 16, cB = f.b0 >> 16;
-        const BufRsrc rp = make_rsrc(page + hdr_w + uniform(ra.y), 16u * (bA + bB));
-        f.pk = buf_load_u4(rp, lane * 16u);
-        const bool inA = lane < cA, inB = !inA && lane < cA + cB;
-        const uint32_t idx = inA ? lane : lane - cA;
-        const uint32_t k = ((inA ? f.a0 : f.b0) >> 8) & 255u;
-        const uint32_t bit = (inA ? f.a2 : f.b2) + idx * k;
-        const uint32_t poff = (inA || inB) ? pos_at + (inA ? pa : pbb) + idx : kOut;
-        const uint32_t woff = (inA || inB) ? (bit >> 5) * 4u : kOut;
-        f.pos = __builtin_amdgcn_raw_buffer_load_b8(rpg, (int)poff, 0, 0);
-        f.lo = buf_load_u32(rpg, woff);
-        f.hi = buf_load_u32(rpg, woff + 4u);
-        return f;
-    };
-    // exception e (any index) of the pair whose records are r0/r2 (A) and
-    // s0/s2 (B): target block, shift, high part
-    auto exc_of = [&](const Fetch &f, uint32_t e, uint32_t lo, uint32_t hw, uint32_t &blk, uint32_t &b)
-        __attribute__((always_inline)) {
-        const uint32_t cA = f.a0 >> 16;
-        const bool inA = e < cA;
-        const uint32_t w0 = inA ? f.a0 : f.b0;
-        const uint32_t idx = inA ? e : e - cA;
-        const uint32_t k = (w0 >> 8) & 255u;
-        const uint32_t bit = (inA ? f.a2 : f.b2) + idx * k;
-        blk = inA ? 0u : 1u;
-        b = w0 & 255u;
-        return __builtin_amdgcn_alignbit(hw, lo, bit) & width_mask(k);
-    };
-
     uint32_t carry[4] = {base[0], base[1], base[2], base[3]};
     const uint32_t npass = (nb + BPP - 1) / BPP;
     // pass p from slot f; the slot is refilled with pass p + 2 as soon as
-    // its packed words and exceptions have been used (two named slots, so
-    // nothing is copied between passes)
-    auto run_pass = [&](uint32_t p, Fetch &f) __attribute__((always_inline)) {
+    // its words and exceptions have been used (two named slots, so nothing
+    // is copied between passes)
+    auto run_pass = [&](uint32_t p, FpPairFetch &f) __attribute__((always_inline)) {
         const uint32_t jA = p * BPP + 2u * wave;
-        const uint32_t bA = f.a0 & 255u, bB = f.b0 & 255u, cA = f.a0 >> 16, cB = f.b0 >> 16;
-        *sw = f.pk;
-        wave_lds_order();
-        const uint32_t b = hi ? bB : bA;
-        const uint32_t qb = q * b;
-        const uint32_t w0 = (hi ? 4u * bA : 0u) + (qb >> 5);
-        const uint32_t mask = width_mask(b);
-        uint32_t v[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const uint32_t wi = w0 + m * b;
-            v[m] = __builtin_amdgcn_alignbit(stg[wi + 1], stg[wi], qb) & mask;
-        }
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-            xw[32 * m] = v[m];
-        wave_lds_order();
-        // exceptions: one per lane, the rest (more than 64 in the pair) in rounds
-        const uint32_t ce = cA + cB;
-        {
-            const uint32_t prev = __shfl_up(f.pos, 1);
-            if (lane < ce) {
-                uint32_t blk, eb;
-                const uint32_t hv = exc_of(f, lane, f.lo, f.hi, blk, eb);
-                if (f.pos >= kBlock || (lane != 0 && lane != cA && prev >= f.pos))
-                    L.bad = 1;
-                atomicOr(&xpw[blk * kBlock + (f.pos & (kBlock - 1u))], hv << eb);
-            }
-        }
-        for (uint32_t e0 = 64; e0 < ce; e0 += 64) {
-            const uint32_t e = e0 + lane;
-            if (e < ce) {
-                const bool inA = e < cA;
-                const uint32_t idx = inA ? e : e - cA;
-                const uint32_t k = ((inA ? f.a0 : f.b0) >> 8) & 255u;
-                const uint32_t bit = (inA ? f.a2 : f.b2) + idx * k;
-                const uint8_t *pb = reinterpret_cast<const uint8_t *>(page) + pos_at +
-                                    (inA ? L.rec[jA].w : L.rec[jA + 1u].w) + idx;
-                const uint32_t pos = pb[0], pprev = idx > 0 ? pb[-1] : 0u;
-                const uint32_t lo = page[bit >> 5];
-                const uint32_t hw = (bit & 31u) + k > 32u ? page[(bit >> 5) + 1u] : 0u;
-                uint32_t blk, eb;
-                const uint32_t hv = exc_of(f, e, lo, hw, blk, eb);
-                if (pos >= kBlock || (idx > 0 && pprev >= pos))
-                    L.bad = 1;
-                atomicOr(&xpw[blk * kBlock + (pos & (kBlock - 1u))], hv << eb);
-            }
-        }
-        f = fetch(p + 2);  // beyond the page it reads nothing
-        wave_lds_order();
-        const uint4 tq = *xr;
-        uint32_t x[4] = {tq.x, tq.y, tq.z, tq.w};
+        pair.unpack_patch(f, jA);
+        f = pair.fetch((p + 2) * BPP + 2u * wave);  // beyond the page it reads nothing
+        uint32_t x[4];
+        pair.read_back(x);
         // prefix sum: inside the wavefront, then across wavefronts
         if constexpr (S == 1) {
             x[1] += x[0];
@@ -776,7 +834,7 @@ __device__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint
         }
         buf_store_u4(rout, lane * 16u, uniform(jA * (kBlock * 4u)), make_uint4(x[0], x[1], x[2], x[3]));
     };
-    Fetch f0 = fetch(0), f1 = fetch(1);
+    FpPairFetch f0 = pair.fetch(2u * wave), f1 = pair.fetch(BPP + 2u * wave);
     uint32_t p = 0;
     for (; p + 2 <= npass; p += 2) {
         run_pass(p, f0);
@@ -785,6 +843,105 @@ __device__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint
     if (p < npass)
         run_pass(p, f0);
     __syncthreads();
+    return L.bad == 0;
+}
+
+// A small patched page (nb <= 64 blocks) decoded by one wavefront, with no
+// workgroup barrier: the same setup with one lane per block (tables by wave
+// scans, ranks by one masked scan per distinct k), then the pairs in order
+// with the prefix sum carried inside the wavefront. Used by the batched
+// decoder for the short lists' pages.
+struct alignas(16) FpWaveLds {
+    uint32_t stage[2 * kBlock + 4];
+    uint32_t xp[2 * kBlock];
+    uint4 rec[64];
+    uint32_t bad;
+};
+
+template <uint32_t S>
+__device__ bool fp_small_page(const uint32_t *__restrict__ page, uint32_t nwords, uint32_t nb,
+                              const uint32_t (&base)[4], uint32_t *__restrict__ out, FpWaveLds &L)
+{
+    const uint32_t lane = lane_id();
+    if (nwords < 4 || nb == 0 || nb > 64)
+        return false;
+    const uint32_t h_nb = uniform(page[0]), packed_words = uniform(page[1]), meta_bytes = uniform(page[2]),
+                   bitset = uniform(page[3]);
+    const uint32_t nset = __builtin_popcount(bitset);
+    const uint32_t hdr_w = pad4(4 + nset);
+    const uint32_t meta_w = ((meta_bytes + 15u) / 16u) * 4u;
+    if (h_nb != nb || hdr_w > nwords || packed_words > nwords - hdr_w || meta_bytes < 3 * nb ||
+        meta_bytes > 3 * nb + 127 * nb || meta_w > nwords - hdr_w - packed_words || (packed_words & 3u))
+        return false;
+    const uint32_t exc_at = hdr_w + packed_words + meta_w;
+    const uint8_t *meta = reinterpret_cast<const uint8_t *>(page + hdr_w + packed_words);
+    // exception array directory: lane k - 1 owns array k
+    const bool kl = lane < 32;
+    const uint32_t kown = lane + 1;
+    const bool set = kl && ((bitset >> (lane & 31u)) & 1u);
+    const uint32_t ci = kl ? (uint32_t)__builtin_popcount(bitset & ((1u << (lane & 31u)) - 1u)) : 0u;
+    const uint32_t cnt = set ? page[4 + ci] : 0u;
+    const bool badk = set && (cnt == 0 || cnt > nb * kBlock);
+    const uint32_t wk = (set && !badk) ? ((cnt + kBlock - 1) / kBlock) * 4u * kown : 0u;
+    const uint32_t kincl = wave_scan_incl(wk);
+    const uint32_t excb = exc_at + kincl - wk;  // lane k - 1: first word of array k
+    bool bad = ballot(badk) != 0 || exc_at + wave_read(kincl, 63) != nwords;
+    // blocks: lane j owns block j
+    const bool own = lane < nb;
+    const uint32_t b = own ? meta[lane] : 0u, mb = own ? meta[nb + lane] : 0u, c = own ? meta[2 * nb + lane] : 0u;
+    bad = bad || ballot(own && (b > 32 || mb > 32 || mb < b || c >= kBlock || ((c == 0) != (mb == b)))) != 0;
+    const uint32_t k = own && mb >= b ? mb - b : 0u;
+    const uint32_t bincl = wave_scan_incl(4u * b), cincl = wave_scan_incl(c);
+    const uint32_t cnt_all = wave_read(wave_scan_incl(cnt), 63);
+    bad = bad || wave_read(bincl, 63) != packed_words || 3 * nb + wave_read(cincl, 63) != meta_bytes ||
+          wave_read(cincl, 63) != cnt_all;
+    // rank of each block's first exception in its array: one masked scan per distinct k
+    uint32_t rank = 0;
+    uint64_t todo = ballot(c > 0 && k >= 1 && k <= 32);
+    while (todo) {
+        const uint32_t lead = (uint32_t)__builtin_ctzll(todo);
+        const uint32_t k0 = wave_read(k, lead);
+        const bool mine = c > 0 && k == k0;
+        const uint64_t mm = ballot(mine);
+        const uint32_t xc = mine ? c : 0u;
+        const uint32_t incl = wave_scan_incl(xc);
+        if (mine)
+            rank = incl - xc;
+        bad = bad || wave_read(incl, 63) != wave_read(cnt, (int)k0 - 1);
+        todo &= ~mm;
+    }
+    const uint32_t eb = __shfl(excb, (int)(k >= 1 ? k - 1 : 0));
+    if (own)
+        L.rec[lane] = make_uint4(b | (k << 8) | (c << 16), bincl - 4u * b, (c > 0 ? eb * 32u + rank * k : 0u),
+                                 cincl - c);
+    if (lane == 0)
+        L.bad = 0;
+    if (bad)
+        return false;
+    wave_lds_order();
+
+    const uint32_t pos_at = (hdr_w + packed_words) * 4u + 3u * nb;
+    const FpPair pair{page, L.rec, nb, hdr_w, pos_at, make_rsrc(page, nwords * 4u), L.stage, L.xp, &L.bad};
+    const BufRsrc rout = make_rsrc(out, nb * kBlock * 4u);
+    uint32_t carry[4] = {base[0], base[1], base[2], base[3]};
+    const uint32_t npass = (nb + 1) / 2;
+    auto run_pass = [&](uint32_t p, FpPairFetch &f) __attribute__((always_inline)) {
+        pair.unpack_patch(f, 2u * p);
+        f = pair.fetch(2u * (p + 2));
+        uint32_t x[4];
+        pair.read_back(x);
+        scan_wave4<S>(x, carry);
+        buf_store_u4(rout, lane * 16u, p * (2u * kBlock * 4u), make_uint4(x[0], x[1], x[2], x[3]));
+    };
+    FpPairFetch f0 = pair.fetch(0), f1 = pair.fetch(2);
+    uint32_t p = 0;
+    for (; p + 2 <= npass; p += 2) {
+        run_pass(p, f0);
+        run_pass(p + 1, f1);
+    }
+    if (p < npass)
+        run_pass(p, f0);
+    wave_lds_order();
     return L.bad == 0;
 }
 
@@ -839,34 +996,6 @@ struct alignas(16) WaveLds {
     uint32_t ring[WaveGeo<DEPTH>::RB + WaveGeo<DEPTH>::MIR];
     uint32_t xp[WaveGeo<DEPTH>::PASS];                // transposition of one pass
 };
-
-// Prefix sum of one pass held as four consecutive integers per lane, in
-// place. stride 1: lane-serial sums, a wave scan of the lane totals, plus
-// the carry; stride 4: one wave scan per residue class (each lane holds
-// one integer of each class); stride 0: nothing. carry advances to the
-// value(s) at the end of the pass.
-template <uint32_t S>
-__device__ __forceinline__ void scan_wave4(uint32_t (&x)[4], uint32_t (&carry)[4])
-{
-    if constexpr (S == 1) {
-        x[1] += x[0];
-        x[2] += x[1];
-        x[3] += x[2];
-        const uint32_t incl = wave_scan_incl(x[3]);
-        const uint32_t add = incl - x[3] + carry[0];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            x[r] += add;
-        carry[0] += wave_read(incl, 63);
-    } else if constexpr (S == 4) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const uint32_t incl = wave_scan_incl(x[c]);
-            x[c] = incl + carry[c];
-            carry[c] += wave_read(incl, 63);
-        }
-    }
-}
 
 // Sum of the four byte lanes of each word, and whether any byte exceeds 32.
 __device__ __forceinline__ uint32_t byte_sum(uint32_t d)

@@ -100,3 +100,35 @@ def test_batch_plan_rejects_bad_registry(pool):
         wp.BatchPlan(pool.pool, out, [(0, 100, 0, 10, 7)])  # unknown codec
     with pytest.raises(wp.WavepackError):
         wp.BatchPlan(pool.pool, out, pool.rows[:2], tune=dict(waves=3))
+
+
+@pytest.mark.parametrize("stride", [0, 4])
+def test_batch_strides_and_page_sizes(stride):
+    # lists of every item shape at strides 0 and 4: patched lists of one
+    # small page (<= 64 blocks, one wavefront), of one large page (a
+    # workgroup), of several pages, binary-packing lists, and lists shorter
+    # than one block (a tail item only); each decoded list equals its input
+    rng = np.random.default_rng(40 + stride)
+    lens = [5, 127, 128, 129, 64 * 128, 64 * 128 + 77, 65 * 128 + 3, 300 * 128 + 50, 512 * 128, 512 * 128 + 9000,
+            3 * 512 * 128 + 4000, 2048 * 3 + 17, 33 * 2048 + 1]
+    arrays, codecs = [], []
+    for i, n in enumerate(lens):
+        for codec in (wp.CODEC_BP, wp.CODEC_FP):
+            arrays.append(datagen.patched_gaps(n, seed=1000 * stride + 10 * i + codec) if i % 2 else
+                          datagen.single_geometric(n, mean=float(rng.integers(2, 3000)), seed=i + 7 * codec))
+            codecs.append(codec)
+    pool = ListPool(arrays, codecs, stride=stride)
+    for tune in (dict(waves=4, vpl=4, depth=2, run_units=4, wg_per_cu=2, use_graph=1),
+                 dict(waves=2, vpl=4, depth=3, run_units=16, wg_per_cu=0, use_graph=0)):
+        out = torch.full((pool.total_out + 64,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
+        plan = pool.plan(out, tune=tune)
+        for rep in range(2):
+            out[: pool.total_out].fill_(-1)
+            plan.decode()
+            assert wp.check_code() == wp.OK
+            for i in range(len(pool.rows)):
+                co, cw, oo, n, codec = pool.rows[i]
+                if not torch.equal(out[oo:oo + n], pool.values[oo:oo + n]):
+                    raise AssertionError(f"list {i} (codec {codec}, n {n}, stride {stride}) differs on replay {rep}")
+            assert (out[pool.total_out:] == 0x5A5A5A5A).all()
+        plan.free()
