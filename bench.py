@@ -154,7 +154,7 @@ def bench_copy(n_bytes, steps, warmup):
 
 
 def bench_batch(wp, steps, warmup, n_lists=100_000, total=1.2e9, per_list_passes=2):
-    """Posting-list pool: one batched persistent decode (hipGraph) vs one
+    """Posting-list pool: one batched decode launch (hipGraph) vs one
     single-list launch per list on the same stream."""
     import torch
     from paper_1209_2137_amd import datagen
@@ -165,7 +165,7 @@ def bench_batch(wp, steps, warmup, n_lists=100_000, total=1.2e9, per_list_passes
     pool = ListPool(list_array, codec, stride=1, count=n_lists, keep_values=True)
     t_setup = time.perf_counter() - t0
     out = torch.zeros(pool.total_out + 4, dtype=torch.int32, device="cuda")
-    tune = batch_tune() or dict(waves=4, vpl=4, depth=4, run_units=8, wg_per_cu=4, use_graph=1)
+    tune = batch_tune() or dict(waves=4, vpl=4, depth=3, run_units=4, wg_per_cu=0, use_graph=1)
     tune = dict(tune, use_graph=1)
     plan = pool.plan(out, tune=tune)
     plan.decode()

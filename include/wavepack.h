@@ -150,11 +150,11 @@ const char *wp_strerror(int32_t code);
 /* Batched decoding of many lists in one launch (not in the paper: the GPU
  * counterpart of decoding many posting lists). A plan turns a list
  * registry into work items -- patched pages, runs of meta-blocks and
- * tails of lists without full blocks -- that a persistent kernel pulls
- * from atomic counters: patched pages of more than 64 blocks by whole
- * workgroups first, then runs, small pages and tails by single
- * wavefronts. The item holding a list's last unit also decodes the list's
- * tail. */
+ * tails of lists without full blocks -- and one kernel launch covers them
+ * all: a workgroup for each patched page of more than 64 blocks, then a
+ * wavefront for each run, small page and tail, each class largest first
+ * (the hardware dispatcher balances the load; there is no work queue).
+ * The item holding a list's last unit also decodes the list's tail. */
 
 typedef struct wp_list {
     uint64_t comp_off_words; /* stream start, in words from `pool` (multiple of 4) */
@@ -170,7 +170,7 @@ typedef struct wp_tune {
     int32_t vpl;       /* integers per lane and pass: 4 (0 = 4) */
     int32_t depth;     /* binary packing: 16-byte loads per lane in flight, 2, 3 or 4 (0 = 2) */
     int32_t run_units; /* meta-blocks per binary-packing work item (one wavefront), 1..63 (0 = 8) */
-    int32_t wg_per_cu; /* persistent workgroups per compute unit, 0..64 (0 = 28 / waves) */
+    int32_t wg_per_cu; /* ignored by batched decoding (0..64 accepted) */
     int32_t use_graph; /* 1 = replay a hipGraph built at plan time, 0 = plain launches */
 } wp_tune;
 
@@ -179,7 +179,7 @@ typedef struct wp_tune {
  * into work items (runs of run_units meta-blocks, single pages, tails
  * of lists without full blocks; largest first), uploads the list and item arrays (it synchronises
  * `stream` once), and, when tune->use_graph, builds and instantiates a
- * hipGraph of the counter reset and the persistent decoder. `pool` and
+ * hipGraph holding the decoder's kernel node. `pool` and
  * `out_base` (device, 16-byte aligned) are kept; h_lists may be freed on
  * return; tune may be NULL (defaults, graph on). The plan allocates its
  * own device arrays; *h_plan is released with wp_batch_free. Output ranges
@@ -188,11 +188,11 @@ typedef struct wp_tune {
 int32_t wp_batch_plan(const uint32_t *pool, uint32_t *out_base, const wp_list *h_lists,
                       uint64_t nlists, const wp_tune *tune, void **h_plan, void *stream);
 
-/* Decodes every list of the plan on `stream` (asynchronous): resets the
- * work counter and runs the persistent decoder, as one hipGraph launch when
- * the plan has a graph. Stream contents are validated as in bp_decode; a
- * bad list is reported through wp_check. Two launches of the same plan must
- * not overlap (they share the counter). Allocates nothing. */
+/* Decodes every list of the plan on `stream` (asynchronous): one kernel
+ * launch, or one hipGraph launch when the plan has a graph. Stream
+ * contents are validated as in bp_decode; a bad list is reported through
+ * wp_check. Launches of the same plan may overlap only if the caller
+ * accepts both writing the same outputs. Allocates nothing. */
 int32_t wp_batch_decode(void *h_plan, void *stream);
 
 /* Re-targets an existing plan at a new registry (same meaning as in

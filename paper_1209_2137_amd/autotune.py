@@ -6,7 +6,7 @@ Knobs:
   depth      binary packing: 16-byte loads in flight per lane, which also
              sizes each wavefront's LDS ring (2 or 3: 4 KB, 4: 8 KB)
   wg_per_cu  single list, binary packing: runs (one per wavefront) per
-             compute unit; batched: persistent workgroups per compute unit
+             compute unit (batched decoding ignores it)
   run_units  batched decoding: meta-blocks per work item
 
 Each candidate is timed with HIP events (median of `steps` launches after
@@ -27,8 +27,8 @@ BP_SINGLE = [dict(waves=w, vpl=4, depth=d, wg_per_cu=c)
              for w in (1, 2, 4, 8) for d in (2, 3) for c in (28, 56, 128, 256)] + \
             [dict(waves=w, vpl=4, depth=4, wg_per_cu=c) for w in (1, 4) for c in (64, 128)]
 FP_SINGLE = [dict(waves=w, vpl=4) for w in (2, 4, 8)]
-BATCH = [dict(waves=w, vpl=4, depth=2, run_units=r, wg_per_cu=c, use_graph=1)
-         for w in (2, 4, 8) for r in (4, 8, 16) for c in (32 // w, 48 // w, 64 // w)]
+BATCH = [dict(waves=w, vpl=4, depth=d, run_units=r, wg_per_cu=0, use_graph=1)
+         for w in (2, 4, 8) for d in (2, 3) for r in (4, 8, 16)]
 
 
 def load(path: str = TUNING_PATH) -> dict:

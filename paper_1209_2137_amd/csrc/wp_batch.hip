@@ -1,19 +1,18 @@
 // Batched decoding of many lists in one launch.
 //
-// The host planner cuts every list into work items: single patched pages,
+// The host planner cuts every list into work items: patched pages,
 // runs of up to `run_units` meta-blocks (binary packing) and the Variable
 // Byte tails of lists without full blocks. The tail of any other list is
-// decoded by the item that holds the list's last unit. A persistent grid
-// works through the items in two phases: whole workgroups take the patched
-// pages of more than 64 blocks (a page needs the workgroup's barriers),
-// largest first; then every wavefront takes runs, small patched pages and
-// tails by itself, largest first, with no barrier at all. Claims are spread
-// over several counters. Items are independent because every unit's base
-// is stored in its list's directory.
+// decoded by the item that holds the list's last unit. One grid covers the
+// items: a workgroup for each patched page of more than 64 blocks (a page
+// needs the workgroup's barriers), then a wavefront for each run, small
+// patched page and tail, with no barrier at all; each class is ordered
+// largest first, so the dispatcher, which starts workgroups in index order
+// as compute units free up, schedules the longest items first. Items are
+// independent because every unit's base is stored in its list's directory.
 //
-// A plan owns its device item array and, when asked, a hipGraph of two
-// kernel nodes: a counter reset, then the persistent decoder (no memset
-// node; the graph is built from explicit nodes, not captured).
+// A plan owns its device item array and, when asked, a hipGraph holding
+// the one kernel node (built from an explicit node, not captured).
 #include <algorithm>
 #include <mutex>
 #include <vector>
@@ -44,26 +43,18 @@ union WaveItemLds {
     TailLds<1> tail;
 };
 
-// item: {list index, kind, first unit, unit count (pages: the page's blocks)}
-template <int WAVES, int DEPTH>
-union BatchLds {
-    WaveItemLds<DEPTH> w[WAVES];
+template <int WAVES>
+union BatchPageLds {
     FpLds<WAVES> fp;
     TailLds<WAVES> tail;
 };
 
-// Work counters: kCounters per phase, kCounterStride words apart (one
-// 64-byte line each), so the claims of different workgroups spread over
-// several addresses. Workgroup g uses counter g % min(kCounters, grid),
-// which hands out that class's items c, c + C, c + 2C, ...
-constexpr uint32_t kCounters = 8, kCounterStride = 16;
-constexpr uint32_t kCounterWords = 2 * kCounters * kCounterStride;
-
-__global__ void k_batch_reset(uint32_t *counter)
-{
-    if (threadIdx.x < 2 * kCounters)
-        counter[threadIdx.x * kCounterStride] = 0;
-}
+// item: {list index, kind, first unit, unit count (pages: the page's blocks)}
+template <int WAVES, int DEPTH>
+union BatchLds {
+    WaveItemLds<DEPTH> w[WAVES];
+    BatchPageLds<WAVES> page;
+};
 
 // Header check of item `it`'s list; uniform.
 __device__ __forceinline__ bool item_header(const DevList *__restrict__ lists, const uint4 *__restrict__ items,
@@ -73,153 +64,128 @@ __device__ __forceinline__ bool item_header(const DevList *__restrict__ lists, c
     item = make_uint4(uniform(t.x), uniform(t.y), uniform(t.z), uniform(t.w));
     Ld = lists[item.x];
     Ld.codec = uniform(Ld.codec);
+    Ld.comp = as_global(Ld.comp);
+    Ld.out = as_global(Ld.out);
     return check_header(Ld.comp, Ld.comp_words, Ld.n, Ld.codec == WP_CODEC_BP ? kMagicBP : kMagicFP,
                         Ld.codec == WP_CODEC_BP ? kBpBlocks : kFpBlocks, H);
 }
 
-// grabs: items claimed per atomic, pages in the low 16 bits and runs and
-// tails in the high 16 bits (claiming several items at a time divides the
-// traffic on the counters)
+// Page item `it` (a patched page of more than kSmallPageBlocks blocks),
+// decoded by the whole workgroup; the list's last page also decodes its
+// tail. Uniform result.
+template <int WAVES>
+__device__ __forceinline__ bool page_item(const DevList *__restrict__ lists, const uint4 *__restrict__ items, uint32_t it,
+                          BatchPageLds<WAVES> &L)
+{
+    uint4 item;
+    DevList Ld;
+    ListHdr H;
+    bool ok = item_header(lists, items, it, item, Ld, H) && item.y == kItemFpPage && Ld.codec == WP_CODEC_FP &&
+              item.z < H.units;
+    if (!ok)
+        return false;
+    const uint64_t u = item.z;
+    const uint32_t off = uniform(Ld.comp[kHdrWords + u]);
+    const uint32_t end = (u + 1 < H.units) ? uniform(Ld.comp[kHdrWords + u + 1]) : H.tail_off;
+    const uint32_t *bp = Ld.comp + kHdrWords + H.ndir + u * H.S;
+    const uint32_t base[4] = {H.S > 0 ? uniform(bp[0]) : 0u, H.S > 1 ? uniform(bp[1]) : 0u,
+                              H.S > 2 ? uniform(bp[2]) : 0u, H.S > 3 ? uniform(bp[3]) : 0u};
+    const uint64_t left = H.nfull - u * kFpBlocks;
+    const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
+    const uint32_t *pg = Ld.comp + off;
+    uint32_t *po = Ld.out + u * kFpUnitInts;
+    ok = off >= H.dir_end && end >= off && end <= H.total && (off & 3u) == 0 &&
+         (H.S == 1   ? fp_page<WAVES, 1>(pg, end - off, nb, base, po, L.fp)
+          : H.S == 4 ? fp_page<WAVES, 4>(pg, end - off, nb, base, po, L.fp)
+                     : fp_page<WAVES, 0>(pg, end - off, nb, base, po, L.fp));
+    if (u + 1 == H.units && H.tail) {
+        __syncthreads();
+        ok = decode_tail_entry<WAVES>(Ld.comp, H, Ld.out, L.tail) && ok;
+    }
+    return ok;
+}
+
+// Wavefront item `it`: a run of binary-packing meta-blocks, a small
+// patched page or a tail, decoded by one wavefront with no workgroup
+// barrier; the item holding a list's last unit also decodes its tail.
+template <int DEPTH>
+__device__ __forceinline__ bool wave_item(const DevList *__restrict__ lists, const uint4 *__restrict__ items, uint32_t it,
+                          WaveItemLds<DEPTH> &W)
+{
+    uint4 item;
+    DevList Ld;
+    ListHdr H;
+    if (!item_header(lists, items, it, item, Ld, H))
+        return false;
+    bool ok, last;
+    if (item.y == kItemBpRun) {
+        const uint32_t first = item.z, count = item.w;
+        ok = Ld.codec == WP_CODEC_BP && count >= 1 && count <= 63 && (uint64_t)first + count <= H.units;
+        if (!ok)
+            return false;
+        ok = H.S == 1   ? bp_wave_run<DEPTH, 1>(Ld.comp, H, first, count, Ld.out, W.r)
+             : H.S == 4 ? bp_wave_run<DEPTH, 4>(Ld.comp, H, first, count, Ld.out, W.r)
+                        : bp_wave_run<DEPTH, 0>(Ld.comp, H, first, count, Ld.out, W.r);
+        last = first + count == H.units;
+    } else if (item.y == kItemFpSmall) {
+        const uint64_t u = item.z;
+        if (!(Ld.codec == WP_CODEC_FP && u < H.units))
+            return false;
+        const uint32_t off = uniform(Ld.comp[kHdrWords + u]);
+        const uint32_t end = (u + 1 < H.units) ? uniform(Ld.comp[kHdrWords + u + 1]) : H.tail_off;
+        const uint32_t *bp = Ld.comp + kHdrWords + H.ndir + u * H.S;
+        const uint32_t base[4] = {H.S > 0 ? uniform(bp[0]) : 0u, H.S > 1 ? uniform(bp[1]) : 0u,
+                                  H.S > 2 ? uniform(bp[2]) : 0u, H.S > 3 ? uniform(bp[3]) : 0u};
+        const uint64_t left = H.nfull - u * kFpBlocks;
+        const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
+        const uint32_t *pg = Ld.comp + off;
+        uint32_t *po = Ld.out + u * kFpUnitInts;
+        ok = off >= H.dir_end && end >= off && end <= H.total && (off & 3u) == 0 && nb <= kSmallPageBlocks &&
+             (H.S == 1   ? fp_small_page<1>(pg, end - off, nb, base, po, W.fp)
+              : H.S == 4 ? fp_small_page<4>(pg, end - off, nb, base, po, W.fp)
+                         : fp_small_page<0>(pg, end - off, nb, base, po, W.fp));
+        last = u + 1 == H.units;
+    } else {
+        return item.y == kItemTail && H.tail != 0 && decode_tail_entry<1, false>(Ld.comp, H, Ld.out, W.tail);
+    }
+    if (ok && last && H.tail) {
+        wave_lds_order();
+        ok = decode_tail_entry<1, false>(Ld.comp, H, Ld.out, W.tail);
+    }
+    return ok;
+}
+
+// One launch over the whole plan: workgroup g < npages decodes page item g
+// with all its wavefronts; every later workgroup gives one wavefront item
+// to each of its wavefronts (items npages + (g - npages) * WAVES + wave).
+// Items are sorted largest first, and the dispatcher starts workgroups in
+// index order as compute units free up, which balances the load without a
+// work queue.
 template <int WAVES, int DEPTH>
 __global__ __launch_bounds__(64 * WAVES) void k_batch(const DevList *__restrict__ lists,
                                                       const uint4 *__restrict__ items, uint32_t npages,
-                                                      uint32_t nitems, uint32_t grabs, uint32_t *__restrict__ counter,
-                                                      int *__restrict__ err)
+                                                      uint32_t nitems, int *__restrict__ err)
 {
-    const uint32_t grab_p = grabs & 0xffffu, grab_w = grabs >> 16;
-    const uint32_t nc = gridDim.x < kCounters ? gridDim.x : kCounters;
-    const uint32_t cls = blockIdx.x % nc;
-    uint32_t *const cnt_p = counter + cls * kCounterStride;
-    uint32_t *const cnt_w = counter + (kCounters + cls) * kCounterStride;
     __shared__ BatchLds<WAVES, DEPTH> L;
-    __shared__ uint32_t s_item;
-    const uint32_t tid = threadIdx.x;
-    const uint32_t lane = lane_id();
-    // phase 1: pages, one workgroup each: this class's pages cls + nc * k
-    uint32_t k = 0, k_end = 0;
-    while (npages > 0) {
-        if (k + 1 < k_end) {
-            ++k;
-        } else {
-            if (tid == 0)
-                s_item = atomicAdd(cnt_p, grab_p);
-            __syncthreads();
-            k = uniform(s_item);
-            k_end = k + grab_p;
-            __syncthreads();
-        }
-        const uint64_t it64 = (uint64_t)cls + (uint64_t)nc * k;
-        if (it64 >= npages)
-            break;
-        const uint32_t it = (uint32_t)it64;
-        uint4 item;
-        DevList Ld;
-        ListHdr H;
-        bool ok = item_header(lists, items, it, item, Ld, H) && item.y == kItemFpPage &&
-                  Ld.codec == WP_CODEC_FP && item.z < H.units;
-        if (ok) {
-            const uint64_t u = item.z;
-            const uint32_t off = Ld.comp[kHdrWords + u];
-            const uint32_t end = (u + 1 < H.units) ? Ld.comp[kHdrWords + u + 1] : H.tail_off;
-            uint32_t base[4] = {0u, 0u, 0u, 0u};
-            for (uint32_t s = 0; s < H.S; ++s)
-                base[s] = Ld.comp[kHdrWords + H.ndir + u * H.S + s];
-            const uint64_t left = H.nfull - u * kFpBlocks;
-            const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
-            ok = off >= H.dir_end && end >= off && end <= H.total && (off & 3u) == 0 &&
-                 (H.S == 1   ? fp_page<WAVES, 1>(Ld.comp + off, end - off, nb, base, Ld.out + u * kFpUnitInts, L.fp)
-                  : H.S == 4 ? fp_page<WAVES, 4>(Ld.comp + off, end - off, nb, base, Ld.out + u * kFpUnitInts, L.fp)
-                             : fp_page<WAVES, 0>(Ld.comp + off, end - off, nb, base, Ld.out + u * kFpUnitInts, L.fp));
-            // the list's last page also decodes its tail
-            if (u + 1 == H.units && H.tail) {
-                __syncthreads();
-                ok = decode_tail_entry<WAVES>(Ld.comp, H, Ld.out, L.tail) && ok;
-            }
-        }
-        if (!ok && tid == 0)
+    const uint32_t g = blockIdx.x;
+    if (g < npages) {
+        if (!page_item<WAVES>(lists, items, g, L.page) && threadIdx.x == 0)
             *err = kErrCorrupt;
-        __syncthreads();
+        return;
     }
-    // phase 2: runs and tails, one wavefront each (each wavefront owns its
-    // LDS slice; the page phase's last barrier is behind every wavefront)
-    const uint32_t wave = uniform(tid >> 6);
-    WaveItemLds<DEPTH> &W = L.w[wave];
-    const uint32_t nw = nitems - npages;
-    k = 0;
-    k_end = 0;
-    for (;;) {
-        if (k + 1 < k_end) {
-            ++k;
-        } else {
-            uint32_t got = 0;
-            if (lane == 0)
-                got = atomicAdd(cnt_w, grab_w);
-            k = wave_read(got, 0);
-            k_end = k + grab_w;
-        }
-        const uint64_t i64 = (uint64_t)cls + (uint64_t)nc * k;
-        if (i64 >= nw)
-            break;
-        const uint32_t it = npages + (uint32_t)i64;
-        uint4 item;
-        DevList Ld;
-        ListHdr H;
-        bool ok = item_header(lists, items, it, item, Ld, H);
-        if (ok) {
-            if (item.y == kItemBpRun) {
-                const uint32_t first = item.z, count = item.w;
-                ok = Ld.codec == WP_CODEC_BP && count >= 1 && count <= 63 && (uint64_t)first + count <= H.units;
-                if (ok)
-                    ok = H.S == 1   ? bp_wave_run<DEPTH, 1>(Ld.comp, H, first, count, Ld.out, W.r)
-                         : H.S == 4 ? bp_wave_run<DEPTH, 4>(Ld.comp, H, first, count, Ld.out, W.r)
-                                    : bp_wave_run<DEPTH, 0>(Ld.comp, H, first, count, Ld.out, W.r);
-                // the list's last run also decodes its tail
-                if (ok && first + count == H.units && H.tail) {
-                    wave_lds_order();
-                    ok = decode_tail_entry<1, false>(Ld.comp, H, Ld.out, W.tail);
-                }
-            } else if (item.y == kItemFpSmall) {
-                const uint64_t u = item.z;
-                ok = Ld.codec == WP_CODEC_FP && u < H.units;
-                if (ok) {
-                    const uint32_t off = Ld.comp[kHdrWords + u];
-                    const uint32_t end = (u + 1 < H.units) ? Ld.comp[kHdrWords + u + 1] : H.tail_off;
-                    uint32_t base[4] = {0u, 0u, 0u, 0u};
-                    for (uint32_t s = 0; s < H.S; ++s)
-                        base[s] = Ld.comp[kHdrWords + H.ndir + u * H.S + s];
-                    const uint64_t left = H.nfull - u * kFpBlocks;
-                    const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
-                    const uint32_t *pg = Ld.comp + off;
-                    uint32_t *po = Ld.out + u * kFpUnitInts;
-                    ok = off >= H.dir_end && end >= off && end <= H.total && (off & 3u) == 0 &&
-                         nb <= kSmallPageBlocks &&
-                         (H.S == 1   ? fp_small_page<1>(pg, end - off, nb, base, po, W.fp)
-                          : H.S == 4 ? fp_small_page<4>(pg, end - off, nb, base, po, W.fp)
-                                     : fp_small_page<0>(pg, end - off, nb, base, po, W.fp));
-                    // the list's last page also decodes its tail
-                    if (ok && u + 1 == H.units && H.tail) {
-                        wave_lds_order();
-                        ok = decode_tail_entry<1, false>(Ld.comp, H, Ld.out, W.tail);
-                    }
-                }
-            } else {
-                ok = item.y == kItemTail && H.tail != 0 && decode_tail_entry<1, false>(Ld.comp, H, Ld.out, W.tail);
-            }
-        }
-        if (!ok && lane == 0)
-            *err = kErrCorrupt;
-        // the next item reuses this wavefront's LDS slice
-        wave_lds_order();
-    }
+    const uint32_t wave = uniform(threadIdx.x >> 6);
+    const uint64_t it = npages + (uint64_t)(g - npages) * WAVES + wave;
+    if (it >= nitems)
+        return;
+    if (!wave_item<DEPTH>(lists, items, (uint32_t)it, L.w[wave]) && lane_id() == 0)
+        *err = kErrCorrupt;
 }
 
 struct Plan {
     int device = -1;
     DevList *d_lists = nullptr;
     uint4 *d_items = nullptr;
-    uint32_t *d_counter = nullptr;  // kCounters page counters, then kCounters run and tail counters
     uint64_t nlists = 0, nitems = 0, npages = 0;
-    uint32_t grabs = 0x00010001u;  // items per atomic: runs and tails << 16 | pages
     int waves = 4, vpl = 4, depth = 4;
     uint32_t grid = 1;
     bool use_graph = false;
@@ -233,8 +199,7 @@ struct Plan {
     uint4 *h_items_pin = nullptr;
     uint64_t pin_lists = 0, pin_items = 0;
     hipEvent_t copied = nullptr;
-    int run_units = 8, wpc = 4;
-    int cus = 256;
+    int run_units = 8;
 };
 
 template <int W, int D>
@@ -279,20 +244,24 @@ static void release(Plan *p)
         (void)hipFree(p->d_lists);
     if (p->d_items)
         (void)hipFree(p->d_items);
-    if (p->d_counter)
-        (void)hipFree(p->d_counter);
     delete p;
 }
 
-// Items claimed per atomic: 2 pages, 4 runs or tails.
-static void set_grabs(Plan *p) { p->grabs = 4u << 16 | 2u; }
+// Workgroups of a launch: one per page item, then one per `waves` wavefront
+// items (at least one workgroup).
+static uint64_t grid_for(uint64_t npages, uint64_t nitems, int waves)
+{
+    return std::max<uint64_t>(1, npages + (nitems - npages + (uint64_t)waves - 1) / (uint64_t)waves);
+}
+constexpr uint64_t kMaxGrid = 0x7FFFFFFFull;
 
 static int32_t launch_plan(Plan *p, hipStream_t st)
 {
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, p->d_counter);
+    if (p->nitems == 0)
+        return WP_OK;
     uint32_t npages32 = (uint32_t)p->npages, nitems32 = (uint32_t)p->nitems;
-    void *args[] = {&p->d_lists, &p->d_items, &npages32, &nitems32, &p->grabs, &p->d_counter, &p->err};
+    void *args[] = {&p->d_lists, &p->d_items, &npages32, &nitems32, &p->err};
     if (hipLaunchKernel(p->kernel, dim3(p->grid), dim3(64 * p->waves), args, 0, st) != hipSuccess)
         return WP_ERR_HIP;
     return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
@@ -302,19 +271,9 @@ static int32_t build_graph(Plan *p)
 {
     if (hipGraphCreate(&p->graph, 0) != hipSuccess)
         return WP_ERR_HIP;
-    hipGraphNode_t reset = nullptr, dec = nullptr;
-    void *rargs[] = {&p->d_counter};
-    hipKernelNodeParams rp = {};
-    rp.func = reinterpret_cast<void *>(&k_batch_reset);
-    rp.gridDim = dim3(1);
-    rp.blockDim = dim3(64);
-    rp.sharedMemBytes = 0;
-    rp.kernelParams = rargs;
-    rp.extra = nullptr;
-    if (hipGraphAddKernelNode(&reset, p->graph, nullptr, 0, &rp) != hipSuccess)
-        return WP_ERR_HIP;
+    hipGraphNode_t dec = nullptr;
     uint32_t npages32 = (uint32_t)p->npages, nitems32 = (uint32_t)p->nitems;
-    void *args[] = {&p->d_lists, &p->d_items, &npages32, &nitems32, &p->grabs, &p->d_counter, &p->err};
+    void *args[] = {&p->d_lists, &p->d_items, &npages32, &nitems32, &p->err};
     hipKernelNodeParams kp = {};
     kp.func = const_cast<void *>(p->kernel);
     kp.gridDim = dim3(p->grid);
@@ -322,7 +281,7 @@ static int32_t build_graph(Plan *p)
     kp.sharedMemBytes = 0;
     kp.kernelParams = args;
     kp.extra = nullptr;
-    if (hipGraphAddKernelNode(&dec, p->graph, &reset, 1, &kp) != hipSuccess)
+    if (hipGraphAddKernelNode(&dec, p->graph, nullptr, 0, &kp) != hipSuccess)
         return WP_ERR_HIP;
     if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
         return WP_ERR_HIP;
@@ -422,7 +381,8 @@ extern "C" int32_t wp_batch_plan(const uint32_t *pool, uint32_t *out_base, const
     std::vector<DevList> lists;
     std::vector<uint4> items;
     uint64_t npages = 0;
-    if (!build_items(pool, out_base, h_lists, nlists, t.run_units, lists, items, npages))
+    if (!build_items(pool, out_base, h_lists, nlists, t.run_units, lists, items, npages) ||
+        grid_for(npages, items.size(), t.waves) > kMaxGrid)
         return WP_ERR_INVALID_ARG;
     Plan *p = new Plan();
     p->device = ds->device;
@@ -436,19 +396,11 @@ extern "C" int32_t wp_batch_plan(const uint32_t *pool, uint32_t *out_base, const
     p->kernel = kern;
     p->use_graph = t.use_graph != 0;
     p->run_units = t.run_units;
-    p->cus = ds->cus;
-    // default: about kBpRunsPerCu wavefronts per compute unit
-    const uint64_t wpc = t.wg_per_cu > 0 ? (uint64_t)t.wg_per_cu : std::max<uint64_t>(1, kBpRunsPerCu / t.waves);
-    p->wpc = (int)wpc;
     p->cap_lists = std::max<uint64_t>(1, lists.size());
     p->cap_items = std::max<uint64_t>(1, items.size());
-    uint64_t grid = (uint64_t)ds->cus * wpc;
-    grid = std::max<uint64_t>(1, std::min<uint64_t>(grid, p->nitems ? p->nitems : 1));
-    p->grid = (uint32_t)grid;
-    set_grabs(p);
+    p->grid = (uint32_t)grid_for(npages, items.size(), t.waves);
     hipStream_t st = as_stream(stream);
-    if (hipMalloc(&p->d_counter, kCounterWords * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc(&p->d_lists, std::max<size_t>(1, lists.size()) * sizeof(DevList)) != hipSuccess ||
+    if (hipMalloc(&p->d_lists, std::max<size_t>(1, lists.size()) * sizeof(DevList)) != hipSuccess ||
         hipMalloc(&p->d_items, std::max<size_t>(1, items.size()) * sizeof(uint4)) != hipSuccess) {
         release(p);
         return WP_ERR_HIP;
@@ -520,7 +472,7 @@ extern "C" int32_t wp_batch_replan(void *h_plan, const uint32_t *pool, uint32_t 
     std::vector<uint4> items;
     uint64_t npages = 0;
     if (!build_items(pool, out_base, h_lists, nlists, p->run_units, lists, items, npages) ||
-        items.size() > 0xFFFFFFF0ull)
+        grid_for(npages, items.size(), p->waves) > kMaxGrid)
         return WP_ERR_INVALID_ARG;
     hipStream_t st = as_stream(stream);
     // the previous copy out of the pinned staging must have finished
@@ -579,10 +531,7 @@ extern "C" int32_t wp_batch_replan(void *h_plan, const uint32_t *pool, uint32_t 
     p->nlists = lists.size();
     p->nitems = items.size();
     p->npages = npages;
-    uint64_t grid = (uint64_t)p->cus * (uint64_t)p->wpc;
-    grid = std::max<uint64_t>(1, std::min<uint64_t>(grid, p->nitems ? p->nitems : 1));
-    p->grid = (uint32_t)grid;
-    set_grabs(p);
+    p->grid = (uint32_t)grid_for(npages, items.size(), p->waves);
     // the graph baked in the old item count and grid
     if (p->exec)
         (void)hipGraphExecDestroy(p->exec), p->exec = nullptr;

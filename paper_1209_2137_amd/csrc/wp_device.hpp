@@ -50,6 +50,16 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// A pointer read from memory is generic to the compiler (flat loads and
+// stores); rebuilding it as a global-memory pointer lets the compiler use
+// global loads and stores.
+template <typename T>
+__device__ __forceinline__ T *as_global(T *p)
+{
+    typedef __attribute__((address_space(1))) T *GPtr;
+    return (T *)(GPtr)reinterpret_cast<uintptr_t>(p);
+}
+
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 // Inclusive prefix sum inside each row of 16 lanes (row_shr 1, 2, 4, 8).
@@ -129,15 +139,17 @@ struct Hdr {
 
 __device__ __forceinline__ Hdr load_hdr(const uint32_t *in)
 {
+    // uniform() keeps the fields in scalar registers also when `in` was
+    // itself read from memory (a generic pointer, loaded per lane)
     Hdr h;
-    h.magic = in[0];
-    h.n_lo = in[1];
-    h.n_hi = in[2];
-    h.stride = in[3];
-    h.n_units = in[4];
-    h.tail_bytes = in[5];
-    h.tail_off = in[6];
-    h.total = in[7];
+    h.magic = uniform(in[0]);
+    h.n_lo = uniform(in[1]);
+    h.n_hi = uniform(in[2]);
+    h.stride = uniform(in[3]);
+    h.n_units = uniform(in[4]);
+    h.tail_bytes = uniform(in[5]);
+    h.tail_off = uniform(in[6]);
+    h.total = uniform(in[7]);
     return h;
 }
 
@@ -311,7 +323,7 @@ struct TailLds {
 // WG: the whole workgroup of WAVES wavefronts takes part; otherwise one
 // wavefront by itself (WAVES == 1, no workgroup barrier).
 template <int WAVES, bool WG = true>
-__device__ bool tail_decode(const uint32_t *__restrict__ tw, uint32_t tail_bytes, uint32_t count,
+__device__ __forceinline__ bool tail_decode(const uint32_t *__restrict__ tw, uint32_t tail_bytes, uint32_t count,
                             uint32_t S, const uint32_t (&base)[4], uint32_t *__restrict__ out,
                             TailLds<WAVES> &L)
 {
@@ -412,13 +424,13 @@ __device__ bool tail_decode(const uint32_t *__restrict__ tw, uint32_t tail_bytes
 // The list's tail entry (directory entry n_units): offset check, bases,
 // then tail_decode. Called by a whole workgroup (WG) or one wavefront.
 template <int WAVES, bool WG = true>
-__device__ bool decode_tail_entry(const uint32_t *__restrict__ in, const ListHdr &H, uint32_t *__restrict__ out,
+__device__ __forceinline__ bool decode_tail_entry(const uint32_t *__restrict__ in, const ListHdr &H, uint32_t *__restrict__ out,
                                   TailLds<WAVES> &L)
 {
-    const uint32_t off = in[kHdrWords + H.units];
-    uint32_t base[4] = {0u, 0u, 0u, 0u};
-    for (uint32_t s = 0; s < H.S; ++s)
-        base[s] = in[kHdrWords + H.ndir + H.units * H.S + s];
+    const uint32_t off = uniform(in[kHdrWords + H.units]);
+    const uint32_t *bp = in + kHdrWords + H.ndir + H.units * H.S;
+    const uint32_t base[4] = {H.S > 0 ? uniform(bp[0]) : 0u, H.S > 1 ? uniform(bp[1]) : 0u,
+                              H.S > 2 ? uniform(bp[2]) : 0u, H.S > 3 ? uniform(bp[3]) : 0u};
     if (!(off == H.tail_off && (uint64_t)off + (H.tail_bytes + 3) / 4 == H.total))
         return false;
     return tail_decode<WAVES, WG>(in + off, H.tail_bytes, H.tail, H.S, base, out + H.nfull * kBlock, L);
@@ -434,7 +446,7 @@ __device__ bool decode_tail_entry(const uint32_t *__restrict__ in, const ListHdr
 // as is L.ktot). Rounds of T blocks; within a wavefront the same-k ranks
 // come from one masked scan per distinct k (ballot loop).
 template <int WAVES>
-__device__ void fp_tables(FpLds<WAVES> &L, uint32_t nb, uint32_t &tot_words, uint32_t &tot_pos)
+__device__ __forceinline__ void fp_tables(FpLds<WAVES> &L, uint32_t nb, uint32_t &tot_words, uint32_t &tot_pos)
 {
     constexpr int T = 64 * WAVES;
     const uint32_t tid = threadIdx.x;
@@ -684,7 +696,7 @@ struct FpPair {
 // words and exceptions in flight; one barrier per pass hands the wavefront
 // totals over for the prefix sum.
 template <int WAVES, uint32_t S>
-__device__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint32_t nb,
+__device__ __forceinline__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint32_t nb,
                         const uint32_t (&base)[4], uint32_t *__restrict__ out, FpLds<WAVES> &L)
 {
     constexpr int T = 64 * WAVES;
@@ -694,7 +706,8 @@ __device__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint
     const uint32_t wave = uniform(tid >> 6);
     if (nwords < 4)
         return false;
-    const uint32_t h_nb = page[0], packed_words = page[1], meta_bytes = page[2], bitset = page[3];
+    const uint32_t h_nb = uniform(page[0]), packed_words = uniform(page[1]), meta_bytes = uniform(page[2]),
+                   bitset = uniform(page[3]);
     const uint32_t nset = __builtin_popcount(bitset);
     const uint32_t hdr_w = pad4(4 + nset);
     const uint32_t meta_w = ((meta_bytes + 15u) / 16u) * 4u;
@@ -859,7 +872,7 @@ struct alignas(16) FpWaveLds {
 };
 
 template <uint32_t S>
-__device__ bool fp_small_page(const uint32_t *__restrict__ page, uint32_t nwords, uint32_t nb,
+__device__ __forceinline__ bool fp_small_page(const uint32_t *__restrict__ page, uint32_t nwords, uint32_t nb,
                               const uint32_t (&base)[4], uint32_t *__restrict__ out, FpWaveLds &L)
 {
     const uint32_t lane = lane_id();
@@ -1017,7 +1030,7 @@ __device__ __forceinline__ bool byte_over32(uint32_t d)
 // stops, its output is unspecified but every store stays inside the run's
 // output range.
 template <int DEPTH, uint32_t S>
-__device__ bool bp_wave_run(const uint32_t *__restrict__ in, const ListHdr &H, uint64_t ua, uint32_t cnt,
+__device__ __forceinline__ bool bp_wave_run(const uint32_t *__restrict__ in, const ListHdr &H, uint64_t ua, uint32_t cnt,
                             uint32_t *__restrict__ out, WaveLds<DEPTH> &L)
 {
     using G = WaveGeo<DEPTH>;

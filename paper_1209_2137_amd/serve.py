@@ -3,8 +3,8 @@
 Requests arrive over time; each asks for a set of lists of the pool to be
 decoded into the caller's buffer. The loop admits arrived requests while
 the output arena (an HBM budget) has room, groups every admitted request
-not yet launched into one micro-batch, and launches it (one persistent
-batched decode) on the next free stream, so batches overlap on the device
+not yet launched into one micro-batch, and launches it (one batched
+decode launch) on the next free stream, so batches overlap on the device
 while new requests keep arriving. A request is complete when its batch's
 completion event has fired; its latency is completion minus arrival (host
 clock, polled).

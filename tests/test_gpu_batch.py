@@ -1,4 +1,4 @@
-"""Batched persistent decoding on the GPU: every list decoded in one launch
+"""Batched decoding on the GPU: every list decoded in one launch
 must equal its generator array (which the single-list path and the CPU
 oracle decode to as well), for graph and plain launches and for every
 workgroup shape. Integer work: exact comparison."""
