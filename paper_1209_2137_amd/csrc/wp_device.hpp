@@ -285,18 +285,26 @@ __device__ __forceinline__ void unpack_lane(const uint32_t *words, uint32_t bit0
 
 // Page tables of a patched page (shared by the encoder and the decoder)
 // plus, for the decoder, each wavefront's staging and transposition areas.
+// The per-block tables are dead once the block records are built, so the
+// passes' areas overlay them.
 template <int WAVES>
 struct FpLds {
-    uint32_t stage[WAVES][2 * kBlock + 4];  // a wavefront's two blocks of packed words (+1 word)
-    uint32_t xp[WAVES][2 * kBlock];         // a wavefront's two blocks, transposed and patched
-    uint4 rec[kFpBlocks];                   // per block: {b | k << 8 | c << 16, packed word offset,
-                                            //  bit offset of its first exception's high part, position offset}
-    uint8_t b[kFpBlocks];
-    uint8_t mb[kFpBlocks];
-    uint8_t c[kFpBlocks];
-    uint32_t blkoff[kFpBlocks + 1];  // word offset of each block in the packed region
-    uint32_t posoff[kFpBlocks + 1];  // offset of each block's positions
-    uint32_t rank[kFpBlocks];        // index of the block's first exception in its array
+    union {
+        struct {
+            uint32_t stage[WAVES][2 * kBlock + 4];  // a wavefront's two blocks of packed words (+1 word)
+            uint32_t xp[WAVES][2 * kBlock];         // a wavefront's two blocks, transposed and patched
+        };
+        struct {
+            uint8_t b[kFpBlocks];
+            uint8_t mb[kFpBlocks];
+            uint8_t c[kFpBlocks];
+            uint32_t blkoff[kFpBlocks + 1];  // word offset of each block in the packed region
+            uint32_t posoff[kFpBlocks + 1];  // offset of each block's positions
+            uint32_t rank[kFpBlocks];        // index of the block's first exception in its array
+        };
+    };
+    uint4 rec[kFpBlocks];  // per block: {b | k << 8 | c << 16, packed word offset,
+                           //  bit offset of its first exception's high part, position offset}
     uint32_t ktot[WAVES][33];
     uint32_t kcar[33];
     uint32_t excbase[33];            // word offset of array k from the page start

@@ -224,6 +224,7 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
                                                  uint32_t *__restrict__ out)
 {
     __shared__ FpLds<8> L;
+    __shared__ uint32_t sw_all[8][2 * kBlock];  // a wavefront's packed words (L.xp overlays the tables)
     constexpr int T = 512;
     const uint64_t p = blockIdx.x;
     const uint32_t tid = threadIdx.x;
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
         mbytes[nb + t] = L.mb[t];
         mbytes[2 * nb + t] = L.c[t];
     }
-    uint32_t *sw = L.xp[wave];
+    uint32_t *sw = sw_all[wave];
     const uint32_t rounds = (nb + 7) / 8;
     for (uint32_t it = 0; it < rounds; ++it) {
         const uint32_t t = it * 8 + wave;
