@@ -102,18 +102,23 @@ def replicas(t, nbytes_each):
     return [t] + [t.clone() for _ in range(r - 1)]
 
 
-def bench_single(wp, x_np, codec, stride, steps, warmup, name):
+def bench_single(wp, x_np, codec, stride, steps, warmup, name, comp=None, n=None):
+    """Decoder timing on x_np, encoded here; or on a given stream `comp`
+    (device) of n integers, with no comparison against the input."""
     import torch
-    xd = to_dev(x_np)
-    n = x_np.size
-    comp = wp.encode_trimmed(xd, codec, stride)
+    if comp is None:
+        xd = to_dev(x_np)
+        n = x_np.size
+        comp = wp.encode_trimmed(xd, codec, stride)
+    else:
+        xd = None
     comps = replicas(comp, comp.numel() * 4)
     outs = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(2)]
     dec = wp.bp_decode if codec == wp.CODEC_BP else wp.fastpfor_decode
     stream = torch.cuda.current_stream()
     dec(comps[0], n, outs[0])
     wp.check()
-    if not torch.equal(outs[0], xd):
+    if xd is not None and not torch.equal(outs[0], xd):
         raise RuntimeError(f"{name}: decoded output differs from the input")
     del xd
     wall, ev = time_launches(lambda i: dec(comps[i % len(comps)], n, outs[i % 2]), steps, warmup, stream,
@@ -128,6 +133,30 @@ def bench_single(wp, x_np, codec, stride, steps, warmup, name):
         "alg_bytes": alg, "achieved_gbs": alg / (ev * 1e-3) / 1e9,
         "hbm_frac": alg / (ev * 1e-3) / 1e9 / HBM_PEAK_GBS, "replicas": len(comps),
     }
+
+
+def bench_encode(wp, x_np, codec, stride, steps, warmup, name):
+    """Encoder throughput (all its kernels, timed as one call): algorithmic
+    bytes = the input read once plus the stream written."""
+    import torch
+    xd = to_dev(x_np)
+    n = x_np.size
+    xs = replicas(xd, n * 4)
+    enc = wp.bp_encode if codec == wp.CODEC_BP else wp.fastpfor_encode
+    buf, words = enc(xd, stride)
+    wp.check()
+    comp_words = int(words.item())
+    bufs = [buf, torch.empty_like(buf)]
+    stream = torch.cuda.current_stream()
+    wall, ev = time_launches(lambda i: enc(xs[i % len(xs)], stride, out=bufs[i % 2], out_words=words), steps,
+                             warmup, stream)
+    wp.check()
+    if int(words.item()) != comp_words:
+        raise RuntimeError(f"{name}: the stream length changed between calls")
+    alg = 4 * n + 4 * comp_words
+    return {"name": name, "n": n, "ms_per_step": wall, "event_ms": ev, "gints_per_s": n / (ev * 1e-3) / 1e9,
+            "bits_per_int": comp_words * 32 / n, "alg_bytes": alg, "achieved_gbs": alg / (ev * 1e-3) / 1e9,
+            "hbm_frac": alg / (ev * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def bench_delta(wp, n, steps, warmup):
@@ -153,16 +182,13 @@ def bench_copy(n_bytes, steps, warmup):
     return {"bytes": 2 * n_bytes, "kernel_ms": ev, "gbs": 2 * n_bytes / (ev * 1e-3) / 1e9}
 
 
-def bench_batch(wp, steps, warmup, n_lists=100_000, total=1.2e9, per_list_passes=2):
+def bench_batch(wp, steps, warmup, per_list_passes=2):
     """Posting-list pool: one batched decode launch (hipGraph) vs one
     single-list launch per list on the same stream."""
     import torch
-    from paper_1209_2137_amd import datagen
     from paper_1209_2137_amd.autotune import batch_tune
-    from paper_1209_2137_amd.pool import ListPool
     t0 = time.perf_counter()
-    lens, codec, means, list_array = datagen.posting_lists(n_lists=n_lists, total=total, seed=5)
-    pool = ListPool(list_array, codec, stride=1, count=n_lists, keep_values=True)
+    pool = posting_pool(True)
     t_setup = time.perf_counter() - t0
     out = torch.zeros(pool.total_out + 4, dtype=torch.int32, device="cuda")
     tune = batch_tune() or dict(waves=4, vpl=4, depth=3, run_units=4, wg_per_cu=0, use_graph=1)
@@ -275,26 +301,91 @@ def rocprof_summary(d):
     print("\n".join(lines))
 
 
-def profile_run(steps):
-    """For rocprofv3: the headline decode, the 2^28 patched decode and the
-    2^28 in-place delta decode `steps` times each (after their warm-ups),
-    then a 1 GiB device copy `steps` times (the counter calibration)."""
+def posting_pool(keep_values):
+    from paper_1209_2137_amd import datagen
+    from paper_1209_2137_amd.pool import ListPool
+    lens, codec, means, list_array = datagen.posting_lists(n_lists=100_000, total=1.2e9, seed=5)
+    return ListPool(list_array, codec, stride=1, count=len(lens), keep_values=keep_values)
+
+
+def prepare_inputs(d):
+    """Encodes the profiled workloads on the GPU and saves the streams in d,
+    so that a profiled run (--profile-run --inputs d) launches decoders
+    only."""
+    import numpy as np
     import torch
     import paper_1209_2137_amd as wp
     from paper_1209_2137_amd import datagen
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
     wp.lib()
-    x = datagen.cluster_sorted(1 << 26, seed=2)
-    r = bench_single(wp, x, wp.CODEC_BP, 1, steps, 2, "bp cluster 2^26")
-    del x
-    xf = datagen.patched_gaps(1 << 28, seed=4)
-    f = bench_single(wp, xf, wp.CODEC_FP, 1, steps, 2, "fastpfor patched 2^28")
-    del xf
+    os.makedirs(d, exist_ok=True)
+    for name, x, codec in (("bp_cluster_2e26", datagen.cluster_sorted(1 << 26, seed=2), wp.CODEC_BP),
+                           ("fp_patched_2e28", datagen.patched_gaps(1 << 28, seed=4), wp.CODEC_FP)):
+        comp = wp.encode_trimmed(to_dev(x), codec, 1)
+        np.save(os.path.join(d, name + ".npy"), comp.cpu().numpy())
+        np.save(os.path.join(d, name + ".n.npy"), np.array([x.size], dtype=np.int64))
+    packed, rows = posting_pool(False).streams()
+    np.save(os.path.join(d, "pool_words.npy"), packed)
+    np.save(os.path.join(d, "pool_rows.npy"), rows)
+    print(json.dumps({"prepared": d}))
+    return 0
+
+
+def profile_batch(wp, steps, pool):
+    """The posting-list pool decoded `steps` times by one batched launch
+    each (no per-list leg, no value check: the tests cover it)."""
+    import torch
+    from paper_1209_2137_amd.autotune import batch_tune
+    out = torch.empty(pool.total_out + 4, dtype=torch.int32, device="cuda")
+    plan = pool.plan(out, tune=dict(batch_tune() or {}, use_graph=1))
+    _, ev = time_launches(lambda i: plan.decode(), steps, 2, torch.cuda.current_stream())
+    wp.check()
+    plan.free()
+    return {"ms": ev, "alg_bytes": pool.comp_bytes + 4 * pool.total_n, "n": pool.total_n}
+
+
+def profile_run(steps, inputs=None):
+    """For rocprofv3: the headline decode, the 2^28 patched decode, the
+    2^28 in-place delta decode and the batched posting-list decode `steps`
+    times each (after their warm-ups), then a 1 GiB device copy `steps`
+    times (the counter calibration). With `inputs` (a directory written by
+    --prepare-inputs) the streams are loaded instead of encoded here."""
+    import numpy as np
+    import torch
+    import paper_1209_2137_amd as wp
+    from paper_1209_2137_amd import datagen
+    from paper_1209_2137_amd.pool import ListPool
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    wp.lib()
+
+    def single(name, make, codec, label):
+        if inputs is None:
+            return bench_single(wp, make(), codec, 1, steps, 2, label)
+        comp = torch.from_numpy(np.load(os.path.join(inputs, name + ".npy"))).to("cuda")
+        n = int(np.load(os.path.join(inputs, name + ".n.npy"))[0])
+        return bench_single(wp, None, codec, 1, steps, 2, label, comp=comp, n=n)
+
+    r = single("bp_cluster_2e26", lambda: datagen.cluster_sorted(1 << 26, seed=2), wp.CODEC_BP, "bp cluster 2^26")
+    f = single("fp_patched_2e28", lambda: datagen.patched_gaps(1 << 28, seed=4), wp.CODEC_FP,
+               "fastpfor patched 2^28")
     d = bench_delta(wp, 1 << 28, steps, 2)
+    if inputs is None:
+        pool = posting_pool(False)
+    else:
+        pool = ListPool.from_streams(np.load(os.path.join(inputs, "pool_words.npy")),
+                                     np.load(os.path.join(inputs, "pool_rows.npy")))
+    b = profile_batch(wp, steps, pool)
+    del pool
     c = bench_copy(1 << 30, steps, 0)
     torch.cuda.synchronize()
     print(json.dumps({"decode_kernel_ms": r["kernel_ms"], "decode_alg_bytes": r["alg_bytes"],
                       "fp_kernel_ms": f["kernel_ms"], "fp_alg_bytes": f["alg_bytes"],
                       "delta_kernel_ms": d["kernel_ms"], "delta_alg_bytes": 8 * (1 << 28),
+                      "batch_ms": b["ms"], "batch_alg_bytes": b["alg_bytes"], "batch_n": b["n"],
                       "copy_bytes_each_way": 1 << 30, "copy_kernel_ms": c["kernel_ms"],
                       "kernel_hash": kernel_hash()}))
     return 0
@@ -312,15 +403,20 @@ def main():
                     help="length of the serving run (the full workload is 60 s)")
     ap.add_argument("--rocprof-summary", metavar="DIR")
     ap.add_argument("--profile-run", action="store_true",
-                    help="for rocprofv3: the headline decode, the 2^28 patched decode and the 2^28 "
-                         "in-place delta decode `--steps` times each, then a 1 GiB device copy (the "
-                         "counter calibration kernel) `--steps` times")
+                    help="for rocprofv3: the headline decode, the 2^28 patched decode, the 2^28 "
+                         "in-place delta decode and the batched posting-list decode `--steps` times each, "
+                         "then a 1 GiB device copy (the counter calibration kernel) `--steps` times")
+    ap.add_argument("--inputs", metavar="DIR", help="with --profile-run: load the streams saved by --prepare-inputs")
+    ap.add_argument("--prepare-inputs", metavar="DIR",
+                    help="encode the profiled workloads and save their streams in DIR (run it without the profiler)")
     args = ap.parse_args()
     if args.rocprof_summary:
         rocprof_summary(args.rocprof_summary)
         return 0
+    if args.prepare_inputs:
+        return prepare_inputs(args.prepare_inputs)
     if args.profile_run:
-        return profile_run(args.steps)
+        return profile_run(args.steps, args.inputs)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (this build decodes on a "
               "single MI355X; lists and units shard across GPUs without any exchange, see the design notes)",
@@ -352,6 +448,11 @@ def main():
         print("# patched done", file=sys.stderr, flush=True)
         extra["delta_inplace_2e28"] = bench_delta(wp, 1 << 28, args.steps, args.warmup)
         print("# delta done", file=sys.stderr, flush=True)
+        extra["bp_encode_cluster_2e26"] = bench_encode(wp, x, wp.CODEC_BP, 1, args.steps, args.warmup,
+                                                       "bp_encode cluster 2^26")
+        extra["fp_encode_patched_2e28"] = bench_encode(wp, datagen.patched_gaps(1 << 28, seed=4), wp.CODEC_FP, 1,
+                                                       args.steps, args.warmup, "fastpfor_encode patched 2^28")
+        print("# encoders done", file=sys.stderr, flush=True)
         head["pct_of_copy"] = head["achieved_gbs"] / copy["gbs"]
         if not args.no_batch:
             extra["batched_posting_lists"], pool = bench_batch(wp, max(3, args.steps // 2), 2)

@@ -57,6 +57,15 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                            "(wavepack has no CPU fallback)")
+    # let torch bring the HIP runtime up first (as every caller that hands
+    # the library torch tensors has done): the library's own code objects
+    # then load into the runtime torch uses
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except Exception:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp, u64, i32, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint32
     for name in ("bp_encode", "fastpfor_encode"):

@@ -79,6 +79,41 @@ class ListPool:
         if not keep_values:
             self.values = None
 
+    def streams(self):
+        """The compressed lists back to back in one host uint32 array (each
+        stream on a 4-word boundary) and their registry rows, with offsets
+        into that array; from_streams() makes a pool of them again."""
+        words = self.pool.cpu().numpy().view(np.uint32)
+        offs, o = [], 0
+        for co, cw, _, _, _ in self.rows:
+            offs.append(o)
+            o += _round4(cw)
+        packed = np.zeros(max(o, 4), dtype=np.uint32)
+        for (co, cw, _, _, _), po in zip(self.rows, offs):
+            packed[po:po + cw] = words[co:co + cw]
+        rows = np.array([(po, cw, oo, n, codec) for (_, cw, oo, n, codec), po in zip(self.rows, offs)],
+                        dtype=np.int64).reshape(-1, 5)
+        return packed, rows
+
+    @classmethod
+    def from_streams(cls, packed, rows, device="cuda"):
+        """A resident pool of already compressed lists (the arrays returned
+        by streams()); no input values are kept."""
+        import torch
+        self = cls.__new__(cls)
+        packed = np.ascontiguousarray(packed, dtype=np.uint32)
+        self.pool = torch.from_numpy(packed.view(np.int32)).to(device)
+        rows = np.asarray(rows, dtype=np.int64).reshape(-1, 5)
+        self.rows = [tuple(int(v) for v in r) for r in rows]
+        self.lens = rows[:, 3].copy()
+        self.codecs = rows[:, 4].astype(np.int32)
+        self.out_offsets = rows[:, 2].copy()
+        self.total_out = int(max((r[2] + _round4(r[3]) for r in self.rows), default=0))
+        self.total_n = int(self.lens.sum())
+        self.comp_bytes = int(4 * rows[:, 1].sum())
+        self.values = None
+        return self
+
     def rows_for(self, ids, out_offsets):
         """Registry rows of lists `ids` writing to the given output offsets."""
         return [(self.rows[i][0], self.rows[i][1], int(oo), self.rows[i][3], self.rows[i][4])

@@ -43,6 +43,23 @@ def test_pool_streams_match_oracle_encoder(pool):
         assert np.array_equal(p[co:co + cw], want), i
 
 
+def test_pool_streams_round_trip(pool):
+    # the packed streams make a pool again whose batched decode equals the inputs
+    packed, rows = pool.streams()
+    again = ListPool.from_streams(packed, rows)
+    assert again.total_n == pool.total_n and again.comp_bytes == pool.comp_bytes
+    assert again.total_out == pool.total_out
+    out = torch.full((pool.total_out + 64,), -1, dtype=torch.int32, device="cuda")
+    plan = again.plan(out)
+    plan.decode()
+    assert wp.check_code() == wp.OK
+    for i, (co, cw, oo, n, codec) in enumerate(pool.rows):
+        assert again.rows[i][1:] == (cw, oo, n, codec)
+        if not torch.equal(out[oo:oo + n], pool.values[oo:oo + n]):
+            raise AssertionError(f"list {i} (codec {codec}, n {n}) differs")
+    plan.free()
+
+
 @pytest.mark.parametrize("tune", TUNES, ids=lambda t: "w{waves}v{vpl}d{depth}r{run_units}c{wg_per_cu}g{use_graph}".format(**t))
 def test_batch_decode_matches_inputs(pool, tune):
     out = torch.full((pool.total_out + 64,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
