@@ -11,6 +11,8 @@
 // Bits are OR-ed into place (LDS atomics for a block's packed words,
 // device atomics for a page's exception arrays, after the region has been
 // cleared), so the order in which lanes write never matters.
+#include <type_traits>
+
 #include "wp_device.hpp"
 #include "wp_host.hpp"
 
@@ -26,24 +28,6 @@ __device__ __forceinline__ uint32_t delta_at(const uint32_t *__restrict__ x, uin
     if (S == 0)
         return v;
     return i >= S ? v - x[i - S] : v;
-}
-
-__device__ __forceinline__ uint32_t wave_or(uint32_t v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1)
-        v |= (uint32_t)__shfl_xor((int)v, m, 64);
-    return v;
-}
-
-__device__ __forceinline__ uint32_t wave_max(uint32_t v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const uint32_t o = (uint32_t)__shfl_xor((int)v, m, 64);
-        v = o > v ? o : v;
-    }
-    return v;
 }
 
 // ORs the low b bits of value i of a block into the block's word string
@@ -78,95 +62,153 @@ __host__ __device__ __forceinline__ uint64_t dir_entries(uint64_t n, uint64_t pe
 
 // ------------------------------------------------------------------------
 // Binary packing (Section 6.2): block width = bits of the OR of its deltas.
+//
+// One workgroup of 256 threads per meta-block: thread t holds integers
+// 8t .. 8t+7 (two 16-byte loads), so block j is the 16 threads of row j of
+// the workgroup's wavefronts; the deltas' predecessors come from the
+// neighbouring lane, and from memory for a wavefront's first lane.
+
+// Deltas of integers i0 .. i0+7 of the unit starting at integer u0 (full
+// blocks only: integers at or beyond `lim` read as 0).
+__device__ __forceinline__ void unit_deltas8(const uint32_t *__restrict__ x, uint64_t u0, uint64_t lim, uint32_t S,
+                                             uint32_t (&d)[8])
+{
+    const uint32_t tid = threadIdx.x;
+    const uint64_t i0 = u0 + 8ull * tid;
+    const uint64_t have = lim > u0 ? lim - u0 : 0;
+    const BufRsrc rs = make_rsrc(x + u0, (uint32_t)((have < kBpUnitInts ? have : kBpUnitInts) * 4u));
+    const uint4 a = buf_load_u4(rs, tid * 32u), c = buf_load_u4(rs, tid * 32u + 16u);
+    const uint32_t v[8] = {a.x, a.y, a.z, a.w, c.x, c.y, c.z, c.w};
+    if (S == 0) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            d[r] = v[r];
+        return;
+    }
+    // the four integers before i0: the previous lane's last four, or from
+    // memory for lane 0 (0 before the array start)
+    uint32_t pv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        pv[r] = (uint32_t)__shfl_up((int)v[4 + r], 1, 64);
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            pv[r] = (i0 >= (uint64_t)(4 - r) && i0 - 4 + r < lim) ? x[i0 - 4 + r] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const uint32_t before = S == 1 ? (r == 0 ? pv[3] : v[r - 1]) : (r < 4 ? pv[r] : v[r - 4]);
+        d[r] = v[r] - before;
+    }
+}
 
 __global__ __launch_bounds__(256) void k_bp_analyze(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
                                                     uint8_t *__restrict__ widths, uint32_t *__restrict__ sizes)
 {
     __shared__ uint32_t s_b[kBpBlocks];
     const uint64_t u = blockIdx.x;
-    const uint32_t lane = lane_id();
-    const uint32_t wave = uniform(threadIdx.x >> 6);
+    const uint32_t tid = threadIdx.x;
     const uint64_t nfull = n / kBlock;
+    uint32_t d[8];
+    unit_deltas8(x, u * kBpUnitInts, nfull * kBlock, S, d);
+    uint32_t o = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+        o |= d[r];
+    // OR over the block's 16 threads (one row of 16 lanes)
+#pragma unroll
+    for (int m = 1; m < 16; m <<= 1)
+        o |= (uint32_t)__shfl_xor((int)o, m, 64);
     const uint64_t left = nfull - u * kBpBlocks;
     const uint32_t nb = (uint32_t)(left < kBpBlocks ? left : kBpBlocks);
-    for (uint32_t jj = 0; jj < 4; ++jj) {
-        const uint32_t j = wave * 4 + jj;
-        uint32_t b = 0;
-        if (j < nb) {
-            const uint64_t i0 = (u * kBpBlocks + j) * kBlock + 2 * lane;
-            b = nbits(wave_or(delta_at(x, i0, S) | delta_at(x, i0 + 1, S)));
-        }
-        if (lane == 0)
-            s_b[j] = b;
-    }
+    const uint32_t j = tid >> 4;
+    if ((tid & 15u) == 0)
+        s_b[j] = j < nb ? nbits(o) : 0u;
     __syncthreads();
-    if (threadIdx.x < kBpBlocks)
-        widths[u * kBpBlocks + threadIdx.x] = (uint8_t)s_b[threadIdx.x];
-    if (threadIdx.x == 0) {
+    if (tid < kBpBlocks)
+        widths[u * kBpBlocks + tid] = (uint8_t)s_b[tid];
+    if (tid == 0) {
         uint32_t sum = 0;
-        for (uint32_t j = 0; j < kBpBlocks; ++j)
-            sum += s_b[j];
+        for (uint32_t jj = 0; jj < kBpBlocks; ++jj)
+            sum += s_b[jj];
         sizes[u] = 4 + 4 * sum;
     }
 }
 
+// The meta-block is assembled in LDS (descriptor, then the blocks' words,
+// fields OR-ed in by LDS atomics) and written with 16-byte stores: unit
+// offsets are multiples of 4 words.
 __global__ __launch_bounds__(256) void k_bp_pack(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
                                                  const uint8_t *__restrict__ widths,
                                                  const uint32_t *__restrict__ incl, uint32_t dir_end,
                                                  uint32_t *__restrict__ out)
 {
-    __shared__ uint32_t s_w[4][kBlock];
+    __shared__ __align__(16) uint32_t s_u[4 + kBpUnitInts];
     __shared__ uint32_t s_b[kBpBlocks], s_off[kBpBlocks];
     const uint64_t u = blockIdx.x;
     const uint32_t tid = threadIdx.x;
-    const uint32_t lane = lane_id();
-    const uint32_t wave = uniform(tid >> 6);
     const uint64_t nfull = n / kBlock;
-    const uint64_t left = nfull - u * kBpBlocks;
-    const uint32_t nb = (uint32_t)(left < kBpBlocks ? left : kBpBlocks);
+    uint32_t d[8];
+    unit_deltas8(x, u * kBpUnitInts, nfull * kBlock, S, d);
     if (tid < kBpBlocks) {
         uint32_t pre = 0;
         for (uint32_t j = 0; j < tid; ++j)
             pre += widths[u * kBpBlocks + j];
         s_b[tid] = widths[u * kBpBlocks + tid];
-        s_off[tid] = 4 * pre;
+        s_off[tid] = 4 + 4 * pre;
     }
     __syncthreads();
-    const uint32_t size = s_off[kBpBlocks - 1] + 4 * s_b[kBpBlocks - 1] + 4;
+    const uint32_t size = s_off[kBpBlocks - 1] + 4 * s_b[kBpBlocks - 1];
+    for (uint32_t i = tid; i < size; i += 256)
+        s_u[i] = 0;
+    __syncthreads();
+    if (tid < 4)
+        s_u[tid] = s_b[4 * tid] | (s_b[4 * tid + 1] << 8) | (s_b[4 * tid + 2] << 16) | (s_b[4 * tid + 3] << 24);
+    const uint32_t j = tid >> 4, b = s_b[j];
+    if (b) {
+        uint32_t *const w = s_u + s_off[j];
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            or_field(w, 8 * (tid & 15u) + r, b, d[r]);
+    }
     const uint32_t off = dir_end + incl[u] - size;
     write_dir_entry(out, u, dir_entries(n, kBpBlocks), S, off, x, u * kBpUnitInts);
-    if (tid < 4)
-        out[off + tid] = s_b[4 * tid] | (s_b[4 * tid + 1] << 8) | (s_b[4 * tid + 2] << 16) | (s_b[4 * tid + 3] << 24);
-    for (uint32_t jj = 0; jj < 4; ++jj) {
-        const uint32_t j = wave * 4 + jj;
-        const uint32_t b = s_b[j];
-        for (uint32_t i = lane; i < 4 * b; i += 64)
-            s_w[wave][i] = 0;
-        __syncthreads();
-        if (j < nb && b) {
-            const uint64_t i0 = (u * kBpBlocks + j) * kBlock + 2 * lane;
-            or_field(s_w[wave], 2 * lane, b, delta_at(x, i0, S));
-            or_field(s_w[wave], 2 * lane + 1, b, delta_at(x, i0 + 1, S));
-        }
-        __syncthreads();
-        if (j < nb)
-            for (uint32_t i = lane; i < 4 * b; i += 64)
-                out[off + 4 + s_off[j] + i] = s_w[wave][i];
-        __syncthreads();
-    }
+    __syncthreads();
+    uint4 *const dst = reinterpret_cast<uint4 *>(out + off);
+    const uint4 *const src = reinterpret_cast<const uint4 *>(s_u);
+    for (uint32_t i = tid; i < size / 4; i += 256)
+        dst[i] = src[i];
 }
 
 // ------------------------------------------------------------------------
 // Patched pages (Section 5): per block, the width b minimising
 // 128*b + c(b)*(8 + maxb - b) over b in [0, maxb], c(b) = values wider than
-// b; scanning b downward from maxb, only a strictly smaller cost replaces
-// the current choice.
+// b; among equal costs the largest b (the rule scans b downward from maxb
+// and only a strictly smaller cost replaces the current choice).
+//
+// One wavefront per block: the 128 widths go into a 33-bin LDS histogram
+// (eight copies, one per 16-lane row and value slot, so that an atomic add
+// meets at most 16 lanes on one bin), lane b then holds c(b) (values minus
+// the inclusive prefix of the bins up to b), its cost, and one minimum over
+// the wavefront of (cost << 6 | 63 - b) picks the width.
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint32_t o = (uint32_t)__shfl_xor((int)v, m, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
 
 __global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
                                                     uint8_t *__restrict__ meta, uint64_t nblk,
                                                     uint32_t *__restrict__ sizes)
 {
     __shared__ uint32_t s_cnt[33];
+    __shared__ uint32_t s_hist[8][8 * 33];
     __shared__ uint32_t s_pw, s_pc;
     const uint64_t p = blockIdx.x;
     const uint32_t tid = threadIdx.x;
@@ -180,22 +222,42 @@ __global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__
     if (tid == 0)
         s_pw = 0, s_pc = 0;
     __syncthreads();
+    uint32_t *const h = s_hist[wave];
+    // deltas of the wavefront's next block, loaded one block ahead
+    auto load_d = [&](uint32_t t, uint32_t &d0, uint32_t &d1) __attribute__((always_inline)) {
+        d0 = d1 = 0;
+        if (t < nb) {
+            const uint64_t i0 = (p * kFpBlocks + t) * kBlock + 2 * lane;
+            d0 = delta_at(x, i0, S);
+            d1 = delta_at(x, i0 + 1, S);
+        }
+    };
+    uint32_t n0, n1;
+    load_d(wave, n0, n1);
     for (uint32_t t = wave; t < nb; t += 8) {
         const uint64_t blk = p * kFpBlocks + t;
-        const uint64_t i0 = blk * kBlock + 2 * lane;
-        const uint32_t w0 = nbits(delta_at(x, i0, S)), w1 = nbits(delta_at(x, i0 + 1, S));
-        const uint32_t maxb = uniform(wave_max(w0 > w1 ? w0 : w1));
-        uint32_t best_b = maxb, best_cost = kBlock * maxb, best_c = 0;
-        for (int b = (int)maxb - 1; b >= 0; --b) {
-            const uint32_t c = (uint32_t)__builtin_popcountll(ballot(w0 > (uint32_t)b)) +
-                               (uint32_t)__builtin_popcountll(ballot(w1 > (uint32_t)b));
-            const uint32_t cost = kBlock * (uint32_t)b + c * (8u + maxb - (uint32_t)b);
-            if (cost < best_cost) {
-                best_cost = cost;
-                best_b = (uint32_t)b;
-                best_c = c;
-            }
+        const uint32_t w0 = nbits(n0), w1 = nbits(n1);
+        load_d(t + 8, n0, n1);
+        for (uint32_t i = lane; i < 8 * 33; i += 64)
+            h[i] = 0;
+        wave_lds_order();
+        uint32_t *const hc = h + 66 * (lane >> 4);
+        atomicAdd(&hc[w0], 1u);
+        atomicAdd(&hc[33 + w1], 1u);
+        wave_lds_order();
+        uint32_t hb = 0;  // values of width `lane` (0 beyond 32)
+        if (lane < 33) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                hb += h[33 * c + lane];
         }
+        const uint64_t used = ballot(hb != 0);
+        const uint32_t maxb = 63u - (uint32_t)__builtin_clzll(used);
+        const uint32_t c = kBlock - wave_scan_incl(hb);  // values wider than b = lane
+        const uint32_t cost = kBlock * lane + c * (8u + maxb - lane);
+        const uint32_t key = wave_min(lane <= maxb ? (cost << 6) | (63u - lane) : 0xffffffffu);
+        const uint32_t best_b = 63u - (uint32_t)(key & 63u);
+        const uint32_t best_c = wave_read(c, (int)best_b);
         if (lane == 0) {
             meta[blk] = (uint8_t)best_b;
             meta[nblk + blk] = (uint8_t)maxb;
@@ -204,6 +266,7 @@ __global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__
             atomicAdd(&s_pc, best_c);
             atomicAdd(&s_cnt[maxb - best_b], best_c);
         }
+        wave_lds_order();
     }
     __syncthreads();
     if (tid == 0) {
@@ -218,6 +281,9 @@ __global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__
     }
 }
 
+// LDS staging of a page's metadata and exception arrays in k_fp_pack
+constexpr uint32_t kPackTailWords = 8192;
+
 __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
                                                  const uint8_t *__restrict__ meta, uint64_t nblk,
                                                  const uint32_t *__restrict__ incl, uint32_t dir_end,
@@ -225,6 +291,7 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
 {
     __shared__ FpLds<8> L;
     __shared__ uint32_t sw_all[8][2 * kBlock];  // a wavefront's packed words (L.xp overlays the tables)
+    __shared__ __align__(16) uint32_t s_tail[kPackTailWords];
     constexpr int T = 512;
     const uint64_t p = blockIdx.x;
     const uint32_t tid = threadIdx.x;
@@ -283,57 +350,88 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
     }
     if (tid >= 64 && tid - 64 >= 4 + nset && tid - 64 < hdr_w)
         page[tid - 64] = 0;
-    // clear metadata and exception arrays, which are assembled with byte
-    // stores and ORs
-    for (uint32_t i = hdr_w + packed_words + tid; i < size; i += T)
-        page[i] = 0;
-    __threadfence();
-    __syncthreads();
-    uint8_t *mbytes = reinterpret_cast<uint8_t *>(page + hdr_w + packed_words);
-    for (uint32_t t = tid; t < nb; t += T) {
-        mbytes[t] = L.b[t];
-        mbytes[nb + t] = L.mb[t];
-        mbytes[2 * nb + t] = L.c[t];
-    }
-    uint32_t *sw = sw_all[wave];
+    // The metadata bytes and exception arrays (words tail0 .. size of the
+    // page) are assembled with byte stores and ORs: in LDS when they fit,
+    // then written out with 16-byte stores; otherwise in place in HBM after
+    // clearing it (device atomics).
+    const uint32_t tail0 = hdr_w + packed_words;  // a multiple of 4
+    const uint32_t tail_w = size - tail0;         // a multiple of 4
+    uint32_t *const sw = sw_all[wave];
     const uint32_t rounds = (nb + 7) / 8;
-    for (uint32_t it = 0; it < rounds; ++it) {
-        const uint32_t t = it * 8 + wave;
-        const bool live = t < nb;
-        const uint32_t b = live ? L.b[t] : 0u;
-        for (uint32_t i = lane; i < 4 * b; i += 64)
-            sw[i] = 0;
-        __syncthreads();
-        if (live) {
+    // deltas of this wavefront's next block, loaded one round ahead
+    auto load_d = [&](uint32_t t, uint32_t &d0, uint32_t &d1) __attribute__((always_inline)) {
+        d0 = d1 = 0;
+        if (t < nb) {
             const uint64_t i0 = (p * kFpBlocks + t) * kBlock + 2 * lane;
-            const uint32_t d0 = delta_at(x, i0, S), d1 = delta_at(x, i0 + 1, S);
-            or_field(sw, 2 * lane, b, d0);
-            or_field(sw, 2 * lane + 1, b, d1);
-            const bool e0 = nbits(d0) > b, e1 = nbits(d1) > b;
-            const uint64_t m0 = ballot(e0), m1 = ballot(e1);
-            const uint32_t r0 = lanes_below(m0) + lanes_below(m1);
-            const uint32_t k = (uint32_t)L.mb[t] - b;
-            const uint32_t rk = L.rank[t];
-            uint32_t *arr = page + L.excbase[k <= 32 ? k : 0];
-            for (int h = 0; h < 2; ++h) {
-                const bool e = h ? e1 : e0;
-                if (!e)
-                    continue;
-                const uint32_t idx = r0 + (h ? (uint32_t)e0 : 0u);
-                mbytes[3 * nb + L.posoff[t] + idx] = (uint8_t)(2 * lane + h);
-                const uint32_t hv = (h ? d1 : d0) >> b;
-                const uint32_t bit = (rk + idx) * k, s = bit & 31u;
-                atomicOr(&arr[bit >> 5], hv << s);
-                if (s + k > 32u)
-                    atomicOr(&arr[(bit >> 5) + 1], hv >> (32u - s));
-            }
+            d0 = delta_at(x, i0, S);
+            d1 = delta_at(x, i0 + 1, S);
         }
+    };
+    auto assemble = [&](auto in_lds_tag) __attribute__((always_inline)) {
+        constexpr bool IN_LDS = decltype(in_lds_tag)::value;
+        uint32_t *const tw = IN_LDS ? s_tail : page + tail0;
+        for (uint32_t i = tid; i < tail_w; i += T)
+            tw[i] = 0;
+        if constexpr (!IN_LDS)
+            __threadfence();
         __syncthreads();
-        if (live)
+        uint8_t *const mbytes = reinterpret_cast<uint8_t *>(tw);
+        for (uint32_t t = tid; t < nb; t += T) {
+            mbytes[t] = L.b[t];
+            mbytes[nb + t] = L.mb[t];
+            mbytes[2 * nb + t] = L.c[t];
+        }
+        uint32_t n0, n1;
+        load_d(wave, n0, n1);
+        for (uint32_t it = 0; it < rounds; ++it) {
+            const uint32_t t = it * 8 + wave;
+            const bool live = t < nb;
+            const uint32_t d0 = n0, d1 = n1;
+            load_d(t + 8, n0, n1);
+            const uint32_t b = live ? L.b[t] : 0u;
             for (uint32_t i = lane; i < 4 * b; i += 64)
-                page[hdr_w + L.blkoff[t] + i] = sw[i];
-        __syncthreads();
-    }
+                sw[i] = 0;
+            wave_lds_order();
+            if (live) {
+                or_field(sw, 2 * lane, b, d0);
+                or_field(sw, 2 * lane + 1, b, d1);
+                const bool e0 = nbits(d0) > b, e1 = nbits(d1) > b;
+                const uint64_t m0 = ballot(e0), m1 = ballot(e1);
+                const uint32_t r0 = lanes_below(m0) + lanes_below(m1);
+                const uint32_t k = (uint32_t)L.mb[t] - b;
+                const uint32_t rk = L.rank[t];
+                uint32_t *const arr = tw + (L.excbase[k <= 32 ? k : 0] - tail0);
+                for (int h = 0; h < 2; ++h) {
+                    const bool e = h ? e1 : e0;
+                    if (!e)
+                        continue;
+                    const uint32_t idx = r0 + (h ? (uint32_t)e0 : 0u);
+                    mbytes[3 * nb + L.posoff[t] + idx] = (uint8_t)(2 * lane + h);
+                    const uint32_t hv = (h ? d1 : d0) >> b;
+                    const uint32_t bit = (rk + idx) * k, s = bit & 31u;
+                    atomicOr(&arr[bit >> 5], hv << s);
+                    if (s + k > 32u)
+                        atomicOr(&arr[(bit >> 5) + 1], hv >> (32u - s));
+                }
+            }
+            wave_lds_order();
+            if (live)
+                for (uint32_t i = lane; i < 4 * b; i += 64)
+                    page[hdr_w + L.blkoff[t] + i] = sw[i];
+            wave_lds_order();
+        }
+        if constexpr (IN_LDS) {
+            __syncthreads();
+            uint4 *const dst = reinterpret_cast<uint4 *>(page + tail0);
+            const uint4 *const src = reinterpret_cast<const uint4 *>(s_tail);
+            for (uint32_t i = tid; i < tail_w / 4; i += T)
+                dst[i] = src[i];
+        }
+    };
+    if (tail_w <= kPackTailWords)
+        assemble(std::true_type{});
+    else
+        assemble(std::false_type{});
 }
 
 // ------------------------------------------------------------------------

@@ -99,3 +99,28 @@ def test_gpu_roundtrip_of_gpu_streams():
             out = (wp.bp_decode if codec == wp.CODEC_BP else wp.fastpfor_decode)(comp, x.size)
             assert wp.check_code() == wp.OK
             assert torch.equal(out, xd)
+
+
+@pytest.mark.parametrize("wide_frac", [0.05, 0.15, 0.4])
+def test_fastpfor_encode_exception_heavy_pages(wide_frac):
+    # pages whose metadata and exception arrays take from a few KB to more
+    # than 32 KB (the encoder assembles them in LDS when they fit and in
+    # place in HBM otherwise): both forms give the oracle's stream
+    rng = np.random.default_rng(int(wide_frac * 100))
+    n = 3 * 65536 + 128 * 7 + 5
+    small = rng.integers(0, 16, size=n, dtype=np.uint64)
+    wide = rng.integers(1 << 20, 1 << 24, size=n, dtype=np.uint64)
+    x = np.where(rng.random(n) < wide_frac, wide, small).astype(np.uint32)
+    got = gpu_encode(wp.CODEC_FP, x, 0)
+    want = oracle_encode(wp.CODEC_FP, x, 0)
+    assert got.size == want.size
+    assert_same(got, want, f"wide_frac={wide_frac}")
+    # the page tails: metadata + exception words after the packed words
+    hdr_words = 8
+    p0 = int(want[hdr_words])
+    nb, packed, meta_bytes, bitset = (int(v) for v in want[p0:p0 + 4])
+    assert nb == 512
+    p1 = int(want[hdr_words + 1])
+    hdr_w = (4 + bin(bitset).count("1") + 3) & ~3
+    tail_words = (p1 - p0) - hdr_w - packed
+    print(f"wide_frac={wide_frac}: first page tail {4 * tail_words} bytes", flush=True)
