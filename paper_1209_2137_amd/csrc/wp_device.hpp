@@ -303,8 +303,10 @@ struct FpLds {
             uint32_t rank[kFpBlocks];        // index of the block's first exception in its array
         };
     };
-    uint4 rec[kFpBlocks];  // per block: {b | k << 8 | c << 16, packed word offset,
-                           //  bit offset of its first exception's high part, position offset}
+    // per block: {b | k << 8 | c << 16, packed word offset, bit offset of its
+    // first exception's high part, position offset}; zero past the last block
+    // (the passes fetch up to three passes of 2 * WAVES blocks ahead)
+    uint4 rec[kFpBlocks + 6 * WAVES];
     uint32_t ktot[WAVES][33];
     uint32_t kcar[33];
     uint32_t excbase[33];            // word offset of array k from the page start
@@ -557,85 +559,79 @@ __device__ __forceinline__ void scan_wave4(uint32_t (&x)[4], uint32_t (&carry)[4
 //
 // Every block of a page is described by one 16-byte record {b | k << 8 |
 // c << 16, packed word offset, bit offset of its first exception's high
-// part, position offset}, k = maxb - b. A wavefront takes two blocks at a
-// time and unpacks them as the binary-packing decoder does (lanes 0..31 the
-// first, 32..63 the second, strided fields, LDS transpose); lane e patches
-// exception e of the pair (position byte and k-bit high part, OR-ed in above
-// bit b; a pair with more than 64 exceptions patches the rest in a slower
-// loop). The pair's packed words and one exception per lane are fetched by
-// `fetch` into registers ahead of use.
+// part, position offset}, k = maxb - b; the record arrays are zero-padded
+// past the page's last block, so fetching beyond it reads nothing. A
+// wavefront takes two blocks at a time and unpacks them as the
+// binary-packing decoder does (lanes 0..31 the first, 32..63 the second,
+// strided fields, LDS transpose); lane e patches exception e of the pair
+// (position byte and k-bit high part, OR-ed in above bit b; a pair with
+// more than 64 exceptions patches the rest in a slower loop). Each lane
+// reads the record of its own block and the record of its exception's
+// block; the pair's packed words, one exception per lane and everything
+// needed to place it are fetched by `fetch` into registers ahead of use.
 struct FpPairFetch {
-    uint32_t a0, a2, b0, b2;  // record words 0 and 2 of the two blocks (uniform)
+    uint32_t bA, cA, ce;      // width and exceptions of block A, exceptions of the pair (uniform)
     uint4 pk;                 // the pair's packed words, 16 bytes per lane
     uint32_t pos, lo, hi;     // exception `lane`: position byte, words of its high part
+    // exception `lane`: bit shift of its high part | its block's b << 8 |
+    // 128 * (its block is B) << 16; bits 24..29: the width of the lane's own
+    // block (lanes 0..31 block A, 32..63 block B)
+    uint32_t em;
+    uint32_t km;              // exception `lane`: mask of its k high bits
 };
 
 struct FpPair {
     const uint32_t *page;
-    const uint4 *rec;  // the page's block records (LDS)
-    uint32_t nb, hdr_w, pos_at;
+    const uint4 *rec;  // the page's block records (LDS, zero-padded)
+    uint32_t hdr_w, pos_at;
     BufRsrc rpg;
     uint32_t *stg, *xpw;  // this wavefront's staging and transposition areas (LDS)
-    uint32_t *bad;        // set on a bad position (LDS)
 
     static constexpr uint32_t kOut = 0xfffffff0u;  // a buffer offset beyond every page: reads nothing
 
-    // blocks jA, jA + 1 (either may be past nb: no words, no exceptions)
+    // blocks jA, jA + 1 (records past the page are zero: no words, no exceptions)
     __device__ __forceinline__ FpPairFetch fetch(uint32_t jA) const
     {
         const uint32_t lane = lane_id();
         FpPairFetch f;
-        const uint4 ra = jA < nb ? rec[jA] : make_uint4(0u, 0u, 0u, 0u);
-        const uint4 rb = jA + 1u < nb ? rec[jA + 1u] : make_uint4(0u, 0u, 0u, 0u);
-        f.a0 = uniform(ra.x);
-        f.a2 = uniform(ra.z);
-        f.b0 = uniform(rb.x);
-        f.b2 = uniform(rb.z);
-        const uint32_t pa = uniform(ra.w), pbb = uniform(rb.w);
-        const uint32_t bA = f.a0 & 255u, bB = f.b0 & 255u, cA = f.a0 >> 16, cB = f.b0 >> 16;
-        const BufRsrc rp = make_rsrc(page + hdr_w + uniform(ra.y), 16u * (bA + bB));
+        const uint4 rm = rec[jA + (lane >> 5)];
+        const uint32_t a0 = wave_read(rm.x, 0), b0 = wave_read(rm.x, 32), ay = wave_read(rm.y, 0);
+        f.bA = a0 & 255u;
+        f.cA = a0 >> 16;
+        f.ce = f.cA + (b0 >> 16);
+        const BufRsrc rp = make_rsrc(page + hdr_w + ay, 16u * (f.bA + (b0 & 255u)));
         f.pk = buf_load_u4(rp, lane * 16u);
-        const bool inA = lane < cA, inB = !inA && lane < cA + cB;
-        const uint32_t idx = inA ? lane : lane - cA;
-        const uint32_t k = ((inA ? f.a0 : f.b0) >> 8) & 255u;
-        const uint32_t bit = (inA ? f.a2 : f.b2) + idx * k;
-        const uint32_t poff = (inA || inB) ? pos_at + (inA ? pa : pbb) + idx : kOut;
-        const uint32_t woff = (inA || inB) ? (bit >> 5) * 4u : kOut;
+        const bool inA = lane < f.cA;
+        const uint4 re = rec[jA + (inA ? 0u : 1u)];
+        const uint32_t idx = lane - (inA ? 0u : f.cA);
+        const uint32_t k = (re.x >> 8) & 255u;
+        const uint32_t bit = re.z + idx * k;
+        const bool any = lane < f.ce;
+        const uint32_t poff = any ? pos_at + re.w + idx : kOut;
+        const uint32_t woff = any ? (bit >> 5) * 4u : kOut;
         f.pos = __builtin_amdgcn_raw_buffer_load_b8(rpg, (int)poff, 0, 0);
         f.lo = buf_load_u32(rpg, woff);
         f.hi = buf_load_u32(rpg, woff + 4u);
+        f.em = (bit & 31u) | ((re.x & 255u) << 8) | (inA ? 0u : (kBlock << 16)) | ((rm.x & 255u) << 24);
+        f.km = width_mask(k);
         return f;
-    }
-
-    // exception e of the pair: high part, target block (0 or 1), shift b
-    __device__ __forceinline__ static uint32_t exc_of(const FpPairFetch &f, uint32_t e, uint32_t lo, uint32_t hw,
-                                                      uint32_t &blk, uint32_t &b)
-    {
-        const uint32_t cA = f.a0 >> 16;
-        const bool inA = e < cA;
-        const uint32_t w0 = inA ? f.a0 : f.b0;
-        const uint32_t idx = inA ? e : e - cA;
-        const uint32_t k = (w0 >> 8) & 255u;
-        const uint32_t bit = (inA ? f.a2 : f.b2) + idx * k;
-        blk = inA ? 0u : 1u;
-        b = w0 & 255u;
-        return __builtin_amdgcn_alignbit(hw, lo, bit) & width_mask(k);
     }
 
     // Unpacks and patches blocks jA, jA + 1 from f into the transposition
     // area; after it, lane l's integers 4l..4l+3 of the pair are read with
-    // read_back(). f may be refilled once this returns.
-    __device__ __forceinline__ void unpack_patch(const FpPairFetch &f, uint32_t jA) const
+    // read_back(). f may be refilled once this returns. Exception positions
+    // that are not below 128 or not ascending inside their block set `bad`
+    // (a per-lane flag the caller reduces once per page).
+    __device__ __forceinline__ void unpack_patch(const FpPairFetch &f, uint32_t jA, bool &bad) const
     {
         const uint32_t lane = lane_id();
         const uint32_t q = lane & 31u;
         const bool hi = lane >= 32u;
-        const uint32_t bA = f.a0 & 255u, bB = f.b0 & 255u, cA = f.a0 >> 16, cB = f.b0 >> 16;
         *reinterpret_cast<uint4 *>(&stg[4 * lane]) = f.pk;
         wave_lds_order();
-        const uint32_t b = hi ? bB : bA;
+        const uint32_t b = f.em >> 24;
         const uint32_t qb = q * b;
-        const uint32_t w0 = (hi ? 4u * bA : 0u) + (qb >> 5);
+        const uint32_t w0 = (hi ? 4u * f.bA : 0u) + (qb >> 5);
         const uint32_t mask = width_mask(b);
         uint32_t v[4];
 #pragma unroll
@@ -649,34 +645,27 @@ struct FpPair {
             xw[32 * m] = v[m];
         wave_lds_order();
         // exceptions: one per lane, the rest (more than 64 in the pair) in rounds
-        const uint32_t ce = cA + cB;
-        {
-            const uint32_t prev = __shfl_up(f.pos, 1);
-            if (lane < ce) {
-                uint32_t blk, eb;
-                const uint32_t hv = exc_of(f, lane, f.lo, f.hi, blk, eb);
-                if (f.pos >= kBlock || (lane != 0 && lane != cA && prev >= f.pos))
-                    *bad = 1;
-                atomicOr(&xpw[blk * kBlock + (f.pos & (kBlock - 1u))], hv << eb);
-            }
+        const uint32_t prev = (uint32_t)__shfl_up((int)f.pos, 1, 64);
+        if (lane < f.ce) {
+            const uint32_t hv = __builtin_amdgcn_alignbit(f.hi, f.lo, f.em) & f.km;
+            atomicOr(&xpw[((f.em >> 16) & 255u) + (f.pos & (kBlock - 1u))], hv << ((f.em >> 8) & 255u));
+            bad = bad || f.pos >= kBlock || (lane != 0 && lane != f.cA && prev >= f.pos);
         }
-        for (uint32_t e0 = 64; e0 < ce; e0 += 64) {
+        for (uint32_t e0 = 64; e0 < f.ce; e0 += 64) {
             const uint32_t e = e0 + lane;
-            if (e < ce) {
-                const bool inA = e < cA;
-                const uint32_t idx = inA ? e : e - cA;
-                const uint32_t k = ((inA ? f.a0 : f.b0) >> 8) & 255u;
-                const uint32_t bit = (inA ? f.a2 : f.b2) + idx * k;
-                const uint8_t *pb =
-                    reinterpret_cast<const uint8_t *>(page) + pos_at + (inA ? rec[jA].w : rec[jA + 1u].w) + idx;
+            if (e < f.ce) {
+                const bool inA = e < f.cA;
+                const uint4 re = rec[jA + (inA ? 0u : 1u)];
+                const uint32_t idx = inA ? e : e - f.cA;
+                const uint32_t k = (re.x >> 8) & 255u;
+                const uint32_t bit = re.z + idx * k;
+                const uint8_t *const pb = reinterpret_cast<const uint8_t *>(page) + pos_at + re.w + idx;
                 const uint32_t pos = pb[0], pprev = idx > 0 ? pb[-1] : 0u;
+                bad = bad || pos >= kBlock || (idx > 0 && pprev >= pos);
                 const uint32_t lo = page[bit >> 5];
                 const uint32_t hw = (bit & 31u) + k > 32u ? page[(bit >> 5) + 1u] : 0u;
-                uint32_t blk, eb;
-                const uint32_t hv = exc_of(f, e, lo, hw, blk, eb);
-                if (pos >= kBlock || (idx > 0 && pprev >= pos))
-                    *bad = 1;
-                atomicOr(&xpw[blk * kBlock + (pos & (kBlock - 1u))], hv << eb);
+                const uint32_t hv = __builtin_amdgcn_alignbit(hw, lo, bit) & width_mask(k);
+                atomicOr(&xpw[(inA ? 0u : kBlock) + (pos & (kBlock - 1u))], hv << (re.x & 255u));
             }
         }
     }
@@ -785,27 +774,33 @@ __device__ __forceinline__ bool fp_page(const uint32_t *__restrict__ page, uint3
     if (L.bad)
         return false;
 
-    // block records
-    for (uint32_t t = tid; t < nb; t += T) {
-        const uint32_t b = L.b[t], k = (uint32_t)L.mb[t] - b, c = L.c[t];
-        L.rec[t] = make_uint4(b | (k << 8) | (c << 16), L.blkoff[t], L.excbase[k <= 32 ? k : 0] * 32u + L.rank[t] * k,
-                              L.posoff[t]);
+    // block records (zero past the last block)
+    const uint32_t pos_at = (hdr_w + packed_words) * 4u + 3u * nb;  // byte offset of the positions
+    const BufRsrc rpg = make_rsrc(page, nwords * 4u);
+    for (uint32_t t = tid; t < nb + 6 * WAVES; t += T) {
+        if (t < nb) {
+            const uint32_t b = L.b[t], k = (uint32_t)L.mb[t] - b, c = L.c[t];
+            L.rec[t] = make_uint4(b | (k << 8) | (c << 16), L.blkoff[t],
+                                  L.excbase[k <= 32 ? k : 0] * 32u + L.rank[t] * k, L.posoff[t]);
+        } else {
+            L.rec[t] = make_uint4(0u, 0u, 0u, 0u);
+        }
     }
     __syncthreads();
 
     // passes of 2 * WAVES blocks
     constexpr uint32_t BPP = 2 * WAVES;
-    const uint32_t pos_at = (hdr_w + packed_words) * 4u + 3u * nb;  // byte offset of the positions
-    const FpPair pair{page, L.rec, nb, hdr_w, pos_at, make_rsrc(page, nwords * 4u), L.stage[wave], L.xp[wave], &L.bad};
+    const FpPair pair{page, L.rec, hdr_w, pos_at, rpg, L.stage[wave], L.xp[wave]};
     const BufRsrc rout = make_rsrc(out, nb * kBlock * 4u);
     uint32_t carry[4] = {base[0], base[1], base[2], base[3]};
     const uint32_t npass = (nb + BPP - 1) / BPP;
+    bool bad_pos = false;
     // pass p from slot f; the slot is refilled with pass p + 2 as soon as
     // its words and exceptions have been used (two named slots, so nothing
     // is copied between passes)
     auto run_pass = [&](uint32_t p, FpPairFetch &f) __attribute__((always_inline)) {
         const uint32_t jA = p * BPP + 2u * wave;
-        pair.unpack_patch(f, jA);
+        pair.unpack_patch(f, jA, bad_pos);
         f = pair.fetch((p + 2) * BPP + 2u * wave);  // beyond the page it reads nothing
         uint32_t x[4];
         pair.read_back(x);
@@ -863,6 +858,8 @@ __device__ __forceinline__ bool fp_page(const uint32_t *__restrict__ page, uint3
     }
     if (p < npass)
         run_pass(p, f0);
+    if (lane == 0 && ballot(bad_pos) != 0)
+        L.bad = 1;
     __syncthreads();
     return L.bad == 0;
 }
@@ -875,8 +872,7 @@ __device__ __forceinline__ bool fp_page(const uint32_t *__restrict__ page, uint3
 struct alignas(16) FpWaveLds {
     uint32_t stage[2 * kBlock + 4];
     uint32_t xp[2 * kBlock];
-    uint4 rec[64];
-    uint32_t bad;
+    uint4 rec[64 + 8];  // zero past the last block (fetches run two pairs ahead)
 };
 
 template <uint32_t S>
@@ -932,22 +928,24 @@ __device__ __forceinline__ bool fp_small_page(const uint32_t *__restrict__ page,
         todo &= ~mm;
     }
     const uint32_t eb = __shfl(excb, (int)(k >= 1 ? k - 1 : 0));
+    const uint32_t pos_at = (hdr_w + packed_words) * 4u + 3u * nb;
+    const BufRsrc rpg = make_rsrc(page, nwords * 4u);
     if (own)
         L.rec[lane] = make_uint4(b | (k << 8) | (c << 16), bincl - 4u * b, (c > 0 ? eb * 32u + rank * k : 0u),
                                  cincl - c);
-    if (lane == 0)
-        L.bad = 0;
+    if (lane < 8)
+        L.rec[nb + lane] = make_uint4(0u, 0u, 0u, 0u);
     if (bad)
         return false;
     wave_lds_order();
 
-    const uint32_t pos_at = (hdr_w + packed_words) * 4u + 3u * nb;
-    const FpPair pair{page, L.rec, nb, hdr_w, pos_at, make_rsrc(page, nwords * 4u), L.stage, L.xp, &L.bad};
+    const FpPair pair{page, L.rec, hdr_w, pos_at, rpg, L.stage, L.xp};
     const BufRsrc rout = make_rsrc(out, nb * kBlock * 4u);
     uint32_t carry[4] = {base[0], base[1], base[2], base[3]};
     const uint32_t npass = (nb + 1) / 2;
+    bool bad_pos = false;
     auto run_pass = [&](uint32_t p, FpPairFetch &f) __attribute__((always_inline)) {
-        pair.unpack_patch(f, 2u * p);
+        pair.unpack_patch(f, 2u * p, bad_pos);
         f = pair.fetch(2u * (p + 2));
         uint32_t x[4];
         pair.read_back(x);
@@ -963,7 +961,7 @@ __device__ __forceinline__ bool fp_small_page(const uint32_t *__restrict__ page,
     if (p < npass)
         run_pass(p, f0);
     wave_lds_order();
-    return L.bad == 0;
+    return ballot(bad_pos) == 0;
 }
 
 // ------------------------------------------------------------------------
