@@ -64,11 +64,9 @@ union FpKernelLds {
 };
 
 // One workgroup per page; the workgroup after the last page decodes the tail.
-// Eight wavefronts per SIMD fit the workgroup's LDS; the register budget is
-// held to that occupancy (no spills at 4 or 8 wavefronts).
 template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(8))) void k_fp_decode(
-    const uint32_t *__restrict__ in, uint64_t in_words, uint32_t *__restrict__ out, uint64_t n,
+__global__ __launch_bounds__(64 * WAVES) void k_fp_decode(const uint32_t *__restrict__ in, uint64_t in_words,
+                                                          uint32_t *__restrict__ out, uint64_t n,
                                                           int *__restrict__ err)
 {
     __shared__ FpKernelLds<WAVES> L;

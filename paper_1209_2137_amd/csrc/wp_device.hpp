@@ -305,8 +305,8 @@ struct FpLds {
     };
     // per block: {b | k << 8 | c << 16, packed word offset, bit offset of its
     // first exception's high part, position offset}; zero past the last block
-    // (the passes fetch up to three passes of 2 * WAVES blocks ahead)
-    uint4 rec[kFpBlocks + 6 * WAVES];
+    // (the passes fetch up to four passes of 2 * WAVES blocks ahead)
+    uint4 rec[kFpBlocks + 8 * WAVES];
     uint32_t ktot[WAVES][33];
     uint32_t kcar[33];
     uint32_t excbase[33];            // word offset of array k from the page start
@@ -777,7 +777,7 @@ __device__ __forceinline__ bool fp_page(const uint32_t *__restrict__ page, uint3
     // block records (zero past the last block)
     const uint32_t pos_at = (hdr_w + packed_words) * 4u + 3u * nb;  // byte offset of the positions
     const BufRsrc rpg = make_rsrc(page, nwords * 4u);
-    for (uint32_t t = tid; t < nb + 6 * WAVES; t += T) {
+    for (uint32_t t = tid; t < nb + 8 * WAVES; t += T) {
         if (t < nb) {
             const uint32_t b = L.b[t], k = (uint32_t)L.mb[t] - b, c = L.c[t];
             L.rec[t] = make_uint4(b | (k << 8) | (c << 16), L.blkoff[t],
@@ -795,13 +795,14 @@ __device__ __forceinline__ bool fp_page(const uint32_t *__restrict__ page, uint3
     uint32_t carry[4] = {base[0], base[1], base[2], base[3]};
     const uint32_t npass = (nb + BPP - 1) / BPP;
     bool bad_pos = false;
-    // pass p from slot f; the slot is refilled with pass p + 2 as soon as
-    // its words and exceptions have been used (two named slots, so nothing
-    // is copied between passes)
+    // pass p from slot f; the slot is refilled with pass p + 3 as soon as
+    // its words and exceptions have been used (three named slots, so nothing
+    // is copied between passes, and a wait for a slot's loads rarely covers
+    // the stores of the two passes issued after them)
     auto run_pass = [&](uint32_t p, FpPairFetch &f) __attribute__((always_inline)) {
         const uint32_t jA = p * BPP + 2u * wave;
         pair.unpack_patch(f, jA, bad_pos);
-        f = pair.fetch((p + 2) * BPP + 2u * wave);  // beyond the page it reads nothing
+        f = pair.fetch((p + 3) * BPP + 2u * wave);  // beyond the page it reads nothing
         uint32_t x[4];
         pair.read_back(x);
         // prefix sum: inside the wavefront, then across wavefronts
@@ -850,14 +851,17 @@ __device__ __forceinline__ bool fp_page(const uint32_t *__restrict__ page, uint3
         }
         buf_store_u4(rout, lane * 16u, uniform(jA * (kBlock * 4u)), make_uint4(x[0], x[1], x[2], x[3]));
     };
-    FpPairFetch f0 = pair.fetch(2u * wave), f1 = pair.fetch(BPP + 2u * wave);
+    FpPairFetch f0 = pair.fetch(2u * wave), f1 = pair.fetch(BPP + 2u * wave), f2 = pair.fetch(2 * BPP + 2u * wave);
     uint32_t p = 0;
-    for (; p + 2 <= npass; p += 2) {
+    for (; p + 3 <= npass; p += 3) {
         run_pass(p, f0);
         run_pass(p + 1, f1);
+        run_pass(p + 2, f2);
     }
     if (p < npass)
         run_pass(p, f0);
+    if (p + 1 < npass)
+        run_pass(p + 1, f1);
     if (lane == 0 && ballot(bad_pos) != 0)
         L.bad = 1;
     __syncthreads();
