@@ -65,32 +65,39 @@ def to_dev(a):
 
 
 def time_launches(fn, steps, warmup, stream, kernel_events=None):
-    """Runs fn(i) warmup times, then `steps` times. Returns (wall ms per
-    step, mean event ms). With kernel_events (the package), each launch's
-    own main kernel records a pair of HIP events when it starts and ends
-    (wp_time_next_launch), so the event time is the kernel's duration;
-    otherwise the events bracket each launch on `stream`."""
+    """Runs fn(i) warmup times, then `steps` times back to back with nothing
+    between the launches (the host clock around them gives the wall time
+    per step), then `steps` more times with timing events. Returns (wall ms
+    per step, mean event ms). With kernel_events (the package), each
+    launch's own main kernel records a pair of HIP events when it starts and
+    ends (wp_time_next_launch), so the event time is the kernel's duration;
+    otherwise the events bracket each launch on `stream`. (Events between
+    launches add a few microseconds of gap each, so they stay out of the
+    wall-time loop.)"""
     import torch
     for i in range(warmup):
         fn(i)
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        fn(warmup + i)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     if kernel_events is not None:
         for e in starts + ends:  # create the events on the device before handing them over
             e.record(stream)
         torch.cuda.synchronize()
-    t0 = time.perf_counter()
     for i in range(steps):
         if kernel_events is not None:
             kernel_events.time_next_launch(starts[i], ends[i])
         else:
             starts[i].record(stream)
-        fn(warmup + i)
+        fn(warmup + steps + i)
         if kernel_events is None:
             ends[i].record(stream)
     torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) * 1e3 / steps
     ev = sum(s.elapsed_time(e) for s, e in zip(starts, ends)) / steps
     return wall, ev
 
