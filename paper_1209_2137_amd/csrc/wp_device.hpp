@@ -689,10 +689,10 @@ struct FpPair {
 // exception inside its array k = maxb - b (exceptions are appended to
 // array k in block order, so this is the number of exceptions of earlier
 // blocks with the same k); then the block records. Then passes of 2 * WAVES
-// blocks: wavefront w decodes pair w of the pass (FpPair), the next pass's
-// words and exceptions in flight; one barrier per pass hands the wavefront
-// totals over for the prefix sum.
-template <int WAVES, uint32_t S>
+// blocks: wavefront w decodes pair w of the pass (FpPair), the words and
+// exceptions of the next SLOTS - 1 passes in flight; one barrier per pass
+// hands the wavefront totals over for the prefix sum.
+template <int WAVES, uint32_t S, int SLOTS = 3>
 __device__ __forceinline__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint32_t nb,
                         const uint32_t (&base)[4], uint32_t *__restrict__ out, FpLds<WAVES> &L)
 {
@@ -795,14 +795,15 @@ __device__ __forceinline__ bool fp_page(const uint32_t *__restrict__ page, uint3
     uint32_t carry[4] = {base[0], base[1], base[2], base[3]};
     const uint32_t npass = (nb + BPP - 1) / BPP;
     bool bad_pos = false;
-    // pass p from slot f; the slot is refilled with pass p + 3 as soon as
-    // its words and exceptions have been used (three named slots, so nothing
-    // is copied between passes, and a wait for a slot's loads rarely covers
-    // the stores of the two passes issued after them)
+    // pass p from slot f; the slot is refilled with pass p + SLOTS as soon
+    // as its words and exceptions have been used (named slots, so nothing
+    // is copied between passes; with three, a wait for a slot's loads rarely
+    // covers the stores of the two passes issued after them)
+    static_assert(SLOTS == 2 || SLOTS == 3, "fetch slots");
     auto run_pass = [&](uint32_t p, FpPairFetch &f) __attribute__((always_inline)) {
         const uint32_t jA = p * BPP + 2u * wave;
         pair.unpack_patch(f, jA, bad_pos);
-        f = pair.fetch((p + 3) * BPP + 2u * wave);  // beyond the page it reads nothing
+        f = pair.fetch((p + SLOTS) * BPP + 2u * wave);  // beyond the page it reads nothing
         uint32_t x[4];
         pair.read_back(x);
         // prefix sum: inside the wavefront, then across wavefronts
@@ -851,18 +852,30 @@ __device__ __forceinline__ bool fp_page(const uint32_t *__restrict__ page, uint3
         }
         buf_store_u4(rout, lane * 16u, uniform(jA * (kBlock * 4u)), make_uint4(x[0], x[1], x[2], x[3]));
     };
-    FpPairFetch f0 = pair.fetch(2u * wave), f1 = pair.fetch(BPP + 2u * wave), f2 = pair.fetch(2 * BPP + 2u * wave);
     uint32_t p = 0;
-    for (; p + 3 <= npass; p += 3) {
-        run_pass(p, f0);
-        run_pass(p + 1, f1);
-        run_pass(p + 2, f2);
+    if constexpr (SLOTS == 3) {
+        FpPairFetch f0 = pair.fetch(2u * wave), f1 = pair.fetch(BPP + 2u * wave),
+                    f2 = pair.fetch(2 * BPP + 2u * wave);
+        for (; p + 3 <= npass; p += 3) {
+            run_pass(p, f0);
+            run_pass(p + 1, f1);
+            run_pass(p + 2, f2);
+        }
+        if (p < npass)
+            run_pass(p, f0);
+        if (p + 1 < npass)
+            run_pass(p + 1, f1);
+    } else {
+        FpPairFetch f0 = pair.fetch(2u * wave), f1 = pair.fetch(BPP + 2u * wave);
+        for (; p + 2 <= npass; p += 2) {
+            run_pass(p, f0);
+            run_pass(p + 1, f1);
+        }
+        if (p < npass)
+            run_pass(p, f0);
     }
-    if (p < npass)
-        run_pass(p, f0);
-    if (p + 1 < npass)
-        run_pass(p + 1, f1);
-    if (lane == 0 && ballot(bad_pos) != 0)
+    const bool any_bad_pos = ballot(bad_pos) != 0;
+    if (lane == 0 && any_bad_pos)
         L.bad = 1;
     __syncthreads();
     return L.bad == 0;

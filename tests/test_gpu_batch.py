@@ -149,3 +149,23 @@ def test_batch_strides_and_page_sizes(stride):
                     raise AssertionError(f"list {i} (codec {codec}, n {n}, stride {stride}) differs on replay {rep}")
             assert (out[pool.total_out:] == 0x5A5A5A5A).all()
         plan.free()
+
+
+@pytest.mark.parametrize("waves", [2, 4, 8])
+def test_batch_partial_pages(waves):
+    # patched lists of one partial page of 65..511 blocks (decoded by whole
+    # workgroups in the batch) plus a Variable Byte tail: every list exact
+    rng = np.random.default_rng(40 + waves)
+    lists = []
+    for i in range(200):
+        nb = int(rng.integers(65, 512))
+        lists.append(datagen.single_geometric(nb * 128 + int(rng.integers(0, 128)),
+                                              mean=float(rng.integers(2, 4000)), seed=500 + i))
+    pool = ListPool(lists, [wp.CODEC_FP] * len(lists), stride=1)
+    out = torch.zeros(pool.total_out + 4, dtype=torch.int32, device="cuda")
+    plan = pool.plan(out, tune=dict(waves=waves, vpl=4, depth=2, run_units=4, use_graph=1))
+    plan.decode()
+    assert wp.check_code() == wp.OK
+    bad = [i for i, (co, cw, oo, n, c) in enumerate(pool.rows) if not torch.equal(out[oo:oo + n], pool.values[oo:oo + n])]
+    plan.free()
+    assert not bad, f"{len(bad)} lists differ, first {bad[:5]}"
