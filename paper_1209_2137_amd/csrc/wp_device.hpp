@@ -96,14 +96,6 @@ __device__ __forceinline__ void wave_lds_order()
 
 __device__ __forceinline__ uint32_t width_mask(uint32_t b) { return b >= 32u ? 0xffffffffu : ((1u << b) - 1u); }
 
-// Field of `mask`'s width starting at bit `bit` of the word string `w`:
-// funnel shift of two neighbouring words (v_alignbit_b32 uses bit & 31).
-__device__ __forceinline__ uint32_t fetch_field(const uint32_t *w, uint32_t bit, uint32_t mask)
-{
-    const uint32_t i = bit >> 5;
-    return __builtin_amdgcn_alignbit(w[i + 1], w[i], bit) & mask;
-}
-
 // Raw buffer access (gfx9 buffer resource, dword3 = 0x00020000: 32-bit
 // data, no swizzle). Loads at byte offsets beyond `bytes` return 0 without
 // touching memory.
@@ -178,106 +170,6 @@ __device__ __forceinline__ bool check_header(const uint32_t *__restrict__ in, ui
     return h.magic == magic && hn == n && (H.S == 0 || H.S == 1 || H.S == 4) && h.n_units == H.units &&
            h.total <= in_words && H.dir_end <= h.total && h.tail_off <= h.total && h.tail_off >= H.dir_end &&
            ((H.tail == 0) == (h.tail_bytes == 0));
-}
-
-// Geometry of a pass for a (WAVES, VPL) configuration.
-template <int WAVES, int VPL>
-struct Geo {
-    static_assert(WAVES == 2 || WAVES == 4 || WAVES == 8 || WAVES == 16, "waves");
-    static_assert(VPL == 4 || VPL == 8, "integers per lane");
-    static constexpr int T = 64 * WAVES;        // threads
-    static constexpr int LPB = kBlock / VPL;    // lanes per block
-    static constexpr int BPW = 64 / LPB;        // blocks per wave
-    static constexpr int BPP = WAVES * BPW;     // blocks per pass
-    static constexpr int WPP = BPP * kBlock;    // packed words per pass, at most
-    static constexpr int U4PT = WPP / 4 / T;    // 16-byte staging loads per thread
-    static_assert(U4PT * 4 * T == WPP, "staging split");
-};
-
-// Prefix sum of one pass (Section 3), in place on the lane's VPL deltas.
-// stride 1: x_i = x_{i-1} + d_i; stride 4: x_i = x_{i-4} + d_i (a lane's
-// VPL consecutive integers hold VPL/4 of each residue class mod 4, passes
-// start at multiples of 128); stride 0: no change. `carry` holds the value(s)
-// before the pass (per residue class for stride 4) and is advanced to the
-// end of the pass. wtot is a WAVES x 4 LDS scratch; contains one barrier.
-template <int WAVES, int VPL>
-__device__ __forceinline__ void scan_pass(uint32_t (&v)[VPL], uint32_t S, uint32_t (&carry)[4],
-                                          uint32_t (*wtot)[4])
-{
-    const uint32_t lane = lane_id();
-    const uint32_t wave = uniform(threadIdx.x >> 6);
-    if (S == 1) {
-#pragma unroll
-        for (int r = 1; r < VPL; ++r)
-            v[r] += v[r - 1];
-        const uint32_t incl = wave_scan_incl(v[VPL - 1]);
-        const uint32_t excl = incl - v[VPL - 1];
-        if (lane == 63)
-            wtot[wave][0] = incl;
-        __syncthreads();
-        uint32_t before = carry[0], all = 0;
-#pragma unroll
-        for (int w = 0; w < WAVES; ++w) {
-            const uint32_t t = wtot[w][0];
-            before += (w < (int)wave) ? t : 0u;
-            all += t;
-        }
-        const uint32_t add = before + excl;
-#pragma unroll
-        for (int r = 0; r < VPL; ++r)
-            v[r] += add;
-        carry[0] += all;
-    } else if (S == 4) {
-#pragma unroll
-        for (int r = 4; r < VPL; ++r)
-            v[r] += v[r - 4];
-        uint32_t excl[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const uint32_t t = v[VPL - 4 + c];
-            const uint32_t incl = wave_scan_incl(t);
-            excl[c] = incl - t;
-            if (lane == 63)
-                wtot[wave][c] = incl;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            uint32_t before = carry[c], all = 0;
-#pragma unroll
-            for (int w = 0; w < WAVES; ++w) {
-                const uint32_t t = wtot[w][c];
-                before += (w < (int)wave) ? t : 0u;
-                all += t;
-            }
-            excl[c] += before;
-            carry[c] += all;
-        }
-#pragma unroll
-        for (int r = 0; r < VPL; ++r)
-            v[r] += excl[r & 3];
-    }
-}
-
-template <int VPL>
-__device__ __forceinline__ void store_lane(uint32_t *dst, const uint32_t (&v)[VPL])
-{
-#pragma unroll
-    for (int r = 0; r < VPL; r += 4)
-        *reinterpret_cast<uint4 *>(dst + r) = make_uint4(v[r], v[r + 1], v[r + 2], v[r + 3]);
-}
-
-template <int VPL>
-__device__ __forceinline__ void unpack_lane(const uint32_t *words, uint32_t bit0, uint32_t b,
-                                            uint32_t (&v)[VPL])
-{
-    const uint32_t mask = width_mask(b);
-    uint32_t bit = bit0;
-#pragma unroll
-    for (int r = 0; r < VPL; ++r) {
-        v[r] = fetch_field(words, bit, mask);
-        bit += b;
-    }
 }
 
 // ------------------------------------------------------------------------
