@@ -55,6 +55,8 @@ def _load():
     lib.oracle_vbyte_decode.argtypes = [u8p, u64, ctypes.c_uint32, u32p]
     lib.oracle_vbyte_decode.restype = ctypes.c_int64
     lib.oracle_fp_choose.argtypes = [u32p, ctypes.c_uint32, u32p, u32p, u32p]
+    lib.oracle_intersect.argtypes = [u32p, u64, u32p, u64, u32p]
+    lib.oracle_intersect.restype = u64
     lib.oracle_max_words.argtypes = [ctypes.c_int, u64]
     lib.oracle_max_words.restype = u64
     for f in (lib.oracle_bp_encode, lib.oracle_fp_encode):
@@ -188,3 +190,11 @@ def bp_decode_rc(stream, n: int) -> int:
 
 def fp_decode_rc(stream, n: int) -> int:
     return _decode(_load().oracle_fp_decode, stream, n)[0]
+
+
+def intersect(a, b) -> np.ndarray:
+    """Values present in both strictly increasing arrays a and b, ascending."""
+    a, b = _u32(a), _u32(b)
+    out = np.zeros(max(1, min(a.size, b.size)), dtype=np.uint32)
+    k = _load().oracle_intersect(_p32(a), a.size, _p32(b), b.size, _p32(out))
+    return out[:k].copy()

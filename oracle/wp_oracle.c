@@ -620,3 +620,27 @@ int oracle_fp_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint6
 {
     return o_decode(1, in, in_words, out, n);
 }
+
+/* ------------------------------------------------------------------------
+ * Intersection of two posting lists (the consumer of decoded lists that the
+ * paper's conclusion discusses: conjunctive queries intersect sorted lists).
+ * Definition: the values present in both a and b, ascending. a and b must be
+ * strictly increasing. A two-pointer walk: advance whichever side holds the
+ * smaller value, emit on equality. Returns the number of values written to
+ * out (room for min(na, nb) values). */
+uint64_t oracle_intersect(const uint32_t *a, uint64_t na, const uint32_t *b, uint64_t nb, uint32_t *out)
+{
+    uint64_t i = 0, j = 0, k = 0;
+    while (i < na && j < nb) {
+        if (a[i] < b[j]) {
+            i++;
+        } else if (b[j] < a[i]) {
+            j++;
+        } else {
+            out[k++] = a[i];
+            i++;
+            j++;
+        }
+    }
+    return k;
+}

@@ -440,3 +440,36 @@ def test_generators_shapes_and_determinism():
     assert u.size == 1 << 16 and (np.diff(u.astype(np.int64)) > 0).all()
     lens = datagen.zipf_lengths(1000, total=1.2e7)
     assert lens.min() >= 128 and lens.max() <= 1 << 22 and abs(int(lens.sum()) - 1.2e7) < 2000
+
+
+# ---------------------------------------------------------------------------
+# Intersection of posting lists (the consumer of decoded lists): pinned by
+# brute force, the set definition on small inputs, and special cases.
+
+def _sorted_unique(rng, n, hi):
+    return np.unique(rng.integers(0, hi, size=n, dtype=np.uint64)).astype(np.uint32)
+
+
+def test_intersect_matches_set_definition():
+    rng = np.random.default_rng(71)
+    for trial in range(300):
+        hi = int(rng.choice([8, 100, 5000, 2**32]))
+        a = _sorted_unique(rng, int(rng.integers(0, 60)), hi)
+        b = _sorted_unique(rng, int(rng.integers(0, 60)), hi)
+        want = np.array(sorted(set(a.tolist()) & set(b.tolist())), dtype=np.uint32)
+        got = oracle.intersect(a, b)
+        assert got.dtype == np.uint32 and np.array_equal(got, want), (trial, a, b)
+
+
+def test_intersect_special_cases():
+    e = np.zeros(0, np.uint32)
+    x = np.array([0, 1, 7, 2**31, 2**32 - 1], dtype=np.uint32)
+    assert oracle.intersect(e, x).size == 0 and oracle.intersect(x, e).size == 0
+    assert np.array_equal(oracle.intersect(x, x), x)
+    assert oracle.intersect(np.array([1, 3, 5], np.uint32), np.array([2, 4, 6], np.uint32)).size == 0
+    sub = x[[1, 3]]
+    assert np.array_equal(oracle.intersect(sub, x), sub) and np.array_equal(oracle.intersect(x, sub), sub)
+    # symmetric in its arguments
+    rng = np.random.default_rng(5)
+    a, b = _sorted_unique(rng, 500, 2000), _sorted_unique(rng, 300, 2000)
+    assert np.array_equal(oracle.intersect(a, b), oracle.intersect(b, a))
