@@ -166,6 +166,31 @@ def bench_encode(wp, x_np, codec, stride, steps, warmup, name):
             "hbm_frac": alg / (ev * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
+def bench_intersect(wp, steps, warmup, na=1 << 20, nb=1 << 24):
+    """Intersection of two decoded posting lists (recursive-cluster lists of
+    2^20 and 2^24 values in [0, 2^30)); checked against numpy once. Bytes:
+    both lists read once and the result written (what a merge would move)."""
+    import numpy as np
+    import torch
+    from paper_1209_2137_amd import datagen
+    a_np, b_np = datagen.cluster_sorted(na, seed=21), datagen.cluster_sorted(nb, seed=22)
+    a, b = to_dev(a_np), to_dev(b_np)
+    out = torch.empty(na, dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    wp.intersect(a, b, out=out, count=count)
+    wp.check()
+    k = int(count.item())
+    want = np.intersect1d(a_np, b_np, assume_unique=True)
+    if k != want.size or not np.array_equal(out[:k].cpu().numpy().view(np.uint32), want):
+        raise RuntimeError("intersection differs from numpy's")
+    wall, ev = time_launches(lambda i: wp.intersect(a, b, out=out, count=count), steps, warmup,
+                             torch.cuda.current_stream())
+    alg = 4 * (na + nb + k)
+    return {"name": "intersect 2^20 x 2^24 cluster lists", "na": na, "nb": nb, "common": k, "ms_per_step": wall,
+            "event_ms": ev, "lookups_per_s": na / (ev * 1e-3) / 1e9, "achieved_gbs": alg / (ev * 1e-3) / 1e9,
+            "hbm_frac": alg / (ev * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
 def bench_delta(wp, n, steps, warmup):
     import torch
     rng_t = torch.randint(0, 1 << 8, (n,), dtype=torch.int32, device="cuda")
@@ -460,6 +485,8 @@ def main():
         extra["fp_encode_patched_2e28"] = bench_encode(wp, datagen.patched_gaps(1 << 28, seed=4), wp.CODEC_FP, 1,
                                                        args.steps, args.warmup, "fastpfor_encode patched 2^28")
         print("# encoders done", file=sys.stderr, flush=True)
+        extra["intersect_2e20_2e24"] = bench_intersect(wp, args.steps, args.warmup)
+        print("# intersection done", file=sys.stderr, flush=True)
         head["pct_of_copy"] = head["achieved_gbs"] / copy["gbs"]
         if not args.no_batch:
             extra["batched_posting_lists"], pool = bench_batch(wp, max(3, args.steps // 2), 2)

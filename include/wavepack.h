@@ -118,6 +118,20 @@ int32_t fastpfor_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, ui
 int32_t delta_decode_inplace(uint32_t *data, uint64_t n, uint32_t init, int32_t stride,
                              void *stream);
 
+/* Intersection of two decoded posting lists (the conjunctive-query step
+ * that consumes decoded lists, discussed with the paper's conclusions):
+ * writes the values present in both `a` (na values) and `b` (nb values),
+ * ascending, to out[0..k) and k to *out_count (device uint64, 8-byte
+ * aligned), asynchronously on `stream`. a and b are device arrays that must
+ * be strictly increasing (otherwise the result is unspecified but stays in
+ * out[0..na)); out must hold na values. Each element of a is looked up in b
+ * by binary search, so pass the shorter list as a. Uses the library's
+ * per-stream scratch (one byte per element of a). Returns
+ * WP_ERR_INVALID_ARG for null pointers or na >= 2^32, WP_ERR_HIP if a
+ * launch or the scratch allocation fails. */
+int32_t wp_intersect(const uint32_t *a, uint64_t na, const uint32_t *b, uint64_t nb, uint32_t *out,
+                     uint64_t *out_count, void *stream);
+
 /* Timing hook (host): the calling thread's next bp_decode,
  * fastpfor_decode or delta_decode_inplace records `start_event` when its
  * main kernel starts and `stop_event` when that kernel ends (hipEvent_t,

@@ -26,6 +26,7 @@ EXPORTS = (
     "bp_encode", "bp_decode", "fastpfor_encode", "fastpfor_decode", "delta_decode_inplace",
     "wp_max_compressed_words", "wp_check", "wp_strerror", "wp_set_decode_tune", "wp_time_next_launch",
     "wp_batch_plan", "wp_batch_replan", "wp_batch_decode", "wp_batch_items", "wp_batch_free",
+    "wp_intersect",
 )
 
 _lib = None
@@ -99,6 +100,8 @@ def lib():
     L.wp_batch_items.restype = u64
     L.wp_batch_free.argtypes = [vp]
     L.wp_batch_free.restype = i32
+    L.wp_intersect.argtypes = [vp, u64, vp, u64, vp, vp, vp]
+    L.wp_intersect.restype = i32
     _lib = L
     # workgroup shapes chosen by the autotuner for this architecture, if any
     try:
@@ -215,6 +218,33 @@ def encode_trimmed(x, codec: int = CODEC_BP, stride: int = 1, stream=None):
     buf, words = enc(x, stride, stream=stream)
     check(stream)
     return buf[: int(words.item())].clone()
+
+
+def intersect(a, b, out=None, count=None, stream=None):
+    """Values present in both strictly increasing device arrays a and b,
+    ascending, written to out[0:count] (out holds a.numel() values; count is
+    a one-element device int64 tensor). Returns (out, count); asynchronous."""
+    import torch
+    _need_u32(a, "a")
+    _need_u32(b, "b")
+    if out is None:
+        out = torch.empty(max(a.numel(), 1), dtype=torch.int32, device=a.device)
+    _need_u32(out, "out")
+    if out.numel() < a.numel():
+        raise ValueError("out is smaller than a")
+    if count is None:
+        count = torch.zeros(1, dtype=torch.int64, device=a.device)
+    _check(lib().wp_intersect(_ptr(a), a.numel(), _ptr(b), b.numel(), _ptr(out), _ptr(count), _stream(stream)),
+           "wp_intersect")
+    return out, count
+
+
+def intersect_trimmed(a, b, stream=None):
+    """intersect() returning exactly the common values (synchronises the
+    stream to read the count)."""
+    out, count = intersect(a, b, stream=stream)
+    check(stream)
+    return out[: int(count.item())].clone()
 
 
 def delta_decode_inplace(data, init: int = 0, stride: int = 1, stream=None):
