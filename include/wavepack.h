@@ -132,6 +132,21 @@ int32_t delta_decode_inplace(uint32_t *data, uint64_t n, uint32_t init, int32_t 
 int32_t wp_intersect(const uint32_t *a, uint64_t na, const uint32_t *b, uint64_t nb, uint32_t *out,
                      uint64_t *out_count, void *stream);
 
+/* As wp_intersect, with the second list still compressed (`b_comp`,
+ * b_words words, nb integers, codec WP_CODEC_BP or WP_CODEC_FP; 16-byte
+ * aligned): the directory serves as a skip list. A strictly increasing
+ * list's unit holds values between the value stored as its base (the value
+ * just before the unit) and the next unit's, so only the units (and the
+ * tail) that some element of `a` falls in are decoded, into b_work
+ * (device, nb integers, 16-byte aligned, caller-owned; every other element
+ * of b_work is left as it was). A stream without differential coding
+ * (stride 0) gives no such bounds: all of it is decoded. A corrupt stream is
+ * reported through wp_check. Same result, output and errors as
+ * wp_intersect. */
+int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const uint32_t *b_comp, uint64_t b_words,
+                                uint64_t nb, int32_t codec, uint32_t *b_work, uint32_t *out,
+                                uint64_t *out_count, void *stream);
+
 /* Timing hook (host): the calling thread's next bp_decode,
  * fastpfor_decode or delta_decode_inplace records `start_event` when its
  * main kernel starts and `stop_event` when that kernel ends (hipEvent_t,

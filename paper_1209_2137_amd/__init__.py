@@ -26,7 +26,7 @@ EXPORTS = (
     "bp_encode", "bp_decode", "fastpfor_encode", "fastpfor_decode", "delta_decode_inplace",
     "wp_max_compressed_words", "wp_check", "wp_strerror", "wp_set_decode_tune", "wp_time_next_launch",
     "wp_batch_plan", "wp_batch_replan", "wp_batch_decode", "wp_batch_items", "wp_batch_free",
-    "wp_intersect",
+    "wp_intersect", "wp_intersect_compressed",
 )
 
 _lib = None
@@ -102,6 +102,8 @@ def lib():
     L.wp_batch_free.restype = i32
     L.wp_intersect.argtypes = [vp, u64, vp, u64, vp, vp, vp]
     L.wp_intersect.restype = i32
+    L.wp_intersect_compressed.argtypes = [vp, u64, vp, u64, u64, i32, vp, vp, vp, vp]
+    L.wp_intersect_compressed.restype = i32
     _lib = L
     # workgroup shapes chosen by the autotuner for this architecture, if any
     try:
@@ -237,6 +239,31 @@ def intersect(a, b, out=None, count=None, stream=None):
     _check(lib().wp_intersect(_ptr(a), a.numel(), _ptr(b), b.numel(), _ptr(out), _ptr(count), _stream(stream)),
            "wp_intersect")
     return out, count
+
+
+def intersect_compressed(a, b_comp, nb: int, codec: int, work=None, out=None, count=None, stream=None):
+    """intersect() with the second list given as a compressed stream of nb
+    integers: only the units that a's values fall in are decoded (into
+    `work`, nb integers). Returns (out, count, work); asynchronous."""
+    import torch
+    _need_u32(a, "a")
+    _need_u32(b_comp, "b_comp")
+    if work is None:
+        work = torch.empty(max(nb, 4), dtype=torch.int32, device=a.device)
+    _need_u32(work, "work")
+    if work.numel() < nb:
+        raise ValueError("work is smaller than nb")
+    if out is None:
+        out = torch.empty(max(a.numel(), 1), dtype=torch.int32, device=a.device)
+    _need_u32(out, "out")
+    if out.numel() < a.numel():
+        raise ValueError("out is smaller than a")
+    if count is None:
+        count = torch.zeros(1, dtype=torch.int64, device=a.device)
+    _check(lib().wp_intersect_compressed(_ptr(a), a.numel(), _ptr(b_comp), b_comp.numel(), int(nb), int(codec),
+                                         _ptr(work), _ptr(out), _ptr(count), _stream(stream)),
+           "wp_intersect_compressed")
+    return out, count, work
 
 
 def intersect_trimmed(a, b, stream=None):

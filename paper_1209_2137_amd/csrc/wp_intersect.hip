@@ -10,6 +10,14 @@
 // element of a and the tile's match count; an in-place inclusive scan of the
 // counts (the chained scan of delta_decode_inplace) gives every tile its
 // output offset; pass 2 writes the flagged elements in order.
+//
+// With the second list still compressed, the directory serves as a skip
+// list: every unit's stored base is the value just before the unit, so a
+// strictly increasing list's unit e holds values in (base_e, base_{e+1}].
+// One pass flags the units that some element of the first list falls in,
+// a second decodes only those units (the decoders' wavefront and page
+// routines, into the caller's work buffer at their own positions), and the
+// lookups then search the directory for the unit, then the unit's values.
 #include "wp_device.hpp"
 #include "wp_host.hpp"
 
@@ -115,6 +123,190 @@ __global__ __launch_bounds__(kIsThreads) void k_isect_write(const uint32_t *__re
         *out_count = incl[blockIdx.x];
 }
 
+// ---------------------------------------------------------------------
+// Second list compressed. Directory entry e (units, then the tail entry)
+// covers the list's integers [e * per * 128, ...) and, for a strictly
+// increasing list, values in (base_e, base_{e+1}] where base_e is the last
+// of the entry's stored bases (the value just before the entry); entry 0 has
+// no lower bound and the last entry no upper bound. A stream without
+// differential coding (stride 0) has no such bounds: every entry counts as
+// touched and lookups search the whole decoded list.
+
+struct DirView {
+    const uint32_t *in;
+    ListHdr H;
+    uint32_t per;  // blocks per unit
+    __device__ __forceinline__ uint32_t base(uint64_t e) const
+    {
+        return in[kHdrWords + H.ndir + e * H.S + (H.S - 1)];
+    }
+    // first integer of entry e (the tail entry starts after the last full block)
+    __device__ __forceinline__ uint64_t first_int(uint64_t e) const
+    {
+        const uint64_t f = e * per * (uint64_t)kBlock, t = H.nfull * kBlock;
+        return f < t ? f : t;
+    }
+};
+
+__device__ __forceinline__ bool dir_view(const uint32_t *in, uint64_t in_words, uint64_t n, int32_t codec,
+                                         DirView &D)
+{
+    D.in = in;
+    D.per = codec == WP_CODEC_BP ? kBpBlocks : kFpBlocks;
+    return check_header(in, in_words, n, codec == WP_CODEC_BP ? kMagicBP : kMagicFP, D.per, D.H);
+}
+
+// flags[e] = 1 if some element of a lies in entry e's value range
+__global__ __launch_bounds__(256) void k_isect_touch(const uint32_t *__restrict__ a, uint64_t na,
+                                                     const uint32_t *__restrict__ in, uint64_t in_words, uint64_t n,
+                                                     int32_t codec, uint8_t *__restrict__ flags,
+                                                     int *__restrict__ err)
+{
+    DirView D;
+    if (!dir_view(in, in_words, n, codec, D)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            *err = kErrCorrupt;
+        return;
+    }
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= D.H.ndir)
+        return;
+    bool hit = true;
+    if (D.H.S != 0) {
+        // first element of a above the lower bound, and whether it is within the upper
+        const uint64_t i = e == 0 ? 0 : lower_bound(a, 0, na, D.base(e) + 1u);
+        hit = i < na && (e + 1 == D.H.ndir || a[i] <= D.base(e + 1));
+        if (e > 0 && D.base(e) == 0xFFFFFFFFu)
+            hit = false;  // nothing can lie above the largest value
+    }
+    flags[e] = hit ? 1u : 0u;
+}
+
+// Decodes the flagged entries of a binary-packing stream into out (one
+// wavefront per meta-block; the tail entry by a wavefront of its own).
+template <uint32_t S>
+__device__ __forceinline__ bool bp_unit(const uint32_t *in, const ListHdr &H, uint64_t u, uint32_t *out,
+                                        WaveLds<2> &L)
+{
+    return bp_wave_run<2, S>(in, H, u, 1, out, L);
+}
+
+union IsectWaveLds {
+    WaveLds<2> r;
+    TailLds<1> tail;
+};
+
+__global__ __launch_bounds__(256) void k_isect_decode_bp(const uint32_t *__restrict__ in, uint64_t in_words,
+                                                         uint64_t n, const uint8_t *__restrict__ flags,
+                                                         uint32_t *__restrict__ out, int *__restrict__ err)
+{
+    __shared__ IsectWaveLds L[4];
+    ListHdr H;
+    if (!check_header(in, in_words, n, kMagicBP, kBpBlocks, H))
+        return;  // reported by k_isect_touch
+    const uint32_t wave = uniform(threadIdx.x >> 6);
+    const uint64_t e = (uint64_t)blockIdx.x * 4 + wave;
+    if (e >= H.ndir || !flags[e])
+        return;
+    bool ok;
+    if (e < H.units)
+        ok = H.S == 1   ? bp_unit<1>(in, H, e, out, L[wave].r)
+             : H.S == 4 ? bp_unit<4>(in, H, e, out, L[wave].r)
+                        : bp_unit<0>(in, H, e, out, L[wave].r);
+    else
+        ok = decode_tail_entry<1, false>(in, H, out, L[wave].tail);
+    if (!ok && lane_id() == 0)
+        *err = kErrCorrupt;
+}
+
+union IsectPageLds {
+    FpLds<4> fp;
+    TailLds<4> tail;
+};
+
+// Decodes the flagged entries of a patched-page stream (one workgroup per page).
+__global__ __launch_bounds__(256) void k_isect_decode_fp(const uint32_t *__restrict__ in, uint64_t in_words,
+                                                         uint64_t n, const uint8_t *__restrict__ flags,
+                                                         uint32_t *__restrict__ out, int *__restrict__ err)
+{
+    __shared__ IsectPageLds L;
+    ListHdr H;
+    if (!check_header(in, in_words, n, kMagicFP, kFpBlocks, H))
+        return;  // reported by k_isect_touch
+    const uint64_t u = blockIdx.x;
+    if (u >= H.ndir || !flags[u])
+        return;
+    bool ok;
+    if (u == H.units) {
+        ok = decode_tail_entry<4>(in, H, out, L.tail);
+    } else {
+        const uint32_t off = uniform(in[kHdrWords + u]);
+        const uint32_t end = (u + 1 < H.units) ? uniform(in[kHdrWords + u + 1]) : H.tail_off;
+        const uint32_t *bp = in + kHdrWords + H.ndir + u * H.S;
+        const uint32_t base[4] = {H.S > 0 ? uniform(bp[0]) : 0u, H.S > 1 ? uniform(bp[1]) : 0u,
+                                  H.S > 2 ? uniform(bp[2]) : 0u, H.S > 3 ? uniform(bp[3]) : 0u};
+        const uint64_t left = H.nfull - u * kFpBlocks;
+        const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
+        ok = off >= H.dir_end && end >= off && end <= H.total && (off & 3u) == 0 &&
+             (H.S == 1   ? fp_page<4, 1, 2>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp)
+              : H.S == 4 ? fp_page<4, 4, 2>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp)
+                         : fp_page<4, 0, 2>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp));
+    }
+    if (!ok && threadIdx.x == 0)
+        *err = kErrCorrupt;
+}
+
+// Pass 1 against the decoded entries: each element of a finds its entry by
+// a search of the directory's bases, then itself inside the entry's values.
+__global__ __launch_bounds__(kIsThreads) void k_isect_flag_dir(const uint32_t *__restrict__ a, uint64_t na,
+                                                               const uint32_t *__restrict__ in, uint64_t in_words,
+                                                               uint64_t n, int32_t codec,
+                                                               const uint32_t *__restrict__ b,
+                                                               uint8_t *__restrict__ flags,
+                                                               uint32_t *__restrict__ counts)
+{
+    __shared__ uint32_t s_part[kIsThreads / 64];
+    DirView D;
+    const bool valid = dir_view(in, in_words, n, codec, D);
+    const uint64_t t0 = (uint64_t)blockIdx.x * kIsTile;
+    const uint64_t i0 = t0 + (uint64_t)threadIdx.x * kIsPer;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (uint32_t r = 0; r < kIsPer; ++r) {
+        const uint64_t i = i0 + r;
+        if (i >= na)
+            break;
+        const uint32_t v = a[i];
+        bool hit = false;
+        if (valid) {
+            uint64_t lo = 0, hi = n;
+            if (D.H.S != 0) {
+                // entry: number of entries e >= 1 whose base is below v
+                uint64_t l = 1, h = D.H.ndir;
+                while (l < h) {
+                    const uint64_t m = l + ((h - l) >> 1);
+                    if (D.base(m) < v)
+                        l = m + 1;
+                    else
+                        h = m;
+                }
+                const uint64_t e = l - 1;
+                lo = D.first_int(e);
+                hi = e + 1 < D.H.ndir ? D.first_int(e + 1) : n;
+                hi = hi < n ? hi : n;
+            }
+            const uint64_t pos = lower_bound(b, lo, hi, v);
+            hit = pos < hi && b[pos] == v;
+        }
+        flags[i] = hit ? 1u : 0u;
+        cnt += hit ? 1u : 0u;
+    }
+    uint32_t total;
+    block_scan_incl(cnt, s_part, total);
+    if (threadIdx.x == 0)
+        counts[blockIdx.x] = total;
+}
+
 __global__ void k_isect_none(uint64_t *__restrict__ out_count)
 {
     if (threadIdx.x == 0)
@@ -124,6 +316,30 @@ __global__ void k_isect_none(uint64_t *__restrict__ out_count)
 }  // namespace wp
 
 using namespace wp;
+
+// scratch: scan status | tile counts | one flag byte per element of a |
+// one flag byte per directory entry of the compressed list
+struct IsectScratch {
+    uint64_t *status;
+    uint32_t *counts;
+    uint8_t *flags, *touched;
+};
+
+static bool isect_scratch(hipStream_t st, uint64_t tiles, uint64_t na, uint64_t nent, IsectScratch &S)
+{
+    const uint64_t status_bytes = scan_status_words(tiles) * sizeof(uint64_t);
+    const uint64_t counts_off = (status_bytes + 255) & ~255ull;
+    const uint64_t flags_off = (counts_off + tiles * sizeof(uint32_t) + 255) & ~255ull;
+    const uint64_t touched_off = (flags_off + na + 255) & ~255ull;
+    char *scr = static_cast<char *>(stream_scratch(st, touched_off + nent + 1));
+    if (scr == nullptr)
+        return false;
+    S.status = reinterpret_cast<uint64_t *>(scr);
+    S.counts = reinterpret_cast<uint32_t *>(scr + counts_off);
+    S.flags = reinterpret_cast<uint8_t *>(scr + flags_off);
+    S.touched = reinterpret_cast<uint8_t *>(scr + touched_off);
+    return true;
+}
 
 extern "C" int32_t wp_intersect(const uint32_t *a, uint64_t na, const uint32_t *b, uint64_t nb, uint32_t *out,
                                 uint64_t *out_count, void *stream)
@@ -138,20 +354,56 @@ extern "C" int32_t wp_intersect(const uint32_t *a, uint64_t na, const uint32_t *
         return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
     }
     const uint64_t tiles = (na + kIsTile - 1) / kIsTile;
-    // scratch: scan status | tile counts | one flag byte per element of a
-    const uint64_t status_bytes = scan_status_words(tiles) * sizeof(uint64_t);
-    const uint64_t counts_off = (status_bytes + 255) & ~255ull;
-    const uint64_t flags_off = (counts_off + tiles * sizeof(uint32_t) + 255) & ~255ull;
-    char *scr = static_cast<char *>(stream_scratch(st, flags_off + na));
-    if (scr == nullptr)
+    IsectScratch S;
+    if (!isect_scratch(st, tiles, na, 0, S))
         return WP_ERR_HIP;
-    uint64_t *status = reinterpret_cast<uint64_t *>(scr);
-    uint32_t *counts = reinterpret_cast<uint32_t *>(scr + counts_off);
-    uint8_t *flags = reinterpret_cast<uint8_t *>(scr + flags_off);
-    hipLaunchKernelGGL(k_isect_flag, dim3((uint32_t)tiles), dim3(kIsThreads), 0, st, a, na, b, nb, flags, counts);
-    if (launch_inclusive_scan(counts, tiles, status, st) != WP_OK)
+    hipLaunchKernelGGL(k_isect_flag, dim3((uint32_t)tiles), dim3(kIsThreads), 0, st, a, na, b, nb, S.flags,
+                       S.counts);
+    if (launch_inclusive_scan(S.counts, tiles, S.status, st) != WP_OK)
         return WP_ERR_HIP;
-    hipLaunchKernelGGL(k_isect_write, dim3((uint32_t)tiles), dim3(kIsThreads), 0, st, a, na, flags, counts, out,
+    hipLaunchKernelGGL(k_isect_write, dim3((uint32_t)tiles), dim3(kIsThreads), 0, st, a, na, S.flags, S.counts, out,
+                       out_count);
+    return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
+}
+
+extern "C" int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const uint32_t *b_comp, uint64_t b_words,
+                                           uint64_t nb, int32_t codec, uint32_t *b_work, uint32_t *out,
+                                           uint64_t *out_count, void *stream)
+{
+    if (out_count == nullptr || (na > 0 && (a == nullptr || out == nullptr)) || b_comp == nullptr ||
+        b_words < kHdrWords || (nb > 0 && b_work == nullptr) || (reinterpret_cast<uintptr_t>(out_count) & 7u) ||
+        na > 0xFFFFFFFFull || (codec != WP_CODEC_BP && codec != WP_CODEC_FP) || !aligned16(b_comp) ||
+        !aligned16(b_work) || nb > 0xFFFFFFFFull * 32ull)
+        return WP_ERR_INVALID_ARG;
+    DevState *ds = dev_state();
+    if (ds == nullptr)
+        return WP_ERR_HIP;
+    hipStream_t st = as_stream(stream);
+    (void)hipGetLastError();
+    if (na == 0 || nb == 0) {
+        hipLaunchKernelGGL(k_isect_none, dim3(1), dim3(64), 0, st, out_count);
+        return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
+    }
+    const uint64_t per = codec == WP_CODEC_BP ? kBpBlocks : kFpBlocks;
+    const uint64_t nfull = nb / kBlock;
+    const uint64_t nent = (nfull + per - 1) / per + ((nb % kBlock) ? 1 : 0);
+    const uint64_t tiles = (na + kIsTile - 1) / kIsTile;
+    IsectScratch S;
+    if (nent > 0x7FFFFFFFull || !isect_scratch(st, tiles, na, nent, S))
+        return WP_ERR_HIP;
+    hipLaunchKernelGGL(k_isect_touch, dim3((uint32_t)((nent + 255) / 256)), dim3(256), 0, st, a, na, b_comp,
+                       b_words, nb, codec, S.touched, ds->err);
+    if (codec == WP_CODEC_BP)
+        hipLaunchKernelGGL(k_isect_decode_bp, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, b_comp, b_words,
+                           nb, S.touched, b_work, ds->err);
+    else
+        hipLaunchKernelGGL(k_isect_decode_fp, dim3((uint32_t)nent), dim3(256), 0, st, b_comp, b_words, nb,
+                           S.touched, b_work, ds->err);
+    hipLaunchKernelGGL(k_isect_flag_dir, dim3((uint32_t)tiles), dim3(kIsThreads), 0, st, a, na, b_comp, b_words, nb,
+                       codec, b_work, S.flags, S.counts);
+    if (launch_inclusive_scan(S.counts, tiles, S.status, st) != WP_OK)
+        return WP_ERR_HIP;
+    hipLaunchKernelGGL(k_isect_write, dim3((uint32_t)tiles), dim3(kIsThreads), 0, st, a, na, S.flags, S.counts, out,
                        out_count);
     return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
 }

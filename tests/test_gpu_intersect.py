@@ -76,3 +76,62 @@ def test_intersect_decoded_posting_lists():
     want = oracle.intersect(a, b)
     assert want.size > 0
     assert np.array_equal(got.cpu().numpy().view(np.uint32), want)
+
+
+@pytest.mark.parametrize("codec", [wp.CODEC_BP, wp.CODEC_FP])
+@pytest.mark.parametrize("stride", [0, 1, 4])
+def test_intersect_compressed_matches_oracle(codec, stride):
+    # the long list stays compressed: only the units the short list can
+    # touch are decoded; ragged lengths (partial last unit and a tail)
+    rng = np.random.default_rng(90 + 10 * codec + stride)
+    for nb, na, hi in ((200_000 + 77, 300, 1 << 26), (70_000 + 5, 5000, 1 << 20), (128 * 17, 40, 1 << 16),
+                       (100, 30, 1000), (300_000, 1, 1 << 30)):
+        b = sorted_unique(rng, nb, hi)
+        a = sorted_unique(rng, na, hi)
+        if a.size > 4:  # make sure some values are common
+            a = np.unique(np.concatenate([a, b[rng.integers(0, b.size, size=a.size // 4)]])).astype(np.uint32)
+        comp = wp.encode_trimmed(dev(b), codec, stride)
+        print(f"compressed intersect codec={codec} stride={stride} na={a.size} nb={b.size}", flush=True)
+        out, count, work = wp.intersect_compressed(dev(a), comp, b.size, codec)
+        assert wp.check_code() == wp.OK
+        got = out[: int(count.item())].cpu().numpy().view(np.uint32)
+        want = oracle.intersect(a, b)
+        assert got.size == want.size and np.array_equal(got, want)
+
+
+def test_intersect_compressed_decodes_only_touched_units():
+    # one value of a in the middle of a long list: everything outside the
+    # unit that holds it keeps the work buffer's fill pattern
+    b = np.arange(1, 2 * 2048 * 40, 2, dtype=np.uint32)  # 81920 odd values, 40 meta-blocks
+    comp = wp.encode_trimmed(dev(b), wp.CODEC_BP, 1)
+    a = np.array([b[2048 * 7 + 100]], dtype=np.uint32)
+    work = torch.full((b.size,), -1, dtype=torch.int32, device="cuda")
+    out, count, work = wp.intersect_compressed(dev(a), comp, b.size, wp.CODEC_BP, work=work)
+    assert wp.check_code() == wp.OK
+    assert int(count.item()) == 1 and int(out[0].item()) == int(a[0])
+    w = work.cpu().numpy().view(np.uint32)
+    assert np.array_equal(w[2048 * 7:2048 * 8], b[2048 * 7:2048 * 8])
+    untouched = np.ones(b.size, bool)
+    untouched[2048 * 7:2048 * 8] = False
+    assert np.all(w[untouched] == 0xFFFFFFFF)
+
+
+@pytest.mark.parametrize("codec", [wp.CODEC_BP, wp.CODEC_FP])
+def test_intersect_compressed_corrupt_and_empty(codec):
+    b = np.arange(3, 3 * 5000, 3, dtype=np.uint32)
+    comp = wp.encode_trimmed(dev(b), codec, 1)
+    a = dev(b[::7])
+    # a header that disagrees with nb is reported, nothing is read beyond it
+    out, count, _ = wp.intersect_compressed(a, comp, b.size + 128, codec)
+    assert wp.check_code() == wp.ERR_CORRUPT
+    assert wp.check_code() == wp.OK
+    # empty first list, or an empty second list
+    out, count, _ = wp.intersect_compressed(dev(np.zeros(0, np.uint32)), comp, b.size, codec)
+    assert int(count.item()) == 0
+    empty = wp.encode_trimmed(dev(np.zeros(0, np.uint32)), codec, 1)
+    out, count, _ = wp.intersect_compressed(a, empty, 0, codec)
+    assert int(count.item()) == 0 and wp.check_code() == wp.OK
+    # values beyond the largest of b, and below the smallest
+    a2 = dev(np.array([0, 1, 2, 0xFFFFFFF0, 0xFFFFFFFF], np.uint32))
+    out, count, _ = wp.intersect_compressed(a2, comp, b.size, codec)
+    assert int(count.item()) == 0 and wp.check_code() == wp.OK
