@@ -191,6 +191,46 @@ def bench_intersect(wp, steps, warmup, na=1 << 20, nb=1 << 24):
             "hbm_frac": alg / (ev * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
+def bench_intersect_compressed(wp, steps, warmup, nb=1 << 24, nas=(1 << 10, 1 << 14, 1 << 18)):
+    """A short list against a 2^24-value list that stays compressed (binary
+    packing, differential coding): only the units the short list falls in
+    are decoded. Timed beside decoding the whole list and intersecting the
+    decoded lists; each result checked against numpy once."""
+    import numpy as np
+    import torch
+    from paper_1209_2137_amd import datagen
+    b_np = datagen.cluster_sorted(nb, seed=22)
+    b = to_dev(b_np)
+    comp = wp.encode_trimmed(b, wp.CODEC_BP, 1)
+    work = torch.empty(nb, dtype=torch.int32, device="cuda")
+    full = torch.empty(nb, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    rows = []
+    for na in nas:
+        a_np = datagen.cluster_sorted(na, seed=23)
+        a = to_dev(a_np)
+        out = torch.empty(na, dtype=torch.int32, device="cuda")
+        count = torch.zeros(1, dtype=torch.int64, device="cuda")
+        wp.intersect_compressed(a, comp, nb, wp.CODEC_BP, work=work, out=out, count=count)
+        wp.check()
+        k = int(count.item())
+        want = np.intersect1d(a_np, b_np, assume_unique=True)
+        if k != want.size or not np.array_equal(out[:k].cpu().numpy().view(np.uint32), want):
+            raise RuntimeError("compressed intersection differs from numpy's")
+        wall, ev = time_launches(lambda i: wp.intersect_compressed(a, comp, nb, wp.CODEC_BP, work=work, out=out,
+                                                                   count=count), steps, warmup, stream)
+
+        def decode_then_intersect(i):
+            wp.bp_decode(comp, nb, full)
+            wp.intersect(a, full, out=out, count=count)
+
+        wall_full, ev_full = time_launches(decode_then_intersect, steps, warmup, stream)
+        rows.append({"na": na, "common": k, "ms_per_step": wall, "event_ms": ev, "decode_all_ms": wall_full,
+                     "decode_all_event_ms": ev_full, "speedup": wall_full / wall})
+    return {"name": "intersect short lists x compressed 2^24 cluster list", "nb": nb, "comp_words": comp.numel(),
+            "rows": rows}
+
+
 def bench_delta(wp, n, steps, warmup):
     import torch
     rng_t = torch.randint(0, 1 << 8, (n,), dtype=torch.int32, device="cuda")
@@ -487,6 +527,8 @@ def main():
         print("# encoders done", file=sys.stderr, flush=True)
         extra["intersect_2e20_2e24"] = bench_intersect(wp, args.steps, args.warmup)
         print("# intersection done", file=sys.stderr, flush=True)
+        extra["intersect_compressed_2e24"] = bench_intersect_compressed(wp, args.steps, args.warmup)
+        print("# compressed intersection done", file=sys.stderr, flush=True)
         head["pct_of_copy"] = head["achieved_gbs"] / copy["gbs"]
         if not args.no_batch:
             extra["batched_posting_lists"], pool = bench_batch(wp, max(3, args.steps // 2), 2)
