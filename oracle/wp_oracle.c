@@ -21,6 +21,10 @@
  *                     array start); zero-padded to a multiple of 4 words
  *   units             binary packing: 4-word width descriptor (byte j = b_j)
  *                     then 16 blocks of 128 values, block j in 4*b_j words.
+ *                     BP32: 16 meta-blocks, each a descriptor word (byte j =
+ *                     width of its block j) then its four blocks of 32
+ *                     values, block j in b_j words; zero-padded to a
+ *                     multiple of 4 words (see oracle_bp32_encode)
  *                     patched (FastPFOR) page of up to 512 blocks: see
  *                     oracle_fp_encode
  *   tail              Variable Byte of the last n mod 128 deltas,
@@ -35,6 +39,8 @@
 #define OFP_BLOCKS 512u        /* patched page: 2^16 integers (Section 5) */
 #define OMAGIC_BP 0x31425057u  /* "WPB1" */
 #define OMAGIC_FP 0x31465057u  /* "WPF1" */
+#define OMAGIC_BP32 0x32335057u /* "WP32" */
+#define OB32 32u               /* BP32 block: 32 integers (Section 6.2) */
 
 enum { O_OK = 0, O_ERR_ARG = -1, O_ERR_CAP = -2, O_ERR_CORRUPT = -3 };
 
@@ -203,8 +209,13 @@ static uint64_t o_pad4(uint64_t w) { return (w + 3u) & ~(uint64_t)3u; }
 static uint64_t o_units(int codec, uint64_t n)
 {
     uint64_t nfull = n / OB;
-    uint64_t per = codec == 0 ? OBP_BLOCKS : OFP_BLOCKS;
+    uint64_t per = codec == 1 ? OFP_BLOCKS : OBP_BLOCKS;
     return (nfull + per - 1) / per;
+}
+
+static uint32_t o_magic(int codec)
+{
+    return codec == 0 ? OMAGIC_BP : codec == 1 ? OMAGIC_FP : OMAGIC_BP32;
 }
 
 /* Worst-case stream size in words, computed from the layout. */
@@ -216,6 +227,10 @@ uint64_t oracle_max_words(int codec, uint64_t n)
     uint64_t words = 8 + o_pad4((1 + 4) * (units + 1));
     if (codec == 0) {
         words += units * 4 + nfull * OB;
+    } else if (codec == 2) {
+        /* a descriptor word per 128 values, every block at 32 bits, and at
+         * most 3 words of padding per unit */
+        words += units * 3 + nfull * (1 + OB);
     } else {
         /* per page: header <= 36 words; packed <= 128 words per block;
          * metadata <= (3 + 127) bytes per block (+16 B padding); every array
@@ -247,6 +262,17 @@ int64_t oracle_fp_encode(const uint32_t *x, uint64_t n, int stride, uint32_t *ou
     return o_encode(1, x, n, stride, out, cap);
 }
 
+/* ---- Section 6.2, BP32: blocks of 32 deltas, each at b = bits(max) bits
+ * in the plain (horizontal) layout of Section 4, four blocks per meta-block
+ * behind one 32-bit word of four 8-bit widths, so every block starts on a
+ * 32-bit boundary. Meta-blocks hold 128 values, so the header, directory
+ * (units of 16 meta-blocks) and Variable Byte remainder are those of the
+ * SIMD-BP128 stream. */
+int64_t oracle_bp32_encode(const uint32_t *x, uint64_t n, int stride, uint32_t *out, uint64_t cap)
+{
+    return o_encode(2, x, n, stride, out, cap);
+}
+
 /* Binary-packing meta-block: the descriptor then each block's packed words. */
 static uint64_t o_bp_unit(const uint32_t *d, uint64_t nblocks, uint32_t *out)
 {
@@ -262,6 +288,31 @@ static uint64_t o_bp_unit(const uint32_t *d, uint64_t nblocks, uint32_t *out)
         pos += (uint64_t)OB * b / 32;
     }
     memcpy(out, desc, sizeof desc);
+    return pos;
+}
+
+/* BP32 unit: nmeta meta-blocks, each [descriptor][block 0]..[block 3],
+ * then zero words up to a multiple of 4. */
+static uint64_t o_bp32_unit(const uint32_t *d, uint64_t nmeta, uint32_t *out)
+{
+    uint64_t pos = 0;
+    for (uint64_t m = 0; m < nmeta; m++) {
+        uint64_t at = pos++;
+        uint32_t desc = 0;
+        for (uint32_t j = 0; j < 4; j++) {
+            const uint32_t *blk = d + (m * 4 + j) * OB32;
+            uint32_t all = 0;
+            for (uint32_t i = 0; i < OB32; i++)
+                all |= blk[i];
+            uint32_t b = oracle_bits(all);
+            desc |= b << (8 * j);
+            oracle_pack(blk, OB32, b, out + pos);
+            pos += b; /* 32 values of b bits fill b words */
+        }
+        out[at] = desc;
+    }
+    while (pos % 4)
+        out[pos++] = 0;
     return pos;
 }
 
@@ -381,7 +432,7 @@ static int64_t o_encode(int codec, const uint32_t *x, uint64_t n, int stride,
     uint64_t nfull = n / OB;
     uint64_t tail = n % OB;
     uint64_t units = o_units(codec, n);
-    uint64_t per = codec == 0 ? OBP_BLOCKS : OFP_BLOCKS;
+    uint64_t per = codec == 1 ? OFP_BLOCKS : OBP_BLOCKS;
     uint64_t E = 1 + (uint64_t)stride;
     uint64_t ndir = units + (tail ? 1 : 0);
     uint64_t dir_words = o_pad4(E * ndir);
@@ -401,8 +452,9 @@ static int64_t o_encode(int codec, const uint32_t *x, uint64_t n, int stride,
             uint64_t nb = nfull - u * per;
             if (nb > per)
                 nb = per;
-            p += codec == 0 ? o_bp_unit(d + start, nb, out + p)
-                            : o_fp_page(d + start, nb, out + p);
+            p += codec == 0   ? o_bp_unit(d + start, nb, out + p)
+                 : codec == 2 ? o_bp32_unit(d + start, nb, out + p)
+                              : o_fp_page(d + start, nb, out + p);
         }
     }
     uint64_t tail_off = p;
@@ -415,7 +467,7 @@ static int64_t o_encode(int codec, const uint32_t *x, uint64_t n, int stride,
         memcpy(out + p, buf, tail_bytes);
         p += tw;
     }
-    out[0] = codec == 0 ? OMAGIC_BP : OMAGIC_FP;
+    out[0] = o_magic(codec);
     out[1] = (uint32_t)(n & 0xFFFFFFFFu);
     out[2] = (uint32_t)(n >> 32);
     out[3] = (uint32_t)stride;
@@ -449,6 +501,26 @@ static int o_bp_unit_decode(const uint32_t *w, uint64_t avail, uint64_t nblocks,
         pos += (uint64_t)OB * b / 32;
     }
     if (pos != avail)
+        return O_ERR_CORRUPT;
+    return O_OK;
+}
+
+static int o_bp32_unit_decode(const uint32_t *w, uint64_t avail, uint64_t nmeta, uint32_t *d)
+{
+    uint64_t pos = 0;
+    for (uint64_t m = 0; m < nmeta; m++) {
+        if (pos >= avail)
+            return O_ERR_CORRUPT;
+        uint32_t desc = w[pos++];
+        for (uint32_t j = 0; j < 4; j++) {
+            uint32_t b = (desc >> (8 * j)) & 255u;
+            if (b > 32 || pos + b > avail)
+                return O_ERR_CORRUPT;
+            oracle_unpack(w + pos, OB32, b, d + (m * 4 + j) * OB32);
+            pos += b;
+        }
+    }
+    if (o_pad4(pos) != avail)
         return O_ERR_CORRUPT;
     return O_OK;
 }
@@ -557,7 +629,7 @@ static int o_decode(int codec, const uint32_t *in, uint64_t in_words, uint32_t *
 {
     if (in_words < 8)
         return O_ERR_CORRUPT;
-    if (in[0] != (codec == 0 ? OMAGIC_BP : OMAGIC_FP))
+    if (in[0] != o_magic(codec))
         return O_ERR_CORRUPT;
     uint64_t hn = (uint64_t)in[1] | ((uint64_t)in[2] << 32);
     int stride = (int)in[3];
@@ -565,7 +637,7 @@ static int o_decode(int codec, const uint32_t *in, uint64_t in_words, uint32_t *
         return O_ERR_CORRUPT;
     uint64_t nfull = n / OB, tail = n % OB;
     uint64_t units = o_units(codec, n);
-    uint64_t per = codec == 0 ? OBP_BLOCKS : OFP_BLOCKS;
+    uint64_t per = codec == 1 ? OFP_BLOCKS : OBP_BLOCKS;
     uint64_t total = in[7], tail_off = in[6], tail_bytes = in[5];
     if (in[4] != units || total > in_words || (tail == 0) != (tail_bytes == 0))
         return O_ERR_CORRUPT;
@@ -588,8 +660,9 @@ static int o_decode(int codec, const uint32_t *in, uint64_t in_words, uint32_t *
             count = nb * OB;
             if (off < dir_end || end < off || end > total)
                 return O_ERR_CORRUPT;
-            rc = codec == 0 ? o_bp_unit_decode(in + off, end - off, nb, out + start)
-                            : o_fp_page_decode(in + off, end - off, nb, out + start);
+            rc = codec == 0   ? o_bp_unit_decode(in + off, end - off, nb, out + start)
+                 : codec == 2 ? o_bp32_unit_decode(in + off, end - off, nb, out + start)
+                              : o_fp_page_decode(in + off, end - off, nb, out + start);
         } else {
             count = tail;
             if (off != tail_off || off + (tail_bytes + 3) / 4 != total)
@@ -619,6 +692,11 @@ int oracle_bp_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint6
 int oracle_fp_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n)
 {
     return o_decode(1, in, in_words, out, n);
+}
+
+int oracle_bp32_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n)
+{
+    return o_decode(2, in, in_words, out, n);
 }
 
 /* ------------------------------------------------------------------------

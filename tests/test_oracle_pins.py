@@ -329,11 +329,15 @@ def test_appendix_a_bound_on_sorted_distinct_arrays():
 
 # ---------------------------------------------------------------- round trips
 
-@pytest.mark.parametrize("codec", ["bp", "fp"])
+_ENC = {"bp": oracle.bp_encode, "fp": oracle.fp_encode, "bp32": oracle.bp32_encode}
+_DEC = {"bp": oracle.bp_decode, "fp": oracle.fp_decode, "bp32": oracle.bp32_decode}
+_RC = {"bp": oracle.bp_decode_rc, "fp": oracle.fp_decode_rc, "bp32": oracle.bp32_decode_rc}
+
+
+@pytest.mark.parametrize("codec", ["bp", "fp", "bp32"])
 @pytest.mark.parametrize("stride", [0, 1, 4])
 def test_roundtrip_every_small_length(codec, stride):
-    enc = oracle.bp_encode if codec == "bp" else oracle.fp_encode
-    dec = oracle.bp_decode if codec == "bp" else oracle.fp_decode
+    enc, dec = _ENC[codec], _DEC[codec]
     rng = np.random.default_rng(stride)
     for n in range(0, 301):
         x = rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)
@@ -395,10 +399,9 @@ def test_patched_page_counts_match_blocks():
 
 # ---------------------------------------------------------------- corrupt input
 
-@pytest.mark.parametrize("codec", ["bp", "fp"])
+@pytest.mark.parametrize("codec", ["bp", "fp", "bp32"])
 def test_corrupt_streams_are_rejected(codec):
-    enc = oracle.bp_encode if codec == "bp" else oracle.fp_encode
-    rc = oracle.bp_decode_rc if codec == "bp" else oracle.fp_decode_rc
+    enc, rc = _ENC[codec], _RC[codec]
     x = datagen.single_geometric(5000, seed=3)
     s = enc(x, 1)
     assert rc(s, 5000) == oracle.OK
@@ -412,7 +415,7 @@ def test_corrupt_streams_are_rejected(codec):
     assert rc(bad, 5000) == oracle.ERR_CORRUPT                 # unit offset
     unit = int(s[8])
     bad = s.copy()
-    if codec == "bp":
+    if codec != "fp":
         bad[unit] = (int(bad[unit]) & ~0xFF) | 33              # width 33
     else:
         bad[unit] = 7                                          # block count
@@ -423,7 +426,7 @@ def test_max_words_bounds_worst_case():
     rng = np.random.default_rng(1)
     for n in (0, 1, 128, 2048, 65536 + 129):
         x = rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)
-        for codec, enc in ((0, oracle.bp_encode), (1, oracle.fp_encode)):
+        for codec, enc in ((0, oracle.bp_encode), (1, oracle.fp_encode), (2, oracle.bp32_encode)):
             for stride in (0, 1, 4):
                 assert enc(x, stride).size <= oracle.max_words(codec, n)
 
@@ -473,3 +476,119 @@ def test_intersect_special_cases():
     rng = np.random.default_rng(5)
     a, b = _sorted_unique(rng, 500, 2000), _sorted_unique(rng, 300, 2000)
     assert np.array_equal(oracle.intersect(a, b), oracle.intersect(b, a))
+
+
+# ---------------------------------------------------------------- BP32 (Section 6.2)
+
+def _deltas(x, stride):
+    x = np.asarray(x, dtype=np.uint64)
+    d = x.copy()
+    if stride:
+        d[stride:] = (x[stride:] - x[:-stride]) % (1 << 32)
+    return d
+
+
+def _pack_big(vals, b):
+    """Fields of b bits end to end, least significant first (Section 4),
+    written as one big integer and cut into 32-bit words."""
+    big = 0
+    for i, v in enumerate(vals):
+        big |= (int(v) & ((1 << b) - 1)) << (i * b)
+    return [(big >> (32 * k)) & 0xFFFFFFFF for k in range(len(vals) * b // 32)]
+
+
+def test_bp32_meta_block_layout():
+    # one meta-block: a descriptor word of four 8-bit widths, then the four
+    # 32-integer blocks, each in exactly b words (32 fields of b bits)
+    rng = np.random.default_rng(7)
+    widths = [3, 0, 32, 17]
+    x = np.zeros(128, dtype=np.uint32)
+    for j, b in enumerate(widths):
+        if b:
+            blk = rng.integers(0, 1 << b, size=32, dtype=np.uint64)
+            blk[5] = (1 << b) - 1
+            x[32 * j:32 * j + 32] = blk.astype(np.uint32)
+    s = oracle.bp32_encode(x, 0)
+    unit = int(s[8])
+    assert int(s[0]) == 0x32335057 and int(s[4]) == 1
+    desc = int(s[unit])
+    assert [(desc >> (8 * j)) & 255 for j in range(4)] == widths
+    at = unit + 1
+    for j, b in enumerate(widths):
+        assert [int(w) for w in s[at:at + b]] == _pack_big(x[32 * j:32 * j + 32], b)
+        at += b
+    # the unit is zero-padded to a multiple of 4 words, then the stream ends
+    used = 1 + sum(widths)
+    assert s.size == unit + -(-used // 4) * 4 and not s[unit + used:].any()
+    assert np.array_equal(oracle.bp32_decode(s, 128), x)
+
+
+@pytest.mark.parametrize("stride", [0, 1, 4])
+@pytest.mark.parametrize("n", [0, 5, 128, 2048 * 3 + 127, 40000])
+def test_bp32_size_closed_form(n, stride):
+    x = datagen.single_geometric(n, mean=100, seed=n + stride + 50)
+    s = oracle.bp32_encode(x, stride)
+    d = _deltas(x, stride)
+    nfull, tail = n // 128, n % 128
+    units = -(-nfull // 16)
+    ndir = units + (1 if tail else 0)
+    w32 = [_bitlen(int(m)) for m in d[:nfull * 128].reshape(-1, 32).max(axis=1)] if nfull else []
+    words = 8 + -(-(1 + stride) * ndir // 4) * 4
+    for u in range(units):
+        metas = min(16, nfull - 16 * u)
+        used = metas + sum(w32[64 * u:64 * u + 4 * metas])
+        words += -(-used // 4) * 4
+        # the descriptor of every meta-block holds its four block widths
+        at = int(s[8 + u])
+        for m in range(metas):
+            desc = int(s[at])
+            got = [(desc >> (8 * j)) & 255 for j in range(4)]
+            assert got == w32[64 * u + 4 * m:64 * u + 4 * m + 4]
+            at += 1 + sum(got)
+    tail_bytes = sum(_vbyte_len(int(v)) for v in d[nfull * 128:])
+    words += -(-tail_bytes // 4)
+    assert s.size == words and int(s[7]) == words and int(s[5]) == tail_bytes
+    assert np.array_equal(oracle.bp32_decode(s, n), x)
+
+
+@pytest.mark.parametrize("b", range(0, 33))
+def test_bp32_single_block_every_width(b):
+    # widths differ block by block: blocks 0..3 of the meta-block get b,
+    # 32 - b, b // 2 and 0
+    rng = np.random.default_rng(300 + b)
+    ws = [b, 32 - b, b // 2, 0]
+    x = np.zeros(128, dtype=np.uint32)
+    for j, w in enumerate(ws):
+        if w:
+            blk = rng.integers(0, 1 << w, size=32, dtype=np.uint64)
+            blk[int(rng.integers(0, 32))] = (1 << w) - 1
+            x[32 * j:32 * j + 32] = blk.astype(np.uint32)
+    s = oracle.bp32_encode(x, 0)
+    desc = int(s[int(s[8])])
+    assert [(desc >> (8 * j)) & 255 for j in range(4)] == ws
+    assert np.array_equal(oracle.bp32_decode(s, 128), x)
+
+
+def test_appendix_a_bound_bp32():
+    # Appendix A with B = 32: fewer than 8/32 + 1 + log2(32) + log2(2^32/n)
+    # bits per integer for the deltas of n sorted distinct integers, plus the
+    # stream's header, directory (8 bytes per 2048 integers) and unit padding
+    # (at most 3 words per 2048 integers)
+    n = 1 << 18
+    for x in (datagen.cluster_sorted(n, hi=1 << 32, max_depth=12, seed=23),
+              datagen.uniform_sorted(n, seed=24)):
+        s = oracle.bp32_encode(x, 1)
+        bound = 8 / 32 + 1 + 5 + math.log2(2**32 / n)
+        extra = (32 * 8 + (8 + 12) * 8 * (n / 2048)) / n
+        assert s.size * 32 / n <= bound + extra
+
+
+def test_bp32_never_wider_than_bp128_plus_descriptors():
+    # a 32-integer block's width never exceeds that of the 128-integer block
+    # holding it, so BP32 spends at most the extra descriptor words (one per
+    # 128 integers instead of a quarter) and the unit padding more
+    for seed, x in enumerate((datagen.cluster_sorted(1 << 16, max_depth=10, seed=31),
+                              datagen.patched_gaps(1 << 16, seed=32))):
+        a, b = oracle.bp32_encode(x, 1), oracle.bp_encode(x, 1)
+        metas, units = (1 << 16) // 128, (1 << 16) // 2048
+        assert a.size <= b.size + metas - metas // 4 + 3 * units
