@@ -38,6 +38,12 @@
  *       (field i at bits [i*b, i*b+b) of the block's words, least
  *       significant bit first). Section 4 (bit layout) and Section 6.2
  *       (SIMD-BP128: 16 blocks of 128 integers behind a 128-bit descriptor).
+ *       BP32 -- 16 meta-blocks of four 32-value blocks (2048 values):
+ *       each meta-block is a descriptor word whose byte j is the width b_j
+ *       of its block j, then its four blocks, block j in b_j words (32
+ *       fields of b_j bits, same bit order); the unit is zero-padded to a
+ *       multiple of 4 words. Section 6.2 (BP32: four blocks of 32 integers
+ *       behind a 32-bit descriptor of 8-bit widths, blocks 32-bit aligned).
  *       patched -- a page of up to 512 blocks (2^16 values), Section 5:
  *       [nblocks, packed_words, meta_bytes, bitset] + one count per
  *       non-empty exception array k (bit k-1 of bitset), padded to 4 words;
@@ -69,6 +75,7 @@ extern "C" {
 
 #define WP_CODEC_BP 0 /* binary packing, 16 x 128-integer blocks per unit */
 #define WP_CODEC_FP 1 /* patched pages of 2^16 integers */
+#define WP_CODEC_BP32 2 /* binary packing, 64 x 32-integer blocks per unit */
 
 /* Largest stream any input of n integers can produce, in 32-bit words.
  * Host only, pure. Returns 0 when n is beyond the format (streams are
@@ -93,6 +100,20 @@ int32_t bp_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t
  * recorded in the stream header (checked on the device). Allocates nothing. */
 int32_t bp_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
                   void *stream);
+
+/* BP32 encoder (Section 6.2, BP32: 32-integer blocks at b = bits of the OR
+ * of their deltas, four per meta-block behind a word of widths). Arguments
+ * as bp_encode, with WP_CODEC_BP32 for the capacity. Narrower blocks adapt
+ * better to local gaps than 128-integer ones, for a descriptor word per 128
+ * integers instead of a quarter. */
+int32_t bp32_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,
+                    uint64_t out_cap_words, uint64_t *out_words, void *stream);
+
+/* BP32 decoder: unpacks each 32-integer block at its width (Section 4),
+ * then the prefix sum of Section 3 from the unit's stored base. Arguments
+ * and errors as bp_decode. Allocates nothing. */
+int32_t bp32_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
+                    void *stream);
 
 /* Patched encoder (Section 5, FastPFOR with SIMD-FastPFOR padding): per
  * 128-integer block the width b minimising 128*b + c*(8 + maxb - b) (c =

@@ -21,9 +21,11 @@ ERR_CORRUPT = -3
 ERR_HIP = -4
 CODEC_BP = 0
 CODEC_FP = 1
+CODEC_BP32 = 2
 
 EXPORTS = (
-    "bp_encode", "bp_decode", "fastpfor_encode", "fastpfor_decode", "delta_decode_inplace",
+    "bp_encode", "bp_decode", "bp32_encode", "bp32_decode", "fastpfor_encode", "fastpfor_decode",
+    "delta_decode_inplace",
     "wp_max_compressed_words", "wp_check", "wp_strerror", "wp_set_decode_tune", "wp_time_next_launch",
     "wp_batch_plan", "wp_batch_replan", "wp_batch_decode", "wp_batch_items", "wp_batch_free",
     "wp_intersect", "wp_intersect_compressed",
@@ -69,11 +71,11 @@ def lib():
         pass
     L = ctypes.CDLL(LIB_PATH)
     vp, u64, i32, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint32
-    for name in ("bp_encode", "fastpfor_encode"):
+    for name in ("bp_encode", "bp32_encode", "fastpfor_encode"):
         f = getattr(L, name)
         f.argtypes = [vp, u64, i32, vp, u64, vp, vp]
         f.restype = i32
-    for name in ("bp_decode", "fastpfor_decode"):
+    for name in ("bp_decode", "bp32_decode", "fastpfor_decode"):
         f = getattr(L, name)
         f.argtypes = [vp, u64, vp, u64, vp]
         f.restype = i32
@@ -181,6 +183,11 @@ def bp_decode(comp, n: int, out=None, stream=None):
     return _decode(lib().bp_decode, comp, n, out, stream, "bp_decode")
 
 
+def bp32_decode(comp, n: int, out=None, stream=None):
+    """Decodes a BP32 stream (32-integer blocks) into out[0:n]."""
+    return _decode(lib().bp32_decode, comp, n, out, stream, "bp32_decode")
+
+
 def fastpfor_decode(comp, n: int, out=None, stream=None):
     """Decodes a patched (FastPFOR page) stream (device tensor) into out[0:n]."""
     return _decode(lib().fastpfor_decode, comp, n, out, stream, "fastpfor_decode")
@@ -208,6 +215,11 @@ def bp_encode(x, stride: int = 1, out=None, out_words=None, stream=None):
     return _encode(lib().bp_encode, CODEC_BP, x, stride, out, out_words, stream, "bp_encode")
 
 
+def bp32_encode(x, stride: int = 1, out=None, out_words=None, stream=None):
+    """Encodes x (device uint32) as a BP32 stream."""
+    return _encode(lib().bp32_encode, CODEC_BP32, x, stride, out, out_words, stream, "bp32_encode")
+
+
 def fastpfor_encode(x, stride: int = 1, out=None, out_words=None, stream=None):
     """Encodes x (device uint32) as a patched-page stream."""
     return _encode(lib().fastpfor_encode, CODEC_FP, x, stride, out, out_words, stream, "fastpfor_encode")
@@ -216,7 +228,7 @@ def fastpfor_encode(x, stride: int = 1, out=None, out_words=None, stream=None):
 def encode_trimmed(x, codec: int = CODEC_BP, stride: int = 1, stream=None):
     """Encodes and returns a tensor of exactly the stream's length
     (synchronises the stream to read the length)."""
-    enc = bp_encode if codec == CODEC_BP else fastpfor_encode
+    enc = {CODEC_BP: bp_encode, CODEC_FP: fastpfor_encode, CODEC_BP32: bp32_encode}[codec]
     buf, words = enc(x, stride, stream=stream)
     check(stream)
     return buf[: int(words.item())].clone()

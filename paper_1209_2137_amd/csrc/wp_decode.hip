@@ -1,4 +1,4 @@
-// Single-list decoders: bp_decode and fastpfor_decode.
+// Single-list decoders: bp_decode, bp32_decode and fastpfor_decode.
 //
 // Units are independent because the directory stores each unit's offset
 // and base value(s): no cross-workgroup dependency, no second pass.
@@ -6,6 +6,7 @@
 // Binary packing: every wavefront decodes its own contiguous run of
 // meta-blocks (bp_wave_run); a workgroup is just WAVES such runs side by
 // side. The workgroup after the last run decodes the Variable Byte tail.
+// BP32 streams (32-integer blocks) take the same kernel in its B32 mode.
 //
 // Patched pages: one workgroup per page (see fp_page).
 #include <mutex>
@@ -16,22 +17,22 @@
 
 namespace wp {
 
-template <int WAVES, int DEPTH>
+template <int WAVES, int DEPTH, bool B32>
 union BpKernelLds {
-    WaveLds<DEPTH> w[WAVES];
+    WaveLds<DEPTH, B32> w[WAVES];
     TailLds<WAVES> tail;
 };
 
-// Wavefront w of workgroup g decodes run g * WAVES + w: meta-blocks
+// Wavefront w of workgroup g decodes run g * WAVES + w: units
 // [run * upw, run * upw + upw) of one list.
-template <int WAVES, int DEPTH>
+template <int WAVES, int DEPTH, bool B32 = false>
 __global__ __launch_bounds__(64 * WAVES) void k_bp_decode(const uint32_t *__restrict__ in, uint64_t in_words,
                                                           uint32_t *__restrict__ out, uint64_t n,
                                                           int *__restrict__ err, uint32_t upw)
 {
-    __shared__ BpKernelLds<WAVES, DEPTH> L;
+    __shared__ BpKernelLds<WAVES, DEPTH, B32> L;
     ListHdr H;
-    if (!check_header(in, in_words, n, kMagicBP, kBpBlocks, H)) {
+    if (!check_header(in, in_words, n, B32 ? kMagicBP32 : kMagicBP, kBpBlocks, H)) {
         if (blockIdx.x == 0 && threadIdx.x == 0)
             *err = kErrCorrupt;
         return;
@@ -50,9 +51,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_bp_decode(const uint32_t *__rest
         return;
     const uint64_t ua = r * upw;
     const uint32_t cnt = (uint32_t)((H.units - ua) < upw ? (H.units - ua) : upw);
-    const bool ok = H.S == 1   ? bp_wave_run<DEPTH, 1>(in, H, ua, cnt, out, L.w[wave])
-                    : H.S == 4 ? bp_wave_run<DEPTH, 4>(in, H, ua, cnt, out, L.w[wave])
-                               : bp_wave_run<DEPTH, 0>(in, H, ua, cnt, out, L.w[wave]);
+    const bool ok = H.S == 1   ? bp_wave_run<DEPTH, 1, B32>(in, H, ua, cnt, out, L.w[wave])
+                    : H.S == 4 ? bp_wave_run<DEPTH, 4, B32>(in, H, ua, cnt, out, L.w[wave])
+                               : bp_wave_run<DEPTH, 0, B32>(in, H, ua, cnt, out, L.w[wave]);
     if (!ok && lane_id() == 0)
         *err = kErrCorrupt;
 }
@@ -154,12 +155,12 @@ static bool valid_tune(int codec, int waves, int vpl)
     return (waves == 2 || waves == 4 || waves == 8) && vpl == 4;
 }
 
-template <int WAVES, int DEPTH>
+template <int WAVES, int DEPTH, bool B32 = false>
 static void launch_bp(uint64_t grid, hipStream_t st, const uint32_t *in, uint64_t in_words, uint32_t *out,
                       uint64_t n, int *err, uint32_t upw)
 {
-    launch_timed(k_bp_decode<WAVES, DEPTH>, dim3((uint32_t)grid), dim3(64 * WAVES), st, in, in_words, out, n, err,
-                 upw);
+    launch_timed(k_bp_decode<WAVES, DEPTH, B32>, dim3((uint32_t)grid), dim3(64 * WAVES), st, in, in_words, out, n,
+                 err, upw);
 }
 
 template <int WAVES>
@@ -181,14 +182,14 @@ static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, u
     DevState *ds = dev_state();
     if (ds == nullptr)
         return WP_ERR_HIP;
-    const uint64_t per = codec == WP_CODEC_BP ? kBpBlocks : kFpBlocks;
+    const uint64_t per = codec == WP_CODEC_FP ? kFpBlocks : kBpBlocks;
     const uint64_t nfull = n / kBlock;
     const uint64_t units = (nfull + per - 1) / per;
     const uint64_t has_tail = (n % kBlock) ? 1 : 0;
     hipStream_t st = as_stream(stream);
     const Tune t = decode_tune(codec);
     (void)hipGetLastError();
-    if (codec == WP_CODEC_BP) {
+    if (codec != WP_CODEC_FP) {
         // runs of upw meta-blocks, one per wavefront: about wg_per_cu runs
         // per compute unit
         const uint64_t target = (uint64_t)ds->cus * (uint64_t)(t.wg_per_cu > 0 ? t.wg_per_cu : kBpRunsPerCu);
@@ -200,10 +201,13 @@ static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, u
         if (grid > 0x7FFFFFFFull)
             return WP_ERR_INVALID_ARG;
         const uint32_t u32 = (uint32_t)upw;
+        // BP32 keeps two loads in flight: its ring then stays at 4 KB (a
+        // pass reads two descriptor words beyond the 256 of packed data)
 #define WP_BP(W)                                                                                                \
-    (t.depth >= 4   ? launch_bp<W, 4>(grid, st, in, in_words, out, n, ds->err, u32)                            \
-     : t.depth == 3 ? launch_bp<W, 3>(grid, st, in, in_words, out, n, ds->err, u32)                            \
-                    : launch_bp<W, 2>(grid, st, in, in_words, out, n, ds->err, u32))
+    (codec == WP_CODEC_BP32 ? launch_bp<W, 2, true>(grid, st, in, in_words, out, n, ds->err, u32)               \
+     : t.depth >= 4         ? launch_bp<W, 4>(grid, st, in, in_words, out, n, ds->err, u32)                     \
+     : t.depth == 3         ? launch_bp<W, 3>(grid, st, in, in_words, out, n, ds->err, u32)                     \
+                            : launch_bp<W, 2>(grid, st, in, in_words, out, n, ds->err, u32))
         if (t.waves == 1)
             WP_BP(1);
         else if (t.waves == 2)
@@ -241,6 +245,11 @@ extern "C" int32_t fastpfor_decode(const uint32_t *in, uint64_t in_words, uint32
                                    void *stream)
 {
     return decode_common(WP_CODEC_FP, in, in_words, out, n, stream);
+}
+
+extern "C" int32_t bp32_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n, void *stream)
+{
+    return decode_common(WP_CODEC_BP32, in, in_words, out, n, stream);
 }
 
 extern "C" int32_t wp_set_decode_tune(int32_t codec, int32_t waves, int32_t vpl, int32_t depth, int32_t wg_per_cu)
@@ -295,14 +304,18 @@ extern "C" const char *wp_strerror(int32_t code)
 
 extern "C" uint64_t wp_max_compressed_words(int32_t codec, uint64_t n)
 {
-    if (codec != WP_CODEC_BP && codec != WP_CODEC_FP)
+    if (codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32)
         return 0;
     const uint64_t nfull = n / kBlock, tail = n % kBlock;
-    const uint64_t per = codec == WP_CODEC_BP ? kBpBlocks : kFpBlocks;
+    const uint64_t per = codec == WP_CODEC_FP ? kFpBlocks : kBpBlocks;
     const uint64_t units = (nfull + per - 1) / per;
     uint64_t w = kHdrWords + ((5 * (units + 1) + 3) & ~3ull);
     if (codec == WP_CODEC_BP) {
         w += units * 4 + nfull * 128;  // descriptor + every block at 32 bits
+    } else if (codec == WP_CODEC_BP32) {
+        // a descriptor word per meta-block, every block at 32 bits, at most
+        // three words of padding per unit
+        w += units * 3 + nfull * (1 + 128);
     } else {
         // page header <= 36 words; metadata <= 130 bytes per block + 16 bytes
         // padding; packed <= 128 words per block; exception bits of a block

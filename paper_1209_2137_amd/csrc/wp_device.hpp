@@ -31,6 +31,8 @@ constexpr uint32_t kBpUnitInts = kBlock * kBpBlocks;
 constexpr uint32_t kFpUnitInts = kBlock * kFpBlocks;
 constexpr uint32_t kMagicBP = 0x31425057u;  // "WPB1"
 constexpr uint32_t kMagicFP = 0x31465057u;  // "WPF1"
+constexpr uint32_t kMagicBP32 = 0x32335057u;  // "WP32"
+constexpr uint32_t kB32 = 32;                 // BP32 block length (Section 6.2)
 constexpr uint32_t kHdrWords = 8;
 constexpr uint32_t kMaxTailBytes = 127 * 5;
 constexpr int kErrCorrupt = -3;
@@ -907,22 +909,33 @@ constexpr uint32_t pow2ceil(uint32_t x)
 // consecutive words. The integers are then transposed through LDS so that
 // lane l holds integers 4l..4l+3 of the pass for the prefix sum and the
 // 16-byte stores.
-template <int DEPTH>
+//
+// BP32 (B32): a pass is two meta-blocks of four 32-integer blocks, each
+// meta-block behind its own descriptor word. Lane q of a meta-block takes
+// integer q of each of its four blocks, i.e. integers q, q+32, q+64 and
+// q+96 of the meta-block, the same places as above, so the transposition,
+// scan and stores are shared; each of the four has its own width and word
+// offset (the byte-wise prefix of the descriptor, one multiply).
+template <int DEPTH, bool B32 = false>
 struct WaveGeo {
     static_assert(DEPTH >= 2 && DEPTH <= 4, "depth");
     static constexpr uint32_t CW = 256;               // words per chunk
-    static constexpr uint32_t PASS = 2 * kBlock;      // integers of a pass, and the most words it reads
-    // a group is written while the pass that needs it (at most PASS words,
-    // starting less than PASS words before the group) stays intact
-    static constexpr uint32_t RB = pow2ceil(DEPTH * CW + PASS);
-    static constexpr uint32_t MIR = kBlock + 4;       // ring words mirrored after the end
-    static constexpr uint32_t MAXU = 4 + kBpUnitInts; // words of the largest meta-block
+    static constexpr uint32_t PASS = 2 * kBlock;      // integers of a pass
+    static constexpr uint32_t PASSW = PASS + (B32 ? 2 : 0);  // the most words a pass reads
+    // a group is written while the pass that needs it (at most PASSW words,
+    // starting at or before the group) stays intact
+    static constexpr uint32_t RB = pow2ceil(DEPTH * CW + PASSW);
+    // ring words mirrored after the end: a block's reads run on past the
+    // end (SIMD-BP128), or only one word does (BP32 wraps each address)
+    static constexpr uint32_t MIR = B32 ? 4 : kBlock + 4;
+    // words of the largest unit
+    static constexpr uint32_t MAXU = (B32 ? kBpBlocks : 4) + kBpUnitInts;
 };
 
-template <int DEPTH>
+template <int DEPTH, bool B32 = false>
 struct alignas(16) WaveLds {
-    uint32_t ring[WaveGeo<DEPTH>::RB + WaveGeo<DEPTH>::MIR];
-    uint32_t xp[WaveGeo<DEPTH>::PASS];                // transposition of one pass
+    uint32_t ring[WaveGeo<DEPTH, B32>::RB + WaveGeo<DEPTH, B32>::MIR];
+    uint32_t xp[WaveGeo<DEPTH, B32>::PASS];           // transposition of one pass
 };
 
 // Sum of the four byte lanes of each word, and whether any byte exceeds 32.
@@ -939,16 +952,16 @@ __device__ __forceinline__ bool byte_over32(uint32_t d)
     return (d & 0xc0c0c0c0u) != 0u || (nz & b5) != 0u;
 }
 
-// Decodes meta-blocks [ua, ua + cnt) (cnt <= 63) of the list whose validated
+// Decodes units [ua, ua + cnt) (cnt <= 63) of the list whose validated
 // header is H, whose stride is S; one wavefront, its own LDS slice L.
 // Returns the uniform validity of the run: on a bad run the wavefront
 // stops, its output is unspecified but every store stays inside the run's
 // output range.
-template <int DEPTH, uint32_t S>
+template <int DEPTH, uint32_t S, bool B32 = false>
 __device__ __forceinline__ bool bp_wave_run(const uint32_t *__restrict__ in, const ListHdr &H, uint64_t ua, uint32_t cnt,
-                            uint32_t *__restrict__ out, WaveLds<DEPTH> &L)
+                            uint32_t *__restrict__ out, WaveLds<DEPTH, B32> &L)
 {
-    using G = WaveGeo<DEPTH>;
+    using G = WaveGeo<DEPTH, B32>;
     constexpr uint32_t RB = G::RB, CW = G::CW;
     const uint32_t lane = lane_id();
     // the run's directory: lane i holds the offset of entry ua + i (i <= cnt)
@@ -994,9 +1007,9 @@ __device__ __forceinline__ bool bp_wave_run(const uint32_t *__restrict__ in, con
         slot = buf_load_u4(rs, ((c + DEPTH) * CW + lane * 4) * 4);
     };
     // Brings the ring up to word `need` with at most one group: a pass
-    // reads at most PASS words starting at or before `written`, and a
+    // reads at most PASSW words starting at or before `written`, and a
     // descriptor starts where the previous meta-block ended, so one group
-    // (DEPTH * CW >= PASS words) always suffices for a consistent run (no
+    // (DEPTH * CW >= PASSW words) always suffices for a consistent run (no
     // loop here: a loop would make every wait cover all younger stores).
     auto fill_to = [&](uint32_t need) __attribute__((always_inline)) {
         if (written < need) {
@@ -1019,6 +1032,52 @@ __device__ __forceinline__ bool bp_wave_run(const uint32_t *__restrict__ in, con
     for (uint32_t i = 0; i < cnt; ++i) {
         const uint32_t su = wave_read(offv, i) - W0, eu = wave_read(offv, i + 1) - W0;
         const uint32_t nb = unit_blocks(H, ua + i);
+        if constexpr (B32) {
+            uint32_t carry[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                carry[k] = wave_read(bv[k], i);
+            const uint32_t sbase = i * (kBpUnitInts * 4u);
+            uint32_t ps = su;  // the pass's first descriptor word
+            for (uint32_t p = 0; 2 * p < nb; ++p) {
+                if (!fill_to(ps + 1))
+                    return false;
+                const uint32_t dA = uniform(L.ring[ps & (RB - 1)]);
+                const bool hasB = 2 * p + 1 < nb;
+                const uint32_t pB = ps + 1 + byte_sum(dA);
+                if (!fill_to(hasB ? pB + 1 : pB))
+                    return false;
+                const uint32_t dB = hasB ? uniform(L.ring[pB & (RB - 1)]) : 0u;
+                const uint32_t pe = hasB ? pB + 1 + byte_sum(dB) : pB;
+                if (byte_over32(dA) || byte_over32(dB) || pe > eu || !fill_to(pe))
+                    return false;
+                const uint32_t d = hi ? dB : dA;
+                const uint32_t st = (hi ? pB : ps) + 1;
+                const uint32_t ex = d * 0x01010100u;  // byte m: widths of blocks 0..m-1 (each <= 32)
+                uint32_t v[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const uint32_t b = (d >> (8 * m)) & 255u;
+                    const uint32_t qb = q * b;
+                    const uint32_t w = (st + ((ex >> (8 * m)) & 255u) + (qb >> 5)) & (RB - 1);
+                    v[m] = __builtin_amdgcn_alignbit(L.ring[w + 1], L.ring[w], qb) & width_mask(b);
+                }
+                wave_lds_order();
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    xw[32 * m] = v[m];
+                wave_lds_order();
+                const uint4 t = *xr;
+                uint32_t x[4] = {t.x, t.y, t.z, t.w};
+                scan_wave4<S>(x, carry);
+                buf_store_u4(ro, lane * 16u, sbase + p * (G::PASS * 4u), make_uint4(x[0], x[1], x[2], x[3]));
+                ps = pe;
+            }
+            // the unit ends, zero-padded to 4 words, where its last meta-block ends
+            if (((ps - su + 3u) & ~3u) != eu - su)
+                return false;
+            continue;
+        }
         if (!fill_to(su + 4))
             return false;
         const uint4 dsc = *reinterpret_cast<const uint4 *>(&L.ring[su & (RB - 1)]);

@@ -1,5 +1,5 @@
-// Encoders: bp_encode and fastpfor_encode, producing the stream layout the
-// decoders read (see wavepack.h).
+// Encoders: bp_encode, bp32_encode and fastpfor_encode, producing the
+// stream layout the decoders read (see wavepack.h).
 //
 // Four stream-ordered launches:
 //   1. analyze: one workgroup per unit computes every block's width(s) and
@@ -171,6 +171,97 @@ __global__ __launch_bounds__(256) void k_bp_pack(const uint32_t *__restrict__ x,
 #pragma unroll
         for (int r = 0; r < 8; ++r)
             or_field(w, 8 * (tid & 15u) + r, b, d[r]);
+    }
+    const uint32_t off = dir_end + incl[u] - size;
+    write_dir_entry(out, u, dir_entries(n, kBpBlocks), S, off, x, u * kBpUnitInts);
+    __syncthreads();
+    uint4 *const dst = reinterpret_cast<uint4 *>(out + off);
+    const uint4 *const src = reinterpret_cast<const uint4 *>(s_u);
+    for (uint32_t i = tid; i < size / 4; i += 256)
+        dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------------
+// BP32 (Section 6.2): 32-integer blocks, four per meta-block behind a
+// descriptor word of their widths. Same thread layout as above: block k of
+// the unit is the four threads 4k .. 4k+3.
+
+__global__ __launch_bounds__(256) void k_bp32_analyze(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
+                                                      uint8_t *__restrict__ widths, uint32_t *__restrict__ sizes)
+{
+    constexpr uint32_t NB = kBpUnitInts / kB32;
+    __shared__ uint32_t s_b[NB];
+    const uint64_t u = blockIdx.x;
+    const uint32_t tid = threadIdx.x;
+    const uint64_t nfull = n / kBlock;
+    uint32_t d[8];
+    unit_deltas8(x, u * kBpUnitInts, nfull * kBlock, S, d);
+    uint32_t o = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+        o |= d[r];
+    o |= (uint32_t)__shfl_xor((int)o, 1, 64);
+    o |= (uint32_t)__shfl_xor((int)o, 2, 64);
+    const uint64_t left = nfull - u * kBpBlocks;
+    const uint32_t nm = (uint32_t)(left < kBpBlocks ? left : kBpBlocks);  // meta-blocks of the unit
+    const uint32_t k = tid >> 2;
+    if ((tid & 3u) == 0)
+        s_b[k] = k < 4 * nm ? nbits(o) : 0u;
+    __syncthreads();
+    if (tid < NB)
+        widths[u * NB + tid] = (uint8_t)s_b[tid];
+    if (tid == 0) {
+        uint32_t sum = 0;
+        for (uint32_t j = 0; j < NB; ++j)
+            sum += s_b[j];
+        sizes[u] = (nm + sum + 3u) & ~3u;
+    }
+}
+
+// The unit is assembled in LDS (each meta-block's descriptor word, then its
+// blocks' words, fields OR-ed in by LDS atomics) and written with 16-byte
+// stores.
+__global__ __launch_bounds__(256) void k_bp32_pack(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
+                                                   const uint8_t *__restrict__ widths,
+                                                   const uint32_t *__restrict__ incl, uint32_t dir_end,
+                                                   uint32_t *__restrict__ out)
+{
+    constexpr uint32_t NB = kBpUnitInts / kB32;
+    __shared__ __align__(16) uint32_t s_u[kBpBlocks + kBpUnitInts];
+    __shared__ uint32_t s_b[NB], s_off[NB];
+    const uint64_t u = blockIdx.x;
+    const uint32_t tid = threadIdx.x;
+    const uint64_t nfull = n / kBlock;
+    const uint64_t left = nfull - u * kBpBlocks;
+    const uint32_t nm = (uint32_t)(left < kBpBlocks ? left : kBpBlocks);
+    uint32_t d[8];
+    unit_deltas8(x, u * kBpUnitInts, nfull * kBlock, S, d);
+    if (tid < NB)
+        s_b[tid] = widths[u * NB + tid];
+    __syncthreads();
+    if (tid < NB) {
+        // block k's first word: the descriptors of meta-blocks 0..k/4 and
+        // the words of blocks 0..k-1 come before it
+        uint32_t pre = 0;
+        for (uint32_t j = 0; j < tid; ++j)
+            pre += s_b[j];
+        s_off[tid] = (tid >> 2) + 1u + pre;
+    }
+    __syncthreads();
+    const uint32_t used = nm ? s_off[4 * nm - 1] + s_b[4 * nm - 1] : 0u;
+    const uint32_t size = (used + 3u) & ~3u;
+    for (uint32_t i = tid; i < size; i += 256)
+        s_u[i] = 0;
+    __syncthreads();
+    if (tid < nm)
+        s_u[s_off[4 * tid] - 1] =
+            s_b[4 * tid] | (s_b[4 * tid + 1] << 8) | (s_b[4 * tid + 2] << 16) | (s_b[4 * tid + 3] << 24);
+    const uint32_t k = tid >> 2, b = s_b[k];
+    if (b) {
+        uint32_t *const w = s_u + s_off[k];
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            or_field(w, 8 * (tid & 3u) + r, b, d[r]);
     }
     const uint32_t off = dir_end + incl[u] - size;
     write_dir_entry(out, u, dir_entries(n, kBpBlocks), S, off, x, u * kBpUnitInts);
@@ -475,7 +566,7 @@ __global__ __launch_bounds__(128) void k_finish(const uint32_t *__restrict__ x, 
         out[i] = 0;
     const uint32_t total = tail_off + (tail_bytes + 3) / 4;
     if (tid == 0) {
-        out[0] = codec == WP_CODEC_BP ? kMagicBP : kMagicFP;
+        out[0] = codec == WP_CODEC_BP ? kMagicBP : codec == WP_CODEC_BP32 ? kMagicBP32 : kMagicFP;
         out[1] = (uint32_t)n;
         out[2] = (uint32_t)(n >> 32);
         out[3] = S;
@@ -501,7 +592,7 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
         return WP_ERR_INVALID_ARG;
     if (cap < need)
         return WP_ERR_CAPACITY;
-    const uint64_t per = codec == WP_CODEC_BP ? kBpBlocks : kFpBlocks;
+    const uint64_t per = codec == WP_CODEC_FP ? kFpBlocks : kBpBlocks;
     const uint64_t nfull = n / kBlock;
     const uint64_t units = (nfull + per - 1) / per;
     const uint64_t E = 1 + (uint64_t)stride;
@@ -513,7 +604,7 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
     const uint64_t sizes_off = status_words * 8;
     const uint64_t meta_off = sizes_off + ((units * 4 + 255) & ~255ull);
     const uint64_t nblk = units * per;
-    const uint64_t meta_len = codec == WP_CODEC_BP ? nblk : 3 * nblk;
+    const uint64_t meta_len = codec == WP_CODEC_BP ? nblk : codec == WP_CODEC_BP32 ? 4 * nblk : 3 * nblk;
     char *scr = static_cast<char *>(stream_scratch(st, meta_off + meta_len + 256));
     if (scr == nullptr)
         return WP_ERR_HIP;
@@ -525,6 +616,9 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
         if (codec == WP_CODEC_BP)
             hipLaunchKernelGGL(k_bp_analyze, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride, meta,
                                sizes);
+        else if (codec == WP_CODEC_BP32)
+            hipLaunchKernelGGL(k_bp32_analyze, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride,
+                               meta, sizes);
         else
             hipLaunchKernelGGL(k_fp_analyze, dim3((uint32_t)units), dim3(512), 0, st, in, n, (uint32_t)stride, meta,
                                nblk, sizes);
@@ -532,6 +626,9 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
             return WP_ERR_HIP;
         if (codec == WP_CODEC_BP)
             hipLaunchKernelGGL(k_bp_pack, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride, meta,
+                               sizes, dir_end, out);
+        else if (codec == WP_CODEC_BP32)
+            hipLaunchKernelGGL(k_bp32_pack, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride, meta,
                                sizes, dir_end, out);
         else
             hipLaunchKernelGGL(k_fp_pack, dim3((uint32_t)units), dim3(512), 0, st, in, n, (uint32_t)stride, meta,
@@ -550,6 +647,12 @@ extern "C" int32_t bp_encode(const uint32_t *in, uint64_t n, int32_t delta_strid
                              uint64_t out_cap_words, uint64_t *out_words, void *stream)
 {
     return encode_common(WP_CODEC_BP, in, n, delta_stride, out, out_cap_words, out_words, stream);
+}
+
+extern "C" int32_t bp32_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,
+                               uint64_t out_cap_words, uint64_t *out_words, void *stream)
+{
+    return encode_common(WP_CODEC_BP32, in, n, delta_stride, out, out_cap_words, out_words, stream);
 }
 
 extern "C" int32_t fastpfor_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,
