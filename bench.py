@@ -121,7 +121,7 @@ def bench_single(wp, x_np, codec, stride, steps, warmup, name, comp=None, n=None
         xd = None
     comps = replicas(comp, comp.numel() * 4)
     outs = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(2)]
-    dec = wp.bp_decode if codec == wp.CODEC_BP else wp.fastpfor_decode
+    dec = {wp.CODEC_BP: wp.bp_decode, wp.CODEC_FP: wp.fastpfor_decode, wp.CODEC_BP32: wp.bp32_decode}[codec]
     stream = torch.cuda.current_stream()
     dec(comps[0], n, outs[0])
     wp.check()
@@ -134,7 +134,8 @@ def bench_single(wp, x_np, codec, stride, steps, warmup, name, comp=None, n=None
     comp_bytes = comp.numel() * 4
     alg = comp_bytes + 4 * n
     return {
-        "name": name, "n": n, "codec": "bp" if codec == wp.CODEC_BP else "fp", "stride": stride,
+        "name": name, "n": n, "codec": {wp.CODEC_BP: "bp", wp.CODEC_FP: "fp", wp.CODEC_BP32: "bp32"}[codec],
+        "stride": stride,
         "bits_per_int": comp_bytes * 8 / n, "ms_per_step": wall, "kernel_ms": ev,
         "gints_per_s": n / (wall * 1e-3) / 1e9, "kernel_gints_per_s": n / (ev * 1e-3) / 1e9,
         "alg_bytes": alg, "achieved_gbs": alg / (ev * 1e-3) / 1e9,
@@ -149,7 +150,7 @@ def bench_encode(wp, x_np, codec, stride, steps, warmup, name):
     xd = to_dev(x_np)
     n = x_np.size
     xs = replicas(xd, n * 4)
-    enc = wp.bp_encode if codec == wp.CODEC_BP else wp.fastpfor_encode
+    enc = {wp.CODEC_BP: wp.bp_encode, wp.CODEC_FP: wp.fastpfor_encode, wp.CODEC_BP32: wp.bp32_encode}[codec]
     buf, words = enc(xd, stride)
     wp.check()
     comp_words = int(words.item())
@@ -524,6 +525,10 @@ def main():
                                                        "bp_encode cluster 2^26")
         extra["fp_encode_patched_2e28"] = bench_encode(wp, datagen.patched_gaps(1 << 28, seed=4), wp.CODEC_FP, 1,
                                                        args.steps, args.warmup, "fastpfor_encode patched 2^28")
+        extra["bp32_cluster_2e26"] = bench_single(wp, x, wp.CODEC_BP32, 1, args.steps, args.warmup,
+                                                  "bp32 cluster 2^26")
+        extra["bp32_encode_cluster_2e26"] = bench_encode(wp, x, wp.CODEC_BP32, 1, args.steps, args.warmup,
+                                                         "bp32_encode cluster 2^26")
         print("# encoders done", file=sys.stderr, flush=True)
         extra["intersect_2e20_2e24"] = bench_intersect(wp, args.steps, args.warmup)
         print("# intersection done", file=sys.stderr, flush=True)

@@ -154,7 +154,7 @@ int32_t wp_intersect(const uint32_t *a, uint64_t na, const uint32_t *b, uint64_t
                      uint64_t *out_count, void *stream);
 
 /* As wp_intersect, with the second list still compressed (`b_comp`,
- * b_words words, nb integers, codec WP_CODEC_BP or WP_CODEC_FP; 16-byte
+ * b_words words, nb integers, codec WP_CODEC_BP, WP_CODEC_BP32 or WP_CODEC_FP; 16-byte
  * aligned): the directory serves as a skip list. A strictly increasing
  * list's unit holds values between the value stored as its base (the value
  * just before the unit) and the next unit's, so only the units (and the
@@ -177,7 +177,8 @@ int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const uint32_t *
 int32_t wp_time_next_launch(void *start_event, void *stop_event);
 
 /* Workgroup shape of the single-list decoders (set by the autotuner;
- * process-wide). Binary packing: every wavefront decodes its own run of
+ * process-wide; one setting per codec). Binary packing (WP_CODEC_BP and
+ * WP_CODEC_BP32): every wavefront decodes its own run of
  * consecutive meta-blocks, streaming the run's compressed words through a
  * private LDS ring; waves: wavefronts per workgroup (1, 2, 4 or 8); vpl
  * must be 4 (each lane unpacks four integers of a block per pass); depth:

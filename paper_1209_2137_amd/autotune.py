@@ -5,8 +5,9 @@ Knobs:
   vpl        integers per lane and pass (4)
   depth      binary packing: 16-byte loads in flight per lane, which also
              sizes each wavefront's LDS ring (2 or 3: 4 KB, 4: 8 KB)
-  wg_per_cu  single list, binary packing: runs (one per wavefront) per
-             compute unit (batched decoding ignores it)
+  wg_per_cu  single list, binary packing (SIMD-BP128 and BP32, each its
+             own shape): runs (one per wavefront) per compute unit
+             (batched decoding ignores it)
   run_units  batched decoding: meta-blocks per work item
 
 Each candidate is timed with HIP events (median of `steps` launches after
@@ -27,6 +28,7 @@ BP_SINGLE = [dict(waves=w, vpl=4, depth=d, wg_per_cu=c)
              for w in (1, 2, 4, 8) for d in (2, 3) for c in (28, 56, 128, 256)] + \
             [dict(waves=w, vpl=4, depth=4, wg_per_cu=c) for w in (1, 4) for c in (64, 128)]
 FP_SINGLE = [dict(waves=w, vpl=4) for w in (2, 4, 8)]
+BP32_SINGLE = [dict(waves=w, vpl=4, depth=d, wg_per_cu=c) for w in (2, 4, 8) for d in (2, 3) for c in (56, 128, 256)]
 BATCH = [dict(waves=w, vpl=4, depth=d, run_units=r, wg_per_cu=0, use_graph=1)
          for w in (2, 4, 8) for d in (2, 3) for r in (4, 8, 16)]
 
@@ -55,8 +57,9 @@ def arch() -> str:
 
 
 def apply(table: dict | None = None, arch_name: str = "gfx950"):
-    """Installs the table's single-list shapes (binary packing, patched)."""
-    from . import CODEC_BP, CODEC_FP, lib
+    """Installs the table's single-list shapes (binary packing, patched,
+    BP32; BP32 takes its default shape when the table has none)."""
+    from . import CODEC_BP, CODEC_BP32, CODEC_FP, lib
     table = load() if table is None else table
     ent = table.get(arch_name, {})
     bp = ent.get("bp_single")
@@ -65,6 +68,8 @@ def apply(table: dict | None = None, arch_name: str = "gfx950"):
     fp = ent.get("fp_single")
     if fp:
         lib().wp_set_decode_tune(CODEC_FP, fp["waves"], fp["vpl"], fp.get("depth", 0), 0)
+    b32 = ent.get("bp32_single") or dict(waves=4, vpl=4, depth=2, wg_per_cu=0)
+    lib().wp_set_decode_tune(CODEC_BP32, b32["waves"], b32["vpl"], b32.get("depth", 0), b32.get("wg_per_cu", 0))
 
 
 def batch_tune(table: dict | None = None, arch_name: str = "gfx950") -> dict | None:
@@ -93,14 +98,15 @@ def _median_ms(fn, steps, warmup):
 def tune_single(codec: int, x_np, candidates=None, steps: int = 9, warmup: int = 3, log=print):
     """Times every candidate shape decoding x (numpy uint32) with `codec`."""
     import torch
-    from . import CODEC_BP, bp_decode, check, encode_trimmed, fastpfor_decode, set_decode_tune
+    from . import CODEC_BP, CODEC_BP32, CODEC_FP, bp32_decode, bp_decode, check, encode_trimmed, fastpfor_decode, \
+        set_decode_tune
     xd = torch.from_numpy(x_np.view("int32")).to("cuda")
     comp = encode_trimmed(xd, codec, 1)
     reps = max(2, min(16, (512 << 20) // max(comp.numel() * 4, 1)))
     comps = [comp] + [comp.clone() for _ in range(reps - 1)]
     outs = [torch.empty_like(xd) for _ in range(2)]
-    dec = bp_decode if codec == CODEC_BP else fastpfor_decode
-    cands = candidates or (BP_SINGLE if codec == CODEC_BP else FP_SINGLE)
+    dec = {CODEC_BP: bp_decode, CODEC_FP: fastpfor_decode, CODEC_BP32: bp32_decode}[codec]
+    cands = candidates or {CODEC_BP: BP_SINGLE, CODEC_FP: FP_SINGLE, CODEC_BP32: BP32_SINGLE}[codec]
     results = []
     for c in cands:
         set_decode_tune(codec, c["waves"], c["vpl"], c.get("wg_per_cu", 0), c.get("depth", 0))
@@ -139,7 +145,7 @@ def main():
     """Tunes single-list and batched shapes on the standard synthetic
     workloads and writes tuning.json."""
     import argparse
-    from . import CODEC_BP, CODEC_FP, datagen
+    from . import CODEC_BP, CODEC_BP32, CODEC_FP, datagen
     from .pool import ListPool
     ap = argparse.ArgumentParser()
     ap.add_argument("--lists", type=int, default=20000, help="lists in the batched-decoding pool")
@@ -153,6 +159,9 @@ def main():
     print("binary packing, 2^26 recursive-cluster list", flush=True)
     best_bp, _ = tune_single(CODEC_BP, datagen.cluster_sorted(1 << 26, seed=2))
     ent["bp_single"] = best_bp
+    print("BP32, 2^26 recursive-cluster list", flush=True)
+    best_b32, _ = tune_single(CODEC_BP32, datagen.cluster_sorted(1 << 26, seed=2))
+    ent["bp32_single"] = best_b32
     print("patched, 2^28 list", flush=True)
     best_fp, _ = tune_single(CODEC_FP, datagen.patched_gaps(1 << 28, seed=4))
     ent["fp_single"] = best_fp

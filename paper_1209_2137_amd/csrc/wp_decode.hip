@@ -113,7 +113,8 @@ LaunchEvents take_launch_events()
     t_events = LaunchEvents{};
     return e;
 }
-static Tune g_tune[2] = {{4, 4, kBpRunsPerCu, 2}, {4, 4, 0, 0}};
+// per codec: SIMD-BP128, patched pages, BP32
+static Tune g_tune[3] = {{4, 4, kBpRunsPerCu, 2}, {4, 4, 0, 0}, {4, 4, kBpRunsPerCu, 2}};
 
 DevState *dev_state()
 {
@@ -145,12 +146,12 @@ DevState *dev_state()
 Tune decode_tune(int codec)
 {
     std::lock_guard<std::mutex> lk(g_mu);
-    return g_tune[codec == WP_CODEC_FP ? 1 : 0];
+    return g_tune[codec == WP_CODEC_FP ? 1 : codec == WP_CODEC_BP32 ? 2 : 0];
 }
 
 static bool valid_tune(int codec, int waves, int vpl)
 {
-    if (codec == WP_CODEC_BP)
+    if (codec == WP_CODEC_BP || codec == WP_CODEC_BP32)
         return (waves == 1 || waves == 2 || waves == 4 || waves == 8) && vpl == 4;
     return (waves == 2 || waves == 4 || waves == 8) && vpl == 4;
 }
@@ -201,13 +202,11 @@ static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, u
         if (grid > 0x7FFFFFFFull)
             return WP_ERR_INVALID_ARG;
         const uint32_t u32 = (uint32_t)upw;
-        // BP32 keeps two loads in flight: its ring then stays at 4 KB (a
-        // pass reads two descriptor words beyond the 256 of packed data)
-#define WP_BP(W)                                                                                                \
-    (codec == WP_CODEC_BP32 ? launch_bp<W, 2, true>(grid, st, in, in_words, out, n, ds->err, u32)               \
-     : t.depth >= 4         ? launch_bp<W, 4>(grid, st, in, in_words, out, n, ds->err, u32)                     \
-     : t.depth == 3         ? launch_bp<W, 3>(grid, st, in, in_words, out, n, ds->err, u32)                     \
-                            : launch_bp<W, 2>(grid, st, in, in_words, out, n, ds->err, u32))
+        const bool b32 = codec == WP_CODEC_BP32;
+#define WP_BP_D(W, D)                                                                                           \
+    (b32 ? launch_bp<W, D, true>(grid, st, in, in_words, out, n, ds->err, u32)                                  \
+         : launch_bp<W, D>(grid, st, in, in_words, out, n, ds->err, u32))
+#define WP_BP(W) (t.depth >= 4 ? WP_BP_D(W, 4) : t.depth == 3 ? WP_BP_D(W, 3) : WP_BP_D(W, 2))
         if (t.waves == 1)
             WP_BP(1);
         else if (t.waves == 2)
@@ -217,6 +216,7 @@ static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, u
         else
             WP_BP(8);
 #undef WP_BP
+#undef WP_BP_D
     } else {
         uint64_t grid = units + has_tail;
         grid = grid ? grid : 1;
@@ -254,7 +254,8 @@ extern "C" int32_t bp32_decode(const uint32_t *in, uint64_t in_words, uint32_t *
 
 extern "C" int32_t wp_set_decode_tune(int32_t codec, int32_t waves, int32_t vpl, int32_t depth, int32_t wg_per_cu)
 {
-    if ((codec != WP_CODEC_BP && codec != WP_CODEC_FP) || !valid_tune(codec, waves, vpl) || wg_per_cu < 0 ||
+    if ((codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32) || !valid_tune(codec, waves, vpl) ||
+        wg_per_cu < 0 ||
         wg_per_cu > 1024 || depth < 0 || depth == 1 || depth > 4)
         return WP_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(g_mu);

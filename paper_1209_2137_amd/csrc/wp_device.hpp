@@ -911,17 +911,20 @@ constexpr uint32_t pow2ceil(uint32_t x)
 // 16-byte stores.
 //
 // BP32 (B32): a pass is two meta-blocks of four 32-integer blocks, each
-// meta-block behind its own descriptor word. Lane q of a meta-block takes
-// integer q of each of its four blocks, i.e. integers q, q+32, q+64 and
-// q+96 of the meta-block, the same places as above, so the transposition,
-// scan and stores are shared; each of the four has its own width and word
-// offset (the byte-wise prefix of the descriptor, one multiply).
+// meta-block behind its own descriptor word: eight blocks of eight lanes.
+// Lane l takes integers 4l..4l+3 of the pass, four consecutive integers of
+// one block, so its width, mask and block offset (the byte-wise prefix of
+// the descriptor, one multiply) are computed once, the four fields follow
+// each other at b bits, and the lane already holds what the prefix sum and
+// the 16-byte store need: no transposition.
 template <int DEPTH, bool B32 = false>
 struct WaveGeo {
     static_assert(DEPTH >= 2 && DEPTH <= 4, "depth");
     static constexpr uint32_t CW = 256;               // words per chunk
     static constexpr uint32_t PASS = 2 * kBlock;      // integers of a pass
-    static constexpr uint32_t PASSW = PASS + (B32 ? 2 : 0);  // the most words a pass reads
+    // the most words a pass reads (BP32: two descriptors, and the next
+    // pass's first descriptor, read ahead)
+    static constexpr uint32_t PASSW = PASS + (B32 ? 3 : 0);
     // a group is written while the pass that needs it (at most PASSW words,
     // starting at or before the group) stays intact
     static constexpr uint32_t RB = pow2ceil(DEPTH * CW + PASSW);
@@ -935,7 +938,7 @@ struct WaveGeo {
 template <int DEPTH, bool B32 = false>
 struct alignas(16) WaveLds {
     uint32_t ring[WaveGeo<DEPTH, B32>::RB + WaveGeo<DEPTH, B32>::MIR];
-    uint32_t xp[WaveGeo<DEPTH, B32>::PASS];           // transposition of one pass
+    uint32_t xp[B32 ? 4 : WaveGeo<DEPTH, B32>::PASS];  // transposition of one pass (SIMD-BP128)
 };
 
 // Sum of the four byte lanes of each word, and whether any byte exceeds 32.
@@ -1027,6 +1030,7 @@ __device__ __forceinline__ bool bp_wave_run(const uint32_t *__restrict__ in, con
 
     const uint32_t q = lane & 31u;
     const bool hi = lane >= 32u;
+    const uint32_t sh32 = 8u * ((lane >> 3) & 3u), r4 = 4u * (lane & 7u);  // BP32 lane geometry
     uint32_t *const xw = &L.xp[lane + (hi ? 96u : 0u)];   // integer q of the lane's block
     const uint4 *const xr = reinterpret_cast<const uint4 *>(&L.xp[4 * lane]);
     for (uint32_t i = 0; i < cnt; ++i) {
@@ -1038,43 +1042,51 @@ __device__ __forceinline__ bool bp_wave_run(const uint32_t *__restrict__ in, con
             for (int k = 0; k < 4; ++k)
                 carry[k] = wave_read(bv[k], i);
             const uint32_t sbase = i * (kBpUnitInts * 4u);
-            uint32_t ps = su;  // the pass's first descriptor word
+            uint32_t ps = su;     // the pass's first descriptor word
+            uint32_t wmax = 0;    // widest block seen by the lane (checked at the unit's end)
+            if (!fill_to(ps + G::PASSW))
+                return false;
+            uint32_t dnext = L.ring[ps & (RB - 1)];
             for (uint32_t p = 0; 2 * p < nb; ++p) {
-                if (!fill_to(ps + 1))
+                // one fill covers the largest pass and the next descriptor
+                // (PASSW words from ps)
+                if (!fill_to(ps + G::PASSW))
                     return false;
-                const uint32_t dA = uniform(L.ring[ps & (RB - 1)]);
+                const uint32_t dA = uniform(dnext);
                 const bool hasB = 2 * p + 1 < nb;
-                const uint32_t pB = ps + 1 + byte_sum(dA);
-                if (!fill_to(hasB ? pB + 1 : pB))
-                    return false;
+                // (d * 0x01010101) >> 24: sum of the four widths (<= 128 when valid)
+                const uint32_t pB = ps + 1u + ((dA * 0x01010101u) >> 24);
                 const uint32_t dB = hasB ? uniform(L.ring[pB & (RB - 1)]) : 0u;
-                const uint32_t pe = hasB ? pB + 1 + byte_sum(dB) : pB;
-                if (byte_over32(dA) || byte_over32(dB) || pe > eu || !fill_to(pe))
+                const uint32_t pe = hasB ? pB + 1u + ((dB * 0x01010101u) >> 24) : pB;
+                if (pe > eu)
                     return false;
+                // the next pass's first descriptor, read now: its latency
+                // overlaps this pass's unpacking
+                dnext = L.ring[pe & (RB - 1)];
+                // lane l: block jj = (l >> 3) & 3 of its meta-block,
+                // integers 4r .. 4r+3 of the block, r = l & 7; byte jj of
+                // d * 0x01010100 is the width of blocks 0..jj-1
                 const uint32_t d = hi ? dB : dA;
-                const uint32_t st = (hi ? pB : ps) + 1;
-                const uint32_t ex = d * 0x01010100u;  // byte m: widths of blocks 0..m-1 (each <= 32)
-                uint32_t v[4];
+                const uint32_t ex = hi ? dB * 0x01010100u : dA * 0x01010100u;
+                const uint32_t b = (d >> sh32) & 255u;
+                wmax = wmax > b ? wmax : b;
+                const uint32_t o = (hi ? pB : ps) + 1u + ((ex >> sh32) & 255u);
+                const uint32_t mask = width_mask(b);
+                uint32_t pos = r4 * b;  // bit offset of the lane's first field
+                uint32_t x[4];
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const uint32_t b = (d >> (8 * m)) & 255u;
-                    const uint32_t qb = q * b;
-                    const uint32_t w = (st + ((ex >> (8 * m)) & 255u) + (qb >> 5)) & (RB - 1);
-                    v[m] = __builtin_amdgcn_alignbit(L.ring[w + 1], L.ring[w], qb) & width_mask(b);
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t w = (o + (pos >> 5)) & (RB - 1);
+                    x[k] = __builtin_amdgcn_alignbit(L.ring[w + 1], L.ring[w], pos) & mask;
+                    pos += b;
                 }
-                wave_lds_order();
-#pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    xw[32 * m] = v[m];
-                wave_lds_order();
-                const uint4 t = *xr;
-                uint32_t x[4] = {t.x, t.y, t.z, t.w};
                 scan_wave4<S>(x, carry);
                 buf_store_u4(ro, lane * 16u, sbase + p * (G::PASS * 4u), make_uint4(x[0], x[1], x[2], x[3]));
                 ps = pe;
             }
-            // the unit ends, zero-padded to 4 words, where its last meta-block ends
-            if (((ps - su + 3u) & ~3u) != eu - su)
+            // widths <= 32, and the unit ends (zero-padded to 4 words)
+            // where its last meta-block ends
+            if (ballot(wmax > 32u) != 0 || ((ps - su + 3u) & ~3u) != eu - su)
                 return false;
             continue;
         }

@@ -152,8 +152,9 @@ __device__ __forceinline__ bool dir_view(const uint32_t *in, uint64_t in_words, 
                                          DirView &D)
 {
     D.in = in;
-    D.per = codec == WP_CODEC_BP ? kBpBlocks : kFpBlocks;
-    return check_header(in, in_words, n, codec == WP_CODEC_BP ? kMagicBP : kMagicFP, D.per, D.H);
+    D.per = codec == WP_CODEC_FP ? kFpBlocks : kBpBlocks;
+    const uint32_t magic = codec == WP_CODEC_BP ? kMagicBP : codec == WP_CODEC_BP32 ? kMagicBP32 : kMagicFP;
+    return check_header(in, in_words, n, magic, D.per, D.H);
 }
 
 // flags[e] = 1 if some element of a lies in entry e's value range
@@ -182,27 +183,30 @@ __global__ __launch_bounds__(256) void k_isect_touch(const uint32_t *__restrict_
     flags[e] = hit ? 1u : 0u;
 }
 
-// Decodes the flagged entries of a binary-packing stream into out (one
-// wavefront per meta-block; the tail entry by a wavefront of its own).
-template <uint32_t S>
+// Decodes the flagged entries of a binary-packing (SIMD-BP128 or BP32)
+// stream into out (one wavefront per unit; the tail entry by a wavefront of
+// its own).
+template <uint32_t S, bool B32>
 __device__ __forceinline__ bool bp_unit(const uint32_t *in, const ListHdr &H, uint64_t u, uint32_t *out,
-                                        WaveLds<2> &L)
+                                        WaveLds<2, B32> &L)
 {
-    return bp_wave_run<2, S>(in, H, u, 1, out, L);
+    return bp_wave_run<2, S, B32>(in, H, u, 1, out, L);
 }
 
+template <bool B32>
 union IsectWaveLds {
-    WaveLds<2> r;
+    WaveLds<2, B32> r;
     TailLds<1> tail;
 };
 
+template <bool B32>
 __global__ __launch_bounds__(256) void k_isect_decode_bp(const uint32_t *__restrict__ in, uint64_t in_words,
                                                          uint64_t n, const uint8_t *__restrict__ flags,
                                                          uint32_t *__restrict__ out, int *__restrict__ err)
 {
-    __shared__ IsectWaveLds L[4];
+    __shared__ IsectWaveLds<B32> L[4];
     ListHdr H;
-    if (!check_header(in, in_words, n, kMagicBP, kBpBlocks, H))
+    if (!check_header(in, in_words, n, B32 ? kMagicBP32 : kMagicBP, kBpBlocks, H))
         return;  // reported by k_isect_touch
     const uint32_t wave = uniform(threadIdx.x >> 6);
     const uint64_t e = (uint64_t)blockIdx.x * 4 + wave;
@@ -210,9 +214,9 @@ __global__ __launch_bounds__(256) void k_isect_decode_bp(const uint32_t *__restr
         return;
     bool ok;
     if (e < H.units)
-        ok = H.S == 1   ? bp_unit<1>(in, H, e, out, L[wave].r)
-             : H.S == 4 ? bp_unit<4>(in, H, e, out, L[wave].r)
-                        : bp_unit<0>(in, H, e, out, L[wave].r);
+        ok = H.S == 1   ? bp_unit<1, B32>(in, H, e, out, L[wave].r)
+             : H.S == 4 ? bp_unit<4, B32>(in, H, e, out, L[wave].r)
+                        : bp_unit<0, B32>(in, H, e, out, L[wave].r);
     else
         ok = decode_tail_entry<1, false>(in, H, out, L[wave].tail);
     if (!ok && lane_id() == 0)
@@ -372,7 +376,8 @@ extern "C" int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const
 {
     if (out_count == nullptr || (na > 0 && (a == nullptr || out == nullptr)) || b_comp == nullptr ||
         b_words < kHdrWords || (nb > 0 && b_work == nullptr) || (reinterpret_cast<uintptr_t>(out_count) & 7u) ||
-        na > 0xFFFFFFFFull || (codec != WP_CODEC_BP && codec != WP_CODEC_FP) || !aligned16(b_comp) ||
+        na > 0xFFFFFFFFull || (codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32) ||
+        !aligned16(b_comp) ||
         !aligned16(b_work) || nb > 0xFFFFFFFFull * 32ull)
         return WP_ERR_INVALID_ARG;
     DevState *ds = dev_state();
@@ -384,7 +389,7 @@ extern "C" int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const
         hipLaunchKernelGGL(k_isect_none, dim3(1), dim3(64), 0, st, out_count);
         return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
     }
-    const uint64_t per = codec == WP_CODEC_BP ? kBpBlocks : kFpBlocks;
+    const uint64_t per = codec == WP_CODEC_FP ? kFpBlocks : kBpBlocks;
     const uint64_t nfull = nb / kBlock;
     const uint64_t nent = (nfull + per - 1) / per + ((nb % kBlock) ? 1 : 0);
     const uint64_t tiles = (na + kIsTile - 1) / kIsTile;
@@ -394,8 +399,11 @@ extern "C" int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const
     hipLaunchKernelGGL(k_isect_touch, dim3((uint32_t)((nent + 255) / 256)), dim3(256), 0, st, a, na, b_comp,
                        b_words, nb, codec, S.touched, ds->err);
     if (codec == WP_CODEC_BP)
-        hipLaunchKernelGGL(k_isect_decode_bp, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, b_comp, b_words,
-                           nb, S.touched, b_work, ds->err);
+        hipLaunchKernelGGL(k_isect_decode_bp<false>, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, b_comp,
+                           b_words, nb, S.touched, b_work, ds->err);
+    else if (codec == WP_CODEC_BP32)
+        hipLaunchKernelGGL(k_isect_decode_bp<true>, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, b_comp,
+                           b_words, nb, S.touched, b_work, ds->err);
     else
         hipLaunchKernelGGL(k_isect_decode_fp, dim3((uint32_t)nent), dim3(256), 0, st, b_comp, b_words, nb,
                            S.touched, b_work, ds->err);

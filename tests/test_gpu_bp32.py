@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 CANARY = 0x5A5A5A5A
 PAD = 64
-# (waves, vpl, runs per CU, depth): BP32 keeps its own depth, the rest applies
+# (waves, vpl, runs per CU, depth)
 TUNES = [(4, 4, 28, 2), (1, 4, 4, 3), (2, 4, 64, 4), (8, 4, 16, 2), (4, 4, 1, 3)]
 
 
@@ -78,7 +78,7 @@ def test_decode_lengths_strides_tunes(stride):
         x = _case(rng, n)
         cases.append((n, x, oracle.bp32_encode(x, stride)))
     for waves, vpl, wpc, depth in TUNES:
-        wp.set_decode_tune(wp.CODEC_BP, waves, vpl, wpc, depth)
+        wp.set_decode_tune(wp.CODEC_BP32, waves, vpl, wpc, depth)
         for n, x, s in cases:
             print(f"bp32 stride={stride} tune=({waves},{vpl},{wpc},{depth}) n={n}", flush=True)
             rc, got = gpu_decode(s, n)
@@ -108,7 +108,7 @@ def test_mixed_widths_every_offset(stride):
     x = d if stride == 0 else np.cumsum(d.astype(np.uint64)).astype(np.uint32)
     s = oracle.bp32_encode(x, stride)
     for waves, vpl, wpc, depth in TUNES:
-        wp.set_decode_tune(wp.CODEC_BP, waves, vpl, wpc, depth)
+        wp.set_decode_tune(wp.CODEC_BP32, waves, vpl, wpc, depth)
         print(f"bp32 mixed stride={stride} tune=({waves},{vpl},{wpc},{depth})", flush=True)
         rc, got = gpu_decode(s, x.size)
         assert rc == wp.OK
