@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 OK, ERR_ARG, ERR_CAP, ERR_CORRUPT = 0, -1, -2, -3
-CODEC_BP, CODEC_FP, CODEC_BP32 = 0, 1, 2
+CODEC_BP, CODEC_FP, CODEC_BP32, CODEC_FP32 = 0, 1, 2, 3
 
 
 def build() -> str:
@@ -59,10 +59,10 @@ def _load():
     lib.oracle_intersect.restype = u64
     lib.oracle_max_words.argtypes = [ctypes.c_int, u64]
     lib.oracle_max_words.restype = u64
-    for f in (lib.oracle_bp_encode, lib.oracle_fp_encode, lib.oracle_bp32_encode):
+    for f in (lib.oracle_bp_encode, lib.oracle_fp_encode, lib.oracle_bp32_encode, lib.oracle_fp32_encode):
         f.argtypes = [u32p, u64, ctypes.c_int, u32p, u64]
         f.restype = ctypes.c_int64
-    for f in (lib.oracle_bp_decode, lib.oracle_fp_decode, lib.oracle_bp32_decode):
+    for f in (lib.oracle_bp_decode, lib.oracle_fp_decode, lib.oracle_bp32_decode, lib.oracle_fp32_decode):
         f.argtypes = [u32p, u64, u32p, u64]
         f.restype = ctypes.c_int
     _lib = lib
@@ -169,6 +169,11 @@ def bp32_encode(x, stride: int = 1) -> np.ndarray:
     return _encode(_load().oracle_bp32_encode, CODEC_BP32, x, stride)
 
 
+def fp32_encode(x, stride: int = 1) -> np.ndarray:
+    """Patched (FastPFOR) stream of x: exception arrays padded to 32 values."""
+    return _encode(_load().oracle_fp32_encode, CODEC_FP32, x, stride)
+
+
 def _decode(fn, stream, n):
     s = _u32(stream)
     out = np.zeros(max(n, 1), dtype=np.uint32)
@@ -195,6 +200,17 @@ def bp32_decode(stream, n: int) -> np.ndarray:
     if rc != OK:
         raise ValueError(f"oracle decode failed: {rc}")
     return out
+
+
+def fp32_decode(stream, n: int) -> np.ndarray:
+    rc, out = _decode(_load().oracle_fp32_decode, stream, n)
+    if rc != OK:
+        raise ValueError(f"oracle decode failed: {rc}")
+    return out
+
+
+def fp32_decode_rc(stream, n: int) -> int:
+    return _decode(_load().oracle_fp32_decode, stream, n)[0]
 
 
 def bp32_decode_rc(stream, n: int) -> int:

@@ -26,7 +26,9 @@
  *                     values, block j in b_j words; zero-padded to a
  *                     multiple of 4 words (see oracle_bp32_encode)
  *                     patched (FastPFOR) page of up to 512 blocks: see
- *                     oracle_fp_encode
+ *                     oracle_fp_encode; exception arrays padded to 128
+ *                     values (SIMD-FastPFOR) or to 32 (FastPFOR,
+ *                     oracle_fp32_encode)
  *   tail              Variable Byte of the last n mod 128 deltas,
  *                     zero-padded to a word
  */
@@ -40,6 +42,7 @@
 #define OMAGIC_BP 0x31425057u  /* "WPB1" */
 #define OMAGIC_FP 0x31465057u  /* "WPF1" */
 #define OMAGIC_BP32 0x32335057u /* "WP32" */
+#define OMAGIC_FP32 0x33465057u /* "WPF3" */
 #define OB32 32u               /* BP32 block: 32 integers (Section 6.2) */
 
 enum { O_OK = 0, O_ERR_ARG = -1, O_ERR_CAP = -2, O_ERR_CORRUPT = -3 };
@@ -209,13 +212,13 @@ static uint64_t o_pad4(uint64_t w) { return (w + 3u) & ~(uint64_t)3u; }
 static uint64_t o_units(int codec, uint64_t n)
 {
     uint64_t nfull = n / OB;
-    uint64_t per = codec == 1 ? OFP_BLOCKS : OBP_BLOCKS;
+    uint64_t per = (codec == 1 || codec == 3) ? OFP_BLOCKS : OBP_BLOCKS;
     return (nfull + per - 1) / per;
 }
 
 static uint32_t o_magic(int codec)
 {
-    return codec == 0 ? OMAGIC_BP : codec == 1 ? OMAGIC_FP : OMAGIC_BP32;
+    return codec == 0 ? OMAGIC_BP : codec == 1 ? OMAGIC_FP : codec == 2 ? OMAGIC_BP32 : OMAGIC_FP32;
 }
 
 /* Worst-case stream size in words, computed from the layout. */
@@ -271,6 +274,16 @@ int64_t oracle_fp_encode(const uint32_t *x, uint64_t n, int stride, uint32_t *ou
 int64_t oracle_bp32_encode(const uint32_t *x, uint64_t n, int stride, uint32_t *out, uint64_t cap)
 {
     return o_encode(2, x, n, stride, out, cap);
+}
+
+/* ---- Section 5, FastPFOR: the same pages as SIMD-FastPFOR except that
+ * each exception array is padded to a multiple of 32 values (packed at k
+ * bits, 32 values in k words) instead of 128. The regular values need no
+ * change: 128 values packed one after the other at b bits are the same
+ * words as four groups of 32. */
+int64_t oracle_fp32_encode(const uint32_t *x, uint64_t n, int stride, uint32_t *out, uint64_t cap)
+{
+    return o_encode(3, x, n, stride, out, cap);
 }
 
 /* Binary-packing meta-block: the descriptor then each block's packed words. */
@@ -330,7 +343,7 @@ static uint64_t o_bp32_unit(const uint32_t *d, uint64_t nmeta, uint32_t *out)
  *       of exceptions of blocks with maxb - b = k, in block order, packed
  *       at k bits in groups of 128 (SIMD-FastPFOR pads to a multiple of 128
  *       values; the padding values are 0), 4*k words per group. */
-static uint64_t o_fp_page(const uint32_t *d, uint64_t nblocks, uint32_t *out)
+static uint64_t o_fp_page(const uint32_t *d, uint64_t nblocks, uint32_t *out, uint64_t pad)
 {
     uint32_t *bw = malloc(nblocks * sizeof(uint32_t));
     uint32_t *mb = malloc(nblocks * sizeof(uint32_t));
@@ -401,7 +414,7 @@ static uint64_t o_fp_page(const uint32_t *d, uint64_t nblocks, uint32_t *out)
     for (uint32_t k = 1; k <= 32; k++) {
         if (cnt[k] == 0)
             continue;
-        uint64_t padded = ((cnt[k] + OB - 1) / OB) * OB;
+        uint64_t padded = ((cnt[k] + pad - 1) / pad) * pad;
         for (uint64_t e = cnt[k]; e < padded; e++)
             arr[k][e] = 0;
         oracle_pack(arr[k], padded, k, out + p);
@@ -432,7 +445,7 @@ static int64_t o_encode(int codec, const uint32_t *x, uint64_t n, int stride,
     uint64_t nfull = n / OB;
     uint64_t tail = n % OB;
     uint64_t units = o_units(codec, n);
-    uint64_t per = codec == 1 ? OFP_BLOCKS : OBP_BLOCKS;
+    uint64_t per = (codec == 1 || codec == 3) ? OFP_BLOCKS : OBP_BLOCKS;
     uint64_t E = 1 + (uint64_t)stride;
     uint64_t ndir = units + (tail ? 1 : 0);
     uint64_t dir_words = o_pad4(E * ndir);
@@ -454,7 +467,7 @@ static int64_t o_encode(int codec, const uint32_t *x, uint64_t n, int stride,
                 nb = per;
             p += codec == 0   ? o_bp_unit(d + start, nb, out + p)
                  : codec == 2 ? o_bp32_unit(d + start, nb, out + p)
-                              : o_fp_page(d + start, nb, out + p);
+                              : o_fp_page(d + start, nb, out + p, codec == 3 ? 32 : OB);
         }
     }
     uint64_t tail_off = p;
@@ -530,7 +543,7 @@ static int o_bp32_unit_decode(const uint32_t *w, uint64_t avail, uint64_t nmeta,
  * listed position gains the next high part of array k = maxb - b, shifted
  * left by b. */
 static int o_fp_page_decode(const uint32_t *w, uint64_t avail, uint64_t nblocks_expected,
-                            uint32_t *d)
+                            uint32_t *d, uint64_t pad)
 {
     if (avail < 4)
         return O_ERR_CORRUPT;
@@ -570,7 +583,7 @@ static int o_fp_page_decode(const uint32_t *w, uint64_t avail, uint64_t nblocks_
     for (uint32_t k = 1; k <= 32; k++) {
         if (cnt[k] == 0)
             continue;
-        uint64_t padded = ((cnt[k] + OB - 1) / OB) * OB;
+        uint64_t padded = ((cnt[k] + pad - 1) / pad) * pad;
         if (padded * k / 32 > avail - p) {
             rc = O_ERR_CORRUPT;
             goto done;
@@ -637,7 +650,7 @@ static int o_decode(int codec, const uint32_t *in, uint64_t in_words, uint32_t *
         return O_ERR_CORRUPT;
     uint64_t nfull = n / OB, tail = n % OB;
     uint64_t units = o_units(codec, n);
-    uint64_t per = codec == 1 ? OFP_BLOCKS : OBP_BLOCKS;
+    uint64_t per = (codec == 1 || codec == 3) ? OFP_BLOCKS : OBP_BLOCKS;
     uint64_t total = in[7], tail_off = in[6], tail_bytes = in[5];
     if (in[4] != units || total > in_words || (tail == 0) != (tail_bytes == 0))
         return O_ERR_CORRUPT;
@@ -662,7 +675,7 @@ static int o_decode(int codec, const uint32_t *in, uint64_t in_words, uint32_t *
                 return O_ERR_CORRUPT;
             rc = codec == 0   ? o_bp_unit_decode(in + off, end - off, nb, out + start)
                  : codec == 2 ? o_bp32_unit_decode(in + off, end - off, nb, out + start)
-                              : o_fp_page_decode(in + off, end - off, nb, out + start);
+                              : o_fp_page_decode(in + off, end - off, nb, out + start, codec == 3 ? 32 : OB);
         } else {
             count = tail;
             if (off != tail_off || off + (tail_bytes + 3) / 4 != total)
@@ -697,6 +710,11 @@ int oracle_fp_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint6
 int oracle_bp32_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n)
 {
     return o_decode(2, in, in_words, out, n);
+}
+
+int oracle_fp32_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n)
+{
+    return o_decode(3, in, in_words, out, n);
 }
 
 /* ------------------------------------------------------------------------

@@ -329,12 +329,13 @@ def test_appendix_a_bound_on_sorted_distinct_arrays():
 
 # ---------------------------------------------------------------- round trips
 
-_ENC = {"bp": oracle.bp_encode, "fp": oracle.fp_encode, "bp32": oracle.bp32_encode}
-_DEC = {"bp": oracle.bp_decode, "fp": oracle.fp_decode, "bp32": oracle.bp32_decode}
-_RC = {"bp": oracle.bp_decode_rc, "fp": oracle.fp_decode_rc, "bp32": oracle.bp32_decode_rc}
+_ENC = {"bp": oracle.bp_encode, "fp": oracle.fp_encode, "bp32": oracle.bp32_encode, "fp32": oracle.fp32_encode}
+_DEC = {"bp": oracle.bp_decode, "fp": oracle.fp_decode, "bp32": oracle.bp32_decode, "fp32": oracle.fp32_decode}
+_RC = {"bp": oracle.bp_decode_rc, "fp": oracle.fp_decode_rc, "bp32": oracle.bp32_decode_rc,
+       "fp32": oracle.fp32_decode_rc}
 
 
-@pytest.mark.parametrize("codec", ["bp", "fp", "bp32"])
+@pytest.mark.parametrize("codec", ["bp", "fp", "bp32", "fp32"])
 @pytest.mark.parametrize("stride", [0, 1, 4])
 def test_roundtrip_every_small_length(codec, stride):
     enc, dec = _ENC[codec], _DEC[codec]
@@ -399,7 +400,7 @@ def test_patched_page_counts_match_blocks():
 
 # ---------------------------------------------------------------- corrupt input
 
-@pytest.mark.parametrize("codec", ["bp", "fp", "bp32"])
+@pytest.mark.parametrize("codec", ["bp", "fp", "bp32", "fp32"])
 def test_corrupt_streams_are_rejected(codec):
     enc, rc = _ENC[codec], _RC[codec]
     x = datagen.single_geometric(5000, seed=3)
@@ -415,7 +416,7 @@ def test_corrupt_streams_are_rejected(codec):
     assert rc(bad, 5000) == oracle.ERR_CORRUPT                 # unit offset
     unit = int(s[8])
     bad = s.copy()
-    if codec != "fp":
+    if codec in ("bp", "bp32"):
         bad[unit] = (int(bad[unit]) & ~0xFF) | 33              # width 33
     else:
         bad[unit] = 7                                          # block count
@@ -426,7 +427,8 @@ def test_max_words_bounds_worst_case():
     rng = np.random.default_rng(1)
     for n in (0, 1, 128, 2048, 65536 + 129):
         x = rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)
-        for codec, enc in ((0, oracle.bp_encode), (1, oracle.fp_encode), (2, oracle.bp32_encode)):
+        for codec, enc in ((0, oracle.bp_encode), (1, oracle.fp_encode), (2, oracle.bp32_encode),
+                           (3, oracle.fp32_encode)):
             for stride in (0, 1, 4):
                 assert enc(x, stride).size <= oracle.max_words(codec, n)
 
@@ -592,3 +594,51 @@ def test_bp32_never_wider_than_bp128_plus_descriptors():
         a, b = oracle.bp32_encode(x, 1), oracle.bp_encode(x, 1)
         metas, units = (1 << 16) // 128, (1 << 16) // 2048
         assert a.size <= b.size + metas - metas // 4 + 3 * units
+
+
+# ---------------------------------------------------------------- FastPFOR, arrays padded to 32 (Section 5)
+
+def _fp_pages(s):
+    """(offset, words, nblocks, packed_words, meta_bytes, counts by k) of each page."""
+    units = int(s[4])
+    ends = [int(s[8 + u]) for u in range(1, units)] + [int(s[6])]
+    pages = []
+    for u in range(units):
+        at = int(s[8 + u])
+        nb, packed, meta, bitset = (int(v) for v in s[at:at + 4])
+        ks = [k for k in range(1, 33) if bitset >> (k - 1) & 1]
+        counts = dict(zip(ks, (int(v) for v in s[at + 4:at + 4 + len(ks)])))
+        pages.append((at, ends[u] - at, nb, packed, meta, counts))
+    return pages
+
+
+@pytest.mark.parametrize("stride", [0, 1, 4])
+def test_fastpfor_32_padding_against_128(stride):
+    # FastPFOR and SIMD-FastPFOR differ only in how far each exception array
+    # is padded (32 values against 128): same headers, packed values and
+    # metadata; array k of the first is the first ceil(c/32)*k words of
+    # array k of the second (the same LSB-first stream of k-bit fields)
+    x = datagen.patched_gaps(3 * 65536 + 5000, seed=40 + stride)
+    a, b = oracle.fp32_encode(x, stride), oracle.fp_encode(x, stride)
+    assert int(a[0]) == 0x33465057 and int(b[0]) == 0x31465057
+    pa, pb = _fp_pages(a), _fp_pages(b)
+    assert len(pa) == len(pb) == 4
+    saved = 0
+    for (oa, wa, nba, pka, ma, ca), (ob, wb, nbb, pkb, mb_, cb) in zip(pa, pb):
+        assert (nba, pka, ma, ca) == (nbb, pkb, mb_, cb)
+        hdr = -(-(4 + len(ca)) // 4) * 4
+        meta_w = -(-ma // 16) * 4
+        fixed = hdr + pka + meta_w
+        assert np.array_equal(a[oa:oa + fixed], b[ob:ob + fixed])
+        xa, xb = oa + fixed, ob + fixed
+        for k in sorted(ca):
+            c = ca[k]
+            wa_k, wb_k = -(-c // 32) * k, -(-c // 128) * 4 * k
+            assert np.array_equal(a[xa:xa + wa_k], b[xb:xb + wa_k])
+            assert not b[xb + wa_k:xb + wb_k].any()  # the rest of the 128-padding is zero
+            xa += wa_k
+            xb += wb_k
+            saved += wb_k - wa_k
+        assert xa == oa + wa and xb == ob + wb
+    assert b.size - a.size == saved > 0
+    assert np.array_equal(oracle.fp32_decode(a, x.size), x)
