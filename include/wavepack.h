@@ -51,7 +51,10 @@
  *       b[nblocks], maxb[nblocks], c[nblocks] and all exception positions,
  *       padded to 16 bytes; then for each k ascending the high parts
  *       (delta >> b) of the exceptions of blocks with maxb - b = k, packed
- *       at k bits in groups of 128 (zero padded).
+ *       at k bits in groups of 128 (zero padded). FastPFOR (WP_CODEC_FP32,
+ *       magic 'WPF3'): the same page with each array padded to a multiple
+ *       of 32 values (k words per 32) instead of 128, and the page
+ *       zero-padded to 4 words.
  *   tail: Variable Byte (Section 2.4; 7 data bits per byte, low group
  *       first, top bit set on the last byte) of the last n % 128 deltas,
  *       zero-padded to a word.
@@ -76,6 +79,7 @@ extern "C" {
 #define WP_CODEC_BP 0 /* binary packing, 16 x 128-integer blocks per unit */
 #define WP_CODEC_FP 1 /* patched pages of 2^16 integers */
 #define WP_CODEC_BP32 2 /* binary packing, 64 x 32-integer blocks per unit */
+#define WP_CODEC_FP32 3 /* patched pages, exception arrays padded to 32 values */
 
 /* Largest stream any input of n integers can produce, in 32-bit words.
  * Host only, pure. Returns 0 when n is beyond the format (streams are
@@ -123,6 +127,18 @@ int32_t bp32_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64
 int32_t fastpfor_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,
                         uint64_t out_cap_words, uint64_t *out_words, void *stream);
 
+/* FastPFOR encoder (Section 5: as fastpfor_encode, but each page's
+ * exception arrays are padded to a multiple of 32 values, not 128, which
+ * saves up to 96 values of padding per array). Arguments as bp_encode,
+ * with WP_CODEC_FP32 for the capacity. */
+int32_t fastpfor32_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,
+                          uint64_t out_cap_words, uint64_t *out_words, void *stream);
+
+/* FastPFOR decoder for fastpfor32_encode's streams: as fastpfor_decode.
+ * Allocates nothing. */
+int32_t fastpfor32_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
+                          void *stream);
+
 /* Patched decoder (Section 5): unpack each block's low bits, patch each
  * exception with its high part from array k shifted left by b, then the
  * prefix sum. Arguments as bp_decode. Allocates nothing. */
@@ -154,7 +170,7 @@ int32_t wp_intersect(const uint32_t *a, uint64_t na, const uint32_t *b, uint64_t
                      uint64_t *out_count, void *stream);
 
 /* As wp_intersect, with the second list still compressed (`b_comp`,
- * b_words words, nb integers, codec WP_CODEC_BP, WP_CODEC_BP32 or WP_CODEC_FP; 16-byte
+ * b_words words, nb integers, any WP_CODEC_*; 16-byte
  * aligned): the directory serves as a skip list. A strictly increasing
  * list's unit holds values between the value stored as its base (the value
  * just before the unit) and the next unit's, so only the units (and the

@@ -8,7 +8,9 @@
 // side. The workgroup after the last run decodes the Variable Byte tail.
 // BP32 streams (32-integer blocks) take the same kernel in its B32 mode.
 //
-// Patched pages: one workgroup per page (see fp_page).
+// Patched pages: one workgroup per page (see fp_page); FastPFOR streams
+// (exception arrays padded to 32 values) take the same kernel in its P32
+// mode.
 #include <mutex>
 #include <vector>
 
@@ -65,14 +67,14 @@ union FpKernelLds {
 };
 
 // One workgroup per page; the workgroup after the last page decodes the tail.
-template <int WAVES>
+template <int WAVES, bool P32 = false>
 __global__ __launch_bounds__(64 * WAVES) void k_fp_decode(const uint32_t *__restrict__ in, uint64_t in_words,
                                                           uint32_t *__restrict__ out, uint64_t n,
                                                           int *__restrict__ err)
 {
     __shared__ FpKernelLds<WAVES> L;
     ListHdr H;
-    if (!check_header(in, in_words, n, kMagicFP, kFpBlocks, H)) {
+    if (!check_header(in, in_words, n, P32 ? kMagicFP32 : kMagicFP, kFpBlocks, H)) {
         if (blockIdx.x == 0 && threadIdx.x == 0)
             *err = kErrCorrupt;
         return;
@@ -92,9 +94,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_fp_decode(const uint32_t *__rest
         const uint64_t left = H.nfull - u * kFpBlocks;
         const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
         if (ok)
-            ok = H.S == 1 ? fp_page<WAVES, 1>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp)
-               : H.S == 4 ? fp_page<WAVES, 4>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp)
-                          : fp_page<WAVES, 0>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp);
+            ok = H.S == 1 ? fp_page<WAVES, 1, 3, P32>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp)
+               : H.S == 4 ? fp_page<WAVES, 4, 3, P32>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp)
+                          : fp_page<WAVES, 0, 3, P32>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp);
     }
     if (!ok && threadIdx.x == 0)
         *err = kErrCorrupt;
@@ -113,8 +115,13 @@ LaunchEvents take_launch_events()
     t_events = LaunchEvents{};
     return e;
 }
-// per codec: SIMD-BP128, patched pages, BP32
+// per tuning slot: SIMD-BP128, patched pages (both paddings), BP32
 static Tune g_tune[3] = {{4, 4, kBpRunsPerCu, 2}, {4, 4, 0, 0}, {4, 4, kBpRunsPerCu, 2}};
+
+static int tune_slot(int codec)
+{
+    return (codec == WP_CODEC_FP || codec == WP_CODEC_FP32) ? 1 : codec == WP_CODEC_BP32 ? 2 : 0;
+}
 
 DevState *dev_state()
 {
@@ -146,7 +153,7 @@ DevState *dev_state()
 Tune decode_tune(int codec)
 {
     std::lock_guard<std::mutex> lk(g_mu);
-    return g_tune[codec == WP_CODEC_FP ? 1 : codec == WP_CODEC_BP32 ? 2 : 0];
+    return g_tune[tune_slot(codec)];
 }
 
 static bool valid_tune(int codec, int waves, int vpl)
@@ -165,10 +172,14 @@ static void launch_bp(uint64_t grid, hipStream_t st, const uint32_t *in, uint64_
 }
 
 template <int WAVES>
-static void launch_fp(uint64_t grid, hipStream_t st, const uint32_t *in, uint64_t in_words, uint32_t *out,
+static void launch_fp(bool p32, uint64_t grid, hipStream_t st, const uint32_t *in, uint64_t in_words, uint32_t *out,
                       uint64_t n, int *err)
 {
-    launch_timed(k_fp_decode<WAVES>, dim3((uint32_t)grid), dim3(64 * WAVES), st, in, in_words, out, n, err);
+    if (p32)
+        launch_timed(k_fp_decode<WAVES, true>, dim3((uint32_t)grid), dim3(64 * WAVES), st, in, in_words, out, n,
+                     err);
+    else
+        launch_timed(k_fp_decode<WAVES>, dim3((uint32_t)grid), dim3(64 * WAVES), st, in, in_words, out, n, err);
 }
 
 static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
@@ -183,14 +194,15 @@ static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, u
     DevState *ds = dev_state();
     if (ds == nullptr)
         return WP_ERR_HIP;
-    const uint64_t per = codec == WP_CODEC_FP ? kFpBlocks : kBpBlocks;
+    const bool paged = codec == WP_CODEC_FP || codec == WP_CODEC_FP32;
+    const uint64_t per = paged ? kFpBlocks : kBpBlocks;
     const uint64_t nfull = n / kBlock;
     const uint64_t units = (nfull + per - 1) / per;
     const uint64_t has_tail = (n % kBlock) ? 1 : 0;
     hipStream_t st = as_stream(stream);
     const Tune t = decode_tune(codec);
     (void)hipGetLastError();
-    if (codec != WP_CODEC_FP) {
+    if (!paged) {
         // runs of upw meta-blocks, one per wavefront: about wg_per_cu runs
         // per compute unit
         const uint64_t target = (uint64_t)ds->cus * (uint64_t)(t.wg_per_cu > 0 ? t.wg_per_cu : kBpRunsPerCu);
@@ -222,12 +234,13 @@ static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, u
         grid = grid ? grid : 1;
         if (grid > 0x7FFFFFFFull)
             return WP_ERR_INVALID_ARG;
+        const bool p32 = codec == WP_CODEC_FP32;
         if (t.waves == 2)
-            launch_fp<2>(grid, st, in, in_words, out, n, ds->err);
+            launch_fp<2>(p32, grid, st, in, in_words, out, n, ds->err);
         else if (t.waves == 4)
-            launch_fp<4>(grid, st, in, in_words, out, n, ds->err);
+            launch_fp<4>(p32, grid, st, in, in_words, out, n, ds->err);
         else
-            launch_fp<8>(grid, st, in, in_words, out, n, ds->err);
+            launch_fp<8>(p32, grid, st, in, in_words, out, n, ds->err);
     }
     return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
 }
@@ -252,14 +265,20 @@ extern "C" int32_t bp32_decode(const uint32_t *in, uint64_t in_words, uint32_t *
     return decode_common(WP_CODEC_BP32, in, in_words, out, n, stream);
 }
 
+extern "C" int32_t fastpfor32_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
+                                     void *stream)
+{
+    return decode_common(WP_CODEC_FP32, in, in_words, out, n, stream);
+}
+
 extern "C" int32_t wp_set_decode_tune(int32_t codec, int32_t waves, int32_t vpl, int32_t depth, int32_t wg_per_cu)
 {
-    if ((codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32) || !valid_tune(codec, waves, vpl) ||
-        wg_per_cu < 0 ||
+    if ((codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32 && codec != WP_CODEC_FP32) ||
+        !valid_tune(codec, waves, vpl) || wg_per_cu < 0 ||
         wg_per_cu > 1024 || depth < 0 || depth == 1 || depth > 4)
         return WP_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(g_mu);
-    g_tune[codec] = Tune{waves, vpl, wg_per_cu, depth ? depth : 2};
+    g_tune[tune_slot(codec)] = Tune{waves, vpl, wg_per_cu, depth ? depth : 2};
     return WP_OK;
 }
 
@@ -305,10 +324,10 @@ extern "C" const char *wp_strerror(int32_t code)
 
 extern "C" uint64_t wp_max_compressed_words(int32_t codec, uint64_t n)
 {
-    if (codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32)
+    if (codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32 && codec != WP_CODEC_FP32)
         return 0;
     const uint64_t nfull = n / kBlock, tail = n % kBlock;
-    const uint64_t per = codec == WP_CODEC_FP ? kFpBlocks : kBpBlocks;
+    const uint64_t per = (codec == WP_CODEC_FP || codec == WP_CODEC_FP32) ? kFpBlocks : kBpBlocks;
     const uint64_t units = (nfull + per - 1) / per;
     uint64_t w = kHdrWords + ((5 * (units + 1) + 3) & ~3ull);
     if (codec == WP_CODEC_BP) {

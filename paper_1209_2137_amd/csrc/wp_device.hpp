@@ -33,6 +33,17 @@ constexpr uint32_t kMagicBP = 0x31425057u;  // "WPB1"
 constexpr uint32_t kMagicFP = 0x31465057u;  // "WPF1"
 constexpr uint32_t kMagicBP32 = 0x32335057u;  // "WP32"
 constexpr uint32_t kB32 = 32;                 // BP32 block length (Section 6.2)
+constexpr uint32_t kMagicFP32 = 0x33465057u;  // "WPF3"
+
+// Words of a page's exception array of `cnt` values at k bits, padded to a
+// multiple of 128 values (SIMD-FastPFOR) or of 32 (FastPFOR, P32); either
+// way the values form one stream of k-bit fields, least significant first.
+// A FastPFOR page ends zero-padded to 4 words.
+template <bool P32>
+__device__ __forceinline__ uint32_t exc_array_words(uint32_t cnt, uint32_t k)
+{
+    return P32 ? ((cnt + 31u) / 32u) * k : ((cnt + kBlock - 1) / kBlock) * 4u * k;
+}
 constexpr uint32_t kHdrWords = 8;
 constexpr uint32_t kMaxTailBytes = 127 * 5;
 constexpr int kErrCorrupt = -3;
@@ -586,7 +597,7 @@ struct FpPair {
 // blocks: wavefront w decodes pair w of the pass (FpPair), the words and
 // exceptions of the next SLOTS - 1 passes in flight; one barrier per pass
 // hands the wavefront totals over for the prefix sum.
-template <int WAVES, uint32_t S, int SLOTS = 3>
+template <int WAVES, uint32_t S, int SLOTS = 3, bool P32 = false>
 __device__ __forceinline__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint32_t nb,
                         const uint32_t (&base)[4], uint32_t *__restrict__ out, FpLds<WAVES> &L)
 {
@@ -617,7 +628,7 @@ __device__ __forceinline__ bool fp_page(const uint32_t *__restrict__ page, uint3
         const uint32_t ci = kl ? (uint32_t)__builtin_popcount(bitset & ((1u << (lane & 31u)) - 1u)) : 0u;
         const uint32_t cnt = set ? page[4 + ci] : 0u;
         const bool badk = set && (cnt == 0 || cnt > nb * kBlock);
-        const uint32_t wk = (set && !badk) ? ((cnt + kBlock - 1) / kBlock) * 4u * k : 0u;
+        const uint32_t wk = (set && !badk) ? exc_array_words<P32>(cnt, k) : 0u;
         const uint32_t incl = wave_scan_incl(wk);
         const uint32_t tot = wave_read(incl, 63);
         const uint64_t anybad = ballot(badk);
@@ -632,7 +643,7 @@ __device__ __forceinline__ bool fp_page(const uint32_t *__restrict__ page, uint3
             L.kcnt[0] = 0;
         }
         if (lane == 0)
-            L.bad = (anybad != 0 || exc_at + tot != nwords) ? 1u : 0u;
+            L.bad = (anybad != 0 || (P32 ? pad4(exc_at + tot) : exc_at + tot) != nwords) ? 1u : 0u;
     }
     const uint32_t nbr = ((nb + T - 1) / T) * T;  // the rounds of the table pass (entries beyond nb are 0)
     for (uint32_t t = tid; t < nbr; t += T) {
@@ -786,7 +797,7 @@ struct alignas(16) FpWaveLds {
     uint4 rec[64 + 8];  // zero past the last block (fetches run two pairs ahead)
 };
 
-template <uint32_t S>
+template <uint32_t S, bool P32 = false>
 __device__ __forceinline__ bool fp_small_page(const uint32_t *__restrict__ page, uint32_t nwords, uint32_t nb,
                               const uint32_t (&base)[4], uint32_t *__restrict__ out, FpWaveLds &L)
 {
@@ -810,10 +821,11 @@ __device__ __forceinline__ bool fp_small_page(const uint32_t *__restrict__ page,
     const uint32_t ci = kl ? (uint32_t)__builtin_popcount(bitset & ((1u << (lane & 31u)) - 1u)) : 0u;
     const uint32_t cnt = set ? page[4 + ci] : 0u;
     const bool badk = set && (cnt == 0 || cnt > nb * kBlock);
-    const uint32_t wk = (set && !badk) ? ((cnt + kBlock - 1) / kBlock) * 4u * kown : 0u;
+    const uint32_t wk = (set && !badk) ? exc_array_words<P32>(cnt, kown) : 0u;
     const uint32_t kincl = wave_scan_incl(wk);
     const uint32_t excb = exc_at + kincl - wk;  // lane k - 1: first word of array k
-    bool bad = ballot(badk) != 0 || exc_at + wave_read(kincl, 63) != nwords;
+    const uint32_t exc_end = exc_at + wave_read(kincl, 63);
+    bool bad = ballot(badk) != 0 || (P32 ? pad4(exc_end) : exc_end) != nwords;
     // blocks: lane j owns block j
     const bool own = lane < nb;
     const uint32_t b = own ? meta[lane] : 0u, mb = own ? meta[nb + lane] : 0u, c = own ? meta[2 * nb + lane] : 0u;

@@ -294,6 +294,7 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v)
     return v;
 }
 
+template <bool P32>
 __global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
                                                     uint8_t *__restrict__ meta, uint64_t nblk,
                                                     uint32_t *__restrict__ sizes)
@@ -365,16 +366,17 @@ __global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__
         for (uint32_t k = 1; k <= 32; ++k)
             if (s_cnt[k]) {
                 ++nset;
-                exc_w += ((s_cnt[k] + kBlock - 1) / kBlock) * 4 * k;
+                exc_w += exc_array_words<P32>(s_cnt[k], k);
             }
         const uint32_t meta_bytes = 3 * nb + s_pc;
-        sizes[p] = pad4(4 + nset) + s_pw + ((meta_bytes + 15) / 16) * 4 + exc_w;
+        sizes[p] = pad4(pad4(4 + nset) + s_pw + ((meta_bytes + 15) / 16) * 4 + exc_w);
     }
 }
 
 // LDS staging of a page's metadata and exception arrays in k_fp_pack
 constexpr uint32_t kPackTailWords = 8192;
 
+template <bool P32>
 __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
                                                  const uint8_t *__restrict__ meta, uint64_t nblk,
                                                  const uint32_t *__restrict__ incl, uint32_t dir_end,
@@ -416,12 +418,12 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
     if (wave == 0) {
         const uint32_t k = lane + 1;
         const uint32_t cnt = lane < 32 ? L.kcar[k] : 0u;
-        const uint32_t wk = ((cnt + kBlock - 1) / kBlock) * 4u * k;
+        const uint32_t wk = exc_array_words<P32>(cnt, k);
         const uint32_t incl_k = wave_scan_incl(wk);
         if (lane < 32)
             L.excbase[k] = exc_at + incl_k - wk;
         if (lane == 63)
-            L.kcnt[0] = exc_at + incl_k;  // page length in words
+            L.kcnt[0] = pad4(exc_at + incl_k);  // page length in words
     }
     __syncthreads();
     const uint32_t size = L.kcnt[0];
@@ -566,7 +568,10 @@ __global__ __launch_bounds__(128) void k_finish(const uint32_t *__restrict__ x, 
         out[i] = 0;
     const uint32_t total = tail_off + (tail_bytes + 3) / 4;
     if (tid == 0) {
-        out[0] = codec == WP_CODEC_BP ? kMagicBP : codec == WP_CODEC_BP32 ? kMagicBP32 : kMagicFP;
+        out[0] = codec == WP_CODEC_BP     ? kMagicBP
+                 : codec == WP_CODEC_BP32 ? kMagicBP32
+                 : codec == WP_CODEC_FP32 ? kMagicFP32
+                                          : kMagicFP;
         out[1] = (uint32_t)n;
         out[2] = (uint32_t)(n >> 32);
         out[3] = S;
@@ -592,7 +597,8 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
         return WP_ERR_INVALID_ARG;
     if (cap < need)
         return WP_ERR_CAPACITY;
-    const uint64_t per = codec == WP_CODEC_FP ? kFpBlocks : kBpBlocks;
+    const bool paged = codec == WP_CODEC_FP || codec == WP_CODEC_FP32;
+    const uint64_t per = paged ? kFpBlocks : kBpBlocks;
     const uint64_t nfull = n / kBlock;
     const uint64_t units = (nfull + per - 1) / per;
     const uint64_t E = 1 + (uint64_t)stride;
@@ -619,9 +625,12 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
         else if (codec == WP_CODEC_BP32)
             hipLaunchKernelGGL(k_bp32_analyze, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride,
                                meta, sizes);
+        else if (codec == WP_CODEC_FP32)
+            hipLaunchKernelGGL(k_fp_analyze<true>, dim3((uint32_t)units), dim3(512), 0, st, in, n, (uint32_t)stride,
+                               meta, nblk, sizes);
         else
-            hipLaunchKernelGGL(k_fp_analyze, dim3((uint32_t)units), dim3(512), 0, st, in, n, (uint32_t)stride, meta,
-                               nblk, sizes);
+            hipLaunchKernelGGL(k_fp_analyze<false>, dim3((uint32_t)units), dim3(512), 0, st, in, n, (uint32_t)stride,
+                               meta, nblk, sizes);
         if (launch_inclusive_scan(sizes, units, status, st) != WP_OK)
             return WP_ERR_HIP;
         if (codec == WP_CODEC_BP)
@@ -630,9 +639,12 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
         else if (codec == WP_CODEC_BP32)
             hipLaunchKernelGGL(k_bp32_pack, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride, meta,
                                sizes, dir_end, out);
+        else if (codec == WP_CODEC_FP32)
+            hipLaunchKernelGGL(k_fp_pack<true>, dim3((uint32_t)units), dim3(512), 0, st, in, n, (uint32_t)stride,
+                               meta, nblk, sizes, dir_end, out);
         else
-            hipLaunchKernelGGL(k_fp_pack, dim3((uint32_t)units), dim3(512), 0, st, in, n, (uint32_t)stride, meta,
-                               nblk, sizes, dir_end, out);
+            hipLaunchKernelGGL(k_fp_pack<false>, dim3((uint32_t)units), dim3(512), 0, st, in, n, (uint32_t)stride,
+                               meta, nblk, sizes, dir_end, out);
     }
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(128), 0, st, in, n, (uint32_t)stride, (uint32_t)codec, sizes, units,
                        dir_end, out, out_words);
@@ -653,6 +665,12 @@ extern "C" int32_t bp32_encode(const uint32_t *in, uint64_t n, int32_t delta_str
                                uint64_t out_cap_words, uint64_t *out_words, void *stream)
 {
     return encode_common(WP_CODEC_BP32, in, n, delta_stride, out, out_cap_words, out_words, stream);
+}
+
+extern "C" int32_t fastpfor32_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,
+                                     uint64_t out_cap_words, uint64_t *out_words, void *stream)
+{
+    return encode_common(WP_CODEC_FP32, in, n, delta_stride, out, out_cap_words, out_words, stream);
 }
 
 extern "C" int32_t fastpfor_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,

@@ -152,8 +152,11 @@ __device__ __forceinline__ bool dir_view(const uint32_t *in, uint64_t in_words, 
                                          DirView &D)
 {
     D.in = in;
-    D.per = codec == WP_CODEC_FP ? kFpBlocks : kBpBlocks;
-    const uint32_t magic = codec == WP_CODEC_BP ? kMagicBP : codec == WP_CODEC_BP32 ? kMagicBP32 : kMagicFP;
+    D.per = (codec == WP_CODEC_FP || codec == WP_CODEC_FP32) ? kFpBlocks : kBpBlocks;
+    const uint32_t magic = codec == WP_CODEC_BP     ? kMagicBP
+                           : codec == WP_CODEC_BP32 ? kMagicBP32
+                           : codec == WP_CODEC_FP32 ? kMagicFP32
+                                                    : kMagicFP;
     return check_header(in, in_words, n, magic, D.per, D.H);
 }
 
@@ -228,14 +231,16 @@ union IsectPageLds {
     TailLds<4> tail;
 };
 
-// Decodes the flagged entries of a patched-page stream (one workgroup per page).
+// Decodes the flagged entries of a patched-page stream (one workgroup per
+// page; P32: exception arrays padded to 32 values).
+template <bool P32>
 __global__ __launch_bounds__(256) void k_isect_decode_fp(const uint32_t *__restrict__ in, uint64_t in_words,
                                                          uint64_t n, const uint8_t *__restrict__ flags,
                                                          uint32_t *__restrict__ out, int *__restrict__ err)
 {
     __shared__ IsectPageLds L;
     ListHdr H;
-    if (!check_header(in, in_words, n, kMagicFP, kFpBlocks, H))
+    if (!check_header(in, in_words, n, P32 ? kMagicFP32 : kMagicFP, kFpBlocks, H))
         return;  // reported by k_isect_touch
     const uint64_t u = blockIdx.x;
     if (u >= H.ndir || !flags[u])
@@ -252,9 +257,9 @@ __global__ __launch_bounds__(256) void k_isect_decode_fp(const uint32_t *__restr
         const uint64_t left = H.nfull - u * kFpBlocks;
         const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
         ok = off >= H.dir_end && end >= off && end <= H.total && (off & 3u) == 0 &&
-             (H.S == 1   ? fp_page<4, 1, 2>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp)
-              : H.S == 4 ? fp_page<4, 4, 2>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp)
-                         : fp_page<4, 0, 2>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp));
+             (H.S == 1   ? fp_page<4, 1, 2, P32>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp)
+              : H.S == 4 ? fp_page<4, 4, 2, P32>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp)
+                         : fp_page<4, 0, 2, P32>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp));
     }
     if (!ok && threadIdx.x == 0)
         *err = kErrCorrupt;
@@ -376,7 +381,8 @@ extern "C" int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const
 {
     if (out_count == nullptr || (na > 0 && (a == nullptr || out == nullptr)) || b_comp == nullptr ||
         b_words < kHdrWords || (nb > 0 && b_work == nullptr) || (reinterpret_cast<uintptr_t>(out_count) & 7u) ||
-        na > 0xFFFFFFFFull || (codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32) ||
+        na > 0xFFFFFFFFull ||
+        (codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32 && codec != WP_CODEC_FP32) ||
         !aligned16(b_comp) ||
         !aligned16(b_work) || nb > 0xFFFFFFFFull * 32ull)
         return WP_ERR_INVALID_ARG;
@@ -389,7 +395,7 @@ extern "C" int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const
         hipLaunchKernelGGL(k_isect_none, dim3(1), dim3(64), 0, st, out_count);
         return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
     }
-    const uint64_t per = codec == WP_CODEC_FP ? kFpBlocks : kBpBlocks;
+    const uint64_t per = (codec == WP_CODEC_FP || codec == WP_CODEC_FP32) ? kFpBlocks : kBpBlocks;
     const uint64_t nfull = nb / kBlock;
     const uint64_t nent = (nfull + per - 1) / per + ((nb % kBlock) ? 1 : 0);
     const uint64_t tiles = (na + kIsTile - 1) / kIsTile;
@@ -404,8 +410,11 @@ extern "C" int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const
     else if (codec == WP_CODEC_BP32)
         hipLaunchKernelGGL(k_isect_decode_bp<true>, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, b_comp,
                            b_words, nb, S.touched, b_work, ds->err);
+    else if (codec == WP_CODEC_FP32)
+        hipLaunchKernelGGL(k_isect_decode_fp<true>, dim3((uint32_t)nent), dim3(256), 0, st, b_comp, b_words, nb,
+                           S.touched, b_work, ds->err);
     else
-        hipLaunchKernelGGL(k_isect_decode_fp, dim3((uint32_t)nent), dim3(256), 0, st, b_comp, b_words, nb,
+        hipLaunchKernelGGL(k_isect_decode_fp<false>, dim3((uint32_t)nent), dim3(256), 0, st, b_comp, b_words, nb,
                            S.touched, b_work, ds->err);
     hipLaunchKernelGGL(k_isect_flag_dir, dim3((uint32_t)tiles), dim3(kIsThreads), 0, st, a, na, b_comp, b_words, nb,
                        codec, b_work, S.flags, S.counts);
