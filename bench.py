@@ -121,7 +121,8 @@ def bench_single(wp, x_np, codec, stride, steps, warmup, name, comp=None, n=None
         xd = None
     comps = replicas(comp, comp.numel() * 4)
     outs = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(2)]
-    dec = {wp.CODEC_BP: wp.bp_decode, wp.CODEC_FP: wp.fastpfor_decode, wp.CODEC_BP32: wp.bp32_decode}[codec]
+    dec = {wp.CODEC_BP: wp.bp_decode, wp.CODEC_FP: wp.fastpfor_decode, wp.CODEC_BP32: wp.bp32_decode,
+           wp.CODEC_FP32: wp.fastpfor32_decode}[codec]
     stream = torch.cuda.current_stream()
     dec(comps[0], n, outs[0])
     wp.check()
@@ -134,7 +135,8 @@ def bench_single(wp, x_np, codec, stride, steps, warmup, name, comp=None, n=None
     comp_bytes = comp.numel() * 4
     alg = comp_bytes + 4 * n
     return {
-        "name": name, "n": n, "codec": {wp.CODEC_BP: "bp", wp.CODEC_FP: "fp", wp.CODEC_BP32: "bp32"}[codec],
+        "name": name, "n": n,
+        "codec": {wp.CODEC_BP: "bp", wp.CODEC_FP: "fp", wp.CODEC_BP32: "bp32", wp.CODEC_FP32: "fp32"}[codec],
         "stride": stride,
         "bits_per_int": comp_bytes * 8 / n, "ms_per_step": wall, "kernel_ms": ev,
         "gints_per_s": n / (wall * 1e-3) / 1e9, "kernel_gints_per_s": n / (ev * 1e-3) / 1e9,
@@ -518,6 +520,8 @@ def main():
         p = bench_single(wp, datagen.patched_gaps(1 << 28, seed=4), wp.CODEC_FP, 1, args.steps, args.warmup,
                          "fastpfor patched 2^28")
         extra["fp_patched_2e28"] = p
+        extra["fp32_patched_2e28"] = bench_single(wp, datagen.patched_gaps(1 << 28, seed=4), wp.CODEC_FP32, 1,
+                                                  args.steps, args.warmup, "fastpfor (arrays padded to 32) 2^28")
         print("# patched done", file=sys.stderr, flush=True)
         extra["delta_inplace_2e28"] = bench_delta(wp, 1 << 28, args.steps, args.warmup)
         print("# delta done", file=sys.stderr, flush=True)

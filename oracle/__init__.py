@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 OK, ERR_ARG, ERR_CAP, ERR_CORRUPT = 0, -1, -2, -3
-CODEC_BP, CODEC_FP, CODEC_BP32, CODEC_FP32 = 0, 1, 2, 3
+CODEC_BP, CODEC_FP, CODEC_BP32, CODEC_FP32, CODEC_BPV = 0, 1, 2, 3, 4
 
 
 def build() -> str:
@@ -47,6 +47,8 @@ def _load():
     lib.oracle_bits.restype = ctypes.c_uint32
     lib.oracle_pack.argtypes = [u32p, u64, ctypes.c_uint32, u32p]
     lib.oracle_unpack.argtypes = [u32p, u64, ctypes.c_uint32, u32p]
+    lib.oracle_pack_vertical.argtypes = [u32p, u64, ctypes.c_uint32, u32p]
+    lib.oracle_unpack_vertical.argtypes = [u32p, u64, ctypes.c_uint32, u32p]
     for f in (lib.oracle_delta_encode_inplace, lib.oracle_delta_decode_inplace):
         f.argtypes = [u32p, u64, ctypes.c_uint32, ctypes.c_int]
         f.restype = ctypes.c_int
@@ -59,10 +61,12 @@ def _load():
     lib.oracle_intersect.restype = u64
     lib.oracle_max_words.argtypes = [ctypes.c_int, u64]
     lib.oracle_max_words.restype = u64
-    for f in (lib.oracle_bp_encode, lib.oracle_fp_encode, lib.oracle_bp32_encode, lib.oracle_fp32_encode):
+    for f in (lib.oracle_bp_encode, lib.oracle_fp_encode, lib.oracle_bp32_encode, lib.oracle_fp32_encode,
+              lib.oracle_bpv_encode):
         f.argtypes = [u32p, u64, ctypes.c_int, u32p, u64]
         f.restype = ctypes.c_int64
-    for f in (lib.oracle_bp_decode, lib.oracle_fp_decode, lib.oracle_bp32_decode, lib.oracle_fp32_decode):
+    for f in (lib.oracle_bp_decode, lib.oracle_fp_decode, lib.oracle_bp32_decode, lib.oracle_fp32_decode,
+              lib.oracle_bpv_decode):
         f.argtypes = [u32p, u64, u32p, u64]
         f.restype = ctypes.c_int
     _lib = lib
@@ -99,6 +103,22 @@ def unpack(words, count: int, b: int) -> np.ndarray:
     out = np.zeros(count, dtype=np.uint32)
     _load().oracle_unpack(_p32(w if w.size else np.zeros(1, np.uint32)), count, b, _p32(out))
     return out
+
+
+def pack_vertical(vals, b: int) -> np.ndarray:
+    """Four interleaved 32-bit lanes, value i in lane i % 4 (Section 4's
+    vectorized layout); len(vals) a multiple of 4."""
+    v = _u32(vals)
+    out = np.zeros(4 * ((v.size // 4 * b + 31) // 32) or 1, dtype=np.uint32)
+    _load().oracle_pack_vertical(_p32(v), v.size, b, _p32(out))
+    return out[:4 * ((v.size // 4 * b + 31) // 32)]
+
+
+def unpack_vertical(words, count: int, b: int) -> np.ndarray:
+    w = _u32(words)
+    out = np.zeros(max(count, 1), dtype=np.uint32)
+    _load().oracle_unpack_vertical(_p32(w if w.size else np.zeros(1, np.uint32)), count, b, _p32(out))
+    return out[:count]
 
 
 def delta_encode_inplace(data: np.ndarray, init: int = 0, stride: int = 1) -> int:
@@ -174,6 +194,11 @@ def fp32_encode(x, stride: int = 1) -> np.ndarray:
     return _encode(_load().oracle_fp32_encode, CODEC_FP32, x, stride)
 
 
+def bpv_encode(x, stride: int = 1) -> np.ndarray:
+    """SIMD-BP128 stream of x with the paper's four-lane (vertical) block layout."""
+    return _encode(_load().oracle_bpv_encode, CODEC_BPV, x, stride)
+
+
 def _decode(fn, stream, n):
     s = _u32(stream)
     out = np.zeros(max(n, 1), dtype=np.uint32)
@@ -211,6 +236,17 @@ def fp32_decode(stream, n: int) -> np.ndarray:
 
 def fp32_decode_rc(stream, n: int) -> int:
     return _decode(_load().oracle_fp32_decode, stream, n)[0]
+
+
+def bpv_decode(stream, n: int) -> np.ndarray:
+    rc, out = _decode(_load().oracle_bpv_decode, stream, n)
+    if rc != OK:
+        raise ValueError(f"oracle decode failed: {rc}")
+    return out
+
+
+def bpv_decode_rc(stream, n: int) -> int:
+    return _decode(_load().oracle_bpv_decode, stream, n)[0]
 
 
 def bp32_decode_rc(stream, n: int) -> int:

@@ -43,6 +43,7 @@
 #define OMAGIC_FP 0x31465057u  /* "WPF1" */
 #define OMAGIC_BP32 0x32335057u /* "WP32" */
 #define OMAGIC_FP32 0x33465057u /* "WPF3" */
+#define OMAGIC_BPV 0x31565057u  /* "WPV1" */
 #define OB32 32u               /* BP32 block: 32 integers (Section 6.2) */
 
 enum { O_OK = 0, O_ERR_ARG = -1, O_ERR_CAP = -2, O_ERR_CORRUPT = -3 };
@@ -86,6 +87,42 @@ void oracle_unpack(const uint32_t *words, uint64_t count, uint32_t b, uint32_t *
         for (uint32_t j = 0; j < b; j++) {
             uint64_t bit = i * b + j;
             if ((words[bit / 32] >> (bit % 32)) & 1u)
+                v |= 1u << j;
+        }
+        vals[i] = v;
+    }
+}
+
+/* ---- Section 4, vectorized layout (the 4 x 32-bit figure for b = 5):
+ * values go round-robin to four 32-bit lanes -- value i to lane i mod 4,
+ * as that lane's field i div 4 -- each lane lays its fields end to end,
+ * least significant bit first, and the lanes' words interleave: bit q of
+ * lane l is bit q mod 32 of word 4 (q div 32) + l. count must be a
+ * multiple of 4 (128 in a block). Written bit by bit; `words` (4 words per
+ * 32 bits of a lane) are cleared first. */
+void oracle_pack_vertical(const uint32_t *vals, uint64_t count, uint32_t b, uint32_t *words)
+{
+    uint64_t nwords = 4 * ((count / 4 * b + 31) / 32);
+    memset(words, 0, nwords * sizeof(uint32_t));
+    for (uint64_t i = 0; i < count; i++) {
+        uint64_t lane = i % 4, field = i / 4;
+        for (uint32_t j = 0; j < b; j++) {
+            if ((vals[i] >> j) & 1u) {
+                uint64_t q = field * b + j; /* bit q of the lane */
+                words[4 * (q / 32) + lane] |= 1u << (q % 32);
+            }
+        }
+    }
+}
+
+void oracle_unpack_vertical(const uint32_t *words, uint64_t count, uint32_t b, uint32_t *vals)
+{
+    for (uint64_t i = 0; i < count; i++) {
+        uint64_t lane = i % 4, field = i / 4;
+        uint32_t v = 0;
+        for (uint32_t j = 0; j < b; j++) {
+            uint64_t q = field * b + j;
+            if ((words[4 * (q / 32) + lane] >> (q % 32)) & 1u)
                 v |= 1u << j;
         }
         vals[i] = v;
@@ -218,7 +255,8 @@ static uint64_t o_units(int codec, uint64_t n)
 
 static uint32_t o_magic(int codec)
 {
-    return codec == 0 ? OMAGIC_BP : codec == 1 ? OMAGIC_FP : codec == 2 ? OMAGIC_BP32 : OMAGIC_FP32;
+    return codec == 0 ? OMAGIC_BP : codec == 1 ? OMAGIC_FP : codec == 2 ? OMAGIC_BP32 : codec == 3 ? OMAGIC_FP32
+                                                                                       : OMAGIC_BPV;
 }
 
 /* Worst-case stream size in words, computed from the layout. */
@@ -228,7 +266,7 @@ uint64_t oracle_max_words(int codec, uint64_t n)
     uint64_t tail = n % OB;
     uint64_t units = o_units(codec, n);
     uint64_t words = 8 + o_pad4((1 + 4) * (units + 1));
-    if (codec == 0) {
+    if (codec == 0 || codec == 4) {
         words += units * 4 + nfull * OB;
     } else if (codec == 2) {
         /* a descriptor word per 128 values, every block at 32 bits, and at
@@ -280,14 +318,26 @@ int64_t oracle_bp32_encode(const uint32_t *x, uint64_t n, int stride, uint32_t *
  * each exception array is padded to a multiple of 32 values (packed at k
  * bits, 32 values in k words) instead of 128. The regular values need no
  * change: 128 values packed one after the other at b bits are the same
- * words as four groups of 32. */
+ * words as four groups of 32. The page is zero-padded to 4 words (units
+ * start on 16-byte boundaries). */
 int64_t oracle_fp32_encode(const uint32_t *x, uint64_t n, int stride, uint32_t *out, uint64_t cap)
 {
     return o_encode(3, x, n, stride, out, cap);
 }
 
-/* Binary-packing meta-block: the descriptor then each block's packed words. */
-static uint64_t o_bp_unit(const uint32_t *d, uint64_t nblocks, uint32_t *out)
+/* ---- Section 6.2 with the vectorized layout of Section 4: the SIMD-BP128
+ * stream as the paper's own code lays it out, each block packed across
+ * four interleaved 32-bit lanes (oracle_pack_vertical); widths,
+ * descriptors, sizes and everything around the blocks as in
+ * oracle_bp_encode. */
+int64_t oracle_bpv_encode(const uint32_t *x, uint64_t n, int stride, uint32_t *out, uint64_t cap)
+{
+    return o_encode(4, x, n, stride, out, cap);
+}
+
+/* Binary-packing meta-block: the descriptor then each block's packed words
+ * (vertical: the four-lane layout). */
+static uint64_t o_bp_unit(const uint32_t *d, uint64_t nblocks, uint32_t *out, int vertical)
 {
     uint32_t desc[4] = {0, 0, 0, 0};
     uint64_t pos = 4;
@@ -297,7 +347,10 @@ static uint64_t o_bp_unit(const uint32_t *d, uint64_t nblocks, uint32_t *out)
             all |= d[j * OB + i];
         uint32_t b = oracle_bits(all);
         desc[j / 4] |= b << (8 * (j % 4));
-        oracle_pack(d + j * OB, OB, b, out + pos);
+        if (vertical)
+            oracle_pack_vertical(d + j * OB, OB, b, out + pos);
+        else
+            oracle_pack(d + j * OB, OB, b, out + pos);
         pos += (uint64_t)OB * b / 32;
     }
     memcpy(out, desc, sizeof desc);
@@ -420,6 +473,10 @@ static uint64_t o_fp_page(const uint32_t *d, uint64_t nblocks, uint32_t *out, ui
         oracle_pack(arr[k], padded, k, out + p);
         p += padded * k / 32;
     }
+    /* with 32-value padding the arrays may end inside a 16-byte group: the
+     * page is zero-padded to 4 words so that every unit starts on 16 bytes */
+    while (p % 4)
+        out[p++] = 0;
     for (int k = 0; k <= 32; k++)
         free(arr[k]);
     free(bw);
@@ -465,7 +522,7 @@ static int64_t o_encode(int codec, const uint32_t *x, uint64_t n, int stride,
             uint64_t nb = nfull - u * per;
             if (nb > per)
                 nb = per;
-            p += codec == 0   ? o_bp_unit(d + start, nb, out + p)
+            p += (codec == 0 || codec == 4) ? o_bp_unit(d + start, nb, out + p, codec == 4)
                  : codec == 2 ? o_bp32_unit(d + start, nb, out + p)
                               : o_fp_page(d + start, nb, out + p, codec == 3 ? 32 : OB);
         }
@@ -496,7 +553,7 @@ static int64_t o_encode(int codec, const uint32_t *x, uint64_t n, int stride,
 /* Decoding: the exact inverse, with every field checked against the       */
 /* stream's bounds; a bad stream returns O_ERR_CORRUPT.                     */
 
-static int o_bp_unit_decode(const uint32_t *w, uint64_t avail, uint64_t nblocks, uint32_t *d)
+static int o_bp_unit_decode(const uint32_t *w, uint64_t avail, uint64_t nblocks, uint32_t *d, int vertical)
 {
     if (avail < 4)
         return O_ERR_CORRUPT;
@@ -510,7 +567,10 @@ static int o_bp_unit_decode(const uint32_t *w, uint64_t avail, uint64_t nblocks,
         }
         if (b > 32 || pos + (uint64_t)OB * b / 32 > avail)
             return O_ERR_CORRUPT;
-        oracle_unpack(w + pos, OB, b, d + j * OB);
+        if (vertical)
+            oracle_unpack_vertical(w + pos, OB, b, d + j * OB);
+        else
+            oracle_unpack(w + pos, OB, b, d + j * OB);
         pos += (uint64_t)OB * b / 32;
     }
     if (pos != avail)
@@ -592,7 +652,7 @@ static int o_fp_page_decode(const uint32_t *w, uint64_t avail, uint64_t nblocks_
         oracle_unpack(w + p, padded, k, arr[k]);
         p += padded * k / 32;
     }
-    if (p != avail) {
+    if (o_pad4(p) != avail) {
         rc = O_ERR_CORRUPT;
         goto done;
     }
@@ -673,7 +733,7 @@ static int o_decode(int codec, const uint32_t *in, uint64_t in_words, uint32_t *
             count = nb * OB;
             if (off < dir_end || end < off || end > total)
                 return O_ERR_CORRUPT;
-            rc = codec == 0   ? o_bp_unit_decode(in + off, end - off, nb, out + start)
+            rc = (codec == 0 || codec == 4) ? o_bp_unit_decode(in + off, end - off, nb, out + start, codec == 4)
                  : codec == 2 ? o_bp32_unit_decode(in + off, end - off, nb, out + start)
                               : o_fp_page_decode(in + off, end - off, nb, out + start, codec == 3 ? 32 : OB);
         } else {
@@ -715,6 +775,11 @@ int oracle_bp32_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uin
 int oracle_fp32_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n)
 {
     return o_decode(3, in, in_words, out, n);
+}
+
+int oracle_bpv_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n)
+{
+    return o_decode(4, in, in_words, out, n);
 }
 
 /* ------------------------------------------------------------------------

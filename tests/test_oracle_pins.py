@@ -329,13 +329,15 @@ def test_appendix_a_bound_on_sorted_distinct_arrays():
 
 # ---------------------------------------------------------------- round trips
 
-_ENC = {"bp": oracle.bp_encode, "fp": oracle.fp_encode, "bp32": oracle.bp32_encode, "fp32": oracle.fp32_encode}
-_DEC = {"bp": oracle.bp_decode, "fp": oracle.fp_decode, "bp32": oracle.bp32_decode, "fp32": oracle.fp32_decode}
+_ENC = {"bp": oracle.bp_encode, "fp": oracle.fp_encode, "bp32": oracle.bp32_encode, "fp32": oracle.fp32_encode,
+        "bpv": oracle.bpv_encode}
+_DEC = {"bp": oracle.bp_decode, "fp": oracle.fp_decode, "bp32": oracle.bp32_decode, "fp32": oracle.fp32_decode,
+        "bpv": oracle.bpv_decode}
 _RC = {"bp": oracle.bp_decode_rc, "fp": oracle.fp_decode_rc, "bp32": oracle.bp32_decode_rc,
-       "fp32": oracle.fp32_decode_rc}
+       "fp32": oracle.fp32_decode_rc, "bpv": oracle.bpv_decode_rc}
 
 
-@pytest.mark.parametrize("codec", ["bp", "fp", "bp32", "fp32"])
+@pytest.mark.parametrize("codec", ["bp", "fp", "bp32", "fp32", "bpv"])
 @pytest.mark.parametrize("stride", [0, 1, 4])
 def test_roundtrip_every_small_length(codec, stride):
     enc, dec = _ENC[codec], _DEC[codec]
@@ -400,7 +402,7 @@ def test_patched_page_counts_match_blocks():
 
 # ---------------------------------------------------------------- corrupt input
 
-@pytest.mark.parametrize("codec", ["bp", "fp", "bp32", "fp32"])
+@pytest.mark.parametrize("codec", ["bp", "fp", "bp32", "fp32", "bpv"])
 def test_corrupt_streams_are_rejected(codec):
     enc, rc = _ENC[codec], _RC[codec]
     x = datagen.single_geometric(5000, seed=3)
@@ -416,7 +418,7 @@ def test_corrupt_streams_are_rejected(codec):
     assert rc(bad, 5000) == oracle.ERR_CORRUPT                 # unit offset
     unit = int(s[8])
     bad = s.copy()
-    if codec in ("bp", "bp32"):
+    if codec in ("bp", "bp32", "bpv"):
         bad[unit] = (int(bad[unit]) & ~0xFF) | 33              # width 33
     else:
         bad[unit] = 7                                          # block count
@@ -428,7 +430,7 @@ def test_max_words_bounds_worst_case():
     for n in (0, 1, 128, 2048, 65536 + 129):
         x = rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)
         for codec, enc in ((0, oracle.bp_encode), (1, oracle.fp_encode), (2, oracle.bp32_encode),
-                           (3, oracle.fp32_encode)):
+                           (3, oracle.fp32_encode), (4, oracle.bpv_encode)):
             for stride in (0, 1, 4):
                 assert enc(x, stride).size <= oracle.max_words(codec, n)
 
@@ -643,3 +645,74 @@ def test_fastpfor_32_padding_against_128(stride):
         assert -(-(xa - oa) // 4) * 4 == wa and not a[xa:oa + wa].any() and xb == ob + wb
     assert 0 < b.size - a.size <= saved
     assert np.array_equal(oracle.fp32_decode(a, x.size), x)
+
+
+# ---------------------------------------------------------------- vectorized (four-lane) layout (Section 4)
+
+def _words_of_field(i, count, b):
+    # the words that field i occupies: pack a lone all-ones field
+    v = np.zeros(count, dtype=np.uint32)
+    v[i] = (1 << b) - 1
+    w = oracle.pack_vertical(v, b)
+    return [k for k in range(w.size) if w[k]]
+
+
+def test_vertical_layout_paper_example():
+    g = _golden("vertical_layout.json")
+    b, count = g["b"], g["count"]
+    assert oracle.pack_vertical(np.zeros(count, np.uint32), b).size == 8  # two series of four words
+    lo, hi = g["whole_in_first_row"]
+    for i in range(lo, hi + 1):
+        ws = _words_of_field(i - 1, count, b)
+        assert len(ws) == 1 and ws[0] < 4 and ws[0] == (i - 1) % 4, i
+    lo, hi = g["split_between_rows"]
+    for i in range(lo, hi + 1):
+        assert _words_of_field(i - 1, count, b) == [(i - 1) % 4, 4 + (i - 1) % 4], i
+    lo, hi = g["whole_in_second_row"]
+    for i in range(lo, hi + 1):
+        assert _words_of_field(i - 1, count, b) == [4 + (i - 1) % 4], i
+    firsts = [_words_of_field(i - 1, count, b)[0] for i in g["first_four_in_different_words"]]
+    assert sorted(firsts) == [0, 1, 2, 3]
+    a, c = g["adjacent_in_one_word"]
+    wa, wc = _words_of_field(a - 1, count, b), _words_of_field(c - 1, count, b)
+    assert wa == wc
+    # Int 5 starts where Int 1 ends
+    v = np.zeros(count, np.uint32); v[c - 1] = 1
+    assert int(oracle.pack_vertical(v, b)[wa[0]]) == 1 << b
+
+
+@pytest.mark.parametrize("b", range(0, 33))
+def test_vertical_lanes_are_horizontal_packings(b):
+    # lane l (words l, l+4, l+8, ...) is the plain packing of values l, l+4, ...
+    rng = np.random.default_rng(700 + b)
+    vals = rng.integers(0, 2**32, size=128, dtype=np.uint64).astype(np.uint32)
+    w = oracle.pack_vertical(vals, b)
+    assert w.size == 4 * b
+    mask = np.uint32((1 << b) - 1) if b < 32 else np.uint32(0xFFFFFFFF)
+    for lane in range(4):
+        assert np.array_equal(w[lane::4], oracle.pack(vals[lane::4], b)), lane
+    assert np.array_equal(oracle.unpack_vertical(w, 128, b), vals & mask)
+
+
+@pytest.mark.parametrize("stride", [0, 1, 4])
+def test_vertical_stream_differs_from_bp_only_inside_blocks(stride):
+    # same header, directory, descriptors, sizes and tail; each block's
+    # words are the four-lane packing of the same deltas
+    x = datagen.single_geometric(2048 * 3 + 128 * 5 + 77, mean=300, seed=60 + stride)
+    a, h = oracle.bpv_encode(x, stride), oracle.bp_encode(x, stride)
+    assert a.size == h.size and int(a[0]) == 0x31565057 and np.array_equal(a[1:8], h[1:8])
+    d = _deltas(x, stride).astype(np.uint32)
+    for u, widths in enumerate(_bp_widths(h)):
+        off = int(h[8 + u])
+        assert np.array_equal(a[off:off + 4], h[off:off + 4])
+        at = off + 4
+        for j, b in enumerate(widths):
+            if 128 * (16 * u + j) >= x.size // 128 * 128:
+                break
+            blk = d[128 * (16 * u + j):128 * (16 * u + j + 1)]
+            assert np.array_equal(a[at:at + 4 * b], oracle.pack_vertical(blk, b))
+            assert np.array_equal(h[at:at + 4 * b], oracle.pack(blk, b))
+            at += 4 * b
+    tail = int(h[6])
+    assert np.array_equal(a[tail:], h[tail:])
+    assert np.array_equal(oracle.bpv_decode(a, x.size), x)
