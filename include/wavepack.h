@@ -38,6 +38,10 @@
  *       (field i at bits [i*b, i*b+b) of the block's words, least
  *       significant bit first). Section 4 (bit layout) and Section 6.2
  *       (SIMD-BP128: 16 blocks of 128 integers behind a 128-bit descriptor).
+ *       WP_CODEC_BPV (magic 'WPV1'): the same, with each block in the
+ *       paper's vectorized layout (Section 4): value i is field i / 4 of
+ *       32-bit lane i % 4, each lane's fields end to end from its least
+ *       significant bit, word w of lane l at word 4w + l of the block.
  *       BP32 -- 16 meta-blocks of four 32-value blocks (2048 values):
  *       each meta-block is a descriptor word whose byte j is the width b_j
  *       of its block j, then its four blocks, block j in b_j words (32
@@ -80,6 +84,7 @@ extern "C" {
 #define WP_CODEC_FP 1 /* patched pages of 2^16 integers */
 #define WP_CODEC_BP32 2 /* binary packing, 64 x 32-integer blocks per unit */
 #define WP_CODEC_FP32 3 /* patched pages, exception arrays padded to 32 values */
+#define WP_CODEC_BPV 4  /* binary packing as WP_CODEC_BP, four-lane block layout */
 
 /* Largest stream any input of n integers can produce, in 32-bit words.
  * Host only, pure. Returns 0 when n is beyond the format (streams are
@@ -104,6 +109,19 @@ int32_t bp_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t
  * recorded in the stream header (checked on the device). Allocates nothing. */
 int32_t bp_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
                   void *stream);
+
+/* SIMD-BP128 encoder with the paper's own four-lane (vectorized) block
+ * layout (Section 4 figure of 32 integers of 5 bits; Section 6.2): widths,
+ * descriptors, sizes and everything around the blocks as bp_encode, only
+ * the order of the bits inside each block differs. Arguments as bp_encode,
+ * with WP_CODEC_BPV for the capacity. */
+int32_t bp_vertical_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,
+                           uint64_t out_cap_words, uint64_t *out_words, void *stream);
+
+/* Decoder for bp_vertical_encode's streams: as bp_decode. Allocates
+ * nothing. */
+int32_t bp_vertical_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
+                           void *stream);
 
 /* BP32 encoder (Section 6.2, BP32: 32-integer blocks at b = bits of the OR
  * of their deltas, four per meta-block behind a word of widths). Arguments
@@ -193,8 +211,9 @@ int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const uint32_t *
 int32_t wp_time_next_launch(void *start_event, void *stop_event);
 
 /* Workgroup shape of the single-list decoders (set by the autotuner;
- * process-wide; one setting per codec). Binary packing (WP_CODEC_BP and
- * WP_CODEC_BP32): every wavefront decodes its own run of
+ * process-wide; WP_CODEC_BPV shares WP_CODEC_BP's setting and
+ * WP_CODEC_FP32 WP_CODEC_FP's). Binary packing (WP_CODEC_BP, _BPV and
+ * _BP32): every wavefront decodes its own run of
  * consecutive meta-blocks, streaming the run's compressed words through a
  * private LDS ring; waves: wavefronts per workgroup (1, 2, 4 or 8); vpl
  * must be 4 (each lane unpacks four integers of a block per pass); depth:

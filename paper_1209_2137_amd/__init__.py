@@ -23,10 +23,11 @@ CODEC_BP = 0
 CODEC_FP = 1
 CODEC_BP32 = 2
 CODEC_FP32 = 3
+CODEC_BPV = 4
 
 EXPORTS = (
     "bp_encode", "bp_decode", "bp32_encode", "bp32_decode", "fastpfor_encode", "fastpfor_decode",
-    "fastpfor32_encode", "fastpfor32_decode", "delta_decode_inplace",
+    "fastpfor32_encode", "fastpfor32_decode", "bp_vertical_encode", "bp_vertical_decode", "delta_decode_inplace",
     "wp_max_compressed_words", "wp_check", "wp_strerror", "wp_set_decode_tune", "wp_time_next_launch",
     "wp_batch_plan", "wp_batch_replan", "wp_batch_decode", "wp_batch_items", "wp_batch_free",
     "wp_intersect", "wp_intersect_compressed",
@@ -72,11 +73,11 @@ def lib():
         pass
     L = ctypes.CDLL(LIB_PATH)
     vp, u64, i32, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint32
-    for name in ("bp_encode", "bp32_encode", "fastpfor_encode", "fastpfor32_encode"):
+    for name in ("bp_encode", "bp32_encode", "fastpfor_encode", "fastpfor32_encode", "bp_vertical_encode"):
         f = getattr(L, name)
         f.argtypes = [vp, u64, i32, vp, u64, vp, vp]
         f.restype = i32
-    for name in ("bp_decode", "bp32_decode", "fastpfor_decode", "fastpfor32_decode"):
+    for name in ("bp_decode", "bp32_decode", "fastpfor_decode", "fastpfor32_decode", "bp_vertical_decode"):
         f = getattr(L, name)
         f.argtypes = [vp, u64, vp, u64, vp]
         f.restype = i32
@@ -194,6 +195,11 @@ def fastpfor_decode(comp, n: int, out=None, stream=None):
     return _decode(lib().fastpfor_decode, comp, n, out, stream, "fastpfor_decode")
 
 
+def bp_vertical_decode(comp, n: int, out=None, stream=None):
+    """Decodes a SIMD-BP128 stream in the four-lane block layout into out[0:n]."""
+    return _decode(lib().bp_vertical_decode, comp, n, out, stream, "bp_vertical_decode")
+
+
 def fastpfor32_decode(comp, n: int, out=None, stream=None):
     """Decodes a FastPFOR stream (exception arrays padded to 32) into out[0:n]."""
     return _decode(lib().fastpfor32_decode, comp, n, out, stream, "fastpfor32_decode")
@@ -236,10 +242,16 @@ def fastpfor32_encode(x, stride: int = 1, out=None, out_words=None, stream=None)
     return _encode(lib().fastpfor32_encode, CODEC_FP32, x, stride, out, out_words, stream, "fastpfor32_encode")
 
 
+def bp_vertical_encode(x, stride: int = 1, out=None, out_words=None, stream=None):
+    """Encodes x (device uint32) as SIMD-BP128 with the four-lane block layout."""
+    return _encode(lib().bp_vertical_encode, CODEC_BPV, x, stride, out, out_words, stream, "bp_vertical_encode")
+
+
 def encode_trimmed(x, codec: int = CODEC_BP, stride: int = 1, stream=None):
     """Encodes and returns a tensor of exactly the stream's length
     (synchronises the stream to read the length)."""
-    enc = {CODEC_BP: bp_encode, CODEC_FP: fastpfor_encode, CODEC_BP32: bp32_encode, CODEC_FP32: fastpfor32_encode}[codec]
+    enc = {CODEC_BP: bp_encode, CODEC_FP: fastpfor_encode, CODEC_BP32: bp32_encode, CODEC_FP32: fastpfor32_encode,
+           CODEC_BPV: bp_vertical_encode}[codec]
     buf, words = enc(x, stride, stream=stream)
     check(stream)
     return buf[: int(words.item())].clone()

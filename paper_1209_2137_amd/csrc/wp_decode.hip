@@ -6,7 +6,8 @@
 // Binary packing: every wavefront decodes its own contiguous run of
 // meta-blocks (bp_wave_run); a workgroup is just WAVES such runs side by
 // side. The workgroup after the last run decodes the Variable Byte tail.
-// BP32 streams (32-integer blocks) take the same kernel in its B32 mode.
+// BP32 streams (32-integer blocks) take the same kernel in its B32 mode,
+// SIMD-BP128 streams with the four-lane block layout in its V mode.
 //
 // Patched pages: one workgroup per page (see fp_page); FastPFOR streams
 // (exception arrays padded to 32 values) take the same kernel in its P32
@@ -27,14 +28,14 @@ union BpKernelLds {
 
 // Wavefront w of workgroup g decodes run g * WAVES + w: units
 // [run * upw, run * upw + upw) of one list.
-template <int WAVES, int DEPTH, bool B32 = false>
+template <int WAVES, int DEPTH, bool B32 = false, bool V = false>
 __global__ __launch_bounds__(64 * WAVES) void k_bp_decode(const uint32_t *__restrict__ in, uint64_t in_words,
                                                           uint32_t *__restrict__ out, uint64_t n,
                                                           int *__restrict__ err, uint32_t upw)
 {
     __shared__ BpKernelLds<WAVES, DEPTH, B32> L;
     ListHdr H;
-    if (!check_header(in, in_words, n, B32 ? kMagicBP32 : kMagicBP, kBpBlocks, H)) {
+    if (!check_header(in, in_words, n, B32 ? kMagicBP32 : V ? kMagicBPV : kMagicBP, kBpBlocks, H)) {
         if (blockIdx.x == 0 && threadIdx.x == 0)
             *err = kErrCorrupt;
         return;
@@ -53,9 +54,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_bp_decode(const uint32_t *__rest
         return;
     const uint64_t ua = r * upw;
     const uint32_t cnt = (uint32_t)((H.units - ua) < upw ? (H.units - ua) : upw);
-    const bool ok = H.S == 1   ? bp_wave_run<DEPTH, 1, B32>(in, H, ua, cnt, out, L.w[wave])
-                    : H.S == 4 ? bp_wave_run<DEPTH, 4, B32>(in, H, ua, cnt, out, L.w[wave])
-                               : bp_wave_run<DEPTH, 0, B32>(in, H, ua, cnt, out, L.w[wave]);
+    const bool ok = H.S == 1   ? bp_wave_run<DEPTH, 1, B32, V>(in, H, ua, cnt, out, L.w[wave])
+                    : H.S == 4 ? bp_wave_run<DEPTH, 4, B32, V>(in, H, ua, cnt, out, L.w[wave])
+                               : bp_wave_run<DEPTH, 0, B32, V>(in, H, ua, cnt, out, L.w[wave]);
     if (!ok && lane_id() == 0)
         *err = kErrCorrupt;
 }
@@ -115,7 +116,8 @@ LaunchEvents take_launch_events()
     t_events = LaunchEvents{};
     return e;
 }
-// per tuning slot: SIMD-BP128, patched pages (both paddings), BP32
+// per tuning slot: SIMD-BP128 (both block layouts), patched pages (both
+// paddings), BP32
 static Tune g_tune[3] = {{4, 4, kBpRunsPerCu, 2}, {4, 4, 0, 0}, {4, 4, kBpRunsPerCu, 2}};
 
 static int tune_slot(int codec)
@@ -158,17 +160,17 @@ Tune decode_tune(int codec)
 
 static bool valid_tune(int codec, int waves, int vpl)
 {
-    if (codec == WP_CODEC_BP || codec == WP_CODEC_BP32)
+    if (codec == WP_CODEC_BP || codec == WP_CODEC_BP32 || codec == WP_CODEC_BPV)
         return (waves == 1 || waves == 2 || waves == 4 || waves == 8) && vpl == 4;
     return (waves == 2 || waves == 4 || waves == 8) && vpl == 4;
 }
 
-template <int WAVES, int DEPTH, bool B32 = false>
+template <int WAVES, int DEPTH, bool B32 = false, bool V = false>
 static void launch_bp(uint64_t grid, hipStream_t st, const uint32_t *in, uint64_t in_words, uint32_t *out,
                       uint64_t n, int *err, uint32_t upw)
 {
-    launch_timed(k_bp_decode<WAVES, DEPTH, B32>, dim3((uint32_t)grid), dim3(64 * WAVES), st, in, in_words, out, n,
-                 err, upw);
+    launch_timed(k_bp_decode<WAVES, DEPTH, B32, V>, dim3((uint32_t)grid), dim3(64 * WAVES), st, in, in_words, out,
+                 n, err, upw);
 }
 
 template <int WAVES>
@@ -214,10 +216,11 @@ static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, u
         if (grid > 0x7FFFFFFFull)
             return WP_ERR_INVALID_ARG;
         const uint32_t u32 = (uint32_t)upw;
-        const bool b32 = codec == WP_CODEC_BP32;
+        const bool b32 = codec == WP_CODEC_BP32, vert = codec == WP_CODEC_BPV;
 #define WP_BP_D(W, D)                                                                                           \
-    (b32 ? launch_bp<W, D, true>(grid, st, in, in_words, out, n, ds->err, u32)                                  \
-         : launch_bp<W, D>(grid, st, in, in_words, out, n, ds->err, u32))
+    (b32    ? launch_bp<W, D, true>(grid, st, in, in_words, out, n, ds->err, u32)                               \
+     : vert ? launch_bp<W, D, false, true>(grid, st, in, in_words, out, n, ds->err, u32)                        \
+            : launch_bp<W, D>(grid, st, in, in_words, out, n, ds->err, u32))
 #define WP_BP(W) (t.depth >= 4 ? WP_BP_D(W, 4) : t.depth == 3 ? WP_BP_D(W, 3) : WP_BP_D(W, 2))
         if (t.waves == 1)
             WP_BP(1);
@@ -271,9 +274,16 @@ extern "C" int32_t fastpfor32_decode(const uint32_t *in, uint64_t in_words, uint
     return decode_common(WP_CODEC_FP32, in, in_words, out, n, stream);
 }
 
+extern "C" int32_t bp_vertical_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
+                                      void *stream)
+{
+    return decode_common(WP_CODEC_BPV, in, in_words, out, n, stream);
+}
+
 extern "C" int32_t wp_set_decode_tune(int32_t codec, int32_t waves, int32_t vpl, int32_t depth, int32_t wg_per_cu)
 {
-    if ((codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32 && codec != WP_CODEC_FP32) ||
+    if ((codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32 && codec != WP_CODEC_FP32 &&
+         codec != WP_CODEC_BPV) ||
         !valid_tune(codec, waves, vpl) || wg_per_cu < 0 ||
         wg_per_cu > 1024 || depth < 0 || depth == 1 || depth > 4)
         return WP_ERR_INVALID_ARG;
@@ -324,13 +334,14 @@ extern "C" const char *wp_strerror(int32_t code)
 
 extern "C" uint64_t wp_max_compressed_words(int32_t codec, uint64_t n)
 {
-    if (codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32 && codec != WP_CODEC_FP32)
+    if (codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32 && codec != WP_CODEC_FP32 &&
+        codec != WP_CODEC_BPV)
         return 0;
     const uint64_t nfull = n / kBlock, tail = n % kBlock;
     const uint64_t per = (codec == WP_CODEC_FP || codec == WP_CODEC_FP32) ? kFpBlocks : kBpBlocks;
     const uint64_t units = (nfull + per - 1) / per;
     uint64_t w = kHdrWords + ((5 * (units + 1) + 3) & ~3ull);
-    if (codec == WP_CODEC_BP) {
+    if (codec == WP_CODEC_BP || codec == WP_CODEC_BPV) {
         w += units * 4 + nfull * 128;  // descriptor + every block at 32 bits
     } else if (codec == WP_CODEC_BP32) {
         // a descriptor word per meta-block, every block at 32 bits, at most

@@ -34,6 +34,7 @@ constexpr uint32_t kMagicFP = 0x31465057u;  // "WPF1"
 constexpr uint32_t kMagicBP32 = 0x32335057u;  // "WP32"
 constexpr uint32_t kB32 = 32;                 // BP32 block length (Section 6.2)
 constexpr uint32_t kMagicFP32 = 0x33465057u;  // "WPF3"
+constexpr uint32_t kMagicBPV = 0x31565057u;   // "WPV1"
 
 // Words of a page's exception array of `cnt` values at k bits, padded to a
 // multiple of 128 values (SIMD-FastPFOR) or of 32 (FastPFOR, P32); either
@@ -972,10 +973,17 @@ __device__ __forceinline__ bool byte_over32(uint32_t d)
 // Returns the uniform validity of the run: on a bad run the wavefront
 // stops, its output is unspecified but every store stays inside the run's
 // output range.
-template <int DEPTH, uint32_t S, bool B32 = false>
+//
+// V (the four-lane vectorized block layout of Section 4, SIMD-BP128
+// descriptors and sizes): lane q of a block takes integers 4q..4q+3, field
+// q of each of the four 32-bit lanes, at the same bit offset q*b in each:
+// two 16-byte LDS reads (the row holding the field start and the next
+// row) and four funnel shifts, and again no transposition.
+template <int DEPTH, uint32_t S, bool B32 = false, bool V = false>
 __device__ __forceinline__ bool bp_wave_run(const uint32_t *__restrict__ in, const ListHdr &H, uint64_t ua, uint32_t cnt,
                             uint32_t *__restrict__ out, WaveLds<DEPTH, B32> &L)
 {
+    static_assert(!(B32 && V), "one block layout");
     using G = WaveGeo<DEPTH, B32>;
     constexpr uint32_t RB = G::RB, CW = G::CW;
     const uint32_t lane = lane_id();
@@ -1134,21 +1142,39 @@ __device__ __forceinline__ bool bp_wave_run(const uint32_t *__restrict__ in, con
             const uint32_t b = hi ? bB : bA;
             const uint32_t st = hi ? ps + 4u * bA : ps;
             const uint32_t qb = q * b;
-            const uint32_t w0 = (st + (qb >> 5)) & (RB - 1);
             const uint32_t mask = width_mask(b);
-            uint32_t v[4];
+            uint32_t x[4];
+            if constexpr (V) {
+                // row (qb >> 5) of the block holds the start of field q of
+                // every lane; rows are 16-byte aligned in the ring (blocks
+                // are 4b words from a 16-byte aligned run), and the mirror
+                // after the ring end covers the second row
+                const uint32_t w0 = (st + 4u * (qb >> 5)) & (RB - 1);
+                const uint4 r0 = *reinterpret_cast<const uint4 *>(&L.ring[w0]);
+                const uint4 r1 = *reinterpret_cast<const uint4 *>(&L.ring[w0 + 4]);
+                x[0] = __builtin_amdgcn_alignbit(r1.x, r0.x, qb) & mask;
+                x[1] = __builtin_amdgcn_alignbit(r1.y, r0.y, qb) & mask;
+                x[2] = __builtin_amdgcn_alignbit(r1.z, r0.z, qb) & mask;
+                x[3] = __builtin_amdgcn_alignbit(r1.w, r0.w, qb) & mask;
+            } else {
+                const uint32_t w0 = (st + (qb >> 5)) & (RB - 1);
+                uint32_t v[4];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const uint32_t w = w0 + m * b;
-                v[m] = __builtin_amdgcn_alignbit(L.ring[w + 1], L.ring[w], qb) & mask;
+                for (int m = 0; m < 4; ++m) {
+                    const uint32_t w = w0 + m * b;
+                    v[m] = __builtin_amdgcn_alignbit(L.ring[w + 1], L.ring[w], qb) & mask;
+                }
+                wave_lds_order();
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    xw[32 * m] = v[m];
+                wave_lds_order();
+                const uint4 t = *xr;
+                x[0] = t.x;
+                x[1] = t.y;
+                x[2] = t.z;
+                x[3] = t.w;
             }
-            wave_lds_order();
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-                xw[32 * m] = v[m];
-            wave_lds_order();
-            const uint4 t = *xr;
-            uint32_t x[4] = {t.x, t.y, t.z, t.w};
             scan_wave4<S>(x, carry);
             buf_store_u4(ro, lane * 16u, sbase + p * (G::PASS * 4u), make_uint4(x[0], x[1], x[2], x[3]));
             ps = pe;

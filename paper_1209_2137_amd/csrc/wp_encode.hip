@@ -42,6 +42,19 @@ __device__ __forceinline__ void or_field(uint32_t *w, uint32_t i, uint32_t b, ui
         atomicOr(&w[(pos >> 5) + 1], v >> (32u - s));
 }
 
+// The same for the four-lane layout of Section 4: value i is field i / 4 of
+// 32-bit lane i % 4, the lanes' words interleaved (word w of lane l at 4w + l)
+__device__ __forceinline__ void or_field_vertical(uint32_t *w, uint32_t i, uint32_t b, uint32_t v)
+{
+    if (b == 0)
+        return;
+    const uint32_t lane = i & 3u, pos = (i >> 2) * b, s = pos & 31u;
+    v &= width_mask(b);
+    atomicOr(&w[4 * (pos >> 5) + lane], v << s);
+    if (s + b > 32u)
+        atomicOr(&w[4 * ((pos >> 5) + 1) + lane], v >> (32u - s));
+}
+
 // directory entry: offset at word 8 + entry, bases after all ndir offsets;
 // base_s = x[start - S + s], 0 before the array start
 __device__ __forceinline__ void write_dir_entry(uint32_t *out, uint64_t entry, uint64_t ndir, uint32_t S,
@@ -139,6 +152,7 @@ __global__ __launch_bounds__(256) void k_bp_analyze(const uint32_t *__restrict__
 // The meta-block is assembled in LDS (descriptor, then the blocks' words,
 // fields OR-ed in by LDS atomics) and written with 16-byte stores: unit
 // offsets are multiples of 4 words.
+template <bool V>
 __global__ __launch_bounds__(256) void k_bp_pack(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
                                                  const uint8_t *__restrict__ widths,
                                                  const uint32_t *__restrict__ incl, uint32_t dir_end,
@@ -169,8 +183,12 @@ __global__ __launch_bounds__(256) void k_bp_pack(const uint32_t *__restrict__ x,
     if (b) {
         uint32_t *const w = s_u + s_off[j];
 #pragma unroll
-        for (int r = 0; r < 8; ++r)
-            or_field(w, 8 * (tid & 15u) + r, b, d[r]);
+        for (int r = 0; r < 8; ++r) {
+            if constexpr (V)
+                or_field_vertical(w, 8 * (tid & 15u) + r, b, d[r]);
+            else
+                or_field(w, 8 * (tid & 15u) + r, b, d[r]);
+        }
     }
     const uint32_t off = dir_end + incl[u] - size;
     write_dir_entry(out, u, dir_entries(n, kBpBlocks), S, off, x, u * kBpUnitInts);
@@ -569,6 +587,7 @@ __global__ __launch_bounds__(128) void k_finish(const uint32_t *__restrict__ x, 
     const uint32_t total = tail_off + (tail_bytes + 3) / 4;
     if (tid == 0) {
         out[0] = codec == WP_CODEC_BP     ? kMagicBP
+                 : codec == WP_CODEC_BPV  ? kMagicBPV
                  : codec == WP_CODEC_BP32 ? kMagicBP32
                  : codec == WP_CODEC_FP32 ? kMagicFP32
                                           : kMagicFP;
@@ -610,7 +629,9 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
     const uint64_t sizes_off = status_words * 8;
     const uint64_t meta_off = sizes_off + ((units * 4 + 255) & ~255ull);
     const uint64_t nblk = units * per;
-    const uint64_t meta_len = codec == WP_CODEC_BP ? nblk : codec == WP_CODEC_BP32 ? 4 * nblk : 3 * nblk;
+    const uint64_t meta_len = (codec == WP_CODEC_BP || codec == WP_CODEC_BPV) ? nblk
+                              : codec == WP_CODEC_BP32                      ? 4 * nblk
+                                                                            : 3 * nblk;
     char *scr = static_cast<char *>(stream_scratch(st, meta_off + meta_len + 256));
     if (scr == nullptr)
         return WP_ERR_HIP;
@@ -619,7 +640,7 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
     uint8_t *meta = reinterpret_cast<uint8_t *>(scr + meta_off);
     (void)hipGetLastError();
     if (units) {
-        if (codec == WP_CODEC_BP)
+        if (codec == WP_CODEC_BP || codec == WP_CODEC_BPV)
             hipLaunchKernelGGL(k_bp_analyze, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride, meta,
                                sizes);
         else if (codec == WP_CODEC_BP32)
@@ -634,8 +655,11 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
         if (launch_inclusive_scan(sizes, units, status, st) != WP_OK)
             return WP_ERR_HIP;
         if (codec == WP_CODEC_BP)
-            hipLaunchKernelGGL(k_bp_pack, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride, meta,
-                               sizes, dir_end, out);
+            hipLaunchKernelGGL(k_bp_pack<false>, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride,
+                               meta, sizes, dir_end, out);
+        else if (codec == WP_CODEC_BPV)
+            hipLaunchKernelGGL(k_bp_pack<true>, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride,
+                               meta, sizes, dir_end, out);
         else if (codec == WP_CODEC_BP32)
             hipLaunchKernelGGL(k_bp32_pack, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride, meta,
                                sizes, dir_end, out);
@@ -659,6 +683,12 @@ extern "C" int32_t bp_encode(const uint32_t *in, uint64_t n, int32_t delta_strid
                              uint64_t out_cap_words, uint64_t *out_words, void *stream)
 {
     return encode_common(WP_CODEC_BP, in, n, delta_stride, out, out_cap_words, out_words, stream);
+}
+
+extern "C" int32_t bp_vertical_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,
+                                      uint64_t out_cap_words, uint64_t *out_words, void *stream)
+{
+    return encode_common(WP_CODEC_BPV, in, n, delta_stride, out, out_cap_words, out_words, stream);
 }
 
 extern "C" int32_t bp32_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,

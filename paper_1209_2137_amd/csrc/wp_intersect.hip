@@ -154,6 +154,7 @@ __device__ __forceinline__ bool dir_view(const uint32_t *in, uint64_t in_words, 
     D.in = in;
     D.per = (codec == WP_CODEC_FP || codec == WP_CODEC_FP32) ? kFpBlocks : kBpBlocks;
     const uint32_t magic = codec == WP_CODEC_BP     ? kMagicBP
+                           : codec == WP_CODEC_BPV  ? kMagicBPV
                            : codec == WP_CODEC_BP32 ? kMagicBP32
                            : codec == WP_CODEC_FP32 ? kMagicFP32
                                                     : kMagicFP;
@@ -189,11 +190,11 @@ __global__ __launch_bounds__(256) void k_isect_touch(const uint32_t *__restrict_
 // Decodes the flagged entries of a binary-packing (SIMD-BP128 or BP32)
 // stream into out (one wavefront per unit; the tail entry by a wavefront of
 // its own).
-template <uint32_t S, bool B32>
+template <uint32_t S, bool B32, bool V>
 __device__ __forceinline__ bool bp_unit(const uint32_t *in, const ListHdr &H, uint64_t u, uint32_t *out,
                                         WaveLds<2, B32> &L)
 {
-    return bp_wave_run<2, S, B32>(in, H, u, 1, out, L);
+    return bp_wave_run<2, S, B32, V>(in, H, u, 1, out, L);
 }
 
 template <bool B32>
@@ -202,14 +203,14 @@ union IsectWaveLds {
     TailLds<1> tail;
 };
 
-template <bool B32>
+template <bool B32, bool V>
 __global__ __launch_bounds__(256) void k_isect_decode_bp(const uint32_t *__restrict__ in, uint64_t in_words,
                                                          uint64_t n, const uint8_t *__restrict__ flags,
                                                          uint32_t *__restrict__ out, int *__restrict__ err)
 {
     __shared__ IsectWaveLds<B32> L[4];
     ListHdr H;
-    if (!check_header(in, in_words, n, B32 ? kMagicBP32 : kMagicBP, kBpBlocks, H))
+    if (!check_header(in, in_words, n, B32 ? kMagicBP32 : V ? kMagicBPV : kMagicBP, kBpBlocks, H))
         return;  // reported by k_isect_touch
     const uint32_t wave = uniform(threadIdx.x >> 6);
     const uint64_t e = (uint64_t)blockIdx.x * 4 + wave;
@@ -217,9 +218,9 @@ __global__ __launch_bounds__(256) void k_isect_decode_bp(const uint32_t *__restr
         return;
     bool ok;
     if (e < H.units)
-        ok = H.S == 1   ? bp_unit<1, B32>(in, H, e, out, L[wave].r)
-             : H.S == 4 ? bp_unit<4, B32>(in, H, e, out, L[wave].r)
-                        : bp_unit<0, B32>(in, H, e, out, L[wave].r);
+        ok = H.S == 1   ? bp_unit<1, B32, V>(in, H, e, out, L[wave].r)
+             : H.S == 4 ? bp_unit<4, B32, V>(in, H, e, out, L[wave].r)
+                        : bp_unit<0, B32, V>(in, H, e, out, L[wave].r);
     else
         ok = decode_tail_entry<1, false>(in, H, out, L[wave].tail);
     if (!ok && lane_id() == 0)
@@ -382,7 +383,8 @@ extern "C" int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const
     if (out_count == nullptr || (na > 0 && (a == nullptr || out == nullptr)) || b_comp == nullptr ||
         b_words < kHdrWords || (nb > 0 && b_work == nullptr) || (reinterpret_cast<uintptr_t>(out_count) & 7u) ||
         na > 0xFFFFFFFFull ||
-        (codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32 && codec != WP_CODEC_FP32) ||
+        (codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32 && codec != WP_CODEC_FP32 &&
+         codec != WP_CODEC_BPV) ||
         !aligned16(b_comp) ||
         !aligned16(b_work) || nb > 0xFFFFFFFFull * 32ull)
         return WP_ERR_INVALID_ARG;
@@ -405,11 +407,14 @@ extern "C" int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const
     hipLaunchKernelGGL(k_isect_touch, dim3((uint32_t)((nent + 255) / 256)), dim3(256), 0, st, a, na, b_comp,
                        b_words, nb, codec, S.touched, ds->err);
     if (codec == WP_CODEC_BP)
-        hipLaunchKernelGGL(k_isect_decode_bp<false>, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, b_comp,
-                           b_words, nb, S.touched, b_work, ds->err);
+        hipLaunchKernelGGL((k_isect_decode_bp<false, false>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
+                           b_comp, b_words, nb, S.touched, b_work, ds->err);
+    else if (codec == WP_CODEC_BPV)
+        hipLaunchKernelGGL((k_isect_decode_bp<false, true>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
+                           b_comp, b_words, nb, S.touched, b_work, ds->err);
     else if (codec == WP_CODEC_BP32)
-        hipLaunchKernelGGL(k_isect_decode_bp<true>, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, b_comp,
-                           b_words, nb, S.touched, b_work, ds->err);
+        hipLaunchKernelGGL((k_isect_decode_bp<true, false>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
+                           b_comp, b_words, nb, S.touched, b_work, ds->err);
     else if (codec == WP_CODEC_FP32)
         hipLaunchKernelGGL(k_isect_decode_fp<true>, dim3((uint32_t)nent), dim3(256), 0, st, b_comp, b_words, nb,
                            S.touched, b_work, ds->err);

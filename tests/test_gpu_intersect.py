@@ -78,7 +78,7 @@ def test_intersect_decoded_posting_lists():
     assert np.array_equal(got.cpu().numpy().view(np.uint32), want)
 
 
-@pytest.mark.parametrize("codec", [wp.CODEC_BP, wp.CODEC_FP, wp.CODEC_BP32, wp.CODEC_FP32])
+@pytest.mark.parametrize("codec", [wp.CODEC_BP, wp.CODEC_FP, wp.CODEC_BP32, wp.CODEC_FP32, wp.CODEC_BPV])
 @pytest.mark.parametrize("stride", [0, 1, 4])
 def test_intersect_compressed_matches_oracle(codec, stride):
     # the long list stays compressed: only the units the short list can
@@ -116,7 +116,7 @@ def test_intersect_compressed_decodes_only_touched_units():
     assert np.all(w[untouched] == 0xFFFFFFFF)
 
 
-@pytest.mark.parametrize("codec", [wp.CODEC_BP, wp.CODEC_FP, wp.CODEC_BP32, wp.CODEC_FP32])
+@pytest.mark.parametrize("codec", [wp.CODEC_BP, wp.CODEC_FP, wp.CODEC_BP32, wp.CODEC_FP32, wp.CODEC_BPV])
 def test_intersect_compressed_corrupt_and_empty(codec):
     b = np.arange(3, 3 * 5000, 3, dtype=np.uint32)
     comp = wp.encode_trimmed(dev(b), codec, 1)
