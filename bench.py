@@ -122,7 +122,7 @@ def bench_single(wp, x_np, codec, stride, steps, warmup, name, comp=None, n=None
     comps = replicas(comp, comp.numel() * 4)
     outs = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(2)]
     dec = {wp.CODEC_BP: wp.bp_decode, wp.CODEC_FP: wp.fastpfor_decode, wp.CODEC_BP32: wp.bp32_decode,
-           wp.CODEC_FP32: wp.fastpfor32_decode}[codec]
+           wp.CODEC_FP32: wp.fastpfor32_decode, wp.CODEC_BPV: wp.bp_vertical_decode}[codec]
     stream = torch.cuda.current_stream()
     dec(comps[0], n, outs[0])
     wp.check()
@@ -136,7 +136,8 @@ def bench_single(wp, x_np, codec, stride, steps, warmup, name, comp=None, n=None
     alg = comp_bytes + 4 * n
     return {
         "name": name, "n": n,
-        "codec": {wp.CODEC_BP: "bp", wp.CODEC_FP: "fp", wp.CODEC_BP32: "bp32", wp.CODEC_FP32: "fp32"}[codec],
+        "codec": {wp.CODEC_BP: "bp", wp.CODEC_FP: "fp", wp.CODEC_BP32: "bp32", wp.CODEC_FP32: "fp32",
+                  wp.CODEC_BPV: "bpv"}[codec],
         "stride": stride,
         "bits_per_int": comp_bytes * 8 / n, "ms_per_step": wall, "kernel_ms": ev,
         "gints_per_s": n / (wall * 1e-3) / 1e9, "kernel_gints_per_s": n / (ev * 1e-3) / 1e9,
@@ -152,7 +153,8 @@ def bench_encode(wp, x_np, codec, stride, steps, warmup, name):
     xd = to_dev(x_np)
     n = x_np.size
     xs = replicas(xd, n * 4)
-    enc = {wp.CODEC_BP: wp.bp_encode, wp.CODEC_FP: wp.fastpfor_encode, wp.CODEC_BP32: wp.bp32_encode}[codec]
+    enc = {wp.CODEC_BP: wp.bp_encode, wp.CODEC_FP: wp.fastpfor_encode, wp.CODEC_BP32: wp.bp32_encode,
+           wp.CODEC_FP32: wp.fastpfor32_encode, wp.CODEC_BPV: wp.bp_vertical_encode}[codec]
     buf, words = enc(xd, stride)
     wp.check()
     comp_words = int(words.item())
@@ -531,6 +533,10 @@ def main():
                                                        args.steps, args.warmup, "fastpfor_encode patched 2^28")
         extra["bp32_cluster_2e26"] = bench_single(wp, x, wp.CODEC_BP32, 1, args.steps, args.warmup,
                                                   "bp32 cluster 2^26")
+        extra["bpv_cluster_2e26"] = bench_single(wp, x, wp.CODEC_BPV, 1, args.steps, args.warmup,
+                                                 "simd-bp128 four-lane layout cluster 2^26")
+        extra["bpv_cluster_2e26_stride4"] = bench_single(wp, x, wp.CODEC_BPV, 4, args.steps, args.warmup,
+                                                         "simd-bp128 four-lane layout, stride-4 deltas, cluster 2^26")
         extra["bp32_encode_cluster_2e26"] = bench_encode(wp, x, wp.CODEC_BP32, 1, args.steps, args.warmup,
                                                          "bp32_encode cluster 2^26")
         print("# encoders done", file=sys.stderr, flush=True)
