@@ -398,11 +398,16 @@ def prepare_inputs(d):
         return 1
     wp.lib()
     os.makedirs(d, exist_ok=True)
-    for name, x, codec in (("bp_cluster_2e26", datagen.cluster_sorted(1 << 26, seed=2), wp.CODEC_BP),
-                           ("fp_patched_2e28", datagen.patched_gaps(1 << 28, seed=4), wp.CODEC_FP)):
+    cluster = datagen.cluster_sorted(1 << 26, seed=2)
+    patched = datagen.patched_gaps(1 << 28, seed=4)
+    for name, x, codec in (("bp_cluster_2e26", cluster, wp.CODEC_BP), ("fp_patched_2e28", patched, wp.CODEC_FP),
+                           ("bp32_cluster_2e26", cluster, wp.CODEC_BP32),
+                           ("bpv_cluster_2e26", cluster, wp.CODEC_BPV),
+                           ("fp32_patched_2e28", patched, wp.CODEC_FP32)):
         comp = wp.encode_trimmed(to_dev(x), codec, 1)
         np.save(os.path.join(d, name + ".npy"), comp.cpu().numpy())
         np.save(os.path.join(d, name + ".n.npy"), np.array([x.size], dtype=np.int64))
+        del comp
     packed, rows = posting_pool(False).streams()
     np.save(os.path.join(d, "pool_words.npy"), packed)
     np.save(os.path.join(d, "pool_rows.npy"), rows)
@@ -421,6 +426,31 @@ def profile_batch(wp, steps, pool):
     wp.check()
     plan.free()
     return {"ms": ev, "alg_bytes": pool.comp_bytes + 4 * pool.total_n, "n": pool.total_n}
+
+
+def profile_variants(steps, inputs):
+    """For rocprofv3: the variant codecs' decoders (BP32 and the four-lane
+    SIMD-BP128 layout on the 2^26 cluster list, FastPFOR with 32-value
+    padding on the 2^28 patched list) `steps` times each, from the streams
+    that --prepare-inputs saved."""
+    import numpy as np
+    import torch
+    import paper_1209_2137_amd as wp
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    wp.lib()
+    res = {}
+    for name, codec in (("bp32_cluster_2e26", wp.CODEC_BP32), ("bpv_cluster_2e26", wp.CODEC_BPV),
+                        ("fp32_patched_2e28", wp.CODEC_FP32)):
+        comp = torch.from_numpy(np.load(os.path.join(inputs, name + ".npy"))).to("cuda")
+        n = int(np.load(os.path.join(inputs, name + ".n.npy"))[0])
+        r = bench_single(wp, None, codec, 1, steps, 2, name, comp=comp, n=n)
+        res[name] = {"kernel_ms": r["kernel_ms"], "alg_bytes": r["alg_bytes"], "bits_per_int": r["bits_per_int"]}
+        del comp
+        torch.cuda.synchronize()
+    print(json.dumps(res))
+    return 0
 
 
 def profile_run(steps, inputs=None):
@@ -483,7 +513,10 @@ def main():
                     help="for rocprofv3: the headline decode, the 2^28 patched decode, the 2^28 "
                          "in-place delta decode and the batched posting-list decode `--steps` times each, "
                          "then a 1 GiB device copy (the counter calibration kernel) `--steps` times")
-    ap.add_argument("--inputs", metavar="DIR", help="with --profile-run: load the streams saved by --prepare-inputs")
+    ap.add_argument("--profile-variants", action="store_true",
+                    help="for rocprofv3: the BP32, four-lane SIMD-BP128 and FastPFOR-32 decoders (needs --inputs)")
+    ap.add_argument("--inputs", metavar="DIR",
+                    help="with --profile-run / --profile-variants: load the streams saved by --prepare-inputs")
     ap.add_argument("--prepare-inputs", metavar="DIR",
                     help="encode the profiled workloads and save their streams in DIR (run it without the profiler)")
     args = ap.parse_args()
@@ -494,6 +527,11 @@ def main():
         return prepare_inputs(args.prepare_inputs)
     if args.profile_run:
         return profile_run(args.steps, args.inputs)
+    if args.profile_variants:
+        if not args.inputs:
+            print("--profile-variants needs --inputs DIR (from --prepare-inputs)", file=sys.stderr)
+            return 2
+        return profile_variants(args.steps, args.inputs)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (this build decodes on a "
               "single MI355X; lists and units shard across GPUs without any exchange, see the design notes)",
