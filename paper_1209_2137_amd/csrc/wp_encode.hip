@@ -302,14 +302,68 @@ __global__ __launch_bounds__(256) void k_bp32_pack(const uint32_t *__restrict__ 
 // the inclusive prefix of the bins up to b), its cost, and one minimum over
 // the wavefront of (cost << 6 | 63 - b) picks the width.
 
+// Deltas of a page's blocks for a wavefront that takes one block at a time,
+// lane l integers 2l and 2l+1, with D blocks' loads in flight (registers
+// indexed by compile-time slot only). The predecessors come from the
+// neighbouring lanes (one lane back for stride 1, two for stride 4), from
+// memory for the first lanes, 0 before the array start.
+template <int D>
+struct DeltaRing {
+    uint32_t ra[D], rb[D], rp0[D], rp1[D];
+
+    __device__ __forceinline__ void issue(int d, const uint32_t *__restrict__ x, uint64_t i0, bool live, uint32_t S,
+                                          uint32_t lane)
+    {
+        ra[d] = rb[d] = rp0[d] = rp1[d] = 0;
+        if (live) {
+            ra[d] = x[i0];
+            rb[d] = x[i0 + 1];
+            if (S == 1 && lane == 0 && i0 >= 1)
+                rp1[d] = x[i0 - 1];
+            if (S == 4 && lane < 2) {
+                rp0[d] = i0 >= 4 ? x[i0 - 4] : 0u;
+                rp1[d] = i0 >= 3 ? x[i0 - 3] : 0u;
+            }
+        }
+    }
+
+    __device__ __forceinline__ void take(int d, uint32_t S, uint32_t lane, uint32_t &d0, uint32_t &d1) const
+    {
+        if (S == 0) {
+            d0 = ra[d];
+            d1 = rb[d];
+        } else if (S == 1) {
+            uint32_t prev = (uint32_t)__shfl_up((int)rb[d], 1, 64);
+            if (lane == 0)
+                prev = rp1[d];
+            d0 = ra[d] - prev;
+            d1 = rb[d] - ra[d];
+        } else {
+            uint32_t p0 = (uint32_t)__shfl_up((int)ra[d], 2, 64), p1 = (uint32_t)__shfl_up((int)rb[d], 2, 64);
+            if (lane < 2) {
+                p0 = rp0[d];
+                p1 = rp1[d];
+            }
+            d0 = ra[d] - p0;
+            d1 = rb[d] - p1;
+        }
+    }
+};
+constexpr int kEncDepth = 4;  // blocks in flight per wavefront in the patched encoder
+
+// Minimum over the wavefront, uniform: a DPP running minimum (rows, then
+// across rows) read from the last lane; no LDS traffic.
 __device__ __forceinline__ uint32_t wave_min(uint32_t v)
 {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const uint32_t o = (uint32_t)__shfl_xor((int)v, m, 64);
-        v = o < v ? o : v;
-    }
-    return v;
+    constexpr uint32_t kId = 0xffffffffu;  // identity of min for lanes without a source
+    auto step = [&](uint32_t o) __attribute__((always_inline)) { v = o < v ? o : v; };
+    step(__builtin_amdgcn_update_dpp(kId, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    step(__builtin_amdgcn_update_dpp(kId, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    step(__builtin_amdgcn_update_dpp(kId, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    step(__builtin_amdgcn_update_dpp(kId, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    step(__builtin_amdgcn_update_dpp(kId, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    step(__builtin_amdgcn_update_dpp(kId, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return wave_read(v, 63);
 }
 
 template <bool P32>
@@ -333,21 +387,29 @@ __global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__
         s_pw = 0, s_pc = 0;
     __syncthreads();
     uint32_t *const h = s_hist[wave];
-    // deltas of the wavefront's next block, loaded one block ahead
-    auto load_d = [&](uint32_t t, uint32_t &d0, uint32_t &d1) __attribute__((always_inline)) {
-        d0 = d1 = 0;
-        if (t < nb) {
-            const uint64_t i0 = (p * kFpBlocks + t) * kBlock + 2 * lane;
-            d0 = delta_at(x, i0, S);
-            d1 = delta_at(x, i0 + 1, S);
-        }
+    // per-wavefront sums, added to the page's once at the end: packed
+    // words, exceptions, and (lane k) exceptions of width difference k
+    uint32_t acc_pw = 0, acc_pc = 0, acc_k = 0;
+    // the wavefront takes blocks wave, wave + 8, ...; kEncDepth of them in flight
+    constexpr int D = kEncDepth;
+    DeltaRing<D> ring;
+    auto issue = [&](int d, uint32_t t) __attribute__((always_inline)) {
+        ring.issue(d, x, (p * kFpBlocks + t) * kBlock + 2 * lane, t < nb, S, lane);
     };
-    uint32_t n0, n1;
-    load_d(wave, n0, n1);
-    for (uint32_t t = wave; t < nb; t += 8) {
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+        issue(d, wave + 8u * d);
+    for (uint32_t t0 = wave; t0 < nb; t0 += 8u * D)
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const uint32_t t = t0 + 8u * d;
+        if (t >= nb)
+            break;
         const uint64_t blk = p * kFpBlocks + t;
+        uint32_t n0, n1;
+        ring.take(d, S, lane, n0, n1);
+        issue(d, t + 8u * D);
         const uint32_t w0 = nbits(n0), w1 = nbits(n1);
-        load_d(t + 8, n0, n1);
         for (uint32_t i = lane; i < 8 * 33; i += 64)
             h[i] = 0;
         wave_lds_order();
@@ -372,12 +434,18 @@ __global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__
             meta[blk] = (uint8_t)best_b;
             meta[nblk + blk] = (uint8_t)maxb;
             meta[2 * nblk + blk] = (uint8_t)best_c;
-            atomicAdd(&s_pw, 4 * best_b);
-            atomicAdd(&s_pc, best_c);
-            atomicAdd(&s_cnt[maxb - best_b], best_c);
         }
+        acc_pw += 4 * best_b;
+        acc_pc += best_c;
+        acc_k += lane == maxb - best_b ? best_c : 0u;
         wave_lds_order();
     }
+    if (lane == 0) {
+        atomicAdd(&s_pw, acc_pw);
+        atomicAdd(&s_pc, acc_pc);
+    }
+    if (lane < 33 && acc_k)
+        atomicAdd(&s_cnt[lane], acc_k);
     __syncthreads();
     if (tid == 0) {
         uint32_t nset = 0, exc_w = 0;
@@ -469,14 +537,10 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
     const uint32_t tail_w = size - tail0;         // a multiple of 4
     uint32_t *const sw = sw_all[wave];
     const uint32_t rounds = (nb + 7) / 8;
-    // deltas of this wavefront's next block, loaded one round ahead
-    auto load_d = [&](uint32_t t, uint32_t &d0, uint32_t &d1) __attribute__((always_inline)) {
-        d0 = d1 = 0;
-        if (t < nb) {
-            const uint64_t i0 = (p * kFpBlocks + t) * kBlock + 2 * lane;
-            d0 = delta_at(x, i0, S);
-            d1 = delta_at(x, i0 + 1, S);
-        }
+    // the wavefront takes blocks wave, wave + 8, ...; kEncDepth of them in flight
+    constexpr int D = kEncDepth;
+    auto issue = [&](DeltaRing<D> &ring, int d, uint32_t t) __attribute__((always_inline)) {
+        ring.issue(d, x, (p * kFpBlocks + t) * kBlock + 2 * lane, t < nb, S, lane);
     };
     auto assemble = [&](auto in_lds_tag) __attribute__((always_inline)) {
         constexpr bool IN_LDS = decltype(in_lds_tag)::value;
@@ -492,13 +556,21 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
             mbytes[nb + t] = L.mb[t];
             mbytes[2 * nb + t] = L.c[t];
         }
-        uint32_t n0, n1;
-        load_d(wave, n0, n1);
-        for (uint32_t it = 0; it < rounds; ++it) {
+        DeltaRing<D> ring;
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            issue(ring, d, wave + 8u * d);
+        for (uint32_t it0 = 0; it0 < rounds; it0 += D)
+#pragma unroll
+        for (int dd = 0; dd < D; ++dd) {
+            const uint32_t it = it0 + dd;
+            if (it >= rounds)
+                break;
             const uint32_t t = it * 8 + wave;
             const bool live = t < nb;
-            const uint32_t d0 = n0, d1 = n1;
-            load_d(t + 8, n0, n1);
+            uint32_t d0, d1;
+            ring.take(dd, S, lane, d0, d1);
+            issue(ring, dd, t + 8u * D);
             const uint32_t b = live ? L.b[t] : 0u;
             for (uint32_t i = lane; i < 4 * b; i += 64)
                 sw[i] = 0;
