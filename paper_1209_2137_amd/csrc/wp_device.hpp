@@ -132,10 +132,13 @@ __device__ __forceinline__ uint4 buf_load_u4(BufRsrc rs, uint32_t byte_off)
     return make_uint4(v.x, v.y, v.z, v.w);
 }
 
+// Decoded output goes out with the non-temporal hint (cache policy bit 1):
+// it is written once and not read back by the decoder.
+constexpr int kOutPolicy = 2;
 __device__ __forceinline__ void buf_store_u4(BufRsrc rs, uint32_t byte_off, uint32_t soff, uint4 v)
 {
     const u32x4_t w = {v.x, v.y, v.z, v.w};
-    __builtin_amdgcn_raw_buffer_store_b128(w, rs, (int)byte_off, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(w, rs, (int)byte_off, (int)soff, kOutPolicy);
 }
 
 // Stream header, read with uniform (scalar) loads.
