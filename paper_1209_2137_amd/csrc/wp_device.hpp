@@ -135,10 +135,21 @@ __device__ __forceinline__ uint4 buf_load_u4(BufRsrc rs, uint32_t byte_off)
 // Decoded output goes out with the non-temporal hint (cache policy bit 1):
 // it is written once and not read back by the decoder.
 constexpr int kOutPolicy = 2;
+//
+// A 16-byte store reads its last data registers a little after issue; a
+// vector instruction issued right behind it that overwrites them can
+// change what is stored. Without the wait states below, decoding the 2^28
+// patched list with two wavefronts per workgroup stored, in element 2 of
+// lanes 12-15, 28-31, 44-47 and 60-63, the block width that the next
+// instruction wrote into that register. The scheduling barriers keep the
+// wait directly behind the store.
 __device__ __forceinline__ void buf_store_u4(BufRsrc rs, uint32_t byte_off, uint32_t soff, uint4 v)
 {
     const u32x4_t w = {v.x, v.y, v.z, v.w};
     __builtin_amdgcn_raw_buffer_store_b128(w, rs, (int)byte_off, (int)soff, kOutPolicy);
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_nop 1" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
 }
 
 // Stream header, read with uniform (scalar) loads.
@@ -1104,7 +1115,7 @@ __device__ __forceinline__ bool bp_wave_run(const uint32_t *__restrict__ in, con
                     pos += b;
                 }
                 scan_wave4<S>(x, carry);
-                buf_store_u4(ro, lane * 16u, sbase + p * (G::PASS * 4u), make_uint4(x[0], x[1], x[2], x[3]));
+                buf_store_u4(ro, lane * 16u, uniform(sbase + p * (G::PASS * 4u)), make_uint4(x[0], x[1], x[2], x[3]));
                 ps = pe;
             }
             // widths <= 32, and the unit ends (zero-padded to 4 words)

@@ -175,6 +175,29 @@ def test_full_size_patched_list():
     assert torch.equal(out, xd)
 
 
+def test_full_size_patched_list_every_shape():
+    # the 2^28 patched list with two, four and eight wavefronts per page:
+    # with two, the 16-byte output stores once took a register overwritten
+    # right behind them (element 2 of the last four lanes of each row held
+    # the block width) -- only at this size, where many workgroups share
+    # each compute unit
+    x = datagen.patched_gaps()
+    xd = to_dev(x)
+    del x
+    comp = wp.encode_trimmed(xd, wp.CODEC_FP, 1)
+    out = torch.empty(xd.numel(), dtype=torch.int32, device="cuda")
+    for waves in (2, 4, 8):
+        wp.set_decode_tune(wp.CODEC_FP, waves, 4)
+        for rep in range(2):
+            out.fill_(-1)
+            wp.fastpfor_decode(comp, xd.numel(), out)
+            assert wp.check_code() == wp.OK
+            bad = int((out != xd).sum().item())
+            print(f"waves={waves} run {rep}: {bad} mismatches", flush=True)
+            assert bad == 0
+    autotune.apply()
+
+
 @pytest.mark.parametrize("codec", [wp.CODEC_BP, wp.CODEC_FP])
 def test_corrupt_streams_flagged_without_stray_writes(codec):
     n = 2 * 65536 + 300
