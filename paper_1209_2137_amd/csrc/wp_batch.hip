@@ -94,9 +94,10 @@ __device__ __forceinline__ bool page_item(const DevList *__restrict__ lists, con
     const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
     const uint32_t *pg = Ld.comp + off;
     uint32_t *po = Ld.out + u * kFpUnitInts;
-    // two fetch slots here (three gave wrong values for part of the
-    // stores of partial pages in this kernel; see the tests of batches of
-    // partial pages)
+    // two fetch slots here: three measure the same in this kernel. (Three
+    // once gave wrong values in part of the stores of partial pages; the
+    // cause was the output stores' data hazard that buf_store_u4 now
+    // guards, see the tests of batches of partial pages.)
     ok = off >= H.dir_end && end >= off && end <= H.total && (off & 3u) == 0 &&
          (H.S == 1   ? fp_page<WAVES, 1, 2>(pg, end - off, nb, base, po, L.fp)
           : H.S == 4 ? fp_page<WAVES, 4, 2>(pg, end - off, nb, base, po, L.fp)
