@@ -3,8 +3,8 @@
 // conjunctive-query step that consumes decoded lists).
 //
 // Each element of a is looked up in b by binary search. A workgroup takes a
-// tile of 1024 consecutive elements of a; one thread bounds the tile's range
-// of b with two searches, and every thread then searches its four
+// tile of 1024 consecutive elements of a; two wavefronts bound the tile's
+// range of b (64 probes per round trip), and every thread then searches its four
 // consecutive elements inside that range, each search starting where the
 // previous one ended (a is increasing). Pass 1 writes one flag byte per
 // element of a and the tile's match count; an in-place inclusive scan of the
@@ -38,6 +38,26 @@ __device__ __forceinline__ uint64_t lower_bound(const uint32_t *__restrict__ b, 
     return lo;
 }
 
+// lower_bound by a whole wavefront (uniform arguments and result): 64
+// probes per round trip, the range shrinking 64-fold each time.
+__device__ __forceinline__ uint64_t wave_lower_bound(const uint32_t *__restrict__ b, uint64_t lo, uint64_t hi,
+                                                     uint32_t v)
+{
+    const uint32_t lane = lane_id();
+    for (;;) {
+        const uint64_t len = hi - lo;
+        const uint64_t step = len > 64 ? (len + 63) / 64 : 1;
+        const uint64_t p = lo + lane * step;
+        const bool lt = p < hi && b[p] < v;
+        const uint32_t c = (uint32_t)__builtin_popcountll(ballot(lt));
+        if (len <= 64 || c == 0)
+            return lo + (len <= 64 ? c : 0u);
+        const uint64_t nhi = lo + c * step;
+        lo = lo + (c - 1) * step + 1;
+        hi = nhi < hi ? nhi : hi;
+    }
+}
+
 // Block-wide inclusive sum of one value per thread (256 threads); `part`
 // holds kIsThreads / 64 words of LDS.
 __device__ __forceinline__ uint32_t block_scan_incl(uint32_t v, uint32_t *part, uint32_t &total)
@@ -67,11 +87,12 @@ __global__ __launch_bounds__(kIsThreads) void k_isect_flag(const uint32_t *__res
     __shared__ uint32_t s_part[kIsThreads / 64];
     const uint64_t t0 = (uint64_t)blockIdx.x * kIsTile;
     const uint64_t tend = t0 + kIsTile < na ? t0 + kIsTile : na;
-    if (threadIdx.x == 0) {
-        const uint64_t lo = lower_bound(b, 0, nb, a[t0]);
-        const uint64_t hi = lower_bound(b, lo, nb, a[tend - 1]);
-        s_range[0] = lo;
-        s_range[1] = hi < nb ? hi + 1 : nb;
+    // the tile's range of b: wavefront 0 bounds its first element, 1 its last
+    const uint32_t wave = uniform(threadIdx.x >> 6);
+    if (wave < 2) {
+        const uint64_t r = wave_lower_bound(b, 0, nb, a[wave == 0 ? t0 : tend - 1]);
+        if (lane_id() == 0)
+            s_range[wave] = wave == 0 ? r : (r < nb ? r + 1 : nb);
     }
     __syncthreads();
     uint64_t lo = s_range[0];
