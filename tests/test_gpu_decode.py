@@ -175,6 +175,29 @@ def test_full_size_patched_list():
     assert torch.equal(out, xd)
 
 
+@pytest.mark.parametrize("codec", [wp.CODEC_BP, wp.CODEC_BPV, wp.CODEC_BP32])
+def test_full_size_binary_packing_every_shape(codec):
+    # the 2^26 cluster list in every binary-packing layout, decoded with
+    # every launch shape of the tests above (wavefronts per workgroup, runs
+    # per compute unit, loads in flight), twice each, at full occupancy
+    x = datagen.cluster_sorted()
+    xd = to_dev(x)
+    del x
+    comp = wp.encode_trimmed(xd, codec, 1)
+    dec = {wp.CODEC_BP: wp.bp_decode, wp.CODEC_BPV: wp.bp_vertical_decode, wp.CODEC_BP32: wp.bp32_decode}[codec]
+    out = torch.empty(xd.numel(), dtype=torch.int32, device="cuda")
+    for waves, vpl, wpc, depth in BP_TUNES + [(4, 4, 256, 3), (4, 4, 128, 2)]:
+        wp.set_decode_tune(codec, waves, vpl, wpc, depth)
+        for rep in range(2):
+            out.fill_(-1)
+            dec(comp, xd.numel(), out)
+            assert wp.check_code() == wp.OK
+            bad = int((out != xd).sum().item())
+            print(f"codec={codec} tune=({waves},{vpl},{wpc},{depth}) run {rep}: {bad} mismatches", flush=True)
+            assert bad == 0
+    autotune.apply()
+
+
 def test_full_size_patched_list_every_shape():
     # the 2^28 patched list with two, four and eight wavefronts per page:
     # with two, the 16-byte output stores once took a register overwritten
