@@ -42,6 +42,28 @@ __device__ __forceinline__ void or_field(uint32_t *w, uint32_t i, uint32_t b, ui
         atomicOr(&w[(pos >> 5) + 1], v >> (32u - s));
 }
 
+// A thread's eight consecutive values of a block at b bits are b whole
+// bytes of the block's bit string (fields end to end, least significant bit
+// first), starting on byte `byte0` of `wb` because the thread's first field
+// starts on bit 8 * b * (its index in the block): written with byte stores,
+// and no other thread writes those bytes, so no atomics and no clearing.
+__device__ __forceinline__ void put_bytes8(uint8_t *wb, uint32_t byte0, uint32_t b, const uint32_t (&d)[8])
+{
+    const uint32_t m = width_mask(b);
+    uint64_t acc = 0;
+    uint32_t nbits = 0, o = byte0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        acc |= (uint64_t)(d[r] & m) << nbits;
+        nbits += b;
+        while (nbits >= 8) {
+            wb[o++] = (uint8_t)acc;
+            acc >>= 8;
+            nbits -= 8;
+        }
+    }
+}
+
 // The same for the four-lane layout of Section 4: value i is field i / 4 of
 // 32-bit lane i % 4, the lanes' words interleaved (word w of lane l at 4w + l)
 __device__ __forceinline__ void or_field_vertical(uint32_t *w, uint32_t i, uint32_t b, uint32_t v)
@@ -165,29 +187,36 @@ __global__ __launch_bounds__(256) void k_bp_pack(const uint32_t *__restrict__ x,
     const uint64_t nfull = n / kBlock;
     uint32_t d[8];
     unit_deltas8(x, u * kBpUnitInts, nfull * kBlock, S, d);
+    // the widths into LDS once, then each block's offset from them (a loop
+    // over global loads here would chain up to 15 memory round trips)
+    if (tid < kBpBlocks)
+        s_b[tid] = widths[u * kBpBlocks + tid];
+    __syncthreads();
     if (tid < kBpBlocks) {
         uint32_t pre = 0;
         for (uint32_t j = 0; j < tid; ++j)
-            pre += widths[u * kBpBlocks + j];
-        s_b[tid] = widths[u * kBpBlocks + tid];
+            pre += s_b[j];
         s_off[tid] = 4 + 4 * pre;
     }
     __syncthreads();
     const uint32_t size = s_off[kBpBlocks - 1] + 4 * s_b[kBpBlocks - 1];
-    for (uint32_t i = tid; i < size; i += 256)
-        s_u[i] = 0;
-    __syncthreads();
+    if constexpr (V) {
+        // the four-lane layout interleaves the threads' words: OR-ed in
+        for (uint32_t i = tid; i < size; i += 256)
+            s_u[i] = 0;
+        __syncthreads();
+    }
     if (tid < 4)
         s_u[tid] = s_b[4 * tid] | (s_b[4 * tid + 1] << 8) | (s_b[4 * tid + 2] << 16) | (s_b[4 * tid + 3] << 24);
     const uint32_t j = tid >> 4, b = s_b[j];
     if (b) {
         uint32_t *const w = s_u + s_off[j];
+        if constexpr (V) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            if constexpr (V)
+            for (int r = 0; r < 8; ++r)
                 or_field_vertical(w, 8 * (tid & 15u) + r, b, d[r]);
-            else
-                or_field(w, 8 * (tid & 15u) + r, b, d[r]);
+        } else {
+            put_bytes8(reinterpret_cast<uint8_t *>(w), (tid & 15u) * b, b, d);
         }
     }
     const uint32_t off = dir_end + incl[u] - size;
@@ -268,19 +297,14 @@ __global__ __launch_bounds__(256) void k_bp32_pack(const uint32_t *__restrict__ 
     __syncthreads();
     const uint32_t used = nm ? s_off[4 * nm - 1] + s_b[4 * nm - 1] : 0u;
     const uint32_t size = (used + 3u) & ~3u;
-    for (uint32_t i = tid; i < size; i += 256)
-        s_u[i] = 0;
-    __syncthreads();
+    if (tid < size - used)  // the unit's zero padding
+        s_u[used + tid] = 0;
     if (tid < nm)
         s_u[s_off[4 * tid] - 1] =
             s_b[4 * tid] | (s_b[4 * tid + 1] << 8) | (s_b[4 * tid + 2] << 16) | (s_b[4 * tid + 3] << 24);
     const uint32_t k = tid >> 2, b = s_b[k];
-    if (b) {
-        uint32_t *const w = s_u + s_off[k];
-#pragma unroll
-        for (int r = 0; r < 8; ++r)
-            or_field(w, 8 * (tid & 3u) + r, b, d[r]);
-    }
+    if (b)
+        put_bytes8(reinterpret_cast<uint8_t *>(s_u + s_off[k]), (tid & 3u) * b, b, d);
     const uint32_t off = dir_end + incl[u] - size;
     write_dir_entry(out, u, dir_entries(n, kBpBlocks), S, off, x, u * kBpUnitInts);
     __syncthreads();
