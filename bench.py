@@ -236,6 +236,36 @@ def bench_intersect_compressed(wp, steps, warmup, nb=1 << 24, nas=(1 << 10, 1 <<
             "rows": rows}
 
 
+def bench_decode_range(wp, x, steps, warmup, spans=(1 << 10, 1 << 16, 1 << 22)):
+    """Random access by key on the 2^26 recursive-cluster list (binary
+    packing, differential coding): key ranges covering about 2^10, 2^16 and
+    2^22 values, only the units they touch decoded; timed beside decoding
+    the whole list. Each range checked against numpy's searchsorted once."""
+    import numpy as np
+    import torch
+    n = x.size
+    xd = to_dev(x)
+    comp = wp.encode_trimmed(xd, wp.CODEC_BP, 1)
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    rng_t = torch.zeros(2, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    wall_full, ev_full = time_launches(lambda i: wp.bp_decode(comp, n, out), steps, warmup, stream)
+    rows = []
+    for span in spans:
+        i = n // 3
+        lo, hi = int(x[i]), int(x[i + span - 1])
+        wp.decode_range(comp, n, wp.CODEC_BP, lo, hi, out=out, rng=rng_t)
+        wp.check()
+        i0, i1 = (int(v) for v in rng_t.cpu().numpy())
+        if (i0, i1) != (int(np.searchsorted(x, lo)), int(np.searchsorted(x, hi, side="right"))) or \
+                not np.array_equal(out[i0:i1].cpu().numpy().view(np.uint32), x[i0:i1]):
+            raise RuntimeError("decode_range differs from numpy's searchsorted")
+        wall, ev = time_launches(lambda k: wp.decode_range(comp, n, wp.CODEC_BP, lo, hi, out=out, rng=rng_t),
+                                 steps, warmup, stream)
+        rows.append({"values": i1 - i0, "ms_per_step": wall, "event_ms": ev, "speedup_vs_full": wall_full / wall})
+    return {"name": "decode_range on the 2^26 cluster list", "n": n, "full_decode_ms": wall_full, "rows": rows}
+
+
 def bench_delta(wp, n, steps, warmup):
     import torch
     rng_t = torch.randint(0, 1 << 8, (n,), dtype=torch.int32, device="cuda")
@@ -602,6 +632,8 @@ def main():
         print("# intersection done", file=sys.stderr, flush=True)
         extra["intersect_compressed_2e24"] = bench_intersect_compressed(wp, args.steps, args.warmup)
         print("# compressed intersection done", file=sys.stderr, flush=True)
+        extra["decode_range_cluster_2e26"] = bench_decode_range(wp, x, args.steps, args.warmup)
+        print("# key-range decoding done", file=sys.stderr, flush=True)
         head["pct_of_copy"] = head["achieved_gbs"] / copy["gbs"]
         if not args.no_batch:
             extra["batched_posting_lists"], pool = bench_batch(wp, max(3, args.steps // 2), 2)

@@ -202,6 +202,26 @@ int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const uint32_t *
                                 uint64_t nb, int32_t codec, uint32_t *b_work, uint32_t *out,
                                 uint64_t *out_count, void *stream);
 
+/* Random access by key (the directory's bases as a skip list, Section 3
+ * differential coding): the index range [i0, i1) of the values v with
+ * key_lo <= v <= key_hi in a non-decreasing list held as the stream `in`
+ * (in_words words, n integers, any WP_CODEC_*, 16-byte aligned). Only the
+ * units (and the tail) whose values can lie in the key range, or in which
+ * the range's ends fall, are decoded into `out` (device, n integers,
+ * 16-byte aligned, caller-owned), each at its place in the whole list:
+ * out[i0..i1) then holds the values in the key range and every element of
+ * out outside the decoded units is left as it was. range (device, two
+ * uint64, 8-byte aligned) receives i0 and i1. A stream without
+ * differential coding (stride 0) gives no bounds: all of it is decoded.
+ * For a list that is not non-decreasing the range is unspecified (but lies
+ * in [0, n]). Asynchronous on `stream`; a corrupt stream is reported
+ * through wp_check (range then reads 0, 0). Returns WP_ERR_INVALID_ARG for
+ * null or misaligned pointers, an unknown codec or key_lo > key_hi,
+ * WP_ERR_HIP if a launch or the scratch allocation (one byte per unit,
+ * the library's per-stream scratch) fails. */
+int32_t wp_decode_range(const uint32_t *in, uint64_t in_words, uint64_t n, int32_t codec, uint32_t key_lo,
+                        uint32_t key_hi, uint32_t *out, uint64_t *range, void *stream);
+
 /* Timing hook (host): the calling thread's next bp_decode,
  * fastpfor_decode or delta_decode_inplace records `start_event` when its
  * main kernel starts and `stop_event` when that kernel ends (hipEvent_t,

@@ -30,7 +30,7 @@ EXPORTS = (
     "fastpfor32_encode", "fastpfor32_decode", "bp_vertical_encode", "bp_vertical_decode", "delta_decode_inplace",
     "wp_max_compressed_words", "wp_check", "wp_strerror", "wp_set_decode_tune", "wp_time_next_launch",
     "wp_batch_plan", "wp_batch_replan", "wp_batch_decode", "wp_batch_items", "wp_batch_free",
-    "wp_intersect", "wp_intersect_compressed",
+    "wp_intersect", "wp_intersect_compressed", "wp_decode_range",
 )
 
 _lib = None
@@ -108,6 +108,8 @@ def lib():
     L.wp_intersect.restype = i32
     L.wp_intersect_compressed.argtypes = [vp, u64, vp, u64, u64, i32, vp, vp, vp, vp]
     L.wp_intersect_compressed.restype = i32
+    L.wp_decode_range.argtypes = [vp, u64, u64, i32, u32, u32, vp, vp, vp]
+    L.wp_decode_range.restype = i32
     _lib = L
     # workgroup shapes chosen by the autotuner for this architecture, if any
     try:
@@ -299,6 +301,27 @@ def intersect_compressed(a, b_comp, nb: int, codec: int, work=None, out=None, co
                                          _ptr(work), _ptr(out), _ptr(count), _stream(stream)),
            "wp_intersect_compressed")
     return out, count, work
+
+
+def decode_range(comp, n: int, codec: int, key_lo: int, key_hi: int, out=None, rng=None, stream=None):
+    """Random access by key: decodes only the units of the compressed
+    non-decreasing list (n integers) whose values can lie in
+    [key_lo, key_hi], each at its place in `out` (n integers), and writes
+    the index range [i0, i1) of those values to `rng` (two-element device
+    int64 tensor). Returns (out, rng); asynchronous."""
+    import torch
+    _need_u32(comp, "comp")
+    if out is None:
+        out = torch.empty(max(n, 4), dtype=torch.int32, device=comp.device)
+    _need_u32(out, "out")
+    if out.numel() < n:
+        raise ValueError("out is smaller than n")
+    if rng is None:
+        rng = torch.zeros(2, dtype=torch.int64, device=comp.device)
+    _check(lib().wp_decode_range(_ptr(comp), comp.numel(), int(n), int(codec), int(key_lo) & 0xFFFFFFFF,
+                                 int(key_hi) & 0xFFFFFFFF, _ptr(out), _ptr(rng), _stream(stream)),
+           "wp_decode_range")
+    return out, rng
 
 
 def intersect_trimmed(a, b, stream=None):

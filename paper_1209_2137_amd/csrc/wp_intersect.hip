@@ -38,17 +38,18 @@ __device__ __forceinline__ uint64_t lower_bound(const uint32_t *__restrict__ b, 
     return lo;
 }
 
-// lower_bound by a whole wavefront (uniform arguments and result): 64
-// probes per round trip, the range shrinking 64-fold each time.
+// lower_bound by a whole wavefront (uniform arguments and result) over
+// b[i * stride], i in [lo, hi): 64 probes per round trip, the range
+// shrinking 64-fold each time.
 __device__ __forceinline__ uint64_t wave_lower_bound(const uint32_t *__restrict__ b, uint64_t lo, uint64_t hi,
-                                                     uint32_t v)
+                                                     uint32_t v, uint64_t stride = 1)
 {
     const uint32_t lane = lane_id();
     for (;;) {
         const uint64_t len = hi - lo;
         const uint64_t step = len > 64 ? (len + 63) / 64 : 1;
         const uint64_t p = lo + lane * step;
-        const bool lt = p < hi && b[p] < v;
+        const bool lt = p < hi && b[p * stride] < v;
         const uint32_t c = (uint32_t)__builtin_popcountll(ballot(lt));
         if (len <= 64 || c == 0)
             return lo + (len <= 64 ? c : 0u);
@@ -338,6 +339,70 @@ __global__ __launch_bounds__(kIsThreads) void k_isect_flag_dir(const uint32_t *_
         counts[blockIdx.x] = total;
 }
 
+// ---------------------------------------------------------------------
+// Random access by key: the entries whose values can lie in [klo, khi]. In
+// a non-decreasing list entry e holds values in [base_e, base_{e+1}] (equal
+// values may straddle entries); without differential coding every entry
+// counts. Every entry in which one of the two searches below ends is among
+// them: the search for v ends in the entry with base_e < v <= base_{e+1}.
+__global__ __launch_bounds__(256) void k_range_touch(const uint32_t *__restrict__ in, uint64_t in_words, uint64_t n,
+                                                     int32_t codec, uint32_t klo, uint32_t khi,
+                                                     uint8_t *__restrict__ flags, int *__restrict__ err)
+{
+    DirView D;
+    if (!dir_view(in, in_words, n, codec, D)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            *err = kErrCorrupt;
+        return;
+    }
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= D.H.ndir)
+        return;
+    bool hit = true;
+    if (D.H.S != 0) {
+        const bool above_lo = e + 1 == D.H.ndir || D.base(e + 1) >= klo;  // some value of e can be >= klo
+        const bool below_hi = e == 0 || D.base(e) <= khi;                  // some value of e can be <= khi
+        hit = above_lo && below_hi;
+    }
+    flags[e] = hit ? 1u : 0u;
+}
+
+// The index range [i0, i1) of the values in [klo, khi]: wavefront 0 finds
+// the first value >= klo, wavefront 1 the first value > khi, each by the
+// directory's bases (the entry), then inside the entry's decoded values.
+__global__ __launch_bounds__(128) void k_range_bounds(const uint32_t *__restrict__ in, uint64_t in_words, uint64_t n,
+                                                      int32_t codec, uint32_t klo, uint32_t khi,
+                                                      const uint32_t *__restrict__ vals,
+                                                      uint64_t *__restrict__ range, int *__restrict__ err)
+{
+    DirView D;
+    const bool valid = dir_view(in, in_words, n, codec, D);
+    if (!valid && threadIdx.x == 0)
+        *err = kErrCorrupt;
+    const uint32_t wave = uniform(threadIdx.x >> 6);
+    uint64_t r = 0;
+    if (valid) {
+        // first value >= v, v = klo or khi + 1 (none above 0xffffffff)
+        const bool past_top = wave == 1 && khi == 0xffffffffu;
+        const uint32_t v = wave == 0 ? klo : khi + 1u;
+        if (past_top) {
+            r = n;
+        } else if (D.H.S == 0) {
+            r = wave_lower_bound(vals, 0, n, v);
+        } else {
+            // entry: the last e whose base is below v (entry 0 has no base)
+            const uint32_t *bases = in + kHdrWords + D.H.ndir + (D.H.S - 1);
+            const uint64_t e = wave_lower_bound(bases, 1, D.H.ndir, v, D.H.S) - 1;
+            const uint64_t lo = D.first_int(e);
+            uint64_t hi = e + 1 < D.H.ndir ? D.first_int(e + 1) : n;
+            hi = hi < n ? hi : n;
+            r = wave_lower_bound(vals, lo, hi, v);
+        }
+    }
+    if (lane_id() == 0)
+        range[wave] = r;
+}
+
 __global__ void k_isect_none(uint64_t *__restrict__ out_count)
 {
     if (threadIdx.x == 0)
@@ -448,5 +513,51 @@ extern "C" int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const
         return WP_ERR_HIP;
     hipLaunchKernelGGL(k_isect_write, dim3((uint32_t)tiles), dim3(kIsThreads), 0, st, a, na, S.flags, S.counts, out,
                        out_count);
+    return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
+}
+
+extern "C" int32_t wp_decode_range(const uint32_t *in, uint64_t in_words, uint64_t n, int32_t codec,
+                                   uint32_t key_lo, uint32_t key_hi, uint32_t *out, uint64_t *range, void *stream)
+{
+    if (in == nullptr || in_words < kHdrWords || range == nullptr || (n > 0 && out == nullptr) ||
+        (reinterpret_cast<uintptr_t>(range) & 7u) || key_lo > key_hi ||
+        (codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32 && codec != WP_CODEC_FP32 &&
+         codec != WP_CODEC_BPV) ||
+        !aligned16(in) || !aligned16(out) || n > 0xFFFFFFFFull * 32ull)
+        return WP_ERR_INVALID_ARG;
+    DevState *ds = dev_state();
+    if (ds == nullptr)
+        return WP_ERR_HIP;
+    hipStream_t st = as_stream(stream);
+    (void)hipGetLastError();
+    const uint64_t per = (codec == WP_CODEC_FP || codec == WP_CODEC_FP32) ? kFpBlocks : kBpBlocks;
+    const uint64_t nfull = n / kBlock;
+    const uint64_t nent = (nfull + per - 1) / per + ((n % kBlock) ? 1 : 0);
+    if (nent > 0x7FFFFFFFull)
+        return WP_ERR_INVALID_ARG;
+    if (nent > 0) {
+        uint8_t *flags = static_cast<uint8_t *>(stream_scratch(st, nent));
+        if (flags == nullptr)
+            return WP_ERR_HIP;
+        hipLaunchKernelGGL(k_range_touch, dim3((uint32_t)((nent + 255) / 256)), dim3(256), 0, st, in, in_words, n,
+                           codec, key_lo, key_hi, flags, ds->err);
+        if (codec == WP_CODEC_BP)
+            hipLaunchKernelGGL((k_isect_decode_bp<false, false>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
+                               in, in_words, n, flags, out, ds->err);
+        else if (codec == WP_CODEC_BPV)
+            hipLaunchKernelGGL((k_isect_decode_bp<false, true>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
+                               in, in_words, n, flags, out, ds->err);
+        else if (codec == WP_CODEC_BP32)
+            hipLaunchKernelGGL((k_isect_decode_bp<true, false>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
+                               in, in_words, n, flags, out, ds->err);
+        else if (codec == WP_CODEC_FP32)
+            hipLaunchKernelGGL(k_isect_decode_fp<true>, dim3((uint32_t)nent), dim3(256), 0, st, in, in_words, n,
+                               flags, out, ds->err);
+        else
+            hipLaunchKernelGGL(k_isect_decode_fp<false>, dim3((uint32_t)nent), dim3(256), 0, st, in, in_words, n,
+                               flags, out, ds->err);
+    }
+    hipLaunchKernelGGL(k_range_bounds, dim3(1), dim3(128), 0, st, in, in_words, n, codec, key_lo, key_hi, out,
+                       range, ds->err);
     return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
 }
