@@ -322,9 +322,12 @@ __global__ __launch_bounds__(256) void k_bp32_pack(const uint32_t *__restrict__ 
 //
 // One wavefront per block: the 128 widths go into a 33-bin LDS histogram
 // (eight copies, one per 16-lane row and value slot, so that an atomic add
-// meets at most 16 lanes on one bin), lane b then holds c(b) (values minus
-// the inclusive prefix of the bins up to b), its cost, and one minimum over
-// the wavefront of (cost << 6 | 63 - b) picks the width.
+// meets at most 16 lanes on one bin; the eight copies of a bin are adjacent,
+// so the wavefront clears the histogram with two 16-byte stores per lane
+// and lane b reads its bin's copies with two 16-byte loads), lane b then
+// holds c(b) (values minus the inclusive prefix of the bins up to b), its
+// cost, and one minimum over the wavefront of (cost << 6 | 63 - b) picks
+// the width.
 
 // Deltas of a page's blocks for a wavefront that takes one block at a time,
 // lane l integers 2l and 2l+1, with D blocks' loads in flight (registers
@@ -396,7 +399,7 @@ __global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__
                                                     uint32_t *__restrict__ sizes)
 {
     __shared__ uint32_t s_cnt[33];
-    __shared__ uint32_t s_hist[8][8 * 33];
+    __shared__ __align__(16) uint32_t s_hist[8][8 * 33];  // per wavefront: bin w's copies at 8w .. 8w + 7
     __shared__ uint32_t s_pw, s_pc;
     const uint64_t p = blockIdx.x;
     const uint32_t tid = threadIdx.x;
@@ -434,18 +437,19 @@ __global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__
         ring.take(d, S, lane, n0, n1);
         issue(d, t + 8u * D);
         const uint32_t w0 = nbits(n0), w1 = nbits(n1);
-        for (uint32_t i = lane; i < 8 * 33; i += 64)
-            h[i] = 0;
+        uint4 *const h4 = reinterpret_cast<uint4 *>(h);  // 66 groups of four copies
+        h4[lane] = make_uint4(0, 0, 0, 0);
+        if (lane < 2)
+            h4[64 + lane] = make_uint4(0, 0, 0, 0);
         wave_lds_order();
-        uint32_t *const hc = h + 66 * (lane >> 4);
-        atomicAdd(&hc[w0], 1u);
-        atomicAdd(&hc[33 + w1], 1u);
+        const uint32_t copy = 2u * (lane >> 4);
+        atomicAdd(&h[8 * w0 + copy], 1u);
+        atomicAdd(&h[8 * w1 + copy + 1], 1u);
         wave_lds_order();
         uint32_t hb = 0;  // values of width `lane` (0 beyond 32)
         if (lane < 33) {
-#pragma unroll
-            for (int c = 0; c < 8; ++c)
-                hb += h[33 * c + lane];
+            const uint4 g0 = h4[2 * lane], g1 = h4[2 * lane + 1];
+            hb = (g0.x + g0.y) + (g0.z + g0.w) + (g1.x + g1.y) + (g1.z + g1.w);
         }
         const uint64_t used = ballot(hb != 0);
         const uint32_t maxb = 63u - (uint32_t)__builtin_clzll(used);
