@@ -331,17 +331,23 @@ __global__ __launch_bounds__(256) void k_bp32_pack(const uint32_t *__restrict__ 
 
 // Deltas of a page's blocks for a wavefront that takes one block at a time,
 // lane l integers 2l and 2l+1, with D blocks' loads in flight (registers
-// indexed by compile-time slot only). The predecessors come from the
+// indexed by compile-time slot only; the stride S, 0, 1 or 4, fixed at
+// compile time). The predecessors come from the
 // neighbouring lanes (one lane back for stride 1, two for stride 4), from
 // memory for the first lanes, 0 before the array start.
 template <int D>
 struct DeltaRing {
     uint32_t ra[D], rb[D], rp0[D], rp1[D];
 
-    __device__ __forceinline__ void issue(int d, const uint32_t *__restrict__ x, uint64_t i0, bool live, uint32_t S,
+    template <uint32_t S>
+    __device__ __forceinline__ void issue(int d, const uint32_t *__restrict__ x, uint64_t i0, bool live,
                                           uint32_t lane)
     {
-        ra[d] = rb[d] = rp0[d] = rp1[d] = 0;
+        ra[d] = rb[d] = 0;
+        if constexpr (S == 1)
+            rp1[d] = 0;
+        if constexpr (S == 4)
+            rp0[d] = rp1[d] = 0;
         if (live) {
             ra[d] = x[i0];
             rb[d] = x[i0 + 1];
@@ -354,12 +360,13 @@ struct DeltaRing {
         }
     }
 
-    __device__ __forceinline__ void take(int d, uint32_t S, uint32_t lane, uint32_t &d0, uint32_t &d1) const
+    template <uint32_t S>
+    __device__ __forceinline__ void take(int d, uint32_t lane, uint32_t &d0, uint32_t &d1) const
     {
-        if (S == 0) {
+        if constexpr (S == 0) {
             d0 = ra[d];
             d1 = rb[d];
-        } else if (S == 1) {
+        } else if constexpr (S == 1) {
             uint32_t prev = (uint32_t)__shfl_up((int)rb[d], 1, 64);
             if (lane == 0)
                 prev = rp1[d];
@@ -393,8 +400,8 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v)
     return wave_read(v, 63);
 }
 
-template <bool P32>
-__global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
+template <bool P32, uint32_t S>
+__global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__ x, uint64_t n,
                                                     uint8_t *__restrict__ meta, uint64_t nblk,
                                                     uint32_t *__restrict__ sizes)
 {
@@ -421,7 +428,7 @@ __global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__
     constexpr int D = kEncDepth;
     DeltaRing<D> ring;
     auto issue = [&](int d, uint32_t t) __attribute__((always_inline)) {
-        ring.issue(d, x, (p * kFpBlocks + t) * kBlock + 2 * lane, t < nb, S, lane);
+        ring.template issue<S>(d, x, (p * kFpBlocks + t) * kBlock + 2 * lane, t < nb, lane);
     };
 #pragma unroll
     for (int d = 0; d < D; ++d)
@@ -434,7 +441,7 @@ __global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__
             break;
         const uint64_t blk = p * kFpBlocks + t;
         uint32_t n0, n1;
-        ring.take(d, S, lane, n0, n1);
+        ring.template take<S>(d, lane, n0, n1);
         issue(d, t + 8u * D);
         const uint32_t w0 = nbits(n0), w1 = nbits(n1);
         uint4 *const h4 = reinterpret_cast<uint4 *>(h);  // 66 groups of four copies
@@ -490,8 +497,8 @@ __global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__
 // LDS staging of a page's metadata and exception arrays in k_fp_pack
 constexpr uint32_t kPackTailWords = 8192;
 
-template <bool P32>
-__global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
+template <bool P32, uint32_t S>
+__global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x, uint64_t n,
                                                  const uint8_t *__restrict__ meta, uint64_t nblk,
                                                  const uint32_t *__restrict__ incl, uint32_t dir_end,
                                                  uint32_t *__restrict__ out)
@@ -568,7 +575,7 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
     // the wavefront takes blocks wave, wave + 8, ...; kEncDepth of them in flight
     constexpr int D = kEncDepth;
     auto issue = [&](DeltaRing<D> &ring, int d, uint32_t t) __attribute__((always_inline)) {
-        ring.issue(d, x, (p * kFpBlocks + t) * kBlock + 2 * lane, t < nb, S, lane);
+        ring.template issue<S>(d, x, (p * kFpBlocks + t) * kBlock + 2 * lane, t < nb, lane);
     };
     auto assemble = [&](auto in_lds_tag) __attribute__((always_inline)) {
         constexpr bool IN_LDS = decltype(in_lds_tag)::value;
@@ -597,7 +604,7 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
             const uint32_t t = it * 8 + wave;
             const bool live = t < nb;
             uint32_t d0, d1;
-            ring.take(dd, S, lane, d0, d1);
+            ring.template take<S>(dd, lane, d0, d1);
             issue(ring, dd, t + 8u * D);
             const uint32_t b = live ? L.b[t] : 0u;
             for (uint32_t i = lane; i < 4 * b; i += 64)
@@ -702,6 +709,18 @@ __global__ __launch_bounds__(128) void k_finish(const uint32_t *__restrict__ x, 
     }
 }
 
+// the patched encoders for a stride known at compile time
+#define WP_FP_ENC(kern, p32, args)                                                                         \
+    do {                                                                                                   \
+        if (stride == 0)                                                                                   \
+            hipLaunchKernelGGL((kern<p32, 0u>), dim3((uint32_t)units), dim3(512), 0, st, WP_UNPAREN args); \
+        else if (stride == 1)                                                                              \
+            hipLaunchKernelGGL((kern<p32, 1u>), dim3((uint32_t)units), dim3(512), 0, st, WP_UNPAREN args); \
+        else                                                                                               \
+            hipLaunchKernelGGL((kern<p32, 4u>), dim3((uint32_t)units), dim3(512), 0, st, WP_UNPAREN args); \
+    } while (0)
+#define WP_UNPAREN(...) __VA_ARGS__
+
 static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t stride, uint32_t *out,
                              uint64_t cap, uint64_t *out_words, void *stream)
 {
@@ -747,11 +766,9 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
             hipLaunchKernelGGL(k_bp32_analyze, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride,
                                meta, sizes);
         else if (codec == WP_CODEC_FP32)
-            hipLaunchKernelGGL(k_fp_analyze<true>, dim3((uint32_t)units), dim3(512), 0, st, in, n, (uint32_t)stride,
-                               meta, nblk, sizes);
+            WP_FP_ENC(k_fp_analyze, true, (in, n, meta, nblk, sizes));
         else
-            hipLaunchKernelGGL(k_fp_analyze<false>, dim3((uint32_t)units), dim3(512), 0, st, in, n, (uint32_t)stride,
-                               meta, nblk, sizes);
+            WP_FP_ENC(k_fp_analyze, false, (in, n, meta, nblk, sizes));
         if (launch_inclusive_scan(sizes, units, status, st) != WP_OK)
             return WP_ERR_HIP;
         if (codec == WP_CODEC_BP)
@@ -764,11 +781,9 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
             hipLaunchKernelGGL(k_bp32_pack, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride, meta,
                                sizes, dir_end, out);
         else if (codec == WP_CODEC_FP32)
-            hipLaunchKernelGGL(k_fp_pack<true>, dim3((uint32_t)units), dim3(512), 0, st, in, n, (uint32_t)stride,
-                               meta, nblk, sizes, dir_end, out);
+            WP_FP_ENC(k_fp_pack, true, (in, n, meta, nblk, sizes, dir_end, out));
         else
-            hipLaunchKernelGGL(k_fp_pack<false>, dim3((uint32_t)units), dim3(512), 0, st, in, n, (uint32_t)stride,
-                               meta, nblk, sizes, dir_end, out);
+            WP_FP_ENC(k_fp_pack, false, (in, n, meta, nblk, sizes, dir_end, out));
     }
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(128), 0, st, in, n, (uint32_t)stride, (uint32_t)codec, sizes, units,
                        dir_end, out, out_words);
