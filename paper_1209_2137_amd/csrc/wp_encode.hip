@@ -595,6 +595,9 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
 #pragma unroll
         for (int d = 0; d < D; ++d)
             issue(ring, d, wave + 8u * d);
+        for (uint32_t i = lane; i < 2 * kBlock; i += 64)  // the block words start cleared
+            sw[i] = 0;
+        wave_lds_order();
         for (uint32_t it0 = 0; it0 < rounds; it0 += D)
 #pragma unroll
         for (int dd = 0; dd < D; ++dd) {
@@ -607,9 +610,6 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
             ring.template take<S>(dd, lane, d0, d1);
             issue(ring, dd, t + 8u * D);
             const uint32_t b = live ? L.b[t] : 0u;
-            for (uint32_t i = lane; i < 4 * b; i += 64)
-                sw[i] = 0;
-            wave_lds_order();
             if (live) {
                 or_field(sw, 2 * lane, b, d0);
                 or_field(sw, 2 * lane + 1, b, d1);
@@ -634,8 +634,10 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
             }
             wave_lds_order();
             if (live)
-                for (uint32_t i = lane; i < 4 * b; i += 64)
+                for (uint32_t i = lane; i < 4 * b; i += 64) {
                     page[hdr_w + L.blkoff[t] + i] = sw[i];
+                    sw[i] = 0;  // cleared for the wavefront's next block
+                }
             wave_lds_order();
         }
         if constexpr (IN_LDS) {
