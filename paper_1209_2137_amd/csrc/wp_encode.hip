@@ -504,7 +504,7 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
                                                  uint32_t *__restrict__ out)
 {
     __shared__ FpLds<8> L;
-    __shared__ uint32_t sw_all[8][2 * kBlock];  // a wavefront's packed words (L.xp overlays the tables)
+    __shared__ __align__(16) uint32_t sw_all[8][2 * kBlock];  // a wavefront's packed words (L.xp overlays the tables)
     __shared__ __align__(16) uint32_t s_tail[kPackTailWords];
     constexpr int T = 512;
     const uint64_t p = blockIdx.x;
@@ -633,11 +633,11 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
                 }
             }
             wave_lds_order();
-            if (live)
-                for (uint32_t i = lane; i < 4 * b; i += 64) {
-                    page[hdr_w + L.blkoff[t] + i] = sw[i];
-                    sw[i] = 0;  // cleared for the wavefront's next block
-                }
+            if (live && lane < b) {  // the block's 4b words as b 16-byte stores
+                uint4 *const sw4 = reinterpret_cast<uint4 *>(sw);
+                reinterpret_cast<uint4 *>(page + hdr_w + L.blkoff[t])[lane] = sw4[lane];
+                sw4[lane] = make_uint4(0, 0, 0, 0);  // cleared for the wavefront's next block
+            }
             wave_lds_order();
         }
         if constexpr (IN_LDS) {
