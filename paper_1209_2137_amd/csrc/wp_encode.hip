@@ -548,6 +548,15 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
     }
     __syncthreads();
     const uint32_t size = L.kcnt[0];
+    // one record per block, read by the packing wavefront with one load:
+    // {b | k << 8, word offset in the packed region, bit offset of its first
+    // exception's high part from the end of the packed region, offset of its
+    // positions}; visible after the barrier that opens the assembly below
+    for (uint32_t t = tid; t < nb; t += T) {
+        const uint32_t b = L.b[t], k = (uint32_t)L.mb[t] - b;
+        const uint32_t ebit = k ? (L.excbase[k <= 32 ? k : 0] - (hdr_w + packed_words)) * 32u + L.rank[t] * k : 0u;
+        L.rec[t] = make_uint4(b | (k << 8), L.blkoff[t], ebit, L.posoff[t]);
+    }
     const uint32_t off = dir_end + incl[p] - size;
     write_dir_entry(out, p, dir_entries(n, kFpBlocks), S, off, x, p * kFpUnitInts);
     uint32_t *page = out + off;
@@ -609,33 +618,32 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
             uint32_t d0, d1;
             ring.template take<S>(dd, lane, d0, d1);
             issue(ring, dd, t + 8u * D);
-            const uint32_t b = live ? L.b[t] : 0u;
+            const uint4 rc = live ? L.rec[t] : make_uint4(0, 0, 0, 0);
+            const uint32_t b = rc.x & 255u;
             if (live) {
                 or_field(sw, 2 * lane, b, d0);
                 or_field(sw, 2 * lane + 1, b, d1);
                 const bool e0 = nbits(d0) > b, e1 = nbits(d1) > b;
                 const uint64_t m0 = ballot(e0), m1 = ballot(e1);
                 const uint32_t r0 = lanes_below(m0) + lanes_below(m1);
-                const uint32_t k = (uint32_t)L.mb[t] - b;
-                const uint32_t rk = L.rank[t];
-                uint32_t *const arr = tw + (L.excbase[k <= 32 ? k : 0] - tail0);
+                const uint32_t k = rc.x >> 8;
                 for (int h = 0; h < 2; ++h) {
                     const bool e = h ? e1 : e0;
                     if (!e)
                         continue;
                     const uint32_t idx = r0 + (h ? (uint32_t)e0 : 0u);
-                    mbytes[3 * nb + L.posoff[t] + idx] = (uint8_t)(2 * lane + h);
+                    mbytes[3 * nb + rc.w + idx] = (uint8_t)(2 * lane + h);
                     const uint32_t hv = (h ? d1 : d0) >> b;
-                    const uint32_t bit = (rk + idx) * k, s = bit & 31u;
-                    atomicOr(&arr[bit >> 5], hv << s);
+                    const uint32_t bit = rc.z + idx * k, s = bit & 31u;
+                    atomicOr(&tw[bit >> 5], hv << s);
                     if (s + k > 32u)
-                        atomicOr(&arr[(bit >> 5) + 1], hv >> (32u - s));
+                        atomicOr(&tw[(bit >> 5) + 1], hv >> (32u - s));
                 }
             }
             wave_lds_order();
             if (live && lane < b) {  // the block's 4b words as b 16-byte stores
                 uint4 *const sw4 = reinterpret_cast<uint4 *>(sw);
-                reinterpret_cast<uint4 *>(page + hdr_w + L.blkoff[t])[lane] = sw4[lane];
+                reinterpret_cast<uint4 *>(page + hdr_w + rc.y)[lane] = sw4[lane];
                 sw4[lane] = make_uint4(0, 0, 0, 0);  // cleared for the wavefront's next block
             }
             wave_lds_order();
