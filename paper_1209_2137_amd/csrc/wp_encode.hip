@@ -320,14 +320,16 @@ __global__ __launch_bounds__(256) void k_bp32_pack(const uint32_t *__restrict__ 
 // b; among equal costs the largest b (the rule scans b downward from maxb
 // and only a strictly smaller cost replaces the current choice).
 //
-// One wavefront per block: the 128 widths go into a 33-bin LDS histogram
-// (eight copies, one per 16-lane row and value slot, so that an atomic add
-// meets at most 16 lanes on one bin; the eight copies of a bin are adjacent,
-// so the wavefront clears the histogram with two 16-byte stores per lane
-// and lane b reads its bin's copies with two 16-byte loads), lane b then
-// holds c(b) (values minus the inclusive prefix of the bins up to b), its
-// cost, and one minimum over the wavefront of (cost << 6 | 63 - b) picks
-// the width.
+// One wavefront per pair of blocks, four values per lane, each half of the
+// wavefront one block: the block's 128 widths go into its own 33-bin LDS
+// histogram (eight copies, one per 16-lane row and value slot, so that an
+// atomic add meets at most 16 lanes on one bin; a bin's eight copies are
+// adjacent, so the wavefront clears both histograms with 16-byte stores and
+// lane b of a half reads its bin with two 16-byte loads); lane b of a half
+// then holds c(b) (values minus the inclusive prefix of the bins up to b),
+// its cost, and one minimum over the half of (cost << 6 | 63 - b) picks the
+// width; b = 32 (no exceptions) is the one candidate outside the half's
+// lanes, rated when the block has a 32-bit value.
 
 // Deltas of a page's blocks for a wavefront that takes one block at a time,
 // lane l integers 2l and 2l+1, with D blocks' loads in flight (registers
@@ -400,13 +402,79 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v)
     return wave_read(v, 63);
 }
 
+// Deltas of a pair of consecutive blocks of a page for a wavefront: lane l
+// holds integers 4l..4l+3 of the pair (lanes 0..31 the first block, 32..63
+// the second), D pairs' loads in flight. Loads go through a buffer
+// resource over the page's full blocks, so a block past the page reads as
+// zeros; lane 0 takes the four integers before the pair from memory.
+template <int D>
+struct PairRing {
+    uint4 v[D], pv[D];
+
+    template <uint32_t S>
+    __device__ __forceinline__ void issue(int d, BufRsrc rs, const uint32_t *__restrict__ x, uint64_t pstart,
+                                          uint32_t q, uint32_t lane)
+    {
+        v[d] = buf_load_u4(rs, (2u * q * kBlock + 4u * lane) * 4u);
+        pv[d] = make_uint4(0, 0, 0, 0);
+        if (S != 0 && lane == 0) {
+            if (q != 0)
+                pv[d] = buf_load_u4(rs, (2u * q * kBlock - 4u) * 4u);
+            else if (pstart >= 4)
+                pv[d] = make_uint4(x[pstart - 4], x[pstart - 3], x[pstart - 2], x[pstart - 1]);
+        }
+    }
+
+    template <uint32_t S>
+    __device__ __forceinline__ void take(int d, uint32_t lane, uint32_t (&dl)[4]) const
+    {
+        const uint4 a = v[d];
+        if constexpr (S == 0) {
+            dl[0] = a.x, dl[1] = a.y, dl[2] = a.z, dl[3] = a.w;
+        } else if constexpr (S == 1) {
+            uint32_t prev = (uint32_t)__shfl_up((int)a.w, 1, 64);
+            if (lane == 0)
+                prev = pv[d].w;
+            dl[0] = a.x - prev, dl[1] = a.y - a.x, dl[2] = a.z - a.y, dl[3] = a.w - a.z;
+        } else {
+            uint32_t p0 = (uint32_t)__shfl_up((int)a.x, 1, 64), p1 = (uint32_t)__shfl_up((int)a.y, 1, 64);
+            uint32_t p2 = (uint32_t)__shfl_up((int)a.z, 1, 64), p3 = (uint32_t)__shfl_up((int)a.w, 1, 64);
+            if (lane == 0)
+                p0 = pv[d].x, p1 = pv[d].y, p2 = pv[d].z, p3 = pv[d].w;
+            dl[0] = a.x - p0, dl[1] = a.y - p1, dl[2] = a.z - p2, dl[3] = a.w - p3;
+        }
+    }
+};
+
+// Inclusive sum and minimum over each half of the wavefront (lanes 0..31,
+// 32..63): row steps, then row 1 (3) takes row 0's (2's) last lane.
+__device__ __forceinline__ uint32_t half_scan_incl(uint32_t v)
+{
+    v = row_scan_incl(v);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    return v;
+}
+
+__device__ __forceinline__ uint32_t half_min_at_ends(uint32_t v)  // lane 31: min of 0..31, lane 63: of 32..63
+{
+    constexpr uint32_t kId = 0xffffffffu;
+    auto step = [&](uint32_t o) __attribute__((always_inline)) { v = o < v ? o : v; };
+    step(__builtin_amdgcn_update_dpp(kId, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    step(__builtin_amdgcn_update_dpp(kId, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    step(__builtin_amdgcn_update_dpp(kId, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    step(__builtin_amdgcn_update_dpp(kId, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    step(__builtin_amdgcn_update_dpp(kId, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    return v;
+}
+
 template <bool P32, uint32_t S>
 __global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__ x, uint64_t n,
                                                     uint8_t *__restrict__ meta, uint64_t nblk,
                                                     uint32_t *__restrict__ sizes)
 {
     __shared__ uint32_t s_cnt[33];
-    __shared__ __align__(16) uint32_t s_hist[8][8 * 33];  // per wavefront: bin w's copies at 8w .. 8w + 7
+    // per wavefront and block of the pair: bin w's eight copies at 8w .. 8w + 7
+    __shared__ __align__(16) uint32_t s_hist[8][2][8 * 33];
     __shared__ uint32_t s_pw, s_pc;
     const uint64_t p = blockIdx.x;
     const uint32_t tid = threadIdx.x;
@@ -420,59 +488,75 @@ __global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__
     if (tid == 0)
         s_pw = 0, s_pc = 0;
     __syncthreads();
-    uint32_t *const h = s_hist[wave];
+    const uint32_t half = lane >> 5, b_l = lane & 31u;  // the lane's block of the pair; the width it rates
+    uint32_t *const h = s_hist[wave][half];
+    uint4 *const h4all = reinterpret_cast<uint4 *>(s_hist[wave][0]);  // both histograms, 132 groups of four
+    const uint4 *const h4 = reinterpret_cast<const uint4 *>(h);
     // per-wavefront sums, added to the page's once at the end: packed
     // words, exceptions, and (lane k) exceptions of width difference k
     uint32_t acc_pw = 0, acc_pc = 0, acc_k = 0;
-    // the wavefront takes blocks wave, wave + 8, ...; kEncDepth of them in flight
+    const uint64_t pstart = p * kFpUnitInts;
+    const BufRsrc rs = make_rsrc(x + pstart, nb * kBlock * 4u);
+    const uint32_t npair = (nb + 1) / 2;
+    // the wavefront takes pairs wave, wave + 8, ...; kEncDepth of them in flight
     constexpr int D = kEncDepth;
-    DeltaRing<D> ring;
-    auto issue = [&](int d, uint32_t t) __attribute__((always_inline)) {
-        ring.template issue<S>(d, x, (p * kFpBlocks + t) * kBlock + 2 * lane, t < nb, lane);
-    };
+    PairRing<D> ring;
 #pragma unroll
     for (int d = 0; d < D; ++d)
-        issue(d, wave + 8u * d);
-    for (uint32_t t0 = wave; t0 < nb; t0 += 8u * D)
+        ring.template issue<S>(d, rs, x, pstart, wave + 8u * d, lane);
+    for (uint32_t q0 = wave; q0 < npair; q0 += 8u * D)
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        const uint32_t t = t0 + 8u * d;
-        if (t >= nb)
+        const uint32_t q = q0 + 8u * d;
+        if (q >= npair)
             break;
+        uint32_t dl[4];
+        ring.template take<S>(d, lane, dl);
+        ring.template issue<S>(d, rs, x, pstart, q + 8u * D, lane);
+        h4all[lane] = make_uint4(0, 0, 0, 0);
+        h4all[64 + lane] = make_uint4(0, 0, 0, 0);
+        if (lane < 4)
+            h4all[128 + lane] = make_uint4(0, 0, 0, 0);
+        wave_lds_order();
+        const uint32_t copy = 4u * ((lane >> 4) & 1u);
+        bool w32 = false;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t w = nbits(dl[c]);
+            w32 = w32 || w == 32u;
+            atomicAdd(&h[8 * w + copy + c], 1u);
+        }
+        wave_lds_order();
+        const uint4 g0 = h4[2 * b_l], g1 = h4[2 * b_l + 1];
+        const uint32_t hb = (g0.x + g0.y) + (g0.z + g0.w) + (g1.x + g1.y) + (g1.z + g1.w);  // values of width b_l
+        const uint64_t used = ballot(hb != 0), wide = ballot(w32);
+        // widest value of each block: 32 if some value needs 32 bits
+        const uint32_t uA = (uint32_t)used, uB = (uint32_t)(used >> 32);
+        const uint32_t mA = (uint32_t)wide ? 32u : 31u - (uint32_t)__builtin_clz(uA | 1u);
+        const uint32_t mB = (uint32_t)(wide >> 32) ? 32u : 31u - (uint32_t)__builtin_clz(uB | 1u);
+        const uint32_t maxb = half ? mB : mA;
+        const uint32_t c = kBlock - half_scan_incl(hb);  // values wider than b_l
+        const uint32_t cost = kBlock * b_l + c * (8u + maxb - b_l);
+        const uint32_t key = half_min_at_ends(b_l <= maxb ? (cost << 6) | (63u - b_l) : 0xffffffffu);
+        constexpr uint32_t kKey32 = ((kBlock * 32u) << 6) | (63u - 32u);  // b = 32: no exceptions
+        uint32_t kA = wave_read(key, 31), kB = wave_read(key, 63);
+        kA = mA == 32u && kKey32 < kA ? kKey32 : kA;
+        kB = mB == 32u && kKey32 < kB ? kKey32 : kB;
+        const uint32_t bA = 63u - (kA & 63u), bB = 63u - (kB & 63u);
+        const uint32_t cA = bA == 32u ? 0u : wave_read(c, (int)bA);
+        const uint32_t cB = bB == 32u ? 0u : wave_read(c, 32 + (int)(bB & 31u));
+        const uint32_t t = 2u * q;
+        const bool liveB = t + 1 < nb;
         const uint64_t blk = p * kFpBlocks + t;
-        uint32_t n0, n1;
-        ring.template take<S>(d, lane, n0, n1);
-        issue(d, t + 8u * D);
-        const uint32_t w0 = nbits(n0), w1 = nbits(n1);
-        uint4 *const h4 = reinterpret_cast<uint4 *>(h);  // 66 groups of four copies
-        h4[lane] = make_uint4(0, 0, 0, 0);
-        if (lane < 2)
-            h4[64 + lane] = make_uint4(0, 0, 0, 0);
-        wave_lds_order();
-        const uint32_t copy = 2u * (lane >> 4);
-        atomicAdd(&h[8 * w0 + copy], 1u);
-        atomicAdd(&h[8 * w1 + copy + 1], 1u);
-        wave_lds_order();
-        uint32_t hb = 0;  // values of width `lane` (0 beyond 32)
-        if (lane < 33) {
-            const uint4 g0 = h4[2 * lane], g1 = h4[2 * lane + 1];
-            hb = (g0.x + g0.y) + (g0.z + g0.w) + (g1.x + g1.y) + (g1.z + g1.w);
+        if (lane == 0 || (lane == 32 && liveB)) {
+            const uint64_t bk = blk + half;
+            meta[bk] = (uint8_t)(half ? bB : bA);
+            meta[nblk + bk] = (uint8_t)(half ? mB : mA);
+            meta[2 * nblk + bk] = (uint8_t)(half ? cB : cA);
         }
-        const uint64_t used = ballot(hb != 0);
-        const uint32_t maxb = 63u - (uint32_t)__builtin_clzll(used);
-        const uint32_t c = kBlock - wave_scan_incl(hb);  // values wider than b = lane
-        const uint32_t cost = kBlock * lane + c * (8u + maxb - lane);
-        const uint32_t key = wave_min(lane <= maxb ? (cost << 6) | (63u - lane) : 0xffffffffu);
-        const uint32_t best_b = 63u - (uint32_t)(key & 63u);
-        const uint32_t best_c = wave_read(c, (int)best_b);
-        if (lane == 0) {
-            meta[blk] = (uint8_t)best_b;
-            meta[nblk + blk] = (uint8_t)maxb;
-            meta[2 * nblk + blk] = (uint8_t)best_c;
-        }
-        acc_pw += 4 * best_b;
-        acc_pc += best_c;
-        acc_k += lane == maxb - best_b ? best_c : 0u;
+        acc_pw += 4 * bA + (liveB ? 4 * bB : 0u);
+        acc_pc += cA + (liveB ? cB : 0u);
+        acc_k += (lane == mA - bA ? cA : 0u) + (liveB && lane == mB - bB ? cB : 0u);
         wave_lds_order();
     }
     if (lane == 0) {
