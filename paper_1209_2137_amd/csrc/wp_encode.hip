@@ -331,76 +331,7 @@ __global__ __launch_bounds__(256) void k_bp32_pack(const uint32_t *__restrict__ 
 // width; b = 32 (no exceptions) is the one candidate outside the half's
 // lanes, rated when the block has a 32-bit value.
 
-// Deltas of a page's blocks for a wavefront that takes one block at a time,
-// lane l integers 2l and 2l+1, with D blocks' loads in flight (registers
-// indexed by compile-time slot only; the stride S, 0, 1 or 4, fixed at
-// compile time). The predecessors come from the
-// neighbouring lanes (one lane back for stride 1, two for stride 4), from
-// memory for the first lanes, 0 before the array start.
-template <int D>
-struct DeltaRing {
-    uint32_t ra[D], rb[D], rp0[D], rp1[D];
-
-    template <uint32_t S>
-    __device__ __forceinline__ void issue(int d, const uint32_t *__restrict__ x, uint64_t i0, bool live,
-                                          uint32_t lane)
-    {
-        ra[d] = rb[d] = 0;
-        if constexpr (S == 1)
-            rp1[d] = 0;
-        if constexpr (S == 4)
-            rp0[d] = rp1[d] = 0;
-        if (live) {
-            ra[d] = x[i0];
-            rb[d] = x[i0 + 1];
-            if (S == 1 && lane == 0 && i0 >= 1)
-                rp1[d] = x[i0 - 1];
-            if (S == 4 && lane < 2) {
-                rp0[d] = i0 >= 4 ? x[i0 - 4] : 0u;
-                rp1[d] = i0 >= 3 ? x[i0 - 3] : 0u;
-            }
-        }
-    }
-
-    template <uint32_t S>
-    __device__ __forceinline__ void take(int d, uint32_t lane, uint32_t &d0, uint32_t &d1) const
-    {
-        if constexpr (S == 0) {
-            d0 = ra[d];
-            d1 = rb[d];
-        } else if constexpr (S == 1) {
-            uint32_t prev = (uint32_t)__shfl_up((int)rb[d], 1, 64);
-            if (lane == 0)
-                prev = rp1[d];
-            d0 = ra[d] - prev;
-            d1 = rb[d] - ra[d];
-        } else {
-            uint32_t p0 = (uint32_t)__shfl_up((int)ra[d], 2, 64), p1 = (uint32_t)__shfl_up((int)rb[d], 2, 64);
-            if (lane < 2) {
-                p0 = rp0[d];
-                p1 = rp1[d];
-            }
-            d0 = ra[d] - p0;
-            d1 = rb[d] - p1;
-        }
-    }
-};
-constexpr int kEncDepth = 4;  // blocks in flight per wavefront in the patched encoder
-
-// Minimum over the wavefront, uniform: a DPP running minimum (rows, then
-// across rows) read from the last lane; no LDS traffic.
-__device__ __forceinline__ uint32_t wave_min(uint32_t v)
-{
-    constexpr uint32_t kId = 0xffffffffu;  // identity of min for lanes without a source
-    auto step = [&](uint32_t o) __attribute__((always_inline)) { v = o < v ? o : v; };
-    step(__builtin_amdgcn_update_dpp(kId, v, 0x111, 0xf, 0xf, false));  // row_shr:1
-    step(__builtin_amdgcn_update_dpp(kId, v, 0x112, 0xf, 0xf, false));  // row_shr:2
-    step(__builtin_amdgcn_update_dpp(kId, v, 0x114, 0xf, 0xf, false));  // row_shr:4
-    step(__builtin_amdgcn_update_dpp(kId, v, 0x118, 0xf, 0xf, false));  // row_shr:8
-    step(__builtin_amdgcn_update_dpp(kId, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
-    step(__builtin_amdgcn_update_dpp(kId, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
-    return wave_read(v, 63);
-}
+constexpr int kEncDepth = 4;  // block pairs in flight per wavefront in the patched encoder
 
 // Deltas of a pair of consecutive blocks of a page for a wavefront: lane l
 // holds integers 4l..4l+3 of the pair (lanes 0..31 the first block, 32..63
@@ -664,12 +595,8 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
     const uint32_t tail0 = hdr_w + packed_words;  // a multiple of 4
     const uint32_t tail_w = size - tail0;         // a multiple of 4
     uint32_t *const sw = sw_all[wave];
-    const uint32_t rounds = (nb + 7) / 8;
     // the wavefront takes blocks wave, wave + 8, ...; kEncDepth of them in flight
     constexpr int D = kEncDepth;
-    auto issue = [&](DeltaRing<D> &ring, int d, uint32_t t) __attribute__((always_inline)) {
-        ring.template issue<S>(d, x, (p * kFpBlocks + t) * kBlock + 2 * lane, t < nb, lane);
-    };
     auto assemble = [&](auto in_lds_tag) __attribute__((always_inline)) {
         constexpr bool IN_LDS = decltype(in_lds_tag)::value;
         uint32_t *const tw = IN_LDS ? s_tail : page + tail0;
@@ -684,51 +611,62 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
             mbytes[nb + t] = L.mb[t];
             mbytes[2 * nb + t] = L.c[t];
         }
-        DeltaRing<D> ring;
+        // a wavefront packs two blocks per pass, four integers per lane, each
+        // half of the wavefront one block into its half of the block area
+        const uint64_t pstart = p * kFpUnitInts;
+        const BufRsrc rs = make_rsrc(x + pstart, nb * kBlock * 4u);
+        const uint32_t npair = (nb + 1) / 2;
+        const uint32_t half = lane >> 5, ql = lane & 31u;
+        PairRing<D> ring;
 #pragma unroll
         for (int d = 0; d < D; ++d)
-            issue(ring, d, wave + 8u * d);
+            ring.template issue<S>(d, rs, x, pstart, wave + 8u * d, lane);
         for (uint32_t i = lane; i < 2 * kBlock; i += 64)  // the block words start cleared
             sw[i] = 0;
         wave_lds_order();
-        for (uint32_t it0 = 0; it0 < rounds; it0 += D)
+        uint32_t *const swh = sw + half * kBlock;
+        for (uint32_t q0 = wave; q0 < npair; q0 += 8u * D)
 #pragma unroll
-        for (int dd = 0; dd < D; ++dd) {
-            const uint32_t it = it0 + dd;
-            if (it >= rounds)
+        for (int d = 0; d < D; ++d) {
+            const uint32_t q = q0 + 8u * d;
+            if (q >= npair)
                 break;
-            const uint32_t t = it * 8 + wave;
+            uint32_t dl[4];
+            ring.template take<S>(d, lane, dl);
+            ring.template issue<S>(d, rs, x, pstart, q + 8u * D, lane);
+            const uint32_t t = 2u * q + half;  // the lane's block
             const bool live = t < nb;
-            uint32_t d0, d1;
-            ring.template take<S>(dd, lane, d0, d1);
-            issue(ring, dd, t + 8u * D);
             const uint4 rc = live ? L.rec[t] : make_uint4(0, 0, 0, 0);
-            const uint32_t b = rc.x & 255u;
-            if (live) {
-                or_field(sw, 2 * lane, b, d0);
-                or_field(sw, 2 * lane + 1, b, d1);
-                const bool e0 = nbits(d0) > b, e1 = nbits(d1) > b;
-                const uint64_t m0 = ballot(e0), m1 = ballot(e1);
-                const uint32_t r0 = lanes_below(m0) + lanes_below(m1);
-                const uint32_t k = rc.x >> 8;
-                for (int h = 0; h < 2; ++h) {
-                    const bool e = h ? e1 : e0;
-                    if (!e)
-                        continue;
-                    const uint32_t idx = r0 + (h ? (uint32_t)e0 : 0u);
-                    mbytes[3 * nb + rc.w + idx] = (uint8_t)(2 * lane + h);
-                    const uint32_t hv = (h ? d1 : d0) >> b;
-                    const uint32_t bit = rc.z + idx * k, s = bit & 31u;
-                    atomicOr(&tw[bit >> 5], hv << s);
-                    if (s + k > 32u)
-                        atomicOr(&tw[(bit >> 5) + 1], hv >> (32u - s));
+            const uint32_t b = rc.x & 255u, k = rc.x >> 8;
+            bool e[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                or_field(swh, 4 * ql + c, b, dl[c]);
+                e[c] = live && nbits(dl[c]) > b;
+            }
+            // exceptions of the block before this lane's: those of the lanes
+            // below it in its half, then its own earlier ones
+            const uint64_t m0 = ballot(e[0]), m1 = ballot(e[1]), m2 = ballot(e[2]), m3 = ballot(e[3]);
+            const uint32_t in_a = __builtin_popcount((uint32_t)m0) + __builtin_popcount((uint32_t)m1) +
+                                  __builtin_popcount((uint32_t)m2) + __builtin_popcount((uint32_t)m3);
+            uint32_t idx = lanes_below(m0) + lanes_below(m1) + lanes_below(m2) + lanes_below(m3) - (half ? in_a : 0u);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (e[c]) {
+                    mbytes[3 * nb + rc.w + idx] = (uint8_t)(4 * ql + c);
+                    const uint32_t hv = dl[c] >> b;
+                    const uint32_t bit = rc.z + idx * k, sh = bit & 31u;
+                    atomicOr(&tw[bit >> 5], hv << sh);
+                    if (sh + k > 32u)
+                        atomicOr(&tw[(bit >> 5) + 1], hv >> (32u - sh));
+                    ++idx;
                 }
             }
             wave_lds_order();
-            if (live && lane < b) {  // the block's 4b words as b 16-byte stores
-                uint4 *const sw4 = reinterpret_cast<uint4 *>(sw);
-                reinterpret_cast<uint4 *>(page + hdr_w + rc.y)[lane] = sw4[lane];
-                sw4[lane] = make_uint4(0, 0, 0, 0);  // cleared for the wavefront's next block
+            if (live && ql < b) {  // the block's 4b words as b 16-byte stores
+                uint4 *const sw4 = reinterpret_cast<uint4 *>(swh);
+                reinterpret_cast<uint4 *>(page + hdr_w + rc.y)[ql] = sw4[ql];
+                sw4[ql] = make_uint4(0, 0, 0, 0);  // cleared for the wavefront's next pass
             }
             wave_lds_order();
         }
