@@ -60,3 +60,16 @@ def test_host_argument_errors_need_no_gpu():
     assert L.fastpfor_decode(ctypes.c_void_p(16), 4, None, 0, None) == wp.ERR_INVALID_ARG
     # misaligned pointers
     assert L.bp_decode(ctypes.c_void_p(4), 8, ctypes.c_void_p(16), 1, None) == wp.ERR_INVALID_ARG
+
+
+def test_range_and_intersection_argument_errors_need_no_gpu():
+    L = wp.lib()
+    p16, r8 = ctypes.c_void_p(16), ctypes.c_void_p(64)
+    # key_lo > key_hi, unknown codec, null or misaligned pointers: rejected on the host
+    assert L.wp_decode_range(p16, 64, 10, wp.CODEC_BP, 5, 4, p16, r8, None) == wp.ERR_INVALID_ARG
+    assert L.wp_decode_range(p16, 64, 10, 9, 0, 4, p16, r8, None) == wp.ERR_INVALID_ARG
+    assert L.wp_decode_range(None, 64, 10, wp.CODEC_BP, 0, 4, p16, r8, None) == wp.ERR_INVALID_ARG
+    assert L.wp_decode_range(p16, 64, 10, wp.CODEC_BP, 0, 4, p16, None, None) == wp.ERR_INVALID_ARG
+    assert L.wp_decode_range(p16, 64, 10, wp.CODEC_BP, 0, 4, ctypes.c_void_p(20), r8, None) == wp.ERR_INVALID_ARG
+    assert L.wp_decode_range(p16, 64, 10, wp.CODEC_BP, 0, 4, p16, ctypes.c_void_p(68), None) == wp.ERR_INVALID_ARG
+    assert L.wp_decode_range(p16, 4, 10, wp.CODEC_BP, 0, 4, p16, r8, None) == wp.ERR_INVALID_ARG
