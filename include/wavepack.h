@@ -217,8 +217,8 @@ int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const uint32_t *
  * in [0, n]). Asynchronous on `stream`; a corrupt stream is reported
  * through wp_check (range then reads 0, 0). Returns WP_ERR_INVALID_ARG for
  * null or misaligned pointers, an unknown codec or key_lo > key_hi,
- * WP_ERR_HIP if a launch or the scratch allocation (one byte per unit,
- * the library's per-stream scratch) fails. */
+ * WP_ERR_HIP if a launch fails. Allocates nothing: two launches, the
+ * decoding (each unit checks its own stored bases) and the two searches. */
 int32_t wp_decode_range(const uint32_t *in, uint64_t in_words, uint64_t n, int32_t codec, uint32_t key_lo,
                         uint32_t key_hi, uint32_t *out, uint64_t *range, void *stream);
 

@@ -225,18 +225,36 @@ union IsectWaveLds {
     TailLds<1> tail;
 };
 
+// Whether entry e is to be decoded: its flag, or (no flags) whether its
+// values can lie in [klo, khi] -- in a non-decreasing list entry e holds
+// values in [base_e, base_{e+1}] (base_e the last of its stored bases);
+// without differential coding every entry counts.
+__device__ __forceinline__ bool entry_wanted(const uint32_t *__restrict__ in, const ListHdr &H, uint64_t e,
+                                             const uint8_t *__restrict__ flags, uint32_t klo, uint32_t khi)
+{
+    if (flags != nullptr)
+        return flags[e] != 0;
+    if (H.S == 0)
+        return true;
+    const uint32_t *const bases = in + kHdrWords + H.ndir + (H.S - 1);
+    const bool above_lo = e + 1 == H.ndir || bases[(e + 1) * H.S] >= klo;  // some value can be >= klo
+    const bool below_hi = e == 0 || bases[e * H.S] <= khi;                  // some value can be <= khi
+    return above_lo && below_hi;
+}
+
 template <bool B32, bool V>
 __global__ __launch_bounds__(256) void k_isect_decode_bp(const uint32_t *__restrict__ in, uint64_t in_words,
                                                          uint64_t n, const uint8_t *__restrict__ flags,
-                                                         uint32_t *__restrict__ out, int *__restrict__ err)
+                                                         uint32_t klo, uint32_t khi, uint32_t *__restrict__ out,
+                                                         int *__restrict__ err)
 {
     __shared__ IsectWaveLds<B32> L[4];
     ListHdr H;
     if (!check_header(in, in_words, n, B32 ? kMagicBP32 : V ? kMagicBPV : kMagicBP, kBpBlocks, H))
-        return;  // reported by k_isect_touch
+        return;  // reported by k_isect_touch or k_range_bounds
     const uint32_t wave = uniform(threadIdx.x >> 6);
     const uint64_t e = (uint64_t)blockIdx.x * 4 + wave;
-    if (e >= H.ndir || !flags[e])
+    if (e >= H.ndir || !entry_wanted(in, H, e, flags, klo, khi))
         return;
     bool ok;
     if (e < H.units)
@@ -259,14 +277,15 @@ union IsectPageLds {
 template <bool P32>
 __global__ __launch_bounds__(256) void k_isect_decode_fp(const uint32_t *__restrict__ in, uint64_t in_words,
                                                          uint64_t n, const uint8_t *__restrict__ flags,
-                                                         uint32_t *__restrict__ out, int *__restrict__ err)
+                                                         uint32_t klo, uint32_t khi, uint32_t *__restrict__ out,
+                                                         int *__restrict__ err)
 {
     __shared__ IsectPageLds L;
     ListHdr H;
     if (!check_header(in, in_words, n, P32 ? kMagicFP32 : kMagicFP, kFpBlocks, H))
-        return;  // reported by k_isect_touch
+        return;  // reported by k_isect_touch or k_range_bounds
     const uint64_t u = blockIdx.x;
-    if (u >= H.ndir || !flags[u])
+    if (u >= H.ndir || !entry_wanted(in, H, u, flags, klo, khi))
         return;
     bool ok;
     if (u == H.units) {
@@ -340,32 +359,10 @@ __global__ __launch_bounds__(kIsThreads) void k_isect_flag_dir(const uint32_t *_
 }
 
 // ---------------------------------------------------------------------
-// Random access by key: the entries whose values can lie in [klo, khi]. In
-// a non-decreasing list entry e holds values in [base_e, base_{e+1}] (equal
-// values may straddle entries); without differential coding every entry
-// counts. Every entry in which one of the two searches below ends is among
-// them: the search for v ends in the entry with base_e < v <= base_{e+1}.
-__global__ __launch_bounds__(256) void k_range_touch(const uint32_t *__restrict__ in, uint64_t in_words, uint64_t n,
-                                                     int32_t codec, uint32_t klo, uint32_t khi,
-                                                     uint8_t *__restrict__ flags, int *__restrict__ err)
-{
-    DirView D;
-    if (!dir_view(in, in_words, n, codec, D)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0)
-            *err = kErrCorrupt;
-        return;
-    }
-    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= D.H.ndir)
-        return;
-    bool hit = true;
-    if (D.H.S != 0) {
-        const bool above_lo = e + 1 == D.H.ndir || D.base(e + 1) >= klo;  // some value of e can be >= klo
-        const bool below_hi = e == 0 || D.base(e) <= khi;                  // some value of e can be <= khi
-        hit = above_lo && below_hi;
-    }
-    flags[e] = hit ? 1u : 0u;
-}
+// Random access by key. The decode kernels above take the entries whose
+// values can lie in [klo, khi] (entry_wanted); every entry in which one of
+// the two searches below ends is among them: the search for v ends in the
+// entry with base_e < v <= base_{e+1}.
 
 // The index range [i0, i1) of the values in [klo, khi]: wavefront 0 finds
 // the first value >= klo, wavefront 1 the first value > khi, each by the
@@ -494,19 +491,19 @@ extern "C" int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const
                        b_words, nb, codec, S.touched, ds->err);
     if (codec == WP_CODEC_BP)
         hipLaunchKernelGGL((k_isect_decode_bp<false, false>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
-                           b_comp, b_words, nb, S.touched, b_work, ds->err);
+                           b_comp, b_words, nb, S.touched, 0u, 0u, b_work, ds->err);
     else if (codec == WP_CODEC_BPV)
         hipLaunchKernelGGL((k_isect_decode_bp<false, true>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
-                           b_comp, b_words, nb, S.touched, b_work, ds->err);
+                           b_comp, b_words, nb, S.touched, 0u, 0u, b_work, ds->err);
     else if (codec == WP_CODEC_BP32)
         hipLaunchKernelGGL((k_isect_decode_bp<true, false>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
-                           b_comp, b_words, nb, S.touched, b_work, ds->err);
+                           b_comp, b_words, nb, S.touched, 0u, 0u, b_work, ds->err);
     else if (codec == WP_CODEC_FP32)
         hipLaunchKernelGGL(k_isect_decode_fp<true>, dim3((uint32_t)nent), dim3(256), 0, st, b_comp, b_words, nb,
-                           S.touched, b_work, ds->err);
+                           S.touched, 0u, 0u, b_work, ds->err);
     else
         hipLaunchKernelGGL(k_isect_decode_fp<false>, dim3((uint32_t)nent), dim3(256), 0, st, b_comp, b_words, nb,
-                           S.touched, b_work, ds->err);
+                           S.touched, 0u, 0u, b_work, ds->err);
     hipLaunchKernelGGL(k_isect_flag_dir, dim3((uint32_t)tiles), dim3(kIsThreads), 0, st, a, na, b_comp, b_words, nb,
                        codec, b_work, S.flags, S.counts);
     if (launch_inclusive_scan(S.counts, tiles, S.status, st) != WP_OK)
@@ -536,26 +533,23 @@ extern "C" int32_t wp_decode_range(const uint32_t *in, uint64_t in_words, uint64
     if (nent > 0x7FFFFFFFull)
         return WP_ERR_INVALID_ARG;
     if (nent > 0) {
-        uint8_t *flags = static_cast<uint8_t *>(stream_scratch(st, nent));
-        if (flags == nullptr)
-            return WP_ERR_HIP;
-        hipLaunchKernelGGL(k_range_touch, dim3((uint32_t)((nent + 255) / 256)), dim3(256), 0, st, in, in_words, n,
-                           codec, key_lo, key_hi, flags, ds->err);
+        // no flags: each entry's own bases decide (entry_wanted)
+        const uint8_t *const nf = nullptr;
         if (codec == WP_CODEC_BP)
             hipLaunchKernelGGL((k_isect_decode_bp<false, false>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
-                               in, in_words, n, flags, out, ds->err);
+                               in, in_words, n, nf, key_lo, key_hi, out, ds->err);
         else if (codec == WP_CODEC_BPV)
             hipLaunchKernelGGL((k_isect_decode_bp<false, true>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
-                               in, in_words, n, flags, out, ds->err);
+                               in, in_words, n, nf, key_lo, key_hi, out, ds->err);
         else if (codec == WP_CODEC_BP32)
             hipLaunchKernelGGL((k_isect_decode_bp<true, false>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
-                               in, in_words, n, flags, out, ds->err);
+                               in, in_words, n, nf, key_lo, key_hi, out, ds->err);
         else if (codec == WP_CODEC_FP32)
-            hipLaunchKernelGGL(k_isect_decode_fp<true>, dim3((uint32_t)nent), dim3(256), 0, st, in, in_words, n,
-                               flags, out, ds->err);
+            hipLaunchKernelGGL(k_isect_decode_fp<true>, dim3((uint32_t)nent), dim3(256), 0, st, in, in_words, n, nf,
+                               key_lo, key_hi, out, ds->err);
         else
-            hipLaunchKernelGGL(k_isect_decode_fp<false>, dim3((uint32_t)nent), dim3(256), 0, st, in, in_words, n,
-                               flags, out, ds->err);
+            hipLaunchKernelGGL(k_isect_decode_fp<false>, dim3((uint32_t)nent), dim3(256), 0, st, in, in_words, n, nf,
+                               key_lo, key_hi, out, ds->err);
     }
     hipLaunchKernelGGL(k_range_bounds, dim3(1), dim3(128), 0, st, in, in_words, n, codec, key_lo, key_hi, out,
                        range, ds->err);
