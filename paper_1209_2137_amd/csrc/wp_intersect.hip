@@ -389,7 +389,7 @@ __global__ __launch_bounds__(128) void k_range_bounds(const uint32_t *__restrict
         } else {
             // entry: the last e whose base is below v (entry 0 has no base)
             const uint32_t *bases = in + kHdrWords + D.H.ndir + (D.H.S - 1);
-            const uint64_t e = wave_lower_bound(bases, 1, D.H.ndir, v, D.H.S) - 1;
+            const uint64_t e = D.H.ndir > 1 ? wave_lower_bound(bases, 1, D.H.ndir, v, D.H.S) - 1 : 0;
             const uint64_t lo = D.first_int(e);
             uint64_t hi = e + 1 < D.H.ndir ? D.first_int(e + 1) : n;
             hi = hi < n ? hi : n;
