@@ -151,8 +151,8 @@ __global__ __launch_bounds__(kIsThreads) void k_isect_write(const uint32_t *__re
 // increasing list, values in (base_e, base_{e+1}] where base_e is the last
 // of the entry's stored bases (the value just before the entry); entry 0 has
 // no lower bound and the last entry no upper bound. A stream without
-// differential coding (stride 0) has no such bounds: every entry counts as
-// touched and lookups search the whole decoded list.
+// differential coding (stride 0) has no such bounds: every entry is
+// decoded and lookups search the whole decoded list.
 
 struct DirView {
     const uint32_t *in;
@@ -183,33 +183,7 @@ __device__ __forceinline__ bool dir_view(const uint32_t *in, uint64_t in_words, 
     return check_header(in, in_words, n, magic, D.per, D.H);
 }
 
-// flags[e] = 1 if some element of a lies in entry e's value range
-__global__ __launch_bounds__(256) void k_isect_touch(const uint32_t *__restrict__ a, uint64_t na,
-                                                     const uint32_t *__restrict__ in, uint64_t in_words, uint64_t n,
-                                                     int32_t codec, uint8_t *__restrict__ flags,
-                                                     int *__restrict__ err)
-{
-    DirView D;
-    if (!dir_view(in, in_words, n, codec, D)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0)
-            *err = kErrCorrupt;
-        return;
-    }
-    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= D.H.ndir)
-        return;
-    bool hit = true;
-    if (D.H.S != 0) {
-        // first element of a above the lower bound, and whether it is within the upper
-        const uint64_t i = e == 0 ? 0 : lower_bound(a, 0, na, D.base(e) + 1u);
-        hit = i < na && (e + 1 == D.H.ndir || a[i] <= D.base(e + 1));
-        if (e > 0 && D.base(e) == 0xFFFFFFFFu)
-            hit = false;  // nothing can lie above the largest value
-    }
-    flags[e] = hit ? 1u : 0u;
-}
-
-// Decodes the flagged entries of a binary-packing (SIMD-BP128 or BP32)
+// Decodes the wanted entries of a binary-packing (SIMD-BP128 or BP32)
 // stream into out (one wavefront per unit; the tail entry by a wavefront of
 // its own).
 template <uint32_t S, bool B32, bool V>
@@ -225,36 +199,46 @@ union IsectWaveLds {
     TailLds<1> tail;
 };
 
-// Whether entry e is to be decoded: its flag, or (no flags) whether its
-// values can lie in [klo, khi] -- in a non-decreasing list entry e holds
-// values in [base_e, base_{e+1}] (base_e the last of its stored bases);
-// without differential coding every entry counts.
+// Whether entry e is to be decoded (uniform over the wavefront). With a
+// short list a (strictly increasing, na values): whether some element of a
+// lies in the entry's values, (base_e, base_{e+1}] for a strictly
+// increasing list, found by a wavefront search of a. Without it: whether
+// the entry's values can lie in [klo, khi], [base_e, base_{e+1}] for a
+// non-decreasing list. base_e is the last of the entry's stored bases (the
+// value just before it); entry 0 has no lower bound and the last entry no
+// upper bound; without differential coding every entry counts.
 __device__ __forceinline__ bool entry_wanted(const uint32_t *__restrict__ in, const ListHdr &H, uint64_t e,
-                                             const uint8_t *__restrict__ flags, uint32_t klo, uint32_t khi)
+                                             const uint32_t *__restrict__ a, uint64_t na, uint32_t klo,
+                                             uint32_t khi)
 {
-    if (flags != nullptr)
-        return flags[e] != 0;
     if (H.S == 0)
         return true;
     const uint32_t *const bases = in + kHdrWords + H.ndir + (H.S - 1);
-    const bool above_lo = e + 1 == H.ndir || bases[(e + 1) * H.S] >= klo;  // some value can be >= klo
-    const bool below_hi = e == 0 || bases[e * H.S] <= khi;                  // some value can be <= khi
+    const bool last = e + 1 == H.ndir;
+    if (a != nullptr) {
+        if (e > 0 && bases[e * H.S] == 0xFFFFFFFFu)
+            return false;  // nothing can lie above the largest value
+        const uint64_t i = e == 0 ? 0 : wave_lower_bound(a, 0, na, bases[e * H.S] + 1u);
+        return i < na && (last || a[i] <= bases[(e + 1) * H.S]);
+    }
+    const bool above_lo = last || bases[(e + 1) * H.S] >= klo;  // some value can be >= klo
+    const bool below_hi = e == 0 || bases[e * H.S] <= khi;      // some value can be <= khi
     return above_lo && below_hi;
 }
 
 template <bool B32, bool V>
 __global__ __launch_bounds__(256) void k_isect_decode_bp(const uint32_t *__restrict__ in, uint64_t in_words,
-                                                         uint64_t n, const uint8_t *__restrict__ flags,
+                                                         uint64_t n, const uint32_t *__restrict__ a, uint64_t na,
                                                          uint32_t klo, uint32_t khi, uint32_t *__restrict__ out,
                                                          int *__restrict__ err)
 {
     __shared__ IsectWaveLds<B32> L[4];
     ListHdr H;
     if (!check_header(in, in_words, n, B32 ? kMagicBP32 : V ? kMagicBPV : kMagicBP, kBpBlocks, H))
-        return;  // reported by k_isect_touch or k_range_bounds
+        return;  // reported by k_isect_flag_dir or k_range_bounds
     const uint32_t wave = uniform(threadIdx.x >> 6);
     const uint64_t e = (uint64_t)blockIdx.x * 4 + wave;
-    if (e >= H.ndir || !entry_wanted(in, H, e, flags, klo, khi))
+    if (e >= H.ndir || !entry_wanted(in, H, e, a, na, klo, khi))
         return;
     bool ok;
     if (e < H.units)
@@ -272,20 +256,20 @@ union IsectPageLds {
     TailLds<4> tail;
 };
 
-// Decodes the flagged entries of a patched-page stream (one workgroup per
+// Decodes the wanted entries of a patched-page stream (one workgroup per
 // page; P32: exception arrays padded to 32 values).
 template <bool P32>
 __global__ __launch_bounds__(256) void k_isect_decode_fp(const uint32_t *__restrict__ in, uint64_t in_words,
-                                                         uint64_t n, const uint8_t *__restrict__ flags,
+                                                         uint64_t n, const uint32_t *__restrict__ a, uint64_t na,
                                                          uint32_t klo, uint32_t khi, uint32_t *__restrict__ out,
                                                          int *__restrict__ err)
 {
     __shared__ IsectPageLds L;
     ListHdr H;
     if (!check_header(in, in_words, n, P32 ? kMagicFP32 : kMagicFP, kFpBlocks, H))
-        return;  // reported by k_isect_touch or k_range_bounds
+        return;  // reported by k_isect_flag_dir or k_range_bounds
     const uint64_t u = blockIdx.x;
-    if (u >= H.ndir || !entry_wanted(in, H, u, flags, klo, khi))
+    if (u >= H.ndir || !entry_wanted(in, H, u, a, na, klo, khi))
         return;
     bool ok;
     if (u == H.units) {
@@ -314,11 +298,13 @@ __global__ __launch_bounds__(kIsThreads) void k_isect_flag_dir(const uint32_t *_
                                                                uint64_t n, int32_t codec,
                                                                const uint32_t *__restrict__ b,
                                                                uint8_t *__restrict__ flags,
-                                                               uint32_t *__restrict__ counts)
+                                                               uint32_t *__restrict__ counts, int *__restrict__ err)
 {
     __shared__ uint32_t s_part[kIsThreads / 64];
     DirView D;
     const bool valid = dir_view(in, in_words, n, codec, D);
+    if (!valid && blockIdx.x == 0 && threadIdx.x == 0)
+        *err = kErrCorrupt;
     const uint64_t t0 = (uint64_t)blockIdx.x * kIsTile;
     const uint64_t i0 = t0 + (uint64_t)threadIdx.x * kIsPer;
     uint32_t cnt = 0;
@@ -410,27 +396,24 @@ __global__ void k_isect_none(uint64_t *__restrict__ out_count)
 
 using namespace wp;
 
-// scratch: scan status | tile counts | one flag byte per element of a |
-// one flag byte per directory entry of the compressed list
+// scratch: scan status | tile counts | one flag byte per element of a
 struct IsectScratch {
     uint64_t *status;
     uint32_t *counts;
-    uint8_t *flags, *touched;
+    uint8_t *flags;
 };
 
-static bool isect_scratch(hipStream_t st, uint64_t tiles, uint64_t na, uint64_t nent, IsectScratch &S)
+static bool isect_scratch(hipStream_t st, uint64_t tiles, uint64_t na, IsectScratch &S)
 {
     const uint64_t status_bytes = scan_status_words(tiles) * sizeof(uint64_t);
     const uint64_t counts_off = (status_bytes + 255) & ~255ull;
     const uint64_t flags_off = (counts_off + tiles * sizeof(uint32_t) + 255) & ~255ull;
-    const uint64_t touched_off = (flags_off + na + 255) & ~255ull;
-    char *scr = static_cast<char *>(stream_scratch(st, touched_off + nent + 1));
+    char *scr = static_cast<char *>(stream_scratch(st, flags_off + na + 1));
     if (scr == nullptr)
         return false;
     S.status = reinterpret_cast<uint64_t *>(scr);
     S.counts = reinterpret_cast<uint32_t *>(scr + counts_off);
     S.flags = reinterpret_cast<uint8_t *>(scr + flags_off);
-    S.touched = reinterpret_cast<uint8_t *>(scr + touched_off);
     return true;
 }
 
@@ -448,7 +431,7 @@ extern "C" int32_t wp_intersect(const uint32_t *a, uint64_t na, const uint32_t *
     }
     const uint64_t tiles = (na + kIsTile - 1) / kIsTile;
     IsectScratch S;
-    if (!isect_scratch(st, tiles, na, 0, S))
+    if (!isect_scratch(st, tiles, na, S))
         return WP_ERR_HIP;
     hipLaunchKernelGGL(k_isect_flag, dim3((uint32_t)tiles), dim3(kIsThreads), 0, st, a, na, b, nb, S.flags,
                        S.counts);
@@ -485,27 +468,25 @@ extern "C" int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const
     const uint64_t nent = (nfull + per - 1) / per + ((nb % kBlock) ? 1 : 0);
     const uint64_t tiles = (na + kIsTile - 1) / kIsTile;
     IsectScratch S;
-    if (nent > 0x7FFFFFFFull || !isect_scratch(st, tiles, na, nent, S))
+    if (nent > 0x7FFFFFFFull || !isect_scratch(st, tiles, na, S))
         return WP_ERR_HIP;
-    hipLaunchKernelGGL(k_isect_touch, dim3((uint32_t)((nent + 255) / 256)), dim3(256), 0, st, a, na, b_comp,
-                       b_words, nb, codec, S.touched, ds->err);
     if (codec == WP_CODEC_BP)
         hipLaunchKernelGGL((k_isect_decode_bp<false, false>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
-                           b_comp, b_words, nb, S.touched, 0u, 0u, b_work, ds->err);
+                           b_comp, b_words, nb, a, na, 0u, 0u, b_work, ds->err);
     else if (codec == WP_CODEC_BPV)
         hipLaunchKernelGGL((k_isect_decode_bp<false, true>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
-                           b_comp, b_words, nb, S.touched, 0u, 0u, b_work, ds->err);
+                           b_comp, b_words, nb, a, na, 0u, 0u, b_work, ds->err);
     else if (codec == WP_CODEC_BP32)
         hipLaunchKernelGGL((k_isect_decode_bp<true, false>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
-                           b_comp, b_words, nb, S.touched, 0u, 0u, b_work, ds->err);
+                           b_comp, b_words, nb, a, na, 0u, 0u, b_work, ds->err);
     else if (codec == WP_CODEC_FP32)
         hipLaunchKernelGGL(k_isect_decode_fp<true>, dim3((uint32_t)nent), dim3(256), 0, st, b_comp, b_words, nb,
-                           S.touched, 0u, 0u, b_work, ds->err);
+                           a, na, 0u, 0u, b_work, ds->err);
     else
         hipLaunchKernelGGL(k_isect_decode_fp<false>, dim3((uint32_t)nent), dim3(256), 0, st, b_comp, b_words, nb,
-                           S.touched, 0u, 0u, b_work, ds->err);
+                           a, na, 0u, 0u, b_work, ds->err);
     hipLaunchKernelGGL(k_isect_flag_dir, dim3((uint32_t)tiles), dim3(kIsThreads), 0, st, a, na, b_comp, b_words, nb,
-                       codec, b_work, S.flags, S.counts);
+                       codec, b_work, S.flags, S.counts, ds->err);
     if (launch_inclusive_scan(S.counts, tiles, S.status, st) != WP_OK)
         return WP_ERR_HIP;
     hipLaunchKernelGGL(k_isect_write, dim3((uint32_t)tiles), dim3(kIsThreads), 0, st, a, na, S.flags, S.counts, out,
@@ -533,23 +514,23 @@ extern "C" int32_t wp_decode_range(const uint32_t *in, uint64_t in_words, uint64
     if (nent > 0x7FFFFFFFull)
         return WP_ERR_INVALID_ARG;
     if (nent > 0) {
-        // no flags: each entry's own bases decide (entry_wanted)
-        const uint8_t *const nf = nullptr;
+        // no short list: each entry's own bases against the key range decide (entry_wanted)
+        const uint32_t *const nf = nullptr;
         if (codec == WP_CODEC_BP)
             hipLaunchKernelGGL((k_isect_decode_bp<false, false>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
-                               in, in_words, n, nf, key_lo, key_hi, out, ds->err);
+                               in, in_words, n, nf, 0, key_lo, key_hi, out, ds->err);
         else if (codec == WP_CODEC_BPV)
             hipLaunchKernelGGL((k_isect_decode_bp<false, true>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
-                               in, in_words, n, nf, key_lo, key_hi, out, ds->err);
+                               in, in_words, n, nf, 0, key_lo, key_hi, out, ds->err);
         else if (codec == WP_CODEC_BP32)
             hipLaunchKernelGGL((k_isect_decode_bp<true, false>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
-                               in, in_words, n, nf, key_lo, key_hi, out, ds->err);
+                               in, in_words, n, nf, 0, key_lo, key_hi, out, ds->err);
         else if (codec == WP_CODEC_FP32)
             hipLaunchKernelGGL(k_isect_decode_fp<true>, dim3((uint32_t)nent), dim3(256), 0, st, in, in_words, n, nf,
-                               key_lo, key_hi, out, ds->err);
+                               0, key_lo, key_hi, out, ds->err);
         else
             hipLaunchKernelGGL(k_isect_decode_fp<false>, dim3((uint32_t)nent), dim3(256), 0, st, in, in_words, n, nf,
-                               key_lo, key_hi, out, ds->err);
+                               0, key_lo, key_hi, out, ds->err);
     }
     hipLaunchKernelGGL(k_range_bounds, dim3(1), dim3(128), 0, st, in, in_words, n, codec, key_lo, key_hi, out,
                        range, ds->err);
