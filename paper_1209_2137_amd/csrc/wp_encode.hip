@@ -11,6 +11,7 @@
 // Bits are OR-ed into place (LDS atomics for a block's packed words,
 // device atomics for a page's exception arrays, after the region has been
 // cleared), so the order in which lanes write never matters.
+#include <cstddef>
 #include <type_traits>
 
 #include "wp_device.hpp"
@@ -510,7 +511,15 @@ __global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__
 }
 
 // LDS staging of a page's metadata and exception arrays in k_fp_pack
-constexpr uint32_t kPackTailWords = 8192;
+// k_fp_pack's LDS, one buffer: the wavefronts' block areas (8 KB), then the
+// page's metadata and exception arrays, whose area runs on over the page
+// tables of FpLds (dead once the block records exist) up to the records:
+// 51 KB in all, three workgroups per compute unit
+constexpr uint32_t kPackSwBytes = 8u * 2u * kBlock * 4u;
+constexpr uint32_t kPackTailLead = 16384;
+constexpr uint32_t kPackTailWords = (kPackTailLead + (uint32_t)offsetof(FpLds<8>, rec)) / 4u;
+static_assert(kPackTailWords >= 8192, "the metadata and exception area holds 32 KB");
+static_assert((kPackSwBytes + kPackTailLead) % 16 == 0, "the page tables stay 16-byte aligned");
 
 template <bool P32, uint32_t S>
 __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x, uint64_t n,
@@ -518,10 +527,12 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
                                                  const uint32_t *__restrict__ incl, uint32_t dir_end,
                                                  uint32_t *__restrict__ out)
 {
-    __shared__ FpLds<8> L;
-    __shared__ __align__(16) uint32_t sw_all[8][2 * kBlock];  // a wavefront's packed words (L.xp overlays the tables)
-    __shared__ __align__(16) uint32_t s_tail[kPackTailWords];
+    __shared__ __align__(16) uint8_t s_raw[kPackSwBytes + kPackTailLead + sizeof(FpLds<8>)];
+    uint32_t *const sw_all = reinterpret_cast<uint32_t *>(s_raw);  // 2 * kBlock words per wavefront
+    uint32_t *const s_tail = reinterpret_cast<uint32_t *>(s_raw + kPackSwBytes);
+    FpLds<8> &L = *reinterpret_cast<FpLds<8> *>(s_raw + kPackSwBytes + kPackTailLead);
     constexpr int T = 512;
+    static_assert(T == kFpBlocks, "one block's metadata per thread");
     const uint64_t p = blockIdx.x;
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = lane_id();
@@ -529,12 +540,14 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
     const uint64_t nfull = n / kBlock;
     const uint64_t left = nfull - p * kFpBlocks;
     const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
-    for (uint32_t t = tid; t < kFpBlocks; t += T) {
-        const bool in = t < nb;
-        L.b[t] = in ? meta[p * kFpBlocks + t] : 0;
-        L.mb[t] = in ? meta[nblk + p * kFpBlocks + t] : 0;
-        L.c[t] = in ? meta[2 * nblk + p * kFpBlocks + t] : 0;
-    }
+    // block tid's metadata, kept in registers for the metadata bytes
+    const bool my_in = tid < nb;
+    const uint8_t my_b = my_in ? meta[p * kFpBlocks + tid] : 0;
+    const uint8_t my_mb = my_in ? meta[nblk + p * kFpBlocks + tid] : 0;
+    const uint8_t my_c = my_in ? meta[2 * nblk + p * kFpBlocks + tid] : 0;
+    L.b[tid] = my_b;
+    L.mb[tid] = my_mb;
+    L.c[tid] = my_c;
     for (uint32_t i = tid; i < 8 * 33; i += T)
         (&L.ktot[0][0])[i] = 0;
     if (tid < 33)
@@ -594,7 +607,7 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
     // clearing it (device atomics).
     const uint32_t tail0 = hdr_w + packed_words;  // a multiple of 4
     const uint32_t tail_w = size - tail0;         // a multiple of 4
-    uint32_t *const sw = sw_all[wave];
+    uint32_t *const sw = sw_all + wave * (2 * kBlock);
     // the wavefront takes blocks wave, wave + 8, ...; kEncDepth of them in flight
     constexpr int D = kEncDepth;
     auto assemble = [&](auto in_lds_tag) __attribute__((always_inline)) {
@@ -606,10 +619,10 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
             __threadfence();
         __syncthreads();
         uint8_t *const mbytes = reinterpret_cast<uint8_t *>(tw);
-        for (uint32_t t = tid; t < nb; t += T) {
-            mbytes[t] = L.b[t];
-            mbytes[nb + t] = L.mb[t];
-            mbytes[2 * nb + t] = L.c[t];
+        if (my_in) {
+            mbytes[tid] = my_b;
+            mbytes[nb + tid] = my_mb;
+            mbytes[2 * nb + tid] = my_c;
         }
         // a wavefront packs two blocks per pass, four integers per lane, each
         // half of the wavefront one block into its half of the block area
@@ -678,6 +691,7 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
                 dst[i] = src[i];
         }
     };
+    __syncthreads();  // the page tables are read; the metadata area may overwrite them
     if (tail_w <= kPackTailWords)
         assemble(std::true_type{});
     else
