@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 OK, ERR_ARG, ERR_CAP, ERR_CORRUPT = 0, -1, -2, -3
-CODEC_BP, CODEC_FP, CODEC_BP32, CODEC_FP32, CODEC_BPV = 0, 1, 2, 3, 4
+CODEC_BP, CODEC_FP, CODEC_BP32, CODEC_FP32, CODEC_BPV, CODEC_SP = 0, 1, 2, 3, 4, 5
 
 
 def build() -> str:
@@ -62,13 +62,20 @@ def _load():
     lib.oracle_max_words.argtypes = [ctypes.c_int, u64]
     lib.oracle_max_words.restype = u64
     for f in (lib.oracle_bp_encode, lib.oracle_fp_encode, lib.oracle_bp32_encode, lib.oracle_fp32_encode,
-              lib.oracle_bpv_encode):
+              lib.oracle_bpv_encode, lib.oracle_sp_encode):
         f.argtypes = [u32p, u64, ctypes.c_int, u32p, u64]
         f.restype = ctypes.c_int64
     for f in (lib.oracle_bp_decode, lib.oracle_fp_decode, lib.oracle_bp32_decode, lib.oracle_fp32_decode,
-              lib.oracle_bpv_decode):
+              lib.oracle_bpv_decode, lib.oracle_sp_decode):
         f.argtypes = [u32p, u64, u32p, u64]
         f.restype = ctypes.c_int
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.oracle_s8_mode.argtypes = [ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]
+    lib.oracle_s8_mode.restype = None
+    lib.oracle_s8_encode.argtypes = [u32p, u64, u64p]
+    lib.oracle_s8_encode.restype = u64
+    lib.oracle_s8_decode.argtypes = [u64p, u64, u32p, u64]
+    lib.oracle_s8_decode.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -267,3 +274,45 @@ def intersect(a, b) -> np.ndarray:
     out = np.zeros(max(1, min(a.size, b.size)), dtype=np.uint32)
     k = _load().oracle_intersect(_p32(a), a.size, _p32(b), b.size, _p32(out))
     return out[:k].copy()
+
+
+def sp_encode(x, stride: int = 1) -> np.ndarray:
+    """SimplePFOR stream of x: FastPFOR pages whose exceptions' high parts
+    are one Simple-8b array per page."""
+    return _encode(_load().oracle_sp_encode, CODEC_SP, x, stride)
+
+
+def sp_decode(stream, n: int) -> np.ndarray:
+    rc, out = _decode(_load().oracle_sp_decode, stream, n)
+    if rc != OK:
+        raise ValueError(f"oracle decode failed: {rc}")
+    return out
+
+
+def sp_decode_rc(stream, n: int) -> int:
+    return _decode(_load().oracle_sp_decode, stream, n)[0]
+
+
+def s8_mode(selector: int):
+    """(integers per word, bits per integer) of a Simple-8b selector."""
+    c, b = ctypes.c_uint32(), ctypes.c_uint32()
+    _load().oracle_s8_mode(selector, ctypes.byref(c), ctypes.byref(b))
+    return int(c.value), int(b.value)
+
+
+def s8_encode(v) -> np.ndarray:
+    """Simple-8b words (uint64) of the uint32 values v, greedy."""
+    v = _u32(v)
+    out = np.zeros(max(v.size, 1), dtype=np.uint64)
+    src = v if v.size else np.zeros(1, np.uint32)
+    w = _load().oracle_s8_encode(_p32(src), v.size, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    return out[:w].copy()
+
+
+def s8_decode(words, n: int):
+    """(count or negative error, values) of Simple-8b words holding at most n values."""
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    out = np.zeros(max(n, 1), dtype=np.uint32)
+    src = w if w.size else np.zeros(1, np.uint64)
+    k = _load().oracle_s8_decode(src.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), w.size, _p32(out), n)
+    return int(k), out[:max(k, 0)]

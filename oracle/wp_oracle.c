@@ -28,7 +28,8 @@
  *                     patched (FastPFOR) page of up to 512 blocks: see
  *                     oracle_fp_encode; exception arrays padded to 128
  *                     values (SIMD-FastPFOR) or to 32 (FastPFOR,
- *                     oracle_fp32_encode)
+ *                     oracle_fp32_encode); SimplePFOR pages hold one
+ *                     Simple-8b array instead (oracle_sp_encode)
  *   tail              Variable Byte of the last n mod 128 deltas,
  *                     zero-padded to a word
  */
@@ -44,6 +45,7 @@
 #define OMAGIC_BP32 0x32335057u /* "WP32" */
 #define OMAGIC_FP32 0x33465057u /* "WPF3" */
 #define OMAGIC_BPV 0x31565057u  /* "WPV1" */
+#define OMAGIC_SP 0x31535057u   /* "WPS1" */
 #define OB32 32u               /* BP32 block: 32 integers (Section 6.2) */
 
 enum { O_OK = 0, O_ERR_ARG = -1, O_ERR_CAP = -2, O_ERR_CORRUPT = -3 };
@@ -249,14 +251,18 @@ static uint64_t o_pad4(uint64_t w) { return (w + 3u) & ~(uint64_t)3u; }
 static uint64_t o_units(int codec, uint64_t n)
 {
     uint64_t nfull = n / OB;
-    uint64_t per = (codec == 1 || codec == 3) ? OFP_BLOCKS : OBP_BLOCKS;
+    uint64_t per = (codec == 1 || codec == 3 || codec == 5) ? OFP_BLOCKS : OBP_BLOCKS;
     return (nfull + per - 1) / per;
 }
 
 static uint32_t o_magic(int codec)
 {
-    return codec == 0 ? OMAGIC_BP : codec == 1 ? OMAGIC_FP : codec == 2 ? OMAGIC_BP32 : codec == 3 ? OMAGIC_FP32
-                                                                                       : OMAGIC_BPV;
+    return codec == 0   ? OMAGIC_BP
+           : codec == 1 ? OMAGIC_FP
+           : codec == 2 ? OMAGIC_BP32
+           : codec == 3 ? OMAGIC_FP32
+           : codec == 4 ? OMAGIC_BPV
+                        : OMAGIC_SP;
 }
 
 /* Worst-case stream size in words, computed from the layout. */
@@ -272,6 +278,11 @@ uint64_t oracle_max_words(int codec, uint64_t n)
         /* a descriptor word per 128 values, every block at 32 bits, and at
          * most 3 words of padding per unit */
         words += units * 3 + nfull * (1 + OB);
+    } else if (codec == 5) {
+        /* per page: 4 header words and 3 words of padding; packed <= 128
+         * words per block; metadata <= (3 + 128) bytes per block (+16 B
+         * padding); at most one 64-bit Simple-8b word per exception */
+        words += units * (4 + 3 + 4) + nfull * (OB + (3 + OB) / 4 + 1 + 2 * OB);
     } else {
         /* per page: header <= 36 words; packed <= 128 words per block;
          * metadata <= (3 + 127) bytes per block (+16 B padding); every array
@@ -486,6 +497,143 @@ static uint64_t o_fp_page(const uint32_t *d, uint64_t nblocks, uint32_t *out, ui
     return p;
 }
 
+/* ---- Section 2 (the Simple family), Simple-8b: 64-bit words, a 4-bit
+ * selector and 60 data bits holding `count` integers of `bits` bits each,
+ * the modes of the paper's Simple-8b table (selectors 0 and 1: runs of 240
+ * and 120 zeros, no data bits). Encoding is greedy: for the next word the
+ * selectors are tried from 0 upward and the first one whose count of
+ * integers is still available and fits in its bits is taken (selector 15,
+ * one integer of up to 60 bits, always fits a 32-bit value). Readings:
+ * the selector is the word's top four bits, integer j of a word sits at
+ * bits [j*bits, (j+1)*bits), and a selector needs `count` integers left
+ * (no padding of the last word). */
+static const uint32_t O_S8_COUNT[16] = {240, 120, 60, 30, 20, 15, 12, 10, 8, 7, 6, 5, 4, 3, 2, 1};
+static const uint32_t O_S8_BITS[16] = {0, 0, 1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 15, 20, 30, 60};
+
+void oracle_s8_mode(uint32_t sel, uint32_t *count, uint32_t *bits)
+{
+    *count = O_S8_COUNT[sel & 15u];
+    *bits = O_S8_BITS[sel & 15u];
+}
+
+uint64_t oracle_s8_encode(const uint32_t *v, uint64_t n, uint64_t *out)
+{
+    uint64_t i = 0, w = 0;
+    while (i < n) {
+        uint32_t sel = 0;
+        for (; sel < 16; sel++) {
+            uint64_t cnt = O_S8_COUNT[sel];
+            uint32_t bits = O_S8_BITS[sel];
+            if (cnt > n - i)
+                continue;
+            int fits = 1;
+            for (uint64_t j = 0; j < cnt && fits; j++)
+                fits = bits >= 32 || (v[i + j] >> bits) == 0;
+            if (fits)
+                break;
+        }
+        uint64_t word = (uint64_t)sel << 60;
+        for (uint64_t j = 0; j < O_S8_COUNT[sel] && O_S8_BITS[sel] > 0; j++)
+            word |= (uint64_t)v[i + j] << (j * O_S8_BITS[sel]);
+        out[w++] = word;
+        i += O_S8_COUNT[sel];
+    }
+    return w;
+}
+
+/* Decodes nwords words into at most n integers; returns the number of
+ * integers, or O_ERR_CORRUPT if they exceed n or a value exceeds 32 bits. */
+int64_t oracle_s8_decode(const uint64_t *in, uint64_t nwords, uint32_t *v, uint64_t n)
+{
+    uint64_t k = 0;
+    for (uint64_t w = 0; w < nwords; w++) {
+        uint32_t sel = (uint32_t)(in[w] >> 60), cnt = O_S8_COUNT[sel], bits = O_S8_BITS[sel];
+        if (cnt > n - k)
+            return O_ERR_CORRUPT;
+        for (uint32_t j = 0; j < cnt; j++) {
+            uint64_t x = bits ? (in[w] >> (j * bits)) & ((1ull << bits) - 1u) : 0u;
+            if (x >> 32)
+                return O_ERR_CORRUPT;
+            v[k++] = (uint32_t)x;
+        }
+    }
+    return (int64_t)k;
+}
+
+/* ---- Section 5, SimplePFOR: the pages of FastPFOR (the same widths by
+ * the same cost rule, the same packed values, positions and metadata),
+ * with the exceptions' high parts (value >> b) collected over the whole
+ * page in block order and coded once with Simple-8b instead of one packed
+ * array per width. Page: [nblocks, packed_words, meta_bytes, s8_words]
+ * (s8_words: 32-bit words of the Simple-8b array, two per 64-bit word, low
+ * half first), packed values, metadata (b, maxb, c per block, then the
+ * positions; zero-padded to 16 bytes), the Simple-8b words, zero-padded to
+ * 4 words. */
+static uint64_t o_sp_page(const uint32_t *d, uint64_t nblocks, uint32_t *out)
+{
+    uint32_t *bw = malloc(nblocks * sizeof(uint32_t));
+    uint32_t *mb = malloc(nblocks * sizeof(uint32_t));
+    uint32_t *cc = malloc(nblocks * sizeof(uint32_t));
+    uint32_t *hv = malloc((nblocks * OB + 1) * sizeof(uint32_t));
+    uint8_t *pos_bytes = malloc(nblocks * OB + 1);
+    uint64_t nexc = 0, packed_words = 0;
+    for (uint64_t t = 0; t < nblocks; t++) {
+        const uint32_t *blk = d + t * OB;
+        oracle_fp_choose(blk, OB, &bw[t], &mb[t], &cc[t]);
+        packed_words += (uint64_t)OB * bw[t] / 32;
+        for (uint32_t i = 0; i < OB; i++)
+            if (oracle_bits(blk[i]) > bw[t]) {
+                pos_bytes[nexc] = (uint8_t)i;
+                hv[nexc++] = blk[i] >> bw[t];
+            }
+    }
+    uint64_t *s8 = malloc((nexc + 1) * sizeof(uint64_t));
+    uint64_t ns8 = oracle_s8_encode(hv, nexc, s8);
+    uint64_t meta_bytes = 3 * nblocks + nexc;
+    out[0] = (uint32_t)nblocks;
+    out[1] = (uint32_t)packed_words;
+    out[2] = (uint32_t)meta_bytes;
+    out[3] = (uint32_t)(2 * ns8);
+    uint64_t p = 4;
+    for (uint64_t t = 0; t < nblocks; t++) {
+        oracle_pack(d + t * OB, OB, bw[t], out + p);
+        p += (uint64_t)OB * bw[t] / 32;
+    }
+    uint64_t meta_words = ((meta_bytes + 15) / 16) * 4;
+    uint8_t *mbytes = (uint8_t *)(out + p);
+    memset(mbytes, 0, meta_words * 4);
+    for (uint64_t t = 0; t < nblocks; t++) {
+        mbytes[t] = (uint8_t)bw[t];
+        mbytes[nblocks + t] = (uint8_t)mb[t];
+        mbytes[2 * nblocks + t] = (uint8_t)cc[t];
+    }
+    for (uint64_t e = 0; e < nexc; e++)
+        mbytes[3 * nblocks + e] = pos_bytes[e];
+    p += meta_words;
+    for (uint64_t w = 0; w < ns8; w++) {
+        out[p++] = (uint32_t)(s8[w] & 0xFFFFFFFFu);
+        out[p++] = (uint32_t)(s8[w] >> 32);
+    }
+    while (p % 4)
+        out[p++] = 0;
+    free(bw);
+    free(mb);
+    free(cc);
+    free(hv);
+    free(pos_bytes);
+    free(s8);
+    return p;
+}
+
+/* SimplePFOR (codec 5): see o_sp_page. */
+static int64_t o_encode(int codec, const uint32_t *x, uint64_t n, int stride,
+                        uint32_t *out, uint64_t cap);
+
+int64_t oracle_sp_encode(const uint32_t *x, uint64_t n, int stride, uint32_t *out, uint64_t cap)
+{
+    return o_encode(5, x, n, stride, out, cap);
+}
+
 static int64_t o_encode(int codec, const uint32_t *x, uint64_t n, int stride,
                         uint32_t *out, uint64_t cap)
 {
@@ -502,7 +650,7 @@ static int64_t o_encode(int codec, const uint32_t *x, uint64_t n, int stride,
     uint64_t nfull = n / OB;
     uint64_t tail = n % OB;
     uint64_t units = o_units(codec, n);
-    uint64_t per = (codec == 1 || codec == 3) ? OFP_BLOCKS : OBP_BLOCKS;
+    uint64_t per = (codec == 1 || codec == 3 || codec == 5) ? OFP_BLOCKS : OBP_BLOCKS;
     uint64_t E = 1 + (uint64_t)stride;
     uint64_t ndir = units + (tail ? 1 : 0);
     uint64_t dir_words = o_pad4(E * ndir);
@@ -524,6 +672,7 @@ static int64_t o_encode(int codec, const uint32_t *x, uint64_t n, int stride,
                 nb = per;
             p += (codec == 0 || codec == 4) ? o_bp_unit(d + start, nb, out + p, codec == 4)
                  : codec == 2 ? o_bp32_unit(d + start, nb, out + p)
+                 : codec == 5 ? o_sp_page(d + start, nb, out + p)
                               : o_fp_page(d + start, nb, out + p, codec == 3 ? 32 : OB);
         }
     }
@@ -698,6 +847,70 @@ done:
     return rc;
 }
 
+static int o_sp_page_decode(const uint32_t *w, uint64_t avail, uint64_t nblocks_expected, uint32_t *d)
+{
+    if (avail < 4)
+        return O_ERR_CORRUPT;
+    uint64_t nblocks = w[0], packed_words = w[1], meta_bytes = w[2], s8_words = w[3];
+    if (nblocks != nblocks_expected || (s8_words & 1u))
+        return O_ERR_CORRUPT;
+    uint64_t p = 4, packed_at = 4;
+    if (packed_words > avail - p)
+        return O_ERR_CORRUPT;
+    p += packed_words;
+    uint64_t meta_words = ((meta_bytes + 15) / 16) * 4;
+    if (meta_bytes < 3 * nblocks || meta_words > avail - p)
+        return O_ERR_CORRUPT;
+    const uint8_t *mbytes = (const uint8_t *)(w + p);
+    p += meta_words;
+    if (s8_words > avail - p || o_pad4(p + s8_words) != avail)
+        return O_ERR_CORRUPT;
+    uint64_t nexc = meta_bytes - 3 * nblocks;
+    uint64_t ns8 = s8_words / 2;
+    uint64_t *s8 = malloc((ns8 + 1) * sizeof(uint64_t));
+    uint32_t *hv = malloc((nexc + 1) * sizeof(uint32_t));
+    for (uint64_t k = 0; k < ns8; k++)
+        s8[k] = (uint64_t)w[p + 2 * k] | ((uint64_t)w[p + 2 * k + 1] << 32);
+    int rc = O_OK;
+    if (oracle_s8_decode(s8, ns8, hv, nexc) != (int64_t)nexc) {
+        rc = O_ERR_CORRUPT;
+        goto done;
+    }
+    uint64_t bitpos_words = 0, epos = 3 * nblocks, e_at = 0;
+    for (uint64_t t = 0; t < nblocks; t++) {
+        uint32_t b = mbytes[t], maxb = mbytes[nblocks + t], c = mbytes[2 * nblocks + t];
+        if (b > 32 || maxb > 32 || maxb < b || c > OB || (c == 0) != (maxb == b) ||
+            bitpos_words + (uint64_t)OB * b / 32 > packed_words) {
+            rc = O_ERR_CORRUPT;
+            goto done;
+        }
+        oracle_unpack(w + packed_at + bitpos_words, OB, b, d + t * OB);
+        bitpos_words += (uint64_t)OB * b / 32;
+        uint32_t k = maxb - b;
+        for (uint32_t e = 0; e < c; e++) {
+            if (epos >= meta_bytes) {
+                rc = O_ERR_CORRUPT;
+                goto done;
+            }
+            uint32_t at = mbytes[epos++];
+            uint32_t h = hv[e_at++];
+            /* positions in [0, 127], ascending inside a block; a high part
+             * of at most maxb - b bits */
+            if (at >= OB || (e > 0 && at <= mbytes[epos - 2]) || (k < 32 && (h >> k) != 0)) {
+                rc = O_ERR_CORRUPT;
+                goto done;
+            }
+            d[t * OB + at] |= h << b;
+        }
+    }
+    if (bitpos_words != packed_words || epos != meta_bytes)
+        rc = O_ERR_CORRUPT;
+done:
+    free(s8);
+    free(hv);
+    return rc;
+}
+
 static int o_decode(int codec, const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n)
 {
     if (in_words < 8)
@@ -710,7 +923,7 @@ static int o_decode(int codec, const uint32_t *in, uint64_t in_words, uint32_t *
         return O_ERR_CORRUPT;
     uint64_t nfull = n / OB, tail = n % OB;
     uint64_t units = o_units(codec, n);
-    uint64_t per = (codec == 1 || codec == 3) ? OFP_BLOCKS : OBP_BLOCKS;
+    uint64_t per = (codec == 1 || codec == 3 || codec == 5) ? OFP_BLOCKS : OBP_BLOCKS;
     uint64_t total = in[7], tail_off = in[6], tail_bytes = in[5];
     if (in[4] != units || total > in_words || (tail == 0) != (tail_bytes == 0))
         return O_ERR_CORRUPT;
@@ -735,6 +948,7 @@ static int o_decode(int codec, const uint32_t *in, uint64_t in_words, uint32_t *
                 return O_ERR_CORRUPT;
             rc = (codec == 0 || codec == 4) ? o_bp_unit_decode(in + off, end - off, nb, out + start, codec == 4)
                  : codec == 2 ? o_bp32_unit_decode(in + off, end - off, nb, out + start)
+                 : codec == 5 ? o_sp_page_decode(in + off, end - off, nb, out + start)
                               : o_fp_page_decode(in + off, end - off, nb, out + start, codec == 3 ? 32 : OB);
         } else {
             count = tail;
@@ -780,6 +994,11 @@ int oracle_fp32_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uin
 int oracle_bpv_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n)
 {
     return o_decode(4, in, in_words, out, n);
+}
+
+int oracle_sp_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n)
+{
+    return o_decode(5, in, in_words, out, n);
 }
 
 /* ------------------------------------------------------------------------

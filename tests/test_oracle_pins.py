@@ -716,3 +716,99 @@ def test_vertical_stream_differs_from_bp_only_inside_blocks(stride):
     tail = int(h[6])
     assert np.array_equal(a[tail:], h[tail:])
     assert np.array_equal(oracle.bpv_decode(a, x.size), x)
+
+
+# ---------------------------------------------------------------------------
+# Simple-8b (Section 2) and SimplePFOR (Section 5)
+
+def test_simple8b_modes_are_the_papers_table():
+    g = _golden("simple8b_modes.json")
+    for sel, cnt, bits in zip(g["selector"], g["integers_coded"], g["bits_per_integer"]):
+        assert oracle.s8_mode(sel) == (cnt, bits), sel
+        assert cnt * bits <= g["data_bits"]
+
+
+def _word(sel, vals, bits):
+    w = sel << 60
+    for j, v in enumerate(vals):
+        w |= int(v) << (j * bits)
+    return w
+
+
+def test_simple8b_greedy_special_cases():
+    # worked by hand from the table and the greedy rule (selectors tried
+    # from 0 upward, the first that fits the next integers is taken)
+    assert [int(w) for w in oracle.s8_encode(np.zeros(240, np.uint32))] == [0]
+    # 239 zeros: 120 (selector 1), then 60, 30, 20 (selectors 2, 3, 4), 8
+    # (selector 8: 9 left, too few for selectors 5..7), 1 (selector 15)
+    w = oracle.s8_encode(np.zeros(239, np.uint32))
+    assert [int(x) >> 60 for x in w] == [1, 2, 3, 4, 8, 15]
+    assert [int(x) for x in oracle.s8_encode(np.ones(60, np.uint32))] == [_word(2, [1] * 60, 1)]
+    v = np.array([(1 << 20) - 1, 5, (1 << 20) - 2], np.uint32)
+    assert [int(x) for x in oracle.s8_encode(v)] == [_word(13, v, 20)]
+    assert [int(x) for x in oracle.s8_encode(np.array([0xFFFFFFFF], np.uint32))] == [_word(15, [0xFFFFFFFF], 60)]
+    # one value of 2 bits among 60 small ones: two words of 30 two-bit values
+    v = np.array([1] * 59 + [2], np.uint32)
+    assert [int(x) >> 60 for x in oracle.s8_encode(v)] == [3, 3]
+    # values of 31 bits: one per word (30 bits are too few)
+    assert [int(x) >> 60 for x in oracle.s8_encode(np.array([1 << 30, 1 << 30], np.uint32))] == [15, 15]
+
+
+def test_simple8b_roundtrip_and_errors():
+    rng = np.random.default_rng(81)
+    for n in (0, 1, 2, 59, 60, 61, 239, 240, 241, 1000):
+        for hi in (1, 2, 1 << 7, 1 << 20, 1 << 31):
+            v = rng.integers(0, hi, size=n, dtype=np.uint64).astype(np.uint32)
+            v[rng.random(n) < 0.3] = 0
+            w = oracle.s8_encode(v)
+            k, back = oracle.s8_decode(w, n)
+            assert k == n and np.array_equal(back, v), (n, hi)
+    w = oracle.s8_encode(np.zeros(240, np.uint32))
+    assert oracle.s8_decode(w, 239)[0] == oracle.ERR_CORRUPT  # more values than room
+    assert oracle.s8_decode(np.array([(15 << 60) | (1 << 40)], np.uint64), 1)[0] == oracle.ERR_CORRUPT  # > 32 bits
+
+
+def test_simplepfor_pages_are_fastpfor_pages_but_for_the_exceptions():
+    # Section 5: SimplePFOR and FastPFOR differ only in how the high parts
+    # of the exceptions are stored: same widths, packed values and metadata
+    x = datagen.patched_gaps(2 * 65536 + 128 * 9 + 40, seed=83)
+    fp, sp = oracle.fp_encode(x, 1), oracle.sp_encode(x, 1)
+    assert np.array_equal(oracle.sp_decode(sp, x.size), x)
+    units = int(fp[4])
+    for u in range(units):
+        fo, so = int(fp[8 + u]), int(sp[8 + u])
+        nb, packed, meta_bytes, bitset = (int(v) for v in fp[fo:fo + 4])
+        assert [int(v) for v in sp[so:so + 3]] == [nb, packed, meta_bytes]
+        nset = bin(bitset).count("1")
+        fh = (4 + nset + 3) // 4 * 4
+        meta_w = (meta_bytes + 15) // 16 * 4
+        assert np.array_equal(fp[fo + fh:fo + fh + packed + meta_w], sp[so + 4:so + 4 + packed + meta_w])
+        # the Simple-8b array holds one high part per exception, in block order
+        s8w = int(sp[so + 3])
+        words = sp[so + 4 + packed + meta_w:so + 4 + packed + meta_w + s8w].astype(np.uint64)
+        w64 = words[0::2] | (words[1::2] << np.uint64(32))
+        k, hv = oracle.s8_decode(w64, meta_bytes - 3 * nb)
+        assert k == meta_bytes - 3 * nb and (hv > 0).all()
+
+
+@pytest.mark.parametrize("stride", [0, 1, 4])
+def test_simplepfor_roundtrip_and_size(stride):
+    rng = np.random.default_rng(84 + stride)
+    for n in (0, 1, 127, 128, 129, 1000, 65536, 65536 + 128 * 3 + 5):
+        d = np.where(rng.random(n) < 0.05, rng.integers(1 << 16, 1 << 28, size=n), rng.integers(0, 16, size=n))
+        x = (d if stride == 0 else np.cumsum(d)).astype(np.uint32)
+        s = oracle.sp_encode(x, stride)
+        assert s.size <= oracle.max_words(oracle.CODEC_SP, n)
+        assert np.array_equal(oracle.sp_decode(s, n), x), n
+
+
+def test_simplepfor_corrupt_streams_are_rejected():
+    x = datagen.patched_gaps(65536 + 500, seed=85)
+    s = oracle.sp_encode(x, 1)
+    assert oracle.sp_decode_rc(s, x.size) == oracle.OK
+    unit = int(s[8])
+    for at, val in ((0, int(s[0]) ^ 1), (unit, 7), (unit + 2, int(s[unit + 2]) + 1), (unit + 3, int(s[unit + 3]) + 2)):
+        bad = s.copy()
+        bad[at] = val & 0xFFFFFFFF
+        assert oracle.sp_decode_rc(bad, x.size) == oracle.ERR_CORRUPT, at
+    assert oracle.sp_decode_rc(oracle.fp_encode(x, 1), x.size) == oracle.ERR_CORRUPT

@@ -4,9 +4,10 @@ the oracle's streams.
 The reader below is written from the layout alone (header, directory with
 unit offsets and bases, SIMD-BP128 meta-blocks in the sequential and in the
 four-lane block layout, BP32 meta-blocks, FastPFOR pages with exception
-arrays padded to 128 or to 32 values, Variable Byte remainder), with bit
-fields read from Python big integers; it shares nothing with the oracle but
-the layout. Every stream the oracle writes for small inputs (every length
+arrays padded to 128 or to 32 values, SimplePFOR pages with one Simple-8b
+array of exception high parts, Variable Byte remainder), with bit fields
+read from Python big integers; it shares nothing with the oracle but the
+layout. Every stream the oracle writes for small inputs (every length
 0..300, every stride, every codec) and for a few multi-unit inputs must read
 back to the input: a mistake in either one's reading of the layout shows.
 No GPU.
@@ -17,9 +18,13 @@ import pytest
 import oracle
 from paper_1209_2137_amd import datagen
 
-MAGIC = {"bp": 0x31425057, "fp": 0x31465057, "bp32": 0x32335057, "fp32": 0x33465057, "bpv": 0x31565057}
+MAGIC = {"bp": 0x31425057, "fp": 0x31465057, "bp32": 0x32335057, "fp32": 0x33465057, "bpv": 0x31565057,
+         "sp": 0x31535057}
 ENC = {"bp": oracle.bp_encode, "fp": oracle.fp_encode, "bp32": oracle.bp32_encode, "fp32": oracle.fp32_encode,
-       "bpv": oracle.bpv_encode}
+       "bpv": oracle.bpv_encode, "sp": oracle.sp_encode}
+# Simple-8b modes (Section 2): selector -> (integers per word, bits each)
+S8 = [(240, 0), (120, 0), (60, 1), (30, 2), (20, 3), (15, 4), (12, 5), (10, 6), (8, 7), (7, 8), (6, 10), (5, 12),
+      (4, 15), (3, 20), (2, 30), (1, 60)]
 
 
 def _big(words):
@@ -118,6 +123,38 @@ def _fp_page(w, nblocks, pad):
     return out
 
 
+def _sp_page(w, nblocks):
+    """SimplePFOR page: FastPFOR's packed values and metadata, the
+    exceptions' high parts as one Simple-8b array (selector in the top four
+    bits of each 64-bit word, low 32-bit half first)."""
+    nb, packed, meta_bytes, s8_words = (int(v) for v in w[:4])
+    assert nb == nblocks
+    at = 4
+    packed_at = at
+    at += packed
+    meta = bytes(np.asarray(w[at:at + -(-meta_bytes // 16) * 4], dtype=np.uint32).tobytes())[:meta_bytes]
+    at += -(-meta_bytes // 16) * 4
+    b, mb, c = meta[:nb], meta[nb:2 * nb], meta[2 * nb:3 * nb]
+    pos = meta[3 * nb:]
+    high = []
+    for i in range(0, s8_words, 2):
+        word = int(w[at + i]) | (int(w[at + i + 1]) << 32)
+        cnt, bits = S8[word >> 60]
+        high += [(word >> (j * bits)) & ((1 << bits) - 1) if bits else 0 for j in range(cnt)]
+    at += s8_words
+    assert -(-at // 4) * 4 == len(w) and len(high) == len(pos)
+    out, p_at, blk_at = [], 0, packed_at
+    for t in range(nb):
+        vals = _fields(w[blk_at:blk_at + 4 * b[t]], 128, b[t])
+        blk_at += 4 * b[t]
+        for j in range(c[t]):
+            assert 0 < high[p_at + j] < (1 << (mb[t] - b[t]))
+            vals[pos[p_at + j]] |= high[p_at + j] << b[t]
+        p_at += c[t]
+        out += vals
+    return out
+
+
 def read(stream, codec):
     """The integers the stream holds (deltas undone from the stored bases)."""
     s = np.asarray(stream, dtype=np.uint32)
@@ -125,7 +162,7 @@ def read(stream, codec):
     n = int(s[1]) | (int(s[2]) << 32)
     S, units, tail_bytes, tail_off, total = (int(v) for v in s[3:8])
     assert total == s.size
-    per = 512 if codec in ("fp", "fp32") else 16
+    per = 512 if codec in ("fp", "fp32", "sp") else 16
     nfull, tail = n // 128, n % 128
     assert units == -(-nfull // per)
     ndir = units + (1 if tail else 0)
@@ -142,6 +179,8 @@ def read(stream, codec):
                 d = _bp_unit(w, nb, codec == "bpv")
             elif codec == "bp32":
                 d = _bp32_unit(w, nb)
+            elif codec == "sp":
+                d = _sp_page(w, nb)
             else:
                 d = _fp_page(w, nb, 32 if codec == "fp32" else 128)
         else:
