@@ -14,10 +14,13 @@
 // With the second list still compressed, the directory serves as a skip
 // list: every unit's stored base is the value just before the unit, so a
 // strictly increasing list's unit e holds values in (base_e, base_{e+1}].
-// One pass flags the units that some element of the first list falls in,
-// a second decodes only those units (the decoders' wavefront and page
-// routines, into the caller's work buffer at their own positions), and the
-// lookups then search the directory for the unit, then the unit's values.
+// The decode pass takes one unit per wavefront (or workgroup, for pages):
+// it searches the first list for a value in its unit's range and decodes
+// the unit only then (the decoders' wavefront and page routines, into the
+// caller's work buffer at the unit's own positions); the lookups then
+// search the directory for the unit, then the unit's values. Random access
+// by key uses the same decode pass with the key range in place of the
+// first list, then two wavefront searches for the range's ends.
 #include "wp_device.hpp"
 #include "wp_host.hpp"
 
