@@ -583,8 +583,8 @@ def main():
             return 2
         return profile_variants(args.steps, args.inputs)
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (this build decodes on a "
-              "single MI355X; lists and units shard across GPUs without any exchange, see the design notes)",
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the library decodes on a "
+              "single MI355X; lists and units would shard across GPUs without any exchange)",
               file=sys.stderr)
         return 2
     import torch
