@@ -19,8 +19,15 @@
  *     can see (null pointers, bad stride, capacity, misalignment) return at
  *     once and enqueue nothing. Problems inside a compressed stream are
  *     found by the kernels: they record WP_ERR_CORRUPT in a per-device
- *     error word (read and cleared by wp_check), skip the bad unit, and
- *     never write outside [out, out + n).
+ *     error word (a static device variable of the library, read and cleared
+ *     by wp_check; it is shared by all streams of the device), skip the bad
+ *     unit, and never write outside [out, out + n).
+ *   - Allocation and synchronisation: the decoders, wp_batch_decode and
+ *     wp_decode_range neither allocate nor synchronise. The encoders, delta_decode_inplace, wp_intersect and
+ *     wp_intersect_compressed use a library-owned scratch area per (device,
+ *     stream); when a call needs more than that stream's area holds, it
+ *     synchronises the stream, frees the area and allocates a larger one
+ *     (so such a first call must not happen under stream capture).
  *   - All arithmetic on values is uint32 modulo 2^32 (sums wrap).
  *
  * Stream layout (32-bit little-endian words; both codecs)
@@ -85,6 +92,7 @@ extern "C" {
 #define WP_CODEC_BP32 2 /* binary packing, 64 x 32-integer blocks per unit */
 #define WP_CODEC_FP32 3 /* patched pages, exception arrays padded to 32 values */
 #define WP_CODEC_BPV 4  /* binary packing as WP_CODEC_BP, four-lane block layout */
+#define WP_CODEC_SP 5   /* patched pages, exception high parts in one Simple-8b array per page */
 
 /* Largest stream any input of n integers can produce, in 32-bit words.
  * Host only, pure. Returns 0 when n is beyond the format (streams are
@@ -99,7 +107,8 @@ uint64_t wp_max_compressed_words(int32_t codec, uint64_t n);
  *                    wp_max_compressed_words(WP_CODEC_BP, n)
  *   out_words        device uint64: receives the stream length in words
  *                    (written on the stream, no implicit synchronisation)
- * Uses a library-owned scratch area per (device, stream), grown on demand. */
+ * Uses a library-owned scratch area per (device, stream), grown on demand
+ * (growing synchronises the stream and allocates). */
 int32_t bp_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,
                   uint64_t out_cap_words, uint64_t *out_words, void *stream);
 
@@ -157,6 +166,24 @@ int32_t fastpfor32_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, 
 int32_t fastpfor32_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
                           void *stream);
 
+/* SimplePFOR pages (Section 5, SimplePFOR; Section 2, Simple-8b): the
+ * pages of fastpfor_encode (same widths by the same cost rule, same packed
+ * values, metadata and positions), with the high parts of a page's
+ * exceptions collected in block order into one array coded with Simple-8b
+ * (64-bit words: a 4-bit selector, the word's top four bits, and 60 data
+ * bits holding the mode's count of equal-width integers, integer j at bits
+ * [j*bits, (j+1)*bits); greedy: the first selector, from 0 up, whose count
+ * is still available and whose width fits them). Page: [nblocks,
+ * packed_words, meta_bytes, Simple-8b words (32-bit words, two per 64-bit
+ * word, low half first)], packed values, metadata, the Simple-8b words,
+ * zero-padded to 4 words (magic 'WPS1'). */
+
+/* SimplePFOR decoder: as fastpfor_decode,
+ * the high parts taken from the page's Simple-8b words (decoded by
+ * wavefronts as the page's blocks need them). Allocates nothing. */
+int32_t simplepfor_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
+                          void *stream);
+
 /* Patched decoder (Section 5): unpack each block's low bits, patch each
  * exception with its high part from array k shifted left by b, then the
  * prefix sum. Arguments as bp_decode. Allocates nothing. */
@@ -169,7 +196,10 @@ int32_t fastpfor_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, ui
  *   stride 4: data[i] = init + sum of d_j, j <= i, j = i (mod 4)
  * One pass over the data (8 bytes of traffic per integer) with a
  * decoupled look-back across tiles. Uses a library-owned scratch area per
- * (device, stream) of 32 bytes per 8192 integers, grown on demand. */
+ * (device, stream) of 64 bytes per 16384 integers, grown on demand
+ * (growing synchronises the stream and allocates). Returns
+ * WP_ERR_INVALID_ARG for a stride other than 1 or 4, a null or misaligned
+ * `data` (n > 0), WP_ERR_HIP if the scratch allocation or a launch fails. */
 int32_t delta_decode_inplace(uint32_t *data, uint64_t n, uint32_t init, int32_t stride,
                              void *stream);
 
@@ -240,13 +270,16 @@ int32_t wp_time_next_launch(void *start_event, void *stop_event);
  * 16-byte loads per lane in flight (2, 3 or 4; 0 = 2); wg_per_cu: runs
  * per compute unit, 0..1024, which sets the run length (0 = 128; many
  * short runs let the hardware balance the load). Patched pages: one
- * workgroup per page, waves 2, 4 or 8 (each wavefront unpacks two blocks
- * per pass), vpl 4; depth and wg_per_cu are ignored. Returns
+ * wavefront per page (four blocks per pass), waves = pages per workgroup
+ * (1, 2, 4 or 8), vpl 4; depth and wg_per_cu are ignored. Returns
  * WP_ERR_INVALID_ARG for anything else. */
 int32_t wp_set_decode_tune(int32_t codec, int32_t waves, int32_t vpl, int32_t depth, int32_t wg_per_cu);
 
 /* Synchronises `stream`, then returns and clears this device's error word:
- * WP_OK, WP_ERR_CORRUPT, or WP_ERR_HIP if the synchronisation failed. */
+ * WP_OK, WP_ERR_CORRUPT, or WP_ERR_HIP if the synchronisation failed. The
+ * word is device-wide: it reports a corrupt stream met by work on any
+ * stream of the device since the last wp_check, and work still running on
+ * other streams may set it after this call has read it. */
 int32_t wp_check(void *stream);
 
 /* Static description of a code. */
@@ -269,6 +302,9 @@ typedef struct wp_list {
     uint64_t n;              /* integers in the list */
     int32_t codec;           /* WP_CODEC_BP or WP_CODEC_FP */
     int32_t reserved;        /* must be 0 */
+    uint32_t *out;           /* if not NULL: the list's own destination (device,
+                                16-byte aligned, n integers, caller-owned), used
+                                instead of out_base + out_off (out_off ignored) */
 } wp_list;
 
 typedef struct wp_tune {
@@ -281,13 +317,17 @@ typedef struct wp_tune {
 } wp_tune;
 
 /* Builds a plan: validates the registry on the host (codec, alignment of
- * comp_off_words and out_off to 4 words, comp_words >= 8), cuts every list
+ * comp_off_words and out_off (or of the list's own `out`) to 4 words,
+ * comp_words >= 8), cuts every list
  * into work items (runs of run_units meta-blocks, single pages, tails
  * of lists without full blocks; largest first), uploads the list and item arrays (it synchronises
  * `stream` once), and, when tune->use_graph, builds and instantiates a
  * hipGraph holding the decoder's kernel node. `pool` and
- * `out_base` (device, 16-byte aligned) are kept; h_lists may be freed on
- * return; tune may be NULL (defaults, graph on). The plan allocates its
+ * `out_base` (device, 16-byte aligned) are kept; out_base may be NULL when
+ * every list names its own `out`; h_lists may be freed on return. `tune`
+ * (an addition to the plan call of the design: the workgroup shape and
+ * the size of a binary-packing work item are chosen by the autotuner,
+ * which must be able to try them) may be NULL (defaults, graph on). The plan allocates its
  * own device arrays; *h_plan is released with wp_batch_free. Output ranges
  * of different lists must not overlap. Returns WP_ERR_INVALID_ARG for a bad
  * registry or tune, WP_ERR_HIP if an allocation or copy fails. */

@@ -24,6 +24,7 @@ CODEC_FP = 1
 CODEC_BP32 = 2
 CODEC_FP32 = 3
 CODEC_BPV = 4
+CODEC_SP = 5
 
 EXPORTS = (
     "bp_encode", "bp_decode", "bp32_encode", "bp32_decode", "fastpfor_encode", "fastpfor_decode",
@@ -31,6 +32,7 @@ EXPORTS = (
     "wp_max_compressed_words", "wp_check", "wp_strerror", "wp_set_decode_tune", "wp_time_next_launch",
     "wp_batch_plan", "wp_batch_replan", "wp_batch_decode", "wp_batch_items", "wp_batch_free",
     "wp_intersect", "wp_intersect_compressed", "wp_decode_range",
+    "simplepfor_decode",
 )
 
 _lib = None
@@ -45,7 +47,7 @@ class WavepackError(RuntimeError):
 class wp_list(ctypes.Structure):
     _fields_ = [("comp_off_words", ctypes.c_uint64), ("comp_words", ctypes.c_uint64),
                 ("out_off", ctypes.c_uint64), ("n", ctypes.c_uint64),
-                ("codec", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("codec", ctypes.c_int32), ("reserved", ctypes.c_int32), ("out", ctypes.c_void_p)]
 
 
 class wp_tune(ctypes.Structure):
@@ -77,7 +79,8 @@ def lib():
         f = getattr(L, name)
         f.argtypes = [vp, u64, i32, vp, u64, vp, vp]
         f.restype = i32
-    for name in ("bp_decode", "bp32_decode", "fastpfor_decode", "fastpfor32_decode", "bp_vertical_decode"):
+    for name in ("bp_decode", "bp32_decode", "fastpfor_decode", "fastpfor32_decode", "bp_vertical_decode",
+                 "simplepfor_decode"):
         f = getattr(L, name)
         f.argtypes = [vp, u64, vp, u64, vp]
         f.restype = i32
@@ -143,6 +146,10 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _ptr_or_null(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p()
+
+
 def _need_u32(t, what):
     import torch
     if t.dtype not in (torch.int32, torch.uint32) or not t.is_contiguous() or not t.is_cuda:
@@ -205,6 +212,11 @@ def bp_vertical_decode(comp, n: int, out=None, stream=None):
 def fastpfor32_decode(comp, n: int, out=None, stream=None):
     """Decodes a FastPFOR stream (exception arrays padded to 32) into out[0:n]."""
     return _decode(lib().fastpfor32_decode, comp, n, out, stream, "fastpfor32_decode")
+
+
+def simplepfor_decode(comp, n: int, out=None, stream=None):
+    """Decodes a SimplePFOR stream (exception high parts in Simple-8b) into out[0:n]."""
+    return _decode(lib().simplepfor_decode, comp, n, out, stream, "simplepfor_decode")
 
 
 def _encode(fn, codec, x, stride, out, out_words, stream, name):
@@ -351,21 +363,33 @@ def check_code(stream=None) -> int:
     return int(lib().wp_check(_stream(stream)))
 
 
+def _registry(lists):
+    """wp_list array of rows (comp_off_words, comp_words, out_off, n, codec)
+    or (..., codec, out_ptr): a non-zero out_ptr is the list's own device
+    destination (out_off is then ignored)."""
+    n = len(lists)
+    arr = (wp_list * max(n, 1))()
+    for i, row in enumerate(lists):
+        co, cw, oo, nn, codec = row[:5]
+        dst = int(row[5]) if len(row) > 5 else 0
+        arr[i] = wp_list(int(co), int(cw), int(oo), int(nn), int(codec), 0, dst or None)
+    return arr, n
+
+
 class BatchPlan:
     """A batched decode of many lists (see wp_batch_plan).
 
     pool: device tensor holding all compressed streams; out: device tensor
-    receiving all outputs; lists: rows (comp_off_words, comp_words, out_off,
-    n, codec). tune: dict with waves, vpl, depth, run_units, wg_per_cu,
-    use_graph (missing keys take the library defaults)."""
+    receiving the outputs at the rows' offsets (None when every row names
+    its own destination); lists: rows (comp_off_words, comp_words, out_off,
+    n, codec[, out_ptr]). tune: dict with waves, vpl, depth, run_units,
+    wg_per_cu, use_graph (missing keys take the library defaults)."""
 
     def __init__(self, pool, out, lists, tune=None, stream=None):
         _need_u32(pool, "pool")
-        _need_u32(out, "out")
-        n = len(lists)
-        arr = (wp_list * max(n, 1))()
-        for i, (co, cw, oo, nn, codec) in enumerate(lists):
-            arr[i] = wp_list(int(co), int(cw), int(oo), int(nn), int(codec), 0)
+        if out is not None:
+            _need_u32(out, "out")
+        arr, n = _registry(lists)
         t = None
         if tune is not None:
             t = wp_tune(int(tune.get("waves", 0)), int(tune.get("vpl", 0)), int(tune.get("depth", 0)),
@@ -373,19 +397,19 @@ class BatchPlan:
                         int(tune.get("use_graph", 1)))
         self._h = ctypes.c_void_p()
         self.pool, self.out = pool, out  # keep the buffers alive
-        _check(lib().wp_batch_plan(_ptr(pool), _ptr(out), arr, n, ctypes.byref(t) if t is not None else None,
-                                   ctypes.byref(self._h), _stream(stream)), "wp_batch_plan")
+        _check(lib().wp_batch_plan(_ptr(pool), _ptr_or_null(out), arr, n,
+                                   ctypes.byref(t) if t is not None else None, ctypes.byref(self._h),
+                                   _stream(stream)), "wp_batch_plan")
 
     def replan(self, pool, out, lists, stream=None):
         """Points the plan at a new registry without allocating (async copy)."""
         _need_u32(pool, "pool")
-        _need_u32(out, "out")
-        n = len(lists)
-        arr = (wp_list * max(n, 1))()
-        for i, (co, cw, oo, nn, codec) in enumerate(lists):
-            arr[i] = wp_list(int(co), int(cw), int(oo), int(nn), int(codec), 0)
+        if out is not None:
+            _need_u32(out, "out")
+        arr, n = _registry(lists)
         self.pool, self.out = pool, out
-        _check(lib().wp_batch_replan(self._h, _ptr(pool), _ptr(out), arr, n, _stream(stream)), "wp_batch_replan")
+        _check(lib().wp_batch_replan(self._h, _ptr(pool), _ptr_or_null(out), arr, n, _stream(stream)),
+               "wp_batch_replan")
 
     @property
     def items(self) -> int:

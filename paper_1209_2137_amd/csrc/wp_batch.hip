@@ -1,14 +1,12 @@
 // Batched decoding of many lists in one launch.
 //
-// The host planner cuts every list into work items: patched pages,
-// runs of up to `run_units` meta-blocks (binary packing) and the Variable
-// Byte tails of lists without full blocks. The tail of any other list is
-// decoded by the item that holds the list's last unit. One grid covers the
-// items: a workgroup for each patched page of more than 64 blocks (a page
-// needs the workgroup's barriers), then a wavefront for each run, small
-// patched page and tail, with no barrier at all; each class is ordered
-// largest first, so the dispatcher, which starts workgroups in index order
-// as compute units free up, schedules the longest items first. Items are
+// The host planner cuts every list into work items: patched pages (one
+// each), runs of up to `run_units` meta-blocks (binary packing) and the
+// Variable Byte tails of lists without full blocks. The tail of any other
+// list is decoded by the item that holds the list's last unit. One grid
+// covers the items, one wavefront each with no barrier at all, ordered
+// largest first: the dispatcher, which starts workgroups in index order as
+// compute units free up, schedules the longest items first. Items are
 // independent because every unit's base is stored in its list's directory.
 //
 // A plan owns its device item array and, when asked, a hipGraph holding
@@ -22,10 +20,7 @@
 
 namespace wp {
 
-enum : uint32_t { kItemBpRun = 0, kItemFpPage = 1, kItemTail = 2, kItemFpSmall = 3 };
-
-// Patched pages of at most this many blocks are decoded by one wavefront.
-constexpr uint32_t kSmallPageBlocks = 64;
+enum : uint32_t { kItemBpRun = 0, kItemFpPage = 1, kItemTail = 2 };
 
 struct DevList {
     const uint32_t *comp;
@@ -43,19 +38,6 @@ union WaveItemLds {
     TailLds<1> tail;
 };
 
-template <int WAVES>
-union BatchPageLds {
-    FpLds<WAVES> fp;
-    TailLds<WAVES> tail;
-};
-
-// item: {list index, kind, first unit, unit count (pages: the page's blocks)}
-template <int WAVES, int DEPTH>
-union BatchLds {
-    WaveItemLds<DEPTH> w[WAVES];
-    BatchPageLds<WAVES> page;
-};
-
 // Header check of item `it`'s list; uniform.
 __device__ __forceinline__ bool item_header(const DevList *__restrict__ lists, const uint4 *__restrict__ items,
                                             uint32_t it, uint4 &item, DevList &Ld, ListHdr &H)
@@ -70,48 +52,10 @@ __device__ __forceinline__ bool item_header(const DevList *__restrict__ lists, c
                         Ld.codec == WP_CODEC_BP ? kBpBlocks : kFpBlocks, H);
 }
 
-// Page item `it` (a patched page of more than kSmallPageBlocks blocks),
-// decoded by the whole workgroup; the list's last page also decodes its
-// tail. Uniform result.
-template <int WAVES>
-__device__ __forceinline__ bool page_item(const DevList *__restrict__ lists, const uint4 *__restrict__ items, uint32_t it,
-                          BatchPageLds<WAVES> &L)
-{
-    uint4 item;
-    DevList Ld;
-    ListHdr H;
-    bool ok = item_header(lists, items, it, item, Ld, H) && item.y == kItemFpPage && Ld.codec == WP_CODEC_FP &&
-              item.z < H.units;
-    if (!ok)
-        return false;
-    const uint64_t u = item.z;
-    const uint32_t off = uniform(Ld.comp[kHdrWords + u]);
-    const uint32_t end = (u + 1 < H.units) ? uniform(Ld.comp[kHdrWords + u + 1]) : H.tail_off;
-    const uint32_t *bp = Ld.comp + kHdrWords + H.ndir + u * H.S;
-    const uint32_t base[4] = {H.S > 0 ? uniform(bp[0]) : 0u, H.S > 1 ? uniform(bp[1]) : 0u,
-                              H.S > 2 ? uniform(bp[2]) : 0u, H.S > 3 ? uniform(bp[3]) : 0u};
-    const uint64_t left = H.nfull - u * kFpBlocks;
-    const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
-    const uint32_t *pg = Ld.comp + off;
-    uint32_t *po = Ld.out + u * kFpUnitInts;
-    // two fetch slots here: three measure the same in this kernel. (Three
-    // once gave wrong values in part of the stores of partial pages; the
-    // cause was the output stores' data hazard that buf_store_u4 now
-    // guards, see the tests of batches of partial pages.)
-    ok = off >= H.dir_end && end >= off && end <= H.total && (off & 3u) == 0 &&
-         (H.S == 1   ? fp_page<WAVES, 1, 2>(pg, end - off, nb, base, po, L.fp)
-          : H.S == 4 ? fp_page<WAVES, 4, 2>(pg, end - off, nb, base, po, L.fp)
-                     : fp_page<WAVES, 0, 2>(pg, end - off, nb, base, po, L.fp));
-    if (u + 1 == H.units && H.tail) {
-        __syncthreads();
-        ok = decode_tail_entry<WAVES>(Ld.comp, H, Ld.out, L.tail) && ok;
-    }
-    return ok;
-}
-
-// Wavefront item `it`: a run of binary-packing meta-blocks, a small
-// patched page or a tail, decoded by one wavefront with no workgroup
-// barrier; the item holding a list's last unit also decodes its tail.
+// Item `it` -- a run of binary-packing meta-blocks {list, kind, first unit,
+// unit count}, a patched page {list, kind, page, its blocks} or a tail --
+// decoded by one wavefront; the item holding a list's last unit also
+// decodes its tail. Uniform result.
 template <int DEPTH>
 __device__ __forceinline__ bool wave_item(const DevList *__restrict__ lists, const uint4 *__restrict__ items, uint32_t it,
                           WaveItemLds<DEPTH> &W)
@@ -131,23 +75,11 @@ __device__ __forceinline__ bool wave_item(const DevList *__restrict__ lists, con
              : H.S == 4 ? bp_wave_run<DEPTH, 4>(Ld.comp, H, first, count, Ld.out, W.r)
                         : bp_wave_run<DEPTH, 0>(Ld.comp, H, first, count, Ld.out, W.r);
         last = first + count == H.units;
-    } else if (item.y == kItemFpSmall) {
+    } else if (item.y == kItemFpPage) {
         const uint64_t u = item.z;
         if (!(Ld.codec == WP_CODEC_FP && u < H.units))
             return false;
-        const uint32_t off = uniform(Ld.comp[kHdrWords + u]);
-        const uint32_t end = (u + 1 < H.units) ? uniform(Ld.comp[kHdrWords + u + 1]) : H.tail_off;
-        const uint32_t *bp = Ld.comp + kHdrWords + H.ndir + u * H.S;
-        const uint32_t base[4] = {H.S > 0 ? uniform(bp[0]) : 0u, H.S > 1 ? uniform(bp[1]) : 0u,
-                                  H.S > 2 ? uniform(bp[2]) : 0u, H.S > 3 ? uniform(bp[3]) : 0u};
-        const uint64_t left = H.nfull - u * kFpBlocks;
-        const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
-        const uint32_t *pg = Ld.comp + off;
-        uint32_t *po = Ld.out + u * kFpUnitInts;
-        ok = off >= H.dir_end && end >= off && end <= H.total && (off & 3u) == 0 && nb <= kSmallPageBlocks &&
-             (H.S == 1   ? fp_small_page<1>(pg, end - off, nb, base, po, W.fp)
-              : H.S == 4 ? fp_small_page<4>(pg, end - off, nb, base, po, W.fp)
-                         : fp_small_page<0>(pg, end - off, nb, base, po, W.fp));
+        ok = fp_unit(Ld.comp, H, u, Ld.out, W.fp);
         last = u + 1 == H.units;
     } else {
         return item.y == kItemTail && H.tail != 0 && decode_tail_entry<1, false>(Ld.comp, H, Ld.out, W.tail);
@@ -159,29 +91,21 @@ __device__ __forceinline__ bool wave_item(const DevList *__restrict__ lists, con
     return ok;
 }
 
-// One launch over the whole plan: workgroup g < npages decodes page item g
-// with all its wavefronts; every later workgroup gives one wavefront item
-// to each of its wavefronts (items npages + (g - npages) * WAVES + wave).
-// Items are sorted largest first, and the dispatcher starts workgroups in
-// index order as compute units free up, which balances the load without a
-// work queue.
+// One launch over the whole plan: wavefront w of workgroup g decodes item
+// g * WAVES + w. Items are sorted largest first, and the dispatcher starts
+// workgroups in index order as compute units free up, which balances the
+// load without a work queue.
 template <int WAVES, int DEPTH>
 __global__ __launch_bounds__(64 * WAVES) void k_batch(const DevList *__restrict__ lists,
-                                                      const uint4 *__restrict__ items, uint32_t npages,
-                                                      uint32_t nitems, int *__restrict__ err)
+                                                      const uint4 *__restrict__ items, uint32_t nitems,
+                                                      int *__restrict__ err)
 {
-    __shared__ BatchLds<WAVES, DEPTH> L;
-    const uint32_t g = blockIdx.x;
-    if (g < npages) {
-        if (!page_item<WAVES>(lists, items, g, L.page) && threadIdx.x == 0)
-            *err = kErrCorrupt;
-        return;
-    }
+    __shared__ WaveItemLds<DEPTH> L[WAVES];
     const uint32_t wave = uniform(threadIdx.x >> 6);
-    const uint64_t it = npages + (uint64_t)(g - npages) * WAVES + wave;
+    const uint64_t it = (uint64_t)blockIdx.x * WAVES + wave;
     if (it >= nitems)
         return;
-    if (!wave_item<DEPTH>(lists, items, (uint32_t)it, L.w[wave]) && lane_id() == 0)
+    if (!wave_item<DEPTH>(lists, items, (uint32_t)it, L[wave]) && lane_id() == 0)
         *err = kErrCorrupt;
 }
 
@@ -189,7 +113,7 @@ struct Plan {
     int device = -1;
     DevList *d_lists = nullptr;
     uint4 *d_items = nullptr;
-    uint64_t nlists = 0, nitems = 0, npages = 0;
+    uint64_t nlists = 0, nitems = 0;
     int waves = 4, vpl = 4, depth = 4;
     uint32_t grid = 1;
     bool use_graph = false;
@@ -251,11 +175,10 @@ static void release(Plan *p)
     delete p;
 }
 
-// Workgroups of a launch: one per page item, then one per `waves` wavefront
-// items (at least one workgroup).
-static uint64_t grid_for(uint64_t npages, uint64_t nitems, int waves)
+// Workgroups of a launch: one per `waves` items (at least one).
+static uint64_t grid_for(uint64_t nitems, int waves)
 {
-    return std::max<uint64_t>(1, npages + (nitems - npages + (uint64_t)waves - 1) / (uint64_t)waves);
+    return std::max<uint64_t>(1, (nitems + (uint64_t)waves - 1) / (uint64_t)waves);
 }
 constexpr uint64_t kMaxGrid = 0x7FFFFFFFull;
 
@@ -264,8 +187,8 @@ static int32_t launch_plan(Plan *p, hipStream_t st)
     (void)hipGetLastError();
     if (p->nitems == 0)
         return WP_OK;
-    uint32_t npages32 = (uint32_t)p->npages, nitems32 = (uint32_t)p->nitems;
-    void *args[] = {&p->d_lists, &p->d_items, &npages32, &nitems32, &p->err};
+    uint32_t nitems32 = (uint32_t)p->nitems;
+    void *args[] = {&p->d_lists, &p->d_items, &nitems32, &p->err};
     if (hipLaunchKernel(p->kernel, dim3(p->grid), dim3(64 * p->waves), args, 0, st) != hipSuccess)
         return WP_ERR_HIP;
     return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
@@ -276,8 +199,8 @@ static int32_t build_graph(Plan *p)
     if (hipGraphCreate(&p->graph, 0) != hipSuccess)
         return WP_ERR_HIP;
     hipGraphNode_t dec = nullptr;
-    uint32_t npages32 = (uint32_t)p->npages, nitems32 = (uint32_t)p->nitems;
-    void *args[] = {&p->d_lists, &p->d_items, &npages32, &nitems32, &p->err};
+    uint32_t nitems32 = (uint32_t)p->nitems;
+    void *args[] = {&p->d_lists, &p->d_items, &nitems32, &p->err};
     hipKernelNodeParams kp = {};
     kp.func = const_cast<void *>(p->kernel);
     kp.gridDim = dim3(p->grid);
@@ -295,17 +218,22 @@ static int32_t build_graph(Plan *p)
 // Validates a registry and cuts it into work items: binary-packing runs of
 // run_units meta-blocks, single pages, tails; largest first.
 static bool build_items(const uint32_t *pool, uint32_t *out_base, const wp_list *h_lists, uint64_t nlists,
-                        int run_units, std::vector<DevList> &lists, std::vector<uint4> &items, uint64_t &npages)
+                        int run_units, std::vector<DevList> &lists, std::vector<uint4> &items)
 {
     lists.assign(nlists, DevList{});
-    std::vector<uint4> fp_items, bp_items, tail_items;
+    std::vector<uint4> unit_items, tail_items;
+    if (nlists > 0xFFFFFFFFull)
+        return false;
     for (uint64_t i = 0; i < nlists; ++i) {
         const wp_list &l = h_lists[i];
         if ((l.codec != WP_CODEC_BP && l.codec != WP_CODEC_FP) || l.reserved != 0 || (l.comp_off_words & 3u) ||
-            (l.out_off & 3u) || l.comp_words < kHdrWords || l.n > 0xFFFFFFFFull * 32ull)
+            l.comp_words < kHdrWords || l.n > 0xFFFFFFFFull * 32ull)
+            return false;
+        // the list's own destination, else its place in out_base
+        if (l.out != nullptr ? !aligned16(l.out) : (out_base == nullptr || (l.out_off & 3u)))
             return false;
         lists[i].comp = pool + l.comp_off_words;
-        lists[i].out = out_base + l.out_off;
+        lists[i].out = l.out != nullptr ? l.out : out_base + l.out_off;
         lists[i].comp_words = l.comp_words;
         lists[i].n = l.n;
         lists[i].codec = (uint32_t)l.codec;
@@ -316,17 +244,13 @@ static bool build_items(const uint32_t *pool, uint32_t *out_base, const wp_list 
             const uint64_t units = (nfull + kBpBlocks - 1) / kBpBlocks;
             for (uint64_t u = 0; u < units; u += (uint64_t)run_units) {
                 const uint64_t c = std::min<uint64_t>((uint64_t)run_units, units - u);
-                bp_items.push_back(make_uint4(li, kItemBpRun, (uint32_t)u, (uint32_t)c));
+                unit_items.push_back(make_uint4(li, kItemBpRun, (uint32_t)u, (uint32_t)c));
             }
         } else {
             const uint64_t units = (nfull + kFpBlocks - 1) / kFpBlocks;
             for (uint64_t u = 0; u < units; ++u) {
                 const uint64_t nb = std::min<uint64_t>(kFpBlocks, nfull - u * kFpBlocks);
-                // w: blocks (for ordering); small pages go to single wavefronts
-                if (nb <= kSmallPageBlocks)
-                    bp_items.push_back(make_uint4(li, kItemFpSmall, (uint32_t)u, (uint32_t)nb));
-                else
-                    fp_items.push_back(make_uint4(li, kItemFpPage, (uint32_t)u, (uint32_t)nb));
+                unit_items.push_back(make_uint4(li, kItemFpPage, (uint32_t)u, (uint32_t)nb));
             }
         }
         // a tail has an item of its own only in a list without full blocks;
@@ -334,22 +258,14 @@ static bool build_items(const uint32_t *pool, uint32_t *out_base, const wp_list 
         if ((l.n % kBlock) && nfull == 0)
             tail_items.push_back(make_uint4(li, kItemTail, 0, 0));
     }
-    if (nlists > 0xFFFFFFFFull)
-        return false;
-    // largest items first: pages (most blocks first), runs (longest first), then tails
-    std::stable_sort(fp_items.begin(), fp_items.end(), [](const uint4 &a, const uint4 &b) { return a.w > b.w; });
-    // wavefront items by blocks: a run of w meta-blocks holds up to 16 w
+    // largest first by blocks (a run of w meta-blocks holds up to 16 w), then tails
     auto blocks = [](const uint4 &a) { return a.y == kItemBpRun ? 16u * a.w : a.w; };
-    std::stable_sort(bp_items.begin(), bp_items.end(),
+    std::stable_sort(unit_items.begin(), unit_items.end(),
                      [&](const uint4 &a, const uint4 &b) { return blocks(a) > blocks(b); });
-    items.reserve(fp_items.size() + bp_items.size() + tail_items.size());
-    items.insert(items.end(), fp_items.begin(), fp_items.end());
-    npages = fp_items.size();
-    items.insert(items.end(), bp_items.begin(), bp_items.end());
+    items.reserve(unit_items.size() + tail_items.size());
+    items.insert(items.end(), unit_items.begin(), unit_items.end());
     items.insert(items.end(), tail_items.begin(), tail_items.end());
-    if (items.size() > 0xFFFFFFF0ull)
-        return false;
-    return true;
+    return items.size() <= 0xFFFFFFF0ull;
 }
 
 }  // namespace wp
@@ -359,7 +275,7 @@ using namespace wp;
 extern "C" int32_t wp_batch_plan(const uint32_t *pool, uint32_t *out_base, const wp_list *h_lists, uint64_t nlists,
                                  const wp_tune *tune, void **h_plan, void *stream)
 {
-    if (h_plan == nullptr || (nlists > 0 && (pool == nullptr || out_base == nullptr || h_lists == nullptr)))
+    if (h_plan == nullptr || (nlists > 0 && (pool == nullptr || h_lists == nullptr)))
         return WP_ERR_INVALID_ARG;
     *h_plan = nullptr;
     if (!aligned16(pool) || !aligned16(out_base))
@@ -384,16 +300,14 @@ extern "C" int32_t wp_batch_plan(const uint32_t *pool, uint32_t *out_base, const
         return WP_ERR_HIP;
     std::vector<DevList> lists;
     std::vector<uint4> items;
-    uint64_t npages = 0;
-    if (!build_items(pool, out_base, h_lists, nlists, t.run_units, lists, items, npages) ||
-        grid_for(npages, items.size(), t.waves) > kMaxGrid)
+    if (!build_items(pool, out_base, h_lists, nlists, t.run_units, lists, items) ||
+        grid_for(items.size(), t.waves) > kMaxGrid)
         return WP_ERR_INVALID_ARG;
     Plan *p = new Plan();
     p->device = ds->device;
     p->err = ds->err;
     p->nlists = nlists;
     p->nitems = items.size();
-    p->npages = npages;
     p->waves = t.waves;
     p->vpl = t.vpl;
     p->depth = t.depth;
@@ -402,7 +316,7 @@ extern "C" int32_t wp_batch_plan(const uint32_t *pool, uint32_t *out_base, const
     p->run_units = t.run_units;
     p->cap_lists = std::max<uint64_t>(1, lists.size());
     p->cap_items = std::max<uint64_t>(1, items.size());
-    p->grid = (uint32_t)grid_for(npages, items.size(), t.waves);
+    p->grid = (uint32_t)grid_for(items.size(), t.waves);
     hipStream_t st = as_stream(stream);
     if (hipMalloc(&p->d_lists, std::max<size_t>(1, lists.size()) * sizeof(DevList)) != hipSuccess ||
         hipMalloc(&p->d_items, std::max<size_t>(1, items.size()) * sizeof(uint4)) != hipSuccess) {
@@ -466,17 +380,16 @@ extern "C" int32_t wp_batch_replan(void *h_plan, const uint32_t *pool, uint32_t 
                                    uint64_t nlists, void *stream)
 {
     Plan *p = static_cast<Plan *>(h_plan);
-    if (p == nullptr || (nlists > 0 && (pool == nullptr || out_base == nullptr || h_lists == nullptr)) ||
-        !aligned16(pool) || !aligned16(out_base))
+    if (p == nullptr || (nlists > 0 && (pool == nullptr || h_lists == nullptr)) || !aligned16(pool) ||
+        !aligned16(out_base))
         return WP_ERR_INVALID_ARG;
     int d = -1;
     if (hipGetDevice(&d) != hipSuccess || d != p->device)
         return WP_ERR_INVALID_ARG;
     std::vector<DevList> lists;
     std::vector<uint4> items;
-    uint64_t npages = 0;
-    if (!build_items(pool, out_base, h_lists, nlists, p->run_units, lists, items, npages) ||
-        grid_for(npages, items.size(), p->waves) > kMaxGrid)
+    if (!build_items(pool, out_base, h_lists, nlists, p->run_units, lists, items) ||
+        grid_for(items.size(), p->waves) > kMaxGrid)
         return WP_ERR_INVALID_ARG;
     hipStream_t st = as_stream(stream);
     // the previous copy out of the pinned staging must have finished
@@ -534,8 +447,7 @@ extern "C" int32_t wp_batch_replan(void *h_plan, const uint32_t *pool, uint32_t 
         return WP_ERR_HIP;
     p->nlists = lists.size();
     p->nitems = items.size();
-    p->npages = npages;
-    p->grid = (uint32_t)grid_for(npages, items.size(), p->waves);
+    p->grid = (uint32_t)grid_for(items.size(), p->waves);
     // the graph baked in the old item count and grid
     if (p->exec)
         (void)hipGraphExecDestroy(p->exec), p->exec = nullptr;

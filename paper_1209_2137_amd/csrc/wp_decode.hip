@@ -9,9 +9,9 @@
 // BP32 streams (32-integer blocks) take the same kernel in its B32 mode,
 // SIMD-BP128 streams with the four-lane block layout in its V mode.
 //
-// Patched pages: one workgroup per page (see fp_page); FastPFOR streams
-// (exception arrays padded to 32 values) take the same kernel in its P32
-// mode.
+// Patched pages: one wavefront per page (fp_wave_page), a workgroup being
+// WAVES such pages side by side; FastPFOR streams (exception arrays padded
+// to 32 values) take the same kernel in its P32 mode.
 #include <mutex>
 #include <vector>
 
@@ -61,45 +61,52 @@ __global__ __launch_bounds__(64 * WAVES) void k_bp_decode(const uint32_t *__rest
         *err = kErrCorrupt;
 }
 
-template <int WAVES>
-union FpKernelLds {
-    FpLds<WAVES> fp;
-    TailLds<WAVES> tail;
+template <int KIND>
+union FpWaveItemLds {
+    FpWaveLds page;
+    SpWaveLds sp;  // SimplePFOR pages also hold a ring of decoded high parts
+    TailLds<1> tail;
+};
+template <>
+union FpWaveItemLds<kPageFp> {
+    FpWaveLds page;
+    TailLds<1> tail;
+};
+template <>
+union FpWaveItemLds<kPageFp32> {
+    FpWaveLds page;
+    TailLds<1> tail;
 };
 
-// One workgroup per page; the workgroup after the last page decodes the tail.
-template <int WAVES, bool P32 = false>
+// Wavefront w of workgroup g decodes page g * WAVES + w; the wavefront
+// after the last page decodes the tail. KIND: SIMD-FastPFOR, FastPFOR or
+// SimplePFOR pages.
+template <int WAVES, int KIND = kPageFp>
 __global__ __launch_bounds__(64 * WAVES) void k_fp_decode(const uint32_t *__restrict__ in, uint64_t in_words,
                                                           uint32_t *__restrict__ out, uint64_t n,
                                                           int *__restrict__ err)
 {
-    __shared__ FpKernelLds<WAVES> L;
+    __shared__ FpWaveItemLds<KIND> L[WAVES];
     ListHdr H;
-    if (!check_header(in, in_words, n, P32 ? kMagicFP32 : kMagicFP, kFpBlocks, H)) {
+    const uint32_t magic = KIND == kPageSp ? kMagicSP : KIND == kPageFp32 ? kMagicFP32 : kMagicFP;
+    if (!check_header(in, in_words, n, magic, kFpBlocks, H)) {
         if (blockIdx.x == 0 && threadIdx.x == 0)
             *err = kErrCorrupt;
         return;
     }
-    const uint64_t u = blockIdx.x;
+    const uint32_t wave = uniform(threadIdx.x >> 6);
+    const uint64_t u = (uint64_t)blockIdx.x * WAVES + wave;
     bool ok = true;
     if (u == H.units) {
         if (H.tail)
-            ok = decode_tail_entry<WAVES>(in, H, out, L.tail);
+            ok = decode_tail_entry<1, false>(in, H, out, L[wave].tail);
     } else if (u < H.units) {
-        const uint32_t off = in[kHdrWords + u];
-        const uint32_t end = (u + 1 < H.units) ? in[kHdrWords + u + 1] : H.tail_off;
-        uint32_t base[4] = {0u, 0u, 0u, 0u};
-        for (uint32_t s = 0; s < H.S; ++s)
-            base[s] = in[kHdrWords + H.ndir + u * H.S + s];
-        ok = off >= H.dir_end && end >= off && end <= H.total && (off & 3u) == 0;
-        const uint64_t left = H.nfull - u * kFpBlocks;
-        const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
-        if (ok)
-            ok = H.S == 1 ? fp_page<WAVES, 1, 3, P32>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp)
-               : H.S == 4 ? fp_page<WAVES, 4, 3, P32>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp)
-                          : fp_page<WAVES, 0, 3, P32>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp);
+        if constexpr (KIND == kPageSp)
+            ok = fp_unit<KIND>(in, H, u, out, L[wave].sp.fp, L[wave].sp.ring);
+        else
+            ok = fp_unit<KIND>(in, H, u, out, L[wave].page);
     }
-    if (!ok && threadIdx.x == 0)
+    if (!ok && lane_id() == 0)
         *err = kErrCorrupt;
 }
 
@@ -109,6 +116,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_fp_decode(const uint32_t *__rest
 static std::mutex g_mu;
 static std::vector<DevState> g_dev;
 static thread_local LaunchEvents t_events;
+
+// The error word kernels report corrupt streams into: one per device, in
+// the library's own code object (zero when the code object loads), so no
+// decoder call allocates. Host code reaches it through the address that
+// hipGetSymbolAddress returns for the current device, never through this
+// name.
+static __device__ __align__(16) int g_err_word[4];
 
 LaunchEvents take_launch_events()
 {
@@ -122,7 +136,9 @@ static Tune g_tune[3] = {{4, 4, kBpRunsPerCu, 2}, {4, 4, 0, 0}, {4, 4, kBpRunsPe
 
 static int tune_slot(int codec)
 {
-    return (codec == WP_CODEC_FP || codec == WP_CODEC_FP32) ? 1 : codec == WP_CODEC_BP32 ? 2 : 0;
+    return (codec == WP_CODEC_FP || codec == WP_CODEC_FP32 || codec == WP_CODEC_SP) ? 1
+           : codec == WP_CODEC_BP32                                                ? 2
+                                                                                   : 0;
 }
 
 DevState *dev_state()
@@ -135,17 +151,13 @@ DevState *dev_state()
         g_dev.resize(d + 1);
     DevState &s = g_dev[d];
     if (s.err == nullptr) {
-        int *e = nullptr;
-        if (hipMalloc(&e, 16) != hipSuccess)
+        void *e = nullptr;
+        if (hipGetSymbolAddress(&e, HIP_SYMBOL(g_err_word)) != hipSuccess || e == nullptr)
             return nullptr;
-        if (hipMemset(e, 0, 16) != hipSuccess) {
-            (void)hipFree(e);
-            return nullptr;
-        }
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess)
             cus = 256;
-        s.err = e;
+        s.err = static_cast<int *>(e);
         s.cus = cus;
         s.device = d;
     }
@@ -160,9 +172,8 @@ Tune decode_tune(int codec)
 
 static bool valid_tune(int codec, int waves, int vpl)
 {
-    if (codec == WP_CODEC_BP || codec == WP_CODEC_BP32 || codec == WP_CODEC_BPV)
-        return (waves == 1 || waves == 2 || waves == 4 || waves == 8) && vpl == 4;
-    return (waves == 2 || waves == 4 || waves == 8) && vpl == 4;
+    (void)codec;
+    return (waves == 1 || waves == 2 || waves == 4 || waves == 8) && vpl == 4;
 }
 
 template <int WAVES, int DEPTH, bool B32 = false, bool V = false>
@@ -174,14 +185,18 @@ static void launch_bp(uint64_t grid, hipStream_t st, const uint32_t *in, uint64_
 }
 
 template <int WAVES>
-static void launch_fp(bool p32, uint64_t grid, hipStream_t st, const uint32_t *in, uint64_t in_words, uint32_t *out,
+static void launch_fp(int kind, uint64_t grid, hipStream_t st, const uint32_t *in, uint64_t in_words, uint32_t *out,
                       uint64_t n, int *err)
 {
-    if (p32)
-        launch_timed(k_fp_decode<WAVES, true>, dim3((uint32_t)grid), dim3(64 * WAVES), st, in, in_words, out, n,
+    if (kind == kPageFp32)
+        launch_timed(k_fp_decode<WAVES, kPageFp32>, dim3((uint32_t)grid), dim3(64 * WAVES), st, in, in_words, out,
+                     n, err);
+    else if (kind == kPageSp)
+        launch_timed(k_fp_decode<WAVES, kPageSp>, dim3((uint32_t)grid), dim3(64 * WAVES), st, in, in_words, out, n,
                      err);
     else
-        launch_timed(k_fp_decode<WAVES>, dim3((uint32_t)grid), dim3(64 * WAVES), st, in, in_words, out, n, err);
+        launch_timed(k_fp_decode<WAVES, kPageFp>, dim3((uint32_t)grid), dim3(64 * WAVES), st, in, in_words, out, n,
+                     err);
 }
 
 static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
@@ -196,7 +211,7 @@ static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, u
     DevState *ds = dev_state();
     if (ds == nullptr)
         return WP_ERR_HIP;
-    const bool paged = codec == WP_CODEC_FP || codec == WP_CODEC_FP32;
+    const bool paged = codec == WP_CODEC_FP || codec == WP_CODEC_FP32 || codec == WP_CODEC_SP;
     const uint64_t per = paged ? kFpBlocks : kBpBlocks;
     const uint64_t nfull = n / kBlock;
     const uint64_t units = (nfull + per - 1) / per;
@@ -233,17 +248,20 @@ static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, u
 #undef WP_BP
 #undef WP_BP_D
     } else {
-        uint64_t grid = units + has_tail;
+        // one wavefront per page, then one for the tail
+        uint64_t grid = (units + has_tail + t.waves - 1) / t.waves;
         grid = grid ? grid : 1;
         if (grid > 0x7FFFFFFFull)
             return WP_ERR_INVALID_ARG;
-        const bool p32 = codec == WP_CODEC_FP32;
-        if (t.waves == 2)
-            launch_fp<2>(p32, grid, st, in, in_words, out, n, ds->err);
+        const int kind = codec == WP_CODEC_FP32 ? kPageFp32 : codec == WP_CODEC_SP ? kPageSp : kPageFp;
+        if (t.waves == 1)
+            launch_fp<1>(kind, grid, st, in, in_words, out, n, ds->err);
+        else if (t.waves == 2)
+            launch_fp<2>(kind, grid, st, in, in_words, out, n, ds->err);
         else if (t.waves == 4)
-            launch_fp<4>(p32, grid, st, in, in_words, out, n, ds->err);
+            launch_fp<4>(kind, grid, st, in, in_words, out, n, ds->err);
         else
-            launch_fp<8>(p32, grid, st, in, in_words, out, n, ds->err);
+            launch_fp<8>(kind, grid, st, in, in_words, out, n, ds->err);
     }
     return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
 }
@@ -274,6 +292,12 @@ extern "C" int32_t fastpfor32_decode(const uint32_t *in, uint64_t in_words, uint
     return decode_common(WP_CODEC_FP32, in, in_words, out, n, stream);
 }
 
+extern "C" int32_t simplepfor_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
+                                     void *stream)
+{
+    return decode_common(WP_CODEC_SP, in, in_words, out, n, stream);
+}
+
 extern "C" int32_t bp_vertical_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
                                       void *stream)
 {
@@ -283,7 +307,7 @@ extern "C" int32_t bp_vertical_decode(const uint32_t *in, uint64_t in_words, uin
 extern "C" int32_t wp_set_decode_tune(int32_t codec, int32_t waves, int32_t vpl, int32_t depth, int32_t wg_per_cu)
 {
     if ((codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32 && codec != WP_CODEC_FP32 &&
-         codec != WP_CODEC_BPV) ||
+         codec != WP_CODEC_BPV && codec != WP_CODEC_SP) ||
         !valid_tune(codec, waves, vpl) || wg_per_cu < 0 ||
         wg_per_cu > 1024 || depth < 0 || depth == 1 || depth > 4)
         return WP_ERR_INVALID_ARG;
@@ -335,10 +359,11 @@ extern "C" const char *wp_strerror(int32_t code)
 extern "C" uint64_t wp_max_compressed_words(int32_t codec, uint64_t n)
 {
     if (codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32 && codec != WP_CODEC_FP32 &&
-        codec != WP_CODEC_BPV)
+        codec != WP_CODEC_BPV && codec != WP_CODEC_SP)
         return 0;
     const uint64_t nfull = n / kBlock, tail = n % kBlock;
-    const uint64_t per = (codec == WP_CODEC_FP || codec == WP_CODEC_FP32) ? kFpBlocks : kBpBlocks;
+    const uint64_t per = (codec == WP_CODEC_FP || codec == WP_CODEC_FP32 || codec == WP_CODEC_SP) ? kFpBlocks
+                                                                                                 : kBpBlocks;
     const uint64_t units = (nfull + per - 1) / per;
     uint64_t w = kHdrWords + ((5 * (units + 1) + 3) & ~3ull);
     if (codec == WP_CODEC_BP || codec == WP_CODEC_BPV) {
@@ -347,6 +372,11 @@ extern "C" uint64_t wp_max_compressed_words(int32_t codec, uint64_t n)
         // a descriptor word per meta-block, every block at 32 bits, at most
         // three words of padding per unit
         w += units * 3 + nfull * (1 + 128);
+    } else if (codec == WP_CODEC_SP) {
+        // page header 4 words and 3 words of padding; packed <= 128 words per
+        // block; metadata <= 131 bytes per block + 16 bytes padding; at most
+        // one 64-bit Simple-8b word (two words) per exception
+        w += units * (4 + 3 + 4) + nfull * (128 + 33 + 1 + 2 * 128);
     } else {
         // page header <= 36 words; metadata <= 130 bytes per block + 16 bytes
         // padding; packed <= 128 words per block; exception bits of a block

@@ -35,6 +35,7 @@ constexpr uint32_t kMagicBP32 = 0x32335057u;  // "WP32"
 constexpr uint32_t kB32 = 32;                 // BP32 block length (Section 6.2)
 constexpr uint32_t kMagicFP32 = 0x33465057u;  // "WPF3"
 constexpr uint32_t kMagicBPV = 0x31565057u;   // "WPV1"
+constexpr uint32_t kMagicSP = 0x31535057u;    // "WPS1"
 
 // Words of a page's exception array of `cnt` values at k bits, padded to a
 // multiple of 128 values (SIMD-FastPFOR) or of 32 (FastPFOR, P32); either
@@ -203,39 +204,6 @@ __device__ __forceinline__ bool check_header(const uint32_t *__restrict__ in, ui
 // ------------------------------------------------------------------------
 // LDS arena shared by all roles (a workgroup plays one role at a time).
 
-// Page tables of a patched page (shared by the encoder and the decoder)
-// plus, for the decoder, each wavefront's staging and transposition areas.
-// The per-block tables are dead once the block records are built, so the
-// passes' areas overlay them.
-template <int WAVES>
-struct FpLds {
-    union {
-        struct {
-            uint32_t stage[WAVES][2 * kBlock + 4];  // a wavefront's two blocks of packed words (+1 word)
-            uint32_t xp[WAVES][2 * kBlock];         // a wavefront's two blocks, transposed and patched
-        };
-        struct {
-            uint8_t b[kFpBlocks];
-            uint8_t mb[kFpBlocks];
-            uint8_t c[kFpBlocks];
-            uint32_t blkoff[kFpBlocks + 1];  // word offset of each block in the packed region
-            uint32_t posoff[kFpBlocks + 1];  // offset of each block's positions
-            uint32_t rank[kFpBlocks];        // index of the block's first exception in its array
-        };
-    };
-    // per block: {b | k << 8 | c << 16, packed word offset, bit offset of its
-    // first exception's high part, position offset}; zero past the last block
-    // (the passes fetch up to four passes of 2 * WAVES blocks ahead)
-    uint4 rec[kFpBlocks + 8 * WAVES];
-    uint32_t ktot[WAVES][33];
-    uint32_t kcar[33];
-    uint32_t excbase[33];            // word offset of array k from the page start
-    uint32_t kcnt[33];
-    uint32_t stot[WAVES][2];
-    uint32_t wtot[2][WAVES][4];
-    uint32_t bad;
-};
-
 template <int WAVES>
 struct TailLds {
     uint32_t words[(kMaxTailBytes + 3) / 4 + 4];
@@ -366,86 +334,6 @@ __device__ __forceinline__ bool decode_tail_entry(const uint32_t *__restrict__ i
     return tail_decode<WAVES, WG>(in + off, H.tail_bytes, H.tail, H.S, base, out + H.nfull * kBlock, L);
 }
 
-// Tables of a patched page from its per-block metadata L.b, L.mb, L.c
-// (entries from nb to the end of its last round of T blocks hold 0): block
-// offsets in the packed region (exclusive sum of 4*b), offsets into the position bytes
-// (exclusive sum of c) and, per block, the index of its first exception in
-// array k = maxb - b -- exceptions are appended to their array in block
-// order (Section 5), so this is the number of exceptions of earlier blocks
-// with the same k. Per-k totals accumulate in L.kcar (zeroed by the caller,
-// as is L.ktot). Rounds of T blocks; within a wavefront the same-k ranks
-// come from one masked scan per distinct k (ballot loop).
-template <int WAVES>
-__device__ __forceinline__ void fp_tables(FpLds<WAVES> &L, uint32_t nb, uint32_t &tot_words, uint32_t &tot_pos)
-{
-    constexpr int T = 64 * WAVES;
-    const uint32_t tid = threadIdx.x;
-    const uint32_t lane = lane_id();
-    const uint32_t wave = uniform(tid >> 6);
-    uint32_t carry_w = 0, carry_p = 0;
-    for (uint32_t r0 = 0; r0 < nb; r0 += T) {
-        const uint32_t t = r0 + tid;
-        const uint32_t bw = 4u * L.b[t];
-        const uint32_t cc = L.c[t];
-        const uint32_t kk = (uint32_t)L.mb[t] - (uint32_t)L.b[t];
-        const uint32_t iw = wave_scan_incl(bw);
-        const uint32_t ip = wave_scan_incl(cc);
-        if (lane == 63) {
-            L.stot[wave][0] = iw;
-            L.stot[wave][1] = ip;
-        }
-        // rank among the wave's earlier blocks of the same k
-        uint32_t rk = 0;
-        uint64_t todo = ballot(cc > 0);
-        while (todo) {
-            const uint32_t lead = (uint32_t)__builtin_ctzll(todo);
-            const uint32_t k0 = wave_read(kk, lead);
-            const bool mine = cc > 0 && kk == k0;
-            const uint64_t mm = ballot(mine);
-            const uint32_t x = mine ? cc : 0u;
-            const uint32_t incl = wave_scan_incl(x);
-            if (mine)
-                rk = incl - x;
-            if (lane == 0)
-                L.ktot[wave][k0 > 32 ? 0 : k0] = wave_read(incl, 63);
-            todo &= ~mm;
-        }
-        __syncthreads();
-        uint32_t bw_before = carry_w, p_before = carry_p, all_w = 0, all_p = 0, k_before = 0;
-        for (int w = 0; w < WAVES; ++w) {
-            const uint32_t a = L.stot[w][0], c2 = L.stot[w][1];
-            if (w < (int)wave) {
-                bw_before += a;
-                p_before += c2;
-            }
-            all_w += a;
-            all_p += c2;
-        }
-        if (cc > 0 && kk <= 32) {
-            k_before = L.kcar[kk];
-            for (int w = 0; w < (int)wave; ++w)
-                k_before += L.ktot[w][kk];
-        }
-        L.blkoff[t] = bw_before + iw - bw;
-        L.posoff[t] = p_before + ip - cc;
-        L.rank[t] = k_before + rk;
-        carry_w += all_w;
-        carry_p += all_p;
-        __syncthreads();
-        if (tid < 33) {
-            uint32_t s = 0;
-            for (int w = 0; w < WAVES; ++w) {
-                s += L.ktot[w][tid];
-                L.ktot[w][tid] = 0;
-            }
-            L.kcar[tid] += s;
-        }
-        __syncthreads();
-    }
-    tot_words = carry_w;
-    tot_pos = carry_p;
-}
-
 // Prefix sum of one pass held as four consecutive integers per lane, in
 // place. stride 1: lane-serial sums, a wave scan of the lane totals, plus
 // the carry; stride 4: one wave scan per residue class (each lane holds
@@ -475,431 +363,430 @@ __device__ __forceinline__ void scan_wave4(uint32_t (&x)[4], uint32_t (&carry)[4
 }
 
 // ------------------------------------------------------------------------
-// Patched pages (Section 5): decoding a pair of blocks in one wavefront.
+// Patched page (Section 5) decoded by one wavefront, 1..512 blocks, with no
+// workgroup barrier: the page is decoded in block order, four blocks (512
+// integers) per pass, the prefix sum carried from the page's stored base.
 //
-// Every block of a page is described by one 16-byte record {b | k << 8 |
-// c << 16, packed word offset, bit offset of its first exception's high
-// part, position offset}, k = maxb - b; the record arrays are zero-padded
-// past the page's last block, so fetching beyond it reads nothing. A
-// wavefront takes two blocks at a time and unpacks them as the
-// binary-packing decoder does (lanes 0..31 the first, 32..63 the second,
-// strided fields, LDS transpose); lane e patches exception e of the pair
-// (position byte and k-bit high part, OR-ed in above bit b; a pair with
-// more than 64 exceptions patches the rest in a slower loop). Each lane
-// reads the record of its own block and the record of its exception's
-// block; the pair's packed words, one exception per lane and everything
-// needed to place it are fetched by `fetch` into registers ahead of use.
-struct FpPairFetch {
-    uint32_t bA, cA, ce;      // width and exceptions of block A, exceptions of the pair (uniform)
-    uint4 pk;                 // the pair's packed words, 16 bytes per lane
-    uint32_t pos, lo, hi;     // exception `lane`: position byte, words of its high part
-    // exception `lane`: bit shift of its high part | its block's b << 8 |
-    // 128 * (its block is B) << 16; bits 24..29: the width of the lane's own
-    // block (lanes 0..31 block A, 32..63 block B)
-    uint32_t em;
-    uint32_t km;              // exception `lane`: mask of its k high bits
+// Block records {b | k << 8 | c << 16, word offset in the packed region,
+// bit offset of the block's first exception's high part from the page
+// start, index of its first exception in the page} are built a round of 64
+// blocks ahead, lane = block: wave scans of 4b and c give the offsets, and
+// the rank of the block's exceptions inside array k = maxb - b is the
+// count of earlier rounds (per k, in LDS) plus one masked scan per distinct
+// k of the round (exceptions are appended to array k in block order). The
+// records of two rounds live in an LDS ring; a record past the last block
+// holds b = c = 0 and the running offsets, so the passes need no special
+// case at the page end.
+//
+// A pass: lanes 0..31 unpack blocks A and C, lanes 32..63 blocks B and D;
+// lane q takes integers q, q+32, q+64, q+96 of its block (integer q + 32m
+// starts at bit q*b + 32*m*b: word (q*b >> 5) + m*b at the same shift), one
+// funnel shift of two LDS words each. The values go to the pass's area in
+// block order, lane e ORs in exception e of the pass (its high part
+// shifted left by b), then lane l reads integers 4l..4l+3 and 256+4l..
+// 256+4l+3 for the prefix sum and two 16-byte stores. The packed words of
+// a pass, and for each lane its exception's position byte and its high
+// part (or the two words holding it), are fetched two passes ahead into
+// named register slots.
+//
+// Three page kinds share this: SIMD-FastPFOR (exception arrays padded to
+// 128 values), FastPFOR (padded to 32) and SimplePFOR, whose high parts
+// are one Simple-8b array over the page in block order (Section 5, and
+// the Simple-8b modes of Section 2). A SimplePFOR page is decoded into an
+// LDS ring of high parts as the passes need them: a wavefront takes up to
+// 64 Simple-8b words at a time (lane i word i), a wave scan of the counts
+// their selectors give places each word's integers, and the words are
+// loaded one batch ahead.
+enum : int { kPageFp = 0, kPageFp32 = 1, kPageSp = 2 };
+constexpr uint32_t kSpRing = 2048;  // high parts held by a SimplePFOR page's ring
+
+struct alignas(16) FpWaveLds {
+    uint32_t buf[4 * kBlock + 4];  // a pass's packed words, then its integers in block order
+    uint4 rec[2][64];              // block records of two rounds of 64 blocks
+    uint32_t kcar[33];             // exceptions of the rounds built so far, per array k
+    uint32_t excb[33];             // page word offset of array k
 };
 
-struct FpPair {
-    const uint32_t *page;
-    const uint4 *rec;  // the page's block records (LDS, zero-padded)
-    uint32_t hdr_w, pos_at;
-    BufRsrc rpg;
-    uint32_t *stg, *xpw;  // this wavefront's staging and transposition areas (LDS)
-
-    static constexpr uint32_t kOut = 0xfffffff0u;  // a buffer offset beyond every page: reads nothing
-
-    // blocks jA, jA + 1 (records past the page are zero: no words, no exceptions)
-    __device__ __forceinline__ FpPairFetch fetch(uint32_t jA) const
-    {
-        const uint32_t lane = lane_id();
-        FpPairFetch f;
-        const uint4 rm = rec[jA + (lane >> 5)];
-        const uint32_t a0 = wave_read(rm.x, 0), b0 = wave_read(rm.x, 32), ay = wave_read(rm.y, 0);
-        f.bA = a0 & 255u;
-        f.cA = a0 >> 16;
-        f.ce = f.cA + (b0 >> 16);
-        const BufRsrc rp = make_rsrc(page + hdr_w + ay, 16u * (f.bA + (b0 & 255u)));
-        f.pk = buf_load_u4(rp, lane * 16u);
-        const bool inA = lane < f.cA;
-        const uint4 re = rec[jA + (inA ? 0u : 1u)];
-        const uint32_t idx = lane - (inA ? 0u : f.cA);
-        const uint32_t k = (re.x >> 8) & 255u;
-        const uint32_t bit = re.z + idx * k;
-        const bool any = lane < f.ce;
-        const uint32_t poff = any ? pos_at + re.w + idx : kOut;
-        const uint32_t woff = any ? (bit >> 5) * 4u : kOut;
-        f.pos = __builtin_amdgcn_raw_buffer_load_b8(rpg, (int)poff, 0, 0);
-        f.lo = buf_load_u32(rpg, woff);
-        f.hi = buf_load_u32(rpg, woff + 4u);
-        f.em = (bit & 31u) | ((re.x & 255u) << 8) | (inA ? 0u : (kBlock << 16)) | ((rm.x & 255u) << 24);
-        f.km = width_mask(k);
-        return f;
-    }
-
-    // Unpacks and patches blocks jA, jA + 1 from f into the transposition
-    // area; after it, lane l's integers 4l..4l+3 of the pair are read with
-    // read_back(). f may be refilled once this returns. Exception positions
-    // that are not below 128 or not ascending inside their block set `bad`
-    // (a per-lane flag the caller reduces once per page).
-    __device__ __forceinline__ void unpack_patch(const FpPairFetch &f, uint32_t jA, bool &bad) const
-    {
-        const uint32_t lane = lane_id();
-        const uint32_t q = lane & 31u;
-        const bool hi = lane >= 32u;
-        *reinterpret_cast<uint4 *>(&stg[4 * lane]) = f.pk;
-        wave_lds_order();
-        const uint32_t b = f.em >> 24;
-        const uint32_t qb = q * b;
-        const uint32_t w0 = (hi ? 4u * f.bA : 0u) + (qb >> 5);
-        const uint32_t mask = width_mask(b);
-        uint32_t v[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const uint32_t wi = w0 + m * b;
-            v[m] = __builtin_amdgcn_alignbit(stg[wi + 1], stg[wi], qb) & mask;
-        }
-        uint32_t *const xw = &xpw[lane + (hi ? 96u : 0u)];
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-            xw[32 * m] = v[m];
-        wave_lds_order();
-        // exceptions: one per lane, the rest (more than 64 in the pair) in rounds
-        const uint32_t prev = (uint32_t)__shfl_up((int)f.pos, 1, 64);
-        if (lane < f.ce) {
-            const uint32_t hv = __builtin_amdgcn_alignbit(f.hi, f.lo, f.em) & f.km;
-            atomicOr(&xpw[((f.em >> 16) & 255u) + (f.pos & (kBlock - 1u))], hv << ((f.em >> 8) & 255u));
-            bad = bad || f.pos >= kBlock || (lane != 0 && lane != f.cA && prev >= f.pos);
-        }
-        for (uint32_t e0 = 64; e0 < f.ce; e0 += 64) {
-            const uint32_t e = e0 + lane;
-            if (e < f.ce) {
-                const bool inA = e < f.cA;
-                const uint4 re = rec[jA + (inA ? 0u : 1u)];
-                const uint32_t idx = inA ? e : e - f.cA;
-                const uint32_t k = (re.x >> 8) & 255u;
-                const uint32_t bit = re.z + idx * k;
-                const uint8_t *const pb = reinterpret_cast<const uint8_t *>(page) + pos_at + re.w + idx;
-                const uint32_t pos = pb[0], pprev = idx > 0 ? pb[-1] : 0u;
-                bad = bad || pos >= kBlock || (idx > 0 && pprev >= pos);
-                const uint32_t lo = page[bit >> 5];
-                const uint32_t hw = (bit & 31u) + k > 32u ? page[(bit >> 5) + 1u] : 0u;
-                const uint32_t hv = __builtin_amdgcn_alignbit(hw, lo, bit) & width_mask(k);
-                atomicOr(&xpw[(inA ? 0u : kBlock) + (pos & (kBlock - 1u))], hv << (re.x & 255u));
-            }
-        }
-    }
-
-    __device__ __forceinline__ void read_back(uint32_t (&x)[4]) const
-    {
-        wave_lds_order();
-        const uint4 t = *reinterpret_cast<const uint4 *>(&xpw[4 * lane_id()]);
-        x[0] = t.x;
-        x[1] = t.y;
-        x[2] = t.z;
-        x[3] = t.w;
-    }
+struct alignas(16) SpWaveLds {
+    FpWaveLds fp;
+    uint32_t ring[kSpRing];  // decoded high parts, by their index in the page mod kSpRing
 };
 
-// Patched page (Section 5) decoded by a whole workgroup. `page` points at
-// the page header (16-byte aligned), `nwords` its length, `nb` the number
-// of blocks it must hold. Setup (bounded by nb): the exception-array
-// directory, the block metadata, block offsets in the packed region,
-// offsets into the position bytes and, per block, the index of its first
-// exception inside its array k = maxb - b (exceptions are appended to
-// array k in block order, so this is the number of exceptions of earlier
-// blocks with the same k); then the block records. Then passes of 2 * WAVES
-// blocks: wavefront w decodes pair w of the pass (FpPair), the words and
-// exceptions of the next SLOTS - 1 passes in flight; one barrier per pass
-// hands the wavefront totals over for the prefix sum.
-template <int WAVES, uint32_t S, int SLOTS = 3, bool P32 = false>
-__device__ __forceinline__ bool fp_page(const uint32_t *__restrict__ page, uint32_t nwords, uint32_t nb,
-                        const uint32_t (&base)[4], uint32_t *__restrict__ out, FpLds<WAVES> &L)
+// What a pass needs, fetched ahead (per lane unless noted).
+struct FpFetch {
+    uint4 pk0, pk1;        // the pass's packed words: words 4l..4l+3 and 256+4l..256+4l+3
+    uint32_t u0, u1;       // blocks A|B (half 0), C|D (half 1): the lane's block width | its first word << 8
+    uint32_t pos, lo, hi;  // exception `lane` of the pass: position byte, the words holding its high
+                           // part (SimplePFOR: lo is the high part itself)
+    uint32_t em;           // its bit shift | (b & 31) << 8 | its block in the pass << 16 | first of its block << 18
+    uint32_t km;           // mask of its k high bits
+    uint32_t ce, e0;       // uniform: exceptions of the pass, index of its first exception in the page
+};
+
+constexpr uint32_t kOutOfRange = 0xfffffff0u;  // a buffer offset beyond every page: reads nothing
+
+__device__ __forceinline__ uint32_t buf_load_u8(BufRsrc rs, uint32_t byte_off)
 {
-    constexpr int T = 64 * WAVES;
-    static_assert(T <= (int)kFpBlocks, "setup maps at most one thread per block and round");
-    const uint32_t tid = threadIdx.x;
-    const uint32_t lane = lane_id();
-    const uint32_t wave = uniform(tid >> 6);
-    if (nwords < 4)
-        return false;
-    const uint32_t h_nb = uniform(page[0]), packed_words = uniform(page[1]), meta_bytes = uniform(page[2]),
-                   bitset = uniform(page[3]);
-    const uint32_t nset = __builtin_popcount(bitset);
-    const uint32_t hdr_w = pad4(4 + nset);
-    const uint32_t meta_w = ((meta_bytes + 15u) / 16u) * 4u;
-    if (h_nb != nb || nb == 0 || hdr_w > nwords || packed_words > nwords - hdr_w ||
-        meta_bytes < 3 * nb || meta_bytes > 3 * nb + 127 * nb || meta_w > nwords - hdr_w - packed_words ||
-        (packed_words & 3u))
-        return false;
-    const uint32_t exc_at = hdr_w + packed_words + meta_w;
-    const uint8_t *meta = reinterpret_cast<const uint8_t *>(page + hdr_w + packed_words);
-
-    // exception array directory: lanes 0..31 of wave 0 own k = lane + 1
-    if (wave == 0) {
-        const bool kl = lane < 32;
-        const uint32_t k = lane + 1;
-        const bool set = kl && ((bitset >> (lane & 31u)) & 1u);
-        const uint32_t ci = kl ? (uint32_t)__builtin_popcount(bitset & ((1u << (lane & 31u)) - 1u)) : 0u;
-        const uint32_t cnt = set ? page[4 + ci] : 0u;
-        const bool badk = set && (cnt == 0 || cnt > nb * kBlock);
-        const uint32_t wk = (set && !badk) ? exc_array_words<P32>(cnt, k) : 0u;
-        const uint32_t incl = wave_scan_incl(wk);
-        const uint32_t tot = wave_read(incl, 63);
-        const uint64_t anybad = ballot(badk);
-        if (kl) {
-            L.excbase[k] = exc_at + incl - wk;
-            L.kcnt[k] = cnt;
-        }
-        if (lane < 33)
-            L.kcar[lane] = 0;
-        if (lane == 32) {
-            L.excbase[0] = exc_at;
-            L.kcnt[0] = 0;
-        }
-        if (lane == 0)
-            L.bad = (anybad != 0 || (P32 ? pad4(exc_at + tot) : exc_at + tot) != nwords) ? 1u : 0u;
-    }
-    const uint32_t nbr = ((nb + T - 1) / T) * T;  // the rounds of the table pass (entries beyond nb are 0)
-    for (uint32_t t = tid; t < nbr; t += T) {
-        uint32_t b = 0, mb = 0, c = 0;
-        if (t < nb) {
-            b = meta[t];
-            mb = meta[nb + t];
-            c = meta[2 * nb + t];
-        }
-        L.b[t] = (uint8_t)b;
-        L.mb[t] = (uint8_t)mb;
-        L.c[t] = (uint8_t)c;
-    }
-    for (uint32_t i = tid; i < WAVES * 33; i += T)
-        (&L.ktot[0][0])[i] = 0;
-    __syncthreads();
-    // validate block metadata
-    for (uint32_t t = tid; t < nb; t += T) {
-        const uint32_t b = L.b[t], mb = L.mb[t], c = L.c[t];
-        if (b > 32 || mb > 32 || mb < b || c >= kBlock || ((c == 0) != (mb == b)))
-            L.bad = 1;
-    }
-    uint32_t carry_w = 0, carry_p = 0;
-    fp_tables<WAVES>(L, nb, carry_w, carry_p);
-    if (tid == 0) {
-        L.blkoff[kFpBlocks] = carry_w;
-        if (carry_w != packed_words || 3 * nb + carry_p != meta_bytes)
-            L.bad = 1;
-    }
-    if (tid >= 1 && tid <= 32 && L.kcar[tid] != L.kcnt[tid])
-        L.bad = 1;
-    __syncthreads();
-    if (L.bad)
-        return false;
-
-    // block records (zero past the last block)
-    const uint32_t pos_at = (hdr_w + packed_words) * 4u + 3u * nb;  // byte offset of the positions
-    const BufRsrc rpg = make_rsrc(page, nwords * 4u);
-    for (uint32_t t = tid; t < nb + 8 * WAVES; t += T) {
-        if (t < nb) {
-            const uint32_t b = L.b[t], k = (uint32_t)L.mb[t] - b, c = L.c[t];
-            L.rec[t] = make_uint4(b | (k << 8) | (c << 16), L.blkoff[t],
-                                  L.excbase[k <= 32 ? k : 0] * 32u + L.rank[t] * k, L.posoff[t]);
-        } else {
-            L.rec[t] = make_uint4(0u, 0u, 0u, 0u);
-        }
-    }
-    __syncthreads();
-
-    // passes of 2 * WAVES blocks
-    constexpr uint32_t BPP = 2 * WAVES;
-    const FpPair pair{page, L.rec, hdr_w, pos_at, rpg, L.stage[wave], L.xp[wave]};
-    const BufRsrc rout = make_rsrc(out, nb * kBlock * 4u);
-    uint32_t carry[4] = {base[0], base[1], base[2], base[3]};
-    const uint32_t npass = (nb + BPP - 1) / BPP;
-    bool bad_pos = false;
-    // pass p from slot f; the slot is refilled with pass p + SLOTS as soon
-    // as its words and exceptions have been used (named slots, so nothing
-    // is copied between passes; with three, a wait for a slot's loads rarely
-    // covers the stores of the two passes issued after them)
-    static_assert(SLOTS == 2 || SLOTS == 3, "fetch slots");
-    auto run_pass = [&](uint32_t p, FpPairFetch &f) __attribute__((always_inline)) {
-        const uint32_t jA = p * BPP + 2u * wave;
-        pair.unpack_patch(f, jA, bad_pos);
-        f = pair.fetch((p + SLOTS) * BPP + 2u * wave);  // beyond the page it reads nothing
-        uint32_t x[4];
-        pair.read_back(x);
-        // prefix sum: inside the wavefront, then across wavefronts
-        if constexpr (S == 1) {
-            x[1] += x[0];
-            x[2] += x[1];
-            x[3] += x[2];
-            const uint32_t incl = wave_scan_incl(x[3]);
-            if (lane == 63)
-                L.wtot[p & 1][wave][0] = incl;
-            __syncthreads();
-            uint32_t before = carry[0], all = 0;
-#pragma unroll
-            for (int w = 0; w < WAVES; ++w) {
-                const uint32_t tw = uniform(L.wtot[p & 1][w][0]);
-                before += w < (int)wave ? tw : 0u;
-                all += tw;
-            }
-            const uint32_t add = incl - x[3] + before;
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                x[r] += add;
-            carry[0] += all;
-        } else if constexpr (S == 4) {
-            uint32_t incl[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                incl[c] = wave_scan_incl(x[c]);
-            if (lane == 63)
-                *reinterpret_cast<uint4 *>(&L.wtot[p & 1][wave][0]) = make_uint4(incl[0], incl[1], incl[2], incl[3]);
-            __syncthreads();
-            uint32_t before[4] = {carry[0], carry[1], carry[2], carry[3]};
-#pragma unroll
-            for (int w = 0; w < WAVES; ++w) {
-                const uint4 tw = *reinterpret_cast<const uint4 *>(&L.wtot[p & 1][w][0]);
-                const uint32_t tv[4] = {uniform(tw.x), uniform(tw.y), uniform(tw.z), uniform(tw.w)};
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    before[c] += w < (int)wave ? tv[c] : 0u;
-                    carry[c] += tv[c];
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                x[c] = incl[c] + before[c];
-        }
-        buf_store_u4(rout, lane * 16u, uniform(jA * (kBlock * 4u)), make_uint4(x[0], x[1], x[2], x[3]));
-    };
-    uint32_t p = 0;
-    if constexpr (SLOTS == 3) {
-        FpPairFetch f0 = pair.fetch(2u * wave), f1 = pair.fetch(BPP + 2u * wave),
-                    f2 = pair.fetch(2 * BPP + 2u * wave);
-        for (; p + 3 <= npass; p += 3) {
-            run_pass(p, f0);
-            run_pass(p + 1, f1);
-            run_pass(p + 2, f2);
-        }
-        if (p < npass)
-            run_pass(p, f0);
-        if (p + 1 < npass)
-            run_pass(p + 1, f1);
-    } else {
-        FpPairFetch f0 = pair.fetch(2u * wave), f1 = pair.fetch(BPP + 2u * wave);
-        for (; p + 2 <= npass; p += 2) {
-            run_pass(p, f0);
-            run_pass(p + 1, f1);
-        }
-        if (p < npass)
-            run_pass(p, f0);
-    }
-    const bool any_bad_pos = ballot(bad_pos) != 0;
-    if (lane == 0 && any_bad_pos)
-        L.bad = 1;
-    __syncthreads();
-    return L.bad == 0;
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs, (int)byte_off, 0, 0);
 }
 
-// A small patched page (nb <= 64 blocks) decoded by one wavefront, with no
-// workgroup barrier: the same setup with one lane per block (tables by wave
-// scans, ranks by one masked scan per distinct k), then the pairs in order
-// with the prefix sum carried inside the wavefront. Used by the batched
-// decoder for the short lists' pages.
-struct alignas(16) FpWaveLds {
-    uint32_t stage[2 * kBlock + 4];
-    uint32_t xp[2 * kBlock];
-    uint4 rec[64 + 8];  // zero past the last block (fetches run two pairs ahead)
-};
-
-template <uint32_t S, bool P32 = false>
-__device__ __forceinline__ bool fp_small_page(const uint32_t *__restrict__ page, uint32_t nwords, uint32_t nb,
-                              const uint32_t (&base)[4], uint32_t *__restrict__ out, FpWaveLds &L)
+// Lane i gets v of lane i - 1 (DPP wave_shr:1); lane 0 gets `first`.
+__device__ __forceinline__ uint32_t wave_shr1(uint32_t first, uint32_t v)
 {
+    return __builtin_amdgcn_update_dpp(first, v, 0x138, 0xf, 0xf, false);
+}
+
+// Simple-8b modes (Section 2's table): selector s -> count | bits << 8.
+__device__ __forceinline__ uint32_t s8_mode(uint32_t sel)
+{
+    // counts 240 120 60 30 20 15 12 10 8 7 6 5 4 3 2 1; bits 0 0 1 2 3 4 5 6 7 8 10 12 15 20 30 60
+    constexpr uint64_t kCnt0 = 0x0a0c0f141e3c78f0ull;  // selectors 0..7, one byte each
+    constexpr uint64_t kCnt1 = 0x0102030405060708ull;  // selectors 8..15
+    constexpr uint64_t kBit0 = 0x0605040302010000ull;
+    constexpr uint64_t kBit1 = 0x3c1e140f0c0a0807ull;
+    const uint32_t sh = 8u * (sel & 7u);
+    const uint32_t cnt = (uint32_t)(((sel & 8u) ? kCnt1 : kCnt0) >> sh) & 255u;
+    const uint32_t bits = (uint32_t)(((sel & 8u) ? kBit1 : kBit0) >> sh) & 255u;
+    return cnt | (bits << 8);
+}
+
+// Decodes the patched page at `page` (16-byte aligned, `nwords` words,
+// which must hold `nb` blocks) into out[0, 128 nb) with differential
+// coding of stride S from `base`. One wavefront; `ring` is the LDS ring of
+// a SimplePFOR page (KIND kPageSp), unused otherwise. Returns the page's
+// validity (uniform); every access stays inside the page, out[0, 128 nb)
+// and the wavefront's LDS whatever the page holds.
+template <uint32_t S, int KIND = kPageFp>
+__device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, uint32_t nwords, uint32_t nb,
+                                             const uint32_t (&base)[4], uint32_t *__restrict__ out, FpWaveLds &L,
+                                             uint32_t *ring = nullptr)
+{
+    constexpr bool SP = KIND == kPageSp;
     const uint32_t lane = lane_id();
-    if (nwords < 4 || nb == 0 || nb > 64)
+    if (nwords < 4 || nb == 0 || nb > kFpBlocks)
         return false;
+    // SIMD-FastPFOR / FastPFOR: [nblocks, packed_words, meta_bytes, bitset]
+    // + a count per non-empty array; SimplePFOR: [nblocks, packed_words,
+    // meta_bytes, Simple-8b words]
     const uint32_t h_nb = uniform(page[0]), packed_words = uniform(page[1]), meta_bytes = uniform(page[2]),
-                   bitset = uniform(page[3]);
+                   w3 = uniform(page[3]);
+    const uint32_t bitset = SP ? 0u : w3;
     const uint32_t nset = __builtin_popcount(bitset);
     const uint32_t hdr_w = pad4(4 + nset);
     const uint32_t meta_w = ((meta_bytes + 15u) / 16u) * 4u;
     if (h_nb != nb || hdr_w > nwords || packed_words > nwords - hdr_w || meta_bytes < 3 * nb ||
         meta_bytes > 3 * nb + 127 * nb || meta_w > nwords - hdr_w - packed_words || (packed_words & 3u))
         return false;
+    const uint32_t meta_at = (hdr_w + packed_words) * 4u;  // byte offset of the metadata
+    const uint32_t pos_at = meta_at + 3u * nb;             // byte offset of the positions
     const uint32_t exc_at = hdr_w + packed_words + meta_w;
-    const uint8_t *meta = reinterpret_cast<const uint8_t *>(page + hdr_w + packed_words);
-    // exception array directory: lane k - 1 owns array k
-    const bool kl = lane < 32;
-    const uint32_t kown = lane + 1;
-    const bool set = kl && ((bitset >> (lane & 31u)) & 1u);
-    const uint32_t ci = kl ? (uint32_t)__builtin_popcount(bitset & ((1u << (lane & 31u)) - 1u)) : 0u;
-    const uint32_t cnt = set ? page[4 + ci] : 0u;
-    const bool badk = set && (cnt == 0 || cnt > nb * kBlock);
-    const uint32_t wk = (set && !badk) ? exc_array_words<P32>(cnt, kown) : 0u;
-    const uint32_t kincl = wave_scan_incl(wk);
-    const uint32_t excb = exc_at + kincl - wk;  // lane k - 1: first word of array k
-    const uint32_t exc_end = exc_at + wave_read(kincl, 63);
-    bool bad = ballot(badk) != 0 || (P32 ? pad4(exc_end) : exc_end) != nwords;
-    // blocks: lane j owns block j
-    const bool own = lane < nb;
-    const uint32_t b = own ? meta[lane] : 0u, mb = own ? meta[nb + lane] : 0u, c = own ? meta[2 * nb + lane] : 0u;
-    bad = bad || ballot(own && (b > 32 || mb > 32 || mb < b || c >= kBlock || ((c == 0) != (mb == b)))) != 0;
-    const uint32_t k = own && mb >= b ? mb - b : 0u;
-    const uint32_t bincl = wave_scan_incl(4u * b), cincl = wave_scan_incl(c);
-    const uint32_t cnt_all = wave_read(wave_scan_incl(cnt), 63);
-    bad = bad || wave_read(bincl, 63) != packed_words || 3 * nb + wave_read(cincl, 63) != meta_bytes ||
-          wave_read(cincl, 63) != cnt_all;
-    // rank of each block's first exception in its array: one masked scan per distinct k
-    uint32_t rank = 0;
-    uint64_t todo = ballot(c > 0 && k >= 1 && k <= 32);
-    while (todo) {
-        const uint32_t lead = (uint32_t)__builtin_ctzll(todo);
-        const uint32_t k0 = wave_read(k, lead);
-        const bool mine = c > 0 && k == k0;
-        const uint64_t mm = ballot(mine);
-        const uint32_t xc = mine ? c : 0u;
-        const uint32_t incl = wave_scan_incl(xc);
-        if (mine)
-            rank = incl - xc;
-        bad = bad || wave_read(incl, 63) != wave_read(cnt, (int)k0 - 1);
-        todo &= ~mm;
-    }
-    const uint32_t eb = __shfl(excb, (int)(k >= 1 ? k - 1 : 0));
-    const uint32_t pos_at = (hdr_w + packed_words) * 4u + 3u * nb;
     const BufRsrc rpg = make_rsrc(page, nwords * 4u);
-    if (own)
-        L.rec[lane] = make_uint4(b | (k << 8) | (c << 16), bincl - 4u * b, (c > 0 ? eb * 32u + rank * k : 0u),
-                                 cincl - c);
-    if (lane < 8)
-        L.rec[nb + lane] = make_uint4(0u, 0u, 0u, 0u);
-    if (bad)
-        return false;
-    wave_lds_order();
-
-    const FpPair pair{page, L.rec, hdr_w, pos_at, rpg, L.stage, L.xp};
-    const BufRsrc rout = make_rsrc(out, nb * kBlock * 4u);
-    uint32_t carry[4] = {base[0], base[1], base[2], base[3]};
-    const uint32_t npass = (nb + 1) / 2;
-    bool bad_pos = false;
-    auto run_pass = [&](uint32_t p, FpPairFetch &f) __attribute__((always_inline)) {
-        pair.unpack_patch(f, 2u * p, bad_pos);
-        f = pair.fetch(2u * (p + 2));
-        uint32_t x[4];
-        pair.read_back(x);
-        scan_wave4<S>(x, carry);
-        buf_store_u4(rout, lane * 16u, p * (2u * kBlock * 4u), make_uint4(x[0], x[1], x[2], x[3]));
-    };
-    FpPairFetch f0 = pair.fetch(0), f1 = pair.fetch(2);
-    uint32_t p = 0;
-    for (; p + 2 <= npass; p += 2) {
-        run_pass(p, f0);
-        run_pass(p + 1, f1);
+    const bool kl = lane < 32;
+    uint32_t kcnt = 0;
+    if constexpr (SP) {
+        // the Simple-8b words run to the page end (zero-padded to 4 words)
+        if ((w3 & 1u) || w3 > nwords - exc_at || pad4(exc_at + w3) != nwords)
+            return false;
+    } else {
+        // exception array directory: lane k - 1 owns array k
+        const bool set = kl && ((bitset >> (lane & 31u)) & 1u);
+        const uint32_t ci = kl ? (uint32_t)__builtin_popcount(bitset & ((1u << (lane & 31u)) - 1u)) : 0u;
+        kcnt = set ? page[4 + ci] : 0u;
+        const bool badk = set && (kcnt == 0 || kcnt > nb * kBlock);
+        const uint32_t wk = (set && !badk) ? exc_array_words<KIND == kPageFp32>(kcnt, lane + 1) : 0u;
+        const uint32_t kincl = wave_scan_incl(wk);
+        const uint32_t exc_end = exc_at + wave_read(kincl, 63);
+        if (ballot(badk) != 0 || (KIND == kPageFp32 ? pad4(exc_end) : exc_end) != nwords)
+            return false;
+        if (kl)
+            L.excb[lane + 1] = exc_at + kincl - wk;
+        if (lane == 32)
+            L.excb[0] = 0;
+        if (lane < 33)
+            L.kcar[lane] = 0;
+        wave_lds_order();
     }
-    if (p < npass)
+
+    bool bad = false;  // per lane, reduced at the end
+    uint32_t pk_run = 0, pos_run = 0;
+    auto load_meta = [&](uint32_t r, uint32_t &mb_, uint32_t &mm_, uint32_t &mc_) __attribute__((always_inline)) {
+        const uint32_t jj = 64u * r + lane;
+        const bool own = jj < nb;
+        mb_ = buf_load_u8(rpg, own ? meta_at + jj : kOutOfRange);
+        mm_ = buf_load_u8(rpg, own ? meta_at + nb + jj : kOutOfRange);
+        mc_ = buf_load_u8(rpg, own ? meta_at + 2u * nb + jj : kOutOfRange);
+    };
+    auto build_round = [&](uint32_t r, uint32_t bv, uint32_t mv, uint32_t cv) __attribute__((always_inline)) {
+        // blocks past the page read 0 for b, maxb and c
+        bad = bad || bv > 32u || mv > 32u || mv < bv || cv >= kBlock || ((cv == 0u) != (mv == bv));
+        const uint32_t k = (mv >= bv && mv <= 32u) ? mv - bv : 0u;
+        const uint32_t bc = bv < 32u ? bv : 32u;  // a corrupt width stays within the pass's words
+        const uint32_t bw = 4u * bc;
+        const uint32_t iw = wave_scan_incl(bw), ip = wave_scan_incl(cv);
+        const uint32_t y = pk_run + iw - bw, w = pos_run + ip - cv;
+        pk_run += wave_read(iw, 63);
+        pos_run += wave_read(ip, 63);
+        uint32_t z = 0;
+        if constexpr (!SP) {
+            const uint32_t kc = L.kcar[k];
+            uint32_t rk = 0;
+            uint64_t todo = ballot(cv > 0u && k > 0u);
+            while (todo) {
+                const uint32_t lead = (uint32_t)__builtin_ctzll(todo);
+                const uint32_t k0 = wave_read(k, (int)lead);
+                const bool mine = cv > 0u && k == k0;
+                const uint64_t mm = ballot(mine);
+                const uint32_t xc = mine ? cv : 0u;
+                const uint32_t incl = wave_scan_incl(xc);
+                if (mine)
+                    rk = incl - xc;
+                if (lane == 0)
+                    L.kcar[k0] = wave_read(kc, (int)lead) + wave_read(incl, 63);
+                todo &= ~mm;
+            }
+            z = L.excb[k] * 32u + (kc + rk) * k;
+        }
+        L.rec[r & 1u][lane] = make_uint4(bc | (k << 8) | (cv << 16), y, z, w);
+        wave_lds_order();
+    };
+    const uint32_t npass = (nb + 3) / 4;
+    uint32_t m0, m1, m2;
+    load_meta(0, m0, m1, m2);
+    build_round(0, m0, m1, m2);
+    load_meta(1, m0, m1, m2);
+    build_round(1, m0, m1, m2);
+    load_meta(2, m0, m1, m2);
+
+    // SimplePFOR: the ring holds the high parts [keep, dec) (indices in the
+    // page); sw = next Simple-8b word, whose batch of 64 (lane i: word
+    // sw + i) sits in plo/phi
+    const uint32_t ns8 = SP ? w3 / 2u : 0u;
+    uint32_t sw = 0, dec = 0, plo = 0, phi = 0;
+    auto s8_load = [&]() __attribute__((always_inline)) {
+        const uint32_t o = sw + lane < ns8 ? (exc_at + 2u * (sw + lane)) * 4u : kOutOfRange;
+        plo = buf_load_u32(rpg, o);
+        phi = buf_load_u32(rpg, o + 4u);
+    };
+    // decodes Simple-8b words until high part need - 1 is in the ring
+    // (never overwriting [keep, dec)); with count_only, only counts them
+    auto s8_fill = [&](uint32_t need, uint32_t keep, bool count_only) __attribute__((always_inline)) {
+        while (dec < need && sw < ns8) {
+            const bool live = sw + lane < ns8;
+            const uint32_t md = s8_mode(phi >> 28);
+            const uint32_t cnt = live ? (md & 255u) : 0u, bits = md >> 8;
+            const uint32_t incl = wave_scan_incl(cnt);
+            const uint32_t room = count_only ? 0xffffffffu : kSpRing - (dec - keep);
+            const uint64_t am = ballot(live && incl <= room);
+            const uint32_t nacc = (uint32_t)__builtin_popcountll(am);
+            if (nacc == 0) {  // a pass's high parts do not fit the ring: corrupt counts
+                bad = true;
+                break;
+            }
+            if (!count_only && ((am >> lane) & 1u)) {
+                const uint64_t word = ((uint64_t)phi << 32) | plo;
+                const uint64_t fm = bits >= 64u ? ~0ull : ((1ull << bits) - 1u);
+                uint32_t at = dec + incl - cnt;
+                for (uint32_t j = 0; j < cnt; ++j, ++at) {
+                    const uint64_t v = bits ? (word >> (j * bits)) & fm : 0u;
+                    bad = bad || (v >> 32) != 0u;
+                    ring[at & (kSpRing - 1u)] = (uint32_t)v;
+                }
+            }
+            dec += wave_read(incl, (int)nacc - 1);
+            sw += nacc;
+            s8_load();
+        }
+    };
+    if constexpr (SP)
+        s8_load();
+
+    const uint32_t jl = lane >> 5;
+    // pass q's words and exceptions; `keep`: the first high part still to
+    // be read from the ring (SimplePFOR)
+    auto fetch = [&](uint32_t q, uint32_t keep) __attribute__((always_inline)) {
+        FpFetch f;
+        const uint4 *const R = &L.rec[(q >> 4) & 1u][(q & 15u) * 4u];
+        const uint4 rA = R[jl], rC = R[2 + jl];
+        const uint32_t yA = wave_read(rA.y, 0), wA = wave_read(rA.w, 0), wB = wave_read(rA.w, 32);
+        const uint32_t wC = wave_read(rC.w, 0), xD = wave_read(rC.x, 32), yD = wave_read(rC.y, 32),
+                       wD = wave_read(rC.w, 32);
+        const uint32_t yE = yD + 4u * (xD & 255u);
+        // words past the packed region (corrupt metadata) are not read
+        const bool okp = yE >= yA && yE <= packed_words;
+        const BufRsrc rs = make_rsrc(page + hdr_w + (okp ? yA : 0u), okp ? 4u * (yE - yA) : 0u);
+        f.pk0 = buf_load_u4(rs, lane * 16u);
+        f.pk1 = buf_load_u4(rs, 1024u + lane * 16u);
+        f.u0 = (rA.x & 255u) | ((rA.y - yA) << 8);
+        f.u1 = (rC.x & 255u) | ((rC.y - yA) << 8);
+        f.e0 = wA;
+        f.ce = wD + ((xD >> 16) & 255u) - wA;
+        // exception `lane`: its block j of the pass, then its place in array k
+        const uint32_t j = (lane >= wB - wA ? 1u : 0u) + (lane >= wC - wA ? 1u : 0u) + (lane >= wD - wA ? 1u : 0u);
+        const uint4 re = R[j];
+        const uint32_t k = (re.x >> 8) & 255u;
+        const uint32_t idx = wA + lane - re.w;
+        const bool any = lane < f.ce;
+        f.pos = buf_load_u8(rpg, any ? pos_at + wA + lane : kOutOfRange);
+        uint32_t bit = 0;
+        if constexpr (SP) {
+            s8_fill(wA + f.ce, keep, false);
+            f.lo = any ? ring[(wA + lane) & (kSpRing - 1u)] : 0u;
+            f.hi = 0;
+        } else {
+            bit = re.z + idx * k;
+            const uint32_t woff = any ? (bit >> 5) * 4u : kOutOfRange;
+            f.lo = buf_load_u32(rpg, woff);
+            f.hi = buf_load_u32(rpg, woff + 4u);
+        }
+        f.em = (bit & 31u) | ((re.x & 31u) << 8) | (j << 16) | (idx == 0u ? (1u << 18) : 0u);
+        f.km = width_mask(k);
+        return f;
+    };
+
+    uint32_t carry[4] = {base[0], base[1], base[2], base[3]};
+    const uint32_t qq = lane & 31u;
+    uint32_t *const xw = &L.buf[jl * kBlock + qq];  // integer q of the lane's block of half 0
+    auto run_pass = [&](uint32_t p, FpFetch &f) __attribute__((always_inline)) {
+        *reinterpret_cast<uint4 *>(&L.buf[4 * lane]) = f.pk0;
+        *reinterpret_cast<uint4 *>(&L.buf[256 + 4 * lane]) = f.pk1;
+        wave_lds_order();
+        uint32_t v[2][4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t u = h ? f.u1 : f.u0;
+            const uint32_t b = u & 255u, qb = qq * b;
+            const uint32_t w0 = (u >> 8) + (qb >> 5);
+            const uint32_t mask = width_mask(b);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const uint32_t wi = w0 + m * b;
+                v[h][m] = __builtin_amdgcn_alignbit(L.buf[wi + 1], L.buf[wi], qb) & mask;
+            }
+        }
+        wave_lds_order();
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                xw[h * 2 * kBlock + 32 * m] = v[h][m];
+        wave_lds_order();
+        // exceptions: one per lane, the rest (more than 64 in the pass) in rounds
+        const uint32_t prev = wave_shr1(0u, f.pos);
+        if (lane < f.ce) {
+            const uint32_t hv = SP ? f.lo : __builtin_amdgcn_alignbit(f.hi, f.lo, f.em) & f.km;
+            atomicOr(&L.buf[((f.em >> 16) & 3u) * kBlock + (f.pos & (kBlock - 1u))], hv << ((f.em >> 8) & 31u));
+            bad = bad || f.pos >= kBlock || (!((f.em >> 18) & 1u) && prev >= f.pos) || (SP && (hv & ~f.km) != 0u);
+        }
+        if (f.ce > 64u) {
+            const uint4 *const R = &L.rec[(p >> 4) & 1u][(p & 15u) * 4u];
+            const uint32_t wA = f.e0, wB = wave_read(R[1].w, 0), wC = wave_read(R[2].w, 0),
+                           wD = wave_read(R[3].w, 0);
+            for (uint32_t e = 64u + lane; e - lane < f.ce; e += 64u) {
+                if (e < f.ce) {
+                    const uint32_t j = (e >= wB - wA ? 1u : 0u) + (e >= wC - wA ? 1u : 0u) + (e >= wD - wA ? 1u : 0u);
+                    const uint4 re = R[j];
+                    const uint32_t k = (re.x >> 8) & 255u, b = re.x & 31u;
+                    const uint32_t idx = wA + e - re.w;
+                    const uint32_t pos = buf_load_u8(rpg, pos_at + wA + e);
+                    const uint32_t pprev = idx > 0u ? buf_load_u8(rpg, pos_at + wA + e - 1u) : 0u;
+                    bad = bad || pos >= kBlock || (idx > 0u && pprev >= pos);
+                    uint32_t hv;
+                    if constexpr (SP) {
+                        hv = ring[(wA + e) & (kSpRing - 1u)];
+                        bad = bad || (hv & ~width_mask(k)) != 0u;
+                    } else {
+                        const uint32_t bit = re.z + idx * k;
+                        const uint32_t lo = buf_load_u32(rpg, (bit >> 5) * 4u);
+                        const uint32_t hw = buf_load_u32(rpg, (bit >> 5) * 4u + 4u);
+                        hv = __builtin_amdgcn_alignbit(hw, lo, bit & 31u) & width_mask(k);
+                    }
+                    atomicOr(&L.buf[j * kBlock + (pos & (kBlock - 1u))], hv << b);
+                }
+            }
+        }
+        // beyond the page it reads nothing; the ring keeps the next pass's high parts
+        f = fetch(p + 2, f.e0 + f.ce);
+        wave_lds_order();
+        const uint4 t0 = *reinterpret_cast<const uint4 *>(&L.buf[4 * lane]);
+        const uint4 t1 = *reinterpret_cast<const uint4 *>(&L.buf[256 + 4 * lane]);
+        uint32_t x[4] = {t0.x, t0.y, t0.z, t0.w}, y[4] = {t1.x, t1.y, t1.z, t1.w};
+        if constexpr (S == 1) {
+            x[1] += x[0];
+            x[2] += x[1];
+            x[3] += x[2];
+            y[1] += y[0];
+            y[2] += y[1];
+            y[3] += y[2];
+            const uint32_t ix = wave_scan_incl(x[3]), iy = wave_scan_incl(y[3]);
+            const uint32_t tx = wave_read(ix, 63);
+            const uint32_t ax = ix - x[3] + carry[0], ay = iy - y[3] + carry[0] + tx;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                x[r] += ax;
+                y[r] += ay;
+            }
+            carry[0] += tx + wave_read(iy, 63);
+        } else if constexpr (S == 4) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const uint32_t ix = wave_scan_incl(x[c]), iy = wave_scan_incl(y[c]);
+                const uint32_t tx = wave_read(ix, 63);
+                x[c] = ix + carry[c];
+                y[c] = iy + carry[c] + tx;
+                carry[c] += tx + wave_read(iy, 63);
+            }
+        }
+        // the pass's output; blocks past the page fall outside the resource
+        const BufRsrc rout = make_rsrc(out + p * (4u * kBlock), (nb - 4u * p) * (kBlock * 4u));
+        buf_store_u4(rout, lane * 16u, 0u, make_uint4(x[0], x[1], x[2], x[3]));
+        buf_store_u4(rout, 1024u + lane * 16u, 0u, make_uint4(y[0], y[1], y[2], y[3]));
+    };
+    FpFetch f0 = fetch(0, 0u);
+    FpFetch f1 = fetch(1, 0u);
+    for (uint32_t p = 0; p < npass; p += 2) {
+        if (p > 0 && (p & 15u) == 0) {
+            // round p / 16 starts: build the next one, load the one after
+            build_round((p >> 4) + 1, m0, m1, m2);
+            load_meta((p >> 4) + 2, m0, m1, m2);
+        }
         run_pass(p, f0);
+        if (p + 1 < npass)
+            run_pass(p + 1, f1);
+    }
+    // totals: packed words, positions, and each array's count (SimplePFOR:
+    // the Simple-8b words hold exactly the page's exceptions)
+    bad = bad || pk_run != packed_words || 3u * nb + pos_run != meta_bytes;
+    if constexpr (SP) {
+        s8_fill(0xffffffffu, 0u, true);
+        bad = bad || dec != pos_run;
+    } else {
+        bad = bad || (kl && L.kcar[lane + 1] != kcnt);
+    }
     wave_lds_order();
-    return ballot(bad_pos) == 0;
+    return ballot(bad) == 0;
+}
+
+// Directory entry u (< H.units) of a patched-page stream decoded by one
+// wavefront into out (the whole list's output): the entry's offset, length
+// and bases, then fp_wave_page. Uniform result.
+template <int KIND = kPageFp>
+__device__ __forceinline__ bool fp_unit(const uint32_t *__restrict__ in, const ListHdr &H, uint64_t u,
+                                        uint32_t *__restrict__ out, FpWaveLds &L, uint32_t *ring = nullptr)
+{
+    const uint32_t off = uniform(in[kHdrWords + u]);
+    const uint32_t end = (u + 1 < H.units) ? uniform(in[kHdrWords + u + 1]) : H.tail_off;
+    const uint32_t *bp = in + kHdrWords + H.ndir + u * H.S;
+    const uint32_t base[4] = {H.S > 0 ? uniform(bp[0]) : 0u, H.S > 1 ? uniform(bp[1]) : 0u,
+                              H.S > 2 ? uniform(bp[2]) : 0u, H.S > 3 ? uniform(bp[3]) : 0u};
+    const uint64_t left = H.nfull - u * kFpBlocks;
+    const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
+    if (!(off >= H.dir_end && end >= off && end <= H.total && (off & 3u) == 0))
+        return false;
+    const uint32_t *pg = in + off;
+    uint32_t *po = out + u * kFpUnitInts;
+    return H.S == 1   ? fp_wave_page<1, KIND>(pg, end - off, nb, base, po, L, ring)
+           : H.S == 4 ? fp_wave_page<4, KIND>(pg, end - off, nb, base, po, L, ring)
+                      : fp_wave_page<0, KIND>(pg, end - off, nb, base, po, L, ring);
 }
 
 // ------------------------------------------------------------------------

@@ -378,6 +378,113 @@ struct PairRing {
     }
 };
 
+// Page tables of a patched page for the packer. The per-block tables are
+// dead once the block records are built; `room` sizes the union so that
+// the packer's metadata and exception area, which runs on over the tables,
+// holds 32 KB.
+template <int WAVES>
+struct FpLds {
+    union {
+        uint32_t room[WAVES][4 * kBlock + 4];
+        struct {
+            uint8_t b[kFpBlocks];
+            uint8_t mb[kFpBlocks];
+            uint8_t c[kFpBlocks];
+            uint32_t blkoff[kFpBlocks + 1];  // word offset of each block in the packed region
+            uint32_t posoff[kFpBlocks + 1];  // offset of each block's positions
+            uint32_t rank[kFpBlocks];        // index of the block's first exception in its array
+        };
+    };
+    // per block: {b | k << 8, packed word offset, bit offset of its first
+    // exception's high part, position offset}
+    uint4 rec[kFpBlocks + 8 * WAVES];
+    uint32_t ktot[WAVES][33];
+    uint32_t kcar[33];
+    uint32_t excbase[33];            // word offset of array k from the page start
+    uint32_t kcnt[33];
+    uint32_t stot[WAVES][2];
+};
+
+// Tables of a patched page from its per-block metadata L.b, L.mb, L.c
+// (entries from nb to the end of its last round of T blocks hold 0): block
+// offsets in the packed region (exclusive sum of 4*b), offsets into the position bytes
+// (exclusive sum of c) and, per block, the index of its first exception in
+// array k = maxb - b -- exceptions are appended to their array in block
+// order (Section 5), so this is the number of exceptions of earlier blocks
+// with the same k. Per-k totals accumulate in L.kcar (zeroed by the caller,
+// as is L.ktot). Rounds of T blocks; within a wavefront the same-k ranks
+// come from one masked scan per distinct k (ballot loop).
+template <int WAVES>
+__device__ __forceinline__ void fp_tables(FpLds<WAVES> &L, uint32_t nb, uint32_t &tot_words, uint32_t &tot_pos)
+{
+    constexpr int T = 64 * WAVES;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform(tid >> 6);
+    uint32_t carry_w = 0, carry_p = 0;
+    for (uint32_t r0 = 0; r0 < nb; r0 += T) {
+        const uint32_t t = r0 + tid;
+        const uint32_t bw = 4u * L.b[t];
+        const uint32_t cc = L.c[t];
+        const uint32_t kk = (uint32_t)L.mb[t] - (uint32_t)L.b[t];
+        const uint32_t iw = wave_scan_incl(bw);
+        const uint32_t ip = wave_scan_incl(cc);
+        if (lane == 63) {
+            L.stot[wave][0] = iw;
+            L.stot[wave][1] = ip;
+        }
+        // rank among the wave's earlier blocks of the same k
+        uint32_t rk = 0;
+        uint64_t todo = ballot(cc > 0);
+        while (todo) {
+            const uint32_t lead = (uint32_t)__builtin_ctzll(todo);
+            const uint32_t k0 = wave_read(kk, lead);
+            const bool mine = cc > 0 && kk == k0;
+            const uint64_t mm = ballot(mine);
+            const uint32_t x = mine ? cc : 0u;
+            const uint32_t incl = wave_scan_incl(x);
+            if (mine)
+                rk = incl - x;
+            if (lane == 0)
+                L.ktot[wave][k0 > 32 ? 0 : k0] = wave_read(incl, 63);
+            todo &= ~mm;
+        }
+        __syncthreads();
+        uint32_t bw_before = carry_w, p_before = carry_p, all_w = 0, all_p = 0, k_before = 0;
+        for (int w = 0; w < WAVES; ++w) {
+            const uint32_t a = L.stot[w][0], c2 = L.stot[w][1];
+            if (w < (int)wave) {
+                bw_before += a;
+                p_before += c2;
+            }
+            all_w += a;
+            all_p += c2;
+        }
+        if (cc > 0 && kk <= 32) {
+            k_before = L.kcar[kk];
+            for (int w = 0; w < (int)wave; ++w)
+                k_before += L.ktot[w][kk];
+        }
+        L.blkoff[t] = bw_before + iw - bw;
+        L.posoff[t] = p_before + ip - cc;
+        L.rank[t] = k_before + rk;
+        carry_w += all_w;
+        carry_p += all_p;
+        __syncthreads();
+        if (tid < 33) {
+            uint32_t s = 0;
+            for (int w = 0; w < WAVES; ++w) {
+                s += L.ktot[w][tid];
+                L.ktot[w][tid] = 0;
+            }
+            L.kcar[tid] += s;
+        }
+        __syncthreads();
+    }
+    tot_words = carry_w;
+    tot_pos = carry_p;
+}
+
 // Inclusive sum and minimum over each half of the wavefront (lanes 0..31,
 // 32..63): row steps, then row 1 (3) takes row 0's (2's) last lane.
 __device__ __forceinline__ uint32_t half_scan_incl(uint32_t v)

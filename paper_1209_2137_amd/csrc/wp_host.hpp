@@ -9,7 +9,8 @@
 
 namespace wp {
 
-// Per-device state: the error word kernels report corrupt streams into,
+// Per-device state: the address of the device's error word (a static
+// device variable of the library; kernels report corrupt streams into it)
 // and the device's compute-unit count.
 struct DevState {
     int *err = nullptr;
@@ -17,8 +18,8 @@ struct DevState {
     int device = -1;
 };
 
-// Returns the current device's state, creating it on first use
-// (one 16-byte allocation per device). nullptr if HIP fails.
+// Returns the current device's state, filling it on first use (a symbol
+// lookup, no allocation). nullptr if HIP fails.
 DevState *dev_state();
 
 // Scratch memory owned by the library for one (device, stream) pair: calls

@@ -177,11 +177,12 @@ __device__ __forceinline__ bool dir_view(const uint32_t *in, uint64_t in_words, 
                                          DirView &D)
 {
     D.in = in;
-    D.per = (codec == WP_CODEC_FP || codec == WP_CODEC_FP32) ? kFpBlocks : kBpBlocks;
+    D.per = (codec == WP_CODEC_FP || codec == WP_CODEC_FP32 || codec == WP_CODEC_SP) ? kFpBlocks : kBpBlocks;
     const uint32_t magic = codec == WP_CODEC_BP     ? kMagicBP
                            : codec == WP_CODEC_BPV  ? kMagicBPV
                            : codec == WP_CODEC_BP32 ? kMagicBP32
                            : codec == WP_CODEC_FP32 ? kMagicFP32
+                           : codec == WP_CODEC_SP   ? kMagicSP
                                                     : kMagicFP;
     return check_header(in, in_words, n, magic, D.per, D.H);
 }
@@ -255,42 +256,36 @@ __global__ __launch_bounds__(256) void k_isect_decode_bp(const uint32_t *__restr
 }
 
 union IsectPageLds {
-    FpLds<4> fp;
-    TailLds<4> tail;
+    FpWaveLds page;
+    SpWaveLds sp;
+    TailLds<1> tail;
 };
 
-// Decodes the wanted entries of a patched-page stream (one workgroup per
-// page; P32: exception arrays padded to 32 values).
-template <bool P32>
+// Decodes the wanted entries of a patched-page stream (one wavefront per
+// page, four per workgroup; P32: exception arrays padded to 32 values).
+template <int KIND>
 __global__ __launch_bounds__(256) void k_isect_decode_fp(const uint32_t *__restrict__ in, uint64_t in_words,
                                                          uint64_t n, const uint32_t *__restrict__ a, uint64_t na,
                                                          uint32_t klo, uint32_t khi, uint32_t *__restrict__ out,
                                                          int *__restrict__ err)
 {
-    __shared__ IsectPageLds L;
+    __shared__ IsectPageLds L[4];
     ListHdr H;
-    if (!check_header(in, in_words, n, P32 ? kMagicFP32 : kMagicFP, kFpBlocks, H))
+    const uint32_t magic = KIND == kPageSp ? kMagicSP : KIND == kPageFp32 ? kMagicFP32 : kMagicFP;
+    if (!check_header(in, in_words, n, magic, kFpBlocks, H))
         return;  // reported by k_isect_flag_dir or k_range_bounds
-    const uint64_t u = blockIdx.x;
+    const uint32_t wave = uniform(threadIdx.x >> 6);
+    const uint64_t u = (uint64_t)blockIdx.x * 4 + wave;
     if (u >= H.ndir || !entry_wanted(in, H, u, a, na, klo, khi))
         return;
     bool ok;
-    if (u == H.units) {
-        ok = decode_tail_entry<4>(in, H, out, L.tail);
-    } else {
-        const uint32_t off = uniform(in[kHdrWords + u]);
-        const uint32_t end = (u + 1 < H.units) ? uniform(in[kHdrWords + u + 1]) : H.tail_off;
-        const uint32_t *bp = in + kHdrWords + H.ndir + u * H.S;
-        const uint32_t base[4] = {H.S > 0 ? uniform(bp[0]) : 0u, H.S > 1 ? uniform(bp[1]) : 0u,
-                                  H.S > 2 ? uniform(bp[2]) : 0u, H.S > 3 ? uniform(bp[3]) : 0u};
-        const uint64_t left = H.nfull - u * kFpBlocks;
-        const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
-        ok = off >= H.dir_end && end >= off && end <= H.total && (off & 3u) == 0 &&
-             (H.S == 1   ? fp_page<4, 1, 2, P32>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp)
-              : H.S == 4 ? fp_page<4, 4, 2, P32>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp)
-                         : fp_page<4, 0, 2, P32>(in + off, end - off, nb, base, out + u * kFpUnitInts, L.fp));
-    }
-    if (!ok && threadIdx.x == 0)
+    if (u == H.units)
+        ok = decode_tail_entry<1, false>(in, H, out, L[wave].tail);
+    else if constexpr (KIND == kPageSp)
+        ok = fp_unit<KIND>(in, H, u, out, L[wave].sp.fp, L[wave].sp.ring);
+    else
+        ok = fp_unit<KIND>(in, H, u, out, L[wave].page);
+    if (!ok && lane_id() == 0)
         *err = kErrCorrupt;
 }
 
@@ -453,6 +448,7 @@ extern "C" int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const
         b_words < kHdrWords || (nb > 0 && b_work == nullptr) || (reinterpret_cast<uintptr_t>(out_count) & 7u) ||
         na > 0xFFFFFFFFull ||
         (codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32 && codec != WP_CODEC_FP32 &&
+         codec != WP_CODEC_SP &&
          codec != WP_CODEC_BPV) ||
         !aligned16(b_comp) ||
         !aligned16(b_work) || nb > 0xFFFFFFFFull * 32ull)
@@ -466,7 +462,8 @@ extern "C" int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const
         hipLaunchKernelGGL(k_isect_none, dim3(1), dim3(64), 0, st, out_count);
         return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
     }
-    const uint64_t per = (codec == WP_CODEC_FP || codec == WP_CODEC_FP32) ? kFpBlocks : kBpBlocks;
+    const uint64_t per =
+        (codec == WP_CODEC_FP || codec == WP_CODEC_FP32 || codec == WP_CODEC_SP) ? kFpBlocks : kBpBlocks;
     const uint64_t nfull = nb / kBlock;
     const uint64_t nent = (nfull + per - 1) / per + ((nb % kBlock) ? 1 : 0);
     const uint64_t tiles = (na + kIsTile - 1) / kIsTile;
@@ -482,11 +479,14 @@ extern "C" int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const
     else if (codec == WP_CODEC_BP32)
         hipLaunchKernelGGL((k_isect_decode_bp<true, false>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
                            b_comp, b_words, nb, a, na, 0u, 0u, b_work, ds->err);
+    else if (codec == WP_CODEC_SP)
+        hipLaunchKernelGGL(k_isect_decode_fp<kPageSp>, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, b_comp,
+                           b_words, nb, a, na, 0u, 0u, b_work, ds->err);
     else if (codec == WP_CODEC_FP32)
-        hipLaunchKernelGGL(k_isect_decode_fp<true>, dim3((uint32_t)nent), dim3(256), 0, st, b_comp, b_words, nb,
+        hipLaunchKernelGGL(k_isect_decode_fp<kPageFp32>, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, b_comp, b_words, nb,
                            a, na, 0u, 0u, b_work, ds->err);
     else
-        hipLaunchKernelGGL(k_isect_decode_fp<false>, dim3((uint32_t)nent), dim3(256), 0, st, b_comp, b_words, nb,
+        hipLaunchKernelGGL(k_isect_decode_fp<kPageFp>, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, b_comp, b_words, nb,
                            a, na, 0u, 0u, b_work, ds->err);
     hipLaunchKernelGGL(k_isect_flag_dir, dim3((uint32_t)tiles), dim3(kIsThreads), 0, st, a, na, b_comp, b_words, nb,
                        codec, b_work, S.flags, S.counts, ds->err);
@@ -503,6 +503,7 @@ extern "C" int32_t wp_decode_range(const uint32_t *in, uint64_t in_words, uint64
     if (in == nullptr || in_words < kHdrWords || range == nullptr || (n > 0 && out == nullptr) ||
         (reinterpret_cast<uintptr_t>(range) & 7u) || key_lo > key_hi ||
         (codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32 && codec != WP_CODEC_FP32 &&
+         codec != WP_CODEC_SP &&
          codec != WP_CODEC_BPV) ||
         !aligned16(in) || !aligned16(out) || n > 0xFFFFFFFFull * 32ull)
         return WP_ERR_INVALID_ARG;
@@ -511,7 +512,8 @@ extern "C" int32_t wp_decode_range(const uint32_t *in, uint64_t in_words, uint64
         return WP_ERR_HIP;
     hipStream_t st = as_stream(stream);
     (void)hipGetLastError();
-    const uint64_t per = (codec == WP_CODEC_FP || codec == WP_CODEC_FP32) ? kFpBlocks : kBpBlocks;
+    const uint64_t per =
+        (codec == WP_CODEC_FP || codec == WP_CODEC_FP32 || codec == WP_CODEC_SP) ? kFpBlocks : kBpBlocks;
     const uint64_t nfull = n / kBlock;
     const uint64_t nent = (nfull + per - 1) / per + ((n % kBlock) ? 1 : 0);
     if (nent > 0x7FFFFFFFull)
@@ -528,11 +530,14 @@ extern "C" int32_t wp_decode_range(const uint32_t *in, uint64_t in_words, uint64
         else if (codec == WP_CODEC_BP32)
             hipLaunchKernelGGL((k_isect_decode_bp<true, false>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
                                in, in_words, n, nf, 0, key_lo, key_hi, out, ds->err);
+        else if (codec == WP_CODEC_SP)
+            hipLaunchKernelGGL(k_isect_decode_fp<kPageSp>, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, in,
+                               in_words, n, nf, 0, key_lo, key_hi, out, ds->err);
         else if (codec == WP_CODEC_FP32)
-            hipLaunchKernelGGL(k_isect_decode_fp<true>, dim3((uint32_t)nent), dim3(256), 0, st, in, in_words, n, nf,
+            hipLaunchKernelGGL(k_isect_decode_fp<kPageFp32>, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, in, in_words, n, nf,
                                0, key_lo, key_hi, out, ds->err);
         else
-            hipLaunchKernelGGL(k_isect_decode_fp<false>, dim3((uint32_t)nent), dim3(256), 0, st, in, in_words, n, nf,
+            hipLaunchKernelGGL(k_isect_decode_fp<kPageFp>, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, in, in_words, n, nf,
                                0, key_lo, key_hi, out, ds->err);
     }
     hipLaunchKernelGGL(k_range_bounds, dim3(1), dim3(128), 0, st, in, in_words, n, codec, key_lo, key_hi, out,

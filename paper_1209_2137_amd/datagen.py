@@ -6,8 +6,9 @@ widths, no packing), so both the CPU oracle and the GPU path may consume it.
 
 All generators use numpy's PCG64 (``numpy.random.default_rng(seed)``).
 
-Workloads (the shapes follow the paper's synthetic and posting-list data,
-Section 6.3 ClusterData/Uniform and Section 6.4 posting lists):
+Workloads (the shapes follow the paper's synthetic and posting-list data:
+Section 6.4, synthetic data sets, ClusterData and Uniform; Section 6.5,
+realistic data sets, posting lists):
 
 * ``single_geometric``   x_1 ~ U[0,1000), gaps ~ Geom(mean) on {1,2,...}.
 * ``cluster_sorted``     distinct sorted values from a recursive-cluster

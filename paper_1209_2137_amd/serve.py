@@ -1,10 +1,13 @@
 """Continuous-batching decode server over a resident list pool.
 
 Requests arrive over time; each asks for a set of lists of the pool to be
-decoded into the caller's buffer. The loop admits arrived requests while
-the output arena (an HBM budget) has room, groups every admitted request
-not yet launched into one micro-batch, and launches it (one batched
-decode launch) on the next free stream, so batches overlap on the device
+decoded into a device buffer that the caller owns (the caller hands it over
+when the request is admitted and gets it back, filled, on completion). The
+loop admits arrived requests while the output bytes of the requests in
+flight stay within an HBM budget and the caller has a buffer for them,
+groups every admitted request not yet launched into one micro-batch, and
+launches it (one batched decode launch, each list straight into its
+request's buffer) on the next free stream, so batches overlap on the device
 while new requests keep arriving. A request is complete when its batch's
 completion event has fired; its latency is completion minus arrival (host
 clock, polled).
@@ -28,11 +31,12 @@ class Request:
     rid: int
     arrival: float           # seconds since the start of the run
     lists: np.ndarray        # pool list ids
-    n: int = 0               # output integers
-    out_off: int = -1        # start in the arena (elements)
+    n: int = 0               # output elements (lists at 4-aligned offsets)
+    ints: int = 0            # integers decoded (the lists' lengths)
+    out: object = None       # the caller's device buffer (int32/uint32 tensor, >= n elements)
     launched: float = -1.0
     done: float = -1.0
-    offsets: list = field(default_factory=list)
+    offsets: list = field(default_factory=list)  # each list's first element in `out`
 
 
 class RingArena:
@@ -87,39 +91,118 @@ class RingArena:
             self.tail = 0
 
 
-class Server:
-    """Continuous batching of decode requests over a ListPool."""
+class ArenaBuffers:
+    """A caller's output buffers carved from one device tensor it owns (a
+    ring): get(request) returns a view of at least request.n elements or
+    None when the ring is full; put(request) gives the space back."""
 
-    def __init__(self, pool, arena_elems: int, budget_bytes: int = 64 << 30, streams: int = 4,
-                 max_batch: int = 512, tune=None):
+    def __init__(self, arena):
+        self.arena = arena
+        self.ring = RingArena(arena.numel() - 4)
+        self.start = {}
+
+    def get(self, r):
+        s = self.ring.alloc(r.n)
+        if s is None:
+            return None
+        self.start[r.rid] = s
+        return self.arena[s:s + max(4, (r.n + 3) & ~3)]
+
+    def put(self, r):
+        self.ring.free(self.start.pop(r.rid))
+
+
+class CheckingCaller:
+    """A caller that owns one zeroed device arena, hands out buffers from
+    it (get) and checks every completed request (done) against the pool's
+    resident input values on a stream of its own: the request's buffer must
+    equal its lists' values, each list zero-padded to 4 elements as the
+    server lays them out. The buffer is zeroed again and given back once the
+    check has run. finish() waits for the checks and returns the number of
+    wrong elements."""
+
+    def __init__(self, pool, arena_elems: int, device="cuda"):
+        import torch
+        if pool.values is None:
+            raise ValueError("checking needs the pool's input values")
+        self.pool = pool
+        self.arena = torch.zeros(int(arena_elems) + 4, dtype=torch.int32, device=device)
+        self.bufs = ArenaBuffers(self.arena)
+        self.stream = torch.cuda.Stream()  # default priority
+        self.bad = torch.zeros(1, dtype=torch.int64, device=device)
+        self.pending = collections.deque()
+        self.checked = 0
+
+    def _reap(self):
+        while self.pending and self.pending[0][0].query():
+            _, r = self.pending.popleft()
+            self.bufs.put(r)
+            self.checked += 1
+
+    def get(self, r):
+        self._reap()
+        return self.bufs.get(r)
+
+    def done(self, r):
+        import torch
+        vals = self.pool.values
+        rows = self.pool.rows
+        with torch.cuda.stream(self.stream):
+            want = torch.cat([vals[rows[li][2]:rows[li][2] + ((rows[li][3] + 3) & ~3)] for li in r.lists])
+            got = r.out[:r.n]
+            self.bad += (got != want).sum()
+            got.zero_()
+            ev = torch.cuda.Event()
+            ev.record(self.stream)
+        self.pending.append((ev, r))
+
+    def finish(self) -> int:
+        self.stream.synchronize()
+        self._reap()
+        return int(self.bad.item())
+
+
+class Server:
+    """Continuous batching of decode requests over a ListPool, into caller
+    buffers, under an HBM budget for the output bytes in flight."""
+
+    def __init__(self, pool, budget_bytes: int = 64 << 30, streams: int = 4, max_batch: int = 512, tune=None):
         import torch
         self.pool = pool
-        self.arena_elems = int(min(arena_elems, budget_bytes // 4))
-        self.arena = torch.empty(self.arena_elems + 4, dtype=torch.int32, device="cuda")
-        self.alloc = RingArena(self.arena_elems)
+        self.budget_bytes = int(budget_bytes)
+        self.in_flight_bytes = 0
+        self.peak_bytes = 0
         self.streams = [torch.cuda.Stream() for _ in range(streams)]  # default priority
         self.tune = dict(tune or {})
         self.tune.setdefault("use_graph", 0)
-        self.plans = [BatchPlan(pool.pool, self.arena, [], tune=self.tune) for _ in range(streams)]
+        self.plans = [BatchPlan(pool.pool, None, [], tune=self.tune) for _ in range(streams)]
         self.events = [torch.cuda.Event() for _ in range(streams)]
         self.busy = [None] * streams
         self.max_batch = max_batch
+        self.waited_for_budget = 0
+        self.waited_for_buffer = 0
 
     def _launch(self, slot, batch, now):
         rows = []
         for r in batch:
-            rows.extend(self.pool.rows_for(r.lists, [r.out_off + o for o in r.offsets]))
+            base = r.out.data_ptr()
+            for li, o in zip(r.lists, r.offsets):
+                co, cw, _, n, codec = self.pool.rows[li]
+                rows.append((co, cw, 0, n, codec, base + 4 * o))
             r.launched = now
         st = self.streams[slot]
-        self.plans[slot].replan(self.pool.pool, self.arena, rows, stream=st)
+        self.plans[slot].replan(self.pool.pool, None, rows, stream=st)
         self.plans[slot].decode(stream=st)
         self.events[slot].record(st)
         self.busy[slot] = batch
 
-    def run(self, times, reqs, check=None, idle_sleep=20e-6):
+    def run(self, times, reqs, get_out, on_done=None, idle_sleep=20e-6):
         """Serves requests with arrival times `times` (seconds) and list ids
-        `reqs`. check(request, arena) is called on completion (optional).
-        Returns the list of completed Request objects."""
+        `reqs`. get_out(request) returns the caller's buffer for it (a
+        device tensor of at least request.n elements) or None if the caller
+        has none free yet (the request then waits); on_done(request) is
+        called when its output is complete (the caller checks and takes the
+        buffer back). Returns the list of completed Request objects."""
         lens = self.pool.lens
         pending = collections.deque()
         for i, (t, ids) in enumerate(zip(times, reqs)):
@@ -129,7 +212,9 @@ class Server:
             for li in ids:
                 offs.append(o)
                 o += (int(lens[li]) + 3) & ~3
-            r.offsets, r.n = offs, o
+            r.offsets, r.n, r.ints = offs, o, int(sum(int(lens[li]) for li in ids))
+            if 4 * r.n > self.budget_bytes:
+                raise ValueError(f"request {i} needs {4 * r.n} output bytes, beyond the budget")
             pending.append(r)
         waiting = collections.deque()
         admitted = collections.deque()
@@ -145,20 +230,29 @@ class Server:
                     tdone = time.perf_counter() - t0
                     for r in b:
                         r.done = tdone
-                        if check is not None:
-                            check(r, self.arena)
-                        self.alloc.free(r.out_off)
+                        self.in_flight_bytes -= 4 * r.n
+                        if on_done is not None:
+                            on_done(r)
                         done.append(r)
                     self.busy[s] = None
                     progressed = True
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
             while waiting:
-                start = self.alloc.alloc(waiting[0].n)
-                if start is None:
+                r = waiting[0]
+                if self.in_flight_bytes + 4 * r.n > self.budget_bytes:
+                    self.waited_for_budget += 1
                     break
-                r = waiting.popleft()
-                r.out_off = start
+                out = get_out(r)
+                if out is None:
+                    self.waited_for_buffer += 1
+                    break
+                if out.numel() < r.n:
+                    raise ValueError(f"request {r.rid}: the caller's buffer holds {out.numel()} < {r.n} elements")
+                waiting.popleft()
+                r.out = out
+                self.in_flight_bytes += 4 * r.n
+                self.peak_bytes = max(self.peak_bytes, self.in_flight_bytes)
                 admitted.append(r)
             if admitted:
                 for s in range(len(self.streams)):
@@ -180,7 +274,7 @@ class Server:
 
 def summarize(done, wall):
     lat = np.array([r.done - r.arrival for r in done]) * 1e3
-    ints = sum(r.n for r in done)
+    ints = sum(r.ints for r in done)
     return {
         "requests": len(done),
         "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,

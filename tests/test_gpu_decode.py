@@ -20,7 +20,7 @@ CANARY = 0x5A5A5A5A
 PAD = 64
 # (waves, vpl, runs or workgroups per CU, depth)
 BP_TUNES = [(4, 4, 28, 2), (1, 4, 4, 3), (2, 4, 64, 4), (8, 4, 16, 2), (4, 4, 1, 3)]
-FP_TUNES = [(8, 4, 0, 0), (4, 4, 0, 0), (2, 4, 0, 0)]
+FP_TUNES = [(8, 4, 0, 0), (4, 4, 0, 0), (2, 4, 0, 0), (1, 4, 0, 0)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -256,6 +256,88 @@ def test_corrupt_streams_flagged_without_stray_writes(codec):
     assert rc == wp.ERR_CORRUPT
     # a good decode afterwards is clean again
     rc, got = gpu_decode(codec, s, n)
+    assert rc == wp.OK and np.array_equal(got, x)
+
+
+def dense_exception_deltas(rng, nblocks, per_block):
+    """Deltas whose blocks hold `per_block[j]` values of 20..24 bits among
+    zeros: the cost rule then keeps b = 0 and makes every one of them an
+    exception (up to about 90 per block), so a pass of four blocks can hold
+    far more than 64."""
+    d = np.zeros(nblocks * 128, dtype=np.uint32)
+    for j in range(nblocks):
+        c = int(per_block[j])
+        pos = rng.choice(128, size=c, replace=False)
+        d[j * 128 + pos] = rng.integers(1 << 19, 1 << 24, size=c).astype(np.uint32)
+    return d
+
+
+@pytest.mark.parametrize("stride", [0, 1, 4])
+def test_patched_dense_exceptions(stride):
+    # passes with 0..360 exceptions (one per lane, then rounds of 64 more),
+    # blocks of up to 90, on pages of every fill; plus a tail
+    rng = np.random.default_rng(900 + stride)
+    nblocks = 512 + 200
+    per = rng.integers(0, 91, size=nblocks)
+    per[:8] = 90
+    per[8:16] = 0
+    per[40:44] = [1, 90, 2, 89]
+    d = np.concatenate([dense_exception_deltas(rng, nblocks, per), np.arange(1, 51, dtype=np.uint32)])
+    if stride == 0:
+        x = d
+    elif stride == 1:
+        x = np.cumsum(d.astype(np.uint64)).astype(np.uint32)
+    else:
+        x = d.astype(np.uint64).copy()
+        for c in range(4):
+            x[c::4] = np.cumsum(x[c::4])
+        x = x.astype(np.uint32)
+    s = encode(wp.CODEC_FP, x, stride)
+    for waves, vpl, wpc, depth in FP_TUNES:
+        wp.set_decode_tune(wp.CODEC_FP, waves, vpl, wpc, depth)
+        print(f"dense exceptions stride={stride} waves={waves}", flush=True)
+        rc, got = gpu_decode(wp.CODEC_FP, s, x.size)
+        assert rc == wp.OK
+        assert_same(got, x, f"waves={waves}")
+    autotune.apply()
+
+
+def _page_meta(s, n):
+    """Word offset of the first page, its block count and the byte offset
+    (from the stream start) of its metadata."""
+    unit = int(s[8])
+    nb, packed, bitset = int(s[unit]), int(s[unit + 1]), int(s[unit + 3])
+    hdr = (4 + bin(bitset).count("1") + 3) & ~3
+    return unit, nb, 4 * (unit + hdr + packed)
+
+
+def test_patched_corrupt_metadata_flagged():
+    # exception positions out of order or past the block, and a block whose
+    # exception count disagrees with its widths: the GPU and the oracle both
+    # reject the stream, and the decode stays inside [out, out + n)
+    n = 2 * 65536 + 300
+    x = datagen.patched_gaps(n, seed=78)
+    s = encode(wp.CODEC_FP, x, 1)
+    unit, nb, meta = _page_meta(s, n)
+    by = s.view(np.uint8)
+    c = by[meta + 2 * nb: meta + 3 * nb].astype(np.int64)
+    t = int(np.nonzero(c >= 2)[0][3])           # a block with at least two exceptions
+    p0 = meta + 3 * nb + int(c[:t].sum())        # its first position byte
+    cases = {}
+    b = s.copy(); bb = b.view(np.uint8); bb[p0], bb[p0 + 1] = bb[p0 + 1], bb[p0]; cases["positions_swapped"] = b
+    b = s.copy(); bb = b.view(np.uint8); bb[p0 + 1] = bb[p0]; cases["position_repeated"] = b
+    b = s.copy(); bb = b.view(np.uint8); bb[p0] = 200; cases["position_past_block"] = b
+    b = s.copy(); bb = b.view(np.uint8); bb[meta + 2 * nb + t] = 0; cases["count_without_width_gap"] = b
+    b = s.copy(); bb = b.view(np.uint8); bb[meta + t] = 40; cases["width_40"] = b
+    for what, bad in cases.items():
+        print("corruption", what, flush=True)
+        for waves in (1, 4):
+            wp.set_decode_tune(wp.CODEC_FP, waves, 4)
+            rc, _ = gpu_decode(wp.CODEC_FP, bad, n)
+            assert rc == wp.ERR_CORRUPT, (what, waves)
+        assert oracle.fp_decode_rc(bad, n) == oracle.ERR_CORRUPT, what
+    autotune.apply()
+    rc, got = gpu_decode(wp.CODEC_FP, s, n)
     assert rc == wp.OK and np.array_equal(got, x)
 
 

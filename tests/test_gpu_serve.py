@@ -1,7 +1,8 @@
 """Continuous-batching server on the GPU: every request's output, decoded in
-the mix with whatever else was in flight, equals the same request decoded
-alone, and equals the generator's arrays (tolerance 0: integer decoding).
-Admission respects the arena budget."""
+the mix with whatever else was in flight, straight into the caller's buffer,
+equals the generator's arrays (every request checked; tolerance 0: integer
+decoding), and the same requests decoded alone equal them too. Admission
+respects the output budget."""
 import numpy as np
 import pytest
 import torch
@@ -9,7 +10,7 @@ import torch
 import paper_1209_2137_amd as wp
 from paper_1209_2137_amd import datagen
 from paper_1209_2137_amd.pool import ListPool
-from paper_1209_2137_amd.serve import Server, summarize
+from paper_1209_2137_amd.serve import CheckingCaller, Server, summarize
 
 pytestmark = pytest.mark.gpu
 
@@ -34,26 +35,20 @@ def decode_alone(pool, ids):
     return out
 
 
-@pytest.mark.parametrize("arena_elems,streams", [(1 << 22, 4), (1 << 20, 2)])
-def test_mix_equals_alone_and_inputs(pool, arena_elems, streams):
+@pytest.mark.parametrize("budget_elems,streams", [(1 << 22, 4), (1 << 20, 2)])
+def test_mix_equals_alone_and_inputs(pool, budget_elems, streams):
     times, reqs = datagen.poisson_arrivals(rate=2000.0, duration=0.5, pool=300, seed=7)
-    srv = Server(pool, arena_elems=arena_elems, streams=streams)
-    mismatches = []
-    peak = [0]
-
-    def check(r, arena):
-        peak[0] = max(peak[0], sum(b[1] for b in srv.alloc.blocks))
-        for li, o in zip(r.lists, r.offsets):
-            _, _, oo, n, _ = pool.rows[li]
-            if not torch.equal(arena[r.out_off + o:r.out_off + o + n], pool.values[oo:oo + n]):
-                mismatches.append((r.rid, int(li)))
-
-    done = srv.run(times, reqs, check=check)
+    print(f"serve budget={budget_elems} streams={streams} requests={len(times)}", flush=True)
+    srv = Server(pool, budget_bytes=4 * budget_elems, streams=streams)
+    caller = CheckingCaller(pool, budget_elems)
+    done = srv.run(times, reqs, caller.get, caller.done)
     stats = summarize(done, srv.wall)
     srv.close()
+    bad = caller.finish()
     assert wp.check_code() == wp.OK
-    assert len(done) == len(times) and not mismatches, mismatches[:5]
-    assert peak[0] <= arena_elems
+    assert len(done) == len(times) and caller.checked == len(done)
+    assert bad == 0, f"{bad} wrong elements"
+    assert srv.peak_bytes <= 4 * budget_elems
     assert stats["p99_ms"] is not None and stats["p50_ms"] <= stats["p99_ms"]
     # the same requests decoded alone, bit for bit
     for r in done[:: max(1, len(done) // 40)]:
@@ -64,15 +59,17 @@ def test_mix_equals_alone_and_inputs(pool, arena_elems, streams):
             assert torch.equal(alone[o:o + n], pool.values[oo:oo + n])
 
 
-def test_requests_larger_than_half_the_arena_still_complete(pool):
-    # an arena that holds about one request at a time: admission queues the rest
-    big = int(max(pool.lens)) * 32
-    times = np.linspace(0, 0.01, 20)
+def test_requests_larger_than_half_the_budget_still_complete(pool):
+    # a budget that holds about one request at a time: admission queues the rest
+    times = np.zeros(20)  # all at once
     rng = np.random.default_rng(3)
     reqs = [rng.integers(0, 300, size=int(rng.integers(1, 33))) for _ in times]
     need = max(sum((int(pool.lens[i]) + 3) & ~3 for i in r) for r in reqs)
-    srv = Server(pool, arena_elems=max(need, 4096), streams=2)
-    done = srv.run(times, reqs)
+    budget = max(need, 4096)
+    srv = Server(pool, budget_bytes=4 * budget, streams=2)
+    caller = CheckingCaller(pool, 2 * budget)
+    done = srv.run(times, reqs, caller.get, caller.done)
     srv.close()
+    assert caller.finish() == 0
     assert len(done) == 20 and wp.check_code() == wp.OK
-    del big
+    assert srv.peak_bytes <= 4 * budget and srv.waited_for_budget > 0
