@@ -203,6 +203,21 @@ int32_t fastpfor_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, ui
 int32_t delta_decode_inplace(uint32_t *data, uint64_t n, uint32_t init, int32_t stride,
                              void *stream);
 
+/* delta_decode_inplace without any allocation, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc). Same arguments, result and errors as
+ * delta_decode_inplace, for n <= 2^28 integers (2^28 + 1 and more return
+ * WP_ERR_CAPACITY and enqueue nothing). Its scan status words live in a
+ * fixed 1 MiB array of the library's code object, one per device, held
+ * until the process ends; each call first clears the part it uses with a
+ * fill kernel (no memset node). Every call on a device shares that array:
+ * calls that overlap on one device (on different streams, or from several
+ * threads) race and give wrong sums; enqueue them on one stream or
+ * serialise them. The first call on a device looks the array's address up
+ * (no allocation). */
+int32_t delta_decode_inplace_noalloc(uint32_t *data, uint64_t n, uint32_t init, int32_t stride,
+                                     void *stream);
+
 /* Intersection of two decoded posting lists (the conjunctive-query step
  * that consumes decoded lists, discussed with the paper's conclusions):
  * writes the values present in both `a` (na values) and `b` (nb values),

@@ -86,6 +86,8 @@ def lib():
         f.restype = i32
     L.delta_decode_inplace.argtypes = [vp, u64, u32, i32, vp]
     L.delta_decode_inplace.restype = i32
+    L.delta_decode_inplace_noalloc.argtypes = [vp, u64, u32, i32, vp]
+    L.delta_decode_inplace_noalloc.restype = i32
     L.wp_max_compressed_words.argtypes = [i32, u64]
     L.wp_max_compressed_words.restype = u64
     L.wp_check.argtypes = [vp]

@@ -13,6 +13,7 @@
 // independent sums (residue classes mod 4): four status words per kind.
 #include <mutex>
 #include <unordered_map>
+#include <vector>
 
 #include "wp_device.hpp"
 #include "wp_host.hpp"
@@ -340,4 +341,59 @@ extern "C" int32_t delta_decode_inplace(uint32_t *data, uint64_t n, uint32_t ini
         return WP_ERR_HIP;
     (void)hipGetLastError();
     return launch_scan(data, n, init, (uint32_t)stride, status, st, true);
+}
+
+// ------------------------------------------------------------------------
+// The same scan with its status words in a fixed array of the library's
+// code object, for callers that cannot allocate. Every device holds its own
+// copy of the array at its own address, looked up once per device with
+// hipGetSymbolAddress; host code passes only that address to kernels and
+// never uses the array's name.
+
+namespace wp {
+
+constexpr uint64_t kNoAllocMaxN = 1ull << 28;
+constexpr uint64_t kNoAllocWords = (uint64_t)kStatusWords * ((kNoAllocMaxN + tile_ints(4) - 1) / tile_ints(4) + 1);
+
+static __device__ __align__(256) uint64_t scratch[kNoAllocWords];
+
+static std::mutex g_nmu;
+static std::vector<uint64_t *> g_noalloc_ptr;  // per device, nullptr until looked up
+
+static uint64_t *noalloc_scratch()
+{
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess)
+        return nullptr;
+    std::lock_guard<std::mutex> lk(g_nmu);
+    if ((int)g_noalloc_ptr.size() <= d)
+        g_noalloc_ptr.resize(d + 1, nullptr);
+    if (g_noalloc_ptr[d] == nullptr) {
+        uint64_t *ptr = nullptr;
+        if (hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr)
+            return nullptr;
+        g_noalloc_ptr[d] = ptr;
+    }
+    return g_noalloc_ptr[d];
+}
+
+}  // namespace wp
+
+extern "C" int32_t delta_decode_inplace_noalloc(uint32_t *data, uint64_t n, uint32_t init, int32_t stride,
+                                                void *stream)
+{
+    if (stride != 1 && stride != 4)
+        return WP_ERR_INVALID_ARG;
+    if (n > kNoAllocMaxN)
+        return WP_ERR_CAPACITY;
+    if (n == 0)
+        return WP_OK;
+    if (data == nullptr || !aligned16(data))
+        return WP_ERR_INVALID_ARG;
+    uint64_t *status = noalloc_scratch();
+    if (status == nullptr)
+        return WP_ERR_HIP;
+    (void)hipGetLastError();
+    // launch_scan clears the status words it uses with a fill kernel first
+    return launch_scan(data, n, init, (uint32_t)stride, status, as_stream(stream), true);
 }
