@@ -47,6 +47,7 @@
 #define OMAGIC_BPV 0x31565057u  /* "WPV1" */
 #define OMAGIC_SP 0x31535057u   /* "WPS1" */
 #define OB32 32u               /* BP32 block: 32 integers (Section 6.2) */
+#define OSEG_BLOCKS 64u        /* patched-page segment: 64 blocks (8192 integers) */
 
 enum { O_OK = 0, O_ERR_ARG = -1, O_ERR_CAP = -2, O_ERR_CORRUPT = -3 };
 
@@ -284,11 +285,12 @@ uint64_t oracle_max_words(int codec, uint64_t n)
          * padding); at most one 64-bit Simple-8b word per exception */
         words += units * (4 + 3 + 4) + nfull * (OB + (3 + OB) / 4 + 1 + 2 * OB);
     } else {
-        /* per page: header <= 36 words; packed <= 128 words per block;
+        /* per page: header <= 64 words (4 + 32 counts + 7 segment bases of
+         * up to 4 words); packed <= 128 words per block;
          * metadata <= (3 + 127) bytes per block (+16 B padding); every array
          * k holds at most one group of padding, and the exception bits of a
          * block never exceed 32*127 */
-        words += units * (36 + 4 + 32 * 4 * 32) + nfull * (OB + (3 + 127) / 4 + 1 + 127);
+        words += units * (64 + 4 + 32 * 4 * 32) + nfull * (OB + (3 + 127) / 4 + 1 + 127);
     }
     words += (tail * 5 + 3) / 4;
     return words;
@@ -395,8 +397,16 @@ static uint64_t o_bp32_unit(const uint32_t *d, uint64_t nmeta, uint32_t *out)
 
 /* ---- Section 5, FastPFOR page, re-arranged for parallel parsing:
  *   [nblocks, packed_words, meta_bytes, bitset] + count_k for every set k
- *       (ascending), zero-padded to 4 words.  bitset bit k-1 <=> array k
- *       non-empty, k = 1..32 (the 32-bit bitset of Section 5)
+ *       (ascending) + the segment bases, zero-padded to 4 words.  bitset bit
+ *       k-1 <=> array k non-empty, k = 1..32 (the 32-bit bitset of Section
+ *       5). Segment bases (an addition to the paper's page, for decoding
+ *       one page by several independent parallel workers): the page's
+ *       blocks form segments of 64 (8192 integers); for every segment g >= 1
+ *       the S values just before its first integer, x[start_g - S + s],
+ *       s = 0..S-1 (S = stride; none for stride 0). Section 3's prefix sum
+ *       is the only dependency between the blocks of a page that the
+ *       metadata does not settle: with these values each segment's sums
+ *       start on their own. Cost: S words per 8192 integers.
  *   packed: block t's low b_t bits of its 128 values, 4*b_t words each,
  *       blocks back to back
  *   metadata bytes: b[nblocks], maxb[nblocks], c[nblocks], then every
@@ -407,7 +417,8 @@ static uint64_t o_bp32_unit(const uint32_t *d, uint64_t nmeta, uint32_t *out)
  *       of exceptions of blocks with maxb - b = k, in block order, packed
  *       at k bits in groups of 128 (SIMD-FastPFOR pads to a multiple of 128
  *       values; the padding values are 0), 4*k words per group. */
-static uint64_t o_fp_page(const uint32_t *d, uint64_t nblocks, uint32_t *out, uint64_t pad)
+static uint64_t o_fp_page(const uint32_t *d, uint64_t nblocks, uint32_t *out, uint64_t pad,
+                          const uint32_t *x, uint64_t start, int stride)
 {
     uint32_t *bw = malloc(nblocks * sizeof(uint32_t));
     uint32_t *mb = malloc(nblocks * sizeof(uint32_t));
@@ -446,7 +457,8 @@ static uint64_t o_fp_page(const uint32_t *d, uint64_t nblocks, uint32_t *out, ui
             nset++;
         }
     uint64_t meta_bytes = 3 * nblocks + npos;
-    uint64_t hdr_words = o_pad4(4 + nset);
+    uint64_t nseg = (nblocks + OSEG_BLOCKS - 1) / OSEG_BLOCKS;
+    uint64_t hdr_words = o_pad4(4 + nset + (uint64_t)stride * (nseg - 1));
     memset(out, 0, hdr_words * sizeof(uint32_t));
     out[0] = (uint32_t)nblocks;
     out[1] = (uint32_t)packed_words;
@@ -456,6 +468,11 @@ static uint64_t o_fp_page(const uint32_t *d, uint64_t nblocks, uint32_t *out, ui
     for (uint32_t k = 1; k <= 32; k++)
         if (cnt[k] != 0)
             out[hi++] = (uint32_t)cnt[k];
+    for (uint64_t g = 1; g < nseg; g++) {
+        uint64_t sg = start + g * OSEG_BLOCKS * OB; /* first integer of segment g */
+        for (int t = 0; t < stride; t++)
+            out[hi++] = x[sg - (uint64_t)stride + (uint64_t)t];
+    }
     uint64_t p = hdr_words;
     /* packed truncated values (oracle_pack keeps the low b bits) */
     for (uint64_t t = 0; t < nblocks; t++) {
@@ -673,7 +690,7 @@ static int64_t o_encode(int codec, const uint32_t *x, uint64_t n, int stride,
             p += (codec == 0 || codec == 4) ? o_bp_unit(d + start, nb, out + p, codec == 4)
                  : codec == 2 ? o_bp32_unit(d + start, nb, out + p)
                  : codec == 5 ? o_sp_page(d + start, nb, out + p)
-                              : o_fp_page(d + start, nb, out + p, codec == 3 ? 32 : OB);
+                              : o_fp_page(d + start, nb, out + p, codec == 3 ? 32 : OB, x, start, stride);
         }
     }
     uint64_t tail_off = p;
@@ -752,7 +769,7 @@ static int o_bp32_unit_decode(const uint32_t *w, uint64_t avail, uint64_t nmeta,
  * listed position gains the next high part of array k = maxb - b, shifted
  * left by b. */
 static int o_fp_page_decode(const uint32_t *w, uint64_t avail, uint64_t nblocks_expected,
-                            uint32_t *d, uint64_t pad)
+                            uint32_t *d, uint64_t pad, int stride, uint32_t *segb)
 {
     if (avail < 4)
         return O_ERR_CORRUPT;
@@ -764,7 +781,8 @@ static int o_fp_page_decode(const uint32_t *w, uint64_t avail, uint64_t nblocks_
     for (uint32_t k = 1; k <= 32; k++)
         if (bitset & (1u << (k - 1)))
             nset++;
-    uint64_t hdr_words = o_pad4(4 + nset);
+    uint64_t nseg = (nblocks + OSEG_BLOCKS - 1) / OSEG_BLOCKS;
+    uint64_t hdr_words = o_pad4(4 + nset + (uint64_t)stride * (nseg - 1));
     if (hdr_words > avail)
         return O_ERR_CORRUPT;
     uint64_t cnt[33] = {0};
@@ -775,6 +793,9 @@ static int o_fp_page_decode(const uint32_t *w, uint64_t avail, uint64_t nblocks_
             if (cnt[k] == 0 || cnt[k] > nblocks * OB)
                 return O_ERR_CORRUPT;
         }
+    /* the segment bases, checked by the caller against the decoded values */
+    for (uint64_t i = 0; i < (uint64_t)stride * (nseg - 1); i++)
+        segb[i] = w[hi++];
     uint64_t p = hdr_words;
     uint64_t packed_at = p;
     if (packed_words > avail - p)
@@ -938,6 +959,8 @@ static int o_decode(int codec, const uint32_t *in, uint64_t in_words, uint32_t *
         uint64_t end = (u + 1 < units) ? in[8 + u + 1] : tail_off;
         uint64_t start = (u == units) ? nfull * OB : u * per * OB;
         uint64_t count;
+        uint64_t nsegb = 0;      /* stored segment bases of a patched page */
+        uint32_t segb[4 * (OFP_BLOCKS / OSEG_BLOCKS)];
         int rc;
         if (u < units) {
             uint64_t nb = nfull - u * per;
@@ -949,7 +972,10 @@ static int o_decode(int codec, const uint32_t *in, uint64_t in_words, uint32_t *
             rc = (codec == 0 || codec == 4) ? o_bp_unit_decode(in + off, end - off, nb, out + start, codec == 4)
                  : codec == 2 ? o_bp32_unit_decode(in + off, end - off, nb, out + start)
                  : codec == 5 ? o_sp_page_decode(in + off, end - off, nb, out + start)
-                              : o_fp_page_decode(in + off, end - off, nb, out + start, codec == 3 ? 32 : OB);
+                              : o_fp_page_decode(in + off, end - off, nb, out + start, codec == 3 ? 32 : OB,
+                                                 stride, segb);
+            if (codec == 1 || codec == 3)
+                nsegb = (uint64_t)stride * ((nb + OSEG_BLOCKS - 1) / OSEG_BLOCKS - 1);
         } else {
             count = tail;
             if (off != tail_off || off + (tail_bytes + 3) / 4 != total)
@@ -964,6 +990,13 @@ static int o_decode(int codec, const uint32_t *in, uint64_t in_words, uint32_t *
         for (uint64_t i = 0; i < count && stride != 0; i++) {
             uint32_t prev = (i >= (uint64_t)stride) ? out[start + i - stride] : bases[i];
             out[start + i] = out[start + i] + prev;
+        }
+        /* a patched page's segment bases are the values just before each
+         * segment */
+        for (uint64_t i = 0; i < nsegb; i++) {
+            uint64_t g = 1 + i / (uint64_t)stride, t = i % (uint64_t)stride;
+            if (out[start + g * OSEG_BLOCKS * OB - (uint64_t)stride + t] != segb[i])
+                return O_ERR_CORRUPT;
         }
     }
     if (ndir == 0 && total != dir_end)

@@ -379,7 +379,11 @@ def test_patched_page_counts_match_blocks():
     page = int(s[8])
     nblocks, packed_words, meta_bytes, bitset = (int(v) for v in s[page:page + 4])
     assert nblocks == 512
-    meta_at = page + (-(-(4 + bin(bitset).count("1")) // 4) * 4) + packed_words
+    # after the counts: the value before each of the page's segments of 64
+    # blocks but the first (stride 1: one word each), taken from the input
+    nset = bin(bitset).count("1")
+    assert [int(v) for v in s[page + 4 + nset:page + 4 + nset + 7]] == [int(x[g * 8192 - 1]) for g in range(1, 8)]
+    meta_at = page + (-(-(4 + nset + 7) // 4) * 4) + packed_words
     meta = s[meta_at:].view(np.uint8)
     b, mb, c = meta[:512].astype(int), meta[512:1024].astype(int), meta[1024:1536].astype(int)
     assert meta_bytes == 3 * 512 + c.sum()
@@ -600,6 +604,12 @@ def test_bp32_never_wider_than_bp128_plus_descriptors():
 
 # ---------------------------------------------------------------- FastPFOR, arrays padded to 32 (Section 5)
 
+def _fp_hdr_words(nb, nset, stride):
+    """Words of a patched page's header: 4 fixed words, a count per set k,
+    stride words per 64-block segment after the first, padded to 4."""
+    return -(-(4 + nset + stride * (-(-nb // 64) - 1)) // 4) * 4
+
+
 def _fp_pages(s):
     """(offset, words, nblocks, packed_words, meta_bytes, counts by k) of each page."""
     units = int(s[4])
@@ -628,7 +638,7 @@ def test_fastpfor_32_padding_against_128(stride):
     saved = 0
     for (oa, wa, nba, pka, ma, ca), (ob, wb, nbb, pkb, mb_, cb) in zip(pa, pb):
         assert (nba, pka, ma, ca) == (nbb, pkb, mb_, cb)
-        hdr = -(-(4 + len(ca)) // 4) * 4
+        hdr = _fp_hdr_words(nba, len(ca), stride)
         meta_w = -(-ma // 16) * 4
         fixed = hdr + pka + meta_w
         assert np.array_equal(a[oa:oa + fixed], b[ob:ob + fixed])
@@ -780,7 +790,7 @@ def test_simplepfor_pages_are_fastpfor_pages_but_for_the_exceptions():
         nb, packed, meta_bytes, bitset = (int(v) for v in fp[fo:fo + 4])
         assert [int(v) for v in sp[so:so + 3]] == [nb, packed, meta_bytes]
         nset = bin(bitset).count("1")
-        fh = (4 + nset + 3) // 4 * 4
+        fh = _fp_hdr_words(nb, nset, 1)
         meta_w = (meta_bytes + 15) // 16 * 4
         assert np.array_equal(fp[fo + fh:fo + fh + packed + meta_w], sp[so + 4:so + 4 + packed + meta_w])
         # the Simple-8b array holds one high part per exception, in block order
@@ -812,3 +822,43 @@ def test_simplepfor_corrupt_streams_are_rejected():
         bad[at] = val & 0xFFFFFFFF
         assert oracle.sp_decode_rc(bad, x.size) == oracle.ERR_CORRUPT, at
     assert oracle.sp_decode_rc(oracle.fp_encode(x, 1), x.size) == oracle.ERR_CORRUPT
+
+
+# ---------------------------------------------------------------- segment bases of patched pages
+
+@pytest.mark.parametrize("stride", [1, 4])
+@pytest.mark.parametrize("codec", ["fp", "fp32"])
+def test_patched_segment_bases_are_the_inputs_before_each_segment(stride, codec):
+    # after the per-array counts, a page header holds, for each 64-block
+    # segment but the first, the `stride` input values just before it; a
+    # page of nb blocks has ceil(nb / 64) segments
+    enc, rc = ((oracle.fp_encode, oracle.fp_decode_rc) if codec == "fp"
+               else (oracle.fp32_encode, oracle.fp32_decode_rc))
+    x = datagen.patched_gaps(2 * 65536 + 200 * 128 + 33, seed=60 + stride)
+    s = enc(x, stride)
+    units = int(s[4])
+    assert units == 3
+    for u in range(units):
+        at = int(s[8 + u])
+        nb, _, _, bitset = (int(v) for v in s[at:at + 4])
+        nseg = -(-nb // 64)
+        assert nseg == (8 if u < 2 else 4)
+        h = at + 4 + bin(bitset).count("1")
+        got = [int(v) for v in s[h:h + stride * (nseg - 1)]]
+        first = u * 65536
+        want = [int(x[first + g * 8192 - stride + t]) for g in range(1, nseg) for t in range(stride)]
+        assert got == want
+        # a wrong segment base is rejected (it disagrees with the decoded values)
+        bad = s.copy()
+        bad[h + stride * (nseg - 1) - 1] ^= np.uint32(1 << 7)
+        assert rc(bad, x.size) == oracle.ERR_CORRUPT
+    assert rc(s, x.size) == oracle.OK
+
+
+def test_patched_stride0_pages_hold_no_segment_bases():
+    x = datagen.patched_gaps(65536, seed=66)
+    s = oracle.fp_encode(x, 0)
+    at = int(s[8])
+    nb, packed, _, bitset = (int(v) for v in s[at:at + 4])
+    assert nb == 512 and _fp_hdr_words(nb, bin(bitset).count("1"), 0) == -(-(4 + bin(bitset).count("1")) // 4) * 4
+    assert np.array_equal(oracle.fp_decode(s, x.size), x)

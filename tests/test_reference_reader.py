@@ -89,12 +89,17 @@ def _bp32_unit(w, nmeta):
     return out
 
 
-def _fp_page(w, nblocks, pad):
+def _fp_page(w, nblocks, pad, S):
+    """Patched page: (deltas, segment bases). After the counts, the header
+    holds S words for every 64-block segment but the first: the values just
+    before that segment."""
     nb, packed, meta_bytes, bitset = (int(v) for v in w[:4])
     assert nb == nblocks
     ks = [k for k in range(1, 33) if bitset >> (k - 1) & 1]
     counts = {k: int(w[4 + i]) for i, k in enumerate(ks)}
-    at = -(-(4 + len(ks)) // 4) * 4
+    nseg = -(-nb // 64)
+    segb = [int(v) for v in w[4 + len(ks):4 + len(ks) + S * (nseg - 1)]]
+    at = -(-(4 + len(ks) + S * (nseg - 1)) // 4) * 4
     packed_at = at
     at += packed
     meta = bytes(np.asarray(w[at:at + -(-meta_bytes // 16) * 4], dtype=np.uint32).tobytes())[:meta_bytes]
@@ -120,7 +125,7 @@ def _fp_page(w, nblocks, pad):
         p_at += c[t]
         out += vals
     assert all(taken[k] == counts[k] for k in ks)
-    return out
+    return out, segb
 
 
 def _sp_page(w, nblocks):
@@ -182,7 +187,7 @@ def read(stream, codec):
             elif codec == "sp":
                 d = _sp_page(w, nb)
             else:
-                d = _fp_page(w, nb, 32 if codec == "fp32" else 128)
+                d, segb = _fp_page(w, nb, 32 if codec == "fp32" else 128, S)
         else:
             assert offs[u] == tail_off
             d = _vbyte(s[tail_off:total].tobytes()[:tail_bytes], tail)
@@ -191,6 +196,11 @@ def read(stream, codec):
         for i, v in enumerate(d):
             prev = (x[i - S] if i >= S else bases[i]) if S else 0
             x.append((v + prev) & 0xFFFFFFFF)
+        if u < units and codec in ("fp", "fp32"):
+            # segment g's stored bases are the values just before it
+            for i, v in enumerate(segb):
+                g, t = 1 + i // S, i % S
+                assert x[g * 64 * 128 - S + t] == v
         out += x
         assert len(out) == start + len(d)
     assert len(out) == n
