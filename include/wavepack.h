@@ -57,7 +57,11 @@
  *       behind a 32-bit descriptor of 8-bit widths, blocks 32-bit aligned).
  *       patched -- a page of up to 512 blocks (2^16 values), Section 5:
  *       [nblocks, packed_words, meta_bytes, bitset] + one count per
- *       non-empty exception array k (bit k-1 of bitset), padded to 4 words;
+ *       non-empty exception array k (bit k-1 of bitset) + the segment
+ *       bases: for each 64-block segment of the page but the first, the S
+ *       values just before its first integer (x[start - S + s]; an addition
+ *       to the paper's page that lets the segments decode independently),
+ *       padded to 4 words;
  *       the blocks' low b bits (4*b words each); the metadata bytes
  *       b[nblocks], maxb[nblocks], c[nblocks] and all exception positions,
  *       padded to 16 bytes; then for each k ascending the high parts
@@ -303,12 +307,11 @@ const char *wp_strerror(int32_t code);
 /* ---------------------------------------------------------------------- */
 /* Batched decoding of many lists in one launch (not in the paper: the GPU
  * counterpart of decoding many posting lists). A plan turns a list
- * registry into work items -- patched pages, runs of meta-blocks and
- * tails of lists without full blocks -- and one kernel launch covers them
- * all: a workgroup for each patched page of more than 64 blocks, then a
- * wavefront for each run, small page and tail, each class largest first
- * (the hardware dispatcher balances the load; there is no work queue).
- * The item holding a list's last unit also decodes the list's tail. */
+ * registry into work items -- 64-block segments of patched pages, runs of
+ * meta-blocks and tails of lists without full blocks -- and one kernel
+ * launch covers them all, a wavefront for each item, largest first (the
+ * hardware dispatcher balances the load; there is no work queue). The
+ * item holding a list's last unit also decodes the list's tail. */
 
 typedef struct wp_list {
     uint64_t comp_off_words; /* stream start, in words from `pool` (multiple of 4) */
@@ -334,7 +337,7 @@ typedef struct wp_tune {
 /* Builds a plan: validates the registry on the host (codec, alignment of
  * comp_off_words and out_off (or of the list's own `out`) to 4 words,
  * comp_words >= 8), cuts every list
- * into work items (runs of run_units meta-blocks, single pages, tails
+ * into work items (runs of run_units meta-blocks, page segments, tails
  * of lists without full blocks; largest first), uploads the list and item arrays (it synchronises
  * `stream` once), and, when tune->use_graph, builds and instantiates a
  * hipGraph holding the decoder's kernel node. `pool` and

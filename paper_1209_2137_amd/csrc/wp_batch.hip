@@ -1,7 +1,7 @@
 // Batched decoding of many lists in one launch.
 //
-// The host planner cuts every list into work items: patched pages (one
-// each), runs of up to `run_units` meta-blocks (binary packing) and the
+// The host planner cuts every list into work items: segments of 64 blocks
+// of patched pages, runs of up to `run_units` meta-blocks (binary packing) and the
 // Variable Byte tails of lists without full blocks. The tail of any other
 // list is decoded by the item that holds the list's last unit. One grid
 // covers the items, one wavefront each with no barrier at all, ordered
@@ -53,9 +53,10 @@ __device__ __forceinline__ bool item_header(const DevList *__restrict__ lists, c
 }
 
 // Item `it` -- a run of binary-packing meta-blocks {list, kind, first unit,
-// unit count}, a patched page {list, kind, page, its blocks} or a tail --
-// decoded by one wavefront; the item holding a list's last unit also
-// decodes its tail. Uniform result.
+// unit count}, a segment of a patched page {list, kind, page, its blocks |
+// segment << 16} or a tail -- decoded by one wavefront; the item holding a
+// list's last unit (its last segment) also decodes its tail. Uniform
+// result.
 template <int DEPTH>
 __device__ __forceinline__ bool wave_item(const DevList *__restrict__ lists, const uint4 *__restrict__ items, uint32_t it,
                           WaveItemLds<DEPTH> &W)
@@ -77,10 +78,14 @@ __device__ __forceinline__ bool wave_item(const DevList *__restrict__ lists, con
         last = first + count == H.units;
     } else if (item.y == kItemFpPage) {
         const uint64_t u = item.z;
+        const uint32_t seg = item.w >> 16;
         if (!(Ld.codec == WP_CODEC_FP && u < H.units))
             return false;
-        ok = fp_unit(Ld.comp, H, u, Ld.out, W.fp);
-        last = u + 1 == H.units;
+        const uint32_t nseg = page_items<kPageFp>(page_blocks(H, u));
+        if (seg >= nseg)
+            return false;
+        ok = fp_unit(Ld.comp, H, u, seg, Ld.out, W.fp);
+        last = u + 1 == H.units && seg + 1 == nseg;
     } else {
         return item.y == kItemTail && H.tail != 0 && decode_tail_entry<1, false>(Ld.comp, H, Ld.out, W.tail);
     }
@@ -250,7 +255,10 @@ static bool build_items(const uint32_t *pool, uint32_t *out_base, const wp_list 
             const uint64_t units = (nfull + kFpBlocks - 1) / kFpBlocks;
             for (uint64_t u = 0; u < units; ++u) {
                 const uint64_t nb = std::min<uint64_t>(kFpBlocks, nfull - u * kFpBlocks);
-                unit_items.push_back(make_uint4(li, kItemFpPage, (uint32_t)u, (uint32_t)nb));
+                for (uint32_t g = 0; g < page_items<kPageFp>((uint32_t)nb); ++g) {
+                    const uint32_t sb = (uint32_t)std::min<uint64_t>(kSegBlocks, nb - g * kSegBlocks);
+                    unit_items.push_back(make_uint4(li, kItemFpPage, (uint32_t)u, sb | (g << 16)));
+                }
             }
         }
         // a tail has an item of its own only in a list without full blocks;
@@ -259,7 +267,7 @@ static bool build_items(const uint32_t *pool, uint32_t *out_base, const wp_list 
             tail_items.push_back(make_uint4(li, kItemTail, 0, 0));
     }
     // largest first by blocks (a run of w meta-blocks holds up to 16 w), then tails
-    auto blocks = [](const uint4 &a) { return a.y == kItemBpRun ? 16u * a.w : a.w; };
+    auto blocks = [](const uint4 &a) { return a.y == kItemBpRun ? 16u * a.w : (a.w & 0xffffu); };
     std::stable_sort(unit_items.begin(), unit_items.end(),
                      [&](const uint4 &a, const uint4 &b) { return blocks(a) > blocks(b); });
     items.reserve(unit_items.size() + tail_items.size());

@@ -9,9 +9,10 @@
 // BP32 streams (32-integer blocks) take the same kernel in its B32 mode,
 // SIMD-BP128 streams with the four-lane block layout in its V mode.
 //
-// Patched pages: one wavefront per page (fp_wave_page), a workgroup being
-// WAVES such pages side by side; FastPFOR streams (exception arrays padded
-// to 32 values) take the same kernel in its P32 mode.
+// Patched pages: one wavefront per 64-block segment of a page
+// (fp_wave_page), a workgroup being WAVES such segments side by side;
+// FastPFOR streams (exception arrays padded to 32 values) take the same
+// kernel in its P32 mode; a SimplePFOR page is one wavefront.
 #include <mutex>
 #include <vector>
 
@@ -78,11 +79,17 @@ union FpWaveItemLds<kPageFp32> {
     TailLds<1> tail;
 };
 
-// Wavefront w of workgroup g decodes page g * WAVES + w; the wavefront
-// after the last page decodes the tail. KIND: SIMD-FastPFOR, FastPFOR or
-// SimplePFOR pages.
+// Wavefronts resident per SIMD that the patched-page kernel is compiled
+// for (register budget).
+#ifndef WP_FP_MIN_WAVES
+#define WP_FP_MIN_WAVES 8
+#endif
+
+// Wavefront w of workgroup g takes item i = g * WAVES + w: segment i % 8 of
+// page i / 8 (SimplePFOR: page i); the item after the last page's decodes
+// the tail. KIND: SIMD-FastPFOR, FastPFOR or SimplePFOR pages.
 template <int WAVES, int KIND = kPageFp>
-__global__ __launch_bounds__(64 * WAVES) void k_fp_decode(const uint32_t *__restrict__ in, uint64_t in_words,
+__global__ __launch_bounds__(64 * WAVES, WP_FP_MIN_WAVES) void k_fp_decode(const uint32_t *__restrict__ in, uint64_t in_words,
                                                           uint32_t *__restrict__ out, uint64_t n,
                                                           int *__restrict__ err)
 {
@@ -95,16 +102,19 @@ __global__ __launch_bounds__(64 * WAVES) void k_fp_decode(const uint32_t *__rest
         return;
     }
     const uint32_t wave = uniform(threadIdx.x >> 6);
-    const uint64_t u = (uint64_t)blockIdx.x * WAVES + wave;
+    constexpr uint32_t per = KIND == kPageSp ? 1u : kPageSegs;
+    const uint64_t item = (uint64_t)blockIdx.x * WAVES + wave;
+    const uint64_t u = item / per;
+    const uint32_t seg = (uint32_t)(item % per);
     bool ok = true;
     if (u == H.units) {
-        if (H.tail)
+        if (H.tail && seg == 0)
             ok = decode_tail_entry<1, false>(in, H, out, L[wave].tail);
-    } else if (u < H.units) {
+    } else if (u < H.units && seg < page_items<KIND>(page_blocks(H, u))) {
         if constexpr (KIND == kPageSp)
-            ok = fp_unit<KIND>(in, H, u, out, L[wave].sp.fp, L[wave].sp.ring);
+            ok = fp_unit<KIND>(in, H, u, seg, out, L[wave].sp.fp, L[wave].sp.ring);
         else
-            ok = fp_unit<KIND>(in, H, u, out, L[wave].page);
+            ok = fp_unit<KIND>(in, H, u, seg, out, L[wave].page);
     }
     if (!ok && lane_id() == 0)
         *err = kErrCorrupt;
@@ -248,8 +258,9 @@ static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, u
 #undef WP_BP
 #undef WP_BP_D
     } else {
-        // one wavefront per page, then one for the tail
-        uint64_t grid = (units + has_tail + t.waves - 1) / t.waves;
+        // one wavefront per segment (SimplePFOR: per page), then one for the tail
+        const uint64_t per_page = codec == WP_CODEC_SP ? 1 : kPageSegs;
+        uint64_t grid = (units * per_page + has_tail + t.waves - 1) / t.waves;
         grid = grid ? grid : 1;
         if (grid > 0x7FFFFFFFull)
             return WP_ERR_INVALID_ARG;
@@ -378,10 +389,11 @@ extern "C" uint64_t wp_max_compressed_words(int32_t codec, uint64_t n)
         // one 64-bit Simple-8b word (two words) per exception
         w += units * (4 + 3 + 4) + nfull * (128 + 33 + 1 + 2 * 128);
     } else {
-        // page header <= 36 words; metadata <= 130 bytes per block + 16 bytes
-        // padding; packed <= 128 words per block; exception bits of a block
-        // <= 127 * 32; one group of padding for each of the 32 arrays
-        w += units * (36 + 4 + 32 * 4 * 32) + nfull * (128 + 33 + 127);
+        // page header <= 64 words (4, a count per array, seven segment
+        // bases of up to four words); metadata <= 130 bytes per block + 16
+        // bytes padding; packed <= 128 words per block; exception bits of a
+        // block <= 127 * 32; one group of padding for each of the 32 arrays
+        w += units * (64 + 4 + 32 * 4 * 32) + nfull * (128 + 33 + 127);
     }
     w += (tail * 5 + 3) / 4;
     return w > 0xFFFFFFFFull ? 0 : w;

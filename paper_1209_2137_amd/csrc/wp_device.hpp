@@ -363,9 +363,18 @@ __device__ __forceinline__ void scan_wave4(uint32_t (&x)[4], uint32_t (&carry)[4
 }
 
 // ------------------------------------------------------------------------
-// Patched page (Section 5) decoded by one wavefront, 1..512 blocks, with no
-// workgroup barrier: the page is decoded in block order, four blocks (512
-// integers) per pass, the prefix sum carried from the page's stored base.
+// Patched page (Section 5) decoded by segments of 64 blocks, one
+// wavefront each, with no workgroup barrier: a segment is decoded in block
+// order, four blocks (512 integers) per pass, the prefix sum carried from
+// the segment's base (the unit's stored bases for the first segment, the
+// page header's segment bases for the others). Everything else a segment
+// needs follows from the page's metadata bytes: before its own blocks, the
+// wavefront reads the widths and exception counts of the earlier segments'
+// blocks (three byte loads per lane and segment, all in flight at once)
+// for the packed-word and position offsets where its segment starts and,
+// per array k, the exceptions before it (LDS atomics). A segment that is
+// not the page's last checks its final running value against the next
+// segment's stored base; the last one checks the page's totals.
 //
 // Block records {b | k << 8 | c << 16, word offset in the packed region,
 // bit offset of the block's first exception's high part from the page
@@ -392,30 +401,61 @@ __device__ __forceinline__ void scan_wave4(uint32_t (&x)[4], uint32_t (&carry)[4
 // Three page kinds share this: SIMD-FastPFOR (exception arrays padded to
 // 128 values), FastPFOR (padded to 32) and SimplePFOR, whose high parts
 // are one Simple-8b array over the page in block order (Section 5, and
-// the Simple-8b modes of Section 2). A SimplePFOR page is decoded into an
+// the Simple-8b modes of Section 2). A SimplePFOR page has no segment
+// bases: one wavefront decodes the whole page (its records built round by
+// round, two rounds in an LDS ring). A SimplePFOR page is decoded into an
 // LDS ring of high parts as the passes need them: a wavefront takes up to
 // 64 Simple-8b words at a time (lane i word i), a wave scan of the counts
 // their selectors give places each word's integers, and the words are
 // loaded one batch ahead.
 enum : int { kPageFp = 0, kPageFp32 = 1, kPageSp = 2 };
 constexpr uint32_t kSpRing = 2048;  // high parts held by a SimplePFOR page's ring
+constexpr uint32_t kSegBlocks = 64;  // blocks per segment of a patched page
+constexpr uint32_t kSegInts = kSegBlocks * kBlock;
+constexpr uint32_t kPageSegs = kFpBlocks / kSegBlocks;
 
-struct alignas(16) FpWaveLds {
-    uint32_t buf[4 * kBlock + 4];  // a pass's packed words, then its integers in block order
-    uint4 rec[2][64];              // block records of two rounds of 64 blocks
-    uint32_t kcar[33];             // exceptions of the rounds built so far, per array k
-    uint32_t excb[33];             // page word offset of array k
+// Wavefront items of a patched page of nb blocks: its segments (one for a
+// SimplePFOR page).
+template <int KIND>
+__host__ __device__ constexpr uint32_t page_items(uint32_t nb)
+{
+    return KIND == kPageSp ? 1u : (nb + kSegBlocks - 1) / kSegBlocks;
+}
+
+// A segment's packed words stream through a per-wavefront LDS ring in
+// chunks of one 16-byte load per lane (256 words), kFpDepth chunks loaded
+// ahead: each read from HBM is a contiguous kilobyte or more, not a pass's
+// few hundred bytes between other wavefronts' stores.
+constexpr uint32_t kFpCW = 256;
+constexpr uint32_t kFpDepth = 2;
+constexpr uint32_t kFpRing = 1024;        // >= kFpDepth * kFpCW + the largest pass (512 words)
+constexpr uint32_t kFpMir = kBlock + 4;   // ring words mirrored after its end
+static_assert(kFpRing >= kFpDepth * kFpCW + 4 * kBlock && (kFpRing & (kFpRing - 1)) == 0, "ring size");
+
+// R: rounds of block records held (a FastPFOR segment is one round; a
+// SimplePFOR page keeps two rounds in a ring).
+template <int R>
+struct alignas(16) FpLdsT {
+    uint32_t ring[kFpRing + kFpMir];  // packed words of the segment
+    uint32_t buf[4 * kBlock + 4];     // a pass's integers in block order
+    uint4 rec[R][64];                 // block records of R rounds of 64 blocks
+    uint32_t kcar[33];                // exceptions of the rounds built so far, per array k
+    uint32_t excb[33];                // page word offset of array k
 };
+using FpWaveLds = FpLdsT<1>;
+template <int KIND>
+using FpLdsOf = FpLdsT<KIND == kPageSp ? 2 : 1>;
 
 struct alignas(16) SpWaveLds {
-    FpWaveLds fp;
+    FpLdsT<2> fp;
     uint32_t ring[kSpRing];  // decoded high parts, by their index in the page mod kSpRing
 };
 
 // What a pass needs, fetched ahead (per lane unless noted).
 struct FpFetch {
-    uint4 pk0, pk1;        // the pass's packed words: words 4l..4l+3 and 256+4l..256+4l+3
-    uint32_t u0, u1;       // blocks A|B (half 0), C|D (half 1): the lane's block width | its first word << 8
+    uint32_t pe;           // uniform: end of the pass's packed words, from the segment's first
+    uint32_t u0, u1;       // blocks A|B (half 0), C|D (half 1): the lane's block width | its first
+                           // word (from the segment's first) << 8
     uint32_t pos, lo, hi;  // exception `lane` of the pass: position byte, the words holding its high
                            // part (SimplePFOR: lo is the high part itself)
     uint32_t em;           // its bit shift | (b & 31) << 8 | its block in the pass << 16 | first of its block << 18
@@ -450,20 +490,23 @@ __device__ __forceinline__ uint32_t s8_mode(uint32_t sel)
     return cnt | (bits << 8);
 }
 
-// Decodes the patched page at `page` (16-byte aligned, `nwords` words,
-// which must hold `nb` blocks) into out[0, 128 nb) with differential
-// coding of stride S from `base`. One wavefront; `ring` is the LDS ring of
-// a SimplePFOR page (KIND kPageSp), unused otherwise. Returns the page's
-// validity (uniform); every access stays inside the page, out[0, 128 nb)
-// and the wavefront's LDS whatever the page holds.
+// Decodes segment `seg` of the patched page at `page` (16-byte aligned,
+// `nwords` words, which must hold `nb` blocks; a SimplePFOR page is one
+// segment) into its part of out[0, 128 nb) (the page's output) with
+// differential coding of stride S, the page's first segment starting from
+// `ubase` (the unit's stored bases). One wavefront; `ring` is the LDS ring
+// of a SimplePFOR page (KIND kPageSp), unused otherwise. Returns the
+// segment's validity (uniform); every access stays inside the page, the
+// segment's output range and the wavefront's LDS whatever the page holds.
 template <uint32_t S, int KIND = kPageFp>
 __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, uint32_t nwords, uint32_t nb,
-                                             const uint32_t (&base)[4], uint32_t *__restrict__ out, FpWaveLds &L,
-                                             uint32_t *ring = nullptr)
+                                             uint32_t seg, const uint32_t (&ubase)[4], uint32_t *__restrict__ out,
+                                             FpLdsOf<KIND> &L, uint32_t *ring = nullptr)
 {
     constexpr bool SP = KIND == kPageSp;
+    constexpr uint32_t NR = SP ? 2u : 1u;  // rounds of records held
     const uint32_t lane = lane_id();
-    if (nwords < 4 || nb == 0 || nb > kFpBlocks)
+    if (nwords < 4 || nb == 0 || nb > kFpBlocks || seg >= page_items<KIND>(nb))
         return false;
     // SIMD-FastPFOR / FastPFOR: [nblocks, packed_words, meta_bytes, bitset]
     // + a count per non-empty array; SimplePFOR: [nblocks, packed_words,
@@ -472,7 +515,8 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
                    w3 = uniform(page[3]);
     const uint32_t bitset = SP ? 0u : w3;
     const uint32_t nset = __builtin_popcount(bitset);
-    const uint32_t hdr_w = pad4(4 + nset);
+    const uint32_t nseg = page_items<KIND>(nb);
+    const uint32_t hdr_w = pad4(4 + nset + (SP ? 0u : S * (nseg - 1)));  // + the segment bases
     const uint32_t meta_w = ((meta_bytes + 15u) / 16u) * 4u;
     if (h_nb != nb || hdr_w > nwords || packed_words > nwords - hdr_w || meta_bytes < 3 * nb ||
         meta_bytes > 3 * nb + 127 * nb || meta_w > nwords - hdr_w - packed_words || (packed_words & 3u))
@@ -482,6 +526,20 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
     const uint32_t exc_at = hdr_w + packed_words + meta_w;
     const BufRsrc rpg = make_rsrc(page, nwords * 4u);
     const bool kl = lane < 32;
+    // the segment: blocks [blk0, blk1)
+    const uint32_t blk0 = SP ? 0u : seg * kSegBlocks;
+    const uint32_t blk1 = SP ? nb : (nb - blk0 < kSegBlocks ? nb : blk0 + kSegBlocks);
+    const bool last_seg = seg + 1 == nseg;
+    uint32_t carry[4] = {ubase[0], ubase[1], ubase[2], ubase[3]};
+    if constexpr (!SP && S > 0) {
+        if (seg > 0) {
+            // segment bases follow the counts; inside the validated header
+            const uint32_t *const sb = page + 4 + nset + S * (seg - 1);
+#pragma unroll
+            for (uint32_t t = 0; t < S; ++t)
+                carry[t] = uniform(sb[t]);
+        }
+    }
     uint32_t kcnt = 0;
     if constexpr (SP) {
         // the Simple-8b words run to the page end (zero-padded to 4 words)
@@ -509,15 +567,43 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
 
     bool bad = false;  // per lane, reduced at the end
     uint32_t pk_run = 0, pos_run = 0;
+    if constexpr (!SP) {
+        // the earlier segments' blocks (all full rounds of 64): packed words,
+        // positions and, per array k, exceptions before this segment
+        if (seg > 0) {
+            uint32_t eb[kPageSegs - 1], em[kPageSegs - 1], ec[kPageSegs - 1];
+#pragma unroll
+            for (uint32_t r = 0; r + 1 < kPageSegs; ++r) {
+                const uint32_t jj = 64u * r + lane;
+                const bool own = r < seg;
+                eb[r] = buf_load_u8(rpg, own ? meta_at + jj : kOutOfRange);
+                em[r] = buf_load_u8(rpg, own ? meta_at + nb + jj : kOutOfRange);
+                ec[r] = buf_load_u8(rpg, own ? meta_at + 2u * nb + jj : kOutOfRange);
+            }
+            uint32_t pk_l = 0, pos_l = 0;
+#pragma unroll
+            for (uint32_t r = 0; r + 1 < kPageSegs; ++r) {
+                const uint32_t k = (em[r] >= eb[r] && em[r] <= 32u) ? em[r] - eb[r] : 0u;
+                pk_l += 4u * (eb[r] < 32u ? eb[r] : 32u);
+                pos_l += ec[r];
+                if (ec[r] != 0u && k != 0u)
+                    atomicAdd(&L.kcar[k], ec[r]);
+            }
+            pk_run = wave_read(wave_scan_incl(pk_l), 63);
+            pos_run = wave_read(wave_scan_incl(pos_l), 63);
+            wave_lds_order();
+        }
+    }
+    // relative round r of the segment: blocks blk0 + 64 r + lane
     auto load_meta = [&](uint32_t r, uint32_t &mb_, uint32_t &mm_, uint32_t &mc_) __attribute__((always_inline)) {
-        const uint32_t jj = 64u * r + lane;
-        const bool own = jj < nb;
+        const uint32_t jj = blk0 + 64u * r + lane;
+        const bool own = jj < blk1;
         mb_ = buf_load_u8(rpg, own ? meta_at + jj : kOutOfRange);
         mm_ = buf_load_u8(rpg, own ? meta_at + nb + jj : kOutOfRange);
         mc_ = buf_load_u8(rpg, own ? meta_at + 2u * nb + jj : kOutOfRange);
     };
     auto build_round = [&](uint32_t r, uint32_t bv, uint32_t mv, uint32_t cv) __attribute__((always_inline)) {
-        // blocks past the page read 0 for b, maxb and c
+        // blocks past the segment read 0 for b, maxb and c
         bad = bad || bv > 32u || mv > 32u || mv < bv || cv >= kBlock || ((cv == 0u) != (mv == bv));
         const uint32_t k = (mv >= bv && mv <= 32u) ? mv - bv : 0u;
         const uint32_t bc = bv < 32u ? bv : 32u;  // a corrupt width stays within the pass's words
@@ -546,16 +632,66 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
             }
             z = L.excb[k] * 32u + (kc + rk) * k;
         }
-        L.rec[r & 1u][lane] = make_uint4(bc | (k << 8) | (cv << 16), y, z, w);
+        L.rec[r % NR][lane] = make_uint4(bc | (k << 8) | (cv << 16), y, z, w);
         wave_lds_order();
     };
-    const uint32_t npass = (nb + 3) / 4;
+    const uint32_t npass = (blk1 - blk0 + 3) / 4;
     uint32_t m0, m1, m2;
+    const uint32_t yS = pk_run, wS = pos_run;  // the segment's first packed word and exception
     load_meta(0, m0, m1, m2);
     build_round(0, m0, m1, m2);
-    load_meta(1, m0, m1, m2);
-    build_round(1, m0, m1, m2);
-    load_meta(2, m0, m1, m2);
+    // a segment of a FastPFOR page is one round: its packed words end here
+    const uint32_t yX = SP ? packed_words : pk_run;
+    if constexpr (SP) {
+        load_meta(1, m0, m1, m2);
+        build_round(1, m0, m1, m2);
+        load_meta(2, m0, m1, m2);
+    }
+    // the segment's packed words [yS, yX) of the packed region stream
+    // through the ring (a SimplePFOR page's, all of them); words a corrupt
+    // stream would place past the packed region are not read
+    const bool okx = yS <= yX && yX <= packed_words;
+    const BufRsrc rsp = make_rsrc(page + hdr_w + (okx ? yS : 0u), okx ? 4u * (yX - yS) : 0u);
+    uint4 c0 = buf_load_u4(rsp, lane * 16u);
+    __builtin_amdgcn_sched_barrier(0);
+    uint4 c1 = buf_load_u4(rsp, (kFpCW + lane * 4u) * 4u);
+    // The exceptions' high parts and positions are read a few bytes per
+    // pass from up to 32 arrays; fetched that way from HBM, between the
+    // other wavefronts' stores, each read would be a small scattered one.
+    // Instead each segment first reads its share of the page's exception
+    // arrays (an equal part for each of the page's segments, all of them
+    // decoded side by side) and its own positions with contiguous 16-byte
+    // loads, so that the passes find those lines in the L2 cache. The data
+    // is only folded into a register that an empty asm statement consumes.
+    uint4 pf[3];
+    if constexpr (!SP) {
+        const uint32_t ex_w = nwords - exc_at, share = (ex_w + nseg - 1) / nseg;
+        const uint32_t pf_at = (exc_at + seg * share) * 4u;
+        pf[0] = buf_load_u4(rpg, pf_at + lane * 16u);
+        pf[1] = buf_load_u4(rpg, pf_at + 1024u + lane * 16u);
+        pf[2] = buf_load_u4(rpg, ((pos_at + wS) & ~15u) + lane * 16u);
+    }
+    uint32_t written = 0;  // words of the segment already in the ring
+    // chunk c goes to the ring (and its mirror), the slot reloads chunk c + 2;
+    // slots are written and reloaded in a fixed order, so the wait for a
+    // slot covers only older loads
+    auto put = [&](uint4 &slot, uint32_t c) __attribute__((always_inline)) {
+        const uint32_t pos = (c * kFpCW + lane * 4u) & (kFpRing - 1u);
+        *reinterpret_cast<uint4 *>(&L.ring[pos]) = slot;
+        if (pos < kFpMir)
+            *reinterpret_cast<uint4 *>(&L.ring[kFpRing + pos]) = slot;
+        slot = buf_load_u4(rsp, ((c + kFpDepth) * kFpCW + lane * 4u) * 4u);
+    };
+    // a pass reads at most 512 words from at or before `written`, so one
+    // group of two chunks always brings the ring up to its end
+    auto fill_to = [&](uint32_t need) __attribute__((always_inline)) {
+        if (written < need) {
+            const uint32_t c = written / kFpCW;
+            put(c0, c);
+            put(c1, c + 1);
+            written += kFpDepth * kFpCW;
+        }
+    };
 
     // SimplePFOR: the ring holds the high parts [keep, dec) (indices in the
     // page); sw = next Simple-8b word, whose batch of 64 (lane i: word
@@ -605,19 +741,19 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
     // be read from the ring (SimplePFOR)
     auto fetch = [&](uint32_t q, uint32_t keep) __attribute__((always_inline)) {
         FpFetch f;
-        const uint4 *const R = &L.rec[(q >> 4) & 1u][(q & 15u) * 4u];
+        if (q >= npass) {  // past the segment: nothing to read
+            f.pe = 0, f.u0 = f.u1 = f.pos = f.lo = f.hi = f.em = f.km = 0, f.ce = f.e0 = 0;
+            return f;
+        }
+        const uint4 *const R = &L.rec[(q >> 4) % NR][(q & 15u) * 4u];
         const uint4 rA = R[jl], rC = R[2 + jl];
         const uint32_t yA = wave_read(rA.y, 0), wA = wave_read(rA.w, 0), wB = wave_read(rA.w, 32);
         const uint32_t wC = wave_read(rC.w, 0), xD = wave_read(rC.x, 32), yD = wave_read(rC.y, 32),
                        wD = wave_read(rC.w, 32);
-        const uint32_t yE = yD + 4u * (xD & 255u);
-        // words past the packed region (corrupt metadata) are not read
-        const bool okp = yE >= yA && yE <= packed_words;
-        const BufRsrc rs = make_rsrc(page + hdr_w + (okp ? yA : 0u), okp ? 4u * (yE - yA) : 0u);
-        f.pk0 = buf_load_u4(rs, lane * 16u);
-        f.pk1 = buf_load_u4(rs, 1024u + lane * 16u);
-        f.u0 = (rA.x & 255u) | ((rA.y - yA) << 8);
-        f.u1 = (rC.x & 255u) | ((rC.y - yA) << 8);
+        (void)yA;
+        f.pe = yD + 4u * (xD & 255u) - yS;
+        f.u0 = (rA.x & 255u) | ((rA.y - yS) << 8);
+        f.u1 = (rC.x & 255u) | ((rC.y - yS) << 8);
         f.e0 = wA;
         f.ce = wD + ((xD >> 16) & 255u) - wA;
         // exception `lane`: its block j of the pass, then its place in array k
@@ -643,24 +779,23 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
         return f;
     };
 
-    uint32_t carry[4] = {base[0], base[1], base[2], base[3]};
     const uint32_t qq = lane & 31u;
     uint32_t *const xw = &L.buf[jl * kBlock + qq];  // integer q of the lane's block of half 0
     auto run_pass = [&](uint32_t p, FpFetch &f) __attribute__((always_inline)) {
-        *reinterpret_cast<uint4 *>(&L.buf[4 * lane]) = f.pk0;
-        *reinterpret_cast<uint4 *>(&L.buf[256 + 4 * lane]) = f.pk1;
+        fill_to(f.pe);
         wave_lds_order();
         uint32_t v[2][4];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const uint32_t u = h ? f.u1 : f.u0;
             const uint32_t b = u & 255u, qb = qq * b;
-            const uint32_t w0 = (u >> 8) + (qb >> 5);
+            // the block's words lie in [w0, w0 + 4b + 1) of the ring and its mirror
+            const uint32_t w0 = ((u >> 8) + (qb >> 5)) & (kFpRing - 1u);
             const uint32_t mask = width_mask(b);
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 const uint32_t wi = w0 + m * b;
-                v[h][m] = __builtin_amdgcn_alignbit(L.buf[wi + 1], L.buf[wi], qb) & mask;
+                v[h][m] = __builtin_amdgcn_alignbit(L.ring[wi + 1], L.ring[wi], qb) & mask;
             }
         }
         wave_lds_order();
@@ -678,7 +813,7 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
             bad = bad || f.pos >= kBlock || (!((f.em >> 18) & 1u) && prev >= f.pos) || (SP && (hv & ~f.km) != 0u);
         }
         if (f.ce > 64u) {
-            const uint4 *const R = &L.rec[(p >> 4) & 1u][(p & 15u) * 4u];
+            const uint4 *const R = &L.rec[(p >> 4) % NR][(p & 15u) * 4u];
             const uint32_t wA = f.e0, wB = wave_read(R[1].w, 0), wC = wave_read(R[2].w, 0),
                            wD = wave_read(R[3].w, 0);
             for (uint32_t e = 64u + lane; e - lane < f.ce; e += 64u) {
@@ -736,8 +871,8 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
                 carry[c] += tx + wave_read(iy, 63);
             }
         }
-        // the pass's output; blocks past the page fall outside the resource
-        const BufRsrc rout = make_rsrc(out + p * (4u * kBlock), (nb - 4u * p) * (kBlock * 4u));
+        // the pass's output; blocks past the segment fall outside the resource
+        const BufRsrc rout = make_rsrc(out + (blk0 + 4u * p) * kBlock, (blk1 - blk0 - 4u * p) * (kBlock * 4u));
         buf_store_u4(rout, lane * 16u, 0u, make_uint4(x[0], x[1], x[2], x[3]));
         buf_store_u4(rout, 1024u + lane * 16u, 0u, make_uint4(y[0], y[1], y[2], y[3]));
     };
@@ -752,26 +887,51 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
         run_pass(p, f0);
         if (p + 1 < npass)
             run_pass(p + 1, f1);
+        if constexpr (!SP) {
+            if (p == 2) {
+                uint32_t t = 0;
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    t ^= pf[i].x ^ pf[i].y ^ pf[i].z ^ pf[i].w;
+                asm volatile("" ::"v"(t));
+            }
+        }
     }
-    // totals: packed words, positions, and each array's count (SimplePFOR:
-    // the Simple-8b words hold exactly the page's exceptions)
-    bad = bad || pk_run != packed_words || 3u * nb + pos_run != meta_bytes;
-    if constexpr (SP) {
-        s8_fill(0xffffffffu, 0u, true);
-        bad = bad || dec != pos_run;
-    } else {
-        bad = bad || (kl && L.kcar[lane + 1] != kcnt);
+    // the page's last segment checks the totals: packed words, positions,
+    // and each array's count (SimplePFOR: the Simple-8b words hold exactly
+    // the page's exceptions); any other checks that its sums end on the
+    // next segment's stored base
+    if (last_seg) {
+        bad = bad || pk_run != packed_words || 3u * nb + pos_run != meta_bytes;
+        if constexpr (SP) {
+            s8_fill(0xffffffffu, 0u, true);
+            bad = bad || dec != pos_run;
+        } else {
+            bad = bad || (kl && L.kcar[lane + 1] != kcnt);
+        }
+    } else if constexpr (!SP && S > 0) {
+        const uint32_t *const nsb = page + 4 + nset + S * seg;
+#pragma unroll
+        for (uint32_t t = 0; t < S; ++t)
+            bad = bad || carry[t] != uniform(nsb[t]);
     }
     wave_lds_order();
     return ballot(bad) == 0;
 }
 
-// Directory entry u (< H.units) of a patched-page stream decoded by one
-// wavefront into out (the whole list's output): the entry's offset, length
-// and bases, then fp_wave_page. Uniform result.
+// Full blocks of patched page u (512 except possibly the last).
+__device__ __forceinline__ uint32_t page_blocks(const ListHdr &H, uint64_t u)
+{
+    const uint64_t left = H.nfull - u * kFpBlocks;
+    return (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
+}
+
+// Segment `seg` of directory entry u (< H.units) of a patched-page stream
+// decoded by one wavefront into out (the whole list's output): the entry's
+// offset, length and bases, then fp_wave_page. Uniform result.
 template <int KIND = kPageFp>
-__device__ __forceinline__ bool fp_unit(const uint32_t *__restrict__ in, const ListHdr &H, uint64_t u,
-                                        uint32_t *__restrict__ out, FpWaveLds &L, uint32_t *ring = nullptr)
+__device__ __forceinline__ bool fp_unit(const uint32_t *__restrict__ in, const ListHdr &H, uint64_t u, uint32_t seg,
+                                        uint32_t *__restrict__ out, FpLdsOf<KIND> &L, uint32_t *ring = nullptr)
 {
     const uint32_t off = uniform(in[kHdrWords + u]);
     const uint32_t end = (u + 1 < H.units) ? uniform(in[kHdrWords + u + 1]) : H.tail_off;
@@ -784,9 +944,9 @@ __device__ __forceinline__ bool fp_unit(const uint32_t *__restrict__ in, const L
         return false;
     const uint32_t *pg = in + off;
     uint32_t *po = out + u * kFpUnitInts;
-    return H.S == 1   ? fp_wave_page<1, KIND>(pg, end - off, nb, base, po, L, ring)
-           : H.S == 4 ? fp_wave_page<4, KIND>(pg, end - off, nb, base, po, L, ring)
-                      : fp_wave_page<0, KIND>(pg, end - off, nb, base, po, L, ring);
+    return H.S == 1   ? fp_wave_page<1, KIND>(pg, end - off, nb, seg, base, po, L, ring)
+           : H.S == 4 ? fp_wave_page<4, KIND>(pg, end - off, nb, seg, base, po, L, ring)
+                      : fp_wave_page<0, KIND>(pg, end - off, nb, seg, base, po, L, ring);
 }
 
 // ------------------------------------------------------------------------

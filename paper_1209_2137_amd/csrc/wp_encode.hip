@@ -613,7 +613,8 @@ __global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__
                 exc_w += exc_array_words<P32>(s_cnt[k], k);
             }
         const uint32_t meta_bytes = 3 * nb + s_pc;
-        sizes[p] = pad4(pad4(4 + nset) + s_pw + ((meta_bytes + 15) / 16) * 4 + exc_w);
+        const uint32_t nsb = S * (page_items<kPageFp>(nb) - 1);  // segment bases
+        sizes[p] = pad4(pad4(4 + nset + nsb) + s_pw + ((meta_bytes + 15) / 16) * 4 + exc_w);
     }
 }
 
@@ -667,7 +668,8 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
     for (uint32_t k = 1; k <= 32; ++k)
         bitset |= L.kcar[k] ? (1u << (k - 1)) : 0u;
     const uint32_t nset = __builtin_popcount(bitset);
-    const uint32_t hdr_w = pad4(4 + nset);
+    const uint32_t nsb = S * (page_items<kPageFp>(nb) - 1);  // segment bases after the counts
+    const uint32_t hdr_w = pad4(4 + nset + nsb);
     const uint32_t meta_bytes = 3 * nb + npos;
     const uint32_t meta_w = ((meta_bytes + 15) / 16) * 4;
     const uint32_t exc_at = hdr_w + packed_words + meta_w;
@@ -706,7 +708,14 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
         if ((bitset >> (k - 1)) & 1u)
             page[4 + __builtin_popcount(bitset & ((1u << (k - 1)) - 1u))] = L.kcar[k];
     }
-    if (tid >= 64 && tid - 64 >= 4 + nset && tid - 64 < hdr_w)
+    if constexpr (S > 0) {
+        // segment g >= 1: the S input values just before its first integer
+        if (tid >= 128 && tid - 128 < nsb) {
+            const uint32_t i = tid - 128, g = 1 + i / S, t = i % S;
+            page[4 + nset + i] = x[p * kFpUnitInts + g * kSegInts - S + t];
+        }
+    }
+    if (tid >= 64 && tid - 64 >= 4 + nset + nsb && tid - 64 < hdr_w)
         page[tid - 64] = 0;
     // The metadata bytes and exception arrays (words tail0 .. size of the
     // page) are assembled with byte stores and ORs: in LDS when they fit,

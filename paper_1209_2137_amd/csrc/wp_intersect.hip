@@ -262,7 +262,8 @@ union IsectPageLds {
 };
 
 // Decodes the wanted entries of a patched-page stream (one wavefront per
-// page, four per workgroup; P32: exception arrays padded to 32 values).
+// 64-block segment of a page (SimplePFOR: per page), four per workgroup;
+// P32: exception arrays padded to 32 values).
 template <int KIND>
 __global__ __launch_bounds__(256) void k_isect_decode_fp(const uint32_t *__restrict__ in, uint64_t in_words,
                                                          uint64_t n, const uint32_t *__restrict__ a, uint64_t na,
@@ -275,16 +276,20 @@ __global__ __launch_bounds__(256) void k_isect_decode_fp(const uint32_t *__restr
     if (!check_header(in, in_words, n, magic, kFpBlocks, H))
         return;  // reported by k_isect_flag_dir or k_range_bounds
     const uint32_t wave = uniform(threadIdx.x >> 6);
-    const uint64_t u = (uint64_t)blockIdx.x * 4 + wave;
-    if (u >= H.ndir || !entry_wanted(in, H, u, a, na, klo, khi))
+    constexpr uint32_t per = KIND == kPageSp ? 1u : kPageSegs;
+    const uint64_t item = (uint64_t)blockIdx.x * 4 + wave;
+    const uint64_t u = item / per;
+    const uint32_t seg = (uint32_t)(item % per);
+    if (u >= H.ndir || seg >= (u == H.units ? 1u : page_items<KIND>(page_blocks(H, u))) ||
+        !entry_wanted(in, H, u, a, na, klo, khi))
         return;
     bool ok;
     if (u == H.units)
         ok = decode_tail_entry<1, false>(in, H, out, L[wave].tail);
     else if constexpr (KIND == kPageSp)
-        ok = fp_unit<KIND>(in, H, u, out, L[wave].sp.fp, L[wave].sp.ring);
+        ok = fp_unit<KIND>(in, H, u, seg, out, L[wave].sp.fp, L[wave].sp.ring);
     else
-        ok = fp_unit<KIND>(in, H, u, out, L[wave].page);
+        ok = fp_unit<KIND>(in, H, u, seg, out, L[wave].page);
     if (!ok && lane_id() == 0)
         *err = kErrCorrupt;
 }
@@ -468,7 +473,7 @@ extern "C" int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const
     const uint64_t nent = (nfull + per - 1) / per + ((nb % kBlock) ? 1 : 0);
     const uint64_t tiles = (na + kIsTile - 1) / kIsTile;
     IsectScratch S;
-    if (nent > 0x7FFFFFFFull || !isect_scratch(st, tiles, na, S))
+    if (nent > 0x0FFFFFFFull || !isect_scratch(st, tiles, na, S))
         return WP_ERR_HIP;
     if (codec == WP_CODEC_BP)
         hipLaunchKernelGGL((k_isect_decode_bp<false, false>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
@@ -483,10 +488,10 @@ extern "C" int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const
         hipLaunchKernelGGL(k_isect_decode_fp<kPageSp>, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, b_comp,
                            b_words, nb, a, na, 0u, 0u, b_work, ds->err);
     else if (codec == WP_CODEC_FP32)
-        hipLaunchKernelGGL(k_isect_decode_fp<kPageFp32>, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, b_comp, b_words, nb,
+        hipLaunchKernelGGL(k_isect_decode_fp<kPageFp32>, dim3((uint32_t)((nent * kPageSegs + 3) / 4)), dim3(256), 0, st, b_comp, b_words, nb,
                            a, na, 0u, 0u, b_work, ds->err);
     else
-        hipLaunchKernelGGL(k_isect_decode_fp<kPageFp>, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, b_comp, b_words, nb,
+        hipLaunchKernelGGL(k_isect_decode_fp<kPageFp>, dim3((uint32_t)((nent * kPageSegs + 3) / 4)), dim3(256), 0, st, b_comp, b_words, nb,
                            a, na, 0u, 0u, b_work, ds->err);
     hipLaunchKernelGGL(k_isect_flag_dir, dim3((uint32_t)tiles), dim3(kIsThreads), 0, st, a, na, b_comp, b_words, nb,
                        codec, b_work, S.flags, S.counts, ds->err);
@@ -516,7 +521,7 @@ extern "C" int32_t wp_decode_range(const uint32_t *in, uint64_t in_words, uint64
         (codec == WP_CODEC_FP || codec == WP_CODEC_FP32 || codec == WP_CODEC_SP) ? kFpBlocks : kBpBlocks;
     const uint64_t nfull = n / kBlock;
     const uint64_t nent = (nfull + per - 1) / per + ((n % kBlock) ? 1 : 0);
-    if (nent > 0x7FFFFFFFull)
+    if (nent > 0x0FFFFFFFull)
         return WP_ERR_INVALID_ARG;
     if (nent > 0) {
         // no short list: each entry's own bases against the key range decide (entry_wanted)
@@ -534,10 +539,10 @@ extern "C" int32_t wp_decode_range(const uint32_t *in, uint64_t in_words, uint64
             hipLaunchKernelGGL(k_isect_decode_fp<kPageSp>, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, in,
                                in_words, n, nf, 0, key_lo, key_hi, out, ds->err);
         else if (codec == WP_CODEC_FP32)
-            hipLaunchKernelGGL(k_isect_decode_fp<kPageFp32>, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, in, in_words, n, nf,
+            hipLaunchKernelGGL(k_isect_decode_fp<kPageFp32>, dim3((uint32_t)((nent * kPageSegs + 3) / 4)), dim3(256), 0, st, in, in_words, n, nf,
                                0, key_lo, key_hi, out, ds->err);
         else
-            hipLaunchKernelGGL(k_isect_decode_fp<kPageFp>, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, in, in_words, n, nf,
+            hipLaunchKernelGGL(k_isect_decode_fp<kPageFp>, dim3((uint32_t)((nent * kPageSegs + 3) / 4)), dim3(256), 0, st, in, in_words, n, nf,
                                0, key_lo, key_hi, out, ds->err);
     }
     hipLaunchKernelGGL(k_range_bounds, dim3(1), dim3(128), 0, st, in, in_words, n, codec, key_lo, key_hi, out,

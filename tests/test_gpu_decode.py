@@ -306,8 +306,10 @@ def _page_meta(s, n):
     """Word offset of the first page, its block count and the byte offset
     (from the stream start) of its metadata."""
     unit = int(s[8])
+    stride = int(s[3])
     nb, packed, bitset = int(s[unit]), int(s[unit + 1]), int(s[unit + 3])
-    hdr = (4 + bin(bitset).count("1") + 3) & ~3
+    # 4 words, a count per non-empty array, the segment bases, padded to 4
+    hdr = (4 + bin(bitset).count("1") + stride * (-(-nb // 64) - 1) + 3) & ~3
     return unit, nb, 4 * (unit + hdr + packed)
 
 

@@ -138,7 +138,15 @@ def test_full_size_patched_list():
     d[0] = (seg[0] - np.uint64(x[lo - 1])) % (1 << 32)
     d[1:] = (seg[1:] - seg[:-1]) % (1 << 32)
     ref = oracle.fp32_encode(d.astype(np.uint32), 0)
-    assert np.array_equal(page, ref[int(ref[8]):int(ref[6])])
+    ref = ref[int(ref[8]):int(ref[6])]
+    # the stride-1 page holds, after the counts, the value before each of
+    # its 64-block segments but the first (the stride-0 page holds none)
+    nset = bin(int(page[3])).count("1")
+    sb = [int(v) for v in page[4 + nset:4 + nset + 7]]
+    assert sb == [int(x[lo + g * 8192 - 1]) for g in range(1, 8)]
+    h_ref, h_got = (4 + nset + 3) // 4 * 4, (4 + nset + 7 + 3) // 4 * 4
+    assert np.array_equal(page[:4 + nset], ref[:4 + nset])
+    assert np.array_equal(page[h_got:], ref[h_ref:])
 
 
 def test_corrupt_streams_flagged_without_stray_writes():
