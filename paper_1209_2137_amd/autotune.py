@@ -1,7 +1,7 @@
 """Autotuner for the decoders' workgroup shapes.
 
 Knobs:
-  waves      wavefronts per workgroup (binary packing 1, 2, 4, 8; patched 2, 4, 8)
+  waves      wavefronts per workgroup (1, 2, 4, 8; batched 2, 4, 8)
   vpl        integers per lane and pass (4)
   depth      binary packing: 16-byte loads in flight per lane, which also
              sizes each wavefront's LDS ring (2 or 3: 4 KB, 4: 8 KB)
@@ -27,7 +27,7 @@ TUNING_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.j
 BP_SINGLE = [dict(waves=w, vpl=4, depth=d, wg_per_cu=c)
              for w in (1, 2, 4, 8) for d in (2, 3) for c in (28, 56, 128, 256)] + \
             [dict(waves=w, vpl=4, depth=4, wg_per_cu=c) for w in (1, 4) for c in (64, 128)]
-FP_SINGLE = [dict(waves=w, vpl=4) for w in (2, 4, 8)]
+FP_SINGLE = [dict(waves=w, vpl=4) for w in (1, 2, 4, 8)]
 BP32_SINGLE = [dict(waves=w, vpl=4, depth=d, wg_per_cu=c) for w in (2, 4, 8) for d in (2, 3) for c in (56, 128, 256)]
 BATCH = [dict(waves=w, vpl=4, depth=d, run_units=r, wg_per_cu=0, use_graph=1)
          for w in (2, 4, 8) for d in (2, 3) for r in (4, 8, 16)]
