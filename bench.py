@@ -122,7 +122,8 @@ def bench_single(wp, x_np, codec, stride, steps, warmup, name, comp=None, n=None
     comps = replicas(comp, comp.numel() * 4)
     outs = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(2)]
     dec = {wp.CODEC_BP: wp.bp_decode, wp.CODEC_FP: wp.fastpfor_decode, wp.CODEC_BP32: wp.bp32_decode,
-           wp.CODEC_FP32: wp.fastpfor32_decode, wp.CODEC_BPV: wp.bp_vertical_decode}[codec]
+           wp.CODEC_FP32: wp.fastpfor32_decode, wp.CODEC_BPV: wp.bp_vertical_decode,
+           wp.CODEC_SP: wp.simplepfor_decode}[codec]
     stream = torch.cuda.current_stream()
     dec(comps[0], n, outs[0])
     wp.check()
@@ -137,7 +138,7 @@ def bench_single(wp, x_np, codec, stride, steps, warmup, name, comp=None, n=None
     return {
         "name": name, "n": n,
         "codec": {wp.CODEC_BP: "bp", wp.CODEC_FP: "fp", wp.CODEC_BP32: "bp32", wp.CODEC_FP32: "fp32",
-                  wp.CODEC_BPV: "bpv"}[codec],
+                  wp.CODEC_BPV: "bpv", wp.CODEC_SP: "sp"}[codec],
         "stride": stride,
         "bits_per_int": comp_bytes * 8 / n, "ms_per_step": wall, "kernel_ms": ev,
         "gints_per_s": n / (wall * 1e-3) / 1e9, "kernel_gints_per_s": n / (ev * 1e-3) / 1e9,
@@ -154,7 +155,8 @@ def bench_encode(wp, x_np, codec, stride, steps, warmup, name):
     n = x_np.size
     xs = replicas(xd, n * 4)
     enc = {wp.CODEC_BP: wp.bp_encode, wp.CODEC_FP: wp.fastpfor_encode, wp.CODEC_BP32: wp.bp32_encode,
-           wp.CODEC_FP32: wp.fastpfor32_encode, wp.CODEC_BPV: wp.bp_vertical_encode}[codec]
+           wp.CODEC_FP32: wp.fastpfor32_encode, wp.CODEC_BPV: wp.bp_vertical_encode,
+           wp.CODEC_SP: wp.simplepfor_encode}[codec]
     buf, words = enc(xd, stride)
     wp.check()
     comp_words = int(words.item())
@@ -649,6 +651,8 @@ def main():
         extra["fp_patched_2e28"] = p
         extra["fp32_patched_2e28"] = bench_single(wp, datagen.patched_gaps(1 << 28, seed=4), wp.CODEC_FP32, 1,
                                                   args.steps, args.warmup, "fastpfor (arrays padded to 32) 2^28")
+        extra["sp_patched_2e28"] = bench_single(wp, datagen.patched_gaps(1 << 28, seed=4), wp.CODEC_SP, 1,
+                                                args.steps, args.warmup, "simplepfor (Simple-8b high parts) 2^28")
         print("# patched done", file=sys.stderr, flush=True)
         extra["delta_inplace_2e28"] = bench_delta(wp, 1 << 28, args.steps, args.warmup)
         print("# delta done", file=sys.stderr, flush=True)
@@ -664,6 +668,8 @@ def main():
                                                          "simd-bp128 four-lane layout, stride-4 deltas, cluster 2^26")
         extra["bp32_encode_cluster_2e26"] = bench_encode(wp, x, wp.CODEC_BP32, 1, args.steps, args.warmup,
                                                          "bp32_encode cluster 2^26")
+        extra["sp_encode_patched_2e28"] = bench_encode(wp, datagen.patched_gaps(1 << 28, seed=4), wp.CODEC_SP, 1,
+                                                       max(3, args.steps // 4), 1, "simplepfor_encode patched 2^28")
         print("# encoders done", file=sys.stderr, flush=True)
         extra["intersect_2e20_2e24"] = bench_intersect(wp, args.steps, args.warmup)
         print("# intersection done", file=sys.stderr, flush=True)

@@ -182,6 +182,13 @@ int32_t fastpfor32_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, 
  * word, low half first)], packed values, metadata, the Simple-8b words,
  * zero-padded to 4 words (magic 'WPS1'). */
 
+/* SimplePFOR encoder: the pages described above (widths, metadata and
+ * positions as fastpfor_encode; the high parts of each page's exceptions,
+ * in block order, coded greedily with Simple-8b). Arguments as bp_encode,
+ * with WP_CODEC_SP for the capacity; scratch as bp_encode. */
+int32_t simplepfor_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,
+                          uint64_t out_cap_words, uint64_t *out_words, void *stream);
+
 /* SimplePFOR decoder: as fastpfor_decode,
  * the high parts taken from the page's Simple-8b words (decoded by
  * wavefronts as the page's blocks need them). Allocates nothing. */

@@ -32,7 +32,7 @@ EXPORTS = (
     "wp_max_compressed_words", "wp_check", "wp_strerror", "wp_set_decode_tune", "wp_time_next_launch",
     "wp_batch_plan", "wp_batch_replan", "wp_batch_decode", "wp_batch_items", "wp_batch_free",
     "wp_intersect", "wp_intersect_compressed", "wp_decode_range",
-    "simplepfor_decode",
+    "simplepfor_decode", "simplepfor_encode", "delta_decode_inplace_noalloc",
 )
 
 _lib = None
@@ -75,7 +75,8 @@ def lib():
         pass
     L = ctypes.CDLL(LIB_PATH)
     vp, u64, i32, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint32
-    for name in ("bp_encode", "bp32_encode", "fastpfor_encode", "fastpfor32_encode", "bp_vertical_encode"):
+    for name in ("bp_encode", "bp32_encode", "fastpfor_encode", "fastpfor32_encode", "bp_vertical_encode",
+                 "simplepfor_encode"):
         f = getattr(L, name)
         f.argtypes = [vp, u64, i32, vp, u64, vp, vp]
         f.restype = i32
@@ -263,11 +264,16 @@ def bp_vertical_encode(x, stride: int = 1, out=None, out_words=None, stream=None
     return _encode(lib().bp_vertical_encode, CODEC_BPV, x, stride, out, out_words, stream, "bp_vertical_encode")
 
 
+def simplepfor_encode(x, stride: int = 1, out=None, out_words=None, stream=None):
+    """Encodes x (device uint32) as SimplePFOR pages (exception high parts in Simple-8b)."""
+    return _encode(lib().simplepfor_encode, CODEC_SP, x, stride, out, out_words, stream, "simplepfor_encode")
+
+
 def encode_trimmed(x, codec: int = CODEC_BP, stride: int = 1, stream=None):
     """Encodes and returns a tensor of exactly the stream's length
     (synchronises the stream to read the length)."""
     enc = {CODEC_BP: bp_encode, CODEC_FP: fastpfor_encode, CODEC_BP32: bp32_encode, CODEC_FP32: fastpfor32_encode,
-           CODEC_BPV: bp_vertical_encode}[codec]
+           CODEC_BPV: bp_vertical_encode, CODEC_SP: simplepfor_encode}[codec]
     buf, words = enc(x, stride, stream=stream)
     check(stream)
     return buf[: int(words.item())].clone()

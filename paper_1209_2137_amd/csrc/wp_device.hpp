@@ -202,6 +202,27 @@ __device__ __forceinline__ bool check_header(const uint32_t *__restrict__ in, ui
 }
 
 // ------------------------------------------------------------------------
+// Encoders: the directory entry of a unit (one workgroup per unit).
+
+// directory entry: offset at word 8 + entry, bases after all ndir offsets;
+// base_s = x[start - S + s], 0 before the array start
+__device__ __forceinline__ void write_dir_entry(uint32_t *out, uint64_t entry, uint64_t ndir, uint32_t S,
+                                                uint32_t off, const uint32_t *__restrict__ x, uint64_t start)
+{
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0)
+        out[kHdrWords + entry] = off;
+    else if (tid <= S)
+        out[kHdrWords + ndir + entry * S + (tid - 1)] = (start + (tid - 1) >= S) ? x[start + (tid - 1) - S] : 0u;
+}
+
+__host__ __device__ __forceinline__ uint64_t dir_entries(uint64_t n, uint64_t per)
+{
+    const uint64_t nfull = n / kBlock;
+    return (nfull + per - 1) / per + ((n % kBlock) ? 1 : 0);
+}
+
+// ------------------------------------------------------------------------
 // LDS arena shared by all roles (a workgroup plays one role at a time).
 
 template <int WAVES>

@@ -78,24 +78,6 @@ __device__ __forceinline__ void or_field_vertical(uint32_t *w, uint32_t i, uint3
         atomicOr(&w[4 * ((pos >> 5) + 1) + lane], v >> (32u - s));
 }
 
-// directory entry: offset at word 8 + entry, bases after all ndir offsets;
-// base_s = x[start - S + s], 0 before the array start
-__device__ __forceinline__ void write_dir_entry(uint32_t *out, uint64_t entry, uint64_t ndir, uint32_t S,
-                                                uint32_t off, const uint32_t *__restrict__ x, uint64_t start)
-{
-    const uint32_t tid = threadIdx.x;
-    if (tid == 0)
-        out[kHdrWords + entry] = off;
-    else if (tid <= S)
-        out[kHdrWords + ndir + entry * S + (tid - 1)] = (start + (tid - 1) >= S) ? x[start + (tid - 1) - S] : 0u;
-}
-
-__host__ __device__ __forceinline__ uint64_t dir_entries(uint64_t n, uint64_t per)
-{
-    const uint64_t nfull = n / kBlock;
-    return (nfull + per - 1) / per + ((n % kBlock) ? 1 : 0);
-}
-
 // ------------------------------------------------------------------------
 // Binary packing (Section 6.2): block width = bits of the OR of its deltas.
 //
@@ -859,6 +841,7 @@ __global__ __launch_bounds__(128) void k_finish(const uint32_t *__restrict__ x, 
                  : codec == WP_CODEC_BPV  ? kMagicBPV
                  : codec == WP_CODEC_BP32 ? kMagicBP32
                  : codec == WP_CODEC_FP32 ? kMagicFP32
+                 : codec == WP_CODEC_SP   ? kMagicSP
                                           : kMagicFP;
         out[1] = (uint32_t)n;
         out[2] = (uint32_t)(n >> 32);
@@ -897,7 +880,7 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
         return WP_ERR_INVALID_ARG;
     if (cap < need)
         return WP_ERR_CAPACITY;
-    const bool paged = codec == WP_CODEC_FP || codec == WP_CODEC_FP32;
+    const bool paged = codec == WP_CODEC_FP || codec == WP_CODEC_FP32 || codec == WP_CODEC_SP;
     const uint64_t per = paged ? kFpBlocks : kBpBlocks;
     const uint64_t nfull = n / kBlock;
     const uint64_t units = (nfull + per - 1) / per;
@@ -931,7 +914,13 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
             WP_FP_ENC(k_fp_analyze, true, (in, n, meta, nblk, sizes));
         else
             WP_FP_ENC(k_fp_analyze, false, (in, n, meta, nblk, sizes));
-        if (launch_inclusive_scan(sizes, units, status, st) != WP_OK)
+        if (codec == WP_CODEC_SP) {
+            // widths and counts as for patched pages; the page sizes depend
+            // on the Simple-8b coding
+            if (sp_encode_units(in, n, (uint32_t)stride, units, meta, nblk, sizes, status, dir_end, out, st) !=
+                WP_OK)
+                return WP_ERR_HIP;
+        } else if (launch_inclusive_scan(sizes, units, status, st) != WP_OK)
             return WP_ERR_HIP;
         if (codec == WP_CODEC_BP)
             hipLaunchKernelGGL(k_bp_pack<false>, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride,
@@ -944,7 +933,7 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
                                sizes, dir_end, out);
         else if (codec == WP_CODEC_FP32)
             WP_FP_ENC(k_fp_pack, true, (in, n, meta, nblk, sizes, dir_end, out));
-        else
+        else if (codec == WP_CODEC_FP)
             WP_FP_ENC(k_fp_pack, false, (in, n, meta, nblk, sizes, dir_end, out));
     }
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(128), 0, st, in, n, (uint32_t)stride, (uint32_t)codec, sizes, units,
@@ -984,4 +973,10 @@ extern "C" int32_t fastpfor_encode(const uint32_t *in, uint64_t n, int32_t delta
                                    uint64_t out_cap_words, uint64_t *out_words, void *stream)
 {
     return encode_common(WP_CODEC_FP, in, n, delta_stride, out, out_cap_words, out_words, stream);
+}
+
+extern "C" int32_t simplepfor_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,
+                                     uint64_t out_cap_words, uint64_t *out_words, void *stream)
+{
+    return encode_common(WP_CODEC_SP, in, n, delta_stride, out, out_cap_words, out_words, stream);
 }

@@ -49,6 +49,14 @@ int32_t launch_inclusive_scan(uint32_t *data, uint64_t n, uint64_t *status, hipS
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// The SimplePFOR pages of an encode call (after the patched analysis has
+// written every block's width, maximum width and exception count to
+// `meta`): page sizes into `sizes`, their chained scan (`status` as for
+// launch_inclusive_scan), then the pages themselves.
+int32_t sp_encode_units(const uint32_t *in, uint64_t n, uint32_t stride, uint64_t units, const uint8_t *meta,
+                        uint64_t nblk, uint32_t *sizes, uint64_t *status, uint32_t dir_end, uint32_t *out,
+                        hipStream_t st);
+
 // Events the calling thread's next decoder launch records when its main
 // kernel starts and ends (set by wp_time_next_launch); taking them clears
 // them.

@@ -1,0 +1,201 @@
+"""GPU parity for SimplePFOR pages (Section 5, SimplePFOR: the patched
+pages' widths, packed values and metadata, with each page's exception high
+parts coded once with Simple-8b, Section 2): the HIP decoder against the
+generators' arrays and the oracle's streams, the HIP encoder against the
+oracle's encoder word for word (its greedy Simple-8b coding included).
+Exact comparisons (integer work); outputs sit between canary fences to
+catch writes outside [out, out + n)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1209_2137_amd as wp
+from paper_1209_2137_amd import autotune
+from paper_1209_2137_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+CANARY = 0x5A5A5A5A
+PAD = 64
+WAVES = (8, 4, 2, 1)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "the GPU tests need a GPU"
+    wp.lib()
+    yield
+    autotune.apply()
+
+
+def to_dev(a):
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    if a.size == 0:
+        return torch.zeros(4, dtype=torch.int32, device="cuda")[:0]
+    return torch.from_numpy(a.view(np.int32)).to("cuda")
+
+
+def to_host(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def gpu_decode(stream_np, n):
+    comp = to_dev(stream_np)
+    buf = torch.full((n + 2 * PAD,), CANARY, dtype=torch.int32, device="cuda")
+    out = buf[PAD:PAD + n]
+    wp.simplepfor_decode(comp, n, out)
+    rc = wp.check_code()
+    h = to_host(buf)
+    assert (h[:PAD] == CANARY).all() and (h[PAD + n:] == CANARY).all(), "write outside [out, out + n)"
+    return rc, h[PAD:PAD + n]
+
+
+def assert_same(got, want, what=""):
+    if not np.array_equal(got, want):
+        bad = np.nonzero(got != want)[0]
+        raise AssertionError(f"{what}: {bad.size} mismatches, first at {bad[0]}: "
+                             f"got {got[bad[0]]} want {want[bad[0]]}")
+
+
+LENGTHS = [0, 1, 5, 127, 128, 129, 1000, 2049, 8192 + 3, 65535, 65536, 65537, 2 * 65536 + 3 * 128 + 77]
+
+
+def _case(rng, n):
+    kind = n % 3
+    if kind == 0:
+        return rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)
+    if kind == 1:
+        return datagen.single_geometric(n, mean=float(rng.integers(2, 5000)), seed=n)
+    return datagen.patched_gaps(n, seed=n) if n else np.zeros(0, np.uint32)
+
+
+@pytest.mark.parametrize("stride", [0, 1, 4])
+def test_decode_lengths_strides_shapes(stride):
+    rng = np.random.default_rng(6200 + stride)
+    cases = [(n, x, oracle.sp_encode(x, stride)) for n, x in ((n, _case(rng, n)) for n in LENGTHS)]
+    for waves in WAVES:
+        wp.set_decode_tune(wp.CODEC_SP, waves, 4)
+        for n, x, s in cases:
+            print(f"sp stride={stride} waves={waves} n={n}", flush=True)
+            rc, got = gpu_decode(s, n)
+            assert rc == wp.OK
+            assert_same(got, x, f"n={n} waves={waves}")
+
+
+@pytest.mark.parametrize("stride", [0, 1, 4])
+def test_encode_small_lengths_match_oracle(stride):
+    rng = np.random.default_rng(6300 + stride)
+    for n in LENGTHS:
+        x = _case(rng, n)
+        print(f"sp encode stride={stride} n={n}", flush=True)
+        got = to_host(wp.encode_trimmed(to_dev(x), wp.CODEC_SP, stride))
+        want = oracle.sp_encode(x, stride)
+        assert got.size == want.size, f"n={n}: {got.size} words, oracle {want.size}"
+        assert_same(got, want, f"n={n}")
+
+
+def _selectors(stream):
+    """Selectors of every Simple-8b word of a SimplePFOR stream's pages."""
+    s = np.asarray(stream, dtype=np.uint32)
+    units, tail_off = int(s[4]), int(s[6])
+    offs = [int(v) for v in s[8:8 + units]] + [tail_off]
+    sels = set()
+    for u in range(units):
+        at = offs[u]
+        nb, packed, meta_bytes, s8w = (int(v) for v in s[at:at + 4])
+        s8_at = at + 4 + packed + (meta_bytes + 15) // 16 * 4
+        sels |= {int(v) >> 28 for v in s[s8_at + 1:s8_at + s8w:2]}
+    return sels
+
+
+# width of every high part -> the selector whose slots have exactly that width
+WIDTH_SELECTOR = {1: 2, 2: 3, 3: 4, 4: 5, 5: 6, 6: 7, 7: 8, 8: 9, 10: 10, 12: 11, 15: 12, 20: 13, 30: 14, 32: 15}
+
+
+@pytest.mark.parametrize("w", sorted(WIDTH_SELECTOR))
+def test_encode_every_simple8b_mode(w):
+    # values of at most two bits with 8 % exceptions whose high parts are
+    # exactly w bits wide (32-bit exceptions over zeros for w = 32): the
+    # greedy coding takes the selector of w-bit slots, 2 (sixty 1-bit
+    # slots) through 15 (one 60-bit slot)
+    rng = np.random.default_rng(w)
+    n = 2 * 65536 + 128 * 9 + 40
+    b0 = 2 if w <= 30 else 0
+    base = rng.integers(0, 1 << b0, size=n, dtype=np.uint64)
+    hi = (np.uint64(1) << np.uint64(w - 1)) | rng.integers(0, 1 << (w - 1), size=n, dtype=np.uint64)
+    exc = rng.random(n) < 0.08
+    x = np.where(exc, (hi << np.uint64(b0)) | base, base).astype(np.uint32)  # stride 0: the deltas themselves
+    print(f"sp encode, high parts of {w} bits", flush=True)
+    want = oracle.sp_encode(x, 0)
+    used = _selectors(want)
+    print(f"selectors used: {sorted(used)}", flush=True)
+    assert WIDTH_SELECTOR[w] in used and 0 not in used and 1 not in used
+    got = to_host(wp.encode_trimmed(to_dev(x), wp.CODEC_SP, 0))
+    assert got.size == want.size
+    assert_same(got, want, f"w={w}")
+    rc, back = gpu_decode(got, n)
+    assert rc == wp.OK
+    assert_same(back, x)
+
+
+def test_full_size_patched_list():
+    # the 2^28 patched workload as SimplePFOR: GPU encode, GPU decode, exact
+    # round trip; a sampled page of the GPU stream equals the oracle's page
+    x = datagen.patched_gaps()
+    xd = to_dev(x)
+    comp = wp.encode_trimmed(xd, wp.CODEC_SP, 1)
+    out = torch.empty(xd.numel(), dtype=torch.int32, device="cuda")
+    autotune.apply()
+    wp.simplepfor_decode(comp, xd.numel(), out)
+    assert wp.check_code() == wp.OK
+    assert torch.equal(out, xd)
+    s = to_host(comp[:8 + 4096 * 2 + 8])
+    off, end = int(s[8 + 1000]), int(s[8 + 1001])
+    page = to_host(comp[off:end])
+    lo = 1000 * 65536
+    seg = x[lo:lo + 65536].astype(np.uint64)
+    d = np.empty(65536, np.uint64)
+    d[0] = (seg[0] - np.uint64(x[lo - 1])) % (1 << 32)
+    d[1:] = (seg[1:] - seg[:-1]) % (1 << 32)
+    ref = oracle.sp_encode(d.astype(np.uint32), 0)
+    assert np.array_equal(page, ref[int(ref[8]):int(ref[6])])
+
+
+def test_corrupt_streams_flagged_without_stray_writes():
+    n = 2 * 65536 + 300
+    x = datagen.patched_gaps(n, seed=81)
+    s = oracle.sp_encode(x, 1)
+    rc, got = gpu_decode(s, n)
+    assert rc == wp.OK and np.array_equal(got, x)
+    unit = int(s[8])
+    mutations = {
+        "magic": (0, int(s[0]) ^ 1),
+        "units": (4, int(s[4]) + 1),
+        "total": (7, int(s[7]) + 100),
+        "unit_offset": (8, 0xFFFFFF),
+        "nblocks": (unit, 7),
+        "packed_words": (unit + 1, int(s[unit + 1]) + 4),
+        "meta_bytes": (unit + 2, int(s[unit + 2]) + 1),
+        "s8_words": (unit + 3, int(s[unit + 3]) + 2),
+    }
+    for what, (at, val) in mutations.items():
+        bad = s.copy()
+        bad[at] = val & 0xFFFFFFFF
+        print("sp corruption", what, flush=True)
+        rc, _ = gpu_decode(bad, n)
+        assert rc == wp.ERR_CORRUPT, what
+        assert oracle.sp_decode_rc(bad, n) == oracle.ERR_CORRUPT, what
+    # a Simple-8b word whose selector claims more high parts than remain
+    nb, packed, meta_bytes, s8w = (int(v) for v in s[unit:unit + 4])
+    s8_at = unit + 4 + packed + (meta_bytes + 15) // 16 * 4
+    bad = s.copy()
+    bad[s8_at + s8w - 1] = (int(bad[s8_at + s8w - 1]) & 0x0FFFFFFF) | (2 << 28)  # last word: sixty 1-bit parts
+    rc, _ = gpu_decode(bad, n)
+    assert rc == wp.ERR_CORRUPT
+    assert oracle.sp_decode_rc(bad, n) == oracle.ERR_CORRUPT
+    # a SIMD-FastPFOR stream is not a SimplePFOR stream
+    rc, _ = gpu_decode(oracle.fp_encode(x, 1), n)
+    assert rc == wp.ERR_CORRUPT
+    rc, got = gpu_decode(s, n)
+    assert rc == wp.OK and np.array_equal(got, x)
