@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 OK, ERR_ARG, ERR_CAP, ERR_CORRUPT = 0, -1, -2, -3
-CODEC_BP, CODEC_FP, CODEC_BP32, CODEC_FP32, CODEC_BPV, CODEC_SP = 0, 1, 2, 3, 4, 5
+CODEC_BP, CODEC_FP, CODEC_BP32, CODEC_FP32, CODEC_BPV, CODEC_SP, CODEC_FPI = 0, 1, 2, 3, 4, 5, 6
 
 
 def build() -> str:
@@ -62,11 +62,11 @@ def _load():
     lib.oracle_max_words.argtypes = [ctypes.c_int, u64]
     lib.oracle_max_words.restype = u64
     for f in (lib.oracle_bp_encode, lib.oracle_fp_encode, lib.oracle_bp32_encode, lib.oracle_fp32_encode,
-              lib.oracle_bpv_encode, lib.oracle_sp_encode):
+              lib.oracle_bpv_encode, lib.oracle_sp_encode, lib.oracle_fpi_encode):
         f.argtypes = [u32p, u64, ctypes.c_int, u32p, u64]
         f.restype = ctypes.c_int64
     for f in (lib.oracle_bp_decode, lib.oracle_fp_decode, lib.oracle_bp32_decode, lib.oracle_fp32_decode,
-              lib.oracle_bpv_decode, lib.oracle_sp_decode):
+              lib.oracle_bpv_decode, lib.oracle_sp_decode, lib.oracle_fpi_decode):
         f.argtypes = [u32p, u64, u32p, u64]
         f.restype = ctypes.c_int
     u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -291,6 +291,23 @@ def sp_decode(stream, n: int) -> np.ndarray:
 
 def sp_decode_rc(stream, n: int) -> int:
     return _decode(_load().oracle_sp_decode, stream, n)[0]
+
+
+def fpi_encode(x, stride: int = 1) -> np.ndarray:
+    """FastPFOR stream of x whose pages keep the paper's own layout (offset
+    word, truncated values, counted byte array, bitset and counted arrays)."""
+    return _encode(_load().oracle_fpi_encode, CODEC_FPI, x, stride)
+
+
+def fpi_decode(stream, n: int) -> np.ndarray:
+    rc, out = _decode(_load().oracle_fpi_decode, stream, n)
+    if rc != OK:
+        raise ValueError(f"oracle decode failed: {rc}")
+    return out
+
+
+def fpi_decode_rc(stream, n: int) -> int:
+    return _decode(_load().oracle_fpi_decode, stream, n)[0]
 
 
 def s8_mode(selector: int):

@@ -29,7 +29,9 @@
  *                     oracle_fp_encode; exception arrays padded to 128
  *                     values (SIMD-FastPFOR) or to 32 (FastPFOR,
  *                     oracle_fp32_encode); SimplePFOR pages hold one
- *                     Simple-8b array instead (oracle_sp_encode)
+ *                     Simple-8b array instead (oracle_sp_encode);
+ *                     codec 6 keeps the page in the paper's own layout
+ *                     (oracle_fpi_encode)
  *   tail              Variable Byte of the last n mod 128 deltas,
  *                     zero-padded to a word
  */
@@ -46,6 +48,7 @@
 #define OMAGIC_FP32 0x33465057u /* "WPF3" */
 #define OMAGIC_BPV 0x31565057u  /* "WPV1" */
 #define OMAGIC_SP 0x31535057u   /* "WPS1" */
+#define OMAGIC_FPI 0x31495057u  /* "WPI1" */
 #define OB32 32u               /* BP32 block: 32 integers (Section 6.2) */
 #define OSEG_BLOCKS 64u        /* patched-page segment: 64 blocks (8192 integers) */
 
@@ -252,7 +255,7 @@ static uint64_t o_pad4(uint64_t w) { return (w + 3u) & ~(uint64_t)3u; }
 static uint64_t o_units(int codec, uint64_t n)
 {
     uint64_t nfull = n / OB;
-    uint64_t per = (codec == 1 || codec == 3 || codec == 5) ? OFP_BLOCKS : OBP_BLOCKS;
+    uint64_t per = (codec == 1 || codec == 3 || codec == 5 || codec == 6) ? OFP_BLOCKS : OBP_BLOCKS;
     return (nfull + per - 1) / per;
 }
 
@@ -263,7 +266,8 @@ static uint32_t o_magic(int codec)
            : codec == 2 ? OMAGIC_BP32
            : codec == 3 ? OMAGIC_FP32
            : codec == 4 ? OMAGIC_BPV
-                        : OMAGIC_SP;
+           : codec == 5 ? OMAGIC_SP
+                              : OMAGIC_FPI;
 }
 
 /* Worst-case stream size in words, computed from the layout. */
@@ -279,6 +283,12 @@ uint64_t oracle_max_words(int codec, uint64_t n)
         /* a descriptor word per 128 values, every block at 32 bits, and at
          * most 3 words of padding per unit */
         words += units * 3 + nfull * (1 + OB);
+    } else if (codec == 6) {
+        /* per page: offset word, byte counter, bitset, 32 array counts and
+         * 3 words of padding; packed <= 128 words per block; byte array <=
+         * (3 + 127) bytes per block + 3 bytes of padding; exception bits of
+         * a block <= 127 * 32 and at most 31 values of padding per array */
+        words += units * (1 + 1 + 1 + 32 + 3 + 1 + 32 * 31) + nfull * (OB + (3 + 127) / 4 + 1 + 127);
     } else if (codec == 5) {
         /* per page: 4 header words and 3 words of padding; packed <= 128
          * words per block; metadata <= (3 + 128) bytes per block (+16 B
@@ -651,6 +661,89 @@ int64_t oracle_sp_encode(const uint32_t *x, uint64_t n, int stride, uint32_t *ou
     return o_encode(5, x, n, stride, out, cap);
 }
 
+/* ---- Section 5, FastPFOR page in the paper's own layout (the page-layout
+ * figure and the text around it), the byte array read serially:
+ *   word 0: the word offset, from the page start, of the byte array's
+ *       32-bit length counter (the offset "of the byte array": the counter
+ *       opens it)
+ *   the blocks' truncated values: block t's low b_t bits, 4*b_t words
+ *   the counter: the byte array's length in bytes
+ *   the byte array, zero-padded to a multiple of 4 bytes: per block in
+ *       order b, maxb, and, only when maxb > b, the exception count c and
+ *       the c positions (0..127), one byte each
+ *   a 32-bit bitset (bit k-1: array k is not empty), then for each
+ *       non-empty array k ascending its 32-bit length counter and its
+ *       values' high parts packed at k bits, padded to a multiple of 32
+ *       values (FastPFOR)
+ *   zero words up to a multiple of 4 (units start on 16 bytes). */
+static uint64_t o_fpi_page(const uint32_t *d, uint64_t nblocks, uint32_t *out)
+{
+    uint32_t *bw = malloc(nblocks * sizeof(uint32_t));
+    uint32_t *mb = malloc(nblocks * sizeof(uint32_t));
+    uint32_t *cc = malloc(nblocks * sizeof(uint32_t));
+    uint8_t *ba = malloc(nblocks * (3 + OB) + 4);
+    uint32_t *arr[33];
+    uint64_t cnt[33];
+    for (int k = 0; k <= 32; k++) {
+        arr[k] = malloc((nblocks * OB + 32) * sizeof(uint32_t));
+        cnt[k] = 0;
+    }
+    uint64_t p = 1, nba = 0;
+    for (uint64_t t = 0; t < nblocks; t++) {
+        const uint32_t *blk = d + t * OB;
+        oracle_fp_choose(blk, OB, &bw[t], &mb[t], &cc[t]);
+        oracle_pack(blk, OB, bw[t], out + p);
+        p += (uint64_t)OB * bw[t] / 32;
+        ba[nba++] = (uint8_t)bw[t];
+        ba[nba++] = (uint8_t)mb[t];
+        if (mb[t] > bw[t]) {
+            uint32_t k = mb[t] - bw[t];
+            ba[nba++] = (uint8_t)cc[t];
+            for (uint32_t i = 0; i < OB; i++)
+                if (oracle_bits(blk[i]) > bw[t]) {
+                    ba[nba++] = (uint8_t)i;
+                    arr[k][cnt[k]++] = blk[i] >> bw[t];
+                }
+        }
+    }
+    out[0] = (uint32_t)p;
+    out[p++] = (uint32_t)nba;
+    uint64_t baw = (nba + 3) / 4;
+    memset(out + p, 0, baw * 4);
+    memcpy(out + p, ba, nba);
+    p += baw;
+    uint32_t bitset = 0;
+    for (uint32_t k = 1; k <= 32; k++)
+        if (cnt[k] != 0)
+            bitset |= 1u << (k - 1);
+    out[p++] = bitset;
+    for (uint32_t k = 1; k <= 32; k++) {
+        if (cnt[k] == 0)
+            continue;
+        out[p++] = (uint32_t)cnt[k];
+        uint64_t padded = ((cnt[k] + 31) / 32) * 32;
+        for (uint64_t e = cnt[k]; e < padded; e++)
+            arr[k][e] = 0;
+        oracle_pack(arr[k], padded, k, out + p);
+        p += padded * k / 32;
+    }
+    while (p % 4)
+        out[p++] = 0;
+    for (int k = 0; k <= 32; k++)
+        free(arr[k]);
+    free(bw);
+    free(mb);
+    free(cc);
+    free(ba);
+    return p;
+}
+
+/* The paper's layout (codec 6): see o_fpi_page. */
+int64_t oracle_fpi_encode(const uint32_t *x, uint64_t n, int stride, uint32_t *out, uint64_t cap)
+{
+    return o_encode(6, x, n, stride, out, cap);
+}
+
 static int64_t o_encode(int codec, const uint32_t *x, uint64_t n, int stride,
                         uint32_t *out, uint64_t cap)
 {
@@ -667,7 +760,7 @@ static int64_t o_encode(int codec, const uint32_t *x, uint64_t n, int stride,
     uint64_t nfull = n / OB;
     uint64_t tail = n % OB;
     uint64_t units = o_units(codec, n);
-    uint64_t per = (codec == 1 || codec == 3 || codec == 5) ? OFP_BLOCKS : OBP_BLOCKS;
+    uint64_t per = (codec == 1 || codec == 3 || codec == 5 || codec == 6) ? OFP_BLOCKS : OBP_BLOCKS;
     uint64_t E = 1 + (uint64_t)stride;
     uint64_t ndir = units + (tail ? 1 : 0);
     uint64_t dir_words = o_pad4(E * ndir);
@@ -690,6 +783,7 @@ static int64_t o_encode(int codec, const uint32_t *x, uint64_t n, int stride,
             p += (codec == 0 || codec == 4) ? o_bp_unit(d + start, nb, out + p, codec == 4)
                  : codec == 2 ? o_bp32_unit(d + start, nb, out + p)
                  : codec == 5 ? o_sp_page(d + start, nb, out + p)
+                 : codec == 6 ? o_fpi_page(d + start, nb, out + p)
                               : o_fp_page(d + start, nb, out + p, codec == 3 ? 32 : OB, x, start, stride);
         }
     }
@@ -932,6 +1026,105 @@ done:
     return rc;
 }
 
+/* The paper's layout, parsed the way the page is written: the offset word
+ * locates the byte array, the byte array is read record by record (b,
+ * maxb, then c and the positions only when maxb > b), the exception
+ * arrays are found one after the other behind the bitset; exceptions are
+ * unpacked in bulk, then each block is unpacked and patched. */
+static int o_fpi_page_decode(const uint32_t *w, uint64_t avail, uint64_t nblocks, uint32_t *d)
+{
+    if (avail < 1)
+        return O_ERR_CORRUPT;
+    uint64_t cpos = w[0];
+    if (cpos < 1 || cpos >= avail)
+        return O_ERR_CORRUPT;
+    uint64_t nba = w[cpos];
+    uint64_t baw = (nba + 3) / 4;
+    if (baw > avail - cpos - 1)
+        return O_ERR_CORRUPT;
+    const uint8_t *ba = (const uint8_t *)(w + cpos + 1);
+    uint64_t xp = cpos + 1 + baw; /* the bitset */
+    if (xp >= avail)
+        return O_ERR_CORRUPT;
+    uint32_t bitset = w[xp++];
+    uint64_t cnt[33] = {0};
+    uint32_t *arr[33] = {0};
+    uint64_t used[33] = {0};
+    int rc = O_OK;
+    for (uint32_t k = 1; k <= 32; k++) {
+        if (!(bitset & (1u << (k - 1))))
+            continue;
+        if (xp >= avail) {
+            rc = O_ERR_CORRUPT;
+            goto done;
+        }
+        cnt[k] = w[xp++];
+        uint64_t padded = ((cnt[k] + 31) / 32) * 32;
+        if (cnt[k] == 0 || cnt[k] > nblocks * OB || padded * k / 32 > avail - xp) {
+            rc = O_ERR_CORRUPT;
+            goto done;
+        }
+        arr[k] = malloc(padded * sizeof(uint32_t));
+        oracle_unpack(w + xp, padded, k, arr[k]);
+        xp += padded * k / 32;
+    }
+    if (o_pad4(xp) != avail) {
+        rc = O_ERR_CORRUPT;
+        goto done;
+    }
+    uint64_t at = 0, pk = 1;
+    for (uint64_t t = 0; t < nblocks; t++) {
+        if (at + 2 > nba) {
+            rc = O_ERR_CORRUPT;
+            goto done;
+        }
+        uint32_t b = ba[at], maxb = ba[at + 1];
+        at += 2;
+        if (b > 32 || maxb > 32 || maxb < b || pk + (uint64_t)OB * b / 32 > cpos) {
+            rc = O_ERR_CORRUPT;
+            goto done;
+        }
+        oracle_unpack(w + pk, OB, b, d + t * OB);
+        pk += (uint64_t)OB * b / 32;
+        if (maxb == b)
+            continue;
+        uint32_t k = maxb - b;
+        if (at + 1 > nba) {
+            rc = O_ERR_CORRUPT;
+            goto done;
+        }
+        uint32_t c = ba[at++];
+        if (c == 0 || c >= OB || at + c > nba) {
+            rc = O_ERR_CORRUPT;
+            goto done;
+        }
+        for (uint32_t e = 0; e < c; e++) {
+            uint32_t pos = ba[at + e];
+            if (pos >= OB || (e > 0 && pos <= ba[at + e - 1]) || arr[k] == NULL || used[k] >= cnt[k]) {
+                rc = O_ERR_CORRUPT;
+                goto done;
+            }
+            d[t * OB + pos] |= arr[k][used[k]++] << b;
+        }
+        at += c;
+    }
+    if (pk != cpos || at != nba) {
+        rc = O_ERR_CORRUPT;
+        goto done;
+    }
+    for (uint32_t k = 1; k <= 32; k++)
+        if (used[k] != cnt[k])
+            rc = O_ERR_CORRUPT;
+    /* the byte array's padding is zero */
+    for (uint64_t i = nba; i < 4 * baw; i++)
+        if (ba[i] != 0)
+            rc = O_ERR_CORRUPT;
+done:
+    for (uint32_t k = 1; k <= 32; k++)
+        free(arr[k]);
+    return rc;
+}
+
 static int o_decode(int codec, const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n)
 {
     if (in_words < 8)
@@ -944,7 +1137,7 @@ static int o_decode(int codec, const uint32_t *in, uint64_t in_words, uint32_t *
         return O_ERR_CORRUPT;
     uint64_t nfull = n / OB, tail = n % OB;
     uint64_t units = o_units(codec, n);
-    uint64_t per = (codec == 1 || codec == 3 || codec == 5) ? OFP_BLOCKS : OBP_BLOCKS;
+    uint64_t per = (codec == 1 || codec == 3 || codec == 5 || codec == 6) ? OFP_BLOCKS : OBP_BLOCKS;
     uint64_t total = in[7], tail_off = in[6], tail_bytes = in[5];
     if (in[4] != units || total > in_words || (tail == 0) != (tail_bytes == 0))
         return O_ERR_CORRUPT;
@@ -972,6 +1165,7 @@ static int o_decode(int codec, const uint32_t *in, uint64_t in_words, uint32_t *
             rc = (codec == 0 || codec == 4) ? o_bp_unit_decode(in + off, end - off, nb, out + start, codec == 4)
                  : codec == 2 ? o_bp32_unit_decode(in + off, end - off, nb, out + start)
                  : codec == 5 ? o_sp_page_decode(in + off, end - off, nb, out + start)
+                 : codec == 6 ? o_fpi_page_decode(in + off, end - off, nb, out + start)
                               : o_fp_page_decode(in + off, end - off, nb, out + start, codec == 3 ? 32 : OB,
                                                  stride, segb);
             if (codec == 1 || codec == 3)
@@ -1032,6 +1226,11 @@ int oracle_bpv_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint
 int oracle_sp_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n)
 {
     return o_decode(5, in, in_words, out, n);
+}
+
+int oracle_fpi_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n)
+{
+    return o_decode(6, in, in_words, out, n);
 }
 
 /* ------------------------------------------------------------------------

@@ -862,3 +862,104 @@ def test_patched_stride0_pages_hold_no_segment_bases():
     nb, packed, _, bitset = (int(v) for v in s[at:at + 4])
     assert nb == 512 and _fp_hdr_words(nb, bin(bitset).count("1"), 0) == -(-(4 + bin(bitset).count("1")) // 4) * 4
     assert np.array_equal(oracle.fp_decode(s, x.size), x)
+
+
+# ---------------------------------------------------------------- the paper's own page layout
+
+def test_paper_layout_worked_example_page():
+    """Section 5's running example (the block extended to 128 values with
+    more '10's, keeping b = 2) as a one-block page in the layout of the
+    page-layout figure: the offset word points at the byte array's counter,
+    which sits right after the truncated values and holds 6; the byte array
+    is the printed 2, 6, 3, 4, 9, 11, zero-padded to 8 bytes; then the
+    bitset (array 4 only), array 4's counter 3 and its three 4-bit high
+    parts 1001, 1000, 1101, padded to 32 values (4 words)."""
+    g, vals = _example_block()
+    block = np.array(vals + [2] * 112, dtype=np.uint32)
+    s = oracle.fpi_encode(block, stride=0)
+    assert int(s[0]) == 0x31495057 and int(s[4]) == 1
+    page = s[int(s[8]):int(s[6])]
+    packed_words = 128 * 2 // 32
+    assert int(page[0]) == 1 + packed_words
+    trunc = oracle.unpack(page[1:1 + packed_words], 16, 2)
+    assert [int(v) for v in trunc] == [int(t, 2) for t in g["truncated_binary"]]
+    assert int(page[1 + packed_words]) == len(g["byte_array"])
+    ba = page[2 + packed_words:4 + packed_words].view(np.uint8)
+    assert list(ba[:6]) == g["byte_array"] and not ba[6:].any()
+    at = 4 + packed_words
+    assert int(page[at]) == 1 << (g["exception_array_width"] - 1)
+    assert int(page[at + 1]) == 3
+    exc = page[at + 2:at + 2 + 4]
+    assert [int(v) for v in oracle.unpack(exc, 3, 4)] == [int(t, 2) for t in g["exception_high_bits_binary"]]
+    assert not oracle.unpack(exc, 32, 4)[3:].any()
+    assert page.size == at + 2 + 4 + 2  # zero words to a multiple of 4
+    assert np.array_equal(oracle.fpi_decode(s, 128), block)
+
+
+@pytest.mark.parametrize("stride", [0, 1, 4])
+def test_paper_layout_holds_the_fastpfor_page_inline(stride):
+    # the same page as the FastPFOR (32-padded) page of the same input,
+    # arranged as the paper arranges it: its packed words, its b / maxb / c
+    # bytes interleaved per block (c and the positions only when maxb > b),
+    # its arrays each behind a counter instead of all counts in the header
+    x = datagen.patched_gaps(2 * 65536 + 128 * 3 + 9, seed=90 + stride)
+    a, f = oracle.fpi_encode(x, stride), oracle.fp32_encode(x, stride)
+    units = int(a[4])
+    assert units == int(f[4]) == 3
+    ends_a = [int(a[8 + u]) for u in range(1, units)] + [int(a[6])]
+    ends_f = [int(f[8 + u]) for u in range(1, units)] + [int(f[6])]
+    for u in range(units):
+        pa = a[int(a[8 + u]):ends_a[u]]
+        pf = f[int(f[8 + u]):ends_f[u]]
+        nb, packed, meta_bytes, bitset = (int(v) for v in pf[:4])
+        ks = [k for k in range(1, 33) if bitset >> (k - 1) & 1]
+        hdr = -(-(4 + len(ks) + stride * (-(-nb // 64) - 1)) // 4) * 4
+        cpos = int(pa[0])
+        assert cpos == 1 + packed
+        assert np.array_equal(pa[1:cpos], pf[hdr:hdr + packed])
+        meta = pf[hdr + packed:].view(np.uint8)[:meta_bytes]
+        b, mb, c, pos = meta[:nb], meta[nb:2 * nb], meta[2 * nb:3 * nb], meta[3 * nb:]
+        want, at = [], 0
+        for t in range(nb):
+            want += [int(b[t]), int(mb[t])]
+            if mb[t] > b[t]:
+                want += [int(c[t])] + [int(v) for v in pos[at:at + int(c[t])]]
+            at += int(c[t])
+        nba = int(pa[cpos])
+        assert nba == len(want) == 3 * nb + len(pos) - int((mb == b).sum())
+        ba = pa[cpos + 1:cpos + 1 + -(-nba // 4)].view(np.uint8)
+        assert list(ba[:nba]) == want and not ba[nba:].any()
+        xp = cpos + 1 + -(-nba // 4)
+        assert int(pa[xp]) == bitset
+        xp += 1
+        xf = hdr + packed + -(-meta_bytes // 16) * 4
+        counts = [int(v) for v in pf[4:4 + len(ks)]]
+        for k, cnt in zip(ks, counts):
+            words = -(-cnt // 32) * k
+            assert int(pa[xp]) == cnt
+            assert np.array_equal(pa[xp + 1:xp + 1 + words], pf[xf:xf + words])
+            xp += 1 + words
+            xf += words
+        assert -(-xp // 4) * 4 == pa.size and not pa[xp:].any()
+    assert np.array_equal(oracle.fpi_decode(a, x.size), x)
+
+
+def test_paper_layout_corrupt_pages_are_rejected():
+    x = datagen.patched_gaps(65536 + 700, seed=95)
+    s = oracle.fpi_encode(x, 1)
+    assert oracle.fpi_decode_rc(s, x.size) == oracle.OK
+    p0 = int(s[8])
+    cpos = p0 + int(s[p0])
+    nba = int(s[cpos])
+    bad_cases = {
+        "offset": (p0, int(s[p0]) + 4),
+        "counter": (cpos, nba + 1),
+        "bitset": (cpos + 1 + -(-nba // 4), int(s[cpos + 1 + -(-nba // 4)]) ^ 1),
+        "first_width": (cpos + 1, (int(s[cpos + 1]) & ~0xFF) | 33),
+    }
+    for what, (at, val) in bad_cases.items():
+        bad = s.copy()
+        bad[at] = val & 0xFFFFFFFF
+        assert oracle.fpi_decode_rc(bad, x.size) == oracle.ERR_CORRUPT, what
+    assert oracle.fpi_decode_rc(oracle.fp32_encode(x, 1), x.size) == oracle.ERR_CORRUPT
+

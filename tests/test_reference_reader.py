@@ -4,7 +4,8 @@ the oracle's streams.
 The reader below is written from the layout alone (header, directory with
 unit offsets and bases, SIMD-BP128 meta-blocks in the sequential and in the
 four-lane block layout, BP32 meta-blocks, FastPFOR pages with exception
-arrays padded to 128 or to 32 values, SimplePFOR pages with one Simple-8b
+arrays padded to 128 or to 32 values, FastPFOR pages in the paper's own
+layout with the counted byte array, SimplePFOR pages with one Simple-8b
 array of exception high parts, Variable Byte remainder), with bit fields
 read from Python big integers; it shares nothing with the oracle but the
 layout. Every stream the oracle writes for small inputs (every length
@@ -19,9 +20,9 @@ import oracle
 from paper_1209_2137_amd import datagen
 
 MAGIC = {"bp": 0x31425057, "fp": 0x31465057, "bp32": 0x32335057, "fp32": 0x33465057, "bpv": 0x31565057,
-         "sp": 0x31535057}
+         "sp": 0x31535057, "fpi": 0x31495057}
 ENC = {"bp": oracle.bp_encode, "fp": oracle.fp_encode, "bp32": oracle.bp32_encode, "fp32": oracle.fp32_encode,
-       "bpv": oracle.bpv_encode, "sp": oracle.sp_encode}
+       "bpv": oracle.bpv_encode, "sp": oracle.sp_encode, "fpi": oracle.fpi_encode}
 # Simple-8b modes (Section 2): selector -> (integers per word, bits each)
 S8 = [(240, 0), (120, 0), (60, 1), (30, 2), (20, 3), (15, 4), (12, 5), (10, 6), (8, 7), (7, 8), (6, 10), (5, 12),
       (4, 15), (3, 20), (2, 30), (1, 60)]
@@ -128,6 +129,44 @@ def _fp_page(w, nblocks, pad, S):
     return out, segb
 
 
+def _fpi_page(w, nblocks):
+    """The paper's page: offset word -> counter of the byte array, whose
+    records are b, maxb and, when maxb > b, c and c positions; after the
+    byte array a bitset, then each array behind its counter, padded to 32
+    values."""
+    at = int(w[0])
+    nba = int(w[at])
+    ba = bytes(np.asarray(w[at + 1:at + 1 + -(-nba // 4)], dtype=np.uint32).tobytes())
+    xp = at + 1 + -(-nba // 4)
+    bitset = int(w[xp])
+    xp += 1
+    arrays = {}
+    for k in range(1, 33):
+        if bitset >> (k - 1) & 1:
+            cnt = int(w[xp])
+            words = -(-cnt // 32) * k
+            arrays[k] = _fields(w[xp + 1:xp + 1 + words], cnt, k)
+            xp += 1 + words
+    assert -(-xp // 4) * 4 == len(w)
+    taken = {k: 0 for k in arrays}
+    out, r, pk = [], 0, 1
+    for _ in range(nblocks):
+        b, mb = ba[r], ba[r + 1]
+        r += 2
+        vals = _fields(w[pk:pk + 4 * b], 128, b)
+        pk += 4 * b
+        if mb > b:
+            c = ba[r]
+            for p_ in ba[r + 1:r + 1 + c]:
+                vals[p_] |= arrays[mb - b][taken[mb - b]] << b
+                taken[mb - b] += 1
+            r += 1 + c
+        out += vals
+    assert pk == at and r == nba and not any(ba[nba:])
+    assert all(taken[k] == len(arrays[k]) for k in arrays)
+    return out
+
+
 def _sp_page(w, nblocks):
     """SimplePFOR page: FastPFOR's packed values and metadata, the
     exceptions' high parts as one Simple-8b array (selector in the top four
@@ -167,7 +206,7 @@ def read(stream, codec):
     n = int(s[1]) | (int(s[2]) << 32)
     S, units, tail_bytes, tail_off, total = (int(v) for v in s[3:8])
     assert total == s.size
-    per = 512 if codec in ("fp", "fp32", "sp") else 16
+    per = 512 if codec in ("fp", "fp32", "sp", "fpi") else 16
     nfull, tail = n // 128, n % 128
     assert units == -(-nfull // per)
     ndir = units + (1 if tail else 0)
@@ -186,6 +225,8 @@ def read(stream, codec):
                 d = _bp32_unit(w, nb)
             elif codec == "sp":
                 d = _sp_page(w, nb)
+            elif codec == "fpi":
+                d = _fpi_page(w, nb)
             else:
                 d, segb = _fp_page(w, nb, 32 if codec == "fp32" else 128, S)
         else:
