@@ -123,7 +123,7 @@ def bench_single(wp, x_np, codec, stride, steps, warmup, name, comp=None, n=None
     outs = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(2)]
     dec = {wp.CODEC_BP: wp.bp_decode, wp.CODEC_FP: wp.fastpfor_decode, wp.CODEC_BP32: wp.bp32_decode,
            wp.CODEC_FP32: wp.fastpfor32_decode, wp.CODEC_BPV: wp.bp_vertical_decode,
-           wp.CODEC_SP: wp.simplepfor_decode}[codec]
+           wp.CODEC_SP: wp.simplepfor_decode, wp.CODEC_FPI: wp.fastpfor_inline_decode}[codec]
     stream = torch.cuda.current_stream()
     dec(comps[0], n, outs[0])
     wp.check()
@@ -138,7 +138,7 @@ def bench_single(wp, x_np, codec, stride, steps, warmup, name, comp=None, n=None
     return {
         "name": name, "n": n,
         "codec": {wp.CODEC_BP: "bp", wp.CODEC_FP: "fp", wp.CODEC_BP32: "bp32", wp.CODEC_FP32: "fp32",
-                  wp.CODEC_BPV: "bpv", wp.CODEC_SP: "sp"}[codec],
+                  wp.CODEC_BPV: "bpv", wp.CODEC_SP: "sp", wp.CODEC_FPI: "fpi"}[codec],
         "stride": stride,
         "bits_per_int": comp_bytes * 8 / n, "ms_per_step": wall, "kernel_ms": ev,
         "gints_per_s": n / (wall * 1e-3) / 1e9, "kernel_gints_per_s": n / (ev * 1e-3) / 1e9,
@@ -156,7 +156,7 @@ def bench_encode(wp, x_np, codec, stride, steps, warmup, name):
     xs = replicas(xd, n * 4)
     enc = {wp.CODEC_BP: wp.bp_encode, wp.CODEC_FP: wp.fastpfor_encode, wp.CODEC_BP32: wp.bp32_encode,
            wp.CODEC_FP32: wp.fastpfor32_encode, wp.CODEC_BPV: wp.bp_vertical_encode,
-           wp.CODEC_SP: wp.simplepfor_encode}[codec]
+           wp.CODEC_SP: wp.simplepfor_encode, wp.CODEC_FPI: wp.fastpfor_inline_encode}[codec]
     buf, words = enc(xd, stride)
     wp.check()
     comp_words = int(words.item())
@@ -653,6 +653,9 @@ def main():
                                                   args.steps, args.warmup, "fastpfor (arrays padded to 32) 2^28")
         extra["sp_patched_2e28"] = bench_single(wp, datagen.patched_gaps(1 << 28, seed=4), wp.CODEC_SP, 1,
                                                 args.steps, args.warmup, "simplepfor (Simple-8b high parts) 2^28")
+        extra["fpi_patched_2e28"] = bench_single(wp, datagen.patched_gaps(1 << 28, seed=4), wp.CODEC_FPI, 1,
+                                                 max(3, args.steps // 4), 2,
+                                                 "fastpfor pages in the paper's own layout 2^28")
         print("# patched done", file=sys.stderr, flush=True)
         extra["delta_inplace_2e28"] = bench_delta(wp, 1 << 28, args.steps, args.warmup)
         print("# delta done", file=sys.stderr, flush=True)

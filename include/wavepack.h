@@ -97,6 +97,7 @@ extern "C" {
 #define WP_CODEC_FP32 3 /* patched pages, exception arrays padded to 32 values */
 #define WP_CODEC_BPV 4  /* binary packing as WP_CODEC_BP, four-lane block layout */
 #define WP_CODEC_SP 5   /* patched pages, exception high parts in one Simple-8b array per page */
+#define WP_CODEC_FPI 6  /* patched pages in the paper's own page layout (counted byte array) */
 
 /* Largest stream any input of n integers can produce, in 32-bit words.
  * Host only, pure. Returns 0 when n is beyond the format (streams are
@@ -195,6 +196,31 @@ int32_t simplepfor_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, 
 int32_t simplepfor_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
                           void *stream);
 
+/* FastPFOR pages in the paper's own layout (Section 5 and its page-layout
+ * figure), magic 'WPI1', header, directory and tail as everywhere: a page
+ * is [offset word][the blocks' truncated values, 4*b words each][byte
+ * counter][byte array][bitset][for each non-empty array k ascending: its
+ * length counter, its high parts packed at k bits, padded to 32 values],
+ * zero-padded to 4 words. The offset word holds the word offset of the
+ * byte counter; the byte array (zero-padded to 4 bytes) holds per block b,
+ * maxb and, only when maxb > b, the count c and the c positions. Widths,
+ * exceptions and arrays are those of fastpfor32_encode. The byte array
+ * can only be read record by record; the decoder walks it. */
+
+/* Encoder for that layout. Arguments as bp_encode, with WP_CODEC_FPI for
+ * the capacity; scratch as bp_encode (it also holds the FastPFOR stream
+ * that the pages are rearranged from). */
+int32_t fastpfor_inline_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,
+                               uint64_t out_cap_words, uint64_t *out_words, void *stream);
+
+/* Decoder for that layout: as fastpfor_decode. One wavefront per page
+ * copies the page's byte array into LDS (when it fits in 12 KB; otherwise
+ * it reads it from the page), walks its records for every block's widths,
+ * count and positions, walks the counted exception arrays, then decodes
+ * the page pass by pass. Allocates nothing. */
+int32_t fastpfor_inline_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
+                               void *stream);
+
 /* Patched decoder (Section 5): unpack each block's low bits, patch each
  * exception with its high part from array k shifted left by b, then the
  * prefix sum. Arguments as bp_decode. Allocates nothing. */
@@ -244,7 +270,7 @@ int32_t wp_intersect(const uint32_t *a, uint64_t na, const uint32_t *b, uint64_t
                      uint64_t *out_count, void *stream);
 
 /* As wp_intersect, with the second list still compressed (`b_comp`,
- * b_words words, nb integers, any WP_CODEC_*; 16-byte
+ * b_words words, nb integers, any WP_CODEC_* but WP_CODEC_FPI; 16-byte
  * aligned): the directory serves as a skip list. A strictly increasing
  * list's unit holds values between the value stored as its base (the value
  * just before the unit) and the next unit's, so only the units (and the
@@ -261,7 +287,7 @@ int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const uint32_t *
 /* Random access by key (the directory's bases as a skip list, Section 3
  * differential coding): the index range [i0, i1) of the values v with
  * key_lo <= v <= key_hi in a non-decreasing list held as the stream `in`
- * (in_words words, n integers, any WP_CODEC_*, 16-byte aligned). Only the
+ * (in_words words, n integers, any WP_CODEC_* but WP_CODEC_FPI, 16-byte aligned). Only the
  * units (and the tail) whose values can lie in the key range, or in which
  * the range's ends fall, are decoded into `out` (device, n integers,
  * 16-byte aligned, caller-owned), each at its place in the whole list:

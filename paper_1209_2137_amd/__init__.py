@@ -25,6 +25,7 @@ CODEC_BP32 = 2
 CODEC_FP32 = 3
 CODEC_BPV = 4
 CODEC_SP = 5
+CODEC_FPI = 6
 
 EXPORTS = (
     "bp_encode", "bp_decode", "bp32_encode", "bp32_decode", "fastpfor_encode", "fastpfor_decode",
@@ -32,7 +33,8 @@ EXPORTS = (
     "wp_max_compressed_words", "wp_check", "wp_strerror", "wp_set_decode_tune", "wp_time_next_launch",
     "wp_batch_plan", "wp_batch_replan", "wp_batch_decode", "wp_batch_items", "wp_batch_free",
     "wp_intersect", "wp_intersect_compressed", "wp_decode_range",
-    "simplepfor_decode", "simplepfor_encode", "delta_decode_inplace_noalloc",
+    "simplepfor_decode", "simplepfor_encode", "delta_decode_inplace_noalloc", "fastpfor_inline_encode",
+    "fastpfor_inline_decode",
 )
 
 _lib = None
@@ -76,12 +78,12 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     vp, u64, i32, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint32
     for name in ("bp_encode", "bp32_encode", "fastpfor_encode", "fastpfor32_encode", "bp_vertical_encode",
-                 "simplepfor_encode"):
+                 "simplepfor_encode", "fastpfor_inline_encode"):
         f = getattr(L, name)
         f.argtypes = [vp, u64, i32, vp, u64, vp, vp]
         f.restype = i32
     for name in ("bp_decode", "bp32_decode", "fastpfor_decode", "fastpfor32_decode", "bp_vertical_decode",
-                 "simplepfor_decode"):
+                 "simplepfor_decode", "fastpfor_inline_decode"):
         f = getattr(L, name)
         f.argtypes = [vp, u64, vp, u64, vp]
         f.restype = i32
@@ -264,6 +266,17 @@ def bp_vertical_encode(x, stride: int = 1, out=None, out_words=None, stream=None
     return _encode(lib().bp_vertical_encode, CODEC_BPV, x, stride, out, out_words, stream, "bp_vertical_encode")
 
 
+def fastpfor_inline_encode(x, stride: int = 1, out=None, out_words=None, stream=None):
+    """Encodes x (device uint32) as FastPFOR pages in the paper's own layout."""
+    return _encode(lib().fastpfor_inline_encode, CODEC_FPI, x, stride, out, out_words, stream,
+                   "fastpfor_inline_encode")
+
+
+def fastpfor_inline_decode(comp, n: int, out=None, stream=None):
+    """Decodes a stream of FastPFOR pages in the paper's own layout into out[0:n]."""
+    return _decode(lib().fastpfor_inline_decode, comp, n, out, stream, "fastpfor_inline_decode")
+
+
 def simplepfor_encode(x, stride: int = 1, out=None, out_words=None, stream=None):
     """Encodes x (device uint32) as SimplePFOR pages (exception high parts in Simple-8b)."""
     return _encode(lib().simplepfor_encode, CODEC_SP, x, stride, out, out_words, stream, "simplepfor_encode")
@@ -273,7 +286,7 @@ def encode_trimmed(x, codec: int = CODEC_BP, stride: int = 1, stream=None):
     """Encodes and returns a tensor of exactly the stream's length
     (synchronises the stream to read the length)."""
     enc = {CODEC_BP: bp_encode, CODEC_FP: fastpfor_encode, CODEC_BP32: bp32_encode, CODEC_FP32: fastpfor32_encode,
-           CODEC_BPV: bp_vertical_encode, CODEC_SP: simplepfor_encode}[codec]
+           CODEC_BPV: bp_vertical_encode, CODEC_SP: simplepfor_encode, CODEC_FPI: fastpfor_inline_encode}[codec]
     buf, words = enc(x, stride, stream=stream)
     check(stream)
     return buf[: int(words.item())].clone()

@@ -78,6 +78,11 @@ union FpWaveItemLds<kPageFp32> {
     FpWaveLds page;
     TailLds<1> tail;
 };
+template <>
+union FpWaveItemLds<kPageFpi> {
+    FpiLds page;
+    TailLds<1> tail;
+};
 
 // Wavefronts resident per SIMD that the patched-page kernel is compiled
 // for (register budget).
@@ -95,14 +100,17 @@ __global__ __launch_bounds__(64 * WAVES, WP_FP_MIN_WAVES) void k_fp_decode(const
 {
     __shared__ FpWaveItemLds<KIND> L[WAVES];
     ListHdr H;
-    const uint32_t magic = KIND == kPageSp ? kMagicSP : KIND == kPageFp32 ? kMagicFP32 : kMagicFP;
+    const uint32_t magic = KIND == kPageSp     ? kMagicSP
+                           : KIND == kPageFp32 ? kMagicFP32
+                           : KIND == kPageFpi  ? kMagicFPI
+                                               : kMagicFP;
     if (!check_header(in, in_words, n, magic, kFpBlocks, H)) {
         if (blockIdx.x == 0 && threadIdx.x == 0)
             *err = kErrCorrupt;
         return;
     }
     const uint32_t wave = uniform(threadIdx.x >> 6);
-    constexpr uint32_t per = KIND == kPageSp ? 1u : kPageSegs;
+    constexpr uint32_t per = page_items<KIND>(kFpBlocks);
     const uint64_t item = (uint64_t)blockIdx.x * WAVES + wave;
     const uint64_t u = item / per;
     const uint32_t seg = (uint32_t)(item % per);
@@ -146,7 +154,7 @@ static Tune g_tune[3] = {{4, 4, kBpRunsPerCu, 2}, {4, 4, 0, 0}, {4, 4, kBpRunsPe
 
 static int tune_slot(int codec)
 {
-    return (codec == WP_CODEC_FP || codec == WP_CODEC_FP32 || codec == WP_CODEC_SP) ? 1
+    return (codec == WP_CODEC_FP || codec == WP_CODEC_FP32 || codec == WP_CODEC_SP || codec == WP_CODEC_FPI) ? 1
            : codec == WP_CODEC_BP32                                                ? 2
                                                                                    : 0;
 }
@@ -204,6 +212,8 @@ static void launch_fp(int kind, uint64_t grid, hipStream_t st, const uint32_t *i
     else if (kind == kPageSp)
         launch_timed(k_fp_decode<WAVES, kPageSp>, dim3((uint32_t)grid), dim3(64 * WAVES), st, in, in_words, out, n,
                      err);
+    else if (kind == kPageFpi)
+        launch_timed(k_fp_decode<1, kPageFpi>, dim3((uint32_t)grid), dim3(64), st, in, in_words, out, n, err);
     else
         launch_timed(k_fp_decode<WAVES, kPageFp>, dim3((uint32_t)grid), dim3(64 * WAVES), st, in, in_words, out, n,
                      err);
@@ -221,7 +231,7 @@ static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, u
     DevState *ds = dev_state();
     if (ds == nullptr)
         return WP_ERR_HIP;
-    const bool paged = codec == WP_CODEC_FP || codec == WP_CODEC_FP32 || codec == WP_CODEC_SP;
+    const bool paged = codec == WP_CODEC_FP || codec == WP_CODEC_FP32 || codec == WP_CODEC_SP || codec == WP_CODEC_FPI;
     const uint64_t per = paged ? kFpBlocks : kBpBlocks;
     const uint64_t nfull = n / kBlock;
     const uint64_t units = (nfull + per - 1) / per;
@@ -258,13 +268,19 @@ static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, u
 #undef WP_BP
 #undef WP_BP_D
     } else {
-        // one wavefront per segment (SimplePFOR: per page), then one for the tail
-        const uint64_t per_page = codec == WP_CODEC_SP ? 1 : kPageSegs;
-        uint64_t grid = (units * per_page + has_tail + t.waves - 1) / t.waves;
+        // one wavefront per segment (SimplePFOR and the paper's layout: per
+        // page; the latter one wavefront per workgroup, for its LDS), then
+        // one for the tail
+        const uint64_t per_page = (codec == WP_CODEC_SP || codec == WP_CODEC_FPI) ? 1 : kPageSegs;
+        const uint64_t wpg = codec == WP_CODEC_FPI ? 1 : (uint64_t)t.waves;
+        uint64_t grid = (units * per_page + has_tail + wpg - 1) / wpg;
         grid = grid ? grid : 1;
         if (grid > 0x7FFFFFFFull)
             return WP_ERR_INVALID_ARG;
-        const int kind = codec == WP_CODEC_FP32 ? kPageFp32 : codec == WP_CODEC_SP ? kPageSp : kPageFp;
+        const int kind = codec == WP_CODEC_FP32 ? kPageFp32
+                         : codec == WP_CODEC_SP ? kPageSp
+                         : codec == WP_CODEC_FPI ? kPageFpi
+                                                 : kPageFp;
         if (t.waves == 1)
             launch_fp<1>(kind, grid, st, in, in_words, out, n, ds->err);
         else if (t.waves == 2)
@@ -309,6 +325,12 @@ extern "C" int32_t simplepfor_decode(const uint32_t *in, uint64_t in_words, uint
     return decode_common(WP_CODEC_SP, in, in_words, out, n, stream);
 }
 
+extern "C" int32_t fastpfor_inline_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
+                                          void *stream)
+{
+    return decode_common(WP_CODEC_FPI, in, in_words, out, n, stream);
+}
+
 extern "C" int32_t bp_vertical_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
                                       void *stream)
 {
@@ -318,7 +340,7 @@ extern "C" int32_t bp_vertical_decode(const uint32_t *in, uint64_t in_words, uin
 extern "C" int32_t wp_set_decode_tune(int32_t codec, int32_t waves, int32_t vpl, int32_t depth, int32_t wg_per_cu)
 {
     if ((codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32 && codec != WP_CODEC_FP32 &&
-         codec != WP_CODEC_BPV && codec != WP_CODEC_SP) ||
+         codec != WP_CODEC_BPV && codec != WP_CODEC_SP && codec != WP_CODEC_FPI) ||
         !valid_tune(codec, waves, vpl) || wg_per_cu < 0 ||
         wg_per_cu > 1024 || depth < 0 || depth == 1 || depth > 4)
         return WP_ERR_INVALID_ARG;
@@ -370,10 +392,11 @@ extern "C" const char *wp_strerror(int32_t code)
 extern "C" uint64_t wp_max_compressed_words(int32_t codec, uint64_t n)
 {
     if (codec != WP_CODEC_BP && codec != WP_CODEC_FP && codec != WP_CODEC_BP32 && codec != WP_CODEC_FP32 &&
-        codec != WP_CODEC_BPV && codec != WP_CODEC_SP)
+        codec != WP_CODEC_BPV && codec != WP_CODEC_SP && codec != WP_CODEC_FPI)
         return 0;
     const uint64_t nfull = n / kBlock, tail = n % kBlock;
-    const uint64_t per = (codec == WP_CODEC_FP || codec == WP_CODEC_FP32 || codec == WP_CODEC_SP) ? kFpBlocks
+    const uint64_t per = (codec == WP_CODEC_FP || codec == WP_CODEC_FP32 || codec == WP_CODEC_SP ||
+                          codec == WP_CODEC_FPI) ? kFpBlocks
                                                                                                  : kBpBlocks;
     const uint64_t units = (nfull + per - 1) / per;
     uint64_t w = kHdrWords + ((5 * (units + 1) + 3) & ~3ull);
@@ -383,6 +406,12 @@ extern "C" uint64_t wp_max_compressed_words(int32_t codec, uint64_t n)
         // a descriptor word per meta-block, every block at 32 bits, at most
         // three words of padding per unit
         w += units * 3 + nfull * (1 + 128);
+    } else if (codec == WP_CODEC_FPI) {
+        // page: offset word, byte counter, bitset, 32 array counters and 3
+        // words of padding; packed <= 128 words per block; byte array <=
+        // 130 bytes per block + 3 bytes of padding; exception bits of a
+        // block <= 127 * 32; at most 31 values of padding per array
+        w += units * (1 + 1 + 1 + 32 + 3 + 1 + 32 * 31) + nfull * (128 + 33 + 127);
     } else if (codec == WP_CODEC_SP) {
         // page header 4 words and 3 words of padding; packed <= 128 words per
         // block; metadata <= 131 bytes per block + 16 bytes padding; at most

@@ -36,6 +36,7 @@ constexpr uint32_t kB32 = 32;                 // BP32 block length (Section 6.2)
 constexpr uint32_t kMagicFP32 = 0x33465057u;  // "WPF3"
 constexpr uint32_t kMagicBPV = 0x31565057u;   // "WPV1"
 constexpr uint32_t kMagicSP = 0x31535057u;    // "WPS1"
+constexpr uint32_t kMagicFPI = 0x31495057u;   // "WPI1"
 
 // Words of a page's exception array of `cnt` values at k bits, padded to a
 // multiple of 128 values (SIMD-FastPFOR) or of 32 (FastPFOR, P32); either
@@ -429,7 +430,7 @@ __device__ __forceinline__ void scan_wave4(uint32_t (&x)[4], uint32_t (&carry)[4
 // 64 Simple-8b words at a time (lane i word i), a wave scan of the counts
 // their selectors give places each word's integers, and the words are
 // loaded one batch ahead.
-enum : int { kPageFp = 0, kPageFp32 = 1, kPageSp = 2 };
+enum : int { kPageFp = 0, kPageFp32 = 1, kPageSp = 2, kPageFpi = 3 };
 constexpr uint32_t kSpRing = 2048;  // high parts held by a SimplePFOR page's ring
 constexpr uint32_t kSegBlocks = 64;  // blocks per segment of a patched page
 constexpr uint32_t kSegInts = kSegBlocks * kBlock;
@@ -440,7 +441,7 @@ constexpr uint32_t kPageSegs = kFpBlocks / kSegBlocks;
 template <int KIND>
 __host__ __device__ constexpr uint32_t page_items(uint32_t nb)
 {
-    return KIND == kPageSp ? 1u : (nb + kSegBlocks - 1) / kSegBlocks;
+    return (KIND == kPageSp || KIND == kPageFpi) ? 1u : (nb + kSegBlocks - 1) / kSegBlocks;
 }
 
 // A segment's packed words stream through a per-wavefront LDS ring in
@@ -464,8 +465,32 @@ struct alignas(16) FpLdsT {
     uint32_t excb[33];                // page word offset of array k
 };
 using FpWaveLds = FpLdsT<1>;
+
+// A page in the paper's own layout (kPageFpi) is parsed into LDS first:
+// per block its widths and count, and where its positions start in the
+// byte array, which is held in LDS when it fits.
+constexpr uint32_t kFpiBaWords = 3072;
+struct alignas(16) FpiLds : FpLdsT<2> {
+    uint32_t bm[kFpBlocks];      // block t: b | maxb << 8 | c << 16
+    uint32_t posoff[kFpBlocks];  // block t: byte offset of its positions in the byte array
+    uint32_t kc[33];             // array k's length (from its counter)
+    uint32_t ba[kFpiBaWords];    // the byte array, when it fits
+};
+
 template <int KIND>
-using FpLdsOf = FpLdsT<KIND == kPageSp ? 2 : 1>;
+struct FpLdsSel {
+    using T = FpLdsT<1>;
+};
+template <>
+struct FpLdsSel<kPageSp> {
+    using T = FpLdsT<2>;
+};
+template <>
+struct FpLdsSel<kPageFpi> {
+    using T = FpiLds;
+};
+template <int KIND>
+using FpLdsOf = typename FpLdsSel<KIND>::T;
 
 struct alignas(16) SpWaveLds {
     FpLdsT<2> fp;
@@ -525,34 +550,140 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
                                              FpLdsOf<KIND> &L, uint32_t *ring = nullptr)
 {
     constexpr bool SP = KIND == kPageSp;
-    constexpr uint32_t NR = SP ? 2u : 1u;  // rounds of records held
+    constexpr bool IN = KIND == kPageFpi;  // the paper's own page layout
+    constexpr bool WHOLE = SP || IN;       // one wavefront decodes the whole page
+    constexpr uint32_t NR = WHOLE ? 2u : 1u;  // rounds of records held
     const uint32_t lane = lane_id();
-    if (nwords < 4 || nb == 0 || nb > kFpBlocks || seg >= page_items<KIND>(nb))
+    if (nwords < (IN ? 4u : 4u) || nb == 0 || nb > kFpBlocks || seg >= page_items<KIND>(nb))
         return false;
+    const BufRsrc rpg = make_rsrc(page, nwords * 4u);
+    const bool kl = lane < 32;
     // SIMD-FastPFOR / FastPFOR: [nblocks, packed_words, meta_bytes, bitset]
     // + a count per non-empty array; SimplePFOR: [nblocks, packed_words,
-    // meta_bytes, Simple-8b words]
-    const uint32_t h_nb = uniform(page[0]), packed_words = uniform(page[1]), meta_bytes = uniform(page[2]),
-                   w3 = uniform(page[3]);
-    const uint32_t bitset = SP ? 0u : w3;
-    const uint32_t nset = __builtin_popcount(bitset);
+    // meta_bytes, Simple-8b words]; the paper's layout: word 0 = the byte
+    // array's counter, parsed below
+    uint32_t packed_words, meta_bytes, w3, bitset, hdr_w;
+    uint32_t cpos = 0, nba = 0, baw = 0;  // the paper's layout: counter word, byte array bytes and words
+    bool ba_lds = false;                  // the byte array is held in LDS
+    if constexpr (IN) {
+        cpos = uniform(page[0]);
+        if (cpos < 1 || cpos >= nwords || ((cpos - 1) & 3u))
+            return false;
+        nba = uniform(page[cpos]);
+        baw = (nba + 3u) / 4u;
+        if (nba > (3u + 127u) * nb || baw > nwords - cpos - 1u)
+            return false;
+        packed_words = cpos - 1u;
+        hdr_w = 1;
+        w3 = 0;
+        meta_bytes = 0;  // 3 nb + the page's exceptions, once parsed
+        ba_lds = baw <= kFpiBaWords;
+    } else {
+        const uint32_t h_nb = uniform(page[0]);
+        packed_words = uniform(page[1]);
+        meta_bytes = uniform(page[2]);
+        w3 = uniform(page[3]);
+        bitset = SP ? 0u : w3;
+        const uint32_t nset0 = __builtin_popcount(bitset);
+        hdr_w = pad4(4 + nset0 + (SP ? 0u : S * (page_items<KIND>(nb) - 1)));  // + the segment bases
+        const uint32_t meta_w0 = ((meta_bytes + 15u) / 16u) * 4u;
+        if (h_nb != nb || hdr_w > nwords || packed_words > nwords - hdr_w || meta_bytes < 3 * nb ||
+            meta_bytes > 3 * nb + 127 * nb || meta_w0 > nwords - hdr_w - packed_words || (packed_words & 3u))
+            return false;
+    }
+    const uint32_t nset = IN ? 0u : (uint32_t)__builtin_popcount(bitset);
     const uint32_t nseg = page_items<KIND>(nb);
-    const uint32_t hdr_w = pad4(4 + nset + (SP ? 0u : S * (nseg - 1)));  // + the segment bases
     const uint32_t meta_w = ((meta_bytes + 15u) / 16u) * 4u;
-    if (h_nb != nb || hdr_w > nwords || packed_words > nwords - hdr_w || meta_bytes < 3 * nb ||
-        meta_bytes > 3 * nb + 127 * nb || meta_w > nwords - hdr_w - packed_words || (packed_words & 3u))
-        return false;
     const uint32_t meta_at = (hdr_w + packed_words) * 4u;  // byte offset of the metadata
     const uint32_t pos_at = meta_at + 3u * nb;             // byte offset of the positions
     const uint32_t exc_at = hdr_w + packed_words + meta_w;
-    const BufRsrc rpg = make_rsrc(page, nwords * 4u);
-    const bool kl = lane < 32;
+    const uint32_t ba_at = (cpos + 1u) * 4u;               // the paper's layout: byte offset of the byte array
+    // the paper's layout: byte o of the byte array (o < nba), from LDS or the page
+    auto ba_byte = [&](uint32_t o) __attribute__((always_inline)) -> uint32_t {
+        if constexpr (IN) {
+            if (ba_lds)
+                return reinterpret_cast<const uint8_t *>(L.ba)[o];
+            return buf_load_u8(rpg, ba_at + o);
+        }
+        return 0u;
+    };
+    if constexpr (IN) {
+        // the byte array into LDS (eight 4-byte loads per lane in flight),
+        // then walked record by record: b, maxb, and when maxb > b, c and
+        // the c positions; then the exception arrays, each behind its
+        // counter, one after the other behind the bitset
+        if (ba_lds) {
+            const BufRsrc rba = make_rsrc(page + cpos + 1, baw * 4u);
+            for (uint32_t i0 = 0; i0 < baw; i0 += 512u) {
+                uint32_t v[8];
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    v[r] = buf_load_u32(rba, (i0 + 64u * r + lane) * 4u);
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    if (i0 + 64u * r + lane < baw)
+                        L.ba[i0 + 64u * r + lane] = v[r];
+            }
+            wave_lds_order();
+        }
+        uint32_t o = 0, ne = 0, pk = 0;
+        bool pbad = false;
+        for (uint32_t t = 0; t < nb; ++t) {
+            const uint32_t b = uniform(o < nba ? ba_byte(o) : 255u);
+            const uint32_t mb = uniform(o + 1u < nba ? ba_byte(o + 1u) : 255u);
+            const uint32_t cc = uniform(o + 2u < nba ? ba_byte(o + 2u) : 0u);
+            const uint32_t c = mb > b ? cc : 0u;
+            pbad = pbad || b > 32u || mb > 32u || mb < b || (mb > b && (c == 0u || c >= kBlock)) ||
+                   o + 2u + (mb > b ? 1u + c : 0u) > nba;
+            if (pbad)
+                break;
+            if (lane == 0) {
+                L.bm[t] = b | (mb << 8) | (c << 16);
+                L.posoff[t] = o + 3u;
+            }
+            o += mb > b ? 3u + c : 2u;
+            ne += c;
+            pk += 4u * b;
+        }
+        if (pbad || o != nba || pk != packed_words)
+            return false;
+        meta_bytes = 3u * nb + ne;
+        uint32_t xp = cpos + 1u + baw;
+        if (xp >= nwords)
+            return false;
+        bitset = uniform(page[xp]);
+        ++xp;
+        for (uint32_t k = 1; k <= 32; ++k) {
+            uint32_t cnt = 0, at = 0;
+            if ((bitset >> (k - 1u)) & 1u) {
+                if (xp >= nwords)
+                    return false;
+                cnt = uniform(page[xp]);
+                const uint32_t words = ((cnt + 31u) / 32u) * k;
+                if (cnt == 0u || cnt > nb * kBlock || words > nwords - xp - 1u)
+                    return false;
+                at = xp + 1u;
+                xp += 1u + words;
+            }
+            if (lane == 0) {
+                L.kc[k] = cnt;
+                L.excb[k] = at;
+            }
+        }
+        if (pad4(xp) != nwords)
+            return false;
+        if (lane == 32)
+            L.excb[0] = 0, L.kc[0] = 0;
+        if (lane < 33)
+            L.kcar[lane] = 0;
+        wave_lds_order();
+    }
     // the segment: blocks [blk0, blk1)
-    const uint32_t blk0 = SP ? 0u : seg * kSegBlocks;
-    const uint32_t blk1 = SP ? nb : (nb - blk0 < kSegBlocks ? nb : blk0 + kSegBlocks);
+    const uint32_t blk0 = WHOLE ? 0u : seg * kSegBlocks;
+    const uint32_t blk1 = WHOLE ? nb : (nb - blk0 < kSegBlocks ? nb : blk0 + kSegBlocks);
     const bool last_seg = seg + 1 == nseg;
     uint32_t carry[4] = {ubase[0], ubase[1], ubase[2], ubase[3]};
-    if constexpr (!SP && S > 0) {
+    if constexpr (!WHOLE && S > 0) {
         if (seg > 0) {
             // segment bases follow the counts; inside the validated header
             const uint32_t *const sb = page + 4 + nset + S * (seg - 1);
@@ -562,7 +693,9 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
         }
     }
     uint32_t kcnt = 0;
-    if constexpr (SP) {
+    if constexpr (IN) {
+        kcnt = kl ? L.kc[lane + 1] : 0u;
+    } else if constexpr (SP) {
         // the Simple-8b words run to the page end (zero-padded to 4 words)
         if ((w3 & 1u) || w3 > nwords - exc_at || pad4(exc_at + w3) != nwords)
             return false;
@@ -588,7 +721,7 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
 
     bool bad = false;  // per lane, reduced at the end
     uint32_t pk_run = 0, pos_run = 0;
-    if constexpr (!SP) {
+    if constexpr (!WHOLE) {
         // the earlier segments' blocks (all full rounds of 64): packed words,
         // positions and, per array k, exceptions before this segment
         if (seg > 0) {
@@ -619,6 +752,13 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
     auto load_meta = [&](uint32_t r, uint32_t &mb_, uint32_t &mm_, uint32_t &mc_) __attribute__((always_inline)) {
         const uint32_t jj = blk0 + 64u * r + lane;
         const bool own = jj < blk1;
+        if constexpr (IN) {
+            const uint32_t v = own ? L.bm[jj] : 0u;
+            mb_ = v & 255u;
+            mm_ = (v >> 8) & 255u;
+            mc_ = v >> 16;
+            return;
+        }
         mb_ = buf_load_u8(rpg, own ? meta_at + jj : kOutOfRange);
         mm_ = buf_load_u8(rpg, own ? meta_at + nb + jj : kOutOfRange);
         mc_ = buf_load_u8(rpg, own ? meta_at + 2u * nb + jj : kOutOfRange);
@@ -662,8 +802,8 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
     load_meta(0, m0, m1, m2);
     build_round(0, m0, m1, m2);
     // a segment of a FastPFOR page is one round: its packed words end here
-    const uint32_t yX = SP ? packed_words : pk_run;
-    if constexpr (SP) {
+    const uint32_t yX = WHOLE ? packed_words : pk_run;
+    if constexpr (WHOLE) {
         load_meta(1, m0, m1, m2);
         build_round(1, m0, m1, m2);
         load_meta(2, m0, m1, m2);
@@ -685,7 +825,7 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
     // loads, so that the passes find those lines in the L2 cache. The data
     // is only folded into a register that an empty asm statement consumes.
     uint4 pf[3];
-    if constexpr (!SP) {
+    if constexpr (!WHOLE) {
         const uint32_t ex_w = nwords - exc_at, share = (ex_w + nseg - 1) / nseg;
         const uint32_t pf_at = (exc_at + seg * share) * 4u;
         pf[0] = buf_load_u4(rpg, pf_at + lane * 16u);
@@ -783,7 +923,10 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
         const uint32_t k = (re.x >> 8) & 255u;
         const uint32_t idx = wA + lane - re.w;
         const bool any = lane < f.ce;
-        f.pos = buf_load_u8(rpg, any ? pos_at + wA + lane : kOutOfRange);
+        if constexpr (IN)
+            f.pos = any ? ba_byte(L.posoff[blk0 + 4u * q + j] + idx) : 0u;
+        else
+            f.pos = buf_load_u8(rpg, any ? pos_at + wA + lane : kOutOfRange);
         uint32_t bit = 0;
         if constexpr (SP) {
             s8_fill(wA + f.ce, keep, false);
@@ -843,8 +986,15 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
                     const uint4 re = R[j];
                     const uint32_t k = (re.x >> 8) & 255u, b = re.x & 31u;
                     const uint32_t idx = wA + e - re.w;
-                    const uint32_t pos = buf_load_u8(rpg, pos_at + wA + e);
-                    const uint32_t pprev = idx > 0u ? buf_load_u8(rpg, pos_at + wA + e - 1u) : 0u;
+                    uint32_t pos, pprev;
+                    if constexpr (IN) {
+                        const uint32_t po = L.posoff[blk0 + 4u * p + j] + idx;
+                        pos = ba_byte(po);
+                        pprev = idx > 0u ? ba_byte(po - 1u) : 0u;
+                    } else {
+                        pos = buf_load_u8(rpg, pos_at + wA + e);
+                        pprev = idx > 0u ? buf_load_u8(rpg, pos_at + wA + e - 1u) : 0u;
+                    }
                     bad = bad || pos >= kBlock || (idx > 0u && pprev >= pos);
                     uint32_t hv;
                     if constexpr (SP) {
@@ -908,7 +1058,7 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
         run_pass(p, f0);
         if (p + 1 < npass)
             run_pass(p + 1, f1);
-        if constexpr (!SP) {
+        if constexpr (!WHOLE) {
             if (p == 2) {
                 uint32_t t = 0;
 #pragma unroll

@@ -866,6 +866,21 @@ __global__ __launch_bounds__(128) void k_finish(const uint32_t *__restrict__ x, 
     } while (0)
 #define WP_UNPAREN(...) __VA_ARGS__
 
+// Scratch bytes an encode call of `codec` over n integers uses: scan
+// status, unit sizes, per-block metadata.
+static uint64_t encode_scratch_bytes(int codec, uint64_t n)
+{
+    const bool paged = codec == WP_CODEC_FP || codec == WP_CODEC_FP32 || codec == WP_CODEC_SP;
+    const uint64_t per = paged ? kFpBlocks : kBpBlocks;
+    const uint64_t units = (n / kBlock + per - 1) / per;
+    const uint64_t nblk = units * per;
+    const uint64_t meta_off = scan_status_words(units) * 8 + ((units * 4 + 255) & ~255ull);
+    const uint64_t meta_len = (codec == WP_CODEC_BP || codec == WP_CODEC_BPV) ? nblk
+                              : codec == WP_CODEC_BP32                      ? 4 * nblk
+                                                                            : 3 * nblk;
+    return meta_off + meta_len + 256;
+}
+
 static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t stride, uint32_t *out,
                              uint64_t cap, uint64_t *out_words, void *stream)
 {
@@ -893,10 +908,7 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
     const uint64_t sizes_off = status_words * 8;
     const uint64_t meta_off = sizes_off + ((units * 4 + 255) & ~255ull);
     const uint64_t nblk = units * per;
-    const uint64_t meta_len = (codec == WP_CODEC_BP || codec == WP_CODEC_BPV) ? nblk
-                              : codec == WP_CODEC_BP32                      ? 4 * nblk
-                                                                            : 3 * nblk;
-    char *scr = static_cast<char *>(stream_scratch(st, meta_off + meta_len + 256));
+    char *scr = static_cast<char *>(stream_scratch(st, encode_scratch_bytes(codec, n)));
     if (scr == nullptr)
         return WP_ERR_HIP;
     uint64_t *status = reinterpret_cast<uint64_t *>(scr);
@@ -979,4 +991,43 @@ extern "C" int32_t simplepfor_encode(const uint32_t *in, uint64_t n, int32_t del
                                      uint64_t out_cap_words, uint64_t *out_words, void *stream)
 {
     return encode_common(WP_CODEC_SP, in, n, delta_stride, out, out_cap_words, out_words, stream);
+}
+
+extern "C" int32_t fastpfor_inline_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,
+                                          uint64_t out_cap_words, uint64_t *out_words, void *stream)
+{
+    if (delta_stride != 0 && delta_stride != 1 && delta_stride != 4)
+        return WP_ERR_INVALID_ARG;
+    if (out == nullptr || out_words == nullptr || (n > 0 && in == nullptr))
+        return WP_ERR_INVALID_ARG;
+    if (!aligned16(out) || (reinterpret_cast<uintptr_t>(in) & 3u) || (reinterpret_cast<uintptr_t>(out_words) & 7u))
+        return WP_ERR_INVALID_ARG;
+    const uint64_t need = wp_max_compressed_words(WP_CODEC_FPI, n);
+    const uint64_t tmp_words = wp_max_compressed_words(WP_CODEC_FP32, n);
+    if (need == 0 || tmp_words == 0)
+        return WP_ERR_INVALID_ARG;
+    if (out_cap_words < need)
+        return WP_ERR_CAPACITY;
+    const uint64_t units = (n / kBlock + kFpBlocks - 1) / kFpBlocks;
+    const uint64_t E = 1 + (uint64_t)delta_stride;
+    const uint64_t ndir = units + ((n % kBlock) ? 1 : 0);
+    const uint32_t dir_end = (uint32_t)(kHdrWords + ((E * ndir + 3) & ~3ull));
+    hipStream_t st = as_stream(stream);
+    // scratch: the FastPFOR encoder's own | the FastPFOR stream | page sizes
+    // | scan status | the FastPFOR stream's length
+    const uint64_t common = (encode_scratch_bytes(WP_CODEC_FP32, n) + 255) & ~255ull;
+    const uint64_t tmp_off = common;
+    const uint64_t sizes_off = tmp_off + ((tmp_words * 4 + 255) & ~255ull);
+    const uint64_t status_off = sizes_off + ((units * 4 + 255) & ~255ull);
+    const uint64_t len_off = status_off + scan_status_words(units) * 8;
+    char *scr = static_cast<char *>(stream_scratch(st, len_off + 256));
+    if (scr == nullptr)
+        return WP_ERR_HIP;
+    uint32_t *tmp = reinterpret_cast<uint32_t *>(scr + tmp_off);
+    const int32_t rc = encode_common(WP_CODEC_FP32, in, n, delta_stride, tmp, tmp_words,
+                                     reinterpret_cast<uint64_t *>(scr + len_off), stream);
+    if (rc != WP_OK)
+        return rc;
+    return fpi_encode_pages(tmp, units, dir_end, reinterpret_cast<uint32_t *>(scr + sizes_off),
+                            reinterpret_cast<uint64_t *>(scr + status_off), out, out_words, st);
 }

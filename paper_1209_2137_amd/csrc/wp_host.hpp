@@ -57,6 +57,12 @@ int32_t sp_encode_units(const uint32_t *in, uint64_t n, uint32_t stride, uint64_
                         uint64_t nblk, uint32_t *sizes, uint64_t *status, uint32_t dir_end, uint32_t *out,
                         hipStream_t st);
 
+// Rearranges the FastPFOR stream `tmp` (arrays padded to 32) into pages of
+// the paper's own layout in `out`: page sizes, their chained scan, the
+// pages, then header, directory and tail; the length goes to out_words.
+int32_t fpi_encode_pages(const uint32_t *tmp, uint64_t units, uint32_t dir_end, uint32_t *sizes, uint64_t *status,
+                         uint32_t *out, uint64_t *out_words, hipStream_t st);
+
 // Events the calling thread's next decoder launch records when its main
 // kernel starts and ends (set by wp_time_next_launch); taking them clears
 // them.
