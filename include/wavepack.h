@@ -342,9 +342,11 @@ const char *wp_strerror(int32_t code);
  * counterpart of decoding many posting lists). A plan turns a list
  * registry into work items -- 64-block segments of patched pages, runs of
  * meta-blocks and tails of lists without full blocks -- and one kernel
- * launch covers them all, a wavefront for each item, largest first (the
- * hardware dispatcher balances the load; there is no work queue). The
- * item holding a list's last unit also decodes the list's tail. */
+ * launch covers them all, a wavefront for each item, largest first: by
+ * default a grid of one wavefront per item (the hardware dispatcher
+ * balances the load), or, with wp_tune.wg_per_cu > 0, a persistent grid
+ * whose wavefronts pull the items from a work queue (a device counter).
+ * The item holding a list's last unit also decodes the list's tail. */
 
 typedef struct wp_list {
     uint64_t comp_off_words; /* stream start, in words from `pool` (multiple of 4) */
@@ -363,7 +365,11 @@ typedef struct wp_tune {
     int32_t vpl;       /* integers per lane and pass: 4 (0 = 4) */
     int32_t depth;     /* binary packing: 16-byte loads per lane in flight, 2, 3 or 4 (0 = 2) */
     int32_t run_units; /* meta-blocks per binary-packing work item (one wavefront), 1..63 (0 = 8) */
-    int32_t wg_per_cu; /* ignored by batched decoding (0..64 accepted) */
+    int32_t wg_per_cu; /* 0: one workgroup per `waves` items (the one-shot grid);
+                          1..64: the persistent form, wg_per_cu workgroups per
+                          compute unit whose wavefronts take items from a
+                          device counter (cleared by a kernel launched, or a
+                          graph node placed, before the decoder) */
     int32_t use_graph; /* 1 = replay a hipGraph built at plan time, 0 = plain launches */
 } wp_tune;
 

@@ -6,8 +6,9 @@ Knobs:
   depth      binary packing: 16-byte loads in flight per lane, which also
              sizes each wavefront's LDS ring (2 or 3: 4 KB, 4: 8 KB)
   wg_per_cu  single list, binary packing (SIMD-BP128 and BP32, each its
-             own shape): runs (one per wavefront) per compute unit
-             (batched decoding ignores it)
+             own shape): runs (one per wavefront) per compute unit;
+             batched decoding: 0 = one-shot grid, > 0 = persistent
+             workgroups per compute unit pulling items from a work queue
   run_units  batched decoding: meta-blocks per work item
 
 Each candidate is timed with HIP events (median of `steps` launches after
@@ -30,7 +31,8 @@ BP_SINGLE = [dict(waves=w, vpl=4, depth=d, wg_per_cu=c)
 FP_SINGLE = [dict(waves=w, vpl=4) for w in (1, 2, 4, 8)]
 BP32_SINGLE = [dict(waves=w, vpl=4, depth=d, wg_per_cu=c) for w in (2, 4, 8) for d in (2, 3) for c in (56, 128, 256)]
 BATCH = [dict(waves=w, vpl=4, depth=d, run_units=r, wg_per_cu=0, use_graph=1)
-         for w in (2, 4, 8) for d in (2, 3) for r in (4, 8, 16)]
+         for w in (2, 4, 8) for d in (2, 3) for r in (4, 8, 16)] + \
+        [dict(waves=4, vpl=4, depth=2, run_units=r, wg_per_cu=c, use_graph=1) for r in (4, 8) for c in (4, 8)]
 
 
 def load(path: str = TUNING_PATH) -> dict:

@@ -114,6 +114,47 @@ __global__ __launch_bounds__(64 * WAVES) void k_batch(const DevList *__restrict_
         *err = kErrCorrupt;
 }
 
+// The persistent form: a grid sized to the chip (wg_per_cu workgroups per
+// compute unit) whose wavefronts take items, largest first, from a device
+// counter until none is left, kQueueChunk consecutive items per atomic
+// (one device-scope atomic per item serialises on the counter's address);
+// the counter is cleared by a small kernel launched before it (a graph
+// holds both nodes).
+constexpr uint32_t kQueueChunk = 8;
+template <int WAVES, int DEPTH>
+__global__ __launch_bounds__(64 * WAVES) void k_batch_queue(const DevList *__restrict__ lists,
+                                                            const uint4 *__restrict__ items, uint32_t nitems,
+                                                            int *__restrict__ err, uint32_t *__restrict__ next)
+{
+    __shared__ WaveItemLds<DEPTH> L[WAVES];
+    const uint32_t wave = uniform(threadIdx.x >> 6);
+    uint32_t it = 0;
+    if (lane_id() == 0)
+        it = atomicAdd(next, kQueueChunk);
+    it = uniform(it);
+    // every wavefront leaves once the counter has passed the items
+    while (it < nitems) {
+        // the next chunk's first index is taken now; its round trip overlaps
+        // this chunk
+        uint32_t nx = 0;
+        if (lane_id() == 0)
+            nx = atomicAdd(next, kQueueChunk);
+        const uint32_t end = nitems - it < kQueueChunk ? nitems : it + kQueueChunk;
+        for (; it < end; ++it) {
+            if (!wave_item<DEPTH>(lists, items, it, L[wave]) && lane_id() == 0)
+                *err = kErrCorrupt;
+            wave_lds_order();
+        }
+        it = uniform(nx);
+    }
+}
+
+__global__ void k_batch_reset(uint32_t *next)
+{
+    if (threadIdx.x == 0)
+        *next = 0;
+}
+
 struct Plan {
     int device = -1;
     DevList *d_lists = nullptr;
@@ -133,31 +174,34 @@ struct Plan {
     uint64_t pin_lists = 0, pin_items = 0;
     hipEvent_t copied = nullptr;
     int run_units = 8;
+    int wg_per_cu = 0;          // > 0: the persistent form, this many workgroups per compute unit
+    uint32_t *counter = nullptr;  // its item counter
 };
 
 template <int W, int D>
-static const void *batch_kernel()
+static const void *batch_kernel(bool queue)
 {
-    return reinterpret_cast<const void *>(&k_batch<W, D>);
+    return queue ? reinterpret_cast<const void *>(&k_batch_queue<W, D>) : reinterpret_cast<const void *>(&k_batch<W, D>);
 }
 
 template <int W>
-static const void *batch_kernel_depth(int depth)
+static const void *batch_kernel_depth(int depth, bool queue)
 {
-    return depth == 2 ? batch_kernel<W, 2>() : depth == 3 ? batch_kernel<W, 3>() : batch_kernel<W, 4>();
+    return depth == 2 ? batch_kernel<W, 2>(queue) : depth == 3 ? batch_kernel<W, 3>(queue) : batch_kernel<W, 4>(queue);
 }
 
-// waves 2, 4 or 8 (vpl 4), each with ring depth 2..4
-static const void *pick_kernel(int waves, int vpl, int depth)
+// waves 2, 4 or 8 (vpl 4), each with ring depth 2..4; the one-shot grid or
+// the persistent form
+static const void *pick_kernel(int waves, int vpl, int depth, bool queue)
 {
     if (depth < 2 || depth > 4 || vpl != 4)
         return nullptr;
     if (waves == 2)
-        return batch_kernel_depth<2>(depth);
+        return batch_kernel_depth<2>(depth, queue);
     if (waves == 4)
-        return batch_kernel_depth<4>(depth);
+        return batch_kernel_depth<4>(depth, queue);
     if (waves == 8)
-        return batch_kernel_depth<8>(depth);
+        return batch_kernel_depth<8>(depth, queue);
     return nullptr;
 }
 
@@ -177,6 +221,8 @@ static void release(Plan *p)
         (void)hipFree(p->d_lists);
     if (p->d_items)
         (void)hipFree(p->d_items);
+    if (p->counter)
+        (void)hipFree(p->counter);
     delete p;
 }
 
@@ -187,12 +233,26 @@ static uint64_t grid_for(uint64_t nitems, int waves)
 }
 constexpr uint64_t kMaxGrid = 0x7FFFFFFFull;
 
+// Workgroups of the persistent form.
+static uint32_t queue_grid(const Plan *p, int cus)
+{
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)cus * (uint64_t)p->wg_per_cu,
+                                                               grid_for(p->nitems, p->waves)));
+}
+
 static int32_t launch_plan(Plan *p, hipStream_t st)
 {
     (void)hipGetLastError();
     if (p->nitems == 0)
         return WP_OK;
     uint32_t nitems32 = (uint32_t)p->nitems;
+    if (p->wg_per_cu > 0) {
+        hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, st, p->counter);
+        void *qargs[] = {&p->d_lists, &p->d_items, &nitems32, &p->err, &p->counter};
+        if (hipLaunchKernel(p->kernel, dim3(p->grid), dim3(64 * p->waves), qargs, 0, st) != hipSuccess)
+            return WP_ERR_HIP;
+        return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
+    }
     void *args[] = {&p->d_lists, &p->d_items, &nitems32, &p->err};
     if (hipLaunchKernel(p->kernel, dim3(p->grid), dim3(64 * p->waves), args, 0, st) != hipSuccess)
         return WP_ERR_HIP;
@@ -203,17 +263,29 @@ static int32_t build_graph(Plan *p)
 {
     if (hipGraphCreate(&p->graph, 0) != hipSuccess)
         return WP_ERR_HIP;
-    hipGraphNode_t dec = nullptr;
+    hipGraphNode_t dec = nullptr, reset = nullptr;
     uint32_t nitems32 = (uint32_t)p->nitems;
-    void *args[] = {&p->d_lists, &p->d_items, &nitems32, &p->err};
+    void *args[] = {&p->d_lists, &p->d_items, &nitems32, &p->err, &p->counter};
+    if (p->wg_per_cu > 0) {
+        // the counter is cleared by a kernel node (no memset node), then the decoder
+        void *rargs[] = {&p->counter};
+        hipKernelNodeParams rp = {};
+        rp.func = reinterpret_cast<void *>(&k_batch_reset);
+        rp.gridDim = dim3(1);
+        rp.blockDim = dim3(64);
+        rp.kernelParams = rargs;
+        if (hipGraphAddKernelNode(&reset, p->graph, nullptr, 0, &rp) != hipSuccess)
+            return WP_ERR_HIP;
+    }
+    void *args4[] = {&p->d_lists, &p->d_items, &nitems32, &p->err};
     hipKernelNodeParams kp = {};
     kp.func = const_cast<void *>(p->kernel);
     kp.gridDim = dim3(p->grid);
     kp.blockDim = dim3(64 * p->waves);
     kp.sharedMemBytes = 0;
-    kp.kernelParams = args;
+    kp.kernelParams = p->wg_per_cu > 0 ? args : args4;
     kp.extra = nullptr;
-    if (hipGraphAddKernelNode(&dec, p->graph, nullptr, 0, &kp) != hipSuccess)
+    if (hipGraphAddKernelNode(&dec, p->graph, reset ? &reset : nullptr, reset ? 1 : 0, &kp) != hipSuccess)
         return WP_ERR_HIP;
     if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
         return WP_ERR_HIP;
@@ -300,7 +372,7 @@ extern "C" int32_t wp_batch_plan(const uint32_t *pool, uint32_t *out_base, const
         if (t.run_units == 0)
             t.run_units = 8;
     }
-    const void *kern = pick_kernel(t.waves, t.vpl, t.depth);
+    const void *kern = pick_kernel(t.waves, t.vpl, t.depth, t.wg_per_cu > 0);
     if (kern == nullptr || t.run_units < 1 || t.run_units > 63 || t.wg_per_cu < 0 || t.wg_per_cu > 64)
         return WP_ERR_INVALID_ARG;
     DevState *ds = dev_state();
@@ -322,10 +394,15 @@ extern "C" int32_t wp_batch_plan(const uint32_t *pool, uint32_t *out_base, const
     p->kernel = kern;
     p->use_graph = t.use_graph != 0;
     p->run_units = t.run_units;
+    p->wg_per_cu = t.wg_per_cu;
     p->cap_lists = std::max<uint64_t>(1, lists.size());
     p->cap_items = std::max<uint64_t>(1, items.size());
-    p->grid = (uint32_t)grid_for(items.size(), t.waves);
+    p->grid = p->wg_per_cu > 0 ? queue_grid(p, ds->cus) : (uint32_t)grid_for(items.size(), t.waves);
     hipStream_t st = as_stream(stream);
+    if (p->wg_per_cu > 0 && hipMalloc(&p->counter, 256) != hipSuccess) {
+        release(p);
+        return WP_ERR_HIP;
+    }
     if (hipMalloc(&p->d_lists, std::max<size_t>(1, lists.size()) * sizeof(DevList)) != hipSuccess ||
         hipMalloc(&p->d_items, std::max<size_t>(1, items.size()) * sizeof(uint4)) != hipSuccess) {
         release(p);
@@ -455,7 +532,14 @@ extern "C" int32_t wp_batch_replan(void *h_plan, const uint32_t *pool, uint32_t 
         return WP_ERR_HIP;
     p->nlists = lists.size();
     p->nitems = items.size();
-    p->grid = (uint32_t)grid_for(items.size(), p->waves);
+    if (p->wg_per_cu > 0) {
+        DevState *ds = dev_state();
+        if (ds == nullptr)
+            return WP_ERR_HIP;
+        p->grid = queue_grid(p, ds->cus);
+    } else {
+        p->grid = (uint32_t)grid_for(items.size(), p->waves);
+    }
     // the graph baked in the old item count and grid
     if (p->exec)
         (void)hipGraphExecDestroy(p->exec), p->exec = nullptr;
