@@ -492,7 +492,9 @@ def prepare_inputs(d):
     for name, x, codec in (("bp_cluster_2e26", cluster, wp.CODEC_BP), ("fp_patched_2e28", patched, wp.CODEC_FP),
                            ("bp32_cluster_2e26", cluster, wp.CODEC_BP32),
                            ("bpv_cluster_2e26", cluster, wp.CODEC_BPV),
-                           ("fp32_patched_2e28", patched, wp.CODEC_FP32)):
+                           ("fp32_patched_2e28", patched, wp.CODEC_FP32),
+                           ("sp_patched_2e28", patched, wp.CODEC_SP),
+                           ("fpi_patched_2e28", patched, wp.CODEC_FPI)):
         comp = wp.encode_trimmed(to_dev(x), codec, 1)
         np.save(os.path.join(d, name + ".npy"), comp.cpu().numpy())
         np.save(os.path.join(d, name + ".n.npy"), np.array([x.size], dtype=np.int64))
@@ -519,9 +521,10 @@ def profile_batch(wp, steps, pool):
 
 def profile_variants(steps, inputs):
     """For rocprofv3: the variant codecs' decoders (BP32 and the four-lane
-    SIMD-BP128 layout on the 2^26 cluster list, FastPFOR with 32-value
-    padding on the 2^28 patched list) `steps` times each, from the streams
-    that --prepare-inputs saved."""
+    SIMD-BP128 layout on the 2^26 cluster list; FastPFOR with 32-value
+    padding, SimplePFOR and FastPFOR pages in the paper's own layout on the
+    2^28 patched list) `steps` times each, from the streams that
+    --prepare-inputs saved."""
     import numpy as np
     import torch
     import paper_1209_2137_amd as wp
@@ -531,7 +534,8 @@ def profile_variants(steps, inputs):
     wp.lib()
     res = {}
     for name, codec in (("bp32_cluster_2e26", wp.CODEC_BP32), ("bpv_cluster_2e26", wp.CODEC_BPV),
-                        ("fp32_patched_2e28", wp.CODEC_FP32)):
+                        ("fp32_patched_2e28", wp.CODEC_FP32), ("sp_patched_2e28", wp.CODEC_SP),
+                        ("fpi_patched_2e28", wp.CODEC_FPI)):
         comp = torch.from_numpy(np.load(os.path.join(inputs, name + ".npy"))).to("cuda")
         n = int(np.load(os.path.join(inputs, name + ".n.npy"))[0])
         r = bench_single(wp, None, codec, 1, steps, 2, name, comp=comp, n=n)
