@@ -330,14 +330,15 @@ def test_appendix_a_bound_on_sorted_distinct_arrays():
 # ---------------------------------------------------------------- round trips
 
 _ENC = {"bp": oracle.bp_encode, "fp": oracle.fp_encode, "bp32": oracle.bp32_encode, "fp32": oracle.fp32_encode,
-        "bpv": oracle.bpv_encode}
+        "bpv": oracle.bpv_encode, "sp": oracle.sp_encode, "fpi": oracle.fpi_encode}
 _DEC = {"bp": oracle.bp_decode, "fp": oracle.fp_decode, "bp32": oracle.bp32_decode, "fp32": oracle.fp32_decode,
-        "bpv": oracle.bpv_decode}
+        "bpv": oracle.bpv_decode, "sp": oracle.sp_decode, "fpi": oracle.fpi_decode}
 _RC = {"bp": oracle.bp_decode_rc, "fp": oracle.fp_decode_rc, "bp32": oracle.bp32_decode_rc,
-       "fp32": oracle.fp32_decode_rc, "bpv": oracle.bpv_decode_rc}
+       "fp32": oracle.fp32_decode_rc, "bpv": oracle.bpv_decode_rc, "sp": oracle.sp_decode_rc,
+       "fpi": oracle.fpi_decode_rc}
 
 
-@pytest.mark.parametrize("codec", ["bp", "fp", "bp32", "fp32", "bpv"])
+@pytest.mark.parametrize("codec", ["bp", "fp", "bp32", "fp32", "bpv", "sp", "fpi"])
 @pytest.mark.parametrize("stride", [0, 1, 4])
 def test_roundtrip_every_small_length(codec, stride):
     enc, dec = _ENC[codec], _DEC[codec]
