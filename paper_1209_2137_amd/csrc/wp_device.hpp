@@ -553,6 +553,7 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
     constexpr bool IN = KIND == kPageFpi;  // the paper's own page layout
     constexpr bool WHOLE = SP || IN;       // one wavefront decodes the whole page
     constexpr uint32_t NR = WHOLE ? 2u : 1u;  // rounds of records held
+    static_assert(sizeof(L.rec) / sizeof(L.rec[0]) >= NR, "the LDS record area holds every round in use");
     const uint32_t lane = lane_id();
     if (nwords < (IN ? 4u : 4u) || nb == 0 || nb > kFpBlocks || seg >= page_items<KIND>(nb))
         return false;
@@ -692,6 +693,54 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
                 carry[t] = uniform(sb[t]);
         }
     }
+    // relative round r of the segment: blocks blk0 + 64 r + lane
+    auto load_meta = [&](uint32_t r, uint32_t &mb_, uint32_t &mm_, uint32_t &mc_) __attribute__((always_inline)) {
+        const uint32_t jj = blk0 + 64u * r + lane;
+        const bool own = jj < blk1;
+        if constexpr (IN) {
+            const uint32_t v = own ? L.bm[jj] : 0u;
+            mb_ = v & 255u;
+            mm_ = (v >> 8) & 255u;
+            mc_ = v >> 16;
+            return;
+        }
+        mb_ = buf_load_u8(rpg, own ? meta_at + jj : kOutOfRange);
+        mm_ = buf_load_u8(rpg, own ? meta_at + nb + jj : kOutOfRange);
+        mc_ = buf_load_u8(rpg, own ? meta_at + 2u * nb + jj : kOutOfRange);
+    };
+    // A segment's setup is a chain of dependent reads; every read that
+    // needs only the header is issued here at once: the earlier segments'
+    // metadata bytes, this segment's, and the L2 prefetch of its share of
+    // the exception arrays (below).
+    uint32_t m0 = 0, m1 = 0, m2 = 0;
+    uint32_t eb[kPageSegs - 1], em[kPageSegs - 1], ec[kPageSegs - 1];
+    uint4 pf[3];
+    if constexpr (!WHOLE) {
+        if (seg > 0) {
+#pragma unroll
+            for (uint32_t r = 0; r + 1 < kPageSegs; ++r) {
+                const uint32_t jj = 64u * r + lane;
+                const bool own = r < seg;
+                eb[r] = buf_load_u8(rpg, own ? meta_at + jj : kOutOfRange);
+                em[r] = buf_load_u8(rpg, own ? meta_at + nb + jj : kOutOfRange);
+                ec[r] = buf_load_u8(rpg, own ? meta_at + 2u * nb + jj : kOutOfRange);
+            }
+        }
+        load_meta(0, m0, m1, m2);
+        // The exceptions' high parts and positions are read a few bytes per
+        // pass from up to 32 arrays; fetched that way from HBM, between the
+        // other wavefronts' stores, each read would be a small scattered
+        // one. Instead each segment first reads its share of the page's
+        // exception arrays (an equal part for each of the page's segments,
+        // all of them decoded side by side) and its own positions with
+        // contiguous 16-byte loads, so that the passes find those lines in
+        // the L2 cache. The data is only folded into a register that an
+        // empty asm statement consumes.
+        const uint32_t ex_w = nwords - exc_at, share = (ex_w + nseg - 1) / nseg;
+        const uint32_t pf_at = (exc_at + seg * share) * 4u;
+        pf[0] = buf_load_u4(rpg, pf_at + lane * 16u);
+        pf[1] = buf_load_u4(rpg, pf_at + 1024u + lane * 16u);
+    }
     uint32_t kcnt = 0;
     if constexpr (IN) {
         kcnt = kl ? L.kc[lane + 1] : 0u;
@@ -725,15 +774,6 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
         // the earlier segments' blocks (all full rounds of 64): packed words,
         // positions and, per array k, exceptions before this segment
         if (seg > 0) {
-            uint32_t eb[kPageSegs - 1], em[kPageSegs - 1], ec[kPageSegs - 1];
-#pragma unroll
-            for (uint32_t r = 0; r + 1 < kPageSegs; ++r) {
-                const uint32_t jj = 64u * r + lane;
-                const bool own = r < seg;
-                eb[r] = buf_load_u8(rpg, own ? meta_at + jj : kOutOfRange);
-                em[r] = buf_load_u8(rpg, own ? meta_at + nb + jj : kOutOfRange);
-                ec[r] = buf_load_u8(rpg, own ? meta_at + 2u * nb + jj : kOutOfRange);
-            }
             uint32_t pk_l = 0, pos_l = 0;
 #pragma unroll
             for (uint32_t r = 0; r + 1 < kPageSegs; ++r) {
@@ -748,20 +788,20 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
             wave_lds_order();
         }
     }
-    // relative round r of the segment: blocks blk0 + 64 r + lane
-    auto load_meta = [&](uint32_t r, uint32_t &mb_, uint32_t &mm_, uint32_t &mc_) __attribute__((always_inline)) {
-        const uint32_t jj = blk0 + 64u * r + lane;
-        const bool own = jj < blk1;
-        if constexpr (IN) {
-            const uint32_t v = own ? L.bm[jj] : 0u;
-            mb_ = v & 255u;
-            mm_ = (v >> 8) & 255u;
-            mc_ = v >> 16;
-            return;
-        }
-        mb_ = buf_load_u8(rpg, own ? meta_at + jj : kOutOfRange);
-        mm_ = buf_load_u8(rpg, own ? meta_at + nb + jj : kOutOfRange);
-        mc_ = buf_load_u8(rpg, own ? meta_at + 2u * nb + jj : kOutOfRange);
+    // the segment's packed words [yS, yX) of the packed region stream
+    // through the ring (a SimplePFOR page's, all of them); words a corrupt
+    // stream would place past the packed region are not read
+    uint32_t yS = 0, wS = 0, yX = 0;  // the segment's first packed word and exception, its words' end
+    BufRsrc rsp = make_rsrc(page, 0u);
+    uint4 c0, c1;
+    auto issue_ring = [&]() __attribute__((always_inline)) {
+        const bool okx = yS <= yX && yX <= packed_words;
+        rsp = make_rsrc(page + hdr_w + (okx ? yS : 0u), okx ? 4u * (yX - yS) : 0u);
+        c0 = buf_load_u4(rsp, lane * 16u);
+        __builtin_amdgcn_sched_barrier(0);
+        c1 = buf_load_u4(rsp, (kFpCW + lane * 4u) * 4u);
+        if constexpr (!WHOLE)
+            pf[2] = buf_load_u4(rpg, ((pos_at + wS) & ~15u) + lane * 16u);
     };
     auto build_round = [&](uint32_t r, uint32_t bv, uint32_t mv, uint32_t cv) __attribute__((always_inline)) {
         // blocks past the segment read 0 for b, maxb and c
@@ -773,6 +813,12 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
         const uint32_t y = pk_run + iw - bw, w = pos_run + ip - cv;
         pk_run += wave_read(iw, 63);
         pos_run += wave_read(ip, 63);
+        if (!WHOLE && r == 0) {
+            // a segment of a FastPFOR page is one round: its packed words
+            // end here, and the ring's first loads go out before the ranks
+            yX = pk_run;
+            issue_ring();
+        }
         uint32_t z = 0;
         if constexpr (!SP) {
             const uint32_t kc = L.kcar[k];
@@ -797,40 +843,17 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
         wave_lds_order();
     };
     const uint32_t npass = (blk1 - blk0 + 3) / 4;
-    uint32_t m0, m1, m2;
-    const uint32_t yS = pk_run, wS = pos_run;  // the segment's first packed word and exception
-    load_meta(0, m0, m1, m2);
+    yS = pk_run;
+    wS = pos_run;
+    if constexpr (WHOLE)
+        load_meta(0, m0, m1, m2);
     build_round(0, m0, m1, m2);
-    // a segment of a FastPFOR page is one round: its packed words end here
-    const uint32_t yX = WHOLE ? packed_words : pk_run;
     if constexpr (WHOLE) {
         load_meta(1, m0, m1, m2);
         build_round(1, m0, m1, m2);
         load_meta(2, m0, m1, m2);
-    }
-    // the segment's packed words [yS, yX) of the packed region stream
-    // through the ring (a SimplePFOR page's, all of them); words a corrupt
-    // stream would place past the packed region are not read
-    const bool okx = yS <= yX && yX <= packed_words;
-    const BufRsrc rsp = make_rsrc(page + hdr_w + (okx ? yS : 0u), okx ? 4u * (yX - yS) : 0u);
-    uint4 c0 = buf_load_u4(rsp, lane * 16u);
-    __builtin_amdgcn_sched_barrier(0);
-    uint4 c1 = buf_load_u4(rsp, (kFpCW + lane * 4u) * 4u);
-    // The exceptions' high parts and positions are read a few bytes per
-    // pass from up to 32 arrays; fetched that way from HBM, between the
-    // other wavefronts' stores, each read would be a small scattered one.
-    // Instead each segment first reads its share of the page's exception
-    // arrays (an equal part for each of the page's segments, all of them
-    // decoded side by side) and its own positions with contiguous 16-byte
-    // loads, so that the passes find those lines in the L2 cache. The data
-    // is only folded into a register that an empty asm statement consumes.
-    uint4 pf[3];
-    if constexpr (!WHOLE) {
-        const uint32_t ex_w = nwords - exc_at, share = (ex_w + nseg - 1) / nseg;
-        const uint32_t pf_at = (exc_at + seg * share) * 4u;
-        pf[0] = buf_load_u4(rpg, pf_at + lane * 16u);
-        pf[1] = buf_load_u4(rpg, pf_at + 1024u + lane * 16u);
-        pf[2] = buf_load_u4(rpg, ((pos_at + wS) & ~15u) + lane * 16u);
+        yX = packed_words;
+        issue_ring();
     }
     uint32_t written = 0;  // words of the segment already in the ring
     // chunk c goes to the ring (and its mirror), the slot reloads chunk c + 2;
