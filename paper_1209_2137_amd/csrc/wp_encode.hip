@@ -1,7 +1,10 @@
-// Encoders: bp_encode, bp32_encode and fastpfor_encode, producing the
-// stream layout the decoders read (see wavepack.h).
+// Encoders: bp_encode, bp_vertical_encode, bp32_encode, fastpfor_encode
+// and fastpfor32_encode, producing the stream layout the decoders read (see
+// wavepack.h).
 //
-// Four stream-ordered launches:
+// SIMD-BP128 and its four-lane layout: one fused launch (k_bp_encode below)
+// that reads the input once, then the tail and header. The other codecs,
+// four stream-ordered launches:
 //   1. analyze: one workgroup per unit computes every block's width(s) and
 //      the unit's length in words;
 //   2. an in-place inclusive scan of the unit lengths (the chained scan of
@@ -16,6 +19,7 @@
 
 #include "wp_device.hpp"
 #include "wp_host.hpp"
+#include "wp_lookback.hpp"
 
 namespace wp {
 
@@ -121,94 +125,217 @@ __device__ __forceinline__ void unit_deltas8(const uint32_t *__restrict__ x, uin
     }
 }
 
-__global__ __launch_bounds__(256) void k_bp_analyze(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
-                                                    uint8_t *__restrict__ widths, uint32_t *__restrict__ sizes)
-{
-    __shared__ uint32_t s_b[kBpBlocks];
-    const uint64_t u = blockIdx.x;
-    const uint32_t tid = threadIdx.x;
-    const uint64_t nfull = n / kBlock;
-    uint32_t d[8];
-    unit_deltas8(x, u * kBpUnitInts, nfull * kBlock, S, d);
-    uint32_t o = 0;
-#pragma unroll
-    for (int r = 0; r < 8; ++r)
-        o |= d[r];
-    // OR over the block's 16 threads (one row of 16 lanes)
-#pragma unroll
-    for (int m = 1; m < 16; m <<= 1)
-        o |= (uint32_t)__shfl_xor((int)o, m, 64);
-    const uint64_t left = nfull - u * kBpBlocks;
-    const uint32_t nb = (uint32_t)(left < kBpBlocks ? left : kBpBlocks);
-    const uint32_t j = tid >> 4;
-    if ((tid & 15u) == 0)
-        s_b[j] = j < nb ? nbits(o) : 0u;
-    __syncthreads();
-    if (tid < kBpBlocks)
-        widths[u * kBpBlocks + tid] = (uint8_t)s_b[tid];
-    if (tid == 0) {
-        uint32_t sum = 0;
-        for (uint32_t jj = 0; jj < kBpBlocks; ++jj)
-            sum += s_b[jj];
-        sizes[u] = 4 + 4 * sum;
-    }
-}
+// ------------------------------------------------------------------------
+// Binary packing in one pass over the input (SIMD-BP128 and its four-lane
+// layout). A workgroup of 512 threads takes kEncTile consecutive
+// meta-blocks, its tile index from the launch's counter (so a tile's
+// predecessors always started first). Thread t of half h = t / 256 holds
+// integers 8 (t mod 256) .. +7 of meta-blocks kEncHalf h .. kEncHalf h +
+// kEncHalf - 1 in registers, all read at once; the widths give every
+// meta-block's length, the tile's total goes through the decoupled
+// look-back for the tile's offset in the stream, and each half then
+// assembles its meta-blocks one after the other in LDS (the descriptor,
+// then the blocks' words: byte stores, or fields OR-ed in by LDS atomics
+// for the four-lane layout) and writes them with 16-byte stores (unit
+// offsets are multiples of 4 words). The input is read once.
+// Tiles of 8 meta-blocks: the chained scan completes about 64 tiles per
+// device-scope round trip, which caps smaller tiles; larger ones hold more
+// registers per thread and leave fewer workgroups per compute unit to
+// overlap one tile's loads with another's look-back and writes.
+#ifndef WP_ENC_TILE
+#define WP_ENC_TILE 8
+#endif
+constexpr uint32_t kEncTile = WP_ENC_TILE;  // meta-blocks per workgroup
+constexpr uint32_t kEncHalf = kEncTile / 2;
+// LDS words for the tile's compressed stream (the tiles of compressible
+// lists fit; the others are assembled a meta-block per half at a time)
+constexpr uint32_t kEncLdsWords = 8192;
+static_assert(kEncLdsWords >= 2 * (4 + kBpUnitInts), "one meta-block per half");
+static_assert(kEncTile % 2 == 0 && kEncTile <= 64, "two halves; one look-back lane per meta-block");
 
-// The meta-block is assembled in LDS (descriptor, then the blocks' words,
-// fields OR-ed in by LDS atomics) and written with 16-byte stores: unit
-// offsets are multiples of 4 words.
 template <bool V>
-__global__ __launch_bounds__(256) void k_bp_pack(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
-                                                 const uint8_t *__restrict__ widths,
-                                                 const uint32_t *__restrict__ incl, uint32_t dir_end,
-                                                 uint32_t *__restrict__ out)
+__global__ __launch_bounds__(512, 4) void k_bp_encode(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
+                                                   uint64_t units, uint32_t dir_end, uint32_t *__restrict__ out,
+                                                   uint64_t *__restrict__ status, uint32_t *__restrict__ total)
 {
-    __shared__ __align__(16) uint32_t s_u[4 + kBpUnitInts];
-    __shared__ uint32_t s_b[kBpBlocks], s_off[kBpBlocks];
-    const uint64_t u = blockIdx.x;
+    __shared__ __align__(16) uint32_t s_u[kEncLdsWords];  // the tile's stream, or one meta-block per half
+    __shared__ uint32_t s_b[kEncTile][kBpBlocks];     // widths
+    __shared__ uint32_t s_boff[kEncTile][kBpBlocks];  // a block's first word in its meta-block
+    __shared__ uint32_t s_off[kEncTile + 1];          // a meta-block's first word in the tile
+    __shared__ uint32_t s_tile, s_pre;
     const uint32_t tid = threadIdx.x;
-    const uint64_t nfull = n / kBlock;
-    uint32_t d[8];
-    unit_deltas8(x, u * kBpUnitInts, nfull * kBlock, S, d);
-    // the widths into LDS once, then each block's offset from them (a loop
-    // over global loads here would chain up to 15 memory round trips)
-    if (tid < kBpBlocks)
-        s_b[tid] = widths[u * kBpBlocks + tid];
+    const uint32_t h = tid >> 8, t = tid & 255u;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform(tid >> 6);
+    if (tid == 0)
+        s_tile = (uint32_t)atomicAdd(reinterpret_cast<unsigned long long *>(status), 1ull);
     __syncthreads();
-    if (tid < kBpBlocks) {
-        uint32_t pre = 0;
-        for (uint32_t j = 0; j < tid; ++j)
-            pre += s_b[j];
-        s_off[tid] = 4 + 4 * pre;
+    const uint32_t tile = uniform(s_tile);
+    const uint64_t u0 = (uint64_t)tile * kEncTile;
+    const uint32_t nu = (uint32_t)(units - u0 < kEncTile ? units - u0 : kEncTile);
+    const uint64_t lim = (n / kBlock) * kBlock;  // full blocks only
+    // every load of the half's meta-blocks first: the thread's eight values
+    // and, for the wavefront's first lane, the four before them
+    uint32_t d[kEncHalf][8];
+    uint32_t pw[kEncHalf][4];  // uniform: the four values before the wavefront's first
+    const uint64_t i0w = 512ull * (wave & 3u);  // the wavefront's first integer in its meta-block
+    const uint32_t hw = uniform(h);
+#pragma unroll
+    for (uint32_t m = 0; m < kEncHalf; ++m) {
+        const uint64_t base = (u0 + kEncHalf * hw + m) * kBpUnitInts;
+        const uint64_t have = lim > base ? lim - base : 0;
+        const BufRsrc rs = make_rsrc(x + base, (uint32_t)((have < kBpUnitInts ? have : kBpUnitInts) * 4u));
+        const uint4 a = buf_load_u4(rs, t * 32u), c = buf_load_u4(rs, t * 32u + 16u);
+        d[m][0] = a.x, d[m][1] = a.y, d[m][2] = a.z, d[m][3] = a.w;
+        d[m][4] = c.x, d[m][5] = c.y, d[m][6] = c.z, d[m][7] = c.w;
+        const uint64_t iw = base + i0w;
+        const bool prev = S != 0 && iw >= 4 && iw <= lim;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            pw[m][r] = prev ? uniform(x[iw - 4 + r]) : 0u;
     }
-    __syncthreads();
-    const uint32_t size = s_off[kBpBlocks - 1] + 4 * s_b[kBpBlocks - 1];
-    if constexpr (V) {
-        // the four-lane layout interleaves the threads' words: OR-ed in
-        for (uint32_t i = tid; i < size; i += 256)
-            s_u[i] = 0;
-        __syncthreads();
-    }
-    if (tid < 4)
-        s_u[tid] = s_b[4 * tid] | (s_b[4 * tid + 1] << 8) | (s_b[4 * tid + 2] << 16) | (s_b[4 * tid + 3] << 24);
-    const uint32_t j = tid >> 4, b = s_b[j];
-    if (b) {
-        uint32_t *const w = s_u + s_off[j];
-        if constexpr (V) {
+    if (S != 0) {
+#pragma unroll
+        for (uint32_t m = 0; m < kEncHalf; ++m) {
+            // the four integers before the thread's first: the previous
+            // lane's last four (0 before the array start)
+            uint32_t pv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                pv[r] = (uint32_t)__shfl_up((int)d[m][4 + r], 1, 64);
+            if (lane == 0)
+                pv[0] = pw[m][0], pv[1] = pw[m][1], pv[2] = pw[m][2], pv[3] = pw[m][3];
+            uint32_t v[8];
 #pragma unroll
             for (int r = 0; r < 8; ++r)
-                or_field_vertical(w, 8 * (tid & 15u) + r, b, d[r]);
-        } else {
-            put_bytes8(reinterpret_cast<uint8_t *>(w), (tid & 15u) * b, b, d);
+                v[r] = d[m][r];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const uint32_t before = S == 1 ? (r == 0 ? pv[3] : v[r - 1]) : (r < 4 ? pv[r] : v[r - 4]);
+                d[m][r] = v[r] - before;
+            }
         }
     }
-    const uint32_t off = dir_end + incl[u] - size;
-    write_dir_entry(out, u, dir_entries(n, kBpBlocks), S, off, x, u * kBpUnitInts);
+    // block widths: OR over the block's 16 threads (one row of 16 lanes)
+    const uint32_t j = t >> 4;
+#pragma unroll
+    for (uint32_t m = 0; m < kEncHalf; ++m) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            o |= d[m][r];
+#pragma unroll
+        for (int k = 1; k < 16; k <<= 1)
+            o |= (uint32_t)__shfl_xor((int)o, k, 64);
+        const uint64_t u = u0 + kEncHalf * hw + m;
+        const uint64_t left = lim / kBlock > u * kBpBlocks ? lim / kBlock - u * kBpBlocks : 0;
+        const uint32_t nb = (uint32_t)(left < kBpBlocks ? left : kBpBlocks);
+        if ((t & 15u) == 0)
+            s_b[kEncHalf * h + m][j] = j < nb ? nbits(o) : 0u;
+    }
     __syncthreads();
-    uint4 *const dst = reinterpret_cast<uint4 *>(out + off);
-    const uint4 *const src = reinterpret_cast<const uint4 *>(s_u);
-    for (uint32_t i = tid; i < size / 4; i += 256)
-        dst[i] = src[i];
+    // each block's first word inside its meta-block (threads 0..255), each
+    // meta-block's length, the tile's offset (wavefront 0)
+    if (tid < kEncTile * kBpBlocks) {
+        const uint32_t mb = tid >> 4, jj = tid & 15u;
+        uint32_t pre = 0;
+        for (uint32_t q = 0; q < jj; ++q)
+            pre += s_b[mb][q];
+        s_boff[mb][jj] = 4 + 4 * pre;
+    }
+    if (wave == 0) {
+        uint32_t sz = 0;
+        if (lane < nu)
+            for (uint32_t q = 0; q < kBpBlocks; ++q)
+                sz += s_b[lane][q];
+        sz = lane < nu ? 4 + 4 * sz : 0u;
+        const uint32_t incl = wave_scan_incl(sz);
+        if (lane < kEncTile)
+            s_off[lane + 1] = incl;
+        if (lane == 0)
+            s_off[0] = 0;
+        const uint32_t agg[4] = {wave_read(incl, 63), 0, 0, 0};
+        uint32_t pre[4];
+        wave_lookback<1>(status, tile, agg, 0u, pre);
+        if (lane == 0) {
+            s_pre = pre[0];
+            if (u0 + nu == units)
+                *total = pre[0] + agg[0];
+        }
+    }
+    __syncthreads();
+    const uint32_t pre = s_pre;
+    // directory entries of the tile's meta-blocks: offset, then S bases
+    const uint64_t ndir = dir_entries(n, kBpBlocks);
+    if (tid < nu * (1 + S)) {
+        const uint32_t mb = tid / (1 + S), k = tid % (1 + S);
+        const uint64_t u = u0 + mb, start = u * kBpUnitInts;
+        if (k == 0)
+            out[kHdrWords + u] = dir_end + pre + s_off[mb];
+        else
+            out[kHdrWords + ndir + u * S + (k - 1)] = (start + (k - 1) >= S) ? x[start + (k - 1) - S] : 0u;
+    }
+    // meta-block m of the half into `dst` (its descriptor, then its blocks'
+    // words: each thread's eight fields are b whole bytes of its block, or
+    // are OR-ed into the cleared words in the four-lane layout)
+    auto assemble = [&](uint32_t m, uint32_t *dst) __attribute__((always_inline)) {
+        const uint32_t mb = kEncHalf * hw + m;
+        if (t < 4)
+            dst[t] = s_b[mb][4 * t] | (s_b[mb][4 * t + 1] << 8) | (s_b[mb][4 * t + 2] << 16) |
+                     (s_b[mb][4 * t + 3] << 24);
+        const uint32_t b = s_b[mb][j];
+        if (b) {
+            uint32_t *const w = dst + s_boff[mb][j];
+            if constexpr (V) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                    or_field_vertical(w, 8 * (t & 15u) + r, b, d[m][r]);
+            } else {
+                put_bytes8(reinterpret_cast<uint8_t *>(w), (t & 15u) * b, b, d[m]);
+            }
+        }
+    };
+    const uint32_t tile_words = s_off[nu];
+    if (tile_words <= kEncLdsWords) {
+        // the whole tile in LDS at once, then one contiguous copy
+        if constexpr (V) {
+            for (uint32_t i = tid; i < tile_words; i += 512)
+                s_u[i] = 0;
+            __syncthreads();
+        }
+#pragma unroll
+        for (uint32_t m = 0; m < kEncHalf; ++m)
+            if (kEncHalf * hw + m < nu)
+                assemble(m, s_u + s_off[kEncHalf * hw + m]);
+        __syncthreads();
+        uint4 *const dst = reinterpret_cast<uint4 *>(out + dir_end + pre);
+        const uint4 *const src = reinterpret_cast<const uint4 *>(s_u);
+        for (uint32_t i = tid; i < tile_words / 4; i += 512)
+            dst[i] = src[i];
+        return;
+    }
+    uint32_t *const su = s_u + hw * (4 + kBpUnitInts);
+#pragma unroll
+    for (uint32_t m = 0; m < kEncHalf; ++m) {
+        const uint32_t mb = kEncHalf * hw + m;
+        const bool live = mb < nu;
+        const uint32_t size = live ? s_off[mb + 1] - s_off[mb] : 0u;
+        if constexpr (V) {
+            for (uint32_t i = t; i < size; i += 256)
+                su[i] = 0;
+            __syncthreads();
+        }
+        if (live)
+            assemble(m, su);
+        __syncthreads();
+        if (live) {
+            uint4 *const dst = reinterpret_cast<uint4 *>(out + dir_end + pre + s_off[mb]);
+            const uint4 *const src = reinterpret_cast<const uint4 *>(su);
+            for (uint32_t i = t; i < size / 4; i += 256)
+                dst[i] = src[i];
+        }
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -800,7 +927,7 @@ __global__ __launch_bounds__(512) void k_fp_pack(const uint32_t *__restrict__ x,
 // Tail (Variable Byte, Section 2.4), directory padding, header, length.
 
 __global__ __launch_bounds__(128) void k_finish(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
-                                                uint32_t codec, const uint32_t *__restrict__ incl, uint64_t units,
+                                                uint32_t codec, const uint32_t *__restrict__ units_words, uint64_t units,
                                                 uint32_t dir_end, uint32_t *__restrict__ out,
                                                 uint64_t *__restrict__ out_words)
 {
@@ -813,7 +940,7 @@ __global__ __launch_bounds__(128) void k_finish(const uint32_t *__restrict__ x, 
     const uint32_t tail = (uint32_t)(n % kBlock);
     const uint32_t E = 1 + S;
     const uint64_t ndir = units + (tail ? 1 : 0);
-    const uint32_t tail_off = units ? dir_end + incl[units - 1] : dir_end;
+    const uint32_t tail_off = units ? dir_end + *units_words : dir_end;
     for (uint32_t i = tid; i < sizeof(s_bytes) / 4; i += 128)
         s_bytes[i] = 0;
     const uint32_t d = tid < tail ? delta_at(x, nfull * kBlock + tid, S) : 0u;
@@ -868,13 +995,22 @@ __global__ __launch_bounds__(128) void k_finish(const uint32_t *__restrict__ x, 
 
 // Scratch bytes an encode call of `codec` over n integers uses: scan
 // status, unit sizes, per-block metadata.
+// Look-back status words of an encode call: the chained scan of the unit
+// sizes, or the fused binary-packing encoder's tiles.
+static uint64_t encode_status_words(int codec, uint64_t units)
+{
+    if (codec == WP_CODEC_BP || codec == WP_CODEC_BPV)
+        return (uint64_t)kStatusWords * ((units + kEncTile - 1) / kEncTile + 1);
+    return scan_status_words(units);
+}
+
 static uint64_t encode_scratch_bytes(int codec, uint64_t n)
 {
     const bool paged = codec == WP_CODEC_FP || codec == WP_CODEC_FP32 || codec == WP_CODEC_SP;
     const uint64_t per = paged ? kFpBlocks : kBpBlocks;
     const uint64_t units = (n / kBlock + per - 1) / per;
     const uint64_t nblk = units * per;
-    const uint64_t meta_off = scan_status_words(units) * 8 + ((units * 4 + 255) & ~255ull);
+    const uint64_t meta_off = encode_status_words(codec, units) * 8 + ((units * 4 + 255) & ~255ull);
     const uint64_t meta_len = (codec == WP_CODEC_BP || codec == WP_CODEC_BPV) ? nblk
                               : codec == WP_CODEC_BP32                      ? 4 * nblk
                                                                             : 3 * nblk;
@@ -904,7 +1040,7 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
     const uint32_t dir_end = (uint32_t)(kHdrWords + ((E * ndir + 3) & ~3ull));
     hipStream_t st = as_stream(stream);
     // scratch: scan status | unit sizes | per-block metadata
-    const uint64_t status_words = scan_status_words(units);
+    const uint64_t status_words = encode_status_words(codec, units);
     const uint64_t sizes_off = status_words * 8;
     const uint64_t meta_off = sizes_off + ((units * 4 + 255) & ~255ull);
     const uint64_t nblk = units * per;
@@ -915,11 +1051,22 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
     uint32_t *sizes = reinterpret_cast<uint32_t *>(scr + sizes_off);
     uint8_t *meta = reinterpret_cast<uint8_t *>(scr + meta_off);
     (void)hipGetLastError();
-    if (units) {
-        if (codec == WP_CODEC_BP || codec == WP_CODEC_BPV)
-            hipLaunchKernelGGL(k_bp_analyze, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride, meta,
-                               sizes);
-        else if (codec == WP_CODEC_BP32)
+    // the units' total length in words, for the tail's offset
+    const uint32_t *units_words = sizes + (units ? units - 1 : 0);
+    if (units && (codec == WP_CODEC_BP || codec == WP_CODEC_BPV)) {
+        const uint64_t tiles = (units + kEncTile - 1) / kEncTile;
+        if (tiles > 0x7FFFFFFFull)
+            return WP_ERR_INVALID_ARG;
+        launch_clear(status, status_words, st);
+        if (codec == WP_CODEC_BP)
+            hipLaunchKernelGGL(k_bp_encode<false>, dim3((uint32_t)tiles), dim3(512), 0, st, in, n, (uint32_t)stride,
+                               units, dir_end, out, status, sizes);
+        else
+            hipLaunchKernelGGL(k_bp_encode<true>, dim3((uint32_t)tiles), dim3(512), 0, st, in, n, (uint32_t)stride,
+                               units, dir_end, out, status, sizes);
+        units_words = sizes;
+    } else if (units) {
+        if (codec == WP_CODEC_BP32)
             hipLaunchKernelGGL(k_bp32_analyze, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride,
                                meta, sizes);
         else if (codec == WP_CODEC_FP32)
@@ -934,13 +1081,7 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
                 return WP_ERR_HIP;
         } else if (launch_inclusive_scan(sizes, units, status, st) != WP_OK)
             return WP_ERR_HIP;
-        if (codec == WP_CODEC_BP)
-            hipLaunchKernelGGL(k_bp_pack<false>, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride,
-                               meta, sizes, dir_end, out);
-        else if (codec == WP_CODEC_BPV)
-            hipLaunchKernelGGL(k_bp_pack<true>, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride,
-                               meta, sizes, dir_end, out);
-        else if (codec == WP_CODEC_BP32)
+        if (codec == WP_CODEC_BP32)
             hipLaunchKernelGGL(k_bp32_pack, dim3((uint32_t)units), dim3(256), 0, st, in, n, (uint32_t)stride, meta,
                                sizes, dir_end, out);
         else if (codec == WP_CODEC_FP32)
@@ -948,7 +1089,7 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
         else if (codec == WP_CODEC_FP)
             WP_FP_ENC(k_fp_pack, false, (in, n, meta, nblk, sizes, dir_end, out));
     }
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(128), 0, st, in, n, (uint32_t)stride, (uint32_t)codec, sizes, units,
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(128), 0, st, in, n, (uint32_t)stride, (uint32_t)codec, units_words, units,
                        dir_end, out, out_words);
     return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
 }

@@ -47,6 +47,10 @@ Tune decode_tune(int codec);
 uint64_t scan_status_words(uint64_t n);
 int32_t launch_inclusive_scan(uint32_t *data, uint64_t n, uint64_t *status, hipStream_t st);
 
+// Clears `count` 64-bit words on `st` with a kernel (look-back status words
+// before a chained scan).
+void launch_clear(uint64_t *p, uint64_t count, hipStream_t st);
+
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 // The SimplePFOR pages of an encode call (after the patched analysis has

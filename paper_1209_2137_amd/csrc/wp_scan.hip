@@ -17,6 +17,7 @@
 
 #include "wp_device.hpp"
 #include "wp_host.hpp"
+#include "wp_lookback.hpp"
 
 namespace wp {
 
@@ -24,20 +25,6 @@ constexpr int kScanWaves = 16;
 constexpr int kScanT = 64 * kScanWaves;
 constexpr int kRows1 = 4, kRows4 = 4;  // rows per tile for stride 1 and stride 4
 constexpr uint32_t tile_ints(uint32_t S) { return kScanT * 4u * (S == 1 ? kRows1 : kRows4); }
-constexpr uint64_t kFlagAgg = 1ull << 32;
-constexpr uint64_t kFlagInc = 2ull << 32;
-constexpr int kStatusWords = 8;  // per tile: aggregate[4], inclusive[4]
-
-__device__ __forceinline__ void st_status(uint64_t *p, uint64_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ uint64_t ld_status(const uint64_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __global__ void k_fill_zero(uint64_t *__restrict__ p, uint64_t count)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -133,75 +120,9 @@ __global__ __launch_bounds__(kScanT) void k_delta_scan(uint32_t *__restrict__ da
         }
     }
     // publish and look back (wave 0)
-    uint64_t *my = status + kStatusWords + (uint64_t)tile * kStatusWords;
     if (wave == 0) {
-        uint32_t pre[4] = {init, init, init, init};
-        if (tile == 0) {
-            if (lane < (uint32_t)NC)
-                st_status(my + 4 + lane, kFlagInc | (uint32_t)(init + agg[lane & 3]));
-        } else {
-            if (lane < (uint32_t)NC)
-                st_status(my + lane, kFlagAgg | agg[lane & 3]);
-            uint32_t acc[4] = {0, 0, 0, 0};
-            int64_t pos = (int64_t)tile;
-            for (;;) {
-                const int64_t t = pos - 1 - (int64_t)lane;
-                // per lane: state of predecessor t (2 = inclusive, 1 = aggregate, 0 = not ready)
-                uint32_t state = 0;
-                uint32_t val[4] = {0, 0, 0, 0};
-                if (t < 0) {
-                    state = 2;
-                    val[0] = val[1] = val[2] = val[3] = init;
-                } else {
-                    const uint64_t *st = status + kStatusWords + (uint64_t)t * kStatusWords;
-                    bool inc = true, ag = true;
-                    uint64_t w[4];
-                    for (int c = 0; c < NC; ++c) {
-                        w[c] = ld_status(st + 4 + c);
-                        inc = inc && (w[c] >> 32) == 2;
-                    }
-                    if (inc) {
-                        state = 2;
-                        for (int c = 0; c < NC; ++c)
-                            val[c] = (uint32_t)w[c];
-                    } else {
-                        for (int c = 0; c < NC; ++c) {
-                            w[c] = ld_status(st + c);
-                            ag = ag && (w[c] >> 32) == 1;
-                        }
-                        if (ag) {
-                            state = 1;
-                            for (int c = 0; c < NC; ++c)
-                                val[c] = (uint32_t)w[c];
-                        }
-                    }
-                }
-                const uint64_t incm = ballot(state == 2);
-                const uint64_t notready = ballot(state == 0);
-                const uint32_t first = incm ? (uint32_t)__builtin_ctzll(incm) : 64u;
-                const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1ull);
-                if (notready & need) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                for (int c = 0; c < NC; ++c) {
-                    const uint32_t x = lane <= first ? val[c] : 0u;
-                    acc[c] += wave_read(wave_scan_incl(x), 63);
-                }
-                if (first < 64)
-                    break;
-                pos -= 64;
-            }
-            for (int c = 0; c < NC; ++c)
-                pre[c] = acc[c];
-            if (lane < (uint32_t)NC) {
-                uint32_t mine = 0;
-                for (int c = 0; c < NC; ++c)
-                    if ((uint32_t)c == lane)
-                        mine = pre[c] + agg[c];
-                st_status(my + 4 + lane, kFlagInc | mine);
-            }
-        }
+        uint32_t pre[4];
+        wave_lookback<NC>(status, tile, agg, init, pre);
         if (lane == 0)
             for (int c = 0; c < 4; ++c)
                 s_excl[c] = pre[c];
@@ -313,6 +234,12 @@ static int32_t launch_scan(uint32_t *data, uint64_t n, uint32_t init, uint32_t s
         hipExtLaunchKernelGGL(k_delta_scan<4>, dim3((uint32_t)tiles), dim3(kScanT), 0, st, e.start, e.stop, 0, data, n,
                               init, status);
     return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
+}
+
+void launch_clear(uint64_t *p, uint64_t count, hipStream_t st)
+{
+    if (count)
+        hipLaunchKernelGGL(k_fill_zero, dim3((uint32_t)((count + 255) / 256)), dim3(256), 0, st, p, count);
 }
 
 int32_t launch_inclusive_scan(uint32_t *data, uint64_t n, uint64_t *status, hipStream_t st)
