@@ -127,38 +127,45 @@ __device__ __forceinline__ void unit_deltas8(const uint32_t *__restrict__ x, uin
 
 // ------------------------------------------------------------------------
 // Binary packing in one pass over the input (SIMD-BP128 and its four-lane
-// layout). A workgroup of 512 threads takes kEncTile consecutive
-// meta-blocks, its tile index from the launch's counter (so a tile's
-// predecessors always started first). Thread t of half h = t / 256 holds
-// integers 8 (t mod 256) .. +7 of meta-blocks kEncHalf h .. kEncHalf h +
-// kEncHalf - 1 in registers, all read at once; the widths give every
-// meta-block's length, the tile's total goes through the decoupled
-// look-back for the tile's offset in the stream, and each half then
-// assembles its meta-blocks one after the other in LDS (the descriptor,
+// layout). A workgroup of kEncGroups groups of 256 threads takes kEncTile
+// consecutive meta-blocks, its tile index from the launch's counter (so a
+// tile's predecessors always started first). Thread t of group h = t / 256
+// holds integers 8 (t mod 256) .. +7 of the group's kEncHalf meta-blocks in
+// registers, all read at once; the widths give every meta-block's length,
+// the tile's total goes through the decoupled look-back for the tile's
+// offset in the stream, and the tile is assembled in LDS (the descriptor,
 // then the blocks' words: byte stores, or fields OR-ed in by LDS atomics
-// for the four-lane layout) and writes them with 16-byte stores (unit
-// offsets are multiples of 4 words). The input is read once.
-// Tiles of 8 meta-blocks: the chained scan completes about 64 tiles per
-// device-scope round trip, which caps smaller tiles; larger ones hold more
-// registers per thread and leave fewer workgroups per compute unit to
-// overlap one tile's loads with another's look-back and writes.
+// for the four-lane layout) and written with 16-byte stores (unit offsets
+// are multiples of 4 words). The input is read once.
+// Tiles of 8 meta-blocks in two groups: the chained scan completes at most
+// about 64 tiles per device-scope round trip, which caps smaller tiles;
+// larger ones need more registers per thread or more threads per
+// workgroup, and leave fewer workgroups per compute unit to overlap one
+// tile's loads with another's look-back and writes.
 #ifndef WP_ENC_TILE
 #define WP_ENC_TILE 8
 #endif
 constexpr uint32_t kEncTile = WP_ENC_TILE;  // meta-blocks per workgroup
-constexpr uint32_t kEncHalf = kEncTile / 2;
+#ifndef WP_ENC_GROUPS
+#define WP_ENC_GROUPS 2
+#endif
+#ifndef WP_ENC_MIN_WAVES
+#define WP_ENC_MIN_WAVES 4
+#endif
+constexpr uint32_t kEncGroups = WP_ENC_GROUPS;     // groups of 256 threads per workgroup
+constexpr uint32_t kEncThreads = 256 * kEncGroups;
+constexpr uint32_t kEncHalf = kEncTile / kEncGroups;  // meta-blocks per group
 // LDS words for the tile's compressed stream (the tiles of compressible
-// lists fit; the others are assembled a meta-block per half at a time)
-constexpr uint32_t kEncLdsWords = 8192;
-static_assert(kEncLdsWords >= 2 * (4 + kBpUnitInts), "one meta-block per half");
-static_assert(kEncTile % 2 == 0 && kEncTile <= 64, "two halves; one look-back lane per meta-block");
+// lists fit; the others are assembled a meta-block per group at a time)
+constexpr uint32_t kEncLdsWords = 8192 > kEncGroups * (4 + kBpUnitInts) ? 8192 : kEncGroups * (4 + kBpUnitInts);
+static_assert(kEncTile % kEncGroups == 0 && kEncTile <= 64, "whole groups; one look-back lane per meta-block");
 
 template <bool V>
-__global__ __launch_bounds__(512, 4) void k_bp_encode(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
+__global__ __launch_bounds__(kEncThreads, WP_ENC_MIN_WAVES) void k_bp_encode(const uint32_t *__restrict__ x, uint64_t n, uint32_t S,
                                                    uint64_t units, uint32_t dir_end, uint32_t *__restrict__ out,
                                                    uint64_t *__restrict__ status, uint32_t *__restrict__ total)
 {
-    __shared__ __align__(16) uint32_t s_u[kEncLdsWords];  // the tile's stream, or one meta-block per half
+    __shared__ __align__(16) uint32_t s_u[kEncLdsWords];  // the tile's stream, or one meta-block per group
     __shared__ uint32_t s_b[kEncTile][kBpBlocks];     // widths
     __shared__ uint32_t s_boff[kEncTile][kBpBlocks];  // a block's first word in its meta-block
     __shared__ uint32_t s_off[kEncTile + 1];          // a meta-block's first word in the tile
@@ -174,7 +181,7 @@ __global__ __launch_bounds__(512, 4) void k_bp_encode(const uint32_t *__restrict
     const uint64_t u0 = (uint64_t)tile * kEncTile;
     const uint32_t nu = (uint32_t)(units - u0 < kEncTile ? units - u0 : kEncTile);
     const uint64_t lim = (n / kBlock) * kBlock;  // full blocks only
-    // every load of the half's meta-blocks first: the thread's eight values
+    // every load of the group's meta-blocks first: the thread's eight values
     // and, for the wavefront's first lane, the four before them
     uint32_t d[kEncHalf][8];
     uint32_t pw[kEncHalf][4];  // uniform: the four values before the wavefront's first
@@ -275,7 +282,7 @@ __global__ __launch_bounds__(512, 4) void k_bp_encode(const uint32_t *__restrict
         else
             out[kHdrWords + ndir + u * S + (k - 1)] = (start + (k - 1) >= S) ? x[start + (k - 1) - S] : 0u;
     }
-    // meta-block m of the half into `dst` (its descriptor, then its blocks'
+    // meta-block m of the group into `dst` (its descriptor, then its blocks'
     // words: each thread's eight fields are b whole bytes of its block, or
     // are OR-ed into the cleared words in the four-lane layout)
     auto assemble = [&](uint32_t m, uint32_t *dst) __attribute__((always_inline)) {
@@ -299,7 +306,7 @@ __global__ __launch_bounds__(512, 4) void k_bp_encode(const uint32_t *__restrict
     if (tile_words <= kEncLdsWords) {
         // the whole tile in LDS at once, then one contiguous copy
         if constexpr (V) {
-            for (uint32_t i = tid; i < tile_words; i += 512)
+            for (uint32_t i = tid; i < tile_words; i += kEncThreads)
                 s_u[i] = 0;
             __syncthreads();
         }
@@ -310,7 +317,7 @@ __global__ __launch_bounds__(512, 4) void k_bp_encode(const uint32_t *__restrict
         __syncthreads();
         uint4 *const dst = reinterpret_cast<uint4 *>(out + dir_end + pre);
         const uint4 *const src = reinterpret_cast<const uint4 *>(s_u);
-        for (uint32_t i = tid; i < tile_words / 4; i += 512)
+        for (uint32_t i = tid; i < tile_words / 4; i += kEncThreads)
             dst[i] = src[i];
         return;
     }
@@ -1059,10 +1066,10 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
             return WP_ERR_INVALID_ARG;
         launch_clear(status, status_words, st);
         if (codec == WP_CODEC_BP)
-            hipLaunchKernelGGL(k_bp_encode<false>, dim3((uint32_t)tiles), dim3(512), 0, st, in, n, (uint32_t)stride,
+            hipLaunchKernelGGL(k_bp_encode<false>, dim3((uint32_t)tiles), dim3(kEncThreads), 0, st, in, n, (uint32_t)stride,
                                units, dir_end, out, status, sizes);
         else
-            hipLaunchKernelGGL(k_bp_encode<true>, dim3((uint32_t)tiles), dim3(512), 0, st, in, n, (uint32_t)stride,
+            hipLaunchKernelGGL(k_bp_encode<true>, dim3((uint32_t)tiles), dim3(kEncThreads), 0, st, in, n, (uint32_t)stride,
                                units, dir_end, out, status, sizes);
         units_words = sizes;
     } else if (units) {
