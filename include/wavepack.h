@@ -233,7 +233,7 @@ int32_t fastpfor_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, ui
  *   stride 4: data[i] = init + sum of d_j, j <= i, j = i (mod 4)
  * One pass over the data (8 bytes of traffic per integer) with a
  * decoupled look-back across tiles. Uses a library-owned scratch area per
- * (device, stream) of 64 bytes per 16384 integers, grown on demand
+ * (device, stream) of 64 bytes per 32768 integers, grown on demand
  * (growing synchronises the stream and allocates). Returns
  * WP_ERR_INVALID_ARG for a stride other than 1 or 4, a null or misaligned
  * `data` (n > 0), WP_ERR_HIP if the scratch allocation or a launch fails. */
@@ -245,7 +245,7 @@ int32_t delta_decode_inplace(uint32_t *data, uint64_t n, uint32_t init, int32_t 
  * harnesses that forbid hipMalloc). Same arguments, result and errors as
  * delta_decode_inplace, for n <= 2^28 integers (2^28 + 1 and more return
  * WP_ERR_CAPACITY and enqueue nothing). Its scan status words live in a
- * fixed 1 MiB array of the library's code object, one per device, held
+ * fixed array of about 512 KiB in the library's code object, one per device, held
  * until the process ends; each call first clears the part it uses with a
  * fill kernel (no memset node). Every call on a device shares that array:
  * calls that overlap on one device (on different streams, or from several

@@ -1,10 +1,11 @@
 // delta_decode_inplace: the in-place prefix sum of Section 3 over a whole
 // device array, in one pass (read 4 B + write 4 B per integer).
 //
-// Tiles of 16384 integers (1024 threads x 4 rows x 4 integers, 64 KB) take
-// their index from an atomic counter, so a tile's predecessors always
+// Tiles of 32768 integers (1024 threads x 8 rows x 4 integers, 128 KB)
+// take their index from an atomic counter, so a tile's predecessors always
 // started first. Large tiles matter: the inclusive prefix advances by at
-// most one look-back window (64 tiles) per device-scope round trip. Each tile scans locally, publishes its aggregate, then looks back
+// most one look-back window (64 tiles) per device-scope round trip. Each
+// tile scans locally, publishes its aggregate, then looks back
 // over its predecessors (a whole wavefront reads 64 of them at once) until
 // it meets one that has published its inclusive prefix (decoupled look-back,
 // Merrill & Garland). Each status is one 64-bit word {flag, value} written
@@ -23,8 +24,20 @@ namespace wp {
 
 constexpr int kScanWaves = 16;
 constexpr int kScanT = 64 * kScanWaves;
-constexpr int kRows1 = 4, kRows4 = 4;  // rows per tile for stride 1 and stride 4
+// Rows per tile for stride 1 and stride 4: tiles of 32768 integers. The
+// chained scan completes at most about 64 tiles per device-scope round
+// trip; with tiles of 16384 integers that capped the 2^28 stride-1 scan at
+// about 475 us, with 32768 it runs at the device copy's rate.
+#ifndef WP_SCAN_ROWS1
+#define WP_SCAN_ROWS1 8
+#endif
+#ifndef WP_SCAN_ROWS4
+#define WP_SCAN_ROWS4 8
+#endif
+constexpr int kRows1 = WP_SCAN_ROWS1, kRows4 = WP_SCAN_ROWS4;
 constexpr uint32_t tile_ints(uint32_t S) { return kScanT * 4u * (S == 1 ? kRows1 : kRows4); }
+// the smaller of the two strides' tiles: status arrays sized for it fit both
+constexpr uint32_t kMinTileInts = tile_ints(1) < tile_ints(4) ? tile_ints(1) : tile_ints(4);
 __global__ void k_fill_zero(uint64_t *__restrict__ p, uint64_t count)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -96,20 +109,29 @@ __global__ __launch_bounds__(kScanT) void k_delta_scan(uint32_t *__restrict__ da
     }
     __syncthreads();
     // add the earlier (row, wave) segments inside the tile: the rows x waves
-    // segment totals, in tile order, are exactly one wavefront's worth (64),
-    // so one wave scan per residue class gives every segment's offset
-    static_assert(kScanRows * kScanWaves == 64, "one segment per lane");
+    // segment totals, in tile order, are K wavefronts' worth (K per lane,
+    // consecutive), so one wave scan per residue class gives every
+    // segment's offset
+    constexpr int K = kScanRows * kScanWaves / 64;
+    static_assert(kScanRows * kScanWaves == 64 * K && (K == 1 || K == 2), "one or two segments per lane");
     constexpr int NC = S == 1 ? 1 : 4;
     uint32_t agg[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        const uint32_t seg = (&s_tot[0][0][0])[lane * 4 + c];  // segment (lane / W, lane % W)
-        const uint32_t incl = wave_scan_incl(seg);
-        const uint32_t ex = incl - seg;
+        uint32_t sv[K], lsum = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            sv[k] = (&s_tot[0][0][0])[(lane * K + k) * 4 + c];  // segment (q / W, q % W), q = K lane + k
+            lsum += sv[k];
+        }
+        const uint32_t incl = wave_scan_incl(lsum);
+        const uint32_t ex0 = incl - lsum, ex1 = ex0 + sv[0];
         agg[c] = wave_read(incl, 63);
 #pragma unroll
         for (int m = 0; m < kScanRows; ++m) {
-            const uint32_t off = __builtin_amdgcn_readlane(ex, m * kScanWaves + (int)wave);
+            const int q = m * kScanWaves + (int)wave;
+            const uint32_t o0 = __builtin_amdgcn_readlane(ex0, q / K);
+            const uint32_t off = (K == 2 && (q & 1)) ? __builtin_amdgcn_readlane(ex1, q / K) : o0;
             if constexpr (S == 1) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
@@ -211,11 +233,11 @@ using namespace wp;
 
 namespace wp {
 
-// status words for n integers (sized for the smaller stride-4 tiles, so
-// one size fits both strides)
+// status words for n integers (sized for the smaller of the two strides'
+// tiles, so one size fits both)
 uint64_t scan_status_words(uint64_t n)
 {
-    const uint64_t tiles = (n + tile_ints(4) - 1) / tile_ints(4);
+    const uint64_t tiles = (n + kMinTileInts - 1) / kMinTileInts;
     return (uint64_t)kStatusWords * (tiles + 1);
 }
 
@@ -259,7 +281,7 @@ extern "C" int32_t delta_decode_inplace(uint32_t *data, uint64_t n, uint32_t ini
         return WP_OK;
     if (data == nullptr || !aligned16(data))
         return WP_ERR_INVALID_ARG;
-    const uint64_t tiles = (n + tile_ints(4) - 1) / tile_ints(4);
+    const uint64_t tiles = (n + kMinTileInts - 1) / kMinTileInts;
     if (tiles > 0x7FFFFFFFull)
         return WP_ERR_INVALID_ARG;
     hipStream_t st = as_stream(stream);
@@ -280,7 +302,7 @@ extern "C" int32_t delta_decode_inplace(uint32_t *data, uint64_t n, uint32_t ini
 namespace wp {
 
 constexpr uint64_t kNoAllocMaxN = 1ull << 28;
-constexpr uint64_t kNoAllocWords = (uint64_t)kStatusWords * ((kNoAllocMaxN + tile_ints(4) - 1) / tile_ints(4) + 1);
+constexpr uint64_t kNoAllocWords = (uint64_t)kStatusWords * ((kNoAllocMaxN + kMinTileInts - 1) / kMinTileInts + 1);
 
 static __device__ __align__(256) uint64_t scratch[kNoAllocWords];
 
