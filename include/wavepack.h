@@ -342,7 +342,8 @@ const char *wp_strerror(int32_t code);
  * counterpart of decoding many posting lists). A plan turns a list
  * registry into work items -- 64-block segments of patched pages, runs of
  * meta-blocks and tails of lists without full blocks -- and one kernel
- * launch covers them all, a wavefront for each item, largest first: by
+ * launch covers them all, a wavefront for each item, the largest and the
+ * smallest items alternately (the longest start first): by
  * default a grid of one wavefront per item (the hardware dispatcher
  * balances the load), or, with wp_tune.wg_per_cu > 0, a persistent grid
  * whose wavefronts pull the items from a work queue (a device counter).
@@ -377,7 +378,7 @@ typedef struct wp_tune {
  * comp_off_words and out_off (or of the list's own `out`) to 4 words,
  * comp_words >= 8), cuts every list
  * into work items (runs of run_units meta-blocks, page segments, tails
- * of lists without full blocks; largest first), uploads the list and item arrays (it synchronises
+ * of lists without full blocks; largest and smallest alternately), uploads the list and item arrays (it synchronises
  * `stream` once), and, when tune->use_graph, builds and instantiates a
  * hipGraph holding the decoder's kernel node. `pool` and
  * `out_base` (device, 16-byte aligned) are kept; out_base may be NULL when
