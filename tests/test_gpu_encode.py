@@ -124,3 +124,26 @@ def test_fastpfor_encode_exception_heavy_pages(wide_frac):
     hdr_w = (4 + bin(bitset).count("1") + 3) & ~3
     tail_words = (p1 - p0) - hdr_w - packed
     print(f"wide_frac={wide_frac}: first page tail {4 * tail_words} bytes", flush=True)
+
+
+def test_binary_packing_encode_tiles_mixed_and_ragged():
+    """Lists cut at and around the binary-packing encoder's tiles of 8
+    meta-blocks (16384 integers), where every other tile holds 32-bit
+    values (too long for the tile's LDS assembly, so it is assembled a
+    meta-block at a time) and the others compress: both block layouts and
+    every stride, word for word against the oracle."""
+    rng = np.random.default_rng(77)
+    tile = 8 * 2048
+    for n in (tile - 1, tile, tile + 1, tile + 128, 3 * tile - 129, 3 * tile + 2047, 5 * tile + 3):
+        x = datagen.single_geometric(n, mean=20.0, seed=n)
+        for t in range(1, n // tile + 1, 2):
+            hi = min(n, (t + 1) * tile)
+            x[t * tile:hi] = rng.integers(0, 2**32, size=hi - t * tile, dtype=np.uint64).astype(np.uint32)
+        for codec, enc in ((wp.CODEC_BP, oracle.bp_encode), (wp.CODEC_BPV, oracle.bpv_encode)):
+            for stride in (0, 1, 4):
+                print(f"tiles codec={codec} stride={stride} n={n}", flush=True)
+                got = to_host(wp.encode_trimmed(to_dev(x), codec, stride))
+                assert wp.check_code() == wp.OK
+                want = enc(x, stride)
+                assert got.size == want.size, (n, codec, stride)
+                assert_same(got, want, f"n={n} codec={codec} stride={stride}")
