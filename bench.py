@@ -73,7 +73,8 @@ def time_launches(fn, steps, warmup, stream, kernel_events=None):
     ends (wp_time_next_launch), so the event time is the kernel's duration;
     otherwise the events bracket each launch on `stream`. (Events between
     launches add a few microseconds of gap each, so they stay out of the
-    wall-time loop.)"""
+    wall-time loop; with kernel events, `warmup` untimed launches queued just
+    before the timed ones keep the GPU busy between them.)"""
     import torch
     for i in range(warmup):
         fn(i)
@@ -89,6 +90,11 @@ def time_launches(fn, steps, warmup, stream, kernel_events=None):
         for e in starts + ends:  # create the events on the device before handing them over
             e.record(stream)
         torch.cuda.synchronize()
+        # a backlog of untimed launches first, so that the timed kernels run
+        # back to back as in the wall-time loop instead of each starting on
+        # an idle GPU after the host's per-launch work
+        for i in range(warmup):
+            fn(warmup + i)
     for i in range(steps):
         if kernel_events is not None:
             kernel_events.time_next_launch(starts[i], ends[i])
