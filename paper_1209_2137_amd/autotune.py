@@ -31,7 +31,7 @@ BP_SINGLE = [dict(waves=w, vpl=4, depth=d, wg_per_cu=c)
 FP_SINGLE = [dict(waves=w, vpl=4) for w in (1, 2, 4, 8)]
 BP32_SINGLE = [dict(waves=w, vpl=4, depth=d, wg_per_cu=c) for w in (2, 4, 8) for d in (2, 3) for c in (56, 128, 256)]
 BATCH = [dict(waves=w, vpl=4, depth=d, run_units=r, wg_per_cu=0, use_graph=1)
-         for w in (2, 4, 8) for d in (2, 3) for r in (4, 8, 16)] + \
+         for w in (2, 4, 8) for d in (2, 3) for r in (1, 2, 4, 8)] + \
         [dict(waves=4, vpl=4, depth=2, run_units=r, wg_per_cu=c, use_graph=1) for r in (4, 8) for c in (4, 8)]
 
 
