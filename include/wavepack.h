@@ -180,8 +180,15 @@ int32_t fastpfor32_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, 
  * [j*bits, (j+1)*bits); greedy: the first selector, from 0 up, whose count
  * is still available and whose width fits them). Page: [nblocks,
  * packed_words, meta_bytes, Simple-8b words (32-bit words, two per 64-bit
- * word, low half first)], packed values, metadata, the Simple-8b words,
- * zero-padded to 4 words (magic 'WPS1'). */
+ * word, low half first)] + the segment bases (as in the patched pages: for
+ * each 64-block segment after the first, the S values just before it) +
+ * for each such segment its entry into the Simple-8b words (the index of
+ * the 64-bit word holding the high part of the segment's first exception
+ * | the number of that word's values before it << 24; the word count when
+ * no exception follows), padded to 4 words; packed values, metadata, the
+ * Simple-8b words, zero-padded to 4 words (magic 'WPS1'). The bases and
+ * entries are additions to the paper's page that let segments decode
+ * independently. */
 
 /* SimplePFOR encoder: the pages described above (widths, metadata and
  * positions as fastpfor_encode; the high parts of each page's exceptions,
@@ -190,9 +197,9 @@ int32_t fastpfor32_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, 
 int32_t simplepfor_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,
                           uint64_t out_cap_words, uint64_t *out_words, void *stream);
 
-/* SimplePFOR decoder: as fastpfor_decode,
- * the high parts taken from the page's Simple-8b words (decoded by
- * wavefronts as the page's blocks need them). Allocates nothing. */
+/* SimplePFOR decoder: as fastpfor_decode (one wavefront per 64-block
+ * segment), the high parts taken from the page's Simple-8b words, decoded
+ * from the segment's entry on as its blocks need them. Allocates nothing. */
 int32_t simplepfor_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
                           void *stream);
 

@@ -290,10 +290,11 @@ uint64_t oracle_max_words(int codec, uint64_t n)
          * a block <= 127 * 32 and at most 31 values of padding per array */
         words += units * (1 + 1 + 1 + 32 + 3 + 1 + 32 * 31) + nfull * (OB + (3 + 127) / 4 + 1 + 127);
     } else if (codec == 5) {
-        /* per page: 4 header words and 3 words of padding; packed <= 128
+        /* per page: header <= 39 words (4, 7 segment bases of up to 4
+         * words, 7 segment entries) and 3 words of padding; packed <= 128
          * words per block; metadata <= (3 + 128) bytes per block (+16 B
          * padding); at most one 64-bit Simple-8b word per exception */
-        words += units * (4 + 3 + 4) + nfull * (OB + (3 + OB) / 4 + 1 + 2 * OB);
+        words += units * (39 + 3 + 4) + nfull * (OB + (3 + OB) / 4 + 1 + 2 * OB);
     } else {
         /* per page: header <= 64 words (4 + 32 counts + 7 segment bases of
          * up to 4 words); packed <= 128 words per block;
@@ -587,16 +588,36 @@ int64_t oracle_s8_decode(const uint64_t *in, uint64_t nwords, uint32_t *v, uint6
     return (int64_t)k;
 }
 
+/* Where high part number e of a page sits in its Simple-8b words: the index
+ * of the word holding it | the number of that word's values before it
+ * << 24; e equal to the page's exception count gives the word count. */
+static uint32_t o_sp_entry(const uint64_t *s8, uint64_t ns8, uint64_t e)
+{
+    uint64_t v = 0;
+    for (uint64_t w = 0; w < ns8; w++) {
+        uint64_t cnt = O_S8_COUNT[s8[w] >> 60];
+        if (e < v + cnt)
+            return (uint32_t)w | ((uint32_t)(e - v) << 24);
+        v += cnt;
+    }
+    return (uint32_t)ns8;
+}
+
 /* ---- Section 5, SimplePFOR: the pages of FastPFOR (the same widths by
  * the same cost rule, the same packed values, positions and metadata),
  * with the exceptions' high parts (value >> b) collected over the whole
  * page in block order and coded once with Simple-8b instead of one packed
  * array per width. Page: [nblocks, packed_words, meta_bytes, s8_words]
  * (s8_words: 32-bit words of the Simple-8b array, two per 64-bit word, low
- * half first), packed values, metadata (b, maxb, c per block, then the
- * positions; zero-padded to 16 bytes), the Simple-8b words, zero-padded to
- * 4 words. */
-static uint64_t o_sp_page(const uint32_t *d, uint64_t nblocks, uint32_t *out)
+ * half first), then, as in the FastPFOR pages, for each 64-block segment
+ * after the first the S values before it, then for each such segment its
+ * entry into the Simple-8b words (o_sp_entry of the exceptions before it;
+ * both additions to the paper's page that let segments decode
+ * independently), padded to 4 words; packed values, metadata (b, maxb, c
+ * per block, then the positions; zero-padded to 16 bytes), the Simple-8b
+ * words, zero-padded to 4 words. */
+static uint64_t o_sp_page(const uint32_t *d, uint64_t nblocks, uint32_t *out, const uint32_t *x, uint64_t start,
+                          int stride)
 {
     uint32_t *bw = malloc(nblocks * sizeof(uint32_t));
     uint32_t *mb = malloc(nblocks * sizeof(uint32_t));
@@ -617,11 +638,26 @@ static uint64_t o_sp_page(const uint32_t *d, uint64_t nblocks, uint32_t *out)
     uint64_t *s8 = malloc((nexc + 1) * sizeof(uint64_t));
     uint64_t ns8 = oracle_s8_encode(hv, nexc, s8);
     uint64_t meta_bytes = 3 * nblocks + nexc;
+    uint64_t nseg = (nblocks + OSEG_BLOCKS - 1) / OSEG_BLOCKS;
+    uint64_t hdr_words = o_pad4(4 + ((uint64_t)stride + 1) * (nseg - 1));
+    memset(out, 0, hdr_words * sizeof(uint32_t));
     out[0] = (uint32_t)nblocks;
     out[1] = (uint32_t)packed_words;
     out[2] = (uint32_t)meta_bytes;
     out[3] = (uint32_t)(2 * ns8);
-    uint64_t p = 4;
+    uint64_t hi = 4;
+    for (uint64_t g = 1; g < nseg; g++) {
+        uint64_t sg = start + g * OSEG_BLOCKS * OB; /* first integer of segment g */
+        for (int t = 0; t < stride; t++)
+            out[hi++] = x[sg - (uint64_t)stride + (uint64_t)t];
+    }
+    uint64_t before = 0; /* exceptions of the blocks before segment g */
+    for (uint64_t g = 1; g < nseg; g++) {
+        for (uint64_t t = (g - 1) * OSEG_BLOCKS; t < g * OSEG_BLOCKS; t++)
+            before += cc[t];
+        out[hi++] = o_sp_entry(s8, ns8, before);
+    }
+    uint64_t p = hdr_words;
     for (uint64_t t = 0; t < nblocks; t++) {
         oracle_pack(d + t * OB, OB, bw[t], out + p);
         p += (uint64_t)OB * bw[t] / 32;
@@ -782,7 +818,7 @@ static int64_t o_encode(int codec, const uint32_t *x, uint64_t n, int stride,
                 nb = per;
             p += (codec == 0 || codec == 4) ? o_bp_unit(d + start, nb, out + p, codec == 4)
                  : codec == 2 ? o_bp32_unit(d + start, nb, out + p)
-                 : codec == 5 ? o_sp_page(d + start, nb, out + p)
+                 : codec == 5 ? o_sp_page(d + start, nb, out + p, x, start, stride)
                  : codec == 6 ? o_fpi_page(d + start, nb, out + p)
                               : o_fp_page(d + start, nb, out + p, codec == 3 ? 32 : OB, x, start, stride);
         }
@@ -962,14 +998,25 @@ done:
     return rc;
 }
 
-static int o_sp_page_decode(const uint32_t *w, uint64_t avail, uint64_t nblocks_expected, uint32_t *d)
+/* The segment bases go to segb (checked by the caller against the decoded
+ * values); every segment entry must be where the page's Simple-8b words
+ * put the segment's first high part. */
+static int o_sp_page_decode(const uint32_t *w, uint64_t avail, uint64_t nblocks_expected, uint32_t *d, int stride,
+                            uint32_t *segb)
 {
     if (avail < 4)
         return O_ERR_CORRUPT;
     uint64_t nblocks = w[0], packed_words = w[1], meta_bytes = w[2], s8_words = w[3];
     if (nblocks != nblocks_expected || (s8_words & 1u))
         return O_ERR_CORRUPT;
-    uint64_t p = 4, packed_at = 4;
+    uint64_t nseg = (nblocks + OSEG_BLOCKS - 1) / OSEG_BLOCKS;
+    uint64_t hdr_words = o_pad4(4 + ((uint64_t)stride + 1) * (nseg - 1));
+    if (hdr_words > avail)
+        return O_ERR_CORRUPT;
+    for (uint64_t i = 0; i < (uint64_t)stride * (nseg - 1); i++)
+        segb[i] = w[4 + i];
+    const uint32_t *entry = w + 4 + (uint64_t)stride * (nseg - 1);
+    uint64_t p = hdr_words, packed_at = hdr_words;
     if (packed_words > avail - p)
         return O_ERR_CORRUPT;
     p += packed_words;
@@ -996,6 +1043,10 @@ static int o_sp_page_decode(const uint32_t *w, uint64_t avail, uint64_t nblocks_
         uint32_t b = mbytes[t], maxb = mbytes[nblocks + t], c = mbytes[2 * nblocks + t];
         if (b > 32 || maxb > 32 || maxb < b || c > OB || (c == 0) != (maxb == b) ||
             bitpos_words + (uint64_t)OB * b / 32 > packed_words) {
+            rc = O_ERR_CORRUPT;
+            goto done;
+        }
+        if (t > 0 && t % OSEG_BLOCKS == 0 && entry[t / OSEG_BLOCKS - 1] != o_sp_entry(s8, ns8, e_at)) {
             rc = O_ERR_CORRUPT;
             goto done;
         }
@@ -1164,11 +1215,11 @@ static int o_decode(int codec, const uint32_t *in, uint64_t in_words, uint32_t *
                 return O_ERR_CORRUPT;
             rc = (codec == 0 || codec == 4) ? o_bp_unit_decode(in + off, end - off, nb, out + start, codec == 4)
                  : codec == 2 ? o_bp32_unit_decode(in + off, end - off, nb, out + start)
-                 : codec == 5 ? o_sp_page_decode(in + off, end - off, nb, out + start)
+                 : codec == 5 ? o_sp_page_decode(in + off, end - off, nb, out + start, stride, segb)
                  : codec == 6 ? o_fpi_page_decode(in + off, end - off, nb, out + start)
                               : o_fp_page_decode(in + off, end - off, nb, out + start, codec == 3 ? 32 : OB,
                                                  stride, segb);
-            if (codec == 1 || codec == 3)
+            if (codec == 1 || codec == 3 || codec == 5)
                 nsegb = (uint64_t)stride * ((nb + OSEG_BLOCKS - 1) / OSEG_BLOCKS - 1);
         } else {
             count = tail;

@@ -268,11 +268,13 @@ static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, u
 #undef WP_BP
 #undef WP_BP_D
     } else {
-        // one wavefront per segment (SimplePFOR and the paper's layout: per
-        // page; the latter one wavefront per workgroup, for its LDS), then
-        // one for the tail
-        const uint64_t per_page = (codec == WP_CODEC_SP || codec == WP_CODEC_FPI) ? 1 : kPageSegs;
-        const uint64_t wpg = codec == WP_CODEC_FPI ? 1 : (uint64_t)t.waves;
+        // one wavefront per segment (the paper's layout: per page, one
+        // wavefront per workgroup, for its LDS), then one for the tail;
+        // SimplePFOR segments at most two per workgroup (each holds 16 KB
+        // of LDS: the ring of decoded high parts besides the packed words)
+        const uint64_t per_page = codec == WP_CODEC_FPI ? 1 : kPageSegs;
+        const int waves = codec == WP_CODEC_FPI ? 1 : codec == WP_CODEC_SP ? (t.waves < 2 ? t.waves : 2) : t.waves;
+        const uint64_t wpg = (uint64_t)waves;
         uint64_t grid = (units * per_page + has_tail + wpg - 1) / wpg;
         grid = grid ? grid : 1;
         if (grid > 0x7FFFFFFFull)
@@ -281,11 +283,11 @@ static int32_t decode_common(int codec, const uint32_t *in, uint64_t in_words, u
                          : codec == WP_CODEC_SP ? kPageSp
                          : codec == WP_CODEC_FPI ? kPageFpi
                                                  : kPageFp;
-        if (t.waves == 1)
+        if (waves == 1)
             launch_fp<1>(kind, grid, st, in, in_words, out, n, ds->err);
-        else if (t.waves == 2)
+        else if (waves == 2)
             launch_fp<2>(kind, grid, st, in, in_words, out, n, ds->err);
-        else if (t.waves == 4)
+        else if (waves == 4)
             launch_fp<4>(kind, grid, st, in, in_words, out, n, ds->err);
         else
             launch_fp<8>(kind, grid, st, in, in_words, out, n, ds->err);
@@ -413,10 +415,11 @@ extern "C" uint64_t wp_max_compressed_words(int32_t codec, uint64_t n)
         // block <= 127 * 32; at most 31 values of padding per array
         w += units * (1 + 1 + 1 + 32 + 3 + 1 + 32 * 31) + nfull * (128 + 33 + 127);
     } else if (codec == WP_CODEC_SP) {
-        // page header 4 words and 3 words of padding; packed <= 128 words per
-        // block; metadata <= 131 bytes per block + 16 bytes padding; at most
-        // one 64-bit Simple-8b word (two words) per exception
-        w += units * (4 + 3 + 4) + nfull * (128 + 33 + 1 + 2 * 128);
+        // page header <= 39 words (4, seven segment bases of up to four
+        // words, seven segment entries) and 3 words of padding; packed <= 128
+        // words per block; metadata <= 131 bytes per block + 16 bytes
+        // padding; at most one 64-bit Simple-8b word (two words) per exception
+        w += units * (39 + 3 + 4) + nfull * (128 + 33 + 1 + 2 * 128);
     } else {
         // page header <= 64 words (4, a count per array, seven segment
         // bases of up to four words); metadata <= 130 bytes per block + 16

@@ -423,25 +423,26 @@ __device__ __forceinline__ void scan_wave4(uint32_t (&x)[4], uint32_t (&carry)[4
 // Three page kinds share this: SIMD-FastPFOR (exception arrays padded to
 // 128 values), FastPFOR (padded to 32) and SimplePFOR, whose high parts
 // are one Simple-8b array over the page in block order (Section 5, and
-// the Simple-8b modes of Section 2). A SimplePFOR page has no segment
-// bases: one wavefront decodes the whole page (its records built round by
-// round, two rounds in an LDS ring). A SimplePFOR page is decoded into an
-// LDS ring of high parts as the passes need them: a wavefront takes up to
-// 64 Simple-8b words at a time (lane i word i), a wave scan of the counts
-// their selectors give places each word's integers, and the words are
-// loaded one batch ahead.
+// the Simple-8b modes of Section 2). A SimplePFOR page holds the same
+// segment bases and, per segment after the first, the Simple-8b word that
+// holds the segment's first high part and that word's values before it,
+// so its segments decode independently too. A SimplePFOR segment's high
+// parts are decoded into an LDS ring as the passes need them: a wavefront
+// takes up to 64 Simple-8b words at a time (lane i word i), a wave scan of
+// the counts their selectors give places each word's integers, and the
+// words are loaded one batch ahead.
 enum : int { kPageFp = 0, kPageFp32 = 1, kPageSp = 2, kPageFpi = 3 };
-constexpr uint32_t kSpRing = 2048;  // high parts held by a SimplePFOR page's ring
+constexpr uint32_t kSpRing = 2048;  // high parts held by a SimplePFOR segment's ring
 constexpr uint32_t kSegBlocks = 64;  // blocks per segment of a patched page
 constexpr uint32_t kSegInts = kSegBlocks * kBlock;
 constexpr uint32_t kPageSegs = kFpBlocks / kSegBlocks;
 
 // Wavefront items of a patched page of nb blocks: its segments (one for a
-// SimplePFOR page).
+// page in the paper's layout).
 template <int KIND>
 __host__ __device__ constexpr uint32_t page_items(uint32_t nb)
 {
-    return (KIND == kPageSp || KIND == kPageFpi) ? 1u : (nb + kSegBlocks - 1) / kSegBlocks;
+    return KIND == kPageFpi ? 1u : (nb + kSegBlocks - 1) / kSegBlocks;
 }
 
 // A segment's packed words stream through a per-wavefront LDS ring in
@@ -454,8 +455,8 @@ constexpr uint32_t kFpRing = 1024;        // >= kFpDepth * kFpCW + the largest p
 constexpr uint32_t kFpMir = kBlock + 4;   // ring words mirrored after its end
 static_assert(kFpRing >= kFpDepth * kFpCW + 4 * kBlock && (kFpRing & (kFpRing - 1)) == 0, "ring size");
 
-// R: rounds of block records held (a FastPFOR segment is one round; a
-// SimplePFOR page keeps two rounds in a ring).
+// R: rounds of block records held (a segment is one round; a page in the
+// paper's layout keeps two rounds in a ring).
 template <int R>
 struct alignas(16) FpLdsT {
     uint32_t ring[kFpRing + kFpMir];  // packed words of the segment
@@ -482,10 +483,6 @@ struct FpLdsSel {
     using T = FpLdsT<1>;
 };
 template <>
-struct FpLdsSel<kPageSp> {
-    using T = FpLdsT<2>;
-};
-template <>
 struct FpLdsSel<kPageFpi> {
     using T = FpiLds;
 };
@@ -493,7 +490,7 @@ template <int KIND>
 using FpLdsOf = typename FpLdsSel<KIND>::T;
 
 struct alignas(16) SpWaveLds {
-    FpLdsT<2> fp;
+    FpLdsT<1> fp;
     uint32_t ring[kSpRing];  // decoded high parts, by their index in the page mod kSpRing
 };
 
@@ -537,11 +534,11 @@ __device__ __forceinline__ uint32_t s8_mode(uint32_t sel)
 }
 
 // Decodes segment `seg` of the patched page at `page` (16-byte aligned,
-// `nwords` words, which must hold `nb` blocks; a SimplePFOR page is one
-// segment) into its part of out[0, 128 nb) (the page's output) with
+// `nwords` words, which must hold `nb` blocks; a page in the paper's
+// layout is one segment) into its part of out[0, 128 nb) (the page's output) with
 // differential coding of stride S, the page's first segment starting from
 // `ubase` (the unit's stored bases). One wavefront; `ring` is the LDS ring
-// of a SimplePFOR page (KIND kPageSp), unused otherwise. Returns the
+// of a SimplePFOR segment (KIND kPageSp), unused otherwise. Returns the
 // segment's validity (uniform); every access stays inside the page, the
 // segment's output range and the wavefront's LDS whatever the page holds.
 template <uint32_t S, int KIND = kPageFp>
@@ -551,7 +548,7 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
 {
     constexpr bool SP = KIND == kPageSp;
     constexpr bool IN = KIND == kPageFpi;  // the paper's own page layout
-    constexpr bool WHOLE = SP || IN;       // one wavefront decodes the whole page
+    constexpr bool WHOLE = IN;             // one wavefront decodes the whole page
     constexpr uint32_t NR = WHOLE ? 2u : 1u;  // rounds of records held
     static_assert(sizeof(L.rec) / sizeof(L.rec[0]) >= NR, "the LDS record area holds every round in use");
     const uint32_t lane = lane_id();
@@ -561,8 +558,9 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
     const bool kl = lane < 32;
     // SIMD-FastPFOR / FastPFOR: [nblocks, packed_words, meta_bytes, bitset]
     // + a count per non-empty array; SimplePFOR: [nblocks, packed_words,
-    // meta_bytes, Simple-8b words]; the paper's layout: word 0 = the byte
-    // array's counter, parsed below
+    // meta_bytes, Simple-8b words] + the segment entries; both + the
+    // segment bases; the paper's layout: word 0 = the byte array's
+    // counter, parsed below
     uint32_t packed_words, meta_bytes, w3, bitset, hdr_w;
     uint32_t cpos = 0, nba = 0, baw = 0;  // the paper's layout: counter word, byte array bytes and words
     bool ba_lds = false;                  // the byte array is held in LDS
@@ -586,7 +584,8 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
         w3 = uniform(page[3]);
         bitset = SP ? 0u : w3;
         const uint32_t nset0 = __builtin_popcount(bitset);
-        hdr_w = pad4(4 + nset0 + (SP ? 0u : S * (page_items<KIND>(nb) - 1)));  // + the segment bases
+        // + the segment bases (SimplePFOR: and one Simple-8b entry per segment)
+        hdr_w = pad4(4 + nset0 + (S + (SP ? 1u : 0u)) * (page_items<KIND>(nb) - 1));
         const uint32_t meta_w0 = ((meta_bytes + 15u) / 16u) * 4u;
         if (h_nb != nb || hdr_w > nwords || packed_words > nwords - hdr_w || meta_bytes < 3 * nb ||
             meta_bytes > 3 * nb + 127 * nb || meta_w0 > nwords - hdr_w - packed_words || (packed_words & 3u))
@@ -780,7 +779,7 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
                 const uint32_t k = (em[r] >= eb[r] && em[r] <= 32u) ? em[r] - eb[r] : 0u;
                 pk_l += 4u * (eb[r] < 32u ? eb[r] : 32u);
                 pos_l += ec[r];
-                if (ec[r] != 0u && k != 0u)
+                if (!SP && ec[r] != 0u && k != 0u)
                     atomicAdd(&L.kcar[k], ec[r]);
             }
             pk_run = wave_read(wave_scan_incl(pk_l), 63);
@@ -895,7 +894,11 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
             const uint32_t md = s8_mode(phi >> 28);
             const uint32_t cnt = live ? (md & 255u) : 0u, bits = md >> 8;
             const uint32_t incl = wave_scan_incl(cnt);
-            const uint32_t room = count_only ? 0xffffffffu : kSpRing - (dec - keep);
+            // accepted high parts stay inside one ring length from dec and
+            // from keep, so no two of them, and none of [keep, dec), share
+            // a slot (dec is below keep while a segment's first word is
+            // read: its values before the segment are not needed)
+            const uint32_t room = count_only ? 0xffffffffu : dec >= keep ? kSpRing - (dec - keep) : kSpRing;
             const uint64_t am = ballot(live && incl <= room);
             const uint32_t nacc = (uint32_t)__builtin_popcountll(am);
             if (nacc == 0) {  // a pass's high parts do not fit the ring: corrupt counts
@@ -917,8 +920,19 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
             s8_load();
         }
     };
-    if constexpr (SP)
+    if constexpr (SP) {
+        // a segment after the first starts on the Simple-8b word its entry
+        // names, that word's first value being high part wS - skip
+        if (seg > 0) {
+            const uint32_t ent = uniform(page[4 + S * (nseg - 1) + seg - 1]);
+            const uint32_t w0 = ent & 0xFFFFFFu, skip = ent >> 24;
+            if (w0 > ns8 || skip > wS || skip >= 60u || (w0 == ns8 && skip != 0u))
+                return false;
+            sw = w0;
+            dec = wS - skip;
+        }
         s8_load();
+    }
 
     const uint32_t jl = lane >> 5;
     // pass q's words and exceptions; `keep`: the first high part still to
@@ -1070,8 +1084,9 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
         buf_store_u4(rout, lane * 16u, 0u, make_uint4(x[0], x[1], x[2], x[3]));
         buf_store_u4(rout, 1024u + lane * 16u, 0u, make_uint4(y[0], y[1], y[2], y[3]));
     };
-    FpFetch f0 = fetch(0, 0u);
-    FpFetch f1 = fetch(1, 0u);
+    // the ring keeps high parts from the segment's first exception on
+    FpFetch f0 = fetch(0, wS);
+    FpFetch f1 = fetch(1, wS);
     for (uint32_t p = 0; p < npass; p += 2) {
         if (p > 0 && (p & 15u) == 0) {
             // round p / 16 starts: build the next one, load the one after
@@ -1103,7 +1118,7 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
         } else {
             bad = bad || (kl && L.kcar[lane + 1] != kcnt);
         }
-    } else if constexpr (!SP && S > 0) {
+    } else if constexpr (S > 0) {
         const uint32_t *const nsb = page + 4 + nset + S * seg;
 #pragma unroll
         for (uint32_t t = 0; t < S; ++t)

@@ -56,13 +56,25 @@ __device__ __forceinline__ uint32_t wave_max_incl(uint32_t v)
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return wave_read(wave_scan_incl(v), 63); }
 
+// Words of a SimplePFOR page's header: 4, then for each 64-block segment
+// after the first S bases and one Simple-8b entry, padded to 4.
+__device__ __forceinline__ uint32_t sp_hdr_words(uint32_t nb, uint32_t S)
+{
+    return pad4(4u + (S + 1u) * (page_items<kPageFp>(nb) - 1u));
+}
+
 // The greedy Simple-8b coding of page `p`'s high parts (nexc of them), by
 // one wavefront; with WRITE the words go to s8 (two 32-bit words each, low
-// half first). Returns the number of 64-bit words (uniform).
+// half first), and the entry of each segment g = 1 .. nseg - 1 (seg_e[g]:
+// the exceptions before it) to entries[g - 1]: the index of the word
+// holding high part seg_e[g] | the word's values before it << 24, or the
+// word count when seg_e[g] = nexc. Returns the number of 64-bit words
+// (uniform).
 template <uint32_t S, bool WRITE>
 __device__ uint32_t sp_code(const uint32_t *__restrict__ x, uint64_t pstart, uint32_t nb,
                             const uint8_t *__restrict__ mb, const uint8_t *__restrict__ mc, uint32_t nexc,
-                            uint32_t *__restrict__ s8, uint32_t *win)
+                            uint32_t *__restrict__ s8, uint32_t *win, const uint32_t *seg_e = nullptr,
+                            uint32_t nseg = 1, uint32_t *__restrict__ entries = nullptr)
 {
     const uint32_t lane = lane_id();
     // selector tested by this lane (2..15): its count and width
@@ -107,10 +119,20 @@ __device__ uint32_t sp_code(const uint32_t *__restrict__ x, uint64_t pstart, uin
                 s8[2 * words] = lo;
                 s8[2 * words + 1] = hi;
             }
+            // lane g: segment g's first high part in this word?
+            if (lane >= 1 && lane < nseg) {
+                const uint32_t e = seg_e[lane];
+                if (e >= i && e < i + cnt)
+                    entries[lane - 1] = words | ((e - i) << 24);
+            }
         }
         ++words;
         i += cnt;
         wave_lds_order();
+    }
+    if constexpr (WRITE) {
+        if (lane >= 1 && lane < nseg && seg_e[lane] >= nexc)
+            entries[lane - 1] = words;
     }
     return words;
 }
@@ -150,13 +172,14 @@ __global__ __launch_bounds__(64) void k_sp_size(const uint32_t *__restrict__ x, 
     const uint32_t words = sp_code<S, false>(x, p * kFpUnitInts, nb, mb, mc, nexc, nullptr, win);
     const uint32_t meta_w = ((3u * nb + nexc + 15u) / 16u) * 4u;
     if (lane_id() == 0)
-        sizes[p] = pad4(4u + packed + meta_w + 2u * words);
+        sizes[p] = pad4(sp_hdr_words(nb, S) + packed + meta_w + 2u * words);
 }
 
 // One workgroup of four wavefronts per page: wavefront 0 writes the page
-// header and codes the high parts into their place; the others write the
-// packed low bits (16 lanes per block, each eight values = b whole bytes)
-// and the metadata bytes, and clear the metadata's padding.
+// header (with the segment bases and entries) and codes the high parts
+// into their place; the others write the packed low bits (16 lanes per
+// block, each eight values = b whole bytes) and the metadata bytes, and
+// clear the metadata's padding.
 template <uint32_t S>
 __global__ __launch_bounds__(256) void k_sp_pack(const uint32_t *__restrict__ x, uint64_t n,
                                                  const uint8_t *__restrict__ meta, uint64_t nblk,
@@ -167,6 +190,7 @@ __global__ __launch_bounds__(256) void k_sp_pack(const uint32_t *__restrict__ x,
     __shared__ uint32_t s_blk[kFpBlocks];  // block t's first packed word (from the packed region)
     __shared__ uint32_t s_exc[kFpBlocks];  // block t's first exception in the page
     __shared__ uint32_t s_tot[2];
+    __shared__ uint32_t s_sege[kPageSegs];  // exceptions before each segment
     const uint64_t p = blockIdx.x;
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = lane_id();
@@ -195,19 +219,32 @@ __global__ __launch_bounds__(256) void k_sp_pack(const uint32_t *__restrict__ x,
     }
     __syncthreads();
     const uint32_t packed = s_tot[0], nexc = s_tot[1];
+    const uint32_t nseg = page_items<kPageFp>(nb), hw = sp_hdr_words(nb, S);
+    if (wave == 0 && lane < kPageSegs)
+        s_sege[lane] = lane < nseg ? s_exc[kSegBlocks * lane] : 0u;
     const uint32_t meta_bytes = 3u * nb + nexc;
     const uint32_t meta_w = ((meta_bytes + 15u) / 16u) * 4u;
     const uint32_t size = incl[p] - (p ? incl[p - 1] : 0u);
     const uint32_t off = dir_end + incl[p] - size;
-    const uint32_t s8_at = 4u + packed + meta_w;
+    const uint32_t s8_at = hw + packed + meta_w;
     const uint32_t s8w = size - s8_at;  // Simple-8b words and the page's end padding
     write_dir_entry(out, p, dir_entries(n, kFpBlocks), S, off, x, pstart);
     uint32_t *page = out + off;
     if (wave == 0) {
-        const uint32_t words = sp_code<S, true>(x, pstart, nb, mb, mc, nexc, page + s8_at, win);
+        wave_lds_order();
+        const uint32_t words = sp_code<S, true>(x, pstart, nb, mb, mc, nexc, page + s8_at, win, s_sege, nseg,
+                                                page + 4 + S * (nseg - 1u));
         // zero padding after the words, up to the page's end
         for (uint32_t w = 2u * words + lane; w < s8w; w += 64)
             page[s8_at + w] = 0u;
+        // segment bases: the S values before each segment after the first;
+        // then the header's padding
+        if (lane < S * (nseg - 1u)) {
+            const uint32_t g = 1u + lane / (S ? S : 1u), t = lane % (S ? S : 1u);
+            page[4u + lane] = x[pstart + (uint64_t)g * kSegInts - S + t];
+        }
+        if (4u + (S + 1u) * (nseg - 1u) + lane < hw)
+            page[4u + (S + 1u) * (nseg - 1u) + lane] = 0u;
         if (lane == 0) {
             page[0] = nb;
             page[1] = packed;
@@ -217,8 +254,8 @@ __global__ __launch_bounds__(256) void k_sp_pack(const uint32_t *__restrict__ x,
         return;
     }
     // waves 1..3: blocks in groups of four, 16 lanes per block
-    uint8_t *const pk = reinterpret_cast<uint8_t *>(page + 4);
-    uint8_t *const md = reinterpret_cast<uint8_t *>(page + 4 + packed);
+    uint8_t *const pk = reinterpret_cast<uint8_t *>(page + hw);
+    uint8_t *const md = reinterpret_cast<uint8_t *>(page + hw + packed);
     const uint32_t g = lane >> 4, r = lane & 15u;
     for (uint32_t t0 = 4u * (wave - 1u); t0 < nb; t0 += 12u) {
         const uint32_t t = t0 + g;

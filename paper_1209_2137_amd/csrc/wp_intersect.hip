@@ -262,7 +262,7 @@ union IsectPageLds {
 };
 
 // Decodes the wanted entries of a patched-page stream (one wavefront per
-// 64-block segment of a page (SimplePFOR: per page), four per workgroup;
+// 64-block segment of a page, four per workgroup;
 // P32: exception arrays padded to 32 values).
 template <int KIND>
 __global__ __launch_bounds__(256) void k_isect_decode_fp(const uint32_t *__restrict__ in, uint64_t in_words,
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(256) void k_isect_decode_fp(const uint32_t *__restr
     if (!check_header(in, in_words, n, magic, kFpBlocks, H))
         return;  // reported by k_isect_flag_dir or k_range_bounds
     const uint32_t wave = uniform(threadIdx.x >> 6);
-    constexpr uint32_t per = KIND == kPageSp ? 1u : kPageSegs;
+    constexpr uint32_t per = kPageSegs;
     const uint64_t item = (uint64_t)blockIdx.x * 4 + wave;
     const uint64_t u = item / per;
     const uint32_t seg = (uint32_t)(item % per);
@@ -485,7 +485,7 @@ extern "C" int32_t wp_intersect_compressed(const uint32_t *a, uint64_t na, const
         hipLaunchKernelGGL((k_isect_decode_bp<true, false>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
                            b_comp, b_words, nb, a, na, 0u, 0u, b_work, ds->err);
     else if (codec == WP_CODEC_SP)
-        hipLaunchKernelGGL(k_isect_decode_fp<kPageSp>, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, b_comp,
+        hipLaunchKernelGGL(k_isect_decode_fp<kPageSp>, dim3((uint32_t)((nent * kPageSegs + 3) / 4)), dim3(256), 0, st, b_comp,
                            b_words, nb, a, na, 0u, 0u, b_work, ds->err);
     else if (codec == WP_CODEC_FP32)
         hipLaunchKernelGGL(k_isect_decode_fp<kPageFp32>, dim3((uint32_t)((nent * kPageSegs + 3) / 4)), dim3(256), 0, st, b_comp, b_words, nb,
@@ -536,7 +536,7 @@ extern "C" int32_t wp_decode_range(const uint32_t *in, uint64_t in_words, uint64
             hipLaunchKernelGGL((k_isect_decode_bp<true, false>), dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st,
                                in, in_words, n, nf, 0, key_lo, key_hi, out, ds->err);
         else if (codec == WP_CODEC_SP)
-            hipLaunchKernelGGL(k_isect_decode_fp<kPageSp>, dim3((uint32_t)((nent + 3) / 4)), dim3(256), 0, st, in,
+            hipLaunchKernelGGL(k_isect_decode_fp<kPageSp>, dim3((uint32_t)((nent * kPageSegs + 3) / 4)), dim3(256), 0, st, in,
                                in_words, n, nf, 0, key_lo, key_hi, out, ds->err);
         else if (codec == WP_CODEC_FP32)
             hipLaunchKernelGGL(k_isect_decode_fp<kPageFp32>, dim3((uint32_t)((nent * kPageSegs + 3) / 4)), dim3(256), 0, st, in, in_words, n, nf,

@@ -95,16 +95,22 @@ def test_encode_small_lengths_match_oracle(stride):
         assert_same(got, want, f"n={n}")
 
 
+def _sp_hdr_words(nb, stride):
+    """Words of a SimplePFOR page's header: 4, then stride bases and one
+    Simple-8b entry per 64-block segment after the first, padded to 4."""
+    return -(-(4 + (stride + 1) * (-(-nb // 64) - 1)) // 4) * 4
+
+
 def _selectors(stream):
     """Selectors of every Simple-8b word of a SimplePFOR stream's pages."""
     s = np.asarray(stream, dtype=np.uint32)
-    units, tail_off = int(s[4]), int(s[6])
+    S, units, tail_off = int(s[3]), int(s[4]), int(s[6])
     offs = [int(v) for v in s[8:8 + units]] + [tail_off]
     sels = set()
     for u in range(units):
         at = offs[u]
         nb, packed, meta_bytes, s8w = (int(v) for v in s[at:at + 4])
-        s8_at = at + 4 + packed + (meta_bytes + 15) // 16 * 4
+        s8_at = at + _sp_hdr_words(nb, S) + packed + (meta_bytes + 15) // 16 * 4
         sels |= {int(v) >> 28 for v in s[s8_at + 1:s8_at + s8w:2]}
     return sels
 
@@ -159,7 +165,14 @@ def test_full_size_patched_list():
     d[0] = (seg[0] - np.uint64(x[lo - 1])) % (1 << 32)
     d[1:] = (seg[1:] - seg[:-1]) % (1 << 32)
     ref = oracle.sp_encode(d.astype(np.uint32), 0)
-    assert np.array_equal(page, ref[int(ref[8]):int(ref[6])])
+    rp = ref[int(ref[8]):int(ref[6])]
+    # the same page but for its header: stride 1 adds the value before
+    # each of the seven later segments ahead of their Simple-8b entries
+    h1, h0 = _sp_hdr_words(512, 1), _sp_hdr_words(512, 0)
+    assert np.array_equal(page[:4], rp[:4])
+    assert np.array_equal(page[4:11], x[lo + 8192 - 1:lo + 65536 - 1:8192])
+    assert np.array_equal(page[11:18], rp[4:11])
+    assert np.array_equal(page[h1:], rp[h0:])
 
 
 def test_corrupt_streams_flagged_without_stray_writes():
@@ -178,6 +191,11 @@ def test_corrupt_streams_flagged_without_stray_writes():
         "packed_words": (unit + 1, int(s[unit + 1]) + 4),
         "meta_bytes": (unit + 2, int(s[unit + 2]) + 1),
         "s8_words": (unit + 3, int(s[unit + 3]) + 2),
+        "segment_base": (unit + 4 + 2, int(s[unit + 4 + 2]) + 1),
+        # a segment entry that starts one high part late (a later segment's
+        # sums then miss its first value)
+        "segment_entry": next((unit + 4 + 7 + g, int(s[unit + 4 + 7 + g]) - (1 << 24))
+                              for g in range(7) if int(s[unit + 4 + 7 + g]) >> 24),
     }
     for what, (at, val) in mutations.items():
         bad = s.copy()
@@ -188,7 +206,7 @@ def test_corrupt_streams_flagged_without_stray_writes():
         assert oracle.sp_decode_rc(bad, n) == oracle.ERR_CORRUPT, what
     # a Simple-8b word whose selector claims more high parts than remain
     nb, packed, meta_bytes, s8w = (int(v) for v in s[unit:unit + 4])
-    s8_at = unit + 4 + packed + (meta_bytes + 15) // 16 * 4
+    s8_at = unit + _sp_hdr_words(nb, 1) + packed + (meta_bytes + 15) // 16 * 4
     bad = s.copy()
     bad[s8_at + s8w - 1] = (int(bad[s8_at + s8w - 1]) & 0x0FFFFFFF) | (2 << 28)  # last word: sixty 1-bit parts
     rc, _ = gpu_decode(bad, n)

@@ -779,11 +779,20 @@ def test_simple8b_roundtrip_and_errors():
     assert oracle.s8_decode(np.array([(15 << 60) | (1 << 40)], np.uint64), 1)[0] == oracle.ERR_CORRUPT  # > 32 bits
 
 
-def test_simplepfor_pages_are_fastpfor_pages_but_for_the_exceptions():
+def _sp_hdr_words(nb, stride):
+    """Words of a SimplePFOR page's header: 4 fixed words, then for each
+    64-block segment after the first `stride` bases and one Simple-8b
+    entry, padded to 4."""
+    return -(-(4 + (stride + 1) * (-(-nb // 64) - 1)) // 4) * 4
+
+
+@pytest.mark.parametrize("stride", [0, 1, 4])
+def test_simplepfor_pages_are_fastpfor_pages_but_for_the_exceptions(stride):
     # Section 5: SimplePFOR and FastPFOR differ only in how the high parts
-    # of the exceptions are stored: same widths, packed values and metadata
+    # of the exceptions are stored: same widths, packed values, metadata and
+    # segment bases
     x = datagen.patched_gaps(2 * 65536 + 128 * 9 + 40, seed=83)
-    fp, sp = oracle.fp_encode(x, 1), oracle.sp_encode(x, 1)
+    fp, sp = oracle.fp_encode(x, stride), oracle.sp_encode(x, stride)
     assert np.array_equal(oracle.sp_decode(sp, x.size), x)
     units = int(fp[4])
     for u in range(units):
@@ -791,15 +800,56 @@ def test_simplepfor_pages_are_fastpfor_pages_but_for_the_exceptions():
         nb, packed, meta_bytes, bitset = (int(v) for v in fp[fo:fo + 4])
         assert [int(v) for v in sp[so:so + 3]] == [nb, packed, meta_bytes]
         nset = bin(bitset).count("1")
-        fh = _fp_hdr_words(nb, nset, 1)
+        nseg = -(-nb // 64)
+        assert np.array_equal(fp[fo + 4 + nset:fo + 4 + nset + stride * (nseg - 1)],
+                              sp[so + 4:so + 4 + stride * (nseg - 1)])
+        fh, sh = _fp_hdr_words(nb, nset, stride), _sp_hdr_words(nb, stride)
         meta_w = (meta_bytes + 15) // 16 * 4
-        assert np.array_equal(fp[fo + fh:fo + fh + packed + meta_w], sp[so + 4:so + 4 + packed + meta_w])
+        assert np.array_equal(fp[fo + fh:fo + fh + packed + meta_w], sp[so + sh:so + sh + packed + meta_w])
         # the Simple-8b array holds one high part per exception, in block order
         s8w = int(sp[so + 3])
-        words = sp[so + 4 + packed + meta_w:so + 4 + packed + meta_w + s8w].astype(np.uint64)
+        words = sp[so + sh + packed + meta_w:so + sh + packed + meta_w + s8w].astype(np.uint64)
         w64 = words[0::2] | (words[1::2] << np.uint64(32))
         k, hv = oracle.s8_decode(w64, meta_bytes - 3 * nb)
         assert k == meta_bytes - 3 * nb and (hv > 0).all()
+
+
+@pytest.mark.parametrize("stride", [0, 1, 4])
+def test_simplepfor_segment_entries_locate_each_segments_first_exception(stride):
+    # each segment's entry names the Simple-8b word holding the high part
+    # of its first exception (the exceptions of the blocks before it,
+    # counted from the metadata) and how many of that word's values come
+    # before it; counted here from the selectors with Section 2's table
+    count_of = _golden("simple8b_modes.json")["integers_coded"]
+    x = datagen.patched_gaps(3 * 65536 + 128 * 70 + 9, seed=86)
+    s = oracle.sp_encode(x, stride)
+    checked = 0
+    for u in range(int(s[4])):
+        so = int(s[8 + u])
+        nb, packed, meta_bytes, s8w = (int(v) for v in s[so:so + 4])
+        nseg = -(-nb // 64)
+        sh = _sp_hdr_words(nb, stride)
+        meta = s[so + sh + packed:].view(np.uint8)
+        counts = [int(c) for c in meta[2 * nb:3 * nb]]
+        meta_w = (meta_bytes + 15) // 16 * 4
+        words = s[so + sh + packed + meta_w:so + sh + packed + meta_w + s8w].astype(np.uint64)
+        sel = [int(w >> np.uint64(28)) for w in words[1::2]]
+        starts = np.concatenate([[0], np.cumsum([count_of[q] for q in sel])])
+        for g in range(1, nseg):
+            e = sum(counts[:64 * g])
+            ent = int(s[so + 4 + stride * (nseg - 1) + g - 1])
+            if e == starts[-1]:
+                assert ent == len(sel)
+            else:
+                w = int(np.searchsorted(starts, e, side="right")) - 1
+                assert ent == w | ((e - int(starts[w])) << 24), (u, g)
+            checked += 1
+    assert checked >= 3 * 7
+    # a wrong entry is rejected
+    so = int(s[8])
+    bad = s.copy()
+    bad[so + 4 + stride * 7] ^= 1
+    assert oracle.sp_decode_rc(bad, x.size) == oracle.ERR_CORRUPT
 
 
 @pytest.mark.parametrize("stride", [0, 1, 4])

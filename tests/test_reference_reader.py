@@ -167,26 +167,38 @@ def _fpi_page(w, nblocks):
     return out
 
 
-def _sp_page(w, nblocks):
+def _sp_page(w, nblocks, S):
     """SimplePFOR page: FastPFOR's packed values and metadata, the
     exceptions' high parts as one Simple-8b array (selector in the top four
-    bits of each 64-bit word, low 32-bit half first)."""
+    bits of each 64-bit word, low 32-bit half first); after the 4 header
+    words, S bases and then one Simple-8b entry for each 64-block segment
+    after the first (the word holding the segment's first high part | the
+    values of that word before it << 24). Returns the deltas and the
+    segment bases."""
     nb, packed, meta_bytes, s8_words = (int(v) for v in w[:4])
     assert nb == nblocks
-    at = 4
+    nseg = -(-nb // 64)
+    segb = [int(v) for v in w[4:4 + S * (nseg - 1)]]
+    entries = [int(v) for v in w[4 + S * (nseg - 1):4 + (S + 1) * (nseg - 1)]]
+    at = -(-(4 + (S + 1) * (nseg - 1)) // 4) * 4
+    assert not any(int(v) for v in w[4 + (S + 1) * (nseg - 1):at])
     packed_at = at
     at += packed
     meta = bytes(np.asarray(w[at:at + -(-meta_bytes // 16) * 4], dtype=np.uint32).tobytes())[:meta_bytes]
     at += -(-meta_bytes // 16) * 4
     b, mb, c = meta[:nb], meta[nb:2 * nb], meta[2 * nb:3 * nb]
     pos = meta[3 * nb:]
-    high = []
+    high, word_of = [], []
     for i in range(0, s8_words, 2):
         word = int(w[at + i]) | (int(w[at + i + 1]) << 32)
         cnt, bits = S8[word >> 60]
+        word_of += [(i // 2) | (j << 24) for j in range(cnt)]
         high += [(word >> (j * bits)) & ((1 << bits) - 1) if bits else 0 for j in range(cnt)]
     at += s8_words
     assert -(-at // 4) * 4 == len(w) and len(high) == len(pos)
+    for g in range(1, nseg):
+        e = sum(c[:64 * g])
+        assert entries[g - 1] == (word_of[e] if e < len(high) else s8_words // 2)
     out, p_at, blk_at = [], 0, packed_at
     for t in range(nb):
         vals = _fields(w[blk_at:blk_at + 4 * b[t]], 128, b[t])
@@ -196,7 +208,7 @@ def _sp_page(w, nblocks):
             vals[pos[p_at + j]] |= high[p_at + j] << b[t]
         p_at += c[t]
         out += vals
-    return out
+    return out, segb
 
 
 def read(stream, codec):
@@ -224,7 +236,7 @@ def read(stream, codec):
             elif codec == "bp32":
                 d = _bp32_unit(w, nb)
             elif codec == "sp":
-                d = _sp_page(w, nb)
+                d, segb = _sp_page(w, nb, S)
             elif codec == "fpi":
                 d = _fpi_page(w, nb)
             else:
@@ -237,7 +249,7 @@ def read(stream, codec):
         for i, v in enumerate(d):
             prev = (x[i - S] if i >= S else bases[i]) if S else 0
             x.append((v + prev) & 0xFFFFFFFF)
-        if u < units and codec in ("fp", "fp32"):
+        if u < units and codec in ("fp", "fp32", "sp"):
             # segment g's stored bases are the values just before it
             for i, v in enumerate(segb):
                 g, t = 1 + i // S, i % S
