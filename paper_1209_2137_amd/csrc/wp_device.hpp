@@ -432,7 +432,12 @@ __device__ __forceinline__ void scan_wave4(uint32_t (&x)[4], uint32_t (&carry)[4
 // the counts their selectors give places each word's integers, and the
 // words are loaded one batch ahead.
 enum : int { kPageFp = 0, kPageFp32 = 1, kPageSp = 2, kPageFpi = 3 };
-constexpr uint32_t kSpRing = 2048;  // high parts held by a SimplePFOR segment's ring
+// High parts held by a SimplePFOR segment's ring: the next pass's beyond
+// its first 64 (those are fetched into registers), the fetched pass's, and
+// one Simple-8b word: at most 4 * 102 - 64 + 4 * 102 + 59, since the cost
+// rule never keeps more than 102 exceptions in a block (c (8 + maxb - b)
+// < 128 (maxb - b)); a pass holding more is flagged.
+constexpr uint32_t kSpRing = 1024;
 constexpr uint32_t kSegBlocks = 64;  // blocks per segment of a patched page
 constexpr uint32_t kSegInts = kSegBlocks * kBlock;
 constexpr uint32_t kPageSegs = kFpBlocks / kSegBlocks;
@@ -982,7 +987,9 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
 
     const uint32_t qq = lane & 31u;
     uint32_t *const xw = &L.buf[jl * kBlock + qq];  // integer q of the lane's block of half 0
-    auto run_pass = [&](uint32_t p, FpFetch &f) __attribute__((always_inline)) {
+    // f: pass p, fetched; nx: pass p + 1, fetched (its exceptions beyond the
+    // first 64 still read from the ring while f is refetched for p + 2)
+    auto run_pass = [&](uint32_t p, FpFetch &f, const FpFetch &nx) __attribute__((always_inline)) {
         fill_to(f.pe);
         wave_lds_order();
         uint32_t v[2][4];
@@ -1048,7 +1055,7 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
             }
         }
         // beyond the page it reads nothing; the ring keeps the next pass's high parts
-        f = fetch(p + 2, f.e0 + f.ce);
+        f = fetch(p + 2, nx.e0 + (nx.ce < 64u ? nx.ce : 64u));
         wave_lds_order();
         const uint4 t0 = *reinterpret_cast<const uint4 *>(&L.buf[4 * lane]);
         const uint4 t1 = *reinterpret_cast<const uint4 *>(&L.buf[256 + 4 * lane]);
@@ -1086,16 +1093,16 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
     };
     // the ring keeps high parts from the segment's first exception on
     FpFetch f0 = fetch(0, wS);
-    FpFetch f1 = fetch(1, wS);
+    FpFetch f1 = fetch(1, wS + (f0.ce < 64u ? f0.ce : 64u));
     for (uint32_t p = 0; p < npass; p += 2) {
         if (p > 0 && (p & 15u) == 0) {
             // round p / 16 starts: build the next one, load the one after
             build_round((p >> 4) + 1, m0, m1, m2);
             load_meta((p >> 4) + 2, m0, m1, m2);
         }
-        run_pass(p, f0);
+        run_pass(p, f0, f1);
         if (p + 1 < npass)
-            run_pass(p + 1, f1);
+            run_pass(p + 1, f1, f0);
         if constexpr (!WHOLE) {
             if (p == 2) {
                 uint32_t t = 0;

@@ -343,7 +343,7 @@ def test_patched_corrupt_metadata_flagged():
     assert rc == wp.OK and np.array_equal(got, x)
 
 
-DELTA_SIZES = [1, 3, 4, 5, 4095, 4096, 4097, 12345, 1 << 20, (1 << 22) + 3]
+DELTA_SIZES = [1, 3, 4, 5, 4095, 4096, 4097, 12345, 32767, 32768, 32769, 3 * 32768 + 5, 1 << 20, (1 << 22) + 3]
 
 
 @pytest.mark.parametrize("stride", [1, 4])

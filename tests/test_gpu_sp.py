@@ -217,3 +217,32 @@ def test_corrupt_streams_flagged_without_stray_writes():
     assert rc == wp.ERR_CORRUPT
     rc, got = gpu_decode(s, n)
     assert rc == wp.OK and np.array_equal(got, x)
+
+
+@pytest.mark.parametrize("wide_frac", [0.5, 0.7])
+def test_exception_heavy_pages(wide_frac):
+    # most values of each block wide: the cost rule keeps up to about 90
+    # exceptions in a block (never more than 102), so a pass of four blocks
+    # can bring some 360 high parts into the segment's ring; GPU encode
+    # equals the oracle's stream and the GPU decode gives the input back,
+    # for every stride
+    rng = np.random.default_rng(int(wide_frac * 100) + 7)
+    n = 2 * 65536 + 128 * 70 + 3
+    small = rng.integers(0, 16, size=n, dtype=np.uint64)
+    wide = rng.integers(1 << 20, 1 << 24, size=n, dtype=np.uint64)
+    x = np.where(rng.random(n) < wide_frac, wide, small).astype(np.uint32)
+    for stride in (0, 1, 4):
+        print(f"sp exception-heavy wide_frac={wide_frac} stride={stride}", flush=True)
+        want = oracle.sp_encode(x, stride)
+        got = to_host(wp.encode_trimmed(to_dev(x), wp.CODEC_SP, stride))
+        assert got.size == want.size
+        assert_same(got, want, f"wide_frac={wide_frac} stride={stride}")
+        rc, back = gpu_decode(got, n)
+        assert rc == wp.OK
+        assert_same(back, x)
+    # the heaviest block's exceptions
+    s = oracle.sp_encode(x, 0)
+    at = int(s[8])
+    nb, packed = int(s[at]), int(s[at + 1])
+    meta = s[at + -(-(4 + 7) // 4) * 4 + packed:].view(np.uint8)
+    print(f"most exceptions in a block: {int(meta[2 * nb:3 * nb].max())}", flush=True)
