@@ -199,7 +199,10 @@ int32_t simplepfor_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, 
 
 /* SimplePFOR decoder: as fastpfor_decode (one wavefront per 64-block
  * segment), the high parts taken from the page's Simple-8b words, decoded
- * from the segment's entry on as its blocks need them. Allocates nothing. */
+ * from the segment's entry on as its blocks need them. A page whose blocks
+ * hold more exceptions than the cost rule ever keeps (over 102 in a block,
+ * in passes that would overfill the segment's ring of high parts) is
+ * reported as corrupt. Allocates nothing. */
 int32_t simplepfor_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, uint64_t n,
                           void *stream);
 
