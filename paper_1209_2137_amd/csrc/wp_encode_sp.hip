@@ -4,23 +4,43 @@
 // encoder's analysis kernel); the exceptions' high parts of a page, in
 // block order, are coded once with Simple-8b.
 //
-// Simple-8b's greedy choice is sequential: the next word starts where the
-// previous one ended. One wavefront per page walks it. The page's high
-// parts stream, block by block, into a 512-entry LDS window (each block's
-// exceptions found with ballots); for the next word the 64 lanes take the
-// next 64 high parts' widths, a prefix maximum over the lanes gives the
-// widest of the first c for every c, and lane s tests selector s (count
-// available, widest of its first `count` within its width) at once. The
-// first selector that passes is the greedy one. High parts are never zero
-// (an exception is wider than its block's width), so selectors 0 and 1
-// (runs of zeros) never pass and only selectors 2..15 are tested.
+// One workgroup of four wavefronts per page, in chunks of blocks whose
+// exceptions fit a 4096-entry LDS ring (a page's 7000 or so exceptions in
+// two chunks; at most 102 per block under the cost rule, so a chunk holds at
+// least nine groups of four blocks). Per chunk:
+//  1. gather: the wavefronts load four blocks at a time (64 lanes, eight
+//     values each), find each block's exceptions (16 lanes per block) and put
+//     their high parts and widths into the ring at their index in the page;
+//     the packer also writes the blocks' low bits and the metadata bytes;
+//  2. counts: Simple-8b's greedy choice at a position depends only on the
+//     high parts from there on, so every position gets, in parallel, the
+//     number of values the greedy word starting there would hold: the largest
+//     count whose width holds the widest of that many values (a count that
+//     fits makes every smaller count fit, so the scan stops at the first
+//     that does not: three or four values of width near 17 are read);
+//  3. walk: the word starts are the chain 0, 0 + count(0), ...; wavefront 0
+//     splits the chunk's positions into 64 ranges and each lane walks the
+//     chain from its range's first position, marking word starts in a
+//     bitmap, up to the next range. A lane whose true entry (where the lane
+//     before left its range) differs from its start walks again from there
+//     until it meets a marked position of its own chain (greedy parses
+//     resynchronise), clears what it had marked before that point, and
+//     hands on its exit if the new chain left the range elsewhere; rounds
+//     repeat until no entry changes (at most 64 rounds: lane r is final
+//     after round r);
+//  4. the size kernel counts the marks; the packer numbers them (prefix
+//     counts over the bitmap words) and every thread assembles the words
+//     starting at its positions, and the segment entries they hold.
+// The chunk's counts are computed for positions whose 60 following high
+// parts are in the ring (the last 59 of a chunk wait for the next one, which
+// the ring keeps them for), and the walk stops at the first word start
+// beyond them.
 //
-// Two passes, as for every unit: k_sp_size runs the coding to size each
-// page (packed words, metadata, Simple-8b words), the chained scan turns
-// sizes into offsets, and k_sp_pack writes the page: its header, the
+// Two passes, as for every unit: k_sp_page<S, false> sizes each page
+// (packed words, metadata, Simple-8b words), the chained scan turns sizes
+// into offsets, and k_sp_page<S, true> writes the page: its header, the
 // blocks' low bits, the metadata bytes (widths, maximum widths, counts,
-// positions) and, from one wavefront, the same coding again, now writing
-// its words.
+// positions) and the words.
 #include "wp_device.hpp"
 #include "wp_host.hpp"
 
@@ -28,31 +48,16 @@ namespace wp {
 
 namespace {
 
-constexpr uint32_t kSpWin = 512;  // high parts held by a page's coding window
+constexpr uint32_t kSpThreads = 256;
+constexpr uint32_t kSpWaves = kSpThreads / 64;
+constexpr uint32_t kSpR = 4096;                 // ring of a page's high parts, by index mod kSpR
+constexpr uint32_t kSpChunkExc = kSpR - 64;     // a chunk's exceptions: the ring keeps the 59 before them too
+constexpr uint32_t kSpQuadInts = 4u * kBlock;   // a wavefront's step: four blocks, eight values a lane
+constexpr uint32_t kSpDepth = 4;                // steps a wavefront loads before coding them
+constexpr uint32_t kSpBm = kSpR / 32;           // bitmap words of a chunk's word starts
+static_assert(kSpChunkExc >= 4u * 102u, "a chunk holds at least one step's exceptions");
 
 __device__ __forceinline__ uint32_t sp_nbits(uint32_t x) { return 32u - (uint32_t)__clz((int)x); }
-
-__device__ __forceinline__ uint32_t sp_delta(const uint32_t *__restrict__ x, uint64_t i, uint32_t S)
-{
-    const uint32_t v = x[i];
-    if (S == 0)
-        return v;
-    return i >= S ? v - x[i - S] : v;
-}
-
-// Inclusive maximum over the 64 lanes (values >= 0): row steps, then the
-// two row broadcasts, as in wave_scan_incl.
-__device__ __forceinline__ uint32_t wave_max_incl(uint32_t v)
-{
-    auto step = [&](uint32_t o) __attribute__((always_inline)) { v = o > v ? o : v; };
-    step(__builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, false));
-    step(__builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, false));
-    step(__builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, false));
-    step(__builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, false));
-    step(__builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false));
-    step(__builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false));
-    return v;
-}
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return wave_read(wave_scan_incl(v), 63); }
 
@@ -63,134 +68,115 @@ __device__ __forceinline__ uint32_t sp_hdr_words(uint32_t nb, uint32_t S)
     return pad4(4u + (S + 1u) * (page_items<kPageFp>(nb) - 1u));
 }
 
-// The greedy Simple-8b coding of page `p`'s high parts (nexc of them), by
-// one wavefront; with WRITE the words go to s8 (two 32-bit words each, low
-// half first), and the entry of each segment g = 1 .. nseg - 1 (seg_e[g]:
-// the exceptions before it) to entries[g - 1]: the index of the word
-// holding high part seg_e[g] | the word's values before it << 24, or the
-// word count when seg_e[g] = nexc. Returns the number of 64-bit words
-// (uniform).
-template <uint32_t S, bool WRITE>
-__device__ uint32_t sp_code(const uint32_t *__restrict__ x, uint64_t pstart, uint32_t nb,
-                            const uint8_t *__restrict__ mb, const uint8_t *__restrict__ mc, uint32_t nexc,
-                            uint32_t *__restrict__ s8, uint32_t *win, const uint32_t *seg_e = nullptr,
-                            uint32_t nseg = 1, uint32_t *__restrict__ entries = nullptr)
+// Simple-8b's non-zero modes by increasing count (selectors 15 down to 2):
+// values per word and their width.
+constexpr uint32_t kS8Modes = 14;
+__device__ constexpr uint8_t kS8Cnt[kS8Modes] = {1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 15, 20, 30, 60};
+__device__ constexpr uint8_t kS8Bits[kS8Modes] = {60, 30, 20, 15, 12, 10, 8, 7, 6, 5, 4, 3, 2, 1};
+
+// Values in the greedy word starting at position p (avail high parts from
+// p on, widths in the ring): the largest count whose width holds the widest
+// of its first `count` values. Count 1 always fits (a high part has at most
+// 32 bits).
+__device__ __forceinline__ uint32_t sp_greedy_count(const uint8_t *__restrict__ wd, uint32_t p, uint32_t avail)
 {
-    const uint32_t lane = lane_id();
-    // selector tested by this lane (2..15): its count and width
-    const uint32_t my_sel = lane >= 2 && lane <= 15 ? lane : 15u;
-    const uint32_t my_md = s8_mode(my_sel);
-    const uint32_t my_cnt = my_md & 255u, my_bits = my_md >> 8;
-    uint32_t t = 0, produced = 0, i = 0, words = 0;
-    while (i < nexc) {
-        // the window holds at least the next 64 high parts (or all that are left)
-        while (t < nb && produced - i < 64u) {
-            const uint32_t b = uniform(mb[t]), c = uniform(mc[t]);
-            if (c != 0u) {
-                const uint64_t j0 = pstart + (uint64_t)t * kBlock + lane;
-                const uint32_t d0 = sp_delta(x, j0, S), d1 = sp_delta(x, j0 + 64, S);
-                const bool e0 = sp_nbits(d0) > b, e1 = sp_nbits(d1) > b;
-                const uint64_t m0 = ballot(e0), m1 = ballot(e1);
-                const uint32_t n0 = (uint32_t)__builtin_popcountll(m0);
-                if (e0)
-                    win[(produced + lanes_below(m0)) & (kSpWin - 1u)] = d0 >> b;
-                if (e1)
-                    win[(produced + n0 + lanes_below(m1)) & (kSpWin - 1u)] = d1 >> b;
-                produced += n0 + (uint32_t)__builtin_popcountll(m1);
-                wave_lds_order();
-            }
-            ++t;
+    uint32_t w = 0, best = 1;
+#pragma unroll
+    for (uint32_t j = 0; j < kS8Modes; ++j) {
+        const uint32_t c = kS8Cnt[j];
+        if (c > avail)
+            break;
+#pragma unroll
+        for (uint32_t m = j ? kS8Cnt[j - 1] : 0u; m < c; ++m) {
+            const uint32_t v = wd[(p + m) & (kSpR - 1u)];
+            w = v > w ? v : w;
         }
-        const uint32_t avail = nexc - i;
-        const bool live = lane < avail;
-        const uint32_t hv = live ? win[(i + lane) & (kSpWin - 1u)] : 0u;
-        const uint32_t widest = wave_max_incl(live ? sp_nbits(hv) : 64u);
-        // widest of the first my_cnt high parts
-        const uint32_t wc = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((my_cnt - 1u) * 4u), (int)widest);
-        const bool pass = lane >= 2 && lane <= 15 && my_cnt <= avail && wc <= my_bits;
-        const uint32_t sel = (uint32_t)__builtin_ctzll(ballot(pass));  // selector 15 always passes
-        const uint32_t md = s8_mode(sel);
-        const uint32_t cnt = md & 255u, bits = md >> 8;
-        if constexpr (WRITE) {
-            // the fields do not overlap: their sum is the word
-            const uint64_t f = lane < cnt ? (uint64_t)hv << (lane * bits) : 0ull;
-            const uint32_t lo = wave_sum((uint32_t)f), hi = wave_sum((uint32_t)(f >> 32)) | (sel << 28);
-            if (lane == 0) {
-                s8[2 * words] = lo;
-                s8[2 * words + 1] = hi;
-            }
-            // lane g: segment g's first high part in this word?
-            if (lane >= 1 && lane < nseg) {
-                const uint32_t e = seg_e[lane];
-                if (e >= i && e < i + cnt)
-                    entries[lane - 1] = words | ((e - i) << 24);
-            }
-        }
-        ++words;
-        i += cnt;
-        wave_lds_order();
+        if (w > kS8Bits[j])
+            break;
+        best = c;
     }
-    if constexpr (WRITE) {
-        if (lane >= 1 && lane < nseg && seg_e[lane] >= nexc)
-            entries[lane - 1] = words;
-    }
-    return words;
+    return best;
 }
 
-// Packed words and exceptions of page p from its blocks' metadata: sums
-// over the blocks (uniform).
-__device__ __forceinline__ void sp_page_sums(const uint8_t *__restrict__ mb, const uint8_t *__restrict__ mc,
-                                             uint32_t nb, uint32_t &packed, uint32_t &nexc)
+// Selector of the word holding `count` values.
+__device__ __forceinline__ uint32_t sp_selector(uint32_t count)
 {
-    const uint32_t lane = lane_id();
-    uint32_t pw = 0, ne = 0;
-    for (uint32_t t = lane; t < nb; t += 64) {
-        pw += 4u * mb[t];
-        ne += mc[t];
+    uint32_t j = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kS8Modes - 1; ++i)
+        j += count > kS8Cnt[i] ? 1u : 0u;
+    return 15u - j;
+}
+
+template <bool WRITE>
+struct SpLds {
+    uint32_t exc[kFpBlocks + 1];          // exceptions before block t in the page (exc[nb]: all)
+    uint32_t blk[WRITE ? kFpBlocks + 1 : 1];  // block t's first packed word, from the packed region
+    uint32_t hv[WRITE ? kSpR : 1];        // high parts (ring)
+    uint32_t bm[WRITE ? kSpBm : 1];                   // word starts of the chunk: bit q - pos0 (packer)
+    uint32_t bmpre[WRITE ? kSpBm : 1];    // words of the page before each bitmap word
+    uint32_t sege[kPageSegs];             // exceptions before each segment
+    uint32_t pos0;                        // the chain's first word start in the chunk
+    uint32_t pw;                          // packed words of the page
+    uint8_t b[kFpBlocks], mb[kFpBlocks], c[kFpBlocks];
+    uint8_t wd[kSpR];                     // widths of the high parts (ring)
+    // cnt: values of the greedy word starting there (ring); xo: where the
+    // chain from there leaves its window, past the window's end. Both are
+    // dead while a chunk is gathered: the packer stages each wavefront's
+    // low bits there (512 words a wavefront: four blocks of at most 128)
+    uint32_t cx[kSpR / 2];
+    __device__ uint8_t *cnt() { return reinterpret_cast<uint8_t *>(cx); }
+    __device__ uint8_t *xo() { return reinterpret_cast<uint8_t *>(cx) + kSpR; }
+};
+static_assert(kSpR / 2 >= kSpWaves * 4u * 4u * 32u, "a wavefront's step of low bits fits the staging area");
+
+// Deltas of the eight values of lane `lane` in step q of the page (values
+// 512 q + 8 lane ...), from the step's two loads and, for lane 0, the four
+// values before the step.
+template <uint32_t S>
+__device__ __forceinline__ void sp_deltas(const uint4 &a, const uint4 &bq, const uint4 &pv, uint32_t lane,
+                                          uint32_t (&d)[8])
+{
+    const uint32_t v[8] = {a.x, a.y, a.z, a.w, bq.x, bq.y, bq.z, bq.w};
+    if constexpr (S == 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            d[k] = v[k];
+    } else if constexpr (S == 1) {
+        uint32_t prev = (uint32_t)__shfl_up((int)v[7], 1, 64);
+        if (lane == 0)
+            prev = pv.w;
+        d[0] = v[0] - prev;
+#pragma unroll
+        for (int k = 1; k < 8; ++k)
+            d[k] = v[k] - v[k - 1];
+    } else {
+        uint32_t p[4] = {(uint32_t)__shfl_up((int)v[4], 1, 64), (uint32_t)__shfl_up((int)v[5], 1, 64),
+                         (uint32_t)__shfl_up((int)v[6], 1, 64), (uint32_t)__shfl_up((int)v[7], 1, 64)};
+        if (lane == 0)
+            p[0] = pv.x, p[1] = pv.y, p[2] = pv.z, p[3] = pv.w;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            d[k] = v[k] - p[k];
+#pragma unroll
+        for (int k = 4; k < 8; ++k)
+            d[k] = v[k] - v[k - 4];
     }
-    packed = wave_sum(pw);
-    nexc = wave_sum(ne);
 }
 
 }  // namespace
 
-// One wavefront per page: the page's length in words.
-template <uint32_t S>
-__global__ __launch_bounds__(64) void k_sp_size(const uint32_t *__restrict__ x, uint64_t n,
-                                                const uint8_t *__restrict__ meta, uint64_t nblk,
-                                                uint32_t *__restrict__ sizes)
+// One workgroup per page. WRITE = false: the page's length in words into
+// sizes[p]. WRITE = true: the page at its offset (incl: inclusive sums of
+// the page lengths), its directory entry, header, low bits, metadata and
+// Simple-8b words.
+template <uint32_t S, bool WRITE>
+__global__ __launch_bounds__(kSpThreads) void k_sp_page(const uint32_t *__restrict__ x, uint64_t n,
+                                                        const uint8_t *__restrict__ meta, uint64_t nblk,
+                                                        uint32_t *__restrict__ sizes, uint32_t dir_end,
+                                                        uint32_t *__restrict__ out)
 {
-    __shared__ uint32_t win[kSpWin];
-    const uint64_t p = blockIdx.x;
-    const uint64_t nfull = n / kBlock;
-    const uint64_t left = nfull - p * kFpBlocks;
-    const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
-    const uint8_t *mb = meta + p * kFpBlocks, *mm = meta + nblk + p * kFpBlocks, *mc = meta + 2 * nblk + p * kFpBlocks;
-    (void)mm;
-    uint32_t packed, nexc;
-    sp_page_sums(mb, mc, nb, packed, nexc);
-    const uint32_t words = sp_code<S, false>(x, p * kFpUnitInts, nb, mb, mc, nexc, nullptr, win);
-    const uint32_t meta_w = ((3u * nb + nexc + 15u) / 16u) * 4u;
-    if (lane_id() == 0)
-        sizes[p] = pad4(sp_hdr_words(nb, S) + packed + meta_w + 2u * words);
-}
-
-// One workgroup of four wavefronts per page: wavefront 0 writes the page
-// header (with the segment bases and entries) and codes the high parts
-// into their place; the others write the packed low bits (16 lanes per
-// block, each eight values = b whole bytes) and the metadata bytes, and
-// clear the metadata's padding.
-template <uint32_t S>
-__global__ __launch_bounds__(256) void k_sp_pack(const uint32_t *__restrict__ x, uint64_t n,
-                                                 const uint8_t *__restrict__ meta, uint64_t nblk,
-                                                 const uint32_t *__restrict__ incl, uint32_t dir_end,
-                                                 uint32_t *__restrict__ out)
-{
-    __shared__ uint32_t win[kSpWin];
-    __shared__ uint32_t s_blk[kFpBlocks];  // block t's first packed word (from the packed region)
-    __shared__ uint32_t s_exc[kFpBlocks];  // block t's first exception in the page
-    __shared__ uint32_t s_tot[2];
-    __shared__ uint32_t s_sege[kPageSegs];  // exceptions before each segment
+    __shared__ SpLds<WRITE> L;
     const uint64_t p = blockIdx.x;
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = lane_id();
@@ -198,45 +184,272 @@ __global__ __launch_bounds__(256) void k_sp_pack(const uint32_t *__restrict__ x,
     const uint64_t nfull = n / kBlock;
     const uint64_t left = nfull - p * kFpBlocks;
     const uint32_t nb = (uint32_t)(left < kFpBlocks ? left : kFpBlocks);
-    const uint8_t *mb = meta + p * kFpBlocks, *mm = meta + nblk + p * kFpBlocks, *mc = meta + 2 * nblk + p * kFpBlocks;
     const uint64_t pstart = p * kFpUnitInts;
-    // block offsets: exclusive sums of 4b and c in block order (wavefront 0)
+    // the page's metadata, then exclusive sums of 4b and c in block order
+    for (uint32_t t = tid; t < nb; t += kSpThreads) {
+        L.b[t] = meta[p * kFpBlocks + t];
+        L.mb[t] = meta[nblk + p * kFpBlocks + t];
+        L.c[t] = meta[2 * nblk + p * kFpBlocks + t];
+    }
+    __syncthreads();
     if (wave == 0) {
         uint32_t cw = 0, cc = 0;
         for (uint32_t t0 = 0; t0 < nb; t0 += 64) {
             const uint32_t t = t0 + lane;
-            const uint32_t bw = t < nb ? 4u * mb[t] : 0u, c = t < nb ? (uint32_t)mc[t] : 0u;
+            const uint32_t bw = t < nb ? 4u * L.b[t] : 0u, c = t < nb ? (uint32_t)L.c[t] : 0u;
             const uint32_t iw = wave_scan_incl(bw), ic = wave_scan_incl(c);
             if (t < nb) {
-                s_blk[t] = cw + iw - bw;
-                s_exc[t] = cc + ic - c;
+                if constexpr (WRITE)
+                    L.blk[t] = cw + iw - bw;
+                L.exc[t] = cc + ic - c;
             }
             cw += wave_read(iw, 63);
             cc += wave_read(ic, 63);
         }
         if (lane == 0)
-            s_tot[0] = cw, s_tot[1] = cc;
+            L.exc[nb] = cc;
+        if (lane == 0) {
+            L.pw = cw;
+            if constexpr (WRITE)
+                L.blk[nb] = cw;
+        }
     }
     __syncthreads();
-    const uint32_t packed = s_tot[0], nexc = s_tot[1];
+    const uint32_t nexc = L.exc[nb];
     const uint32_t nseg = page_items<kPageFp>(nb), hw = sp_hdr_words(nb, S);
-    if (wave == 0 && lane < kPageSegs)
-        s_sege[lane] = lane < nseg ? s_exc[kSegBlocks * lane] : 0u;
     const uint32_t meta_bytes = 3u * nb + nexc;
     const uint32_t meta_w = ((meta_bytes + 15u) / 16u) * 4u;
-    const uint32_t size = incl[p] - (p ? incl[p - 1] : 0u);
-    const uint32_t off = dir_end + incl[p] - size;
-    const uint32_t s8_at = hw + packed + meta_w;
-    const uint32_t s8w = size - s8_at;  // Simple-8b words and the page's end padding
-    write_dir_entry(out, p, dir_entries(n, kFpBlocks), S, off, x, pstart);
-    uint32_t *page = out + off;
-    if (wave == 0) {
-        wave_lds_order();
-        const uint32_t words = sp_code<S, true>(x, pstart, nb, mb, mc, nexc, page + s8_at, win, s_sege, nseg,
-                                                page + 4 + S * (nseg - 1u));
+    const uint32_t packed = L.pw;
+    uint32_t off = 0, s8_at = 0, s8w = 0;
+    uint32_t *page = nullptr;
+    uint8_t *md = nullptr;
+    if constexpr (WRITE) {
+        if (tid < kPageSegs)
+            L.sege[tid] = tid < nseg ? L.exc[kSegBlocks * tid] : 0u;
+        const uint32_t size = sizes[p] - (p ? sizes[p - 1] : 0u);
+        off = dir_end + sizes[p] - size;
+        s8_at = hw + packed + meta_w;
+        s8w = size - s8_at;  // Simple-8b words and the page's end padding
+        write_dir_entry(out, p, dir_entries(n, kFpBlocks), S, off, x, pstart);
+        page = out + off;
+        md = reinterpret_cast<uint8_t *>(page + hw + packed);
+    }
+    const BufRsrc rs = make_rsrc(x + pstart, nb * kBlock * 4u);
+    const uint32_t nq = (nb + 3u) / 4u;
+    auto exc_q = [&](uint32_t q) __attribute__((always_inline)) { return L.exc[4u * q < nb ? 4u * q : nb]; };
+    uint32_t qa = 0, lo = 0;
+    uint32_t pos = 0, words = 0;  // wavefront 0: the chain's next word start, words so far
+    while (qa < nq) {
+        // the chunk: steps [qa, qb) with at most kSpChunkExc exceptions
+        const uint32_t ea = exc_q(qa);
+        uint32_t qb = qa + 1u, hiq = nq;
+        while (qb < hiq) {  // largest qb with exc_q(qb) - ea <= kSpChunkExc
+            const uint32_t mid = (qb + hiq + 1u) / 2u;
+            if (exc_q(mid) - ea <= kSpChunkExc)
+                qb = mid;
+            else
+                hiq = mid - 1u;
+        }
+        const uint32_t eb = exc_q(qb);
+        const uint32_t hi = qb == nq ? nexc : (eb >= lo + 59u ? eb - 59u : lo);
+        if (tid == 0)
+            L.pos0 = pos;  // the chain's first word start in this chunk
+        // 1. gather
+        for (uint32_t q0 = qa + wave; q0 < qb; q0 += kSpWaves * kSpDepth) {
+            uint4 va[kSpDepth], vb[kSpDepth], pv[kSpDepth];
+#pragma unroll
+            for (uint32_t d = 0; d < kSpDepth; ++d) {
+                const uint32_t q = q0 + kSpWaves * d;
+                pv[d] = make_uint4(0, 0, 0, 0);
+                if (q < qb) {
+                    va[d] = buf_load_u4(rs, (q * kSpQuadInts + 8u * lane) * 4u);
+                    vb[d] = buf_load_u4(rs, (q * kSpQuadInts + 8u * lane + 4u) * 4u);
+                    if (S != 0 && lane == 0) {
+                        if (q != 0)
+                            pv[d] = buf_load_u4(rs, (q * kSpQuadInts - 4u) * 4u);
+                        else if (pstart >= 4)
+                            pv[d] = make_uint4(x[pstart - 4], x[pstart - 3], x[pstart - 2], x[pstart - 1]);
+                    }
+                }
+            }
+#pragma unroll
+            for (uint32_t d = 0; d < kSpDepth; ++d) {
+                const uint32_t q = q0 + kSpWaves * d;
+                if (q >= qb)
+                    break;
+                uint32_t dv[8];
+                sp_deltas<S>(va[d], vb[d], pv[d], lane, dv);
+                const uint32_t t = 4u * q + (lane >> 4), r = lane & 15u;
+                const bool in = t < nb;
+                const uint32_t b = in ? (uint32_t)L.b[t] : 32u;
+                uint32_t emask = 0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    emask |= (sp_nbits(dv[k]) > b ? 1u : 0u) << k;
+                const uint32_t ce = (uint32_t)__builtin_popcount(emask);
+                const uint32_t incl16 = row_scan_incl(ce);  // rows of 16 lanes are the blocks
+                uint32_t at = in ? L.exc[t] + incl16 - ce : 0u;
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if ((emask >> k) & 1u) {
+                        const uint32_t slot = at & (kSpR - 1u);
+                        L.wd[slot] = (uint8_t)(sp_nbits(dv[k]) - b);
+                        if constexpr (WRITE) {
+                            L.hv[slot] = dv[k] >> b;
+                            md[3u * nb + at] = (uint8_t)(8u * r + k);
+                        }
+                        ++at;
+                    }
+                if constexpr (WRITE) {
+                    // low b bits of the eight values: b bytes from byte b * r
+                    // of the block, staged with the step's other blocks (whose
+                    // packed words follow one another), then stored as words
+                    const uint32_t w0 = L.blk[4u * q];
+                    uint8_t *const st = reinterpret_cast<uint8_t *>(L.cx + 512u * wave);
+                    if (in) {
+                        const uint32_t m = width_mask(b);
+                        uint64_t acc = 0;
+                        uint32_t nbit = 0, o = 4u * (L.blk[t] - w0) + b * r;
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) {
+                            acc |= (uint64_t)(dv[k] & m) << nbit;
+                            nbit += b;
+                            while (nbit >= 8u) {
+                                st[o++] = (uint8_t)acc;
+                                acc >>= 8;
+                                nbit -= 8u;
+                            }
+                        }
+                        if (r == 0) {
+                            md[t] = (uint8_t)b;
+                            md[nb + t] = L.mb[t];
+                            md[2u * nb + t] = L.c[t];
+                        }
+                    }
+                    wave_lds_order();
+                    const uint32_t nw4 = L.blk[4u * q + 4u < nb ? 4u * q + 4u : nb] - w0;
+                    uint32_t *const pkw = page + hw + w0;
+                    for (uint32_t i = lane; i < nw4; i += 64u)
+                        pkw[i] = L.cx[512u * wave + i];
+                    wave_lds_order();
+                }
+            }
+        }
+        __syncthreads();
+        // 2. greedy counts of positions [lo, hi)
+        for (uint32_t q = lo + tid; q < hi; q += kSpThreads)
+            L.cnt()[q & (kSpR - 1u)] = (uint8_t)sp_greedy_count(L.wd, q, nexc - q);
+        __syncthreads();
+        // 3. the chain from pos0 through [pos0, hi), by windows of 64
+        // positions from pos0. (a) every position's exit from its window: the
+        // chain's first position at or past the window's end, by pointer
+        // jumping within the window (six rounds cover 64 steps), four windows
+        // a wavefront at a time
+        const uint32_t pos0 = L.pos0;
+        const uint32_t span = hi > pos0 ? hi - pos0 : 0u;
+        const uint32_t nw = (span + 63u) / 64u;  // at most kSpR / 64
+        for (uint32_t w0 = wave; w0 < nw; w0 += 4u * kSpWaves) {
+            uint32_t X[4], lim[4];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                const uint32_t w = w0 + kSpWaves * u, base = pos0 + 64u * w;
+                lim[u] = w < nw ? (hi - base < 64u ? hi - base : 64u) : 0u;
+                const uint32_t c = lane < lim[u] ? (uint32_t)L.cnt()[(base + lane) & (kSpR - 1u)] : 0u;
+                X[u] = lane + (c ? c : (lane < lim[u] ? 1u : 0u));
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u) {
+                    const bool inside = X[u] < lim[u];
+                    const uint32_t t = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(4u * (inside ? X[u] : lane)),
+                                                                              (int)X[u]);
+                    X[u] = inside ? t : X[u];
+                }
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u)
+                if (lane < lim[u])
+                    L.xo()[(pos0 + 64u * (w0 + kSpWaves * u) + lane) & (kSpR - 1u)] = (uint8_t)(X[u] - lim[u]);
+        }
+        __syncthreads();
+        if (wave == 0) {
+            // (b) the windows' entries, one after the other: lane w keeps
+            // window w's
+            uint32_t e = pos0, mine = 0;
+            for (uint32_t w = 0; w < nw; ++w) {
+                mine = lane == w ? e : mine;
+                const uint32_t base = pos0 + 64u * w;
+                const uint32_t end = base + (hi - base < 64u ? hi - base : 64u);
+                e = e < end ? end + uniform((uint32_t)L.xo()[e & (kSpR - 1u)]) : e;
+            }
+            pos = e;
+            // (c) lane w marks the word starts of window w: bitmap words 2w, 2w + 1
+            uint64_t mask = 0;
+            if (lane < nw) {
+                const uint32_t base = pos0 + 64u * lane;
+                const uint32_t end = base + (hi - base < 64u ? hi - base : 64u);
+                for (uint32_t q = mine; q < end;) {
+                    mask |= 1ull << (q - base);
+                    const uint32_t c = L.cnt()[q & (kSpR - 1u)];
+                    q += c ? c : 1u;
+                }
+            }
+            const uint32_t lo32 = (uint32_t)mask, hi32 = (uint32_t)(mask >> 32);
+            const uint32_t cl = (uint32_t)__builtin_popcount(lo32), cw = cl + (uint32_t)__builtin_popcount(hi32);
+            const uint32_t incl = wave_scan_incl(cw);
+            if constexpr (WRITE) {
+                if (lane < nw) {
+                    L.bm[2u * lane] = lo32;
+                    L.bm[2u * lane + 1u] = hi32;
+                    L.bmpre[2u * lane] = words + incl - cw;
+                    L.bmpre[2u * lane + 1u] = words + incl - cw + cl;
+                }
+            }
+            words += wave_read(incl, 63);
+        }
+        if constexpr (WRITE) {
+            __syncthreads();
+            // 4. the words starting in the chunk, and the segment entries in them
+            uint32_t *const s8 = page + s8_at;
+            uint32_t *const entries = page + 4u + S * (nseg - 1u);
+            for (uint32_t r = tid; r < span; r += kSpThreads) {
+                const uint32_t bw = L.bm[r >> 5];
+                if (((bw >> (r & 31u)) & 1u) == 0u)
+                    continue;
+                const uint32_t widx = L.bmpre[r >> 5] + (uint32_t)__builtin_popcount(bw & ((1u << (r & 31u)) - 1u));
+                const uint32_t q = pos0 + r;
+                const uint32_t c = L.cnt()[q & (kSpR - 1u)];
+                const uint32_t sel = sp_selector(c);
+                const uint32_t bits = s8_mode(sel) >> 8;
+                uint64_t wv = 0;
+                for (uint32_t m = 0; m < c; ++m)
+                    wv |= (uint64_t)L.hv[(q + m) & (kSpR - 1u)] << (m * bits);
+                s8[2u * widx] = (uint32_t)wv;
+                s8[2u * widx + 1u] = (uint32_t)(wv >> 32) | (sel << 28);
+                for (uint32_t g = 1; g < nseg; ++g) {
+                    const uint32_t e = L.sege[g];
+                    if (e >= q && e - q < c)
+                        entries[g - 1u] = widx | ((e - q) << 24);
+                }
+            }
+        }
+        __syncthreads();
+        qa = qb;
+        lo = hi;
+    }
+    if constexpr (!WRITE) {
+        if (tid == 0)
+            sizes[p] = pad4(hw + packed + meta_w + 2u * words);
+        return;
+    } else {
+        if (wave != 0)
+            return;
         // zero padding after the words, up to the page's end
         for (uint32_t w = 2u * words + lane; w < s8w; w += 64)
             page[s8_at + w] = 0u;
+        // entries of segments with no exception at or after their start
+        if (lane >= 1 && lane < nseg && L.sege[lane] >= nexc)
+            page[4u + S * (nseg - 1u) + lane - 1u] = words;
         // segment bases: the S values before each segment after the first;
         // then the header's padding
         if (lane < S * (nseg - 1u)) {
@@ -251,57 +464,10 @@ __global__ __launch_bounds__(256) void k_sp_pack(const uint32_t *__restrict__ x,
             page[2] = meta_bytes;
             page[3] = 2u * words;
         }
-        return;
+        // the metadata's padding to 16 bytes
+        for (uint32_t i = meta_bytes + lane; i < 4u * meta_w; i += 64u)
+            md[i] = 0;
     }
-    // waves 1..3: blocks in groups of four, 16 lanes per block
-    uint8_t *const pk = reinterpret_cast<uint8_t *>(page + hw);
-    uint8_t *const md = reinterpret_cast<uint8_t *>(page + hw + packed);
-    const uint32_t g = lane >> 4, r = lane & 15u;
-    for (uint32_t t0 = 4u * (wave - 1u); t0 < nb; t0 += 12u) {
-        const uint32_t t = t0 + g;
-        const bool in = t < nb;
-        const uint32_t b = in ? (uint32_t)mb[t] : 0u;
-        uint32_t d[8];
-        uint32_t emask = 0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            d[k] = in ? sp_delta(x, pstart + (uint64_t)t * kBlock + 8u * r + k, S) : 0u;
-            emask |= (sp_nbits(d[k]) > b ? 1u : 0u) << k;
-        }
-        if (in) {
-            // low b bits of the eight values: b bytes from byte b * r of the block
-            const uint32_t m = width_mask(b);
-            uint64_t acc = 0;
-            uint32_t nbit = 0, o = 4u * s_blk[t] + b * r;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                acc |= (uint64_t)(d[k] & m) << nbit;
-                nbit += b;
-                while (nbit >= 8u) {
-                    pk[o++] = (uint8_t)acc;
-                    acc >>= 8;
-                    nbit -= 8u;
-                }
-            }
-        }
-        // positions of the block's exceptions, in order: rank = exceptions of
-        // the lanes before this one in the block's 16, then within the lane
-        const uint32_t cnt = (uint32_t)__builtin_popcount(emask);
-        const uint32_t incl16 = row_scan_incl(cnt);  // rows of 16 lanes are the blocks
-        uint32_t at = in ? 3u * nb + s_exc[t] + incl16 - cnt : 0u;
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            if (in && ((emask >> k) & 1u))
-                md[at++] = (uint8_t)(8u * r + k);
-        if (in && r == 0) {
-            md[t] = (uint8_t)b;
-            md[nb + t] = mm[t];
-            md[2u * nb + t] = mc[t];
-        }
-    }
-    // the metadata's padding to 16 bytes
-    for (uint32_t i = meta_bytes + (tid - 64u); i < 4u * meta_w; i += 192u)
-        md[i] = 0;
 }
 
 }  // namespace wp
@@ -316,19 +482,19 @@ int32_t sp_encode_units(const uint32_t *in, uint64_t n, uint32_t stride, uint64_
                         uint64_t nblk, uint32_t *sizes, uint64_t *status, uint32_t dir_end, uint32_t *out,
                         hipStream_t st)
 {
-#define WP_SP_LAUNCH(kern, threads, ...)                                                                   \
-    do {                                                                                                   \
-        if (stride == 0)                                                                                   \
-            hipLaunchKernelGGL(kern<0u>, dim3((uint32_t)units), dim3(threads), 0, st, __VA_ARGS__);         \
-        else if (stride == 1)                                                                              \
-            hipLaunchKernelGGL(kern<1u>, dim3((uint32_t)units), dim3(threads), 0, st, __VA_ARGS__);         \
-        else                                                                                               \
-            hipLaunchKernelGGL(kern<4u>, dim3((uint32_t)units), dim3(threads), 0, st, __VA_ARGS__);         \
+#define WP_SP_LAUNCH(W, ...)                                                                                    \
+    do {                                                                                                        \
+        if (stride == 0)                                                                                        \
+            hipLaunchKernelGGL((k_sp_page<0u, W>), dim3((uint32_t)units), dim3(kSpThreads), 0, st, __VA_ARGS__); \
+        else if (stride == 1)                                                                                   \
+            hipLaunchKernelGGL((k_sp_page<1u, W>), dim3((uint32_t)units), dim3(kSpThreads), 0, st, __VA_ARGS__); \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_sp_page<4u, W>), dim3((uint32_t)units), dim3(kSpThreads), 0, st, __VA_ARGS__); \
     } while (0)
-    WP_SP_LAUNCH(k_sp_size, 64, in, n, meta, nblk, sizes);
+    WP_SP_LAUNCH(false, in, n, meta, nblk, sizes, 0u, out);
     if (launch_inclusive_scan(sizes, units, status, st) != WP_OK)
         return WP_ERR_HIP;
-    WP_SP_LAUNCH(k_sp_pack, 256, in, n, meta, nblk, sizes, dir_end, out);
+    WP_SP_LAUNCH(true, in, n, meta, nblk, sizes, dir_end, out);
 #undef WP_SP_LAUNCH
     return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
 }

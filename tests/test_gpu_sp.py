@@ -246,3 +246,44 @@ def test_exception_heavy_pages(wide_frac):
     nb, packed = int(s[at]), int(s[at + 1])
     meta = s[at + -(-(4 + 7) // 4) * 4 + packed:].view(np.uint8)
     print(f"most exceptions in a block: {int(meta[2 * nb:3 * nb].max())}", flush=True)
+
+
+@pytest.mark.parametrize("kind", ["one_bit_high_parts", "mixed_high_widths"])
+def test_simple8b_words_across_encoder_chunks(kind):
+    # the encoder codes a page's high parts in chunks of about 4000 (its
+    # LDS ring); pages of 7000 one-bit high parts (14 a block, the most the
+    # cost rule keeps at one bit: 14 * 9 < 128 < 15 * 9) make 60-value words
+    # that straddle the chunk ends, and wide values of every width make
+    # every count from 1 to 60 appear across them; stream equals the
+    # oracle's word for word, and decodes back
+    rng = np.random.default_rng(11 if kind == "one_bit_high_parts" else 12)
+    n = 3 * 65536 + 128 * 33 + 17
+    if kind == "one_bit_high_parts":
+        b = 5
+        x = rng.integers(0, 1 << b, size=n, dtype=np.uint64)
+        pick = np.zeros(n, bool)
+        for t in range(n // 128):
+            pick[t * 128 + rng.choice(128, 14, replace=False)] = True
+        x = np.where(pick, rng.integers(1 << b, 1 << (b + 1), size=n, dtype=np.uint64), x).astype(np.uint32)
+    else:
+        width = rng.integers(5, 33, size=n)
+        wide = (rng.integers(0, 1 << 62, size=n, dtype=np.uint64) >> (64 - width).astype(np.uint64)) | (
+            np.uint64(1) << (width - 1).astype(np.uint64))
+        x = np.where(rng.random(n) < 0.6, wide, rng.integers(0, 16, size=n, dtype=np.uint64)).astype(np.uint32)
+    for stride in (0, 1):
+        print(f"sp encoder chunks {kind} stride={stride}", flush=True)
+        want = oracle.sp_encode(x, stride)
+        got = to_host(wp.encode_trimmed(to_dev(x), wp.CODEC_SP, stride))
+        assert got.size == want.size
+        assert_same(got, want, f"{kind} stride={stride}")
+        rc, back = gpu_decode(got, n)
+        assert rc == wp.OK
+        assert_same(back, x)
+    if kind == "one_bit_high_parts":
+        # the first page: 14 exceptions a block, 7168 high parts of one bit:
+        # 119 words of 60, then the last 28 as 20 (3 bits) and 8 (7 bits)
+        s = oracle.sp_encode(x, 0)
+        at = int(s[8])
+        nb = int(s[at])
+        assert nb == 512 and int(s[at + 2]) == 3 * 512 + 14 * 512
+        assert int(s[at + 3]) == 2 * (119 + 2)
