@@ -1001,7 +1001,8 @@ __global__ __launch_bounds__(128) void k_finish(const uint32_t *__restrict__ x, 
 #define WP_UNPAREN(...) __VA_ARGS__
 
 // Scratch bytes an encode call of `codec` over n integers uses: scan
-// status, unit sizes, per-block metadata.
+// status, unit sizes, per-block metadata (and the SimplePFOR pages' word
+// starts).
 // Look-back status words of an encode call: the chained scan of the unit
 // sizes, or the fused binary-packing encoder's tiles.
 static uint64_t encode_status_words(int codec, uint64_t units)
@@ -1021,7 +1022,8 @@ static uint64_t encode_scratch_bytes(int codec, uint64_t n)
     const uint64_t meta_len = (codec == WP_CODEC_BP || codec == WP_CODEC_BPV) ? nblk
                               : codec == WP_CODEC_BP32                      ? 4 * nblk
                                                                             : 3 * nblk;
-    return meta_off + meta_len + 256;
+    const uint64_t sp_len = codec == WP_CODEC_SP ? sp_scratch_bytes(units) : 0;
+    return ((meta_off + meta_len + 255) & ~255ull) + sp_len + 256;
 }
 
 static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t stride, uint32_t *out,
@@ -1057,6 +1059,8 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
     uint64_t *status = reinterpret_cast<uint64_t *>(scr);
     uint32_t *sizes = reinterpret_cast<uint32_t *>(scr + sizes_off);
     uint8_t *meta = reinterpret_cast<uint8_t *>(scr + meta_off);
+    const uint64_t meta_len = codec == WP_CODEC_BP32 ? 4 * nblk : 3 * nblk;
+    uint8_t *spw = reinterpret_cast<uint8_t *>(scr + ((meta_off + meta_len + 255) & ~255ull));
     (void)hipGetLastError();
     // the units' total length in words, for the tail's offset
     const uint32_t *units_words = sizes + (units ? units - 1 : 0);
@@ -1083,7 +1087,7 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
         if (codec == WP_CODEC_SP) {
             // widths and counts as for patched pages; the page sizes depend
             // on the Simple-8b coding
-            if (sp_encode_units(in, n, (uint32_t)stride, units, meta, nblk, sizes, status, dir_end, out, st) !=
+            if (sp_encode_units(in, n, (uint32_t)stride, units, meta, nblk, sizes, status, spw, dir_end, out, st) !=
                 WP_OK)
                 return WP_ERR_HIP;
         } else if (launch_inclusive_scan(sizes, units, status, st) != WP_OK)
