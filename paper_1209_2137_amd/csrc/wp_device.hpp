@@ -1288,17 +1288,38 @@ __device__ __forceinline__ bool bp_wave_run(const uint32_t *__restrict__ in, con
 
     // slots are loaded, written and reloaded in the same order, so the
     // wait for a slot never covers a younger slot's load
-    uint4 s0, s1, s2, s3;
-    s0 = buf_load_u4(rs, (0 * CW + lane * 4) * 4);
-    __builtin_amdgcn_sched_barrier(0);
-    s1 = buf_load_u4(rs, (1 * CW + lane * 4) * 4);
-    __builtin_amdgcn_sched_barrier(0);
-    if constexpr (DEPTH > 2)
-        s2 = buf_load_u4(rs, (2 * CW + lane * 4) * 4);
-    __builtin_amdgcn_sched_barrier(0);
-    if constexpr (DEPTH > 3)
-        s3 = buf_load_u4(rs, (3 * CW + lane * 4) * 4);
+    uint4 s0 = make_uint4(0, 0, 0, 0), s1 = s0, s2 = s0, s3 = s0;
     uint32_t written = 0;  // words of the run already in the ring
+    if (run_len <= RB) {
+        // the whole run fits the ring: every chunk loaded at once and
+        // written before the first pass, so the passes' stores never share
+        // a wait with a later load (a wait for a load also waits for every
+        // older store)
+        constexpr uint32_t NCH = RB / CW;
+        uint4 ch[NCH];
+#pragma unroll
+        for (uint32_t k = 0; k < NCH; ++k)
+            ch[k] = buf_load_u4(rs, (k * CW + lane * 4) * 4);  // beyond the run: zeros
+#pragma unroll
+        for (uint32_t k = 0; k < NCH; ++k) {
+            const uint32_t pos = k * CW + lane * 4;
+            *reinterpret_cast<uint4 *>(&L.ring[pos]) = ch[k];
+            if (pos < G::MIR)
+                *reinterpret_cast<uint4 *>(&L.ring[RB + pos]) = ch[k];
+        }
+        written = RB;
+        wave_lds_order();
+    } else {
+        s0 = buf_load_u4(rs, (0 * CW + lane * 4) * 4);
+        __builtin_amdgcn_sched_barrier(0);
+        s1 = buf_load_u4(rs, (1 * CW + lane * 4) * 4);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (DEPTH > 2)
+            s2 = buf_load_u4(rs, (2 * CW + lane * 4) * 4);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (DEPTH > 3)
+            s3 = buf_load_u4(rs, (3 * CW + lane * 4) * 4);
+    }
     auto put = [&](uint4 &slot, uint32_t c) __attribute__((always_inline)) {
         const uint32_t pos = (c * CW + lane * 4) & (RB - 1);
         *reinterpret_cast<uint4 *>(&L.ring[pos]) = slot;
