@@ -622,10 +622,11 @@ __device__ __forceinline__ uint32_t half_min_at_ends(uint32_t v)  // lane 31: mi
     return v;
 }
 
-template <bool P32, uint32_t S>
-__global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__ x, uint64_t n,
-                                                    uint8_t *__restrict__ meta, uint64_t nblk,
-                                                    uint32_t *__restrict__ sizes)
+// With SPW (SimplePFOR pages), block k's exceptions' high-part widths also
+// go to spx[k * kSpWidthSlot ...], in position order.
+template <bool P32, uint32_t S, bool SPW>
+__device__ __forceinline__ void fp_analyze(const uint32_t *__restrict__ x, uint64_t n, uint8_t *__restrict__ meta,
+                                           uint64_t nblk, uint32_t *__restrict__ sizes, uint8_t *__restrict__ spx)
 {
     __shared__ uint32_t s_cnt[33];
     // per wavefront and block of the pair: bin w's eight copies at 8w .. 8w + 7
@@ -709,6 +710,24 @@ __global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__
             meta[nblk + bk] = (uint8_t)(half ? mB : mA);
             meta[2 * nblk + bk] = (uint8_t)(half ? cB : cA);
         }
+        if constexpr (SPW) {
+            // the lane's exceptions, ranked within its block (lanes of a half
+            // hold the block's values in order)
+            const uint32_t b = half ? bB : bA;
+            uint32_t em = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                em |= (nbits(dl[k]) > b ? 1u : 0u) << k;
+            if (half && !liveB)
+                em = 0;
+            const uint32_t ce = (uint32_t)__builtin_popcount(em);
+            uint32_t at = half_scan_incl(ce) - ce;  // < 102: the cost rule's bound
+            uint8_t *const slot = spx + (blk + half) * kSpWidthSlot;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if ((em >> k) & 1u)
+                    slot[at++] = (uint8_t)(nbits(dl[k]) - b);
+        }
         acc_pw += 4 * bA + (liveB ? 4 * bB : 0u);
         acc_pc += cA + (liveB ? cB : 0u);
         acc_k += (lane == mA - bA ? cA : 0u) + (liveB && lane == mB - bB ? cB : 0u);
@@ -732,6 +751,31 @@ __global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__
         const uint32_t nsb = S * (page_items<kPageFp>(nb) - 1);  // segment bases
         sizes[p] = pad4(pad4(4 + nset + nsb) + s_pw + ((meta_bytes + 15) / 16) * 4 + exc_w);
     }
+}
+
+template <bool P32, uint32_t S>
+__global__ __launch_bounds__(512) void k_fp_analyze(const uint32_t *__restrict__ x, uint64_t n,
+                                                    uint8_t *__restrict__ meta, uint64_t nblk,
+                                                    uint32_t *__restrict__ sizes)
+{
+    fp_analyze<P32, S, false>(x, n, meta, nblk, sizes, nullptr);
+}
+
+// The SimplePFOR form; strides 0 and 1 fit eight wavefronts per SIMD
+// without spilling (stride 4 does not).
+template <uint32_t S>
+__global__ __launch_bounds__(512) void k_sp_analyze(const uint32_t *__restrict__ x, uint64_t n,
+                                                    uint8_t *__restrict__ meta, uint64_t nblk,
+                                                    uint32_t *__restrict__ sizes, uint8_t *__restrict__ spx)
+{
+    fp_analyze<false, S, true>(x, n, meta, nblk, sizes, spx);
+}
+template <uint32_t S>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(8))) void k_sp_analyze8(
+    const uint32_t *__restrict__ x, uint64_t n, uint8_t *__restrict__ meta, uint64_t nblk,
+    uint32_t *__restrict__ sizes, uint8_t *__restrict__ spx)
+{
+    fp_analyze<false, S, true>(x, n, meta, nblk, sizes, spx);
 }
 
 // LDS staging of a page's metadata and exception arrays in k_fp_pack
@@ -1022,7 +1066,7 @@ static uint64_t encode_scratch_bytes(int codec, uint64_t n)
     const uint64_t meta_len = (codec == WP_CODEC_BP || codec == WP_CODEC_BPV) ? nblk
                               : codec == WP_CODEC_BP32                      ? 4 * nblk
                                                                             : 3 * nblk;
-    const uint64_t sp_len = codec == WP_CODEC_SP ? sp_scratch_bytes(units) : 0;
+    const uint64_t sp_len = codec == WP_CODEC_SP ? sp_scratch_bytes(units) + nblk * kSpWidthSlot : 0;
     return ((meta_off + meta_len + 255) & ~255ull) + sp_len + 256;
 }
 
@@ -1061,6 +1105,7 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
     uint8_t *meta = reinterpret_cast<uint8_t *>(scr + meta_off);
     const uint64_t meta_len = codec == WP_CODEC_BP32 ? 4 * nblk : 3 * nblk;
     uint8_t *spw = reinterpret_cast<uint8_t *>(scr + ((meta_off + meta_len + 255) & ~255ull));
+    uint8_t *spx = spw + sp_scratch_bytes(units);  // SimplePFOR: exception widths per block
     (void)hipGetLastError();
     // the units' total length in words, for the tail's offset
     const uint32_t *units_words = sizes + (units ? units - 1 : 0);
@@ -1082,12 +1127,21 @@ static int32_t encode_common(int codec, const uint32_t *in, uint64_t n, int32_t 
                                meta, sizes);
         else if (codec == WP_CODEC_FP32)
             WP_FP_ENC(k_fp_analyze, true, (in, n, meta, nblk, sizes));
-        else
+        else if (codec == WP_CODEC_FP)
             WP_FP_ENC(k_fp_analyze, false, (in, n, meta, nblk, sizes));
+        else if (stride == 0)
+            hipLaunchKernelGGL((k_sp_analyze8<0u>), dim3((uint32_t)units), dim3(512), 0, st, in, n, meta, nblk, sizes,
+                               spx);
+        else if (stride == 1)
+            hipLaunchKernelGGL((k_sp_analyze8<1u>), dim3((uint32_t)units), dim3(512), 0, st, in, n, meta, nblk, sizes,
+                               spx);
+        else
+            hipLaunchKernelGGL((k_sp_analyze<4u>), dim3((uint32_t)units), dim3(512), 0, st, in, n, meta, nblk, sizes,
+                               spx);
         if (codec == WP_CODEC_SP) {
             // widths and counts as for patched pages; the page sizes depend
             // on the Simple-8b coding
-            if (sp_encode_units(in, n, (uint32_t)stride, units, meta, nblk, sizes, status, spw, dir_end, out, st) !=
+            if (sp_encode_units(in, n, (uint32_t)stride, units, meta, nblk, sizes, status, spw, spx, dir_end, out, st) !=
                 WP_OK)
                 return WP_ERR_HIP;
         } else if (launch_inclusive_scan(sizes, units, status, st) != WP_OK)

@@ -12,9 +12,10 @@
 // scan turns lengths into offsets, and the packer writes the page.
 //
 // Size kernel, per chunk:
-//  1. gather: the wavefronts load four blocks at a time (64 lanes, eight
-//     values each), find each block's exceptions (16 lanes per block) and put
-//     their high parts' widths into the ring at their index in the page;
+//  1. gather: the patched analysis (in its SimplePFOR form) has written
+//     each block's exceptions' high-part widths, one byte each in position
+//     order, to a 128-byte slot per block; 16 lanes per block copy them into
+//     the ring at their index in the page (the input is not read again);
 //  2. counts: Simple-8b's greedy choice at a position depends only on the
 //     high parts from there on, so every position gets, in parallel, the
 //     number of values the greedy word starting there would hold: the largest
@@ -33,7 +34,9 @@
 // the ring keeps them for), and the walk stops at the first word start
 // beyond them.
 //
-// Packer, per chunk: the same gather, now keeping the high parts and writing
+// Packer, per chunk: the wavefronts load four blocks at a time (64 lanes,
+// eight values each), find each block's exceptions (16 lanes per block),
+// keep their high parts in the ring at their index in the page and write
 // the blocks' low bits (staged in LDS, stored as words) and the metadata
 // bytes (widths, maximum widths, counts, positions); then one thread per
 // word of the chunk assembles it from the ring (its count: the distance to
@@ -173,7 +176,8 @@ template <uint32_t S, bool WRITE>
 __global__ __launch_bounds__(kSpThreads) void k_sp_page(const uint32_t *__restrict__ x, uint64_t n,
                                                         const uint8_t *__restrict__ meta, uint64_t nblk,
                                                         uint32_t *__restrict__ sizes, uint8_t *__restrict__ spw,
-                                                        uint32_t dir_end, uint32_t *__restrict__ out)
+                                                        const uint8_t *__restrict__ spx, uint32_t dir_end,
+                                                        uint32_t *__restrict__ out)
 {
     __shared__ SpLds<WRITE> L;
     const uint64_t p = blockIdx.x;
@@ -262,58 +266,83 @@ __global__ __launch_bounds__(kSpThreads) void k_sp_page(const uint32_t *__restri
         if constexpr (!WRITE)
             if (tid == 0)
                 L.pos0 = pos;
-        // 1. gather: the wavefront takes steps wave, wave + 4, ... of the
-        // chunk, kSpDepth of them in flight (a step's slot is refilled as
-        // soon as its values are taken)
-        uint4 va[kSpDepth], vb[kSpDepth], pv[kSpDepth];
-        auto issue = [&](uint32_t d, uint32_t q) __attribute__((always_inline)) {
-            pv[d] = make_uint4(0, 0, 0, 0);
-            if (q < qb) {
-                va[d] = buf_load_u4(rs, (q * kSpQuadInts + 8u * lane) * 4u);
-                vb[d] = buf_load_u4(rs, (q * kSpQuadInts + 8u * lane + 4u) * 4u);
-                if (S != 0 && lane == 0) {
-                    if (q != 0)
-                        pv[d] = buf_load_u4(rs, (q * kSpQuadInts - 4u) * 4u);
-                    else if (pstart >= 4)
-                        pv[d] = make_uint4(x[pstart - 4], x[pstart - 3], x[pstart - 2], x[pstart - 1]);
+        if constexpr (!WRITE) {
+            // 1. gather: the chunk's widths from the analysis's per-block
+            // slots, 16 lanes a block and eight bytes a lane, eight blocks
+            // a thread in flight
+            constexpr uint32_t J = 8, BPS = kSpThreads / 16u;  // blocks per step
+            const uint32_t t0 = 4u * qa, t1 = 4u * qb < nb ? 4u * qb : nb;
+            const uint32_t r = tid & 15u;
+            for (uint32_t tb = t0 + (tid >> 4); tb < t1; tb += J * BPS) {
+                uint2 v[J];
+#pragma unroll
+                for (uint32_t j = 0; j < J; ++j) {
+                    const uint32_t t = tb + j * BPS;
+                    const uint32_t c = t < t1 ? (uint32_t)L.c[t] : 0u;
+                    v[j] = 8u * r < c ? *reinterpret_cast<const uint2 *>(spx + (p * kFpBlocks + t) * kSpWidthSlot + 8u * r)
+                                      : make_uint2(0, 0);
+                }
+#pragma unroll
+                for (uint32_t j = 0; j < J; ++j) {
+                    const uint32_t t = tb + j * BPS;
+                    const uint32_t c = t < t1 ? (uint32_t)L.c[t] : 0u;
+                    if (8u * r < c) {
+                        const uint32_t at = L.exc[t] + 8u * r;
+                        const uint64_t w = v[j].x | ((uint64_t)v[j].y << 32);
+#pragma unroll
+                        for (uint32_t k = 0; k < 8; ++k)
+                            if (8u * r + k < c)
+                                L.wd[(at + k) & (kSpR - 1u)] = (uint8_t)(w >> (8u * k));
+                    }
                 }
             }
-        };
-#pragma unroll
-        for (uint32_t d = 0; d < kSpDepth; ++d)
-            issue(d, qa + wave + kSpWaves * d);
-        for (uint32_t q0 = qa + wave; q0 < qb; q0 += kSpWaves * kSpDepth) {
-#pragma unroll
-            for (uint32_t d = 0; d < kSpDepth; ++d) {
-                const uint32_t q = q0 + kSpWaves * d;
-                if (q >= qb)
-                    break;
-                uint32_t dv[8];
-                sp_deltas<S>(va[d], vb[d], pv[d], lane, dv);
-                issue(d, q + kSpWaves * kSpDepth);
-                const uint32_t t = 4u * q + (lane >> 4), r = lane & 15u;
-                const bool in = t < nb;
-                const uint32_t b = in ? (uint32_t)L.b[t] : 32u;
-                uint32_t emask = 0;
-#pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    emask |= (sp_nbits(dv[k]) > b ? 1u : 0u) << k;
-                const uint32_t ce = (uint32_t)__builtin_popcount(emask);
-                const uint32_t incl16 = row_scan_incl(ce);  // rows of 16 lanes are the blocks
-                uint32_t at = in ? L.exc[t] + incl16 - ce : 0u;
-#pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    if ((emask >> k) & 1u) {
-                        const uint32_t slot = at & (kSpR - 1u);
-                        if constexpr (WRITE) {
-                            L.hv[slot] = dv[k] >> b;
-                            md[3u * nb + at] = (uint8_t)(8u * r + k);
-                        } else {
-                            L.wd[slot] = (uint8_t)(sp_nbits(dv[k]) - b);
-                        }
-                        ++at;
+        } else {
+            // 1. gather: the wavefront takes steps wave, wave + 4, ... of the
+            // chunk, kSpDepth of them in flight (a step's slot is refilled as
+            // soon as its values are taken)
+            uint4 va[kSpDepth], vb[kSpDepth], pv[kSpDepth];
+            auto issue = [&](uint32_t d, uint32_t q) __attribute__((always_inline)) {
+                pv[d] = make_uint4(0, 0, 0, 0);
+                if (q < qb) {
+                    va[d] = buf_load_u4(rs, (q * kSpQuadInts + 8u * lane) * 4u);
+                    vb[d] = buf_load_u4(rs, (q * kSpQuadInts + 8u * lane + 4u) * 4u);
+                    if (S != 0 && lane == 0) {
+                        if (q != 0)
+                            pv[d] = buf_load_u4(rs, (q * kSpQuadInts - 4u) * 4u);
+                        else if (pstart >= 4)
+                            pv[d] = make_uint4(x[pstart - 4], x[pstart - 3], x[pstart - 2], x[pstart - 1]);
                     }
-                if constexpr (WRITE) {
+                }
+            };
+#pragma unroll
+            for (uint32_t d = 0; d < kSpDepth; ++d)
+                issue(d, qa + wave + kSpWaves * d);
+            for (uint32_t q0 = qa + wave; q0 < qb; q0 += kSpWaves * kSpDepth) {
+#pragma unroll
+                for (uint32_t d = 0; d < kSpDepth; ++d) {
+                    const uint32_t q = q0 + kSpWaves * d;
+                    if (q >= qb)
+                        break;
+                    uint32_t dv[8];
+                    sp_deltas<S>(va[d], vb[d], pv[d], lane, dv);
+                    issue(d, q + kSpWaves * kSpDepth);
+                    const uint32_t t = 4u * q + (lane >> 4), r = lane & 15u;
+                    const bool in = t < nb;
+                    const uint32_t b = in ? (uint32_t)L.b[t] : 32u;
+                    uint32_t emask = 0;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        emask |= (sp_nbits(dv[k]) > b ? 1u : 0u) << k;
+                    const uint32_t ce = (uint32_t)__builtin_popcount(emask);
+                    const uint32_t incl16 = row_scan_incl(ce);  // rows of 16 lanes are the blocks
+                    uint32_t at = in ? L.exc[t] + incl16 - ce : 0u;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        if ((emask >> k) & 1u) {
+                            L.hv[at & (kSpR - 1u)] = dv[k] >> b;
+                            md[3u * nb + at] = (uint8_t)(8u * r + k);
+                            ++at;
+                        }
                     // low b bits of the eight values: b bytes from byte b * r
                     // of the block, staged with the step's other blocks (whose
                     // packed words follow one another), then stored as words
@@ -494,8 +523,8 @@ uint64_t sp_scratch_bytes(uint64_t units) { return units * kSpSlotBytes; }
 // the patched analysis's widths, maximum widths and counts; `spw` has
 // sp_scratch_bytes(units) bytes.
 int32_t sp_encode_units(const uint32_t *in, uint64_t n, uint32_t stride, uint64_t units, const uint8_t *meta,
-                        uint64_t nblk, uint32_t *sizes, uint64_t *status, uint8_t *spw, uint32_t dir_end,
-                        uint32_t *out, hipStream_t st)
+                        uint64_t nblk, uint32_t *sizes, uint64_t *status, uint8_t *spw, const uint8_t *spx,
+                        uint32_t dir_end, uint32_t *out, hipStream_t st)
 {
 #define WP_SP_LAUNCH(W, ...)                                                                                    \
     do {                                                                                                        \
@@ -506,10 +535,10 @@ int32_t sp_encode_units(const uint32_t *in, uint64_t n, uint32_t stride, uint64_
         else                                                                                                    \
             hipLaunchKernelGGL((k_sp_page<4u, W>), dim3((uint32_t)units), dim3(kSpThreads), 0, st, __VA_ARGS__); \
     } while (0)
-    WP_SP_LAUNCH(false, in, n, meta, nblk, sizes, spw, 0u, out);
+    WP_SP_LAUNCH(false, in, n, meta, nblk, sizes, spw, spx, 0u, out);
     if (launch_inclusive_scan(sizes, units, status, st) != WP_OK)
         return WP_ERR_HIP;
-    WP_SP_LAUNCH(true, in, n, meta, nblk, sizes, spw, dir_end, out);
+    WP_SP_LAUNCH(true, in, n, meta, nblk, sizes, spw, spx, dir_end, out);
 #undef WP_SP_LAUNCH
     return hipGetLastError() == hipSuccess ? WP_OK : WP_ERR_HIP;
 }

@@ -58,10 +58,14 @@ inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 // `meta`): page sizes into `sizes` and each page's Simple-8b word starts
 // into `spw` (sp_scratch_bytes(units) bytes), the sizes' chained scan
 // (`status` as for launch_inclusive_scan), then the pages themselves.
+// `spx`: each block's exceptions' high-part widths, one byte each in
+// position order, from byte k * kSpWidthSlot for block k (written by the
+// patched analysis in its SimplePFOR form).
+constexpr uint32_t kSpWidthSlot = 128;  // at least the cost rule's 102 exceptions per block
 uint64_t sp_scratch_bytes(uint64_t units);
 int32_t sp_encode_units(const uint32_t *in, uint64_t n, uint32_t stride, uint64_t units, const uint8_t *meta,
-                        uint64_t nblk, uint32_t *sizes, uint64_t *status, uint8_t *spw, uint32_t dir_end,
-                        uint32_t *out, hipStream_t st);
+                        uint64_t nblk, uint32_t *sizes, uint64_t *status, uint8_t *spw, const uint8_t *spx,
+                        uint32_t dir_end, uint32_t *out, hipStream_t st);
 
 // Rearranges the FastPFOR stream `tmp` (arrays padded to 32) into pages of
 // the paper's own layout in `out`: page sizes, their chained scan, the
