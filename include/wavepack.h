@@ -194,7 +194,8 @@ int32_t fastpfor32_decode(const uint32_t *in, uint64_t in_words, uint32_t *out, 
  * positions as fastpfor_encode; the high parts of each page's exceptions,
  * in block order, coded greedily with Simple-8b). Arguments as bp_encode,
  * with WP_CODEC_SP for the capacity; scratch as bp_encode, plus about
- * 105 KB per 65536 integers for each page's Simple-8b word starts. */
+ * 169 KB per 65536 integers (each page's Simple-8b word starts, 105 KB,
+ * and its blocks' exception widths, 64 KB). */
 int32_t simplepfor_encode(const uint32_t *in, uint64_t n, int32_t delta_stride, uint32_t *out,
                           uint64_t out_cap_words, uint64_t *out_words, void *stream);
 
