@@ -287,3 +287,38 @@ def test_simple8b_words_across_encoder_chunks(kind):
         nb = int(s[at])
         assert nb == 512 and int(s[at + 2]) == 3 * 512 + 14 * 512
         assert int(s[at + 3]) == 2 * (119 + 2)
+
+
+def test_most_exceptions_the_cost_rule_allows():
+    # 26 zeros and 102 values of 32 bits in every block: the cost rule takes
+    # b = 0 (102 * (8 + 32) = 4080 < 4096 = 128 * 32), the most exceptions
+    # it lets a block keep; 52224 a page, each high part 32 bits wide and so
+    # a Simple-8b word of its own. The encoder's chunks (about 15 a page),
+    # its list of word starts and the decoder's ring of high parts are at
+    # their limits; FastPFOR pages of the same input too (one array of
+    # 52224 32-bit values a page)
+    rng = np.random.default_rng(21)
+    n = 3 * 65536 + 128 * 5 + 9
+    d = np.zeros(n, np.uint64)
+    for t in range(n // 128):
+        d[t * 128 + rng.choice(128, 102, replace=False)] = rng.integers(1 << 31, 1 << 32, size=102, dtype=np.uint64)
+    d = d.astype(np.uint32)
+    x1 = np.cumsum(d.astype(np.uint64)).astype(np.uint32)  # stride-1 deltas are d
+    for stride, x in ((0, d), (1, x1)):
+        print(f"sp most exceptions stride={stride}", flush=True)
+        want = oracle.sp_encode(x, stride)
+        at = int(want[8])
+        assert list(want[at:at + 4]) == [512, 0, 3 * 512 + 102 * 512, 2 * 102 * 512]
+        got = to_host(wp.encode_trimmed(to_dev(x), wp.CODEC_SP, stride))
+        assert got.size == want.size
+        assert_same(got, want, f"simplepfor stride={stride}")
+        rc, back = gpu_decode(got, n)
+        assert rc == wp.OK
+        assert_same(back, x, f"simplepfor decode stride={stride}")
+        print(f"fp most exceptions stride={stride}", flush=True)
+        want = oracle.fp_encode(x, stride)
+        comp = wp.encode_trimmed(to_dev(x), wp.CODEC_FP, stride)
+        assert_same(to_host(comp), want, f"fastpfor stride={stride}")
+        out = wp.fastpfor_decode(comp, n)
+        wp.check()
+        assert_same(to_host(out), x, f"fastpfor decode stride={stride}")
