@@ -53,12 +53,10 @@ constexpr uint32_t kSpWaves = kSpThreads / 64;
 constexpr uint32_t kSpR = 4096;                 // ring of a page's high parts, by index mod kSpR
 constexpr uint32_t kSpChunkExc = kSpR - 64;     // a chunk's exceptions: the ring keeps the 59 before them too
 constexpr uint32_t kSpQuadInts = 4u * kBlock;   // a wavefront's step: four blocks, eight values a lane
-constexpr uint32_t kSpDepth = 4;                // steps a wavefront loads before coding them
+constexpr uint32_t kSpDepth = 4;                // the packer's steps in flight per wavefront
 static_assert(kSpChunkExc >= 4u * 102u, "a chunk holds at least one step's exceptions");
 
 __device__ __forceinline__ uint32_t sp_nbits(uint32_t x) { return 32u - (uint32_t)__clz((int)x); }
-
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) { return wave_read(wave_scan_incl(v), 63); }
 
 // Words of a SimplePFOR page's header: 4, then for each 64-block segment
 // after the first S bases and one Simple-8b entry, padded to 4.
