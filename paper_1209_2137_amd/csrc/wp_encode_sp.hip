@@ -377,22 +377,38 @@ __global__ __launch_bounds__(kSpThreads) void k_sp_page(const uint32_t *__restri
         }
         __syncthreads();
         if constexpr (WRITE) {
-            // the chunk's words [k0, k1): one thread per word, from the ring
+            // the chunk's words [k0, k1): one thread per word, from the ring;
+            // the word starts of four words a thread are loaded at once
             const uint32_t k1 = uniform(tab[ci]);
-            for (uint32_t k = k0 + tid; k < k1 && k < total; k += kSpThreads) {
-                const uint32_t q = starts[k];
-                const uint32_t c = (k + 1u < total ? (uint32_t)starts[k + 1u] : nexc) - q;
-                const uint32_t sel = sp_selector(c);
-                const uint32_t bits = s8_mode(sel) >> 8;
-                uint64_t wv = 0;
-                for (uint32_t m = 0; m < c && m < 60u; ++m)
-                    wv |= (uint64_t)L.hv[(q + m) & (kSpR - 1u)] << (m * bits);
-                s8[2u * k] = (uint32_t)wv;
-                s8[2u * k + 1u] = (uint32_t)(wv >> 32) | (sel << 28);
+            const uint32_t kend = k1 < total ? k1 : total;
+            constexpr uint32_t U = 4;
+            for (uint32_t kb = k0 + tid; kb < kend; kb += U * kSpThreads) {
+                uint32_t qs[U], qe[U];
 #pragma unroll
-                for (uint32_t g = 1; g < kPageSegs; ++g)
-                    if (g < nseg && sege[g] >= q && sege[g] - q < c)
-                        entries[g - 1u] = k | ((sege[g] - q) << 24);
+                for (uint32_t u = 0; u < U; ++u) {
+                    const uint32_t k = kb + u * kSpThreads;
+                    qs[u] = k < kend ? (uint32_t)starts[k] : 0u;
+                    qe[u] = k < kend ? (k + 1u < total ? (uint32_t)starts[k + 1u] : nexc) : 0u;
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < U; ++u) {
+                    const uint32_t k = kb + u * kSpThreads;
+                    if (k >= kend)
+                        break;
+                    const uint32_t q = qs[u];
+                    const uint32_t c = qe[u] - q;
+                    const uint32_t sel = sp_selector(c);
+                    const uint32_t bits = s8_mode(sel) >> 8;
+                    uint64_t wv = 0;
+                    for (uint32_t m = 0; m < c && m < 60u; ++m)
+                        wv |= (uint64_t)L.hv[(q + m) & (kSpR - 1u)] << (m * bits);
+                    s8[2u * k] = (uint32_t)wv;
+                    s8[2u * k + 1u] = (uint32_t)(wv >> 32) | (sel << 28);
+#pragma unroll
+                    for (uint32_t g = 1; g < kPageSegs; ++g)
+                        if (g < nseg && sege[g] >= q && sege[g] - q < c)
+                            entries[g - 1u] = k | ((sege[g] - q) << 24);
+                }
             }
             k0 = k1;
         } else {
