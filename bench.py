@@ -552,6 +552,36 @@ def profile_variants(steps, inputs):
     return 0
 
 
+def profile_encoders(steps):
+    """For rocprofv3 kernel traces (never under counter collection): the
+    encoders on their bench workloads, `steps` timed calls each after one
+    warm-up: binary packing (both block layouts) and BP32 on the 2^26
+    cluster list, FastPFOR (both paddings), SimplePFOR and FastPFOR pages in
+    the paper's own layout on the 2^28 patched list."""
+    import torch
+    import paper_1209_2137_amd as wp
+    from paper_1209_2137_amd import datagen
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    wp.lib()
+    res = {}
+    cluster = datagen.cluster_sorted(1 << 26, seed=2)
+    for name, codec in (("bp_encode_cluster_2e26", wp.CODEC_BP), ("bpv_encode_cluster_2e26", wp.CODEC_BPV),
+                        ("bp32_encode_cluster_2e26", wp.CODEC_BP32)):
+        r = bench_encode(wp, cluster, codec, 1, steps, 1, name)
+        res[name] = {"event_ms": r["event_ms"], "alg_bytes": r["alg_bytes"], "bits_per_int": r["bits_per_int"]}
+    del cluster
+    patched = datagen.patched_gaps(1 << 28, seed=4)
+    for name, codec in (("fp_encode_patched_2e28", wp.CODEC_FP), ("fp32_encode_patched_2e28", wp.CODEC_FP32),
+                        ("sp_encode_patched_2e28", wp.CODEC_SP), ("fpi_encode_patched_2e28", wp.CODEC_FPI)):
+        r = bench_encode(wp, patched, codec, 1, steps, 1, name)
+        res[name] = {"event_ms": r["event_ms"], "alg_bytes": r["alg_bytes"], "bits_per_int": r["bits_per_int"]}
+        torch.cuda.synchronize()
+    print(json.dumps(res))
+    return 0
+
+
 def profile_run(steps, inputs=None):
     """For rocprofv3: the headline decode, the 2^28 patched decode, the
     2^28 in-place delta decode and the batched posting-list decode `steps`
@@ -614,6 +644,8 @@ def main():
                          "then a 1 GiB device copy (the counter calibration kernel) `--steps` times")
     ap.add_argument("--profile-variants", action="store_true",
                     help="for rocprofv3: the BP32, four-lane SIMD-BP128 and FastPFOR-32 decoders (needs --inputs)")
+    ap.add_argument("--profile-encoders", action="store_true",
+                    help="for rocprofv3 kernel traces: every encoder on its bench workload `--steps` times")
     ap.add_argument("--inputs", metavar="DIR",
                     help="with --profile-run / --profile-variants: load the streams saved by --prepare-inputs")
     ap.add_argument("--prepare-inputs", metavar="DIR",
@@ -626,6 +658,8 @@ def main():
         return prepare_inputs(args.prepare_inputs)
     if args.profile_run:
         return profile_run(args.steps, args.inputs)
+    if args.profile_encoders:
+        return profile_encoders(args.steps)
     if args.profile_variants:
         if not args.inputs:
             print("--profile-variants needs --inputs DIR (from --prepare-inputs)", file=sys.stderr)
