@@ -436,8 +436,11 @@ enum : int { kPageFp = 0, kPageFp32 = 1, kPageSp = 2, kPageFpi = 3 };
 // its first 64 (those are fetched into registers), the fetched pass's, and
 // one Simple-8b word: at most 4 * 102 - 64 + 4 * 102 + 59, since the cost
 // rule never keeps more than 102 exceptions in a block (c (8 + maxb - b)
-// < 128 (maxb - b)); a pass holding more is flagged.
-constexpr uint32_t kSpRing = 1024;
+// < 128 (maxb - b)); a pass holding more is flagged. Not a power of two:
+// 816 entries keep a segment at 11.5 KB of LDS, seven workgroups of two
+// segments per compute unit (six with 1024).
+constexpr uint32_t kSpRing = 816;
+static_assert(kSpRing >= 4u * 102u - 64u + 4u * 102u + 59u, "a segment's high parts fit the ring");
 constexpr uint32_t kSegBlocks = 64;  // blocks per segment of a patched page
 constexpr uint32_t kSegInts = kSegBlocks * kBlock;
 constexpr uint32_t kPageSegs = kFpBlocks / kSegBlocks;
@@ -917,7 +920,7 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
                 for (uint32_t j = 0; j < cnt; ++j, ++at) {
                     const uint64_t v = bits ? (word >> (j * bits)) & fm : 0u;
                     bad = bad || (v >> 32) != 0u;
-                    ring[at & (kSpRing - 1u)] = (uint32_t)v;
+                    ring[at % kSpRing] = (uint32_t)v;
                 }
             }
             dec += wave_read(incl, (int)nacc - 1);
@@ -972,7 +975,7 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
         uint32_t bit = 0;
         if constexpr (SP) {
             s8_fill(wA + f.ce, keep, false);
-            f.lo = any ? ring[(wA + lane) & (kSpRing - 1u)] : 0u;
+            f.lo = any ? ring[(wA + lane) % kSpRing] : 0u;
             f.hi = 0;
         } else {
             bit = re.z + idx * k;
@@ -1042,7 +1045,7 @@ __device__ __forceinline__ bool fp_wave_page(const uint32_t *__restrict__ page, 
                     bad = bad || pos >= kBlock || (idx > 0u && pprev >= pos);
                     uint32_t hv;
                     if constexpr (SP) {
-                        hv = ring[(wA + e) & (kSpRing - 1u)];
+                        hv = ring[(wA + e) % kSpRing];
                         bad = bad || (hv & ~width_mask(k)) != 0u;
                     } else {
                         const uint32_t bit = re.z + idx * k;
